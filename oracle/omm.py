@@ -1,0 +1,327 @@
+"""CPU FP64 oracle: Ordejon-Mauri / Kim functional minimized by conjugate gradients.
+
+TEST INFRASTRUCTURE ONLY (imported by tests/, __graft_entry__.smoke() and
+bench.py's cpu_baseline leg; never by the GPU library, with which it shares no
+code).  Plain NumPy/SciPy in float64.  Every product is recomputed from C and D
+at every iteration; nothing is updated incrementally, blocked or fused.
+
+Notation follows the paper (arXiv 2209.05934, Sec. II): H, S are the m x m
+Hamiltonian and overlap in the atomic-orbital basis, C is the m x n coefficient
+matrix (columns = wavefunctions, Eq. 3), H_W = C^T H C and S_W = C^T S C
+(Eq. 3), and the functional is E~ = 2 Tr[(2I - S_W) H_W] (Eq. 4).  Matrices are
+real (Gamma point, Sec. IV A).  H and S may be dense numpy arrays or
+scipy.sparse matrices; C-shaped matrices are dense.
+
+Readings where the paper is silent (each is also listed in the design doc):
+* gradient: the real gradient dE~/dC = 8HC - 4(HC S_W + SC H_W); the paper's
+  G = dE~/d(C*) (Sec. III B) is half of it.  With an exact line search the CG
+  iterates do not depend on that factor; only the norm threshold does.
+* the gradient is projected on the sparsity pattern of the initial C
+  ("keep_sparsity", Sec. III B); products are never restricted otherwise.
+* CG direction update: Polak-Ribiere, beta = max(0, <G, G - G_old>/<G_old, G_old>).
+* line search: the exact minimum of the quartic E~(C + xD) (Sec. I, ref. to
+  the analytic quartic) reached by going downhill from x = 0: the smallest
+  positive critical point with positive curvature.  When the quartic has no
+  such minimum or the direction is not a descent direction (the failure mode
+  of Sec. IV C), the step is x = 0 and the next direction is the steepest
+  descent -G; if that already was the direction, the run fails.
+* stop: projected gradient Frobenius norm <= tol_grad, or (if rel_tol > 0) the
+  paper's relative energy change |2(E_n - E_{n-1})/(E_n + E_{n-1})| < rel_tol
+  (Table 1, OMM.RelTol).
+* Kim correction: the reported band energy is E~ + 2 eta n (2n electrons,
+  Sec. II), i.e. the paper's "E~ + eta n" with its spin factor.
+* filtering (Sec. V): with filter_eps > 0, every product of H or S with C or
+  D and every n x n projection has its atom blocks of Frobenius norm < eps set
+  to zero; C, D, G, H and S are never filtered.  eps = 0 filters nothing.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+import scipy.linalg
+import scipy.sparse
+
+
+# ---------------------------------------------------------------- helpers
+def _frob(A, B) -> float:
+    """Frobenius inner product <A, B> = sum_ij A_ij B_ij."""
+    if scipy.sparse.issparse(A):
+        return float(A.multiply(B).sum())
+    if scipy.sparse.issparse(B):
+        return float(B.multiply(A).sum())
+    return float(np.sum(np.asarray(A) * np.asarray(B)))
+
+
+def _trace(A) -> float:
+    return float(A.diagonal().sum())
+
+
+def _dense(A) -> np.ndarray:
+    return A.toarray() if scipy.sparse.issparse(A) else np.asarray(A)
+
+
+# ---------------------------------------------------------------- Sec. II
+def kim_shift(H, S, eta: float):
+    """Kim functional, step (1) of Sec. II: eigenspectrum shift H -> H - eta S."""
+    return H - eta * S
+
+
+def projections(H, S, C) -> Tuple[np.ndarray, np.ndarray]:
+    """H_W = C^T H C and S_W = C^T S C (Eq. 3, real C)."""
+    return _dense(C.T @ (H @ C)), _dense(C.T @ (S @ C))
+
+
+def om_energy(H, S, C) -> float:
+    """Ordejon-Mauri functional E~ = 2 Tr[(2I - S_W) H_W] (Eq. 4)."""
+    HW, SW = projections(H, S, C)
+    n = HW.shape[0]
+    return 2.0 * float(np.trace((2.0 * np.eye(n) - SW) @ HW))
+
+
+def om_gradient(H, S, C) -> np.ndarray:
+    """Real gradient of Eq. 4 with respect to C for symmetric H, S.
+
+    E~ = 4 Tr(C^T H C) - 2 Tr(C^T S C C^T H C), so
+    dE~/dC = 8 HC - 4 (HC S_W + SC H_W).
+    """
+    HC = _dense(H @ C)
+    SC = _dense(S @ C)
+    HW = C.T @ HC
+    SW = C.T @ SC
+    return 8.0 * HC - 4.0 * (HC @ SW + SC @ HW)
+
+
+def project(G: np.ndarray, mask: Optional[np.ndarray]) -> np.ndarray:
+    """Keep only the entries inside the pattern of the initial C (Sec. III B)."""
+    return G if mask is None else np.where(mask, G, 0.0)
+
+
+def exact_band_energy(H, S, C) -> float:
+    """E = 2 Tr[S_W^{-1} H_W] (Eq. 2)."""
+    HW, SW = projections(H, S, C)
+    return 2.0 * float(np.trace(np.linalg.solve(SW, HW)))
+
+
+def electron_count(SW: np.ndarray) -> float:
+    """n_e = 2 Tr[(2I - S_W) S_W] (Listing 1)."""
+    n = SW.shape[0]
+    return 2.0 * float(np.trace((2.0 * np.eye(n) - SW) @ SW))
+
+
+def density_matrix(C: np.ndarray, SW: np.ndarray, pattern: Optional[np.ndarray] = None) -> np.ndarray:
+    """rho = 2 C (2I - S_W) C^T (Eq. 5), kept on S's pattern when given (Sec. III B)."""
+    n = SW.shape[0]
+    rho = 2.0 * C @ (2.0 * np.eye(n) - SW) @ C.T
+    return rho if pattern is None else np.where(pattern, rho, 0.0)
+
+
+# ---------------------------------------------------------------- filtering
+def filter_blocks(A: np.ndarray, row_bsz: Optional[Sequence[int]],
+                  col_bsz: Optional[Sequence[int]], eps: float) -> np.ndarray:
+    """Zero every block whose Frobenius norm is strictly below eps (Sec. V)."""
+    if eps <= 0.0 or row_bsz is None or col_bsz is None:
+        return A
+    ro = np.concatenate([[0], np.cumsum(row_bsz)])
+    co = np.concatenate([[0], np.cumsum(col_bsz)])
+    out = np.array(A, copy=True)
+    for i in range(len(row_bsz)):
+        for j in range(len(col_bsz)):
+            blk = out[ro[i]:ro[i + 1], co[j]:co[j + 1]]
+            if np.sqrt(np.sum(blk * blk)) < eps:
+                blk[...] = 0.0
+    return out
+
+
+# ---------------------------------------------------------------- quartic
+def quartic_coefficients(H, S, C, D, filt=None) -> np.ndarray:
+    """Coefficients c0..c4 with E~(C + xD) = sum_k c_k x^k exactly.
+
+    Substituting C + xD into Eq. 4:
+      H_W(x) = H0 + x H1 + x^2 H2,  S_W(x) = S0 + x S1 + x^2 S2 with
+      H0 = C^T H C, H1 = C^T H D + D^T H C, H2 = D^T H D (S likewise), and
+      E~(x) = 4 Tr H_W(x) - 2 <S_W(x), H_W(x)>.
+    `filt` (optional) = (f_mn, f_nn) filters applied to the m x n and n x n products.
+    """
+    f_mn, f_nn = filt if filt is not None else (lambda A: A, lambda A: A)
+    HC, SC = f_mn(_dense(H @ C)), f_mn(_dense(S @ C))
+    HD, SD = f_mn(_dense(H @ D)), f_mn(_dense(S @ D))
+    H0, S0 = f_nn(C.T @ HC), f_nn(C.T @ SC)
+    H1 = f_nn(C.T @ HD) + f_nn(D.T @ HC)
+    S1 = f_nn(C.T @ SD) + f_nn(D.T @ SC)
+    H2, S2 = f_nn(D.T @ HD), f_nn(D.T @ SD)
+    c0 = 4.0 * np.trace(H0) - 2.0 * _frob(S0, H0)
+    c1 = 4.0 * np.trace(H1) - 2.0 * (_frob(S0, H1) + _frob(S1, H0))
+    c2 = 4.0 * np.trace(H2) - 2.0 * (_frob(S0, H2) + _frob(S1, H1) + _frob(S2, H0))
+    c3 = -2.0 * (_frob(S1, H2) + _frob(S2, H1))
+    c4 = -2.0 * _frob(S2, H2)
+    return np.array([c0, c1, c2, c3, c4], dtype=np.float64)
+
+
+def quartic_value(c: Sequence[float], x: float) -> float:
+    return float(c[0] + x * (c[1] + x * (c[2] + x * (c[3] + x * c[4]))))
+
+
+def _dp(c, x):
+    return c[1] + x * (2.0 * c[2] + x * (3.0 * c[3] + x * 4.0 * c[4]))
+
+
+def _d2p(c, x):
+    return 2.0 * c[2] + x * (6.0 * c[3] + x * 12.0 * c[4])
+
+
+def line_minimum(c: Sequence[float]) -> Tuple[float, bool]:
+    """First minimum of the quartic p(x) = sum c_k x^k along the descent direction.
+
+    The step is the exact line minimum of Eq. 4 along D (Sec. I: the quartic's
+    parameters are computed analytically).  With p'(0) = c1 < 0 the minimum
+    reached by going downhill from x = 0 is the smallest positive root of the
+    cubic p'(x) at which p'' > 0; farther minima lie where the Ordejon-Mauri
+    functional is unbounded below and are not taken.  Roots come from the
+    companion matrix (numpy.roots) and are polished by Newton steps.
+    Returns (x*, True), or (nan, False) when c1 >= 0 or no such minimum exists
+    (the failure mode of Sec. IV C).
+    """
+    if not c[1] < 0.0:
+        return float("nan"), False
+    coeffs = [4.0 * c[4], 3.0 * c[3], 2.0 * c[2], c[1]]
+    roots = np.roots(coeffs)
+    cands: List[float] = []
+    for r in roots:
+        if abs(r.imag) > 1e-7 * max(1.0, abs(r.real)):
+            continue
+        x = float(r.real)
+        for _ in range(4):
+            d2 = _d2p(c, x)
+            if d2 == 0.0:
+                break
+            x -= _dp(c, x) / d2
+        if x > 0.0 and _d2p(c, x) > 0.0:
+            cands.append(x)
+    if not cands:
+        return float("nan"), False
+    return min(cands), True
+
+
+# ---------------------------------------------------------------- CG
+@dataclass
+class CGResult:
+    C: np.ndarray
+    energy: float              # shifted functional E~ at the final C
+    energy_band: float         # E~ + 2 eta n
+    iterations: int
+    converged: bool
+    status: str                # "ok", "not_converged", "no_line_min"
+    grad_norm: float
+    restarts: int
+    HW: np.ndarray
+    SW: np.ndarray
+    history: List[dict] = field(default_factory=list)
+
+
+def _block_filters(filter_eps, row_blocks, col_blocks):
+    if filter_eps <= 0.0 or row_blocks is None or col_blocks is None:
+        return None
+    f_mn = lambda A: filter_blocks(A, row_blocks, col_blocks, filter_eps)   # noqa: E731
+    f_nn = lambda A: filter_blocks(A, col_blocks, col_blocks, filter_eps)   # noqa: E731
+    return f_mn, f_nn
+
+
+def _energy_and_gradient(H, S, C, mask, filt):
+    f_mn, f_nn = filt if filt is not None else (lambda A: A, lambda A: A)
+    HC, SC = f_mn(_dense(H @ C)), f_mn(_dense(S @ C))
+    HW, SW = f_nn(C.T @ HC), f_nn(C.T @ SC)
+    n = HW.shape[0]
+    E = 2.0 * float(np.trace((2.0 * np.eye(n) - SW) @ HW))
+    G = project(8.0 * HC - 4.0 * (HC @ SW + SC @ HW), mask)
+    return E, G, HW, SW
+
+
+def cg_minimize(H, S, C0: np.ndarray, *, mask: Optional[np.ndarray] = None, eta: float = 0.0,
+                tol_grad: float = 1e-9, rel_tol: float = 0.0, max_iter: int = 10000,
+                filter_eps: float = 0.0, row_blocks=None, col_blocks=None,
+                keep_history: bool = True) -> CGResult:
+    """Minimize E~ (Eq. 4, with the Kim shift of Sec. II) by conjugate gradients.
+
+    H, S: unshifted Hamiltonian and overlap; the shift H - eta S is applied here.
+    C0: initial guess; `mask` is its sparsity pattern (None = dense).
+    row_blocks/col_blocks: atom block sizes of the basis and of the
+    wavefunctions, used only by filtering.
+    """
+    Heta = kim_shift(H, S, eta)
+    C = project(np.array(C0, dtype=np.float64, copy=True), mask)
+    n = C.shape[1]
+    filt = _block_filters(filter_eps, row_blocks, col_blocks)
+    E, G, HW, SW = _energy_and_gradient(Heta, S, C, mask, filt)
+    D = -G
+    steepest = True
+    gg = _frob(G, G)
+    history: List[dict] = []
+    status, converged, it, restarts = "not_converged", False, 0, 0
+    if np.sqrt(gg) <= tol_grad:
+        status, converged = "ok", True
+    while not converged and it < max_iter:
+        it += 1
+        c = quartic_coefficients(Heta, S, C, D, filt)
+        x, ok = line_minimum(c)
+        restart = False
+        if not ok or c[1] >= 0.0:
+            if steepest:
+                status = "no_line_min"
+                it -= 1
+                break
+            x, restart = 0.0, True
+            restarts += 1
+        C = C + x * D
+        E_old = E
+        E, G_new, HW, SW = _energy_and_gradient(Heta, S, C, mask, filt)
+        gg_new = _frob(G_new, G_new)
+        beta = 0.0 if restart else max(0.0, _frob(G_new, G_new - G) / gg)
+        if keep_history:
+            history.append(dict(E=E, c=c.copy(), x=x, gnorm=np.sqrt(gg_new), beta=beta,
+                                restart=restart))
+        G, gg = G_new, gg_new
+        if np.sqrt(gg) <= tol_grad:
+            status, converged = "ok", True
+            break
+        if rel_tol > 0.0 and not restart and (E + E_old) != 0.0 and \
+                abs(2.0 * (E - E_old) / (E + E_old)) < rel_tol:
+            status, converged = "ok", True
+            break
+        D = -G + beta * D
+        steepest = (beta == 0.0)
+    return CGResult(C=C, energy=E, energy_band=E + 2.0 * eta * n, iterations=it,
+                    converged=converged, status=status, grad_norm=float(np.sqrt(gg)),
+                    restarts=restarts, HW=HW, SW=SW, history=history)
+
+
+# ---------------------------------------------------------------- Cholesky variant
+def cholesky_reduce(H, S) -> Tuple[np.ndarray, np.ndarray]:
+    """Reduce the generalized problem to standard form (Sec. II, Cholesky factorization).
+
+    S = U^T U with U upper triangular, H~ = U^{-T} H U^{-1}.  Returns (H~, U).
+    """
+    Hd, Sd = _dense(H), _dense(S)
+    U = scipy.linalg.cholesky(Sd, lower=False)
+    A = scipy.linalg.solve_triangular(U, Hd, trans="T", lower=False)       # U^{-T} H
+    Ht = scipy.linalg.solve_triangular(U, A.T, trans="T", lower=False).T   # (U^{-T} A^T)^T
+    return Ht, U
+
+
+def cg_minimize_cholesky(H, S, C0: np.ndarray, *, eta: float = 0.0, **kw) -> CGResult:
+    """Cubic-scaling OMM on the Cholesky-reduced problem (dense only, Sec. II/III B).
+
+    The shifted Hamiltonian H - eta S is reduced, the guess is mapped to
+    C~0 = U C0, CG runs with S~ = I, and the result is mapped back C = U^{-1} C~.
+    """
+    Ht, U = cholesky_reduce(kim_shift(H, S, eta), S)
+    m = Ht.shape[0]
+    Ct0 = U @ np.asarray(C0, dtype=np.float64)
+    res = cg_minimize(Ht, np.eye(m), Ct0, eta=0.0, **kw)
+    C = scipy.linalg.solve_triangular(U, res.C, lower=False)
+    n = C.shape[1]
+    res.C = C
+    res.energy_band = res.energy + 2.0 * eta * n
+    return res

@@ -1,0 +1,269 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test pins a part of the oracle to something other than itself:
+finite differences (gradient), an exact polynomial identity evaluated from
+scratch (quartic), a brute-force grid (line search), the generalized
+eigendecomposition (converged dense energy and density matrix, Sec. II: the
+minimum of Eq. 4 equals the solution of Eq. 2), the identities of Eqs. 1, 2,
+5 and Listing 1, the Cholesky reduction (Sec. II) and an independent
+quasi-Newton optimizer on tiny localized problems.
+"""
+
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.optimize
+
+import oracle as O
+from ommgen import config_spec, make_system
+
+
+def _rand_problem(m=10, n=4, seed=0):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((m, m))
+    H = 0.5 * (A + A.T)
+    B = rng.standard_normal((m, m)) * 0.1
+    S = np.eye(m) + 0.5 * (B + B.T)
+    C = rng.standard_normal((m, n)) * 0.3
+    D = rng.standard_normal((m, n)) * 0.3
+    return H, S, C, D
+
+
+def _eigen(H, S, n, eta=0.0):
+    w, X = scipy.linalg.eigh(H - eta * S, S)
+    return 2.0 * w[:n].sum(), 2.0 * X[:, :n] @ X[:, :n].T, w
+
+
+@pytest.fixture(scope="module")
+def chain():
+    s = make_system(config_spec("chain8"))
+    return s, s.H.to_dense(), s.S.to_dense(), s.C0.to_dense()
+
+
+@pytest.fixture(scope="module")
+def cube4():
+    s = make_system(config_spec("cubic4_dense"))
+    return s, s.H.to_dense(), s.S.to_dense(), s.C0.to_dense()
+
+
+# ------------------------------------------------------------ functional, gradient
+def test_gradient_finite_differences():
+    H, S, C, _ = _rand_problem()
+    G = O.om_gradient(H, S, C)
+    h = 1e-5
+    num = np.zeros_like(C)
+    for idx in np.ndindex(C.shape):
+        Cp, Cm = C.copy(), C.copy()
+        Cp[idx] += h
+        Cm[idx] -= h
+        num[idx] = (O.om_energy(H, S, Cp) - O.om_energy(H, S, Cm)) / (2 * h)
+    assert np.max(np.abs(num - G)) <= 1e-7 * np.max(np.abs(G))
+
+
+def test_gradient_chain_fd(chain):
+    s, H, S, C0 = chain
+    G = O.om_gradient(H, S, C0)
+    rng = np.random.default_rng(3)
+    h = 1e-6
+    for _ in range(20):
+        i, j = rng.integers(s.m), rng.integers(s.n)
+        Cp, Cm = C0.copy(), C0.copy()
+        Cp[i, j] += h
+        Cm[i, j] -= h
+        fd = (O.om_energy(H, S, Cp) - O.om_energy(H, S, Cm)) / (2 * h)
+        assert abs(fd - G[i, j]) <= 1e-7 * max(1.0, abs(G[i, j]))
+
+
+def test_energy_matches_trace_form():
+    # Eq. 4 in its expanded form 4 Tr H_W - 2 Tr(S_W H_W); Tr(rho H) equals E~ for any C
+    H, S, C, _ = _rand_problem(seed=1)
+    HW, SW = C.T @ H @ C, C.T @ S @ C
+    E = O.om_energy(H, S, C)
+    assert abs(E - (4 * np.trace(HW) - 2 * np.trace(SW @ HW))) < 1e-12 * abs(E)
+    rho = O.density_matrix(C, SW)
+    assert abs(np.trace(rho @ H) - E) < 1e-11 * max(1, abs(E))
+    # Listing 1: n_e = 2 Tr[(2I - S_W) S_W] equals Tr(rho S) for any C
+    assert abs(O.electron_count(SW) - np.trace(rho @ S)) < 1e-11 * max(1, abs(np.trace(rho @ S)))
+
+
+# ------------------------------------------------------------ quartic
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_quartic_exact(seed):
+    H, S, C, D = _rand_problem(seed=seed)
+    c = O.quartic_coefficients(H, S, C, D)
+    for x in (-1.0, -0.5, 0.3, 1.0, 2.0):
+        ref = O.om_energy(H, S, C + x * D)
+        assert abs(O.quartic_value(c, x) - ref) <= 1e-12 * max(1.0, abs(ref)) * 10
+    # c1 is the directional derivative <dE/dC, D>
+    assert abs(c[1] - np.sum(O.om_gradient(H, S, C) * D)) <= 1e-11 * max(1.0, abs(c[1]))
+    # c0 is the functional itself
+    assert abs(c[0] - O.om_energy(H, S, C)) <= 1e-12 * max(1.0, abs(c[0]))
+
+
+def _grid_first_min(c, xmax=50.0, n=2_000_001):
+    x = np.linspace(0.0, xmax, n)
+    p = c[0] + x * (c[1] + x * (c[2] + x * (c[3] + x * c[4])))
+    up = np.nonzero(np.diff(p) > 0)[0]
+    if up.size == 0:
+        return None, x[1] - x[0]
+    return x[up[0]], x[1] - x[0]
+
+
+def test_line_minimum_vs_grid():
+    rng = np.random.default_rng(7)
+    checked = 0
+    for _ in range(400):
+        c = rng.standard_normal(5) * np.array([1, 1, 3, 3, 1])
+        c[1] = -abs(c[1]) - 0.05
+        xg, dx = _grid_first_min(c)
+        x, ok = O.line_minimum(c)
+        if xg is None or xg >= 49.0:
+            assert not ok or x > 49.0
+            continue
+        assert ok
+        assert abs(x - xg) <= 2 * dx
+        checked += 1
+    assert checked > 200
+
+
+def test_line_minimum_failures():
+    assert not O.line_minimum([0.0, 1.0, 1.0, 0.0, 0.0])[1]           # ascent direction
+    assert not O.line_minimum([0.0, -1.0, -1.0, -1.0, -1.0])[1]       # unbounded, no minimum
+    x, ok = O.line_minimum([0.0, -2.0, 1.0, 0.0, 0.0])                # pure quadratic
+    assert ok and abs(x - 1.0) < 1e-14
+
+
+# ------------------------------------------------------------ converged dense results
+@pytest.mark.parametrize("which", ["chain", "cube4"])
+def test_dense_converges_to_eigen_solution(which, request):
+    s, H, S, C0 = request.getfixturevalue(which)
+    res = O.cg_minimize(H, S, C0, tol_grad=1e-9, max_iter=5000)
+    assert res.status == "ok" and res.converged
+    Estar, rho_star, _ = _eigen(H, S, s.n)
+    assert abs(res.energy - Estar) / s.natoms <= 1e-10
+    rho = O.density_matrix(res.C, res.SW)
+    assert np.max(np.abs(rho - rho_star)) <= 1e-8
+    assert np.max(np.abs(res.SW - np.eye(s.n))) <= 1e-8              # S_W -> I (Sec. II)
+    assert abs(np.trace(rho @ S) - 2 * s.n) <= 1e-8                   # 2n electrons
+    assert np.max(np.abs(rho @ S @ rho - 2 * rho)) <= 1e-8            # idempotency with spin 2
+    assert abs(O.exact_band_energy(H, S, res.C) - res.energy) / s.natoms <= 1e-10   # Eq. 2
+    E = [h["E"] for h in res.history]
+    assert all(b <= a + 1e-9 * abs(a) for a, b in zip(E, E[1:]))    # monotone descent
+
+
+@pytest.mark.parametrize("which", ["chain", "cube4"])
+def test_cholesky_equals_plain(which, request):
+    s, H, S, C0 = request.getfixturevalue(which)
+    plain = O.cg_minimize(H, S, C0, tol_grad=1e-9)
+    chol = O.cg_minimize_cholesky(H, S, C0, tol_grad=1e-9)
+    assert chol.converged
+    assert abs(chol.energy - plain.energy) / s.natoms <= 1e-10
+    rp = O.density_matrix(plain.C, plain.SW)
+    rc = O.density_matrix(chol.C, chol.SW)
+    assert np.max(np.abs(rp - rc)) <= 1e-8
+    # the reduction itself: U^T U = S and U^{-T} H U^{-1} has the generalized spectrum
+    Ht, U = O.cholesky_reduce(H, S)
+    assert np.max(np.abs(U.T @ U - S)) < 1e-13
+    w = scipy.linalg.eigh(H, S, eigvals_only=True)
+    assert np.max(np.abs(np.linalg.eigvalsh(0.5 * (Ht + Ht.T)) - w)) < 1e-12
+
+
+def test_kim_shift_in_gap(chain):
+    s, H, S, C0 = chain
+    base = O.cg_minimize(H, S, C0, tol_grad=1e-9)
+    eta = 0.1                                  # inside the gap
+    shifted = O.cg_minimize(H, S, C0, eta=eta, tol_grad=1e-9)
+    assert shifted.converged
+    assert abs(shifted.energy_band - base.energy) / s.natoms <= 1e-10
+    Estar, _, _ = _eigen(H, S, s.n, eta)
+    assert abs(shifted.energy - Estar) / s.natoms <= 1e-10
+
+
+def test_full_mask_equals_dense(chain):
+    s, H, S, C0 = chain
+    dense = O.cg_minimize(H, S, C0, tol_grad=1e-9)
+    masked = O.cg_minimize(H, S, C0, mask=np.ones_like(C0, dtype=bool), tol_grad=1e-9)
+    assert masked.iterations == dense.iterations
+    assert abs(masked.energy - dense.energy) == 0.0
+
+
+# ------------------------------------------------------------ localized results
+def _tiny_localized(seed=5, natoms=4, norb=3):
+    rng = np.random.default_rng(seed)
+    m = natoms * norb
+    A = rng.standard_normal((m, m)) * 0.1
+    H = 0.5 * (A + A.T)
+    for a in range(natoms):
+        H[a * norb:(a + 1) * norb, a * norb:(a + 1) * norb] += np.diag([-1.0] + [1.0] * (norb - 1))
+    B = rng.standard_normal((m, m)) * 0.03
+    S = np.eye(m) + 0.5 * (B + B.T)
+    # 1 WF per atom, localized on its own atom and the next one (periodic)
+    mask = np.zeros((m, natoms), dtype=bool)
+    for a in range(natoms):
+        for b in (a, (a + 1) % natoms):
+            mask[b * norb:(b + 1) * norb, a] = True
+    C0 = np.where(mask, rng.standard_normal((m, natoms)) * 0.3, 0.0)
+    return H, S, C0, mask
+
+
+def test_localized_matches_bfgs():
+    H, S, C0, mask = _tiny_localized()
+    res = O.cg_minimize(H, S, C0, mask=mask, tol_grad=1e-10, max_iter=20000)
+    assert res.converged
+    free = np.nonzero(mask.ravel())[0]
+
+    def f(v):
+        C = np.zeros(mask.size)
+        C[free] = v
+        C = C.reshape(mask.shape)
+        HW, SW = C.T @ H @ C, C.T @ S @ C
+        return 2.0 * np.trace((2.0 * np.eye(C.shape[1]) - SW) @ HW)
+
+    opt = scipy.optimize.minimize(f, C0.ravel()[free], method="BFGS",
+                                  options=dict(gtol=1e-10, maxiter=20000))
+    assert abs(opt.fun - res.energy) <= 1e-8 * abs(res.energy)
+    assert np.all(res.C[~mask] == 0.0)
+    # variational bound: the constrained minimum lies above the unconstrained one
+    Estar, _, _ = _eigen(H, S, mask.shape[1])
+    assert res.energy >= Estar - 1e-12
+
+
+def test_localized_gradient_projection():
+    H, S, C0, mask = _tiny_localized(seed=11)
+    res = O.cg_minimize(H, S, C0, mask=mask, tol_grad=1e-9, max_iter=20000)
+    G = O.om_gradient(H, S, res.C)
+    assert np.max(np.abs(G[mask])) <= 1e-9          # stationary on the pattern
+    assert np.max(np.abs(G[~mask])) > 1e-6           # but not off it
+
+
+# ------------------------------------------------------------ filtering, stop rules, failures
+def test_filter_blocks_strict():
+    A = np.zeros((4, 4))
+    A[:2, :2] = 0.5                                 # norm 1.0
+    A[2:, 2:] = 0.25                                # norm 0.5
+    A[:2, 2:] = [[1e-7, 0], [0, 0]]
+    out = O.filter_blocks(A, [2, 2], [2, 2], 0.5)
+    assert np.all(out[:2, :2] == 0.5) and np.all(out[2:, 2:] == 0.25)   # norm == eps kept
+    assert np.all(out[:2, 2:] == 0)
+    assert np.array_equal(O.filter_blocks(A, [2, 2], [2, 2], 0.0), A)
+
+
+def test_rel_tol_and_max_iter(chain):
+    s, H, S, C0 = chain
+    r = O.cg_minimize(H, S, C0, tol_grad=0.0, rel_tol=1e-9)
+    assert r.converged and r.iterations < 40
+    Estar, _, _ = _eigen(H, S, s.n)
+    assert abs(r.energy - Estar) / s.natoms < 1e-6
+    r2 = O.cg_minimize(H, S, C0, max_iter=3)
+    assert r2.status == "not_converged" and r2.iterations == 3 and len(r2.history) == 3
+
+
+def test_no_line_minimum_failure():
+    # H positive definite and an oversized guess: along -G the quartic falls without bound
+    m, n = 6, 2
+    H = np.eye(m)
+    S = np.eye(m)
+    C0 = np.zeros((m, n))
+    C0[0, 0] = C0[1, 1] = 3.0
+    r = O.cg_minimize(H, S, C0)
+    assert r.status == "no_line_min" and not r.converged and r.iterations == 0
