@@ -1,0 +1,221 @@
+/*
+ * omm.h - C ABI of an MI355X (gfx950) library for the conjugate-gradient
+ * orbital minimization method (OMM) of arXiv 2209.05934 (Lebedeva, Garcia,
+ * Artacho, Ordejon), cubic-scaling (dense, optionally Cholesky-reduced) and
+ * linear-scaling (atom-block sparse, localized wavefunctions, filtering).
+ *
+ * The library minimizes the Ordejon-Mauri functional (Eq. 4)
+ *     E~ = 2 Tr[(2I - S_W) H_W],   H_W = C^T H C,  S_W = C^T S C   (Eq. 3)
+ * over the m x n coefficient matrix C by conjugate gradients with an exact
+ * quartic line search (Sec. I, Sec. III B), for the Kim-shifted Hamiltonian
+ * H - eta S (Sec. II), and returns C, the energy and the density matrix
+ * rho = 2 C (2I - S_W) C^T on S's pattern (Eq. 5, Sec. III B).  The paper's
+ * solver contract (Sec. III B: H, S and an initial guess in a chosen format
+ * in, converged coefficients and rho out) is kept; its MatrixSwitch formats
+ * become one atom-block BCSR description, and its DBCSR/ScaLAPACK back ends
+ * become HIP kernels on one GPU.
+ *
+ * Conventions for every entry point:
+ *   - Matrices are real (Gamma point, Sec. IV A) and given as omm_matrix:
+ *     index arrays always live in host memory; `val` lives in host or device
+ *     memory as `memspace` says.  Inputs are borrowed for the call only and
+ *     deep-copied into memory the context owns.
+ *   - Every call is stream-ordered on omm_options.hip_stream and returns when
+ *     its work has completed.  Calls on one context must not overlap; there is
+ *     no global state, so different contexts are independent.
+ *   - Return value: an omm_status.  On an error the context stays valid (soft
+ *     errors OMM_ERR_NOT_CONVERGED / OMM_ERR_ELECTRON_COUNT leave readable
+ *     results) and omm_last_error() returns a message.
+ */
+#ifndef OMM_MI355X_H
+#define OMM_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  OMM_OK = 0,
+  OMM_ERR_ARG = 1,            /* shape, pattern or option mismatch */
+  OMM_ERR_STATE = 2,          /* call order (e.g. minimize before set_coeffs) */
+  OMM_ERR_NOT_SPD = 3,        /* Cholesky factorization of S failed (Sec. II) */
+  OMM_ERR_NO_LINE_MIN = 4,    /* quartic has no minimum along steepest descent (Sec. IV C) */
+  OMM_ERR_NOT_CONVERGED = 5,  /* soft: max_iter reached, results readable */
+  OMM_ERR_ELECTRON_COUNT = 6, /* soft: |2Tr[(2I-S_W)S_W] - 2n| above ne_tol (Sec. II, Kim) */
+  OMM_ERR_DEVICE = 7,         /* HIP runtime error */
+  OMM_ERR_OOM = 8             /* device allocation failed */
+} omm_status;
+
+/* Solver form (Table 1: OMM.UseSparse, OMM.Cholesky). */
+typedef enum {
+  OMM_DENSE = 0,           /* cubic scaling, dense C */
+  OMM_DENSE_CHOLESKY = 1,  /* cubic scaling on S = U^T U, H~ = U^-T H U^-1 (Sec. II) */
+  OMM_BLOCK_SPARSE = 2     /* linear scaling: C restricted to the pattern of C0 (Sec. II, III B) */
+} omm_mode;
+
+/* Arithmetic of the block products inside the CG iterations.  Energies,
+ * traces, quartic coefficients, line search, C/D/G and the final refinement
+ * iterations are always FP64. */
+typedef enum { OMM_FP64 = 0, OMM_FP32 = 1, OMM_BF16 = 2 } omm_precision;
+
+typedef enum { OMM_HOST = 0, OMM_DEVICE = 1 } omm_memspace;
+
+/* Atom-block compressed sparse row matrix (the paper's block matrices,
+ * Sec. III B: equal or per-atom rectangular blocks, zero blocks not stored).
+ *   row_bsz[nbrow], col_bsz[nbcol]   block sizes (host)
+ *   row_ptr[nbrow+1]                 stored blocks of block row i are
+ *                                    row_ptr[i] .. row_ptr[i+1]-1 (host)
+ *   col_idx[nnzb]                    block column of each stored block,
+ *                                    strictly increasing within a row (host)
+ *   val_off[nnzb]                    offset in `val` of the block's values,
+ *                                    stored row-major (host)
+ *   val[nval]                        float64 values (host or device)
+ * A dense matrix is one with every block stored. */
+typedef struct {
+  int32_t nbrow, nbcol;
+  const int32_t* row_bsz;
+  const int32_t* col_bsz;
+  const int64_t* row_ptr;
+  const int32_t* col_idx;
+  const int64_t* val_off;
+  const double* val;
+  int64_t nval;
+  int32_t memspace; /* omm_memspace of val */
+} omm_matrix;
+
+/* Options (Table 1 keys and build-only knobs).  Fill with omm_default_options. */
+typedef struct {
+  double eta;               /* Kim shift H -> H - eta S (OMM.Eta, Sec. II); default 0 */
+  double tol_grad;          /* stop when ||G||_F <= tol_grad (projected real gradient); 1e-9 */
+  double rel_tol;           /* stop when |2(E_n-E_{n-1})/(E_n+E_{n-1})| < rel_tol
+                               (OMM.RelTol, Table 1); <= 0 disables; default 0 */
+  int64_t max_iter;         /* CG iteration cap; default 10000 */
+  double filter_eps;        /* block-sparse mode: product blocks with Frobenius norm
+                               < eps are dropped (Sec. V); default 0 */
+  int32_t precision;        /* omm_precision of the CG block products; default FP64 */
+  int32_t fp64_refine_iters;/* mixed precision: FP64 iterations after the low-precision
+                               phase; <= 0 means FP64 until the stop rule; default 5 */
+  double lowprec_rel_switch;/* mixed precision: relative energy change that ends the
+                               low-precision phase; <= 0 picks 1e-7 (FP32) / 1e-5 (BF16) */
+  int64_t lowprec_max_iter; /* mixed precision: cap on low-precision iterations; default max_iter */
+  int32_t graph_iters;      /* CG iterations per captured hipGraph replay; <= 0: eager
+                               launches; default 16 */
+  int32_t history;          /* keep per-iteration history rows (omm_get_history); default 1 */
+  int32_t history_max;      /* rows kept per system; default 20000 */
+  double ne_tol;            /* electron-count check tolerance; <= 0 disables; default 0 */
+  int32_t autotune;         /* 1: time kernel variants at first minimize and keep the
+                               fastest (cached in tune_cache when set); default 0 */
+  const char* tune_cache;   /* path of the autotuner cache file, or NULL */
+  void* hip_stream;         /* hipStream_t to run on; NULL: the library makes its own */
+} omm_options;
+
+/* Per-system results of omm_minimize. */
+typedef struct {
+  double energy;         /* shifted functional E~ (Eq. 4 with H - eta S) */
+  double energy_band;    /* E~ + 2 eta n (Kim correction with spin factor 2, Sec. II) */
+  double grad_norm;      /* ||G||_F of the projected real gradient at the result */
+  double electron_count; /* 2 Tr[(2I - S_W) S_W] (Listing 1) */
+  int64_t iters_total;   /* CG iterations (line searches taken) */
+  int64_t iters_fp64;    /* of which in FP64 */
+  int64_t cg_restarts;   /* steepest-descent restarts */
+  int32_t status;        /* omm_status of this system */
+  int32_t precision_end; /* omm_precision of the last iteration */
+  double seconds;        /* wall time of the omm_minimize call */
+} omm_report;
+
+/* Sizes and work counts of one system (for sizing outputs and for roofline figures). */
+typedef struct {
+  int64_t m, n;             /* basis size, number of wavefunctions */
+  int64_t s_nval;           /* values of S's pattern = length of omm_density_matrix output */
+  int64_t c_nval;           /* values of C0's pattern = length of omm_get_coeffs output */
+  int64_t tiles_h, tiles_c, tiles_hc, tiles_w;  /* 16x16 tiles of H/S, C, HC, H_W */
+  int64_t pairs_s1, pairs_s2, pairs_grad;       /* tile products per CG iteration step */
+  double flops_alg_iter;    /* algorithmic flops of one CG iteration: 2*r*k*c summed
+                               over the unpadded atom-block products */
+  double flops_exec_iter;   /* flops the tile kernels execute per iteration */
+  double bytes_alg_iter;    /* algorithmic HBM bytes of one iteration's products
+                               (each operand and output tile moved once) */
+} omm_sizes;
+
+typedef struct omm_ctx omm_ctx;
+
+/* Fills *opt with the defaults listed above. */
+void omm_default_options(omm_options* opt);
+
+/* Creates a context for one system (Sec. III B solver input).
+ *   H, S  : m x m, identical block structure, square diagonal blocks, both symmetric
+ *           (all blocks stored, not one triangle).  H is shifted to H - eta S here.
+ *   n_occ : number of wavefunction columns n (1 <= n <= m).
+ *   mode  : omm_mode.  OMM_DENSE_CHOLESKY factorizes S (OMM_ERR_NOT_SPD if it fails).
+ *   opt   : may be NULL for defaults.
+ * On success *out owns device copies of H and S; free it with omm_destroy. */
+int omm_init(omm_ctx** out, const omm_matrix* H, const omm_matrix* S, int64_t n_occ,
+             int32_t mode, const omm_options* opt);
+
+/* Creates one context holding `count` independent systems (k-points, snapshots,
+ * separate structures) that every later call advances together, each with its
+ * own H[i], S[i], n_occ[i] and modes[i]; options are shared.  System indices
+ * 0..count-1 are used by the per-system calls below. */
+int omm_init_batch(omm_ctx** out, int32_t count, const omm_matrix* H, const omm_matrix* S,
+                   const int64_t* n_occ, const int32_t* modes, const omm_options* opt);
+
+/* Sets the initial guess of system `sys` (Sec. III C/D: random values inside the
+ * localization radius).  C0 is m x n with the same block rows as H; its block
+ * pattern is the pattern kept fixed during minimization (Sec. III B) and must
+ * include every column block once; in dense modes every block must be stored.
+ * Column blocks must be at most 16 wide in OMM_BLOCK_SPARSE mode. */
+int omm_set_coeffs(omm_ctx* ctx, int32_t sys, const omm_matrix* C0);
+
+/* Runs CG on every system of the context until each one stops (tol_grad,
+ * rel_tol, max_iter, or a failed line search).  reports[count] receives the
+ * per-system results (may be NULL).  Returns the worst per-system status.
+ * Calling it again restarts from the coefficients set by omm_set_coeffs. */
+int omm_minimize(omm_ctx* ctx, omm_report* reports);
+
+/* rho = 2 C (2I - S_W) C^T (Eq. 5) of system `sys` at the current C, on the
+ * block pattern of S and in the value layout (val_off) of the S passed at init:
+ * `rho` holds s_nval doubles in host or device memory (omm_memspace `where`). */
+int omm_density_matrix(omm_ctx* ctx, int32_t sys, double* rho, int32_t where);
+
+/* Current C of system `sys` in the layout of its C0 (c_nval doubles).  For
+ * OMM_DENSE_CHOLESKY this is the back-transformed C = U^-1 C~. */
+int omm_get_coeffs(omm_ctx* ctx, int32_t sys, double* C, int32_t where);
+
+/* Dense n x n row-major H_W and S_W (Eq. 3) of system `sys` at the current C
+ * (either pointer may be NULL). */
+int omm_get_projected(omm_ctx* ctx, int32_t sys, double* HW, double* SW, int32_t where);
+
+/* Per-iteration history of the last omm_minimize of system `sys` (host memory):
+ * rows of OMM_HISTORY_COLS doubles [E~ after the step, c0, c1, c2, c3, c4, x*,
+ * ||G||_F after the step, beta, restart flag, precision]; *rows receives the
+ * number of rows written (at most max_rows). */
+#define OMM_HISTORY_COLS 11
+int omm_get_history(omm_ctx* ctx, int32_t sys, double* out, int64_t max_rows, int64_t* rows);
+
+/* Sizes and work counts of system `sys` (sys = -1: sums over the batch). */
+int omm_query(const omm_ctx* ctx, int32_t sys, omm_sizes* sizes);
+
+/* Device time of the tile-product kernels of the last omm_minimize, measured
+ * with HIP events on the context's stream around every launch of each kernel
+ * class (0: direction products H D, S D; 1: n x n projections; 2: gradient
+ * products).  ms[3] total milliseconds, launches[3] launch counts.  Timing is
+ * recorded only when enabled with omm_set_timing(ctx, 1) before the call. */
+int omm_set_timing(omm_ctx* ctx, int32_t enable);
+int omm_kernel_times(const omm_ctx* ctx, double* ms, int64_t* launches);
+
+/* Name of a status code. */
+const char* omm_status_str(int32_t status);
+
+/* Message of the last error on this context ("" if none); ctx may be NULL for
+ * errors of a failed omm_init/omm_init_batch on the calling thread. */
+const char* omm_last_error(const omm_ctx* ctx);
+
+/* Releases every device buffer of the context. */
+void omm_destroy(omm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OMM_MI355X_H */

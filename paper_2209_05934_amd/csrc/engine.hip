@@ -1,0 +1,1423 @@
+// Context, ingest, CG driver and the C ABI declared in include/omm.h.
+//
+// The driver follows the solver flow of arXiv 2209.05934 (Sec. III A/B, Fig. 2):
+// H and S come in, an initial guess of C is set, libOMM-style CG minimizes the
+// functional of Eq. 4 (Kim shift of Sec. II, optional Cholesky reduction of
+// Sec. II for dense matrices), and rho (Eq. 5) is produced on S's pattern.
+// Everything after ingest runs in HIP kernels; per-system control (line-search
+// step, beta, stop flags) stays on the device, and the host only reads one
+// small state array per replay of a captured graph of several iterations.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+
+using namespace omm;
+
+namespace {
+
+thread_local std::string g_last_init_error;
+
+struct MatDesc {   // host copy of an input matrix's block structure
+  int nbrow = 0, nbcol = 0;
+  std::vector<int> rbs, cbs;
+  std::vector<int64_t> rp;
+  std::vector<int> ci;
+  std::vector<int64_t> voff;
+  int64_t nval = 0;
+  bool same_pattern(const MatDesc& o) const {
+    return nbrow == o.nbrow && nbcol == o.nbcol && rbs == o.rbs && cbs == o.cbs && rp == o.rp && ci == o.ci;
+  }
+};
+
+struct DevMap {    // device copies of one matrix's block structure for scatter/gather
+  int nblk = 0;
+  int *brow = nullptr, *bcol = nullptr;
+  int64_t* voff = nullptr;
+};
+
+struct SysHost {
+  int mode = OMM_DENSE;
+  int64_t m = 0, n = 0;
+  double eta = 0.0;
+  MatDesc H, S, C0;
+  bool has_c0 = false;
+  int RT = 0, WT = 0, rb0 = 0, wb0 = 0;
+  std::vector<int> r_tile, r_off;   // basis element -> local tile row, offset
+  std::vector<int> w_tile, w_off;   // WF element -> local tile col, offset
+  // device
+  int *ro = nullptr, *rtile = nullptr, *roff = nullptr;    // basis maps (global tile rows)
+  int *co = nullptr, *wtile = nullptr, *woff = nullptr;    // WF maps (global tile cols)
+  DevMap mh, mc;
+  int64_t* s_voff = nullptr;
+  double* c0_dev = nullptr;
+  double* Linv = nullptr;
+  int* chol_status = nullptr;
+  int64_t c_nval = 0;
+  // work counts
+  double flops_alg[3] = {0, 0, 0};
+  double flops_exec[3] = {0, 0, 0};
+  double bytes_alg = 0;
+  int64_t pairs[3] = {0, 0, 0};
+  int64_t tiles_h = 0, tiles_c = 0, tiles_hc = 0, tiles_w = 0;
+};
+
+struct Pat {
+  int nrows = 0;
+  int64_t nnz = 0;
+  int *rp = nullptr, *ci = nullptr, *row = nullptr, *ti = nullptr;
+  std::vector<int> hrp;
+  PatView view() const { return PatView{rp, ci, ti}; }
+};
+
+struct Plan {
+  int nout = 0;
+  int64_t npairs = 0;
+  int64_t* pp = nullptr;
+  int2* pairs = nullptr;
+  std::vector<int64_t> hpp;
+  PlanView view() const { return PlanView{nout, pp, pairs}; }
+};
+
+}  // namespace
+
+struct omm_ctx {
+  omm_options opt;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  int nsys = 0;
+  std::vector<SysHost> sys;
+  int NB = 0, NW = 0;
+  Pat TH, TC, TCt, THC, TW, TCM;
+  Plan Ps1, Ps2, Pgrad, Pcm, Prho;
+  int *brow_sys = nullptr, *wrow_sys = nullptr, *c_in_hc = nullptr, *hc_to_c = nullptr, *w_tr = nullptr;
+  uint32_t* cmask = nullptr;
+  uint8_t* wseg = nullptr;
+  int4* chunks = nullptr;
+  int nchunks = 0;
+  int *welem = nullptr;
+  int2 *win_bw = nullptr, *win_bb = nullptr, *win_ww = nullptr, *win_wb = nullptr;
+  double *H = nullptr, *S = nullptr;
+  void *Hl = nullptr, *Sl = nullptr;
+  Bufs b{};
+  double *CM = nullptr, *rho = nullptr, *Cb = nullptr;
+  SysInfo* d_info = nullptr;
+  SysState* d_st = nullptr;
+  SysState* h_st = nullptr;   // pinned
+  std::vector<SysInfo> h_info;
+  double* d_hist = nullptr;
+  bool prepared = false, hs_cast = false, ran = false;
+  Prec prec = P64;
+  std::vector<void*> alloc_init, alloc_prep;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  int graph_iters = 0;
+  // timing
+  bool timing = false;
+  double kt_ms[3] = {0, 0, 0};
+  int64_t kt_n[3] = {0, 0, 0};
+  std::vector<hipEvent_t> ev;
+};
+
+namespace {
+
+template <typename T>
+T* dalloc(omm_ctx* c, size_t n, bool prep) {
+  if (n == 0) n = 1;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, n * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw OomError("hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed");
+  }
+  (prep ? c->alloc_prep : c->alloc_init).push_back(p);
+  return (T*)p;
+}
+
+template <typename T>
+T* dupload(omm_ctx* c, const std::vector<T>& v, bool prep) {
+  T* p = dalloc<T>(c, v.size(), prep);
+  if (!v.empty()) OMM_HIP(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+  return p;
+}
+
+template <typename T>
+std::vector<T> ddownload(omm_ctx* c, const T* p, size_t n) {
+  std::vector<T> v(n);
+  if (n) {
+    OMM_HIP(hipMemcpyAsync(v.data(), p, n * sizeof(T), hipMemcpyDeviceToHost, c->stream));
+    OMM_HIP(hipStreamSynchronize(c->stream));
+  }
+  return v;
+}
+
+void free_list(std::vector<void*>& l) {
+  for (void* p : l) (void)hipFree(p);
+  l.clear();
+}
+
+void copy_desc(MatDesc& d, const omm_matrix* M, const char* name) {
+  if (!M) throw ArgError(std::string(name) + " is NULL");
+  if (M->nbrow <= 0 || M->nbcol <= 0) throw ArgError(std::string(name) + ": empty block structure");
+  if (!M->row_bsz || !M->col_bsz || !M->row_ptr || !M->col_idx || !M->val_off || !M->val)
+    throw ArgError(std::string(name) + ": NULL array");
+  if (M->memspace != OMM_HOST && M->memspace != OMM_DEVICE) throw ArgError(std::string(name) + ": bad memspace");
+  d.nbrow = M->nbrow;
+  d.nbcol = M->nbcol;
+  d.rbs.assign(M->row_bsz, M->row_bsz + M->nbrow);
+  d.cbs.assign(M->col_bsz, M->col_bsz + M->nbcol);
+  for (int v : d.rbs) if (v <= 0) throw ArgError(std::string(name) + ": non-positive row block size");
+  for (int v : d.cbs) if (v <= 0) throw ArgError(std::string(name) + ": non-positive column block size");
+  d.rp.assign(M->row_ptr, M->row_ptr + M->nbrow + 1);
+  if (d.rp[0] != 0) throw ArgError(std::string(name) + ": row_ptr[0] != 0");
+  for (int i = 0; i < M->nbrow; ++i)
+    if (d.rp[i + 1] < d.rp[i]) throw ArgError(std::string(name) + ": row_ptr not monotone");
+  const int64_t nnzb = d.rp[M->nbrow];
+  d.ci.assign(M->col_idx, M->col_idx + nnzb);
+  d.voff.assign(M->val_off, M->val_off + nnzb);
+  d.nval = M->nval;
+  for (int i = 0; i < M->nbrow; ++i)
+    for (int64_t k = d.rp[i]; k < d.rp[i + 1]; ++k) {
+      const int j = d.ci[k];
+      if (j < 0 || j >= M->nbcol) throw ArgError(std::string(name) + ": column index out of range");
+      if (k > d.rp[i] && d.ci[k - 1] >= j) throw ArgError(std::string(name) + ": columns not strictly increasing");
+      const int64_t sz = (int64_t)d.rbs[i] * d.cbs[j];
+      if (d.voff[k] < 0 || d.voff[k] + sz > d.nval) throw ArgError(std::string(name) + ": val_off out of range");
+    }
+}
+
+// upload values (host or device) into a fresh device buffer owned by the caller of this helper
+double* values_on_device(omm_ctx* c, const omm_matrix* M, std::vector<void*>& tmp) {
+  if (M->memspace == OMM_DEVICE) return const_cast<double*>(M->val);
+  void* p = nullptr;
+  if (hipMalloc(&p, std::max<int64_t>(1, M->nval) * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    throw OomError("staging allocation failed");
+  }
+  tmp.push_back(p);
+  OMM_HIP(hipMemcpyAsync(p, M->val, M->nval * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  return (double*)p;
+}
+
+DevMap upload_map(omm_ctx* c, const MatDesc& d, bool prep) {
+  DevMap m;
+  std::vector<int> br, bc;
+  br.reserve(d.ci.size());
+  for (int i = 0; i < d.nbrow; ++i)
+    for (int64_t k = d.rp[i]; k < d.rp[i + 1]; ++k) br.push_back(i);
+  bc = d.ci;
+  m.nblk = (int)d.ci.size();
+  m.brow = dupload(c, br, prep);
+  m.bcol = dupload(c, bc, prep);
+  m.voff = dupload(c, d.voff, prep);
+  return m;
+}
+
+BlkMap blkmap(const DevMap& dm, const int64_t* voff, const SysHost& s, bool wf_cols, const Pat& P) {
+  BlkMap m;
+  m.nblk = dm.nblk;
+  m.brow = dm.brow;
+  m.bcol = dm.bcol;
+  m.voff = voff ? voff : dm.voff;
+  m.ro = s.ro;
+  m.rtile = s.rtile;
+  m.roff = s.roff;
+  if (wf_cols) {
+    m.co = s.co;
+    m.ctile = s.wtile;
+    m.coff = s.woff;
+  } else {
+    m.co = s.ro;
+    m.ctile = s.rtile;
+    m.coff = s.roff;
+  }
+  m.P = P.view();
+  return m;
+}
+
+void set_err(omm_ctx* c, const std::string& m) {
+  if (c) c->err = m;
+  else g_last_init_error = m;
+}
+
+// ----------------------------------------------------------------- pattern helpers
+void upload_pat(omm_ctx* c, Pat& P, int nrows, const std::vector<std::vector<int>>& rows, bool prep) {
+  P.nrows = nrows;
+  P.hrp.assign(nrows + 1, 0);
+  std::vector<int> ci, rw;
+  for (int r = 0; r < nrows; ++r) {
+    P.hrp[r + 1] = P.hrp[r] + (int)rows[r].size();
+    for (int v : rows[r]) {
+      ci.push_back(v);
+      rw.push_back(r);
+    }
+  }
+  P.nnz = P.hrp[nrows];
+  P.rp = dupload(c, P.hrp, prep);
+  P.ci = dupload(c, ci, prep);
+  P.row = dupload(c, rw, prep);
+}
+
+// O = A * B (tile patterns) on the device
+void sym_product(omm_ctx* c, Pat& O, int nrows, const Pat& A, const Pat& B, const int2* win) {
+  hipStream_t s = c->stream;
+  int* cnt = dalloc<int>(c, nrows + 1, true);
+  OMM_HIP(hipMemsetAsync(cnt, 0, (nrows + 1) * sizeof(int), s));
+  sym_count(s, nrows, 0, A.view(), B.view(), win, cnt);
+  O.nrows = nrows;
+  O.rp = dalloc<int>(c, nrows + 1, true);
+  excl_scan(s, cnt, O.rp, nrows + 1);
+  O.hrp = ddownload(c, O.rp, nrows + 1);
+  O.nnz = O.hrp[nrows];
+  O.ci = dalloc<int>(c, O.nnz, true);
+  O.row = dalloc<int>(c, O.nnz, true);
+  sym_fill(s, nrows, 0, A.view(), B.view(), win, O.rp, O.ci, O.row);
+}
+
+void make_plan(omm_ctx* c, Plan& P, const Pat& O, const PatView& A, const PatView& B, const int2* win) {
+  hipStream_t s = c->stream;
+  P.nout = (int)O.nnz;
+  int64_t* cnt = dalloc<int64_t>(c, O.nnz + 1, true);
+  OMM_HIP(hipMemsetAsync(cnt, 0, (O.nnz + 1) * sizeof(int64_t), s));
+  PatView Ov = O.view();
+  Ov.ti = nullptr;
+  pair_count(s, O.nrows, 0, A, B, Ov, win, cnt);
+  P.pp = dalloc<int64_t>(c, O.nnz + 1, true);
+  excl_scan64(s, cnt, P.pp, O.nnz + 1);
+  P.hpp = ddownload(c, P.pp, O.nnz + 1);
+  P.npairs = P.hpp[O.nnz];
+  P.pairs = dalloc<int2>(c, P.npairs, true);
+  pair_fill(s, O.nrows, 0, A, B, Ov, win, P.pp, P.pairs);
+}
+
+// ----------------------------------------------------------------- work counts (host)
+struct Bits {
+  int nw = 0;
+  std::vector<uint64_t> w;
+  void init(int rows, int cols) {
+    nw = (cols + 63) / 64;
+    w.assign((size_t)rows * nw, 0);
+  }
+  uint64_t* row(int r) { return &w[(size_t)r * nw]; }
+};
+
+void count_sparse_work(SysHost& s) {
+  const MatDesc& H = s.H;
+  const MatDesc& C = s.C0;
+  const int nb = H.nbrow, na = C.nbcol;
+  std::vector<double> csum(nb, 0.0);   // sum of WF block widths in each C block row
+  for (int b = 0; b < nb; ++b)
+    for (int64_t k = C.rp[b]; k < C.rp[b + 1]; ++k) csum[b] += C.cbs[C.ci[k]];
+  Bits Crow, HC, W;
+  Crow.init(nb, na);
+  for (int b = 0; b < nb; ++b)
+    for (int64_t k = C.rp[b]; k < C.rp[b + 1]; ++k) Crow.row(b)[C.ci[k] >> 6] |= 1ull << (C.ci[k] & 63);
+  HC.init(nb, na);
+  double f1 = 0.0;
+  for (int b = 0; b < nb; ++b) {
+    uint64_t* o = HC.row(b);
+    for (int64_t e = H.rp[b]; e < H.rp[b + 1]; ++e) {
+      const int k = H.ci[e];
+      const uint64_t* src = Crow.row(k);
+      for (int w = 0; w < HC.nw; ++w) o[w] |= src[w];
+      f1 += 2.0 * H.rbs[b] * H.rbs[k] * csum[k];
+    }
+  }
+  // average WF block width (uniform in practice)
+  double wsum = 0.0;
+  for (int v : C.cbs) wsum += v;
+  const double wavg = wsum / std::max(1, na);
+  double f2 = 0.0, nhc_el = 0.0;
+  W.init(na, na);
+  for (int k = 0; k < nb; ++k) {
+    double hcw = 0.0;
+    const uint64_t* hr = HC.row(k);
+    for (int w = 0; w < HC.nw; ++w) hcw += __builtin_popcountll(hr[w]);
+    nhc_el += hcw * wavg * H.rbs[k];
+    f2 += 2.0 * csum[k] * H.rbs[k] * hcw * wavg;
+    for (int64_t e = C.rp[k]; e < C.rp[k + 1]; ++e) {
+      uint64_t* o = W.row(C.ci[e]);
+      for (int w = 0; w < W.nw; ++w) o[w] |= hr[w];
+    }
+  }
+  double f3 = 0.0, nw_el = 0.0, nc_el = 0.0;
+  for (int a = 0; a < na; ++a) {
+    const uint64_t* wr = W.row(a);
+    for (int w = 0; w < W.nw; ++w) nw_el += __builtin_popcountll(wr[w]) * wavg * C.cbs[a];
+  }
+  for (int b = 0; b < nb; ++b)
+    for (int64_t e = C.rp[b]; e < C.rp[b + 1]; ++e) {
+      const int a = C.ci[e];
+      nc_el += (double)H.rbs[b] * C.cbs[a];
+      const uint64_t* hr = HC.row(b);
+      const uint64_t* wr = W.row(a);
+      double cnt = 0.0;
+      for (int w = 0; w < W.nw; ++w) cnt += __builtin_popcountll(hr[w] & wr[w]);
+      f3 += 2.0 * H.rbs[b] * cnt * wavg * C.cbs[a];
+    }
+  double nh_el = 0.0;
+  for (int b = 0; b < nb; ++b)
+    for (int64_t e = H.rp[b]; e < H.rp[b + 1]; ++e) nh_el += (double)H.rbs[b] * H.rbs[H.ci[e]];
+  const bool ident = s.mode == OMM_DENSE_CHOLESKY;
+  s.flops_alg[0] = (ident ? 1.0 : 2.0) * f1;
+  s.flops_alg[1] = 4.0 * f2;
+  s.flops_alg[2] = 2.0 * f3;
+  // one pass over every operand and output of the three product steps, FP64
+  s.bytes_alg = 8.0 * ((ident ? 1 : 2) * nh_el + nc_el + 2 * nhc_el) +          // S1
+                8.0 * (2 * nc_el + 2 * nhc_el + 4 * nw_el) +                     // S2
+                8.0 * (2 * nhc_el + 2 * nw_el + nc_el);                           // gradient
+}
+
+void count_dense_work(SysHost& s) {
+  const double m = (double)s.m, n = (double)s.n;
+  const bool ident = s.mode == OMM_DENSE_CHOLESKY;
+  s.flops_alg[0] = (ident ? 1.0 : 2.0) * 2.0 * m * m * n;
+  s.flops_alg[1] = 4.0 * 2.0 * m * n * n;
+  s.flops_alg[2] = 2.0 * 2.0 * m * n * n;
+  s.bytes_alg = 8.0 * ((ident ? 1 : 2) * m * m + m * n + 2 * m * n) + 8.0 * (4 * m * n + 4 * n * n) +
+                8.0 * (3 * m * n + 2 * n * n);
+}
+
+// ----------------------------------------------------------------- init (H, S ingest)
+void ingest(omm_ctx* c, int count, const omm_matrix* H, const omm_matrix* S, const int64_t* n_occ,
+            const int32_t* modes) {
+  c->nsys = count;
+  c->sys.resize(count);
+  // validation (host only)
+  for (int i = 0; i < count; ++i) {
+    SysHost& s = c->sys[i];
+    copy_desc(s.H, &H[i], "H");
+    copy_desc(s.S, &S[i], "S");
+    if (!s.H.same_pattern(s.S)) throw ArgError("H and S must share their block structure");
+    if (s.H.nbrow != s.H.nbcol || s.H.rbs != s.H.cbs) throw ArgError("H must be square with square diagonal blocks");
+    for (int b = 0; b < s.H.nbrow; ++b) {
+      bool diag = false;
+      for (int64_t k = s.H.rp[b]; k < s.H.rp[b + 1]; ++k) diag |= (s.H.ci[k] == b);
+      if (!diag) throw ArgError("every diagonal block of H and S must be stored");
+    }
+    s.mode = modes ? modes[i] : OMM_DENSE;
+    if (s.mode != OMM_DENSE && s.mode != OMM_DENSE_CHOLESKY && s.mode != OMM_BLOCK_SPARSE)
+      throw ArgError("unknown mode");
+    s.m = 0;
+    for (int v : s.H.rbs) s.m += v;
+    s.n = n_occ[i];
+    if (s.n < 1 || s.n > s.m) throw ArgError("n_occ must satisfy 1 <= n_occ <= m");
+    s.eta = c->opt.eta;
+    if (s.mode == OMM_BLOCK_SPARSE)
+      for (int v : s.H.rbs)
+        if (v > 16) throw ArgError("block-sparse mode needs basis blocks of at most 16 orbitals");
+    const int64_t dense_tiles = ((s.m + 15) / 16) * ((s.m + 15) / 16);
+    if (s.mode != OMM_BLOCK_SPARSE && dense_tiles > (int64_t)1 << 27)
+      throw ArgError("dense mode: basis too large");
+  }
+  hipStream_t st = c->stream;
+  // basis maps
+  int rb = 0;
+  for (int i = 0; i < count; ++i) {
+    SysHost& s = c->sys[i];
+    s.r_tile.resize(s.m);
+    s.r_off.resize(s.m);
+    if (s.mode == OMM_BLOCK_SPARSE) {
+      int64_t e = 0;
+      for (int b = 0; b < s.H.nbrow; ++b)
+        for (int k = 0; k < s.H.rbs[b]; ++k, ++e) {
+          s.r_tile[e] = b;
+          s.r_off[e] = k;
+        }
+      s.RT = s.H.nbrow;
+    } else {
+      for (int64_t e = 0; e < s.m; ++e) {
+        s.r_tile[e] = (int)(e / 16);
+        s.r_off[e] = (int)(e % 16);
+      }
+      s.RT = (int)((s.m + 15) / 16);
+    }
+    if (s.RT > MAXW) throw ArgError("system too large for one symbolic window");
+    s.rb0 = rb;
+    rb += s.RT;
+  }
+  c->NB = rb;
+  // H/S tile pattern
+  std::vector<std::vector<int>> rows(c->NB);
+  std::vector<int> bsys(c->NB);
+  for (int i = 0; i < count; ++i) {
+    SysHost& s = c->sys[i];
+    for (int r = 0; r < s.RT; ++r) bsys[s.rb0 + r] = i;
+    if (s.mode == OMM_BLOCK_SPARSE) {
+      for (int b = 0; b < s.H.nbrow; ++b)
+        for (int64_t k = s.H.rp[b]; k < s.H.rp[b + 1]; ++k) rows[s.rb0 + b].push_back(s.rb0 + s.H.ci[k]);
+    } else {
+      for (int r = 0; r < s.RT; ++r)
+        for (int q = 0; q < s.RT; ++q) rows[s.rb0 + r].push_back(s.rb0 + q);
+    }
+  }
+  upload_pat(c, c->TH, c->NB, rows, false);
+  c->brow_sys = dupload(c, bsys, false);
+  const size_t nth = (size_t)c->TH.nnz;
+  c->H = dalloc<double>(c, nth * TE, false);
+  c->S = dalloc<double>(c, nth * TE, false);
+  OMM_HIP(hipMemsetAsync(c->H, 0, nth * TE * sizeof(double), st));
+  OMM_HIP(hipMemsetAsync(c->S, 0, nth * TE * sizeof(double), st));
+  std::vector<void*> tmp;
+  for (int i = 0; i < count; ++i) {
+    SysHost& s = c->sys[i];
+    std::vector<int> ro(s.H.nbrow + 1, 0), rtile(s.m), roff(s.m);
+    for (int b = 0; b < s.H.nbrow; ++b) ro[b + 1] = ro[b] + s.H.rbs[b];
+    for (int64_t e = 0; e < s.m; ++e) {
+      rtile[e] = s.rb0 + s.r_tile[e];
+      roff[e] = s.r_off[e];
+    }
+    s.ro = dupload(c, ro, false);
+    s.rtile = dupload(c, rtile, false);
+    s.roff = dupload(c, roff, false);
+    s.mh = upload_map(c, s.H, false);
+    s.s_voff = dupload(c, s.S.voff, false);
+    const double* hv = values_on_device(c, &H[i], tmp);
+    const double* sv = values_on_device(c, &S[i], tmp);
+    launch_scatter(st, blkmap(s.mh, nullptr, s, false, c->TH), hv, c->H);
+    launch_scatter(st, blkmap(s.mh, s.s_voff, s, false, c->TH), sv, c->S);
+  }
+  OMM_HIP(hipStreamSynchronize(st));
+  for (void* p : tmp) (void)hipFree(p);
+  // Kim shift and Cholesky reduction
+  for (int i = 0; i < count; ++i) {
+    SysHost& s = c->sys[i];
+    const int h0 = c->TH.hrp[s.rb0], h1 = c->TH.hrp[s.rb0 + s.RT];
+    if (s.eta != 0.0)
+      launch_axpy_tiles(st, h1 - h0, -s.eta, c->S + (size_t)h0 * TE, c->H + (size_t)h0 * TE);
+    if (s.mode == OMM_DENSE_CHOLESKY) {
+      launch_pad_identity(st, c->S, h0, s.RT, s.m);
+      s.Linv = dalloc<double>(c, (size_t)s.RT * TE, false);
+      s.chol_status = dalloc<int>(c, 1, false);
+      OMM_HIP(hipMemsetAsync(s.chol_status, 0, sizeof(int), st));
+      chol_factor(st, c->S, h0, s.RT, s.Linv, s.chol_status);
+      int flag = 0;
+      OMM_HIP(hipMemcpyAsync(&flag, s.chol_status, sizeof(int), hipMemcpyDeviceToHost, st));
+      OMM_HIP(hipStreamSynchronize(st));
+      if (flag) throw ArgError("__NOT_SPD__");
+      double* work = nullptr;
+      if (hipMalloc(&work, (size_t)s.RT * s.RT * TE * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        throw OomError("Cholesky work buffer");
+      }
+      chol_reduce_h(st, c->S, h0, s.RT, s.Linv, c->H, h0, work);
+      OMM_HIP(hipStreamSynchronize(st));
+      (void)hipFree(work);
+    }
+  }
+  OMM_HIP(hipStreamSynchronize(st));
+}
+
+// ----------------------------------------------------------------- prepare (C pattern dependent)
+void prepare(omm_ctx* c) {
+  hipStream_t st = c->stream;
+  OMM_HIP(hipStreamSynchronize(st));
+  if (c->gexec) {
+    (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+  }
+  if (c->graph) {
+    (void)hipGraphDestroy(c->graph);
+    c->graph = nullptr;
+  }
+  free_list(c->alloc_prep);
+  c->hs_cast = false;
+  const bool low = c->prec != P64;
+  // WF maps
+  int wb = 0;
+  for (int i = 0; i < c->nsys; ++i) {
+    SysHost& s = c->sys[i];
+    s.w_tile.assign(s.n, 0);
+    s.w_off.assign(s.n, 0);
+    if (s.mode == OMM_BLOCK_SPARSE) {
+      int tile = 0, off = 0;
+      int64_t e = 0;
+      for (int a = 0; a < s.C0.nbcol; ++a) {
+        const int cb = s.C0.cbs[a];
+        if (off + cb > 16) {
+          ++tile;
+          off = 0;
+        }
+        for (int k = 0; k < cb; ++k, ++e) {
+          s.w_tile[e] = tile;
+          s.w_off[e] = off + k;
+        }
+        off += cb;
+      }
+      s.WT = tile + 1;
+    } else {
+      for (int64_t e = 0; e < s.n; ++e) {
+        s.w_tile[e] = (int)(e / 16);
+        s.w_off[e] = (int)(e % 16);
+      }
+      s.WT = (int)((s.n + 15) / 16);
+    }
+    if (s.WT > MAXW) throw ArgError("too many wavefunction tiles for one symbolic window");
+    s.wb0 = wb;
+    wb += s.WT;
+  }
+  c->NW = wb;
+  // C tile pattern, masks, segments, element maps
+  std::vector<std::vector<int>> crow(c->NB);
+  std::vector<std::vector<uint32_t>> cmk(c->NB);
+  std::vector<uint8_t> wseg((size_t)c->NW * 32, 0);
+  std::vector<int> welem((size_t)c->NW * 16, -1), wsys(c->NW);
+  std::vector<int2> win_bw(c->NB), win_bb(c->NB), win_ww(c->NW), win_wb(c->NW);
+  for (int i = 0; i < c->nsys; ++i) {
+    SysHost& s = c->sys[i];
+    for (int r = 0; r < s.RT; ++r) {
+      win_bw[s.rb0 + r] = make_int2(s.wb0, s.wb0 + s.WT);
+      win_bb[s.rb0 + r] = make_int2(s.rb0, s.rb0 + s.RT);
+    }
+    for (int g = 0; g < s.WT; ++g) {
+      win_ww[s.wb0 + g] = make_int2(s.wb0, s.wb0 + s.WT);
+      win_wb[s.wb0 + g] = make_int2(s.rb0, s.rb0 + s.RT);
+      wsys[s.wb0 + g] = i;
+      for (int k = 0; k < 16; ++k) {   // padding columns: own 1-wide segment
+        wseg[(size_t)(s.wb0 + g) * 32 + k] = (uint8_t)k;
+        wseg[(size_t)(s.wb0 + g) * 32 + 16 + k] = (uint8_t)(k + 1);
+      }
+    }
+    // element map of WF columns and segments of WF blocks
+    std::vector<int> co(s.C0.nbcol + 1, 0);
+    for (int a = 0; a < s.C0.nbcol; ++a) co[a + 1] = co[a] + s.C0.cbs[a];
+    for (int a = 0; a < s.C0.nbcol; ++a) {
+      const int e0 = co[a], e1 = co[a + 1];
+      const int g = s.wb0 + s.w_tile[e0];
+      const int lo = s.w_off[e0], hi = s.w_off[e1 - 1] + 1;
+      for (int e = e0; e < e1; ++e) {
+        const int gg = s.wb0 + s.w_tile[e];
+        welem[(size_t)gg * 16 + s.w_off[e]] = e;
+        if (s.mode == OMM_BLOCK_SPARSE && gg == g) {
+          wseg[(size_t)g * 32 + s.w_off[e]] = (uint8_t)lo;
+          wseg[(size_t)g * 32 + 16 + s.w_off[e]] = (uint8_t)hi;
+        }
+      }
+    }
+    // row masks of basis tiles
+    std::vector<uint32_t> rmask(s.RT, 0);
+    for (int64_t e = 0; e < s.m; ++e) rmask[s.r_tile[e]] |= 1u << s.r_off[e];
+    if (s.mode == OMM_BLOCK_SPARSE) {
+      for (int b = 0; b < s.C0.nbrow; ++b) {
+        std::vector<std::pair<int, uint32_t>> tiles;   // (local WF tile, column bits)
+        for (int64_t k = s.C0.rp[b]; k < s.C0.rp[b + 1]; ++k) {
+          const int a = s.C0.ci[k];
+          const int g = s.w_tile[co[a]];
+          uint32_t bits = 0;
+          for (int e = co[a]; e < co[a + 1]; ++e) bits |= 1u << s.w_off[e];
+          if (!tiles.empty() && tiles.back().first == g) tiles.back().second |= bits;
+          else tiles.emplace_back(g, bits);
+        }
+        for (auto& tb : tiles) {
+          crow[s.rb0 + b].push_back(s.wb0 + tb.first);
+          cmk[s.rb0 + b].push_back(rmask[b] | (tb.second << 16));
+        }
+      }
+    } else {
+      std::vector<uint32_t> colmask(s.WT, 0);
+      for (int64_t e = 0; e < s.n; ++e) colmask[s.w_tile[e]] |= 1u << s.w_off[e];
+      for (int r = 0; r < s.RT; ++r)
+        for (int g = 0; g < s.WT; ++g) {
+          crow[s.rb0 + r].push_back(s.wb0 + g);
+          cmk[s.rb0 + r].push_back(rmask[r] | (colmask[g] << 16));
+        }
+    }
+  }
+  upload_pat(c, c->TC, c->NB, crow, true);
+  {
+    std::vector<uint32_t> flat;
+    for (auto& v : cmk) flat.insert(flat.end(), v.begin(), v.end());
+    c->cmask = dupload(c, flat, true);
+  }
+  c->wseg = dupload(c, wseg, true);
+  c->welem = dupload(c, welem, true);
+  c->wrow_sys = dupload(c, wsys, true);
+  c->win_bw = dupload(c, win_bw, true);
+  c->win_bb = dupload(c, win_bb, true);
+  c->win_ww = dupload(c, win_ww, true);
+  c->win_wb = dupload(c, win_wb, true);
+  // per-system C maps
+  for (int i = 0; i < c->nsys; ++i) {
+    SysHost& s = c->sys[i];
+    std::vector<int> co(s.C0.nbcol + 1, 0), wtile(s.n), woff(s.n);
+    for (int a = 0; a < s.C0.nbcol; ++a) co[a + 1] = co[a] + s.C0.cbs[a];
+    for (int64_t e = 0; e < s.n; ++e) {
+      wtile[e] = s.wb0 + s.w_tile[e];
+      woff[e] = s.w_off[e];
+    }
+    s.co = dupload(c, co, true);
+    s.wtile = dupload(c, wtile, true);
+    s.woff = dupload(c, woff, true);
+    s.mc = upload_map(c, s.C0, true);
+  }
+  // transposed C pattern: rows = WF tiles, entries = (basis tile, C tile index)
+  {
+    Pat& T = c->TCt;
+    T.nrows = c->NW;
+    int* cnt = dalloc<int>(c, c->NW + 1, true);
+    OMM_HIP(hipMemsetAsync(cnt, 0, (c->NW + 1) * sizeof(int), st));
+    transpose_count(st, c->NW, 0, c->TC.view(), c->win_wb, cnt);
+    T.rp = dalloc<int>(c, c->NW + 1, true);
+    excl_scan(st, cnt, T.rp, c->NW + 1);
+    T.hrp = ddownload(c, T.rp, c->NW + 1);
+    T.nnz = T.hrp[c->NW];
+    T.ci = dalloc<int>(c, T.nnz, true);
+    T.ti = dalloc<int>(c, T.nnz, true);
+    transpose_fill(st, c->NW, 0, c->TC.view(), c->win_wb, T.rp, T.ci, T.ti);
+  }
+  // product patterns
+  sym_product(c, c->THC, c->NB, c->TH, c->TC, c->win_bw);
+  {
+    Pat At = c->TCt;
+    At.ti = nullptr;   // pattern only
+    sym_product(c, c->TW, c->NW, At, c->THC, c->win_ww);
+  }
+  sym_product(c, c->TCM, c->NB, c->TC, c->TW, c->win_bw);
+  // work lists
+  make_plan(c, c->Ps1, c->THC, c->TH.view(), c->TC.view(), c->win_bw);
+  make_plan(c, c->Ps2, c->TW, c->TCt.view(), c->THC.view(), c->win_ww);
+  make_plan(c, c->Pgrad, c->TC, c->THC.view(), c->TW.view(), c->win_bw);
+  make_plan(c, c->Pcm, c->TCM, c->TC.view(), c->TW.view(), c->win_bw);
+  make_plan(c, c->Prho, c->TH, c->TCM.view(), c->TCt.view(), c->win_bb);
+  // lookups
+  c->c_in_hc = dalloc<int>(c, c->TC.nnz, true);
+  find_tiles(st, c->TC.nnz, c->TC.row, c->TC.ci, c->THC.view(), c->c_in_hc);
+  c->hc_to_c = dalloc<int>(c, c->THC.nnz, true);
+  find_tiles(st, c->THC.nnz, c->THC.row, c->THC.ci, c->TC.view(), c->hc_to_c);
+  c->w_tr = dalloc<int>(c, c->TW.nnz, true);
+  {
+    // (col, row) of each n x n tile, with rows/cols in the same WF index space
+    find_tiles(st, c->TW.nnz, c->TW.ci, c->TW.row, c->TW.view(), c->w_tr);
+  }
+  {
+    std::vector<int> chk = ddownload(c, c->c_in_hc, c->TC.nnz);
+    for (int v : chk)
+      if (v < 0) throw ArgError("internal: C tile outside the HC pattern (missing diagonal block?)");
+    std::vector<int> wt = ddownload(c, c->w_tr, c->TW.nnz);
+    for (int v : wt)
+      if (v < 0) throw ArgError("internal: n x n pattern not symmetric (H not symmetric in pattern?)");
+  }
+  // per-system ranges, chunks, info
+  const int CH = 8;
+  std::vector<int4> chunks;
+  c->h_info.assign(c->nsys, SysInfo{});
+  for (int i = 0; i < c->nsys; ++i) {
+    SysHost& s = c->sys[i];
+    SysInfo& f = c->h_info[i];
+    f.rb0 = s.rb0; f.rb1 = s.rb0 + s.RT;
+    f.wb0 = s.wb0; f.wb1 = s.wb0 + s.WT;
+    f.h0 = c->TH.hrp[f.rb0]; f.h1 = c->TH.hrp[f.rb1];
+    f.c0 = c->TC.hrp[f.rb0]; f.c1 = c->TC.hrp[f.rb1];
+    f.hc0 = c->THC.hrp[f.rb0]; f.hc1 = c->THC.hrp[f.rb1];
+    f.w0 = c->TW.hrp[f.wb0]; f.w1 = c->TW.hrp[f.wb1];
+    f.ch0 = (int)chunks.size();
+    for (int t = f.w0; t < f.w1; t += CH) chunks.push_back(make_int4(t, std::min(t + CH, f.w1), i, 0));
+    f.ch1 = (int)chunks.size();
+    f.mode = s.mode;
+    f.ident_s = s.mode == OMM_DENSE_CHOLESKY ? 1 : 0;
+    f.target_low = low ? 1 : 0;
+    f.m = s.m;
+    f.n = s.n;
+    f.eta = s.eta;
+    f.eps2 = s.mode == OMM_BLOCK_SPARSE ? c->opt.filter_eps * c->opt.filter_eps : 0.0;
+    s.tiles_h = f.h1 - f.h0;
+    s.tiles_c = f.c1 - f.c0;
+    s.tiles_hc = f.hc1 - f.hc0;
+    s.tiles_w = f.w1 - f.w0;
+    s.pairs[0] = c->Ps1.hpp[f.hc1] - c->Ps1.hpp[f.hc0];
+    s.pairs[1] = c->Ps2.hpp[f.w1] - c->Ps2.hpp[f.w0];
+    s.pairs[2] = c->Pgrad.hpp[f.c1] - c->Pgrad.hpp[f.c0];
+    const double tf = 2.0 * 16 * 16 * 16;
+    s.flops_exec[0] = (f.ident_s ? 1.0 : 2.0) * tf * s.pairs[0];
+    s.flops_exec[1] = 4.0 * tf * s.pairs[1];
+    s.flops_exec[2] = 2.0 * tf * s.pairs[2];
+    if (s.mode == OMM_BLOCK_SPARSE) count_sparse_work(s);
+    else count_dense_work(s);
+  }
+  c->nchunks = (int)chunks.size();
+  c->chunks = dupload(c, chunks, true);
+  c->d_info = dupload(c, c->h_info, true);
+  c->d_st = dalloc<SysState>(c, c->nsys, true);
+  c->d_hist = dalloc<double>(c, c->opt.history ? (size_t)c->nsys * c->opt.history_max * HCOLS : 1, true);
+  // tile buffers
+  const size_t ntc = c->TC.nnz, nhc = c->THC.nnz, ntw = c->TW.nnz;
+  Bufs& b = c->b;
+  b = Bufs{};
+  b.th_row = c->TH.row; b.th_col = c->TH.ci;
+  b.tc_row = c->TC.row; b.tc_col = c->TC.ci;
+  b.thc_row = c->THC.row; b.thc_col = c->THC.ci;
+  b.tw_row = c->TW.row; b.tw_col = c->TW.ci;
+  b.brow_sys = c->brow_sys; b.wrow_sys = c->wrow_sys;
+  b.c_in_hc = c->c_in_hc; b.hc_to_c = c->hc_to_c; b.w_tr = c->w_tr;
+  b.cmask = c->cmask; b.wseg = c->wseg; b.chunks = c->chunks; b.nchunks = c->nchunks;
+  b.n_th = (int)c->TH.nnz; b.n_tc = (int)ntc; b.n_thc = (int)nhc; b.n_tw = (int)ntw;
+  b.s1 = c->Ps1.view(); b.s2 = c->Ps2.view(); b.grad = c->Pgrad.view();
+  b.H = c->H; b.S = c->S;
+  b.C = dalloc<double>(c, ntc * TE, true);
+  b.D = dalloc<double>(c, ntc * TE, true);
+  b.G = dalloc<double>(c, ntc * TE, true);
+  b.Gold = dalloc<double>(c, ntc * TE, true);
+  b.HC = dalloc<double>(c, nhc * TE, true);
+  b.SC = dalloc<double>(c, nhc * TE, true);
+  b.HD = dalloc<double>(c, nhc * TE, true);
+  b.SD = dalloc<double>(c, nhc * TE, true);
+  b.H0 = dalloc<double>(c, ntw * TE, true);
+  b.S0 = dalloc<double>(c, ntw * TE, true);
+  b.X = dalloc<double>(c, ntw * TE, true);
+  b.Y = dalloc<double>(c, ntw * TE, true);
+  b.S2 = dalloc<double>(c, ntw * TE, true);
+  b.H2 = dalloc<double>(c, ntw * TE, true);
+  for (double* p : {b.C, b.D, b.G, b.Gold}) OMM_HIP(hipMemsetAsync(p, 0, ntc * TE * sizeof(double), st));
+  if (low) {
+    const size_t es = c->prec == P32 ? 4 : 2;
+    auto lal = [&](size_t ntiles) { return (void*)dalloc<uint8_t>(c, ntiles * TE * es, true); };
+    b.Hl = c->Hl = lal(c->TH.nnz);
+    b.Sl = c->Sl = lal(c->TH.nnz);
+    b.Cl = lal(ntc); b.Dl = lal(ntc);
+    b.HCl = lal(nhc); b.SCl = lal(nhc);
+    b.H0l = lal(ntw); b.S0l = lal(ntw);
+    b.HDf = dalloc<float>(c, nhc * TE, true);
+    b.SDf = dalloc<float>(c, nhc * TE, true);
+    b.Xf = dalloc<float>(c, ntw * TE, true);
+    b.Yf = dalloc<float>(c, ntw * TE, true);
+    b.S2f = dalloc<float>(c, ntw * TE, true);
+    b.H2f = dalloc<float>(c, ntw * TE, true);
+  }
+  b.tpart = dalloc<double>(c, (size_t)std::max(1, c->nchunks) * NSUM, true);
+  b.gpart = dalloc<double>(c, std::max<size_t>(1, ntc) * 2, true);
+  b.info = c->d_info;
+  b.st = c->d_st;
+  b.hist = c->d_hist;
+  b.nsys = c->nsys;
+  b.eps2 = 0.0;
+  c->CM = dalloc<double>(c, std::max<int64_t>(1, c->TCM.nnz) * TE, true);
+  c->rho = dalloc<double>(c, std::max<int64_t>(1, c->TH.nnz) * TE, true);
+  bool any_chol = false;
+  for (auto& s : c->sys) any_chol |= s.mode == OMM_DENSE_CHOLESKY;
+  c->Cb = any_chol ? dalloc<double>(c, ntc * TE, true) : nullptr;
+  OMM_HIP(hipStreamSynchronize(st));
+  c->prepared = true;
+}
+
+CGParams params(const omm_ctx* c) {
+  CGParams p{};
+  p.tol_grad = c->opt.tol_grad;
+  p.rel_tol = c->opt.rel_tol;
+  p.low_switch = c->opt.lowprec_rel_switch > 0 ? c->opt.lowprec_rel_switch : (c->prec == PBF ? 1e-5 : 1e-7);
+  p.filter_eps = c->opt.filter_eps;
+  p.max_iter = c->opt.max_iter;
+  p.low_max_iter = c->opt.lowprec_max_iter > 0 ? c->opt.lowprec_max_iter : c->opt.max_iter;
+  p.refine_iters = c->opt.fp64_refine_iters;
+  p.hist_max = c->opt.history_max;
+  p.hist_on = c->opt.history ? 1 : 0;
+  p.low_prec = (int)c->prec;
+  return p;
+}
+
+bool any_filter(const omm_ctx* c) {
+  for (auto& f : c->h_info)
+    if (f.eps2 > 0.0) return true;
+  return false;
+}
+
+void timed(omm_ctx* c, int cls, bool on, void (*fn)(omm_ctx*, void*), void* arg) {
+  if (!on) {
+    fn(c, arg);
+    return;
+  }
+  hipEvent_t a, b;
+  OMM_HIP(hipEventCreate(&a));
+  OMM_HIP(hipEventCreate(&b));
+  OMM_HIP(hipEventRecord(a, c->stream));
+  fn(c, arg);
+  OMM_HIP(hipEventRecord(b, c->stream));
+  c->ev.push_back(a);
+  c->ev.push_back(b);
+  c->ev.push_back((hipEvent_t)(intptr_t)cls);
+}
+
+struct StepArg { Prec p; int mask; bool filter; };
+
+void run_iteration(omm_ctx* c, Prec p, int mask, bool tm) {
+  hipStream_t s = c->stream;
+  const Bufs& b = c->b;
+  const CGParams prm = params(c);
+  StepArg a{p, mask, any_filter(c)};
+  timed(c, 0, tm, [](omm_ctx* cc, void* v) { auto* q = (StepArg*)v; launch_s1(cc->stream, cc->b, q->p, q->mask, false, q->filter); }, &a);
+  timed(c, 1, tm, [](omm_ctx* cc, void* v) { auto* q = (StepArg*)v; launch_s2(cc->stream, cc->b, q->p, q->mask, false, q->filter); }, &a);
+  launch_traces(s, b, p, mask, false);
+  launch_linesearch(s, b, mask, LS_STEP, prm);
+  launch_update_mn(s, b, p, mask);
+  launch_update_nn(s, b, p, mask);
+  timed(c, 2, tm, [](omm_ctx* cc, void* v) { auto* q = (StepArg*)v; launch_grad(cc->stream, cc->b, q->p, q->mask, false); }, &a);
+  launch_beta(s, b, mask, false, prm);
+  launch_update_d(s, b, p, mask);
+}
+
+void run_step(omm_ctx* c, bool tm) {
+  if (c->prec != P64) run_iteration(c, c->prec, PH_LOW, tm);
+  run_iteration(c, P64, PH_FP64, tm);
+}
+
+void init_sequence(omm_ctx* c) {
+  hipStream_t s = c->stream;
+  const Bufs& b = c->b;
+  const CGParams prm = params(c);
+  const bool filt = any_filter(c);
+  launch_s1(s, b, P64, PH_INIT, true, filt);
+  launch_s2(s, b, P64, PH_INIT, true, filt);
+  launch_traces(s, b, P64, PH_INIT, true);
+  launch_linesearch(s, b, PH_INIT, LS_INIT, prm);
+  launch_grad(s, b, P64, PH_INIT, true);
+  launch_beta(s, b, PH_INIT, true, prm);
+  launch_update_d(s, b, P64, PH_INIT);
+  if (c->prec != P64) launch_cast_state(s, b, c->prec, PH_INIT);
+  launch_init_finish(s, b);
+}
+
+void collect_timing(omm_ctx* c) {
+  OMM_HIP(hipStreamSynchronize(c->stream));
+  for (size_t k = 0; k + 2 < c->ev.size(); k += 3) {
+    float ms = 0.f;
+    OMM_HIP(hipEventElapsedTime(&ms, c->ev[k], c->ev[k + 1]));
+    const int cls = (int)(intptr_t)c->ev[k + 2];
+    c->kt_ms[cls] += ms;
+    c->kt_n[cls] += 1;
+    (void)hipEventDestroy(c->ev[k]);
+    (void)hipEventDestroy(c->ev[k + 1]);
+  }
+  c->ev.clear();
+}
+
+void scatter_c0(omm_ctx* c) {
+  hipStream_t st = c->stream;
+  const Bufs& b = c->b;
+  OMM_HIP(hipMemsetAsync(b.C, 0, (size_t)b.n_tc * TE * sizeof(double), st));
+  OMM_HIP(hipMemsetAsync(b.Gold, 0, (size_t)b.n_tc * TE * sizeof(double), st));
+  for (int i = 0; i < c->nsys; ++i) {
+    SysHost& s = c->sys[i];
+    launch_scatter(st, blkmap(s.mc, nullptr, s, true, c->TC), s.c0_dev, b.C);
+    if (s.mode == OMM_DENSE_CHOLESKY) {   // C~ = L^T C, via D as scratch
+      const SysInfo& f = c->h_info[i];
+      chol_apply_lt(st, c->S, f.h0, s.RT, b.C, b.D, f.c0, s.WT);
+      OMM_HIP(hipMemcpyAsync(b.C + (size_t)f.c0 * TE, b.D + (size_t)f.c0 * TE,
+                             (size_t)(f.c1 - f.c0) * TE * sizeof(double), hipMemcpyDeviceToDevice, st));
+    }
+  }
+}
+
+void capture_graph(omm_ctx* c) {
+  const int K = c->opt.graph_iters;
+  OMM_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  try {
+    for (int k = 0; k < K; ++k) run_step(c, false);
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(c->stream, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  OMM_HIP(hipStreamEndCapture(c->stream, &c->graph));
+  OMM_HIP(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+  c->graph_iters = K;
+}
+
+int minimize(omm_ctx* c, omm_report* reps) {
+  auto t0 = std::chrono::steady_clock::now();
+  for (auto& s : c->sys)
+    if (!s.has_c0) throw ArgError("__STATE__omm_set_coeffs must be called for every system before omm_minimize");
+  if (!c->prepared) prepare(c);
+  hipStream_t st = c->stream;
+  scatter_c0(c);
+  if (c->prec != P64 && !c->hs_cast) {
+    launch_cast_hs(st, c->b, c->prec);
+    c->hs_cast = true;
+  }
+  for (int i = 0; i < c->nsys; ++i) {
+    SysState z{};
+    z.phase = PH_INIT;
+    z.prec = c->prec != P64 ? (int)c->prec : 0;
+    z.status = OMM_OK;
+    c->h_st[i] = z;
+  }
+  OMM_HIP(hipMemcpyAsync(c->d_st, c->h_st, sizeof(SysState) * c->nsys, hipMemcpyHostToDevice, st));
+  if (c->opt.history)
+    OMM_HIP(hipMemsetAsync(c->d_hist, 0, sizeof(double) * (size_t)c->nsys * c->opt.history_max * HCOLS, st));
+  for (int k = 0; k < 3; ++k) {
+    c->kt_ms[k] = 0;
+    c->kt_n[k] = 0;
+  }
+  init_sequence(c);
+  const bool use_graph = c->opt.graph_iters > 0 && !c->timing;
+  if (use_graph && !c->gexec) capture_graph(c);
+  const int K = use_graph ? c->graph_iters : std::max(1, c->opt.graph_iters > 0 ? c->opt.graph_iters : 1);
+  int64_t steps = 0, reinits = 0;
+  const int64_t max_steps = c->opt.max_iter + 2 * (int64_t)K + 16;
+  while (true) {
+    OMM_HIP(hipMemcpyAsync(c->h_st, c->d_st, sizeof(SysState) * c->nsys, hipMemcpyDeviceToHost, st));
+    OMM_HIP(hipStreamSynchronize(st));
+    if (c->timing) collect_timing(c);
+    bool all_done = true, any_init = false;
+    for (int i = 0; i < c->nsys; ++i) {
+      all_done &= c->h_st[i].phase == PH_DONE;
+      any_init |= c->h_st[i].phase == PH_INIT;
+    }
+    if (all_done) break;
+    if (any_init) {
+      if (++reinits > 4 * (int64_t)c->nsys + 4) throw DeviceError("phase switching did not settle");
+      init_sequence(c);
+      continue;
+    }
+    if (steps >= max_steps) throw DeviceError("iteration loop exceeded its bound");
+    if (use_graph) OMM_HIP(hipGraphLaunch(c->gexec, st));
+    else
+      for (int k = 0; k < K; ++k) run_step(c, c->timing);
+    steps += K;
+  }
+  // electron count at the final C
+  launch_traces(st, c->b, P64, PH_DONE, true);
+  launch_linesearch(st, c->b, PH_DONE, LS_REPORT, params(c));
+  OMM_HIP(hipMemcpyAsync(c->h_st, c->d_st, sizeof(SysState) * c->nsys, hipMemcpyDeviceToHost, st));
+  OMM_HIP(hipStreamSynchronize(st));
+  c->ran = true;
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int worst = OMM_OK;
+  auto rank = [](int s) {   // hard errors outrank soft ones
+    return s == OMM_OK ? 0 : (s == OMM_ERR_ELECTRON_COUNT ? 1 : (s == OMM_ERR_NOT_CONVERGED ? 2 : 3));
+  };
+  for (int i = 0; i < c->nsys; ++i) {
+    const SysState& S = c->h_st[i];
+    int status = S.status;
+    if (status == OMM_OK && c->opt.ne_tol > 0 && std::fabs(S.ne - 2.0 * c->sys[i].n) > c->opt.ne_tol)
+      status = OMM_ERR_ELECTRON_COUNT;
+    if (rank(status) > rank(worst)) worst = status;
+    if (reps) {
+      omm_report& r = reps[i];
+      r.energy = S.E;
+      r.energy_band = S.E + 2.0 * c->sys[i].eta * (double)c->sys[i].n;
+      r.grad_norm = S.gnorm;
+      r.electron_count = S.ne;
+      r.iters_total = S.iter;
+      r.iters_fp64 = S.iter_fp64;
+      r.cg_restarts = S.restarts;
+      r.status = status;
+      r.precision_end = S.prec;
+      r.seconds = secs;
+    }
+  }
+  if (worst != OMM_OK) {
+    c->err = "at least one system ended with status " + std::string(omm_status_str(worst));
+  }
+  return worst;
+}
+
+double* out_buffer(omm_ctx* c, double* user, int where, int64_t n, std::vector<void*>& tmp) {
+  if (where == OMM_DEVICE) return user;
+  void* p = nullptr;
+  if (hipMalloc(&p, std::max<int64_t>(1, n) * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    throw OomError("output staging");
+  }
+  tmp.push_back(p);
+  OMM_HIP(hipMemsetAsync(p, 0, std::max<int64_t>(1, n) * sizeof(double), c->stream));
+  return (double*)p;
+}
+
+void finish_out(omm_ctx* c, double* user, int where, double* dev, int64_t n, std::vector<void*>& tmp) {
+  if (where == OMM_HOST && n > 0)
+    OMM_HIP(hipMemcpyAsync(user, dev, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  OMM_HIP(hipStreamSynchronize(c->stream));
+  for (void* p : tmp) (void)hipFree(p);
+}
+
+const double* current_c(omm_ctx* c, int sys) {
+  SysHost& s = c->sys[sys];
+  if (s.mode != OMM_DENSE_CHOLESKY) return c->b.C;
+  const SysInfo& f = c->h_info[sys];
+  chol_solve_lt(c->stream, c->S, f.h0, s.RT, s.Linv, c->b.C, c->Cb, f.c0, s.WT);
+  return c->Cb;
+}
+
+int guard(omm_ctx* c, int (*fn)(omm_ctx*, void*), void* arg) {
+  try {
+    return fn(c, arg);
+  } catch (const ArgError& e) {
+    if (e.msg == "__NOT_SPD__") {
+      set_err(c, "Cholesky factorization of S failed (S not positive definite)");
+      return OMM_ERR_NOT_SPD;
+    }
+    if (e.msg.rfind("__STATE__", 0) == 0) {
+      set_err(c, e.msg.substr(9));
+      return OMM_ERR_STATE;
+    }
+    set_err(c, e.msg);
+    return OMM_ERR_ARG;
+  } catch (const OomError& e) {
+    set_err(c, e.msg);
+    return OMM_ERR_OOM;
+  } catch (const DeviceError& e) {
+    set_err(c, e.msg);
+    return OMM_ERR_DEVICE;
+  } catch (const std::bad_alloc&) {
+    set_err(c, "host allocation failed");
+    return OMM_ERR_OOM;
+  } catch (...) {
+    set_err(c, "unexpected exception");
+    return OMM_ERR_DEVICE;
+  }
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+void omm_default_options(omm_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->eta = 0.0;
+  o->tol_grad = 1e-9;
+  o->rel_tol = 0.0;
+  o->max_iter = 10000;
+  o->filter_eps = 0.0;
+  o->precision = OMM_FP64;
+  o->fp64_refine_iters = 5;
+  o->lowprec_rel_switch = 0.0;
+  o->lowprec_max_iter = 0;
+  o->graph_iters = 16;
+  o->history = 1;
+  o->history_max = 20000;
+  o->ne_tol = 0.0;
+  o->autotune = 0;
+  o->tune_cache = nullptr;
+  o->hip_stream = nullptr;
+}
+
+const char* omm_status_str(int32_t s) {
+  switch (s) {
+    case OMM_OK: return "OMM_OK";
+    case OMM_ERR_ARG: return "OMM_ERR_ARG";
+    case OMM_ERR_STATE: return "OMM_ERR_STATE";
+    case OMM_ERR_NOT_SPD: return "OMM_ERR_NOT_SPD";
+    case OMM_ERR_NO_LINE_MIN: return "OMM_ERR_NO_LINE_MIN";
+    case OMM_ERR_NOT_CONVERGED: return "OMM_ERR_NOT_CONVERGED";
+    case OMM_ERR_ELECTRON_COUNT: return "OMM_ERR_ELECTRON_COUNT";
+    case OMM_ERR_DEVICE: return "OMM_ERR_DEVICE";
+    case OMM_ERR_OOM: return "OMM_ERR_OOM";
+    default: return "OMM_UNKNOWN_STATUS";
+  }
+}
+
+const char* omm_last_error(const omm_ctx* c) { return c ? c->err.c_str() : g_last_init_error.c_str(); }
+
+int omm_init_batch(omm_ctx** out, int32_t count, const omm_matrix* H, const omm_matrix* S, const int64_t* n_occ,
+                   const int32_t* modes, const omm_options* opt) {
+  g_last_init_error.clear();
+  if (!out) {
+    g_last_init_error = "out is NULL";
+    return OMM_ERR_ARG;
+  }
+  *out = nullptr;
+  if (count <= 0 || !H || !S || !n_occ) {
+    g_last_init_error = "count must be positive and H, S, n_occ non-NULL";
+    return OMM_ERR_ARG;
+  }
+  omm_options o;
+  omm_default_options(&o);
+  if (opt) o = *opt;
+  if (o.precision < OMM_FP64 || o.precision > OMM_BF16) {
+    g_last_init_error = "unknown precision";
+    return OMM_ERR_ARG;
+  }
+  if (o.max_iter < 0 || o.history_max < 0 || !(o.tol_grad >= 0.0) || !(o.filter_eps >= 0.0)) {
+    g_last_init_error = "invalid option value";
+    return OMM_ERR_ARG;
+  }
+  // argument validation needs no device: do it before touching HIP
+  {
+    std::vector<MatDesc> dh(count), ds(count);
+    try {
+      for (int i = 0; i < count; ++i) {
+        copy_desc(dh[i], &H[i], "H");
+        copy_desc(ds[i], &S[i], "S");
+        if (!dh[i].same_pattern(ds[i])) throw ArgError("H and S must share their block structure");
+        if (dh[i].nbrow != dh[i].nbcol || dh[i].rbs != dh[i].cbs)
+          throw ArgError("H must be square with square diagonal blocks");
+        int64_t m = 0;
+        for (int v : dh[i].rbs) m += v;
+        if (n_occ[i] < 1 || n_occ[i] > m) throw ArgError("n_occ must satisfy 1 <= n_occ <= m");
+        const int md = modes ? modes[i] : OMM_DENSE;
+        if (md != OMM_DENSE && md != OMM_DENSE_CHOLESKY && md != OMM_BLOCK_SPARSE) throw ArgError("unknown mode");
+      }
+    } catch (const ArgError& e) {
+      g_last_init_error = e.msg;
+      return OMM_ERR_ARG;
+    }
+  }
+  omm_ctx* c = new (std::nothrow) omm_ctx();
+  if (!c) {
+    g_last_init_error = "host allocation failed";
+    return OMM_ERR_OOM;
+  }
+  c->opt = o;
+  c->prec = (Prec)o.precision;
+  struct A { int count; const omm_matrix *H, *S; const int64_t* n; const int32_t* modes; } a{count, H, S, n_occ, modes};
+  int rc = guard(c, [](omm_ctx* cc, void* v) -> int {
+    auto* q = (A*)v;
+    if (cc->opt.hip_stream) cc->stream = (hipStream_t)cc->opt.hip_stream;
+    else {
+      OMM_HIP(hipStreamCreateWithFlags(&cc->stream, hipStreamNonBlocking));
+      cc->own_stream = true;
+    }
+    OMM_HIP(hipHostMalloc((void**)&cc->h_st, sizeof(SysState) * q->count, hipHostMallocDefault));
+    ingest(cc, q->count, q->H, q->S, q->n, q->modes);
+    return OMM_OK;
+  }, &a);
+  if (rc != OMM_OK) {
+    g_last_init_error = c->err;
+    omm_destroy(c);
+    return rc;
+  }
+  *out = c;
+  return OMM_OK;
+}
+
+int omm_init(omm_ctx** out, const omm_matrix* H, const omm_matrix* S, int64_t n_occ, int32_t mode,
+             const omm_options* opt) {
+  return omm_init_batch(out, 1, H, S, &n_occ, &mode, opt);
+}
+
+int omm_set_coeffs(omm_ctx* c, int32_t sys, const omm_matrix* C0) {
+  if (!c) return OMM_ERR_ARG;
+  if (sys < 0 || sys >= c->nsys) {
+    c->err = "system index out of range";
+    return OMM_ERR_ARG;
+  }
+  struct A { int sys; const omm_matrix* C0; } a{sys, C0};
+  return guard(c, [](omm_ctx* cc, void* v) -> int {
+    auto* q = (A*)v;
+    SysHost& s = cc->sys[q->sys];
+    MatDesc d;
+    copy_desc(d, q->C0, "C0");
+    if (d.nbrow != s.H.nbrow || d.rbs != s.H.rbs) throw ArgError("C0 must have the block rows of H");
+    int64_t n = 0;
+    for (int v : d.cbs) n += v;
+    if (n != s.n) throw ArgError("C0 must have n_occ columns");
+    if (s.mode == OMM_BLOCK_SPARSE) {
+      for (int v : d.cbs)
+        if (v > 16) throw ArgError("block-sparse mode needs wavefunction blocks of at most 16 columns");
+    } else {
+      for (int b = 0; b < d.nbrow; ++b)
+        if (d.rp[b + 1] - d.rp[b] != d.nbcol) throw ArgError("dense modes need every block of C0 stored");
+    }
+    const bool same = s.has_c0 && s.C0.same_pattern(d);
+    if (!same) {
+      s.C0 = d;
+      cc->prepared = false;
+      if (s.c0_dev) {
+        auto it = std::find(cc->alloc_init.begin(), cc->alloc_init.end(), (void*)s.c0_dev);
+        if (it != cc->alloc_init.end()) cc->alloc_init.erase(it);
+        (void)hipFree(s.c0_dev);
+        s.c0_dev = nullptr;
+      }
+      s.c0_dev = dalloc<double>(cc, std::max<int64_t>(1, d.nval), false);
+      s.c_nval = d.nval;
+    } else {
+      s.C0.voff = d.voff;
+      s.C0.nval = d.nval;
+      if (d.nval > s.c_nval) throw ArgError("C0 values longer than at first set_coeffs");
+    }
+    OMM_HIP(hipMemcpyAsync(s.c0_dev, q->C0->val, d.nval * sizeof(double),
+                           q->C0->memspace == OMM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                           cc->stream));
+    if (same && cc->prepared) {   // value offsets may differ: refresh the device copy
+      OMM_HIP(hipMemcpyAsync(s.mc.voff, d.voff.data(), d.voff.size() * sizeof(int64_t), hipMemcpyHostToDevice,
+                             cc->stream));
+    }
+    OMM_HIP(hipStreamSynchronize(cc->stream));
+    s.has_c0 = true;
+    return OMM_OK;
+  }, &a);
+}
+
+int omm_minimize(omm_ctx* c, omm_report* reps) {
+  if (!c) return OMM_ERR_ARG;
+  struct A { omm_report* r; } a{reps};
+  return guard(c, [](omm_ctx* cc, void* v) -> int { return minimize(cc, ((A*)v)->r); }, &a);
+}
+
+int omm_density_matrix(omm_ctx* c, int32_t sys, double* rho, int32_t where) {
+  if (!c) return OMM_ERR_ARG;
+  if (sys < 0 || sys >= c->nsys || !rho || (where != OMM_HOST && where != OMM_DEVICE)) {
+    c->err = "bad argument";
+    return OMM_ERR_ARG;
+  }
+  if (!c->ran) {
+    c->err = "omm_minimize must run before omm_density_matrix";
+    return OMM_ERR_STATE;
+  }
+  struct A { int sys; double* rho; int where; } a{sys, rho, where};
+  return guard(c, [](omm_ctx* cc, void* v) -> int {
+    auto* q = (A*)v;
+    SysHost& s = cc->sys[q->sys];
+    hipStream_t st = cc->stream;
+    const double* C = current_c(cc, q->sys);
+    launch_cm(st, cc->Pcm.view(), cc->TCM.row, cc->brow_sys, q->sys, C, cc->b.S0, cc->TW.row, cc->TW.ci, cc->CM);
+    launch_rho(st, cc->Prho.view(), cc->TH.row, cc->brow_sys, q->sys, cc->CM, C, cc->rho);
+    std::vector<void*> tmp;
+    double* dst = out_buffer(cc, q->rho, q->where, s.S.nval, tmp);
+    launch_gather(st, blkmap(s.mh, s.s_voff, s, false, cc->TH), cc->rho, dst);
+    finish_out(cc, q->rho, q->where, dst, s.S.nval, tmp);
+    return OMM_OK;
+  }, &a);
+}
+
+int omm_get_coeffs(omm_ctx* c, int32_t sys, double* C, int32_t where) {
+  if (!c) return OMM_ERR_ARG;
+  if (sys < 0 || sys >= c->nsys || !C || (where != OMM_HOST && where != OMM_DEVICE)) {
+    c->err = "bad argument";
+    return OMM_ERR_ARG;
+  }
+  if (!c->ran) {
+    c->err = "omm_minimize must run before omm_get_coeffs";
+    return OMM_ERR_STATE;
+  }
+  struct A { int sys; double* C; int where; } a{sys, C, where};
+  return guard(c, [](omm_ctx* cc, void* v) -> int {
+    auto* q = (A*)v;
+    SysHost& s = cc->sys[q->sys];
+    const double* Cc = current_c(cc, q->sys);
+    std::vector<void*> tmp;
+    double* dst = out_buffer(cc, q->C, q->where, s.C0.nval, tmp);
+    launch_gather(cc->stream, blkmap(s.mc, nullptr, s, true, cc->TC), Cc, dst);
+    finish_out(cc, q->C, q->where, dst, s.C0.nval, tmp);
+    return OMM_OK;
+  }, &a);
+}
+
+int omm_get_projected(omm_ctx* c, int32_t sys, double* HW, double* SW, int32_t where) {
+  if (!c) return OMM_ERR_ARG;
+  if (sys < 0 || sys >= c->nsys || (where != OMM_HOST && where != OMM_DEVICE)) {
+    c->err = "bad argument";
+    return OMM_ERR_ARG;
+  }
+  if (!c->ran) {
+    c->err = "omm_minimize must run before omm_get_projected";
+    return OMM_ERR_STATE;
+  }
+  struct A { int sys; double *HW, *SW; int where; } a{sys, HW, SW, where};
+  return guard(c, [](omm_ctx* cc, void* v) -> int {
+    auto* q = (A*)v;
+    SysHost& s = cc->sys[q->sys];
+    const SysInfo& f = cc->h_info[q->sys];
+    const int64_t nn = s.n * s.n;
+    double* srcs[2] = {cc->b.H0, cc->b.S0};
+    double* users[2] = {q->HW, q->SW};
+    for (int k = 0; k < 2; ++k) {
+      if (!users[k]) continue;
+      std::vector<void*> tmp;
+      double* dst = out_buffer(cc, users[k], q->where, nn, tmp);
+      launch_gather_w(cc->stream, f.w0, f.w1, cc->TW.row, cc->TW.ci, cc->welem, s.n, srcs[k], dst);
+      finish_out(cc, users[k], q->where, dst, nn, tmp);
+    }
+    return OMM_OK;
+  }, &a);
+}
+
+int omm_get_history(omm_ctx* c, int32_t sys, double* out, int64_t max_rows, int64_t* rows) {
+  if (!c) return OMM_ERR_ARG;
+  if (sys < 0 || sys >= c->nsys || !out || max_rows < 0) {
+    c->err = "bad argument";
+    return OMM_ERR_ARG;
+  }
+  if (!c->ran || !c->opt.history) {
+    c->err = "no history recorded";
+    return OMM_ERR_STATE;
+  }
+  struct A { int sys; double* out; int64_t max_rows; int64_t* rows; } a{sys, out, max_rows, rows};
+  return guard(c, [](omm_ctx* cc, void* v) -> int {
+    auto* q = (A*)v;
+    const int64_t have = std::min<int64_t>(cc->h_st[q->sys].iter, cc->opt.history_max);
+    const int64_t n = std::min(have, q->max_rows);
+    if (n > 0)
+      OMM_HIP(hipMemcpyAsync(q->out, cc->d_hist + (size_t)q->sys * cc->opt.history_max * HCOLS,
+                             n * HCOLS * sizeof(double), hipMemcpyDeviceToHost, cc->stream));
+    OMM_HIP(hipStreamSynchronize(cc->stream));
+    if (q->rows) *q->rows = n;
+    return OMM_OK;
+  }, &a);
+}
+
+int omm_query(const omm_ctx* cc, int32_t sys, omm_sizes* z) {
+  omm_ctx* c = const_cast<omm_ctx*>(cc);
+  if (!c || !z) return OMM_ERR_ARG;
+  if (sys < -1 || sys >= c->nsys) {
+    c->err = "system index out of range";
+    return OMM_ERR_ARG;
+  }
+  bool have_c0 = true;
+  for (auto& s : c->sys) have_c0 &= s.has_c0;
+  if (have_c0 && !c->prepared) {
+    int rc = guard(c, [](omm_ctx* q, void*) -> int { prepare(q); return OMM_OK; }, nullptr);
+    if (rc != OMM_OK) return rc;
+  }
+  std::memset(z, 0, sizeof(*z));
+  for (int i = 0; i < c->nsys; ++i) {
+    if (sys >= 0 && i != sys) continue;
+    const SysHost& s = c->sys[i];
+    z->m += s.m;
+    z->n += s.n;
+    z->s_nval += s.S.nval;
+    z->c_nval += s.has_c0 ? s.C0.nval : 0;
+    z->tiles_h += s.tiles_h;
+    z->tiles_c += s.tiles_c;
+    z->tiles_hc += s.tiles_hc;
+    z->tiles_w += s.tiles_w;
+    z->pairs_s1 += s.pairs[0];
+    z->pairs_s2 += s.pairs[1];
+    z->pairs_grad += s.pairs[2];
+    z->flops_alg_iter += s.flops_alg[0] + s.flops_alg[1] + s.flops_alg[2];
+    z->flops_exec_iter += s.flops_exec[0] + s.flops_exec[1] + s.flops_exec[2];
+    z->bytes_alg_iter += s.bytes_alg;
+  }
+  return OMM_OK;
+}
+
+int omm_set_timing(omm_ctx* c, int32_t enable) {
+  if (!c) return OMM_ERR_ARG;
+  c->timing = enable != 0;
+  return OMM_OK;
+}
+
+int omm_kernel_times(const omm_ctx* c, double* ms, int64_t* launches) {
+  if (!c || !ms || !launches) return OMM_ERR_ARG;
+  for (int k = 0; k < 3; ++k) {
+    ms[k] = c->kt_ms[k];
+    launches[k] = c->kt_n[k];
+  }
+  return OMM_OK;
+}
+
+void omm_destroy(omm_ctx* c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (size_t k = 0; k + 2 < c->ev.size(); k += 3) {
+    (void)hipEventDestroy(c->ev[k]);
+    (void)hipEventDestroy(c->ev[k + 1]);
+  }
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  free_list(c->alloc_prep);
+  free_list(c->alloc_init);
+  if (c->h_st) (void)hipHostFree(c->h_st);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+// Host-callable launchers of the device kernels.
+#pragma once
+
+#include "omm_internal.hpp"
+
+namespace omm {
+
+// ---------------------------------------------------------------- symbolic (symbolic.hip)
+void sym_count(hipStream_t st, int nrows, int row0, PatView A, PatView B, const int2* win, int* cnt);
+void sym_fill(hipStream_t st, int nrows, int row0, PatView A, PatView B, const int2* win, const int* orp,
+              int* oci, int* orow);
+void pair_count(hipStream_t st, int nrows, int row0, PatView A, PatView B, PatView O, const int2* win,
+                int64_t* pcnt);
+void pair_fill(hipStream_t st, int nrows, int row0, PatView A, PatView B, PatView O, const int2* win,
+               const int64_t* pp, int2* pairs);
+void find_tiles(hipStream_t st, int64_t n, const int* rows, const int* cols, PatView P, int* out);
+void transpose_count(hipStream_t st, int nrows, int row0, PatView A, const int2* win, int* cnt);
+void transpose_fill(hipStream_t st, int nrows, int row0, PatView A, const int2* win, const int* trp, int* tci,
+                    int* tti);
+void rows_of(hipStream_t st, int nrows, const int* rp, int* rows);
+void excl_scan(hipStream_t st, const int* in, int* out, int64_t n);
+void excl_scan64(hipStream_t st, const int64_t* in, int64_t* out, int64_t n);
+
+// ---------------------------------------------------------------- numeric (numeric.hip)
+enum Prec { P64 = 0, P32 = 1, PBF = 2 };
+
+struct Bufs {   // every device buffer the iteration kernels touch
+  // patterns (global tile rows/cols)
+  const int *th_row, *th_col, *tc_row, *tc_col, *thc_row, *thc_col, *tw_row, *tw_col;
+  const int *brow_sys, *wrow_sys;
+  const int *c_in_hc, *hc_to_c, *w_tr;
+  const uint32_t* cmask;
+  const uint8_t* wseg;           // per wavefunction tile: lo[16], hi[16]
+  const int4* chunks;            // trace chunks (tile begin, end, system)
+  int nchunks;
+  int n_th, n_tc, n_thc, n_tw;   // tile counts
+  PlanView s1, s2, grad;
+  // FP64 masters
+  double *H, *S, *C, *D, *G, *Gold, *HC, *SC, *HD, *SD, *H0, *S0, *X, *Y, *S2, *H2;
+  // low-precision copies (float or bf16 storage, typed at launch) and FP32 product outputs
+  void *Hl, *Sl, *Cl, *Dl, *HCl, *SCl, *H0l, *S0l;
+  float *HDf, *SDf, *Xf, *Yf, *S2f, *H2f;
+  double *tpart, *gpart;         // trace partials (nchunks x NSUM), gradient partials (n_tc x 2)
+  SysInfo* info;
+  SysState* st;
+  double* hist;
+  int nsys;
+  double eps2;                   // filter threshold squared (block-sparse products)
+};
+
+// one CG iteration step (all systems whose phase matches `mask`), arithmetic `prec`
+void launch_s1(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init, bool filter);
+void launch_s2(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init, bool filter);
+void launch_traces(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init);
+void launch_linesearch(hipStream_t s, const Bufs& b, int mask, int mode, const CGParams& prm);
+void launch_update_mn(hipStream_t s, const Bufs& b, Prec prec, int mask);
+void launch_update_nn(hipStream_t s, const Bufs& b, Prec prec, int mask);
+void launch_grad(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init);
+void launch_beta(hipStream_t s, const Bufs& b, int mask, bool init, const CGParams& prm);
+void launch_update_d(hipStream_t s, const Bufs& b, Prec prec, int mask);
+void launch_init_finish(hipStream_t s, const Bufs& b);
+void launch_cast_state(hipStream_t s, const Bufs& b, Prec prec, int mask);   // C, HC, SC, H0, S0 copies
+void launch_cast_hs(hipStream_t s, const Bufs& b, Prec prec);                // H, S copies
+
+// linesearch modes
+enum { LS_STEP = 0, LS_INIT = 1, LS_REPORT = 2 };
+
+// density matrix: CM = C (2I - S0) on the CM plan, rho = 2 CM C^T on the H pattern
+void launch_cm(hipStream_t s, PlanView p, const int* orow, const int* brow_sys, int sys, const double* C,
+               const double* S0, const int* tw_row, const int* tw_col, double* CM);
+void launch_rho(hipStream_t s, PlanView p, const int* orow, const int* brow_sys, int sys, const double* CM,
+                const double* C, double* rho);
+
+// block <-> tile maps for one input matrix of one system
+struct BlkMap {
+  int nblk;
+  const int* brow;       // block row of each stored block
+  const int* bcol;       // block column
+  const int64_t* voff;   // value offset
+  const int* ro;         // first element row of each block row
+  const int* co;         // first element column of each block column
+  const int* rtile;      // element row -> global tile row
+  const int* roff;       // element row -> row inside the tile
+  const int* ctile;      // element column -> global tile column
+  const int* coff;       // element column -> column inside the tile
+  PatView P;             // tile pattern holding the values
+};
+void launch_scatter(hipStream_t s, const BlkMap& m, const double* val, double* tiles);
+void launch_gather(hipStream_t s, const BlkMap& m, const double* tiles, double* val);
+void launch_gather_w(hipStream_t s, int t0, int t1, const int* tw_row, const int* tw_col, const int* welem,
+                     int64_t n, const double* tiles, double* dense);
+void launch_axpy_tiles(hipStream_t s, int64_t ntiles, double alpha, const double* X, double* Y);
+void launch_pad_identity(hipStream_t s, double* S, int t_first, int RT, int64_t m);
+void launch_fill(hipStream_t s, double* p, int64_t n, double v);
+
+// ---------------------------------------------------------------- Cholesky (cholesky.hip)
+// dense tile grid of one system: tile (I, J) at base + I * ld + J
+void chol_factor(hipStream_t s, double* A, int base, int RT, double* Linv, int* status);
+void chol_reduce_h(hipStream_t s, const double* L, int lbase, int RT, const double* Linv, double* H, int hbase,
+                   double* work);
+void chol_apply_lt(hipStream_t s, const double* L, int lbase, int RT, const double* Cin, double* Cout, int cbase,
+                   int WT);     // Cout = L^T Cin
+void chol_solve_lt(hipStream_t s, const double* L, int lbase, int RT, const double* Linv, const double* Cin,
+                   double* Cout, int cbase, int WT);   // Cout = L^-T Cin
+
+}  // namespace omm

@@ -1,0 +1,286 @@
+// Device symbolic phase: tile patterns of block products and their work lists.
+//
+// For a product O = op(A) * B of tile patterns, the kernels below compute
+//   * the pattern of O (union over k in A.row(i) of B.row(k)), one workgroup
+//     per output row with the row's column window held as a bitmap in LDS;
+//   * for every output tile (i, j) the list of (A tile, B tile) pairs with
+//     A(i,k) and B(k,j) both stored, in increasing k, which is the fixed
+//     summation order of the numeric kernels (bitwise-reproducible results).
+// This is the tile-level counterpart of reserving the blocks of a sparse
+// product before filling it (Sec. III C, m_reserve_blocks) and of the
+// product-pattern bookkeeping of a block-sparse library; restricted outputs
+// (the gradient kept on C's pattern, rho on S's pattern, Sec. III B) reuse
+// the pair kernels with a given output pattern.
+#include <hipcub/hipcub.hpp>
+
+#include "kernels.hpp"
+
+namespace omm {
+
+namespace {
+
+constexpr int SYM_THREADS = 256;
+
+__device__ __forceinline__ int a_tile(const PatView& A, int e) { return A.ti ? A.ti[e] : e; }
+
+__global__ __launch_bounds__(SYM_THREADS) void k_sym_count(int row0, PatView A, PatView B,
+                                                         const int2* __restrict__ win,
+                                                         int* __restrict__ cnt) {
+  __shared__ uint32_t bm[MAXW / 32];
+  __shared__ int red[SYM_THREADS];
+  const int i = row0 + blockIdx.x;
+  const int2 w = win[i];
+  const int nw = (w.y - w.x + 31) >> 5;
+  for (int t = threadIdx.x; t < nw; t += blockDim.x) bm[t] = 0u;
+  __syncthreads();
+  for (int e = A.rp[i] + threadIdx.x; e < A.rp[i + 1]; e += blockDim.x) {
+    const int k = A.ci[e];
+    for (int jj = B.rp[k]; jj < B.rp[k + 1]; ++jj) {
+      const int c = B.ci[jj] - w.x;
+      if (c >= 0 && c < w.y - w.x) atomicOr(&bm[c >> 5], 1u << (c & 31));
+    }
+  }
+  __syncthreads();
+  int s = 0;
+  for (int t = threadIdx.x; t < nw; t += blockDim.x) s += __popc(bm[t]);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = SYM_THREADS / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) cnt[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(SYM_THREADS) void k_sym_fill(int row0, PatView A, PatView B,
+                                                        const int2* __restrict__ win,
+                                                        const int* __restrict__ orp,
+                                                        int* __restrict__ oci, int* __restrict__ orow) {
+  __shared__ uint32_t bm[MAXW / 32];
+  __shared__ int pre[SYM_THREADS + 1];
+  const int i = row0 + blockIdx.x;
+  const int2 w = win[i];
+  const int nw = (w.y - w.x + 31) >> 5;
+  for (int t = threadIdx.x; t < nw; t += blockDim.x) bm[t] = 0u;
+  __syncthreads();
+  for (int e = A.rp[i] + threadIdx.x; e < A.rp[i + 1]; e += blockDim.x) {
+    const int k = A.ci[e];
+    for (int jj = B.rp[k]; jj < B.rp[k + 1]; ++jj) {
+      const int c = B.ci[jj] - w.x;
+      if (c >= 0 && c < w.y - w.x) atomicOr(&bm[c >> 5], 1u << (c & 31));
+    }
+  }
+  __syncthreads();
+  // each thread owns a contiguous run of words; exclusive scan of the run counts
+  const int per = (nw + SYM_THREADS - 1) / SYM_THREADS;
+  const int wb = threadIdx.x * per, we = min(nw, wb + per);
+  int s = 0;
+  for (int t = wb; t < we; ++t) s += __popc(bm[t]);
+  pre[threadIdx.x + 1] = s;
+  if (threadIdx.x == 0) pre[0] = 0;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int t = 1; t <= SYM_THREADS; ++t) pre[t] += pre[t - 1];
+  __syncthreads();
+  int pos = orp[i] + pre[threadIdx.x];
+  for (int t = wb; t < we; ++t) {
+    uint32_t word = bm[t];
+    while (word) {
+      const int b = __ffs(word) - 1;
+      word &= word - 1;
+      oci[pos] = w.x + t * 32 + b;
+      orow[pos] = i;
+      ++pos;
+    }
+  }
+}
+
+__global__ __launch_bounds__(SYM_THREADS) void k_pair_count(int row0, PatView A, PatView B, PatView O,
+                                                          const int2* __restrict__ win,
+                                                          int64_t* __restrict__ pcnt) {
+  __shared__ int pos[MAXW];
+  __shared__ int cnt[MAXW];
+  const int i = row0 + blockIdx.x;
+  const int2 w = win[i];
+  const int width = w.y - w.x;
+  const int o0 = O.rp[i], no = O.rp[i + 1] - o0;
+  for (int t = threadIdx.x; t < width; t += blockDim.x) pos[t] = -1;
+  for (int t = threadIdx.x; t < no; t += blockDim.x) cnt[t] = 0;
+  __syncthreads();
+  for (int t = threadIdx.x; t < no; t += blockDim.x) pos[O.ci[o0 + t] - w.x] = t;
+  __syncthreads();
+  for (int e = A.rp[i] + threadIdx.x; e < A.rp[i + 1]; e += blockDim.x) {
+    const int k = A.ci[e];
+    for (int jj = B.rp[k]; jj < B.rp[k + 1]; ++jj) {
+      const int c = B.ci[jj] - w.x;
+      const int p = (c >= 0 && c < width) ? pos[c] : -1;
+      if (p >= 0) atomicAdd(&cnt[p], 1);
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < no; t += blockDim.x) pcnt[o0 + t] = cnt[t];
+}
+
+__global__ __launch_bounds__(SYM_THREADS) void k_pair_fill(int row0, PatView A, PatView B, PatView O,
+                                                         const int2* __restrict__ win,
+                                                         const int64_t* __restrict__ pp,
+                                                         int2* __restrict__ pairs) {
+  __shared__ int pos[MAXW];
+  __shared__ int fill[MAXW];
+  const int i = row0 + blockIdx.x;
+  const int2 w = win[i];
+  const int width = w.y - w.x;
+  const int o0 = O.rp[i], no = O.rp[i + 1] - o0;
+  for (int t = threadIdx.x; t < width; t += blockDim.x) pos[t] = -1;
+  for (int t = threadIdx.x; t < no; t += blockDim.x) fill[t] = 0;
+  __syncthreads();
+  for (int t = threadIdx.x; t < no; t += blockDim.x) pos[O.ci[o0 + t] - w.x] = t;
+  __syncthreads();
+  // k in increasing order; within one k every output column is hit at most once
+  for (int e = A.rp[i]; e < A.rp[i + 1]; ++e) {
+    const int k = A.ci[e];
+    const int at = a_tile(A, e);
+    for (int jj = B.rp[k] + threadIdx.x; jj < B.rp[k + 1]; jj += blockDim.x) {
+      const int c = B.ci[jj] - w.x;
+      const int p = (c >= 0 && c < width) ? pos[c] : -1;
+      if (p >= 0) {
+        const int64_t slot = pp[o0 + p] + fill[p];
+        fill[p] += 1;
+        pairs[slot] = make_int2(at, B.ti ? B.ti[jj] : jj);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// index of tile (rows[e], cols[e]) in pattern P, or -1
+__global__ void k_find_tiles(int64_t n, const int* __restrict__ rows, const int* __restrict__ cols,
+                             PatView P, int* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int r = rows[e], c = cols[e];
+  int lo = P.rp[r], hi = P.rp[r + 1];
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (P.ci[mid] < c) lo = mid + 1; else hi = mid;
+  }
+  out[e] = (lo < P.rp[r + 1] && P.ci[lo] == c) ? lo : -1;
+}
+
+// transposed pattern: row g of A^T lists rows b of A (inside the window) holding column g
+__global__ __launch_bounds__(SYM_THREADS) void k_transpose(int row0, PatView A, const int2* __restrict__ win,
+                                                         const int* __restrict__ trp, int* __restrict__ cnt,
+                                                         int* __restrict__ tci, int* __restrict__ tti) {
+  __shared__ int flag[SYM_THREADS];
+  __shared__ int base;
+  const int g = row0 + blockIdx.x;
+  const int2 w = win[g];
+  if (threadIdx.x == 0) base = trp ? trp[g] : 0;
+  __syncthreads();
+  int total = 0;
+  for (int b0 = w.x; b0 < w.y; b0 += SYM_THREADS) {
+    const int b = b0 + threadIdx.x;
+    int hit = -1;
+    if (b < w.y) {
+      int lo = A.rp[b], hi = A.rp[b + 1];
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (A.ci[mid] < g) lo = mid + 1; else hi = mid;
+      }
+      if (lo < A.rp[b + 1] && A.ci[lo] == g) hit = lo;
+    }
+    flag[threadIdx.x] = hit >= 0 ? 1 : 0;
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int t = 1; t < SYM_THREADS; ++t) flag[t] += flag[t - 1];
+    __syncthreads();
+    if (trp && hit >= 0) {
+      const int slot = base + total + flag[threadIdx.x] - 1;
+      tci[slot] = b;
+      tti[slot] = hit;
+    }
+    total += flag[SYM_THREADS - 1];
+    __syncthreads();
+  }
+  if (!trp && threadIdx.x == 0) cnt[blockIdx.x] = total;
+}
+
+__global__ void k_rows_of(int nrows, const int* __restrict__ rp, int* __restrict__ rows) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  for (int e = rp[r]; e < rp[r + 1]; ++e) rows[e] = r;
+}
+
+}  // namespace
+
+void sym_count(hipStream_t st, int nrows, int row0, PatView A, PatView B, const int2* win, int* cnt) {
+  if (nrows <= 0) return;
+  hipLaunchKernelGGL(k_sym_count, dim3(nrows), dim3(SYM_THREADS), 0, st, row0, A, B, win, cnt);
+  OMM_HIP(hipGetLastError());
+}
+
+void sym_fill(hipStream_t st, int nrows, int row0, PatView A, PatView B, const int2* win,
+              const int* orp, int* oci, int* orow) {
+  if (nrows <= 0) return;
+  hipLaunchKernelGGL(k_sym_fill, dim3(nrows), dim3(SYM_THREADS), 0, st, row0, A, B, win, orp, oci, orow);
+  OMM_HIP(hipGetLastError());
+}
+
+void pair_count(hipStream_t st, int nrows, int row0, PatView A, PatView B, PatView O, const int2* win,
+                int64_t* pcnt) {
+  if (nrows <= 0) return;
+  hipLaunchKernelGGL(k_pair_count, dim3(nrows), dim3(SYM_THREADS), 0, st, row0, A, B, O, win, pcnt);
+  OMM_HIP(hipGetLastError());
+}
+
+void pair_fill(hipStream_t st, int nrows, int row0, PatView A, PatView B, PatView O, const int2* win,
+               const int64_t* pp, int2* pairs) {
+  if (nrows <= 0) return;
+  hipLaunchKernelGGL(k_pair_fill, dim3(nrows), dim3(SYM_THREADS), 0, st, row0, A, B, O, win, pp, pairs);
+  OMM_HIP(hipGetLastError());
+}
+
+void find_tiles(hipStream_t st, int64_t n, const int* rows, const int* cols, PatView P, int* out) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_find_tiles, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, rows, cols, P, out);
+  OMM_HIP(hipGetLastError());
+}
+
+void transpose_count(hipStream_t st, int nrows, int row0, PatView A, const int2* win, int* cnt) {
+  if (nrows <= 0) return;
+  hipLaunchKernelGGL(k_transpose, dim3(nrows), dim3(SYM_THREADS), 0, st, row0, A, win,
+                     (const int*)nullptr, cnt, (int*)nullptr, (int*)nullptr);
+  OMM_HIP(hipGetLastError());
+}
+
+void transpose_fill(hipStream_t st, int nrows, int row0, PatView A, const int2* win, const int* trp,
+                    int* tci, int* tti) {
+  if (nrows <= 0) return;
+  hipLaunchKernelGGL(k_transpose, dim3(nrows), dim3(SYM_THREADS), 0, st, row0, A, win, trp, (int*)nullptr,
+                     tci, tti);
+  OMM_HIP(hipGetLastError());
+}
+
+void rows_of(hipStream_t st, int nrows, const int* rp, int* rows) {
+  if (nrows <= 0) return;
+  hipLaunchKernelGGL(k_rows_of, dim3((nrows + 255) / 256), dim3(256), 0, st, nrows, rp, rows);
+  OMM_HIP(hipGetLastError());
+}
+
+template <typename I>
+static void excl_scan_impl(hipStream_t st, const I* in, I* out, int64_t n) {
+  if (n <= 0) return;
+  size_t tmp = 0;
+  OMM_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, in, out, (int)n, st));
+  void* buf = nullptr;
+  OMM_HIP(hipMallocAsync(&buf, tmp, st));
+  OMM_HIP(hipcub::DeviceScan::ExclusiveSum(buf, tmp, in, out, (int)n, st));
+  OMM_HIP(hipFreeAsync(buf, st));
+}
+
+void excl_scan(hipStream_t st, const int* in, int* out, int64_t n) { excl_scan_impl<int>(st, in, out, n); }
+void excl_scan64(hipStream_t st, const int64_t* in, int64_t* out, int64_t n) {
+  excl_scan_impl<int64_t>(st, in, out, n);
+}
+
+}  // namespace omm

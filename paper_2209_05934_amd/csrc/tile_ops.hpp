@@ -1,0 +1,118 @@
+// Device helpers: 16x16 tile fragments and CDNA MFMA products for gfx950.
+//
+// One 64-lane wavefront multiplies two 16x16 row-major tiles.  Lane
+// l = i + 16*q (i = l & 15, q = l >> 4) supplies, at MFMA step s = 0..3,
+// A[i][k] and B[k][j=i] for one tile index k = K(q, s).  The pairing of k with
+// (q, s) is free as long as A and B agree, and is chosen per instruction so
+// that the accumulator can feed the next product as a B fragment:
+//   v_mfma_f64_16x16x4f64 : accumulator register r of lane (j, q) holds row 4r+q
+//                            -> K(q, s) = 4s + q
+//   v_mfma_f32_16x16x4f32 and v_mfma_f32_16x16x16bf16_1k : register r of lane
+//                            (j, q) holds row 4q+r -> K(q, s) = 4q + s
+// (the f64 placement was measured on gfx950 with delta operands).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace omm {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef uint16_t bf16;
+
+__device__ __forceinline__ bf16 f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (bf16)0x7fc0;   // NaN
+  u += 0x7fffu + ((u >> 16) & 1u);                               // round to nearest even
+  return (bf16)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(bf16 h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+// value conversions between storage types
+template <typename D, typename S> __device__ __forceinline__ D cvt(S v);
+template <> __device__ __forceinline__ double cvt<double, double>(double v) { return v; }
+template <> __device__ __forceinline__ float cvt<float, double>(double v) { return (float)v; }
+template <> __device__ __forceinline__ float cvt<float, float>(float v) { return v; }
+template <> __device__ __forceinline__ double cvt<double, float>(float v) { return (double)v; }
+template <> __device__ __forceinline__ bf16 cvt<bf16, double>(double v) { return f2bf((float)v); }
+template <> __device__ __forceinline__ bf16 cvt<bf16, float>(float v) { return f2bf(v); }
+template <> __device__ __forceinline__ bf16 cvt<bf16, bf16>(bf16 v) { return v; }
+template <> __device__ __forceinline__ float cvt<float, bf16>(bf16 v) { return bf2f(v); }
+template <> __device__ __forceinline__ double cvt<double, bf16>(bf16 v) { return (double)bf2f(v); }
+
+// accumulator type for an operand type
+template <typename T> struct Acc;
+template <> struct Acc<double> { typedef d4 V; typedef double S; };
+template <> struct Acc<float> { typedef f4 V; typedef float S; };
+template <> struct Acc<bf16> { typedef f4 V; typedef float S; };
+
+template <typename T> struct Frag { T v[4]; };
+
+// tile index k supplied by lane-quad q at step s
+template <typename T> struct KMap { static __device__ __forceinline__ int k(int q, int s) { return 4 * q + s; } };
+template <> struct KMap<double> { static __device__ __forceinline__ int k(int q, int s) { return 4 * s + q; } };
+
+// output row of accumulator register r in lane-quad q
+template <typename V> struct Lay;
+template <> struct Lay<d4> { static __device__ __forceinline__ int row(int q, int r) { return 4 * r + q; } };
+template <> struct Lay<f4> { static __device__ __forceinline__ int row(int q, int r) { return 4 * q + r; } };
+
+// "row" load: lane (i, q) takes tile[i][K(q, s)]   (A operand, or B^T)
+template <typename T, typename S>
+__device__ __forceinline__ void ld_row(Frag<T>& f, const S* __restrict__ t, int lane) {
+  const S* p = t + (lane & 15) * 16;
+  const int q = lane >> 4;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) f.v[s] = cvt<T, S>(p[KMap<T>::k(q, s)]);
+}
+// "col" load: lane (j, q) takes tile[K(q, s)][j]   (B operand, or A^T)
+template <typename T, typename S>
+__device__ __forceinline__ void ld_col(Frag<T>& f, const S* __restrict__ t, int lane) {
+  const S* p = t + (lane & 15);
+  const int q = lane >> 4;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) f.v[s] = cvt<T, S>(p[16 * KMap<T>::k(q, s)]);
+}
+
+__device__ __forceinline__ void mma(d4& acc, const Frag<double>& a, const Frag<double>& b) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.v[s], b.v[s], acc, 0, 0, 0);
+}
+__device__ __forceinline__ void mma(f4& acc, const Frag<float>& a, const Frag<float>& b) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[s], b.v[s], acc, 0, 0, 0);
+}
+__device__ __forceinline__ void mma(f4& acc, const Frag<bf16>& a, const Frag<bf16>& b) {
+  s4 av = {(short)a.v[0], (short)a.v[1], (short)a.v[2], (short)a.v[3]};
+  s4 bv = {(short)b.v[0], (short)b.v[1], (short)b.v[2], (short)b.v[3]};
+  acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+}
+
+template <typename V> __device__ __forceinline__ V vzero();
+template <> __device__ __forceinline__ d4 vzero<d4>() { return d4{0.0, 0.0, 0.0, 0.0}; }
+template <> __device__ __forceinline__ f4 vzero<f4>() { return f4{0.f, 0.f, 0.f, 0.f}; }
+
+// accumulator register r of this lane sits at tile offset out_off<V>(lane, r)
+template <typename V>
+__device__ __forceinline__ int out_off(int lane, int r) { return Lay<V>::row(lane >> 4, r) * 16 + (lane & 15); }
+
+// use an accumulator as a B fragment of the next product
+template <typename T, typename V>
+__device__ __forceinline__ Frag<T> acc_as_b(const V& a) {
+  Frag<T> f;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) f.v[s] = cvt<T, typename Acc<T>::S>((typename Acc<T>::S)a[s]);
+  return f;
+}
+
+// deterministic full-wave sum
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+}  // namespace omm

@@ -1,0 +1,114 @@
+"""Convenience layer over the C ABI: one object per context.
+
+Matrices are block-sparse descriptions with the attributes row_bsz, col_bsz,
+row_ptr, col_idx, val_off and val (the layout of omm_matrix).  Values may be
+replaced by device tensors to hand the library device memory.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import Any, List, Optional, Sequence
+
+import numpy as np
+
+from . import omm as L
+
+
+@dataclass
+class Problem:
+    H: Any            # block-sparse H (unshifted)
+    S: Any            # block-sparse S, same block structure
+    C0: Any           # block-sparse initial guess (its pattern is kept fixed)
+    n: int            # number of wavefunctions
+    mode: int = L.OMM_DENSE
+    H_val: Any = None  # optional device tensors replacing the host values
+    S_val: Any = None
+    C0_val: Any = None
+
+
+def options(**kw) -> L.omm_options:
+    o = L.omm_default_options()
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+class Context:
+    def __init__(self, problems: Sequence[Problem], **opts):
+        self.problems = list(problems)
+        self.opt = options(**opts)
+        self._H = [L.BlockArgs.from_block_matrix(p.H, p.H_val) for p in self.problems]
+        self._S = [L.BlockArgs.from_block_matrix(p.S, p.S_val) for p in self.problems]
+        if len(self.problems) == 1:
+            p = self.problems[0]
+            self.ctx = L.omm_init(self._H[0], self._S[0], p.n, p.mode, self.opt)
+        else:
+            self.ctx = L.omm_init_batch(self._H, self._S, [p.n for p in self.problems],
+                                        [p.mode for p in self.problems], self.opt)
+        for i, p in enumerate(self.problems):
+            self.set_coeffs(i, p.C0, p.C0_val)
+
+    @property
+    def count(self) -> int:
+        return len(self.problems)
+
+    def set_coeffs(self, sys: int, C0, val=None) -> None:
+        L.omm_set_coeffs(self.ctx, sys, L.BlockArgs.from_block_matrix(C0, val))
+
+    def minimize(self):
+        rc, reps = L.omm_minimize(self.ctx, self.count)
+        return rc, reps
+
+    def density_matrix(self, sys: int = 0, out=None) -> np.ndarray:
+        if out is None:
+            out = np.zeros(self.problems[sys].S.val.size)
+        L.omm_density_matrix(self.ctx, sys, out)
+        return out
+
+    def coeffs(self, sys: int = 0, out=None) -> np.ndarray:
+        if out is None:
+            out = np.zeros(self.problems[sys].C0.val.size)
+        L.omm_get_coeffs(self.ctx, sys, out)
+        return out
+
+    def projected(self, sys: int = 0):
+        n = self.problems[sys].n
+        HW, SW = np.zeros((n, n)), np.zeros((n, n))
+        L.omm_get_projected(self.ctx, sys, HW, SW)
+        return HW, SW
+
+    def history(self, sys: int = 0, max_rows: int = 100000) -> np.ndarray:
+        return L.omm_get_history(self.ctx, sys, max_rows)
+
+    def sizes(self, sys: int = -1) -> L.omm_sizes:
+        return L.omm_query(self.ctx, sys)
+
+    def set_timing(self, on: bool) -> None:
+        L.omm_set_timing(self.ctx, on)
+
+    def kernel_times(self):
+        return L.omm_kernel_times(self.ctx)
+
+    def close(self) -> None:
+        if getattr(self, "ctx", None):
+            L.omm_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def report_dict(r: L.omm_report) -> dict:
+    return {k: getattr(r, k) for k, _ in r._fields_}
