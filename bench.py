@@ -1,0 +1,205 @@
+#!/usr/bin/env python3
+"""Throughput of the conjugate-gradient OMM hot path on one MI355X.
+
+A step is one whole solve of the workload: reset C to the initial guess (held
+in HBM), run CG to the stop rule through the C ABI, form the density matrix
+(Eq. 5) in device memory.  `value` = CG iterations per second over the timed
+steps.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--precision fp64|fp32|bf16]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "OMM CG iters/s & block GFLOP/s, FP64 vs mixed/batched at fixed E/atom err"
+
+# workloads: generator config, solver form, stop rule
+WORKLOADS = {
+    "cubic4_dense": dict(cfg="cubic4_dense", mode="dense", max_iter=10000,
+                         desc="4x4x4 periodic cubic lattice, 64 atoms x 13 orbitals, N_basis 832, "
+                              "N_occ 128, dense cubic-scaling OMM, eta 0, CG to ||G||_F <= 1e-9"),
+    "cubic4_cholesky": dict(cfg="cubic4_dense", mode="cholesky", max_iter=10000,
+                            desc="same 64-atom system, dense OMM on the Cholesky-reduced problem, "
+                                 "CG to ||G||_F <= 1e-9"),
+    "chain8": dict(cfg="chain8", mode="dense", max_iter=10000,
+                   desc="periodic chain of 8 atoms x 4 orbitals, N_basis 32, N_occ 16, dense, "
+                        "CG to ||G||_F <= 1e-9"),
+    "cubic8_sparse": dict(cfg="cubic8_sparse", mode="sparse", max_iter=200,
+                          desc="8x8x8 lattice, 512 atoms x 13 orbitals, N_basis 6656, N_occ 1024, "
+                               "atom-block sparse, C radius 3.0, eta 1.5, filter 1e-6, 200 CG iterations"),
+    "cubic16_mixed": dict(cfg="cubic16_mixed", mode="sparse", max_iter=20,
+                          desc="16x16x16 lattice, 4096 atoms x 13 orbitals, N_basis 53248, N_occ 8192, "
+                               "atom-block sparse, C radius 3.0, eta 1.5, filter 1e-6, 20 CG iterations"),
+}
+
+PEAKS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}   # dense TFLOP/s of MI355X
+HBM_PEAK = 8000.0                                         # GB/s
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cubic4_dense", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--max-iter", type=int, default=None)
+    ap.add_argument("--graph-iters", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-kernel-timing", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(system, spec, mode, max_iter, budget_s):
+    """The CPU oracle as it stands, on a bounded sample of the same workload."""
+    import numpy as np
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    H, S, C0 = system.H.to_dense(), system.S.to_dense(), system.C0.to_dense()
+    mask = None if spec.dense else system.C0.pattern_mask()
+    kw = dict(eta=spec.eta, tol_grad=1e-9, max_iter=max_iter, keep_history=False)
+    iters, solves, t0 = 0, 0, time.perf_counter()
+    while True:
+        if mode == "cholesky":
+            r = O.cg_minimize_cholesky(H, S, C0, **kw)
+        else:
+            r = O.cg_minimize(H, S, C0, mask=mask, **kw)
+        iters += r.iterations
+        solves += 1
+        if time.perf_counter() - t0 >= budget_s or solves >= 200:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": iters / dt, "unit": "CG iters/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{solves} full solve(s) of the same workload ({iters} CG iterations, "
+                      f"{dt:.1f} s) with the NumPy/OpenBLAS FP64 oracle, every product recomputed "
+                      f"each iteration"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              f"(the multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from ommgen import config_spec, make_system
+    from paper_2209_05934_amd import omm as L
+    from paper_2209_05934_amd.solver import Context, Problem
+
+    wl = WORKLOADS[args.workload]
+    spec = config_spec(wl["cfg"])
+    system = make_system(spec)
+    mode = {"dense": L.OMM_DENSE, "cholesky": L.OMM_DENSE_CHOLESKY, "sparse": L.OMM_BLOCK_SPARSE}[wl["mode"]]
+    prec = {"fp64": L.OMM_FP64, "fp32": L.OMM_FP32, "bf16": L.OMM_BF16}[args.precision]
+    max_iter = args.max_iter or wl["max_iter"]
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    # inputs resident in HBM before the timed region
+    Hv = torch.from_numpy(system.H.val).to(dev)
+    Sv = torch.from_numpy(system.S.val).to(dev)
+    C0v = torch.from_numpy(system.C0.val).to(dev)
+    rho = torch.zeros(system.S.val.size, dtype=torch.float64, device=dev)
+    prob = Problem(system.H, system.S, system.C0, system.n, mode, H_val=Hv, S_val=Sv, C0_val=C0v)
+    ctx = Context([prob], eta=spec.eta, tol_grad=1e-9, max_iter=max_iter, precision=prec,
+                  filter_eps=spec.filter_eps, graph_iters=args.graph_iters, history=0,
+                  hip_stream=stream.cuda_stream)
+    from paper_2209_05934_amd import omm as LL
+
+    def step():
+        ctx.set_coeffs(0, system.C0, C0v)
+        rc, reps = ctx.minimize()
+        LL.omm_density_matrix(ctx.ctx, 0, rho)
+        return reps[0]
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = 0
+    last = None
+    for _ in range(args.steps):
+        last = step()
+        iters += last.iters_total
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    sz = ctx.sizes(0)
+    value = iters / dt
+    flops_iter = sz.flops_alg_iter
+
+    # per-kernel device time with HIP events on the library's stream
+    roof = None
+    if not args.no_kernel_timing:
+        ctx.set_timing(True)
+        nstep = max(1, min(args.steps, 5))
+        for _ in range(nstep):
+            step()
+        ctx.set_timing(False)
+        ms, n = ctx.kernel_times()
+        names = ["direction products (H D, S D)", "n x n projections", "gradient products"]
+        k = int(np.argmax(ms))
+        avg_s = ms[k] / max(1, n[k]) / 1e3
+        if args.precision == "bf16":
+            achieved = sz.bytes_alg_step[k] / avg_s / 1e9
+            roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK, "traffic": None}
+        else:
+            achieved = sz.flops_alg_step[k] / avg_s / 1e12
+            peak = PEAKS[args.precision]
+            roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                    "frac": achieved / peak, "traffic": None}
+        roof.update({"kernel": names[k], "avg_launch_us": avg_s * 1e6, "launches": int(n[k]),
+                     "alg_flops_per_launch": sz.flops_alg_step[k],
+                     "exec_flops_per_launch": sz.flops_exec_step[k],
+                     "alg_bytes_per_launch": sz.bytes_alg_step[k],
+                     "class_ms": {names[i]: ms[i] for i in range(3)}})
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "CG iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32 products, f64 traces/line search",
+                  "bf16": "bf16 products (f32 accumulate), f64 traces/line search"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": args.workload + ": " + wl["desc"], "mode": wl["mode"],
+                   "precision": args.precision, "N_basis": int(system.m), "N_occ": int(system.n),
+                   "atoms": int(system.natoms)},
+        "cg_iters_per_step": iters / args.steps,
+        "gflops_alg": flops_iter * value / 1e9,
+        "alg_flops_per_iter": flops_iter,
+        "exec_flops_per_iter": sz.flops_exec_iter,
+        "energy": last.energy,
+        "energy_per_atom": last.energy / system.natoms,
+        "status": LL.omm_status_str(last.status),
+        "roofline": roof,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(system, spec, wl["mode"], max_iter, args.cpu_seconds)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

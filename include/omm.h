@@ -136,7 +136,13 @@ typedef struct {
                                over the unpadded atom-block products */
   double flops_exec_iter;   /* flops the tile kernels execute per iteration */
   double bytes_alg_iter;    /* algorithmic HBM bytes of one iteration's products
-                               (each operand and output tile moved once) */
+                               (each unpadded operand and output element moved once,
+                               at the context's operand/output precision) */
+  /* the same three figures per product step: [0] direction products H D, S D,
+   * [1] n x n projections, [2] gradient products */
+  double flops_alg_step[3];
+  double flops_exec_step[3];
+  double bytes_alg_step[3];
 } omm_sizes;
 
 typedef struct omm_ctx omm_ctx;
@@ -156,10 +162,13 @@ int omm_init(omm_ctx** out, const omm_matrix* H, const omm_matrix* S, int64_t n_
 
 /* Creates one context holding `count` independent systems (k-points, snapshots,
  * separate structures) that every later call advances together, each with its
- * own H[i], S[i], n_occ[i] and modes[i]; options are shared.  System indices
- * 0..count-1 are used by the per-system calls below. */
+ * own H[i], S[i], n_occ[i], modes[i] and Kim shift etas[i] (etas may be NULL:
+ * opt->eta for all); the other options are shared (filter_eps applies to the
+ * block-sparse systems only).  System indices 0..count-1 are used by the
+ * per-system calls below. */
 int omm_init_batch(omm_ctx** out, int32_t count, const omm_matrix* H, const omm_matrix* S,
-                   const int64_t* n_occ, const int32_t* modes, const omm_options* opt);
+                   const int64_t* n_occ, const int32_t* modes, const double* etas,
+                   const omm_options* opt);
 
 /* Sets the initial guess of system `sys` (Sec. III C/D: random values inside the
  * localization radius).  C0 is m x n with the same block rows as H; its block

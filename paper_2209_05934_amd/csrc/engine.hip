@@ -62,7 +62,8 @@ struct SysHost {
   // work counts
   double flops_alg[3] = {0, 0, 0};
   double flops_exec[3] = {0, 0, 0};
-  double bytes_alg = 0;
+  double el_in[3] = {0, 0, 0};    // unpadded operand elements read per product step
+  double el_out[3] = {0, 0, 0};   // unpadded output elements written per product step
   int64_t pairs[3] = {0, 0, 0};
   int64_t tiles_h = 0, tiles_c = 0, tiles_hc = 0, tiles_w = 0;
 };
@@ -368,10 +369,12 @@ void count_sparse_work(SysHost& s) {
   s.flops_alg[0] = (ident ? 1.0 : 2.0) * f1;
   s.flops_alg[1] = 4.0 * f2;
   s.flops_alg[2] = 2.0 * f3;
-  // one pass over every operand and output of the three product steps, FP64
-  s.bytes_alg = 8.0 * ((ident ? 1 : 2) * nh_el + nc_el + 2 * nhc_el) +          // S1
-                8.0 * (2 * nc_el + 2 * nhc_el + 4 * nw_el) +                     // S2
-                8.0 * (2 * nhc_el + 2 * nw_el + nc_el);                           // gradient
+  s.el_in[0] = (ident ? 1 : 2) * nh_el + nc_el;
+  s.el_out[0] = 2 * nhc_el;
+  s.el_in[1] = 2 * nc_el + 2 * nhc_el;
+  s.el_out[1] = 4 * nw_el;
+  s.el_in[2] = 2 * nhc_el + 2 * nw_el;
+  s.el_out[2] = nc_el;
 }
 
 void count_dense_work(SysHost& s) {
@@ -380,13 +383,17 @@ void count_dense_work(SysHost& s) {
   s.flops_alg[0] = (ident ? 1.0 : 2.0) * 2.0 * m * m * n;
   s.flops_alg[1] = 4.0 * 2.0 * m * n * n;
   s.flops_alg[2] = 2.0 * 2.0 * m * n * n;
-  s.bytes_alg = 8.0 * ((ident ? 1 : 2) * m * m + m * n + 2 * m * n) + 8.0 * (4 * m * n + 4 * n * n) +
-                8.0 * (3 * m * n + 2 * n * n);
+  s.el_in[0] = (ident ? 1 : 2) * m * m + m * n;
+  s.el_out[0] = 2 * m * n;
+  s.el_in[1] = 4 * m * n;
+  s.el_out[1] = 4 * n * n;
+  s.el_in[2] = 2 * m * n + 2 * n * n;
+  s.el_out[2] = m * n;
 }
 
 // ----------------------------------------------------------------- init (H, S ingest)
 void ingest(omm_ctx* c, int count, const omm_matrix* H, const omm_matrix* S, const int64_t* n_occ,
-            const int32_t* modes) {
+            const int32_t* modes, const double* etas) {
   c->nsys = count;
   c->sys.resize(count);
   // validation (host only)
@@ -408,7 +415,8 @@ void ingest(omm_ctx* c, int count, const omm_matrix* H, const omm_matrix* S, con
     for (int v : s.H.rbs) s.m += v;
     s.n = n_occ[i];
     if (s.n < 1 || s.n > s.m) throw ArgError("n_occ must satisfy 1 <= n_occ <= m");
-    s.eta = c->opt.eta;
+    s.eta = etas ? etas[i] : c->opt.eta;
+    if (!std::isfinite(s.eta)) throw ArgError("eta must be finite");
     if (s.mode == OMM_BLOCK_SPARSE)
       for (int v : s.H.rbs)
         if (v > 16) throw ArgError("block-sparse mode needs basis blocks of at most 16 orbitals");
@@ -1117,7 +1125,7 @@ const char* omm_status_str(int32_t s) {
 const char* omm_last_error(const omm_ctx* c) { return c ? c->err.c_str() : g_last_init_error.c_str(); }
 
 int omm_init_batch(omm_ctx** out, int32_t count, const omm_matrix* H, const omm_matrix* S, const int64_t* n_occ,
-                   const int32_t* modes, const omm_options* opt) {
+                   const int32_t* modes, const double* etas, const omm_options* opt) {
   g_last_init_error.clear();
   if (!out) {
     g_last_init_error = "out is NULL";
@@ -1167,7 +1175,8 @@ int omm_init_batch(omm_ctx** out, int32_t count, const omm_matrix* H, const omm_
   }
   c->opt = o;
   c->prec = (Prec)o.precision;
-  struct A { int count; const omm_matrix *H, *S; const int64_t* n; const int32_t* modes; } a{count, H, S, n_occ, modes};
+  struct A { int count; const omm_matrix *H, *S; const int64_t* n; const int32_t* modes; const double* etas; } a{
+      count, H, S, n_occ, modes, etas};
   int rc = guard(c, [](omm_ctx* cc, void* v) -> int {
     auto* q = (A*)v;
     if (cc->opt.hip_stream) cc->stream = (hipStream_t)cc->opt.hip_stream;
@@ -1176,7 +1185,7 @@ int omm_init_batch(omm_ctx** out, int32_t count, const omm_matrix* H, const omm_
       cc->own_stream = true;
     }
     OMM_HIP(hipHostMalloc((void**)&cc->h_st, sizeof(SysState) * q->count, hipHostMallocDefault));
-    ingest(cc, q->count, q->H, q->S, q->n, q->modes);
+    ingest(cc, q->count, q->H, q->S, q->n, q->modes, q->etas);
     return OMM_OK;
   }, &a);
   if (rc != OMM_OK) {
@@ -1190,7 +1199,7 @@ int omm_init_batch(omm_ctx** out, int32_t count, const omm_matrix* H, const omm_
 
 int omm_init(omm_ctx** out, const omm_matrix* H, const omm_matrix* S, int64_t n_occ, int32_t mode,
              const omm_options* opt) {
-  return omm_init_batch(out, 1, H, S, &n_occ, &mode, opt);
+  return omm_init_batch(out, 1, H, S, &n_occ, &mode, nullptr, opt);
 }
 
 int omm_set_coeffs(omm_ctx* c, int32_t sys, const omm_matrix* C0) {
@@ -1382,9 +1391,18 @@ int omm_query(const omm_ctx* cc, int32_t sys, omm_sizes* z) {
     z->pairs_s1 += s.pairs[0];
     z->pairs_s2 += s.pairs[1];
     z->pairs_grad += s.pairs[2];
-    z->flops_alg_iter += s.flops_alg[0] + s.flops_alg[1] + s.flops_alg[2];
-    z->flops_exec_iter += s.flops_exec[0] + s.flops_exec[1] + s.flops_exec[2];
-    z->bytes_alg_iter += s.bytes_alg;
+    // operand / output element sizes of the product kernels at the context precision
+    const double bi = c->prec == P64 ? 8.0 : (c->prec == P32 ? 4.0 : 2.0);
+    const double bo = c->prec == P64 ? 8.0 : 4.0;
+    for (int k = 0; k < 3; ++k) {
+      const double by = s.el_in[k] * bi + s.el_out[k] * bo;
+      z->flops_alg_step[k] += s.flops_alg[k];
+      z->flops_exec_step[k] += s.flops_exec[k];
+      z->bytes_alg_step[k] += by;
+      z->flops_alg_iter += s.flops_alg[k];
+      z->flops_exec_iter += s.flops_exec[k];
+      z->bytes_alg_iter += by;
+    }
   }
   return OMM_OK;
 }

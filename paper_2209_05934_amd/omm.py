@@ -60,6 +60,8 @@ class omm_sizes(C.Structure):
         ("tiles_h", C.c_int64), ("tiles_c", C.c_int64), ("tiles_hc", C.c_int64), ("tiles_w", C.c_int64),
         ("pairs_s1", C.c_int64), ("pairs_s2", C.c_int64), ("pairs_grad", C.c_int64),
         ("flops_alg_iter", C.c_double), ("flops_exec_iter", C.c_double), ("bytes_alg_iter", C.c_double),
+        ("flops_alg_step", C.c_double * 3), ("flops_exec_step", C.c_double * 3),
+        ("bytes_alg_step", C.c_double * 3),
     ]
 
 
@@ -81,7 +83,7 @@ def load(path: Optional[str] = None) -> C.CDLL:
         "omm_default_options": (None, [C.POINTER(omm_options)]),
         "omm_init": (I32, [C.POINTER(P), MP, MP, I64, I32, C.POINTER(omm_options)]),
         "omm_init_batch": (I32, [C.POINTER(P), I32, MP, MP, C.POINTER(I64), C.POINTER(I32),
-                                 C.POINTER(omm_options)]),
+                                 C.POINTER(D), C.POINTER(omm_options)]),
         "omm_set_coeffs": (I32, [P, I32, MP]),
         "omm_minimize": (I32, [P, C.POINTER(omm_report)]),
         "omm_density_matrix": (I32, [P, I32, P, I32]),
@@ -183,14 +185,16 @@ def omm_init(H: BlockArgs, S: BlockArgs, n_occ: int, mode: int, opt: Optional[om
 
 
 def omm_init_batch(Hs: Sequence[BlockArgs], Ss: Sequence[BlockArgs], n_occ: Sequence[int],
-                   modes: Sequence[int], opt: Optional[omm_options] = None):
+                   modes: Sequence[int], etas: Optional[Sequence[float]] = None,
+                   opt: Optional[omm_options] = None):
     count = len(Hs)
     Harr = (omm_matrix * count)(*[h.struct for h in Hs])
     Sarr = (omm_matrix * count)(*[s.struct for s in Ss])
     narr = (C.c_int64 * count)(*[int(v) for v in n_occ])
     marr = (C.c_int32 * count)(*[int(v) for v in modes])
+    earr = (C.c_double * count)(*[float(v) for v in etas]) if etas is not None else None
     ctx = C.c_void_p()
-    rc = load().omm_init_batch(C.byref(ctx), count, Harr, Sarr, narr, marr,
+    rc = load().omm_init_batch(C.byref(ctx), count, Harr, Sarr, narr, marr, earr,
                                C.byref(opt) if opt is not None else None)
     _check(None, rc)
     return ctx

@@ -22,6 +22,7 @@ class Problem:
     C0: Any           # block-sparse initial guess (its pattern is kept fixed)
     n: int            # number of wavefunctions
     mode: int = L.OMM_DENSE
+    eta: Optional[float] = None  # Kim shift of this system (None: the context option)
     H_val: Any = None  # optional device tensors replacing the host values
     S_val: Any = None
     C0_val: Any = None
@@ -44,10 +45,13 @@ class Context:
         self._S = [L.BlockArgs.from_block_matrix(p.S, p.S_val) for p in self.problems]
         if len(self.problems) == 1:
             p = self.problems[0]
+            if p.eta is not None:
+                self.opt.eta = p.eta
             self.ctx = L.omm_init(self._H[0], self._S[0], p.n, p.mode, self.opt)
         else:
+            etas = [self.opt.eta if p.eta is None else p.eta for p in self.problems]
             self.ctx = L.omm_init_batch(self._H, self._S, [p.n for p in self.problems],
-                                        [p.mode for p in self.problems], self.opt)
+                                        [p.mode for p in self.problems], etas, self.opt)
         for i, p in enumerate(self.problems):
             self.set_coeffs(i, p.C0, p.C0_val)
 
