@@ -57,6 +57,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--autotune", action="store_true", help="time the split factors of the tile products")
     return ap.parse_args()
 
 
@@ -117,7 +118,7 @@ def main():
     prob = Problem(system.H, system.S, system.C0, system.n, mode, H_val=Hv, S_val=Sv, C0_val=C0v)
     ctx = Context([prob], eta=spec.eta, tol_grad=1e-9, max_iter=max_iter, precision=prec,
                   filter_eps=spec.filter_eps, graph_iters=args.graph_iters, history=0,
-                  hip_stream=stream.cuda_stream)
+                  hip_stream=stream.cuda_stream, autotune=1 if args.autotune else 0)
     from paper_2209_05934_amd import omm as LL
 
     def step():

@@ -119,6 +119,8 @@ struct omm_ctx {
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
   int graph_iters = 0;
+  bool tuned = false;
+  std::string tune_log;
   // timing
   bool timing = false;
   double kt_ms[3] = {0, 0, 0};
@@ -246,6 +248,8 @@ void set_err(omm_ctx* c, const std::string& m) {
   if (c) c->err = m;
   else g_last_init_error = m;
 }
+
+int pick_ks(int64_t nout, int64_t npairs);
 
 // ----------------------------------------------------------------- pattern helpers
 void upload_pat(omm_ctx* c, Pat& P, int nrows, const std::vector<std::vector<int>>& rows, bool prep) {
@@ -804,6 +808,10 @@ void prepare(omm_ctx* c) {
   b.hist = c->d_hist;
   b.nsys = c->nsys;
   b.eps2 = 0.0;
+  b.ks[0] = pick_ks(c->Ps1.nout, c->Ps1.npairs);
+  b.ks[1] = pick_ks(c->Ps2.nout, c->Ps2.npairs);
+  b.ks[2] = pick_ks(c->Pgrad.nout, c->Pgrad.npairs);
+  c->tuned = false;
   c->CM = dalloc<double>(c, std::max<int64_t>(1, c->TCM.nnz) * TE, true);
   c->rho = dalloc<double>(c, std::max<int64_t>(1, c->TH.nnz) * TE, true);
   bool any_chol = false;
@@ -811,6 +819,102 @@ void prepare(omm_ctx* c) {
   c->Cb = any_chol ? dalloc<double>(c, ntc * TE, true) : nullptr;
   OMM_HIP(hipStreamSynchronize(st));
   c->prepared = true;
+}
+
+// Waves that split one output tile's pair list: enough waves in flight to hide
+// memory latency when there are few output tiles with long pair lists.
+int pick_ks(int64_t nout, int64_t npairs) {
+  if (nout <= 0) return 1;
+  const double avg = (double)npairs / (double)nout;
+  for (int ks : {8, 4, 2})
+    if (nout * ks <= 16384 && avg >= 4.0 * ks) return ks;
+  return 1;
+}
+
+CGParams params(const omm_ctx* c);
+bool any_filter(const omm_ctx* c);
+
+// Autotuner: time every split factor of each product step on the real work
+// lists (after the initial products, so every operand is valid) and keep the
+// fastest; results are cached per (step, precision, work-list size) in a text
+// file when a cache path is given.
+std::string tune_key(int cls, int prec, const Plan& P) {
+  return std::to_string(cls) + ":" + std::to_string(prec) + ":" + std::to_string(P.nout) + ":" +
+         std::to_string(P.npairs);
+}
+
+void autotune(omm_ctx* c) {
+  std::vector<std::pair<std::string, int>> cache;
+  if (c->opt.tune_cache) {
+    if (FILE* f = std::fopen(c->opt.tune_cache, "r")) {
+      char key[256];
+      int v;
+      while (std::fscanf(f, "%255s %d", key, &v) == 2) cache.emplace_back(key, v);
+      std::fclose(f);
+    }
+  }
+  const Plan* plans[3] = {&c->Ps1, &c->Ps2, &c->Pgrad};
+  const Prec p = c->prec;
+  const int mask = PH_FP64 | PH_LOW;
+  const bool filt = any_filter(c);
+  hipEvent_t e0, e1;
+  OMM_HIP(hipEventCreate(&e0));
+  OMM_HIP(hipEventCreate(&e1));
+  bool added = false;
+  c->tune_log.clear();
+  for (int cls = 0; cls < 3; ++cls) {
+    const std::string key = tune_key(cls, (int)p, *plans[cls]);
+    int found = 0;
+    for (auto& kv : cache)
+      if (kv.first == key) found = kv.second;
+    if (found) {
+      c->b.ks[cls] = found;
+      continue;
+    }
+    float best = 1e30f;
+    int best_ks = c->b.ks[cls];
+    for (int ks : {1, 2, 4, 8}) {
+      c->b.ks[cls] = ks;
+      float tmin = 1e30f;
+      for (int rep = 0; rep < 3; ++rep) {
+        OMM_HIP(hipEventRecord(e0, c->stream));
+        if (cls == 0) launch_s1(c->stream, c->b, p, mask, false, filt);
+        else if (cls == 1) launch_s2(c->stream, c->b, p, mask, false, filt);
+        else launch_grad(c->stream, c->b, p, mask, false);
+        OMM_HIP(hipEventRecord(e1, c->stream));
+        OMM_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        OMM_HIP(hipEventElapsedTime(&ms, e0, e1));
+        tmin = std::min(tmin, ms);
+      }
+      c->tune_log += key + " ks=" + std::to_string(ks) + " " + std::to_string(tmin) + "ms; ";
+      if (tmin < best) {
+        best = tmin;
+        best_ks = ks;
+      }
+    }
+    c->b.ks[cls] = best_ks;
+    cache.emplace_back(key, best_ks);
+    added = true;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (added && c->opt.tune_cache) {
+    if (FILE* f = std::fopen(c->opt.tune_cache, "w")) {
+      for (auto& kv : cache) std::fprintf(f, "%s %d\n", kv.first.c_str(), kv.second);
+      std::fclose(f);
+    }
+  }
+  c->tuned = true;
+  // the graph holds the launch shapes: capture again with the tuned factors
+  if (c->gexec) {
+    (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+  }
+  if (c->graph) {
+    (void)hipGraphDestroy(c->graph);
+    c->graph = nullptr;
+  }
 }
 
 CGParams params(const omm_ctx* c) {
@@ -962,6 +1066,7 @@ int minimize(omm_ctx* c, omm_report* reps) {
     c->kt_n[k] = 0;
   }
   init_sequence(c);
+  if (c->opt.autotune && !c->tuned) autotune(c);
   const bool use_graph = c->opt.graph_iters > 0 && !c->timing;
   if (use_graph && !c->gexec) capture_graph(c);
   const int K = use_graph ? c->graph_iters : std::max(1, c->opt.graph_iters > 0 ? c->opt.graph_iters : 1);

@@ -46,6 +46,7 @@ struct Bufs {   // every device buffer the iteration kernels touch
   double* hist;
   int nsys;
   double eps2;                   // filter threshold squared (block-sparse products)
+  int ks[3];                     // waves splitting one output tile: direction, n x n, gradient products
 };
 
 // one CG iteration step (all systems whose phase matches `mask`), arithmetic `prec`

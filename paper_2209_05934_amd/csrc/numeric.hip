@@ -70,107 +70,187 @@ __device__ void filter_tile(V& acc, int lane, const uint8_t* __restrict__ rseg,
     if (tot[r] < eps2) acc[r] = 0;
 }
 
+// Work distribution of the tile-product kernels.  A workgroup holds NW = max(4, KS)
+// waves; KS consecutive waves split the pair list of one output tile into KS
+// contiguous chunks and add their accumulators in a fixed tree through LDS, so
+// results are bitwise reproducible for a given KS.  Logical block ids are
+// renumbered so that consecutive ids (neighbouring output tiles, which share
+// operand tiles) run on the same XCD: the hardware deals workgroups to the 8
+// XCDs round-robin.
+__device__ __forceinline__ int xcd_block() {
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int x = b & 7, q = nb >> 3, r = nb & 7;
+  return x * q + min(x, r) + (b >> 3);
+}
+
+template <int KS> struct Split {
+  static constexpr int NW = KS > 4 ? KS : 4;     // waves per workgroup
+  static constexpr int G = NW / KS;              // output tiles per workgroup
+  static constexpr int RED = KS > 1 ? NW / 2 : 1;   // LDS slots of the reduction tree
+};
+
+template <int KS, int NACC, typename V>
+__device__ __forceinline__ void ks_reduce(V (&acc)[NACC], V* buf, int grp, int wk, int lane) {
+  if (KS == 1) return;
+#pragma unroll
+  for (int stride = KS / 2; stride >= 1; stride >>= 1) {
+    if (wk >= stride && wk < 2 * stride) {
+#pragma unroll
+      for (int a = 0; a < NACC; ++a) buf[((grp * (KS / 2) + wk - stride) * NACC + a) * 64 + lane] = acc[a];
+    }
+    __syncthreads();
+    if (wk < stride) {
+#pragma unroll
+      for (int a = 0; a < NACC; ++a) acc[a] += buf[((grp * (KS / 2) + wk) * NACC + a) * 64 + lane];
+    }
+    __syncthreads();
+  }
+}
+
+// chunk [b, e) of output tile t's pair list handled by split-wave wk
+__device__ __forceinline__ void ks_chunk(const PlanView& P, int t, int wk, int KS, int64_t& b, int64_t& e) {
+  const int64_t p0 = P.pp[t], n = P.pp[t + 1] - p0;
+  b = p0 + (n * wk) / KS;
+  e = p0 + (n * (wk + 1)) / KS;
+}
+
 // ------------------------------------------------------------------ S1: HD = H D, SD = S D
-template <typename TI, typename TO, bool FILTER>
-__global__ __launch_bounds__(256) void k_s1(PlanView P, const int* __restrict__ orow, const int* __restrict__ ocol,
-                                          const int* __restrict__ brow_sys, const SysInfo* __restrict__ info,
-                                          const SysState* __restrict__ st, int mask,
-                                          const TI* __restrict__ Hm, const TI* __restrict__ Sm,
-                                          const TI* __restrict__ Bm, TO* __restrict__ O1, TO* __restrict__ O2,
-                                          const int* __restrict__ hc_to_c, const uint8_t* __restrict__ wseg,
-                                          double eps2) {
+template <typename TI, typename TO, bool FILTER, int KS>
+__global__ __launch_bounds__(Split<KS>::NW * 64) void k_s1(
+    PlanView P, const int* __restrict__ orow, const int* __restrict__ ocol, const int* __restrict__ brow_sys,
+    const SysInfo* __restrict__ info, const SysState* __restrict__ st, int mask, const TI* __restrict__ Hm,
+    const TI* __restrict__ Sm, const TI* __restrict__ Bm, TO* __restrict__ O1, TO* __restrict__ O2,
+    const int* __restrict__ hc_to_c, const uint8_t* __restrict__ wseg) {
   typedef typename Acc<TI>::V V;
-  const int lane = threadIdx.x & 63;
-  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (t >= P.nout) return;
-  const int s = brow_sys[orow[t]];
-  if (!on(st, s, mask)) return;
-  const bool ident = info[s].ident_s != 0;
-  V a1 = vzero<V>(), a2 = vzero<V>();
-  const int64_t pe = P.pp[t + 1];
-  for (int64_t p = P.pp[t]; p < pe; ++p) {
-    const int2 pr = P.pairs[p];
-    Frag<TI> fb, fa;
-    ld_col(fb, Bm + (size_t)pr.y * TE, lane);
-    ld_row(fa, Hm + (size_t)pr.x * TE, lane);
-    mma(a1, fa, fb);
-    if (!ident) {
-      ld_row(fa, Sm + (size_t)pr.x * TE, lane);
-      mma(a2, fa, fb);
+  typedef Split<KS> SP;
+  __shared__ V red[SP::RED * 2 * 64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int grp = wave / KS, wk = wave - grp * KS;
+  const int t = xcd_block() * SP::G + grp;
+  bool act = t < P.nout;
+  int s = 0;
+  if (act) {
+    s = brow_sys[orow[t]];
+    act = on(st, s, mask);
+  }
+  const bool ident = act && info[s].ident_s != 0;
+  V acc[2] = {vzero<V>(), vzero<V>()};
+  if (act) {
+    int64_t b, e;
+    ks_chunk(P, t, wk, KS, b, e);
+    if (b < e) {
+      int2 pr = P.pairs[b];
+      Frag<TI> fb, fh, fs;
+      ld_col(fb, Bm + (size_t)pr.y * TE, lane);
+      ld_row(fh, Hm + (size_t)pr.x * TE, lane);
+      if (!ident) ld_row(fs, Sm + (size_t)pr.x * TE, lane);
+      for (int64_t p = b; p < e; ++p) {
+        const int2 nx = P.pairs[p + 1 < e ? p + 1 : p];   // prefetch the next pair
+        Frag<TI> nb, nh, ns;
+        ld_col(nb, Bm + (size_t)nx.y * TE, lane);
+        ld_row(nh, Hm + (size_t)nx.x * TE, lane);
+        if (!ident) ld_row(ns, Sm + (size_t)nx.x * TE, lane);
+        mma(acc[0], fh, fb);
+        if (!ident) mma(acc[1], fs, fb);
+        fb = nb;
+        fh = nh;
+        fs = ns;
+      }
     }
   }
+  ks_reduce<KS, 2>(acc, red, grp, wk, lane);
+  if (!act || wk != 0) return;
   if (ident) {   // S = I: S B is B's own tile
     typedef typename Acc<TI>::S AS;
     const int ct = hc_to_c[t];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) a2[r] = ct >= 0 ? cvt<AS, TI>(Bm[(size_t)ct * TE + out_off<V>(lane, r)]) : (AS)0;
+    for (int r = 0; r < 4; ++r) acc[1][r] = ct >= 0 ? cvt<AS, TI>(Bm[(size_t)ct * TE + out_off<V>(lane, r)]) : (AS)0;
   }
   if (FILTER) {
     const uint8_t* cs = wseg + 32 * (size_t)ocol[t];
     const double e2 = info[s].eps2;
-    filter_tile(a1, lane, nullptr, cs, e2);
-    filter_tile(a2, lane, nullptr, cs, e2);
+    filter_tile(acc[0], lane, nullptr, cs, e2);
+    filter_tile(acc[1], lane, nullptr, cs, e2);
   }
   TO* o1 = O1 + (size_t)t * TE;
   TO* o2 = O2 + (size_t)t * TE;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    o1[out_off<V>(lane, r)] = (TO)a1[r];
-    o2[out_off<V>(lane, r)] = (TO)a2[r];
+    o1[out_off<V>(lane, r)] = (TO)acc[0][r];
+    o2[out_off<V>(lane, r)] = (TO)acc[1][r];
   }
 }
 
 // ------------------------------------------------------------------ S2: n x n projections
-template <typename TI, typename TM, typename TO, int NPROD, bool FILTER>
-__global__ __launch_bounds__(256) void k_s2(PlanView P, const int* __restrict__ orow, const int* __restrict__ ocol,
-                                          const int* __restrict__ wrow_sys, const SysInfo* __restrict__ info,
-                                          const SysState* __restrict__ st, int mask, const TI* __restrict__ Cm, const TI* __restrict__ Dm,
-                                          const TM* __restrict__ HDm, const TM* __restrict__ SDm,
-                                          TO* __restrict__ X, TO* __restrict__ Y, TO* __restrict__ S2o,
-                                          TO* __restrict__ H2o, const uint8_t* __restrict__ wseg, double eps2) {
+template <typename TI, typename TM, typename TO, int NPROD, bool FILTER, int KS>
+__global__ __launch_bounds__(Split<KS>::NW * 64) void k_s2(
+    PlanView P, const int* __restrict__ orow, const int* __restrict__ ocol, const int* __restrict__ wrow_sys,
+    const SysInfo* __restrict__ info, const SysState* __restrict__ st, int mask, const TI* __restrict__ Cm,
+    const TI* __restrict__ Dm, const TM* __restrict__ HDm, const TM* __restrict__ SDm, TO* __restrict__ X,
+    TO* __restrict__ Y, TO* __restrict__ S2o, TO* __restrict__ H2o, const uint8_t* __restrict__ wseg) {
   typedef typename Acc<TI>::V V;
-  const int lane = threadIdx.x & 63;
-  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (t >= P.nout) return;
-  const int s = wrow_sys[orow[t]];
-  if (!on(st, s, mask)) return;
-  V ax = vzero<V>(), ay = vzero<V>(), as2 = vzero<V>(), ah2 = vzero<V>();
-  const int64_t pe = P.pp[t + 1];
-  for (int64_t p = P.pp[t]; p < pe; ++p) {
-    const int2 pr = P.pairs[p];
-    Frag<TI> fc, fhd, fsd;
-    ld_col(fc, Cm + (size_t)pr.x * TE, lane);     // A = C^T
-    ld_col(fhd, HDm + (size_t)pr.y * TE, lane);
-    ld_col(fsd, SDm + (size_t)pr.y * TE, lane);
-    mma(ax, fc, fsd);
-    mma(ay, fc, fhd);
-    if (NPROD == 4) {
-      Frag<TI> fd;
-      ld_col(fd, Dm + (size_t)pr.x * TE, lane);   // A = D^T
-      mma(as2, fd, fsd);
-      mma(ah2, fd, fhd);
+  typedef Split<KS> SP;
+  __shared__ V red[SP::RED * NPROD * 64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int grp = wave / KS, wk = wave - grp * KS;
+  const int t = xcd_block() * SP::G + grp;
+  bool act = t < P.nout;
+  int s = 0;
+  if (act) {
+    s = wrow_sys[orow[t]];
+    act = on(st, s, mask);
+  }
+  V acc[NPROD];
+#pragma unroll
+  for (int a = 0; a < NPROD; ++a) acc[a] = vzero<V>();
+  if (act) {
+    int64_t b, e;
+    ks_chunk(P, t, wk, KS, b, e);
+    if (b < e) {
+      int2 pr = P.pairs[b];
+      Frag<TI> fc, fd, fhd, fsd;
+      ld_col(fc, Cm + (size_t)pr.x * TE, lane);     // A = C^T
+      if (NPROD == 4) ld_col(fd, Dm + (size_t)pr.x * TE, lane);   // A = D^T
+      ld_col(fhd, HDm + (size_t)pr.y * TE, lane);
+      ld_col(fsd, SDm + (size_t)pr.y * TE, lane);
+      for (int64_t p = b; p < e; ++p) {
+        const int2 nx = P.pairs[p + 1 < e ? p + 1 : p];
+        Frag<TI> nc, nd, nhd, nsd;
+        ld_col(nc, Cm + (size_t)nx.x * TE, lane);
+        if (NPROD == 4) ld_col(nd, Dm + (size_t)nx.x * TE, lane);
+        ld_col(nhd, HDm + (size_t)nx.y * TE, lane);
+        ld_col(nsd, SDm + (size_t)nx.y * TE, lane);
+        mma(acc[0], fc, fsd);
+        mma(acc[1], fc, fhd);
+        if (NPROD == 4) {
+          mma(acc[2], fd, fsd);
+          mma(acc[3], fd, fhd);
+        }
+        fc = nc;
+        fd = nd;
+        fhd = nhd;
+        fsd = nsd;
+      }
     }
   }
+  ks_reduce<KS, NPROD>(acc, red, grp, wk, lane);
+  if (!act || wk != 0) return;
   if (FILTER) {
     const uint8_t* rs = wseg + 32 * (size_t)orow[t];
     const uint8_t* cs = wseg + 32 * (size_t)ocol[t];
     const double e2 = info[s].eps2;
-    filter_tile(ax, lane, rs, cs, e2);
-    filter_tile(ay, lane, rs, cs, e2);
-    if (NPROD == 4) {
-      filter_tile(as2, lane, rs, cs, e2);
-      filter_tile(ah2, lane, rs, cs, e2);
-    }
+#pragma unroll
+    for (int a = 0; a < NPROD; ++a) filter_tile(acc[a], lane, rs, cs, e2);
   }
   const size_t o = (size_t)t * TE;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int e = out_off<V>(lane, r);
-    X[o + e] = (TO)ax[r];
-    Y[o + e] = (TO)ay[r];
+    X[o + e] = (TO)acc[0][r];
+    Y[o + e] = (TO)acc[1][r];
     if (NPROD == 4) {
-      S2o[o + e] = (TO)as2[r];
-      H2o[o + e] = (TO)ah2[r];
+      S2o[o + e] = (TO)acc[2][r];
+      H2o[o + e] = (TO)acc[3][r];
     }
   }
 }
@@ -415,32 +495,50 @@ __global__ __launch_bounds__(256) void k_update_nn(const int* __restrict__ tw_ro
 }
 
 // ------------------------------------------------------------------ gradient on C's pattern
-template <typename TI>
-__global__ __launch_bounds__(256) void k_grad(PlanView P, const int* __restrict__ tc_row,
-                                            const int* __restrict__ brow_sys, const SysState* __restrict__ st,
-                                            int mask, const TI* __restrict__ HCm, const TI* __restrict__ SCm,
-                                            const TI* __restrict__ S0m, const TI* __restrict__ H0m,
-                                            const double* __restrict__ HC, const int* __restrict__ c_in_hc,
-                                            const uint32_t* __restrict__ cmask, const double* __restrict__ Gold,
-                                            double* __restrict__ G, double* __restrict__ gpart) {
+template <typename TI, int KS>
+__global__ __launch_bounds__(Split<KS>::NW * 64) void k_grad(
+    PlanView P, const int* __restrict__ tc_row, const int* __restrict__ brow_sys, const SysState* __restrict__ st,
+    int mask, const TI* __restrict__ HCm, const TI* __restrict__ SCm, const TI* __restrict__ S0m,
+    const TI* __restrict__ H0m, const double* __restrict__ HC, const int* __restrict__ c_in_hc,
+    const uint32_t* __restrict__ cmask, const double* __restrict__ Gold, double* __restrict__ G,
+    double* __restrict__ gpart) {
   typedef typename Acc<TI>::V V;
-  const int lane = threadIdx.x & 63;
-  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (t >= P.nout) return;
-  const int s = brow_sys[tc_row[t]];
-  if (!on(st, s, mask)) return;
-  V acc = vzero<V>();
-  const int64_t pe = P.pp[t + 1];
-  for (int64_t p = P.pp[t]; p < pe; ++p) {
-    const int2 pr = P.pairs[p];
-    Frag<TI> fa, fb;
-    ld_row(fa, HCm + (size_t)pr.x * TE, lane);
-    ld_col(fb, S0m + (size_t)pr.y * TE, lane);
-    mma(acc, fa, fb);
-    ld_row(fa, SCm + (size_t)pr.x * TE, lane);
-    ld_col(fb, H0m + (size_t)pr.y * TE, lane);
-    mma(acc, fa, fb);
+  typedef Split<KS> SP;
+  __shared__ V red[SP::RED * 64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int grp = wave / KS, wk = wave - grp * KS;
+  const int t = xcd_block() * SP::G + grp;
+  bool act = t < P.nout;
+  if (act) act = on(st, brow_sys[tc_row[t]], mask);
+  V acc[1] = {vzero<V>()};
+  if (act) {
+    int64_t b, e;
+    ks_chunk(P, t, wk, KS, b, e);
+    if (b < e) {
+      int2 pr = P.pairs[b];
+      Frag<TI> fh, fs, fw, fv;
+      ld_row(fh, HCm + (size_t)pr.x * TE, lane);
+      ld_row(fs, SCm + (size_t)pr.x * TE, lane);
+      ld_col(fw, S0m + (size_t)pr.y * TE, lane);
+      ld_col(fv, H0m + (size_t)pr.y * TE, lane);
+      for (int64_t p = b; p < e; ++p) {
+        const int2 nx = P.pairs[p + 1 < e ? p + 1 : p];
+        Frag<TI> nh, ns, nw, nv;
+        ld_row(nh, HCm + (size_t)nx.x * TE, lane);
+        ld_row(ns, SCm + (size_t)nx.x * TE, lane);
+        ld_col(nw, S0m + (size_t)nx.y * TE, lane);
+        ld_col(nv, H0m + (size_t)nx.y * TE, lane);
+        mma(acc[0], fh, fw);
+        mma(acc[0], fs, fv);
+        fh = nh;
+        fs = ns;
+        fw = nw;
+        fv = nv;
+      }
+    }
   }
+  ks_reduce<KS, 1>(acc, red, grp, wk, lane);
+  if (!act || wk != 0) return;
   const uint32_t mk = cmask[t];
   const int j = lane & 15, q = lane >> 4;
   const double* hc = HC + (size_t)c_in_hc[t] * TE;
@@ -450,7 +548,7 @@ __global__ __launch_bounds__(256) void k_grad(PlanView P, const int* __restrict_
     const int row = Lay<V>::row(q, r);
     const int e = row * 16 + j;
     const bool in = ((mk >> row) & 1u) && ((mk >> (16 + j)) & 1u);
-    const double g = in ? 8.0 * hc[e] - 4.0 * (double)acc[r] : 0.0;
+    const double g = in ? 8.0 * hc[e] - 4.0 * (double)acc[0][r] : 0.0;
     G[(size_t)t * TE + e] = g;
     gg += g * g;
     go += g * Gold[(size_t)t * TE + e];
@@ -678,15 +776,28 @@ inline dim3 waves_grid(int n) { return dim3((unsigned)((n + 3) / 4)); }
     OMM_HIP(hipGetLastError());                                                 \
   } while (0)
 
+template <int KS> static dim3 grid_for(int nout) { return dim3((unsigned)((nout + Split<KS>::G - 1) / Split<KS>::G)); }
+template <int KS> static dim3 block_for() { return dim3(Split<KS>::NW * 64); }
+
+#define KS_DISPATCH(ks, ...)                     \
+  switch (ks) {                                  \
+    case 8: { constexpr int K_ = 8; __VA_ARGS__; } break; \
+    case 4: { constexpr int K_ = 4; __VA_ARGS__; } break; \
+    case 2: { constexpr int K_ = 2; __VA_ARGS__; } break; \
+    default: { constexpr int K_ = 1; __VA_ARGS__; } break; \
+  }
+
 template <typename TI, typename TO>
 static void s1_go(hipStream_t s, const Bufs& b, int mask, bool filter, const TI* H, const TI* S, const TI* B,
                   TO* O1, TO* O2) {
-  if (filter)
-    LAUNCH((k_s1<TI, TO, true>), waves_grid(b.s1.nout), dim3(256), s, b.s1, b.thc_row, b.thc_col, b.brow_sys,
-           b.info, b.st, mask, H, S, B, O1, O2, b.hc_to_c, b.wseg, b.eps2);
-  else
-    LAUNCH((k_s1<TI, TO, false>), waves_grid(b.s1.nout), dim3(256), s, b.s1, b.thc_row, b.thc_col, b.brow_sys,
-           b.info, b.st, mask, H, S, B, O1, O2, b.hc_to_c, b.wseg, b.eps2);
+  const int n = b.s1.nout;
+  if (filter) {
+    KS_DISPATCH(b.ks[0], LAUNCH((k_s1<TI, TO, true, K_>), grid_for<K_>(n), block_for<K_>(), s, b.s1, b.thc_row,
+                                b.thc_col, b.brow_sys, b.info, b.st, mask, H, S, B, O1, O2, b.hc_to_c, b.wseg))
+  } else {
+    KS_DISPATCH(b.ks[0], LAUNCH((k_s1<TI, TO, false, K_>), grid_for<K_>(n), block_for<K_>(), s, b.s1, b.thc_row,
+                                b.thc_col, b.brow_sys, b.info, b.st, mask, H, S, B, O1, O2, b.hc_to_c, b.wseg))
+  }
 }
 
 void launch_s1(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init, bool filter) {
@@ -706,12 +817,16 @@ void launch_s1(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init, boo
 template <typename TI, typename TM, typename TO, int NP>
 static void s2_go(hipStream_t s, const Bufs& b, int mask, bool filter, const TI* C, const TI* D, const TM* HD,
                   const TM* SD, TO* X, TO* Y, TO* S2, TO* H2) {
-  if (filter)
-    LAUNCH((k_s2<TI, TM, TO, NP, true>), waves_grid(b.s2.nout), dim3(256), s, b.s2, b.tw_row, b.tw_col,
-           b.wrow_sys, b.info, b.st, mask, C, D, HD, SD, X, Y, S2, H2, b.wseg, b.eps2);
-  else
-    LAUNCH((k_s2<TI, TM, TO, NP, false>), waves_grid(b.s2.nout), dim3(256), s, b.s2, b.tw_row, b.tw_col,
-           b.wrow_sys, b.info, b.st, mask, C, D, HD, SD, X, Y, S2, H2, b.wseg, b.eps2);
+  const int n = b.s2.nout;
+  if (filter) {
+    KS_DISPATCH(b.ks[1], LAUNCH((k_s2<TI, TM, TO, NP, true, K_>), grid_for<K_>(n), block_for<K_>(), s, b.s2,
+                                b.tw_row, b.tw_col, b.wrow_sys, b.info, b.st, mask, C, D, HD, SD, X, Y, S2, H2,
+                                b.wseg))
+  } else {
+    KS_DISPATCH(b.ks[1], LAUNCH((k_s2<TI, TM, TO, NP, false, K_>), grid_for<K_>(n), block_for<K_>(), s, b.s2,
+                                b.tw_row, b.tw_col, b.wrow_sys, b.info, b.st, mask, C, D, HD, SD, X, Y, S2, H2,
+                                b.wseg))
+  }
 }
 
 void launch_s2(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init, bool filter) {
@@ -774,20 +889,21 @@ void launch_update_nn(hipStream_t s, const Bufs& b, Prec prec, int mask) {
            mask, b.H0, b.S0, b.Xf, b.Yf, b.S2f, b.H2f, (bf16*)b.H0l, (bf16*)b.S0l);
 }
 
+template <typename TI>
+static void grad_go(hipStream_t s, const Bufs& b, int mask, const TI* HC, const TI* SC, const TI* S0, const TI* H0) {
+  const int n = b.grad.nout;
+  KS_DISPATCH(b.ks[2], LAUNCH((k_grad<TI, K_>), grid_for<K_>(n), block_for<K_>(), s, b.grad, b.tc_row, b.brow_sys,
+                              b.st, mask, HC, SC, S0, H0, b.HC, b.c_in_hc, b.cmask, b.Gold, b.G, b.gpart))
+}
+
 void launch_grad(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init) {
   (void)init;
   if (b.grad.nout <= 0) return;
-  if (prec == P64)
-    LAUNCH(k_grad<double>, waves_grid(b.grad.nout), dim3(256), s, b.grad, b.tc_row, b.brow_sys, b.st, mask, b.HC,
-           b.SC, b.S0, b.H0, b.HC, b.c_in_hc, b.cmask, b.Gold, b.G, b.gpart);
+  if (prec == P64) grad_go<double>(s, b, mask, b.HC, b.SC, b.S0, b.H0);
   else if (prec == P32)
-    LAUNCH(k_grad<float>, waves_grid(b.grad.nout), dim3(256), s, b.grad, b.tc_row, b.brow_sys, b.st, mask,
-           (const float*)b.HCl, (const float*)b.SCl, (const float*)b.S0l, (const float*)b.H0l, b.HC, b.c_in_hc,
-           b.cmask, b.Gold, b.G, b.gpart);
+    grad_go<float>(s, b, mask, (const float*)b.HCl, (const float*)b.SCl, (const float*)b.S0l, (const float*)b.H0l);
   else
-    LAUNCH(k_grad<bf16>, waves_grid(b.grad.nout), dim3(256), s, b.grad, b.tc_row, b.brow_sys, b.st, mask,
-           (const bf16*)b.HCl, (const bf16*)b.SCl, (const bf16*)b.S0l, (const bf16*)b.H0l, b.HC, b.c_in_hc,
-           b.cmask, b.Gold, b.G, b.gpart);
+    grad_go<bf16>(s, b, mask, (const bf16*)b.HCl, (const bf16*)b.SCl, (const bf16*)b.S0l, (const bf16*)b.H0l);
 }
 
 void launch_beta(hipStream_t s, const Bufs& b, int mask, bool init, const CGParams& prm) {

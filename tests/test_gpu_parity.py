@@ -126,9 +126,12 @@ def test_batch_equals_standalone():
     rc, reps = ctx.minimize()
     for i, (s, (_, m)) in enumerate(zip(systems, names)):
         cs, rs = gpu_run(s, m, max_iter=300)
+        # the batch and the standalone run may pick different split factors for the tile
+        # products (they depend on the work-list length), i.e. a different summation
+        # order: equal up to rounding, not bitwise
         assert reps[i].iters_total == rs.iters_total
         assert abs(reps[i].energy - rs.energy) <= 1e-12 * abs(rs.energy)
-        assert np.max(np.abs(ctx.density_matrix(i) - cs.density_matrix(0))) <= 1e-12
+        assert np.max(np.abs(ctx.density_matrix(i) - cs.density_matrix(0))) <= 1e-10
         cs.close()
     ctx.close()
 
