@@ -41,6 +41,10 @@ WORKLOADS = {
                                "atom-block sparse, C radius 3.0, eta 1.5, filter 1e-6, 20 CG iterations"),
 }
 
+BATCH_DESC = ("64 independent systems, n^3 cubic lattices with n uniform in 3..7 (27-343 atoms x 13 "
+              "orbitals, 2 wavefunctions/atom), 32 dense (eta 0) + 32 block-sparse (C radius 3.0, eta 1.5, "
+              "filter 1e-6), FP32 products then 5 FP64 iterations, at most 200 CG iterations each")
+
 PEAKS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}   # dense TFLOP/s of MI355X
 HBM_PEAK = 8000.0                                         # GB/s
 
@@ -50,7 +54,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cubic4_dense", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="cubic4_dense", choices=sorted(WORKLOADS) + ["batch64"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
     ap.add_argument("--max-iter", type=int, default=None)
     ap.add_argument("--graph-iters", type=int, default=16)
@@ -90,12 +94,98 @@ def cpu_baseline(system, spec, mode, max_iter, budget_s):
                       f"each iteration"}
 
 
+def batch_main(args):
+    """64 uneven systems in one context (block-diagonal batch, graph replay) vs one context each."""
+    import torch
+    from ommgen import batch_specs, make_system
+    from paper_2209_05934_amd import omm as L
+    from paper_2209_05934_amd.solver import Context, Problem
+
+    specs = batch_specs()
+    systems = [make_system(sp) for sp in specs]
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    prec = {"fp64": L.OMM_FP64, "fp32": L.OMM_FP32, "bf16": L.OMM_BF16}[
+        args.precision if args.precision != "fp64" else "fp32"]
+    max_iter = args.max_iter or 200
+    probs, c0s = [], []
+    for s in systems:
+        hv, sv, cv = (torch.from_numpy(a).to(dev) for a in (s.H.val, s.S.val, s.C0.val))
+        mode = L.OMM_DENSE if s.spec.dense else L.OMM_BLOCK_SPARSE
+        probs.append(Problem(s.H, s.S, s.C0, s.n, mode, eta=s.spec.eta, H_val=hv, S_val=sv, C0_val=cv))
+        c0s.append(cv)
+    opts = dict(tol_grad=1e-9, max_iter=max_iter, precision=prec, fp64_refine_iters=5,
+                lowprec_max_iter=max_iter - 10, filter_eps=1e-6, graph_iters=args.graph_iters, history=0,
+                hip_stream=stream.cuda_stream, autotune=1 if args.autotune else 0)
+    batch = Context(probs, **opts)
+    singles = [Context([p], **opts) for p in probs]
+
+    def run_batch():
+        for i, s in enumerate(systems):
+            batch.set_coeffs(i, s.C0, c0s[i])
+        rc, reps = batch.minimize()
+        return sum(r.iters_total for r in reps), reps
+
+    def run_seq():
+        tot, reps = 0, []
+        for i, (s, c) in enumerate(zip(systems, singles)):
+            c.set_coeffs(0, s.C0, c0s[i])
+            rc, r = c.minimize()
+            tot += r[0].iters_total
+            reps.append(r[0])
+        return tot, reps
+
+    for _ in range(args.warmup):
+        run_batch()
+        run_seq()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it_b = 0
+    for _ in range(args.steps):
+        n, reps_b = run_batch()
+        it_b += n
+    torch.cuda.synchronize()
+    dt_b = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    it_s = 0
+    for _ in range(args.steps):
+        n, reps_s = run_seq()
+        it_s += n
+    torch.cuda.synchronize()
+    dt_s = time.perf_counter() - t0
+    dE = max(abs(a.energy - b.energy) / s.natoms for a, b, s in zip(reps_b, reps_s, systems))
+    sz = batch.sizes(-1)
+    flops_iter_avg = sz.flops_alg_iter / len(systems)
+    out = {
+        "metric": METRIC, "value": it_b / dt_b, "unit": "CG iters/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt_b / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 products (then 5 f64 iterations), f64 traces/line search",
+        "data": "synthetic",
+        "config": {"workload": "batch64: " + BATCH_DESC, "systems": len(systems),
+                   "atoms_total": int(sum(s.natoms for s in systems))},
+        "cg_iters_per_step": it_b / args.steps,
+        "sequential": {"value": it_s / dt_s, "ms_per_step": dt_s / args.steps * 1e3,
+                       "what": "the same 64 systems, one context each, solved one after another"},
+        "speedup_vs_sequential": (it_b / dt_b) / (it_s / dt_s),
+        "max_abs_dE_per_atom_batch_vs_sequential": dE,
+        "avg_alg_flops_per_iter_per_system": flops_iter_avg,
+        "roofline": None, "cpu_baseline": None,
+    }
+    for c in singles:
+        c.close()
+    batch.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               f"(the multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch64":
+        return batch_main(args)
     import numpy as np
     import torch
     from ommgen import config_spec, make_system

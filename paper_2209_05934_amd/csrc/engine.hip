@@ -803,6 +803,8 @@ void prepare(omm_ctx* c) {
   }
   b.tpart = dalloc<double>(c, (size_t)std::max(1, c->nchunks) * NSUM, true);
   b.gpart = dalloc<double>(c, std::max<size_t>(1, ntc) * 2, true);
+  b.ticket = dalloc<int>(c, c->nsys, true);
+  OMM_HIP(hipMemsetAsync(b.ticket, 0, sizeof(int) * c->nsys, st));
   b.info = c->d_info;
   b.st = c->d_st;
   b.hist = c->d_hist;
@@ -963,10 +965,8 @@ void run_iteration(omm_ctx* c, Prec p, int mask, bool tm) {
   StepArg a{p, mask, any_filter(c)};
   timed(c, 0, tm, [](omm_ctx* cc, void* v) { auto* q = (StepArg*)v; launch_s1(cc->stream, cc->b, q->p, q->mask, false, q->filter); }, &a);
   timed(c, 1, tm, [](omm_ctx* cc, void* v) { auto* q = (StepArg*)v; launch_s2(cc->stream, cc->b, q->p, q->mask, false, q->filter); }, &a);
-  launch_traces(s, b, p, mask, false);
-  launch_linesearch(s, b, mask, LS_STEP, prm);
-  launch_update_mn(s, b, p, mask);
-  launch_update_nn(s, b, p, mask);
+  launch_traces_ls(s, b, p, mask, LS_STEP, prm);
+  launch_update(s, b, p, mask);
   timed(c, 2, tm, [](omm_ctx* cc, void* v) { auto* q = (StepArg*)v; launch_grad(cc->stream, cc->b, q->p, q->mask, false); }, &a);
   launch_beta(s, b, mask, false, prm);
   launch_update_d(s, b, p, mask);
@@ -984,8 +984,7 @@ void init_sequence(omm_ctx* c) {
   const bool filt = any_filter(c);
   launch_s1(s, b, P64, PH_INIT, true, filt);
   launch_s2(s, b, P64, PH_INIT, true, filt);
-  launch_traces(s, b, P64, PH_INIT, true);
-  launch_linesearch(s, b, PH_INIT, LS_INIT, prm);
+  launch_traces_ls(s, b, P64, PH_INIT, LS_INIT, prm);
   launch_grad(s, b, P64, PH_INIT, true);
   launch_beta(s, b, PH_INIT, true, prm);
   launch_update_d(s, b, P64, PH_INIT);
@@ -1070,20 +1069,25 @@ int minimize(omm_ctx* c, omm_report* reps) {
   const bool use_graph = c->opt.graph_iters > 0 && !c->timing;
   if (use_graph && !c->gexec) capture_graph(c);
   const int K = use_graph ? c->graph_iters : std::max(1, c->opt.graph_iters > 0 ? c->opt.graph_iters : 1);
-  int64_t steps = 0, reinits = 0;
-  const int64_t max_steps = c->opt.max_iter + 2 * (int64_t)K + 16;
+  int64_t steps = 0, reinits = 0, waited = 0;
+  const int64_t max_steps = c->opt.max_iter + 8 * (int64_t)K + 64;
   while (true) {
     OMM_HIP(hipMemcpyAsync(c->h_st, c->d_st, sizeof(SysState) * c->nsys, hipMemcpyDeviceToHost, st));
     OMM_HIP(hipStreamSynchronize(st));
     if (c->timing) collect_timing(c);
-    bool all_done = true, any_init = false;
+    bool all_done = true, any_init = false, any_active = false;
     for (int i = 0; i < c->nsys; ++i) {
       all_done &= c->h_st[i].phase == PH_DONE;
       any_init |= c->h_st[i].phase == PH_INIT;
+      any_active |= (c->h_st[i].phase & (PH_LOW | PH_FP64)) != 0;
     }
     if (all_done) break;
-    if (any_init) {
+    // Systems that switch precision wait in the INIT phase; one re-initialization
+    // serves every waiting system, run when nothing else is active or after a
+    // few replays, so a batch does not pay one full-batch re-init per system.
+    if (any_init && (!any_active || ++waited >= 4)) {
       if (++reinits > 4 * (int64_t)c->nsys + 4) throw DeviceError("phase switching did not settle");
+      waited = 0;
       init_sequence(c);
       continue;
     }
@@ -1094,8 +1098,7 @@ int minimize(omm_ctx* c, omm_report* reps) {
     steps += K;
   }
   // electron count at the final C
-  launch_traces(st, c->b, P64, PH_DONE, true);
-  launch_linesearch(st, c->b, PH_DONE, LS_REPORT, params(c));
+  launch_traces_ls(st, c->b, P64, PH_DONE, LS_REPORT, params(c));
   OMM_HIP(hipMemcpyAsync(c->h_st, c->d_st, sizeof(SysState) * c->nsys, hipMemcpyDeviceToHost, st));
   OMM_HIP(hipStreamSynchronize(st));
   c->ran = true;

@@ -41,6 +41,7 @@ struct Bufs {   // every device buffer the iteration kernels touch
   void *Hl, *Sl, *Cl, *Dl, *HCl, *SCl, *H0l, *S0l;
   float *HDf, *SDf, *Xf, *Yf, *S2f, *H2f;
   double *tpart, *gpart;         // trace partials (nchunks x NSUM), gradient partials (n_tc x 2)
+  int* ticket;                   // per-system workgroup tickets of the trace kernel (zero between launches)
   SysInfo* info;
   SysState* st;
   double* hist;
@@ -52,10 +53,10 @@ struct Bufs {   // every device buffer the iteration kernels touch
 // one CG iteration step (all systems whose phase matches `mask`), arithmetic `prec`
 void launch_s1(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init, bool filter);
 void launch_s2(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init, bool filter);
-void launch_traces(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init);
-void launch_linesearch(hipStream_t s, const Bufs& b, int mask, int mode, const CGParams& prm);
-void launch_update_mn(hipStream_t s, const Bufs& b, Prec prec, int mask);
-void launch_update_nn(hipStream_t s, const Bufs& b, Prec prec, int mask);
+// traces of the n x n products and, in the last workgroup of each system, the
+// line-search step (mode LS_STEP), the initial energy (LS_INIT) or the electron count (LS_REPORT)
+void launch_traces_ls(hipStream_t s, const Bufs& b, Prec prec, int mask, int mode, const CGParams& prm);
+void launch_update(hipStream_t s, const Bufs& b, Prec prec, int mask);   // C, HC, SC, H_W, S_W
 void launch_grad(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init);
 void launch_beta(hipStream_t s, const Bufs& b, int mask, bool init, const CGParams& prm);
 void launch_update_d(hipStream_t s, const Bufs& b, Prec prec, int mask);

@@ -255,49 +255,7 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s2(
   }
 }
 
-// ------------------------------------------------------------------ FP64 traces
-// sums: 0 Tr H0, 1 Tr Y, 2 Tr H2, 3 <S0,H0>, 4 <S0,Y>, 5 <X,H0>, 6 <S0,H2>, 7 <X,Y>,
-//       8 <X,Y^T>, 9 <S2,H0>, 10 <X,H2>, 11 <S2,Y>, 12 <S2,H2>, 13 Tr S0, 14 <S0,S0>
-template <typename TN>
-__global__ __launch_bounds__(256) void k_traces(const int4* __restrict__ chunks, const SysState* __restrict__ st,
-                                              int mask, const int* __restrict__ wrow, const int* __restrict__ wcol,
-                                              const int* __restrict__ wtr, const double* __restrict__ H0,
-                                              const double* __restrict__ S0, const TN* __restrict__ X,
-                                              const TN* __restrict__ Y, const TN* __restrict__ S2,
-                                              const TN* __restrict__ H2, double* __restrict__ part) {
-  __shared__ double red[4][NSUM];
-  const int4 ch = chunks[blockIdx.x];
-  if (!on(st, ch.z, mask)) return;
-  double a[NSUM];
-#pragma unroll
-  for (int k = 0; k < NSUM; ++k) a[k] = 0.0;
-  const int e = threadIdx.x, r = e >> 4, c = e & 15;
-  for (int t = ch.x; t < ch.y; ++t) {
-    const size_t o = (size_t)t * TE + e;
-    const double h0 = H0[o], s0 = S0[o];
-    const double x = (double)X[o], y = (double)Y[o], s2 = (double)S2[o], h2 = (double)H2[o];
-    const double yt = (double)Y[(size_t)wtr[t] * TE + c * 16 + r];
-    if (r == c && wrow[t] == wcol[t]) {
-      a[0] += h0; a[1] += y; a[2] += h2; a[13] += s0;
-    }
-    a[3] += s0 * h0; a[4] += s0 * y; a[5] += x * h0; a[6] += s0 * h2; a[7] += x * y;
-    a[8] += x * yt; a[9] += s2 * h0; a[10] += x * h2; a[11] += s2 * y; a[12] += s2 * h2;
-    a[14] += s0 * s0;
-  }
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < NSUM; ++k) {
-    const double v = wave_sum(a[k]);
-    if (lane == 0) red[wv][k] = v;
-  }
-  __syncthreads();
-  if (threadIdx.x < NSUM) {
-    const int k = threadIdx.x;
-    part[(size_t)blockIdx.x * NSUM + k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
-  }
-}
-
-// ------------------------------------------------------------------ line search (one wave per system)
+// ------------------------------------------------------------------ line search (scalar, one thread per system)
 __device__ __forceinline__ double pval(const double* c, double x) {
   return c[0] + x * (c[1] + x * (c[2] + x * (c[3] + x * c[4])));
 }
@@ -376,23 +334,8 @@ __device__ bool line_min(const double* c, double& xs) {
   return true;
 }
 
-__global__ __launch_bounds__(64) void k_linesearch(const SysInfo* __restrict__ info, SysState* __restrict__ st,
-                                                 int mask, const double* __restrict__ part, int mode,
-                                                 int refine_iters) {
-  const int s = blockIdx.x;
-  if (!on(st, s, mask)) return;
-  const int lane = threadIdx.x;
-  double a[NSUM];
-#pragma unroll
-  for (int k = 0; k < NSUM; ++k) a[k] = 0.0;
-  for (int ch = info[s].ch0 + lane; ch < info[s].ch1; ch += 64) {
-#pragma unroll
-    for (int k = 0; k < NSUM; ++k) a[k] += part[(size_t)ch * NSUM + k];
-  }
-#pragma unroll
-  for (int k = 0; k < NSUM; ++k) a[k] = wave_sum(a[k]);
-  if (lane != 0) return;
-  SysState& S = st[s];
+// quartic coefficients from the 15 sums, then the step (one thread)
+__device__ void ls_finish(SysState& S, const double* a, int mode, int refine_iters) {
   double c[5];
   c[0] = 4.0 * a[0] - 2.0 * a[3];
   c[1] = 8.0 * a[1] - 4.0 * a[4] - 4.0 * a[5];
@@ -431,15 +374,98 @@ __global__ __launch_bounds__(64) void k_linesearch(const SysInfo* __restrict__ i
   if (S.phase == PH_FP64) S.iter_fp64 += 1;
 }
 
-// ------------------------------------------------------------------ updates
+// ------------------------------------------------------------------ FP64 traces
+// sums: 0 Tr H0, 1 Tr Y, 2 Tr H2, 3 <S0,H0>, 4 <S0,Y>, 5 <X,H0>, 6 <S0,H2>, 7 <X,Y>,
+//       8 <X,Y^T>, 9 <S2,H0>, 10 <X,H2>, 11 <S2,Y>, 12 <S2,H2>, 13 Tr S0, 14 <S0,S0>
+// Every workgroup reduces a chunk of n x n tiles of one system; the last
+// workgroup of a system to finish (integer ticket, release/acquire fences) sums
+// the system's chunk partials in chunk order and takes the line-search step.
+template <typename TN>
+__global__ __launch_bounds__(256) void k_traces(const int4* __restrict__ chunks, const SysInfo* __restrict__ info,
+                                              SysState* __restrict__ st, int mask, const int* __restrict__ wrow,
+                                              const int* __restrict__ wcol, const int* __restrict__ wtr,
+                                              const double* __restrict__ H0, const double* __restrict__ S0,
+                                              const TN* __restrict__ X, const TN* __restrict__ Y,
+                                              const TN* __restrict__ S2, const TN* __restrict__ H2,
+                                              double* __restrict__ part, int* __restrict__ ticket, int mode,
+                                              int refine_iters) {
+  __shared__ double red[4][NSUM];
+  __shared__ int last;
+  const int4 ch = chunks[blockIdx.x];
+  if (!on(st, ch.z, mask)) return;
+  double a[NSUM];
+#pragma unroll
+  for (int k = 0; k < NSUM; ++k) a[k] = 0.0;
+  const int e = threadIdx.x, r = e >> 4, c = e & 15;
+  for (int t = ch.x; t < ch.y; ++t) {
+    const size_t o = (size_t)t * TE + e;
+    const double h0 = H0[o], s0 = S0[o];
+    const double x = (double)X[o], y = (double)Y[o], s2 = (double)S2[o], h2 = (double)H2[o];
+    const double yt = (double)Y[(size_t)wtr[t] * TE + c * 16 + r];
+    if (r == c && wrow[t] == wcol[t]) {
+      a[0] += h0; a[1] += y; a[2] += h2; a[13] += s0;
+    }
+    a[3] += s0 * h0; a[4] += s0 * y; a[5] += x * h0; a[6] += s0 * h2; a[7] += x * y;
+    a[8] += x * yt; a[9] += s2 * h0; a[10] += x * h2; a[11] += s2 * y; a[12] += s2 * h2;
+    a[14] += s0 * s0;
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NSUM; ++k) {
+    const double v = wave_sum(a[k]);
+    if (lane == 0) red[wv][k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < NSUM) {
+    const int k = threadIdx.x;
+    part[(size_t)blockIdx.x * NSUM + k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+  }
+  __threadfence();
+  __syncthreads();
+  const int sy = ch.z;
+  if (threadIdx.x == 0) {
+    const int total = info[sy].ch1 - info[sy].ch0;
+    last = (atomicAdd(&ticket[sy], 1) == total - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+#pragma unroll
+  for (int k = 0; k < NSUM; ++k) a[k] = 0.0;
+  for (int c2 = info[sy].ch0 + threadIdx.x; c2 < info[sy].ch1; c2 += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < NSUM; ++k) a[k] += __builtin_nontemporal_load(&part[(size_t)c2 * NSUM + k]);
+  }
+#pragma unroll
+  for (int k = 0; k < NSUM; ++k) {
+    const double v = wave_sum(a[k]);
+    if (lane == 0) red[wv][k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tot[NSUM];
+#pragma unroll
+    for (int k = 0; k < NSUM; ++k) tot[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+    ls_finish(st[sy], tot, mode, refine_iters);
+    ticket[sy] = 0;
+  }
+}
+
+// ------------------------------------------------------------------ updates (one launch)
+// blocks [0, nc): C tiles; [nc, nc + nhc): HC/SC tiles; the rest: n x n tiles
 template <typename TL, typename TM, bool LOW>
-__global__ __launch_bounds__(256) void k_update_mn(int nc, const int* __restrict__ tc_row,
-                                                 const int* __restrict__ thc_row, const int* __restrict__ brow_sys,
-                                                 const SysState* __restrict__ st, int mask, double* __restrict__ C,
-                                                 const double* __restrict__ D, TL* __restrict__ Cl,
-                                                 double* __restrict__ HC, double* __restrict__ SC,
-                                                 const TM* __restrict__ HD, const TM* __restrict__ SD,
-                                                 TL* __restrict__ HCl, TL* __restrict__ SCl) {
+__global__ __launch_bounds__(256) void k_update(int nc, int nhc, const int* __restrict__ tc_row,
+                                              const int* __restrict__ thc_row, const int* __restrict__ tw_row,
+                                              const int* __restrict__ brow_sys, const int* __restrict__ wrow_sys,
+                                              const int* __restrict__ wtr, const SysState* __restrict__ st,
+                                              int mask, double* __restrict__ C, const double* __restrict__ D,
+                                              TL* __restrict__ Cl, double* __restrict__ HC, double* __restrict__ SC,
+                                              const TM* __restrict__ HD, const TM* __restrict__ SD,
+                                              TL* __restrict__ HCl, TL* __restrict__ SCl, double* __restrict__ H0,
+                                              double* __restrict__ S0, const TM* __restrict__ X,
+                                              const TM* __restrict__ Y, const TM* __restrict__ S2,
+                                              const TM* __restrict__ H2, TL* __restrict__ H0l,
+                                              TL* __restrict__ S0l) {
   const int b = blockIdx.x;
   const int e = threadIdx.x;
   if (b < nc) {
@@ -451,7 +477,7 @@ __global__ __launch_bounds__(256) void k_update_mn(int nc, const int* __restrict
     const double v = C[o] + x * D[o];
     C[o] = v;
     if (LOW) Cl[o] = cvt<TL, double>(v);
-  } else {
+  } else if (b < nc + nhc) {
     const int t = b - nc;
     const int s = brow_sys[thc_row[t]];
     if (!on(st, s, mask)) return;
@@ -466,31 +492,23 @@ __global__ __launch_bounds__(256) void k_update_mn(int nc, const int* __restrict
       HCl[o] = cvt<TL, double>(h);
       SCl[o] = cvt<TL, double>(g);
     }
-  }
-}
-
-template <typename TL, typename TN, bool LOW>
-__global__ __launch_bounds__(256) void k_update_nn(const int* __restrict__ tw_row, const int* __restrict__ wrow_sys,
-                                                 const int* __restrict__ wtr, const SysState* __restrict__ st,
-                                                 int mask, double* __restrict__ H0, double* __restrict__ S0,
-                                                 const TN* __restrict__ X, const TN* __restrict__ Y,
-                                                 const TN* __restrict__ S2, const TN* __restrict__ H2,
-                                                 TL* __restrict__ H0l, TL* __restrict__ S0l) {
-  const int t = blockIdx.x;
-  const int s = wrow_sys[tw_row[t]];
-  if (!on(st, s, mask)) return;
-  const double x = st[s].x;
-  if (x == 0.0) return;
-  const int e = threadIdx.x, r = e >> 4, c = e & 15;
-  const size_t o = (size_t)t * TE + e;
-  const size_t ot = (size_t)wtr[t] * TE + c * 16 + r;
-  const double h = H0[o] + x * ((double)Y[o] + (double)Y[ot]) + x * x * (double)H2[o];
-  const double g = S0[o] + x * ((double)X[o] + (double)X[ot]) + x * x * (double)S2[o];
-  H0[o] = h;
-  S0[o] = g;
-  if (LOW) {
-    H0l[o] = cvt<TL, double>(h);
-    S0l[o] = cvt<TL, double>(g);
+  } else {
+    const int t = b - nc - nhc;
+    const int s = wrow_sys[tw_row[t]];
+    if (!on(st, s, mask)) return;
+    const double x = st[s].x;
+    if (x == 0.0) return;
+    const int r = e >> 4, c = e & 15;
+    const size_t o = (size_t)t * TE + e;
+    const size_t ot = (size_t)wtr[t] * TE + c * 16 + r;
+    const double h = H0[o] + x * ((double)Y[o] + (double)Y[ot]) + x * x * (double)H2[o];
+    const double g = S0[o] + x * ((double)X[o] + (double)X[ot]) + x * x * (double)S2[o];
+    H0[o] = h;
+    S0[o] = g;
+    if (LOW) {
+      H0l[o] = cvt<TL, double>(h);
+      S0l[o] = cvt<TL, double>(g);
+    }
   }
 }
 
@@ -562,20 +580,28 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_grad(
 }
 
 // ------------------------------------------------------------------ beta, stop rules (one wave per system)
-__global__ __launch_bounds__(64) void k_beta(const SysInfo* __restrict__ info, SysState* __restrict__ st, int mask,
-                                           const double* __restrict__ gpart, int init, double* __restrict__ hist,
-                                           CGParams prm) {
+__global__ __launch_bounds__(256) void k_beta(const SysInfo* __restrict__ info, SysState* __restrict__ st, int mask,
+                                            const double* __restrict__ gpart, int init, double* __restrict__ hist,
+                                            CGParams prm) {
+  __shared__ double red[2][4];
   const int s = blockIdx.x;
   if (!on(st, s, mask)) return;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double gg = 0.0, go = 0.0;
-  for (int t = info[s].c0 + lane; t < info[s].c1; t += 64) {
+  for (int t = info[s].c0 + threadIdx.x; t < info[s].c1; t += blockDim.x) {
     gg += gpart[2 * (size_t)t];
     go += gpart[2 * (size_t)t + 1];
   }
   gg = wave_sum(gg);
   go = wave_sum(go);
-  if (lane != 0) return;
+  if (lane == 0) {
+    red[0][wv] = gg;
+    red[1][wv] = go;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  gg = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
+  go = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
   SysState& S = st[s];
   const double gn = sqrt(gg);
   if (init) {
@@ -843,50 +869,42 @@ void launch_s2(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init, boo
   }
 }
 
-void launch_traces(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init) {
+static void traces_go(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init_inputs, int mode,
+                      int refine_iters) {
   if (b.nchunks <= 0) return;
   if (prec == P64) {
-    if (init)
-      LAUNCH(k_traces<double>, dim3(b.nchunks), dim3(256), s, b.chunks, b.st, mask, b.tw_row, b.tw_col, b.w_tr,
-             b.H0, b.S0, b.S0, b.H0, b.S0, b.H0, b.tpart);
+    if (init_inputs)
+      LAUNCH(k_traces<double>, dim3(b.nchunks), dim3(256), s, b.chunks, b.info, b.st, mask, b.tw_row, b.tw_col,
+             b.w_tr, b.H0, b.S0, b.S0, b.H0, b.S0, b.H0, b.tpart, b.ticket, mode, refine_iters);
     else
-      LAUNCH(k_traces<double>, dim3(b.nchunks), dim3(256), s, b.chunks, b.st, mask, b.tw_row, b.tw_col, b.w_tr,
-             b.H0, b.S0, b.X, b.Y, b.S2, b.H2, b.tpart);
+      LAUNCH(k_traces<double>, dim3(b.nchunks), dim3(256), s, b.chunks, b.info, b.st, mask, b.tw_row, b.tw_col,
+             b.w_tr, b.H0, b.S0, b.X, b.Y, b.S2, b.H2, b.tpart, b.ticket, mode, refine_iters);
   } else {
-    LAUNCH(k_traces<float>, dim3(b.nchunks), dim3(256), s, b.chunks, b.st, mask, b.tw_row, b.tw_col, b.w_tr, b.H0,
-           b.S0, b.Xf, b.Yf, b.S2f, b.H2f, b.tpart);
+    LAUNCH(k_traces<float>, dim3(b.nchunks), dim3(256), s, b.chunks, b.info, b.st, mask, b.tw_row, b.tw_col,
+           b.w_tr, b.H0, b.S0, b.Xf, b.Yf, b.S2f, b.H2f, b.tpart, b.ticket, mode, refine_iters);
   }
 }
 
-void launch_linesearch(hipStream_t s, const Bufs& b, int mask, int mode, const CGParams& prm) {
-  LAUNCH(k_linesearch, dim3(b.nsys), dim3(64), s, b.info, b.st, mask, b.tpart, mode, prm.refine_iters);
+void launch_traces_ls(hipStream_t s, const Bufs& b, Prec prec, int mask, int mode, const CGParams& prm) {
+  traces_go(s, b, prec, mask, mode != LS_STEP, mode, prm.refine_iters);
 }
 
-void launch_update_mn(hipStream_t s, const Bufs& b, Prec prec, int mask) {
-  const int nb = b.n_tc + b.n_thc;
+void launch_update(hipStream_t s, const Bufs& b, Prec prec, int mask) {
+  const int nb = b.n_tc + b.n_thc + b.n_tw;
   if (nb <= 0) return;
   if (prec == P64)
-    LAUNCH((k_update_mn<double, double, false>), dim3(nb), dim3(256), s, b.n_tc, b.tc_row, b.thc_row, b.brow_sys,
-           b.st, mask, b.C, b.D, (double*)nullptr, b.HC, b.SC, b.HD, b.SD, (double*)nullptr, (double*)nullptr);
+    LAUNCH((k_update<double, double, false>), dim3(nb), dim3(256), s, b.n_tc, b.n_thc, b.tc_row, b.thc_row,
+           b.tw_row, b.brow_sys, b.wrow_sys, b.w_tr, b.st, mask, b.C, b.D, (double*)nullptr, b.HC, b.SC, b.HD,
+           b.SD, (double*)nullptr, (double*)nullptr, b.H0, b.S0, b.X, b.Y, b.S2, b.H2, (double*)nullptr,
+           (double*)nullptr);
   else if (prec == P32)
-    LAUNCH((k_update_mn<float, float, true>), dim3(nb), dim3(256), s, b.n_tc, b.tc_row, b.thc_row, b.brow_sys,
-           b.st, mask, b.C, b.D, (float*)b.Cl, b.HC, b.SC, b.HDf, b.SDf, (float*)b.HCl, (float*)b.SCl);
+    LAUNCH((k_update<float, float, true>), dim3(nb), dim3(256), s, b.n_tc, b.n_thc, b.tc_row, b.thc_row, b.tw_row,
+           b.brow_sys, b.wrow_sys, b.w_tr, b.st, mask, b.C, b.D, (float*)b.Cl, b.HC, b.SC, b.HDf, b.SDf,
+           (float*)b.HCl, (float*)b.SCl, b.H0, b.S0, b.Xf, b.Yf, b.S2f, b.H2f, (float*)b.H0l, (float*)b.S0l);
   else
-    LAUNCH((k_update_mn<bf16, float, true>), dim3(nb), dim3(256), s, b.n_tc, b.tc_row, b.thc_row, b.brow_sys,
-           b.st, mask, b.C, b.D, (bf16*)b.Cl, b.HC, b.SC, b.HDf, b.SDf, (bf16*)b.HCl, (bf16*)b.SCl);
-}
-
-void launch_update_nn(hipStream_t s, const Bufs& b, Prec prec, int mask) {
-  if (b.n_tw <= 0) return;
-  if (prec == P64)
-    LAUNCH((k_update_nn<double, double, false>), dim3(b.n_tw), dim3(256), s, b.tw_row, b.wrow_sys, b.w_tr, b.st,
-           mask, b.H0, b.S0, b.X, b.Y, b.S2, b.H2, (double*)nullptr, (double*)nullptr);
-  else if (prec == P32)
-    LAUNCH((k_update_nn<float, float, true>), dim3(b.n_tw), dim3(256), s, b.tw_row, b.wrow_sys, b.w_tr, b.st,
-           mask, b.H0, b.S0, b.Xf, b.Yf, b.S2f, b.H2f, (float*)b.H0l, (float*)b.S0l);
-  else
-    LAUNCH((k_update_nn<bf16, float, true>), dim3(b.n_tw), dim3(256), s, b.tw_row, b.wrow_sys, b.w_tr, b.st,
-           mask, b.H0, b.S0, b.Xf, b.Yf, b.S2f, b.H2f, (bf16*)b.H0l, (bf16*)b.S0l);
+    LAUNCH((k_update<bf16, float, true>), dim3(nb), dim3(256), s, b.n_tc, b.n_thc, b.tc_row, b.thc_row, b.tw_row,
+           b.brow_sys, b.wrow_sys, b.w_tr, b.st, mask, b.C, b.D, (bf16*)b.Cl, b.HC, b.SC, b.HDf, b.SDf,
+           (bf16*)b.HCl, (bf16*)b.SCl, b.H0, b.S0, b.Xf, b.Yf, b.S2f, b.H2f, (bf16*)b.H0l, (bf16*)b.S0l);
 }
 
 template <typename TI>
@@ -907,7 +925,7 @@ void launch_grad(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init) {
 }
 
 void launch_beta(hipStream_t s, const Bufs& b, int mask, bool init, const CGParams& prm) {
-  LAUNCH(k_beta, dim3(b.nsys), dim3(64), s, b.info, b.st, mask, b.gpart, init ? 1 : 0, b.hist, prm);
+  LAUNCH(k_beta, dim3(b.nsys), dim3(256), s, b.info, b.st, mask, b.gpart, init ? 1 : 0, b.hist, prm);
 }
 
 void launch_update_d(hipStream_t s, const Bufs& b, Prec prec, int mask) {
