@@ -46,6 +46,23 @@ BATCH_DESC = ("64 independent systems, n^3 cubic lattices with n uniform in 3..7
               "filter 1e-6), FP32 products then 5 FP64 iterations, at most 200 CG iterations each")
 
 PEAKS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}   # dense TFLOP/s of MI355X
+
+# HBM bytes per launch of a product step from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
+# (calibrated against a plain copy; profiles/traffic_*.md), keyed by workload,
+# precision, step, group width and split, and valid only for the kernel sources
+# they were taken with (sha256 prefix of numeric.hip + tile_ops.hpp)
+MEASURED_TRAFFIC = {
+    ("cubic4_dense", "fp64", 0, 1, 8): (20.714e6, "9f77ea518ff88d7f"),
+}
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("numeric.hip", "tile_ops.hpp"):
+        with open(os.path.join(ROOT, "paper_2209_05934_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 HBM_PEAK = 8000.0                                         # GB/s
 
 
@@ -61,7 +78,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-kernel-timing", action="store_true")
-    ap.add_argument("--autotune", action="store_true", help="time the split factors of the tile products")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run 5 device-to-device copies of BYTES (HBM counter calibration)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the heuristic work split of the tile products instead of timing the variants")
     return ap.parse_args()
 
 
@@ -116,7 +136,7 @@ def batch_main(args):
         c0s.append(cv)
     opts = dict(tol_grad=1e-9, max_iter=max_iter, precision=prec, fp64_refine_iters=5,
                 lowprec_max_iter=max_iter - 10, filter_eps=1e-6, graph_iters=args.graph_iters, history=0,
-                hip_stream=stream.cuda_stream, autotune=1 if args.autotune else 0)
+                hip_stream=stream.cuda_stream, autotune=0 if args.no_autotune else 1)
     batch = Context(probs, **opts)
     singles = [Context([p], **opts) for p in probs]
 
@@ -184,6 +204,16 @@ def main():
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               f"(the multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe:
+        import torch
+        n = args.copy_probe // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n * 8, "copies": 5}), flush=True)
+        return
     if args.workload == "batch64":
         return batch_main(args)
     import numpy as np
@@ -208,7 +238,7 @@ def main():
     prob = Problem(system.H, system.S, system.C0, system.n, mode, H_val=Hv, S_val=Sv, C0_val=C0v)
     ctx = Context([prob], eta=spec.eta, tol_grad=1e-9, max_iter=max_iter, precision=prec,
                   filter_eps=spec.filter_eps, graph_iters=args.graph_iters, history=0,
-                  hip_stream=stream.cuda_stream, autotune=1 if args.autotune else 0)
+                  hip_stream=stream.cuda_stream, autotune=0 if args.no_autotune else 1)
     from paper_2209_05934_amd import omm as LL
 
     def step():
@@ -253,7 +283,11 @@ def main():
             peak = PEAKS[args.precision]
             roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                     "frac": achieved / peak, "traffic": None}
-        roof.update({"kernel": names[k], "avg_launch_us": avg_s * 1e6, "launches": int(n[k]),
+        tk = (args.workload, args.precision, k, int(sz.tile_group[k]), int(sz.tile_split[k]))
+        if tk in MEASURED_TRAFFIC and MEASURED_TRAFFIC[tk][1] == kernel_source_hash():
+            roof["traffic"] = MEASURED_TRAFFIC[tk][0]
+        roof.update({"kernel": names[k], "tile_group": int(sz.tile_group[k]), "tile_split": int(sz.tile_split[k]),
+                     "avg_launch_us": avg_s * 1e6, "launches": int(n[k]),
                      "alg_flops_per_launch": sz.flops_alg_step[k],
                      "exec_flops_per_launch": sz.flops_exec_step[k],
                      "alg_bytes_per_launch": sz.bytes_alg_step[k],

@@ -143,6 +143,10 @@ typedef struct {
   double flops_alg_step[3];
   double flops_exec_step[3];
   double bytes_alg_step[3];
+  /* launch shape in use per product step: output tiles per wave (group width)
+   * and waves splitting one group's work list (chosen by heuristic or autotuner) */
+  int32_t tile_group[3];
+  int32_t tile_split[3];
 } omm_sizes;
 
 typedef struct omm_ctx omm_ctx;

@@ -85,6 +85,17 @@ struct Plan {
   PlanView view() const { return PlanView{nout, pp, pairs}; }
 };
 
+struct GPlan {   // grouped work list of one product step
+  int NT = 1;
+  int ngroups = 0;
+  int64_t nent = 0, npairs = 0;
+  int *gbase = nullptr, *go0 = nullptr, *gn = nullptr, *ent = nullptr;
+  int64_t* gp = nullptr;
+  std::vector<int> hgbase;          // first group of each output row (nrows + 1)
+  std::vector<int64_t> hpairs;      // prefix of tile pairs over groups (ngroups + 1)
+  GroupView view() const { return GroupView{ngroups, NT, go0, gn, gp, ent}; }
+};
+
 }  // namespace
 
 struct omm_ctx {
@@ -96,7 +107,9 @@ struct omm_ctx {
   std::vector<SysHost> sys;
   int NB = 0, NW = 0;
   Pat TH, TC, TCt, THC, TW, TCM;
-  Plan Ps1, Ps2, Pgrad, Pcm, Prho;
+  Plan Pcm, Prho;
+  GPlan G[3][2];      // product steps (direction, n x n, gradient) x (NT = 1, NT = step width)
+  int sel[3] = {0, 0, 0};
   int *brow_sys = nullptr, *wrow_sys = nullptr, *c_in_hc = nullptr, *hc_to_c = nullptr, *w_tr = nullptr;
   uint32_t* cmask = nullptr;
   uint8_t* wseg = nullptr;
@@ -249,7 +262,8 @@ void set_err(omm_ctx* c, const std::string& m) {
   else g_last_init_error = m;
 }
 
-int pick_ks(int64_t nout, int64_t npairs);
+int pick_ks(int64_t nout, int64_t npairs, int kmax);
+void pick_plans(omm_ctx* c);
 
 // ----------------------------------------------------------------- pattern helpers
 void upload_pat(omm_ctx* c, Pat& P, int nrows, const std::vector<std::vector<int>>& rows, bool prep) {
@@ -299,6 +313,38 @@ void make_plan(omm_ctx* c, Plan& P, const Pat& O, const PatView& A, const PatVie
   P.npairs = P.hpp[O.nnz];
   P.pairs = dalloc<int2>(c, P.npairs, true);
   pair_fill(s, O.nrows, 0, A, B, Ov, win, P.pp, P.pairs);
+}
+
+void make_gplan(omm_ctx* c, GPlan& G, const Pat& O, const PatView& A, const PatView& B, int NT) {
+  hipStream_t s = c->stream;
+  G.NT = NT;
+  const int nrows = O.nrows;
+  int* ng = dalloc<int>(c, nrows + 1, true);
+  OMM_HIP(hipMemsetAsync(ng, 0, (nrows + 1) * sizeof(int), s));
+  group_counts(s, nrows, O.rp, NT, ng);
+  G.gbase = dalloc<int>(c, nrows + 1, true);
+  excl_scan(s, ng, G.gbase, nrows + 1);
+  G.hgbase = ddownload(c, G.gbase, nrows + 1);
+  G.ngroups = G.hgbase[nrows];
+  int64_t* gcnt = dalloc<int64_t>(c, G.ngroups + 1, true);
+  int64_t* gpres = dalloc<int64_t>(c, G.ngroups + 1, true);
+  OMM_HIP(hipMemsetAsync(gcnt, 0, (G.ngroups + 1) * sizeof(int64_t), s));
+  OMM_HIP(hipMemsetAsync(gpres, 0, (G.ngroups + 1) * sizeof(int64_t), s));
+  G.go0 = dalloc<int>(c, G.ngroups, true);
+  G.gn = dalloc<int>(c, G.ngroups, true);
+  PatView Ov = O.view();
+  Ov.ti = nullptr;
+  group_lists(s, nrows, A, B, Ov, NT, G.gbase, gcnt, gpres, nullptr, nullptr, G.go0, G.gn);
+  G.gp = dalloc<int64_t>(c, G.ngroups + 1, true);
+  excl_scan64(s, gcnt, G.gp, G.ngroups + 1);
+  std::vector<int64_t> last = ddownload(c, G.gp + G.ngroups, 1);
+  G.nent = last[0];
+  G.ent = dalloc<int>(c, (size_t)std::max<int64_t>(1, G.nent) * (1 + NT), true);
+  group_lists(s, nrows, A, B, Ov, NT, G.gbase, gcnt, gpres, G.gp, G.ent, G.go0, G.gn);
+  std::vector<int64_t> pres = ddownload(c, gpres, G.ngroups);
+  G.hpairs.assign(G.ngroups + 1, 0);
+  for (int g = 0; g < G.ngroups; ++g) G.hpairs[g + 1] = G.hpairs[g] + pres[g];
+  G.npairs = G.hpairs[G.ngroups];
 }
 
 // ----------------------------------------------------------------- work counts (host)
@@ -692,9 +738,16 @@ void prepare(omm_ctx* c) {
   }
   sym_product(c, c->TCM, c->NB, c->TC, c->TW, c->win_bw);
   // work lists
-  make_plan(c, c->Ps1, c->THC, c->TH.view(), c->TC.view(), c->win_bw);
-  make_plan(c, c->Ps2, c->TW, c->TCt.view(), c->THC.view(), c->win_ww);
-  make_plan(c, c->Pgrad, c->TC, c->THC.view(), c->TW.view(), c->win_bw);
+  {
+    const int widths[3] = {NT_S1, NT_S2, NT_GRAD};
+    const Pat* outs[3] = {&c->THC, &c->TW, &c->TC};
+    const PatView As[3] = {c->TH.view(), c->TCt.view(), c->THC.view()};
+    const PatView Bs[3] = {c->TC.view(), c->THC.view(), c->TW.view()};
+    for (int k = 0; k < 3; ++k) {
+      make_gplan(c, c->G[k][0], *outs[k], As[k], Bs[k], 1);
+      make_gplan(c, c->G[k][1], *outs[k], As[k], Bs[k], widths[k]);
+    }
+  }
   make_plan(c, c->Pcm, c->TCM, c->TC.view(), c->TW.view(), c->win_bw);
   make_plan(c, c->Prho, c->TH, c->TCM.view(), c->TCt.view(), c->win_bb);
   // lookups
@@ -716,7 +769,6 @@ void prepare(omm_ctx* c) {
       if (v < 0) throw ArgError("internal: n x n pattern not symmetric (H not symmetric in pattern?)");
   }
   // per-system ranges, chunks, info
-  const int CH = 8;
   std::vector<int4> chunks;
   c->h_info.assign(c->nsys, SysInfo{});
   for (int i = 0; i < c->nsys; ++i) {
@@ -729,6 +781,10 @@ void prepare(omm_ctx* c) {
     f.hc0 = c->THC.hrp[f.rb0]; f.hc1 = c->THC.hrp[f.rb1];
     f.w0 = c->TW.hrp[f.wb0]; f.w1 = c->TW.hrp[f.wb1];
     f.ch0 = (int)chunks.size();
+    // tiles per trace chunk: at least 8 (every workgroup issues one device-scope
+    // fence), up to 32 so that the last workgroup's final reduction stays short
+    const int ntw = f.w1 - f.w0;
+    const int CH = std::max(8, std::min(32, ntw / 1024));
     for (int t = f.w0; t < f.w1; t += CH) chunks.push_back(make_int4(t, std::min(t + CH, f.w1), i, 0));
     f.ch1 = (int)chunks.size();
     f.mode = s.mode;
@@ -742,9 +798,13 @@ void prepare(omm_ctx* c) {
     s.tiles_c = f.c1 - f.c0;
     s.tiles_hc = f.hc1 - f.hc0;
     s.tiles_w = f.w1 - f.w0;
-    s.pairs[0] = c->Ps1.hpp[f.hc1] - c->Ps1.hpp[f.hc0];
-    s.pairs[1] = c->Ps2.hpp[f.w1] - c->Ps2.hpp[f.w0];
-    s.pairs[2] = c->Pgrad.hpp[f.c1] - c->Pgrad.hpp[f.c0];
+    {
+      const int r0[3] = {f.rb0, f.wb0, f.rb0}, r1[3] = {f.rb1, f.wb1, f.rb1};
+      for (int k = 0; k < 3; ++k) {
+        const GPlan& G = c->G[k][0];
+        s.pairs[k] = G.hpairs[G.hgbase[r1[k]]] - G.hpairs[G.hgbase[r0[k]]];
+      }
+    }
     const double tf = 2.0 * 16 * 16 * 16;
     s.flops_exec[0] = (f.ident_s ? 1.0 : 2.0) * tf * s.pairs[0];
     s.flops_exec[1] = 4.0 * tf * s.pairs[1];
@@ -769,7 +829,7 @@ void prepare(omm_ctx* c) {
   b.c_in_hc = c->c_in_hc; b.hc_to_c = c->hc_to_c; b.w_tr = c->w_tr;
   b.cmask = c->cmask; b.wseg = c->wseg; b.chunks = c->chunks; b.nchunks = c->nchunks;
   b.n_th = (int)c->TH.nnz; b.n_tc = (int)ntc; b.n_thc = (int)nhc; b.n_tw = (int)ntw;
-  b.s1 = c->Ps1.view(); b.s2 = c->Ps2.view(); b.grad = c->Pgrad.view();
+  pick_plans(c);
   b.H = c->H; b.S = c->S;
   b.C = dalloc<double>(c, ntc * TE, true);
   b.D = dalloc<double>(c, ntc * TE, true);
@@ -810,9 +870,6 @@ void prepare(omm_ctx* c) {
   b.hist = c->d_hist;
   b.nsys = c->nsys;
   b.eps2 = 0.0;
-  b.ks[0] = pick_ks(c->Ps1.nout, c->Ps1.npairs);
-  b.ks[1] = pick_ks(c->Ps2.nout, c->Ps2.npairs);
-  b.ks[2] = pick_ks(c->Pgrad.nout, c->Pgrad.npairs);
   c->tuned = false;
   c->CM = dalloc<double>(c, std::max<int64_t>(1, c->TCM.nnz) * TE, true);
   c->rho = dalloc<double>(c, std::max<int64_t>(1, c->TH.nnz) * TE, true);
@@ -823,14 +880,31 @@ void prepare(omm_ctx* c) {
   c->prepared = true;
 }
 
-// Waves that split one output tile's pair list: enough waves in flight to hide
-// memory latency when there are few output tiles with long pair lists.
-int pick_ks(int64_t nout, int64_t npairs) {
-  if (nout <= 0) return 1;
-  const double avg = (double)npairs / (double)nout;
+// Waves that split one group's entry list: enough waves in flight to hide
+// memory latency when there are few groups with long lists.
+int pick_ks(int64_t ngroups, int64_t nent, int kmax) {
+  if (ngroups <= 0) return 1;
+  const double avg = (double)nent / (double)ngroups;
   for (int ks : {8, 4, 2})
-    if (nout * ks <= 16384 && avg >= 4.0 * ks) return ks;
+    if (ks <= kmax && ngroups * ks <= 16384 && avg >= 4.0 * ks) return ks;
   return 1;
+}
+
+// Grouped lists (a wave computes several output tiles of one row and loads the
+// shared operand once) when there are enough groups to fill the GPU, one tile
+// per wave otherwise.
+void pick_plans(omm_ctx* c) {
+  for (int k = 0; k < 3; ++k) {
+    const GPlan& wide = c->G[k][1];
+    // n x n projections keep one tile per wave by default: their grouped form
+    // holds twice the accumulators and loses occupancy (the autotuner may still pick it)
+    c->sel[k] = (k != 1 && wide.NT > 1 && wide.ngroups >= 2048) ? 1 : 0;
+    const GPlan& G = c->G[k][c->sel[k]];
+    c->b.ks[k] = pick_ks(G.ngroups, G.nent, G.NT > 1 ? 4 : 8);
+  }
+  c->b.s1 = c->G[0][c->sel[0]].view();
+  c->b.s2 = c->G[1][c->sel[1]].view();
+  c->b.grad = c->G[2][c->sel[2]].view();
 }
 
 CGParams params(const omm_ctx* c);
@@ -840,9 +914,18 @@ bool any_filter(const omm_ctx* c);
 // lists (after the initial products, so every operand is valid) and keep the
 // fastest; results are cached per (step, precision, work-list size) in a text
 // file when a cache path is given.
-std::string tune_key(int cls, int prec, const Plan& P) {
-  return std::to_string(cls) + ":" + std::to_string(prec) + ":" + std::to_string(P.nout) + ":" +
+std::string tune_key(int cls, int prec, const GPlan& P) {
+  return std::to_string(cls) + ":" + std::to_string(prec) + ":" + std::to_string(P.ngroups) + ":" +
          std::to_string(P.npairs);
+}
+
+void set_plan(omm_ctx* c, int cls, int sel, int ks) {
+  c->sel[cls] = sel;
+  c->b.ks[cls] = ks;
+  const GroupView v = c->G[cls][sel].view();
+  if (cls == 0) c->b.s1 = v;
+  else if (cls == 1) c->b.s2 = v;
+  else c->b.grad = v;
 }
 
 void autotune(omm_ctx* c) {
@@ -855,7 +938,6 @@ void autotune(omm_ctx* c) {
       std::fclose(f);
     }
   }
-  const Plan* plans[3] = {&c->Ps1, &c->Ps2, &c->Pgrad};
   const Prec p = c->prec;
   const int mask = PH_FP64 | PH_LOW;
   const bool filt = any_filter(c);
@@ -865,38 +947,43 @@ void autotune(omm_ctx* c) {
   bool added = false;
   c->tune_log.clear();
   for (int cls = 0; cls < 3; ++cls) {
-    const std::string key = tune_key(cls, (int)p, *plans[cls]);
-    int found = 0;
+    const std::string key = tune_key(cls, (int)p, c->G[cls][0]);
+    int found = -1;
     for (auto& kv : cache)
       if (kv.first == key) found = kv.second;
-    if (found) {
-      c->b.ks[cls] = found;
+    if (found >= 0) {      // cached as 10 * plan + KS
+      set_plan(c, cls, found / 10, found % 10);
       continue;
     }
     float best = 1e30f;
-    int best_ks = c->b.ks[cls];
-    for (int ks : {1, 2, 4, 8}) {
-      c->b.ks[cls] = ks;
-      float tmin = 1e30f;
-      for (int rep = 0; rep < 3; ++rep) {
-        OMM_HIP(hipEventRecord(e0, c->stream));
-        if (cls == 0) launch_s1(c->stream, c->b, p, mask, false, filt);
-        else if (cls == 1) launch_s2(c->stream, c->b, p, mask, false, filt);
-        else launch_grad(c->stream, c->b, p, mask, false);
-        OMM_HIP(hipEventRecord(e1, c->stream));
-        OMM_HIP(hipEventSynchronize(e1));
-        float ms = 0.f;
-        OMM_HIP(hipEventElapsedTime(&ms, e0, e1));
-        tmin = std::min(tmin, ms);
-      }
-      c->tune_log += key + " ks=" + std::to_string(ks) + " " + std::to_string(tmin) + "ms; ";
-      if (tmin < best) {
-        best = tmin;
-        best_ks = ks;
+    int best_code = 10 * c->sel[cls] + c->b.ks[cls];
+    for (int sel = 0; sel < 2; ++sel) {
+      if (sel == 1 && c->G[cls][1].NT == 1) continue;
+      for (int ks : {1, 2, 4, 8}) {
+        if (sel == 1 && ks == 8) continue;
+        set_plan(c, cls, sel, ks);
+        float tmin = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+          OMM_HIP(hipEventRecord(e0, c->stream));
+          if (cls == 0) launch_s1(c->stream, c->b, p, mask, false, filt);
+          else if (cls == 1) launch_s2(c->stream, c->b, p, mask, false, filt);
+          else launch_grad(c->stream, c->b, p, mask, false);
+          OMM_HIP(hipEventRecord(e1, c->stream));
+          OMM_HIP(hipEventSynchronize(e1));
+          float ms = 0.f;
+          OMM_HIP(hipEventElapsedTime(&ms, e0, e1));
+          tmin = std::min(tmin, ms);
+        }
+        c->tune_log += key + " nt=" + std::to_string(c->G[cls][sel].NT) + " ks=" + std::to_string(ks) + " " +
+                       std::to_string(tmin) + "ms; ";
+        if (tmin < best) {
+          best = tmin;
+          best_code = 10 * sel + ks;
+        }
       }
     }
-    c->b.ks[cls] = best_ks;
-    cache.emplace_back(key, best_ks);
+    set_plan(c, cls, best_code / 10, best_code % 10);
+    cache.emplace_back(key, best_code);
     added = true;
   }
   (void)hipEventDestroy(e0);
@@ -908,7 +995,7 @@ void autotune(omm_ctx* c) {
     }
   }
   c->tuned = true;
-  // the graph holds the launch shapes: capture again with the tuned factors
+  // the graph holds the launch shapes: capture again with the tuned choice
   if (c->gexec) {
     (void)hipGraphExecDestroy(c->gexec);
     c->gexec = nullptr;
@@ -1485,6 +1572,11 @@ int omm_query(const omm_ctx* cc, int32_t sys, omm_sizes* z) {
     if (rc != OMM_OK) return rc;
   }
   std::memset(z, 0, sizeof(*z));
+  if (c->prepared)
+    for (int k = 0; k < 3; ++k) {
+      z->tile_group[k] = c->G[k][c->sel[k]].NT;
+      z->tile_split[k] = c->b.ks[k];
+    }
   for (int i = 0; i < c->nsys; ++i) {
     if (sys >= 0 && i != sys) continue;
     const SysHost& s = c->sys[i];

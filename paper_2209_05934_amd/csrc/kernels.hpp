@@ -18,11 +18,20 @@ void transpose_count(hipStream_t st, int nrows, int row0, PatView A, const int2*
 void transpose_fill(hipStream_t st, int nrows, int row0, PatView A, const int2* win, const int* trp, int* tci,
                     int* tti);
 void rows_of(hipStream_t st, int nrows, const int* rp, int* rows);
+// grouped work lists: ng[i] = groups of output row i; then entry counts (gp == nullptr) or entries
+void group_counts(hipStream_t st, int nrows, const int* orp, int NT, int* ng);
+void group_lists(hipStream_t st, int nrows, PatView A, PatView B, PatView O, int NT, const int* gbase,
+                 int64_t* gcnt, int64_t* gpres, const int64_t* gp, int* ent, int* go0, int* gn);
 void excl_scan(hipStream_t st, const int* in, int* out, int64_t n);
 void excl_scan64(hipStream_t st, const int64_t* in, int64_t* out, int64_t n);
 
 // ---------------------------------------------------------------- numeric (numeric.hip)
 enum Prec { P64 = 0, P32 = 1, PBF = 2 };
+
+// group widths (output tiles per wave) of the grouped work lists
+constexpr int NT_S1 = 4;     // direction products: H, S tiles shared by 4 tiles of D
+constexpr int NT_S2 = 2;     // n x n projections: C, D tiles shared by 2 tiles of HD, SD
+constexpr int NT_GRAD = 4;   // gradient: HC, SC tiles shared by 4 tiles of S_W, H_W
 
 struct Bufs {   // every device buffer the iteration kernels touch
   // patterns (global tile rows/cols)
@@ -34,7 +43,7 @@ struct Bufs {   // every device buffer the iteration kernels touch
   const int4* chunks;            // trace chunks (tile begin, end, system)
   int nchunks;
   int n_th, n_tc, n_thc, n_tw;   // tile counts
-  PlanView s1, s2, grad;
+  GroupView s1, s2, grad;         // grouped work lists of the three product steps
   // FP64 masters
   double *H, *S, *C, *D, *G, *Gold, *HC, *SC, *HD, *SD, *H0, *S0, *X, *Y, *S2, *H2;
   // low-precision copies (float or bf16 storage, typed at launch) and FP32 product outputs

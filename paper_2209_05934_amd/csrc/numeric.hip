@@ -15,6 +15,8 @@
 // follows from Eq. 3-4.  Tile products run on MFMA (FP64, FP32, or BF16 with
 // FP32 accumulation); every reduction feeding the line search is FP64 in a
 // fixed order.
+#include <type_traits>
+
 #include "kernels.hpp"
 #include "tile_ops.hpp"
 
@@ -107,150 +109,219 @@ __device__ __forceinline__ void ks_reduce(V (&acc)[NACC], V* buf, int grp, int w
   }
 }
 
-// chunk [b, e) of output tile t's pair list handled by split-wave wk
-__device__ __forceinline__ void ks_chunk(const PlanView& P, int t, int wk, int KS, int64_t& b, int64_t& e) {
-  const int64_t p0 = P.pp[t], n = P.pp[t + 1] - p0;
+// chunk [b, e) of group g's entry list handled by split-wave wk
+__device__ __forceinline__ void ks_chunk(const GroupView& P, int g, int wk, int KS, int64_t& b, int64_t& e) {
+  const int64_t p0 = P.gp[g], n = P.gp[g + 1] - p0;
   b = p0 + (n * wk) / KS;
   e = p0 + (n * (wk + 1)) / KS;
 }
 
 // ------------------------------------------------------------------ S1: HD = H D, SD = S D
-template <typename TI, typename TO, bool FILTER, int KS>
+// One wave-group per group of NT output tiles in one row of the HC pattern:
+// per k the H and S tiles are loaded once and multiply NT tiles of D.
+template <typename TI, typename TO, int KS, int NT>
 __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s1(
-    PlanView P, const int* __restrict__ orow, const int* __restrict__ ocol, const int* __restrict__ brow_sys,
+    GroupView P, const int* __restrict__ orow, const int* __restrict__ ocol, const int* __restrict__ brow_sys,
     const SysInfo* __restrict__ info, const SysState* __restrict__ st, int mask, const TI* __restrict__ Hm,
     const TI* __restrict__ Sm, const TI* __restrict__ Bm, TO* __restrict__ O1, TO* __restrict__ O2,
     const int* __restrict__ hc_to_c, const uint8_t* __restrict__ wseg) {
   typedef typename Acc<TI>::V V;
   typedef Split<KS> SP;
-  __shared__ V red[SP::RED * 2 * 64];
+  constexpr int W = 1 + NT;
+  __shared__ V red[SP::RED * 2 * NT * 64];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int grp = wave / KS, wk = wave - grp * KS;
-  const int t = xcd_block() * SP::G + grp;
-  bool act = t < P.nout;
-  int s = 0;
+  const int g = xcd_block() * SP::G + grp;
+  bool act = g < P.ngroups;
+  int s = 0, o0 = 0, cnt = 0;
   if (act) {
-    s = brow_sys[orow[t]];
+    o0 = P.go0[g];
+    cnt = P.gn[g];
+    s = brow_sys[orow[o0]];
     act = on(st, s, mask);
   }
   const bool ident = act && info[s].ident_s != 0;
-  V acc[2] = {vzero<V>(), vzero<V>()};
+  V acc[2 * NT];
+#pragma unroll
+  for (int a = 0; a < 2 * NT; ++a) acc[a] = vzero<V>();
   if (act) {
     int64_t b, e;
-    ks_chunk(P, t, wk, KS, b, e);
+    ks_chunk(P, g, wk, KS, b, e);
     if (b < e) {
-      int2 pr = P.pairs[b];
-      Frag<TI> fb, fh, fs;
-      ld_col(fb, Bm + (size_t)pr.y * TE, lane);
-      ld_row(fh, Hm + (size_t)pr.x * TE, lane);
-      if (!ident) ld_row(fs, Sm + (size_t)pr.x * TE, lane);
+      Frag<TI> fh, fs, fb[NT];
+      int bi[NT];
+      {
+        const int* en = P.ent + b * W;
+        ld_row(fh, Hm + (size_t)en[0] * TE, lane);
+        if (!ident) ld_row(fs, Sm + (size_t)en[0] * TE, lane);
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+          bi[u] = en[1 + u];
+          if (bi[u] >= 0) ld_col(fb[u], Bm + (size_t)bi[u] * TE, lane);
+        }
+      }
       for (int64_t p = b; p < e; ++p) {
-        const int2 nx = P.pairs[p + 1 < e ? p + 1 : p];   // prefetch the next pair
-        Frag<TI> nb, nh, ns;
-        ld_col(nb, Bm + (size_t)nx.y * TE, lane);
-        ld_row(nh, Hm + (size_t)nx.x * TE, lane);
-        if (!ident) ld_row(ns, Sm + (size_t)nx.x * TE, lane);
-        mma(acc[0], fh, fb);
-        if (!ident) mma(acc[1], fs, fb);
-        fb = nb;
+        const int* nx = P.ent + (p + 1 < e ? p + 1 : p) * W;   // prefetch the next entry
+        Frag<TI> nh, ns, nb[NT];
+        int ni[NT];
+        ld_row(nh, Hm + (size_t)nx[0] * TE, lane);
+        if (!ident) ld_row(ns, Sm + (size_t)nx[0] * TE, lane);
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+          ni[u] = nx[1 + u];
+          if (ni[u] >= 0) ld_col(nb[u], Bm + (size_t)ni[u] * TE, lane);
+        }
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+          if (bi[u] >= 0) {
+            mma(acc[u], fh, fb[u]);
+            if (!ident) mma(acc[NT + u], fs, fb[u]);
+          }
+        }
         fh = nh;
         fs = ns;
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+          fb[u] = nb[u];
+          bi[u] = ni[u];
+        }
       }
     }
   }
-  ks_reduce<KS, 2>(acc, red, grp, wk, lane);
+  ks_reduce<KS, 2 * NT>(acc, red, grp, wk, lane);
   if (!act || wk != 0) return;
-  if (ident) {   // S = I: S B is B's own tile
-    typedef typename Acc<TI>::S AS;
-    const int ct = hc_to_c[t];
+  const double e2 = info[s].eps2;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) acc[1][r] = ct >= 0 ? cvt<AS, TI>(Bm[(size_t)ct * TE + out_off<V>(lane, r)]) : (AS)0;
-  }
-  if (FILTER) {
-    const uint8_t* cs = wseg + 32 * (size_t)ocol[t];
-    const double e2 = info[s].eps2;
-    filter_tile(acc[0], lane, nullptr, cs, e2);
-    filter_tile(acc[1], lane, nullptr, cs, e2);
-  }
-  TO* o1 = O1 + (size_t)t * TE;
-  TO* o2 = O2 + (size_t)t * TE;
+  for (int u = 0; u < NT; ++u) {
+    if (u >= cnt) break;
+    const int t = o0 + u;
+    V a1 = acc[u], a2 = acc[NT + u];
+    if (ident) {   // S = I: S B is B's own tile
+      typedef typename Acc<TI>::S AS;
+      const int ct = hc_to_c[t];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    o1[out_off<V>(lane, r)] = (TO)acc[0][r];
-    o2[out_off<V>(lane, r)] = (TO)acc[1][r];
+      for (int r = 0; r < 4; ++r) a2[r] = ct >= 0 ? cvt<AS, TI>(Bm[(size_t)ct * TE + out_off<V>(lane, r)]) : (AS)0;
+    }
+    if (e2 > 0.0) {
+      const uint8_t* cs = wseg + 32 * (size_t)ocol[t];
+      filter_tile(a1, lane, nullptr, cs, e2);
+      filter_tile(a2, lane, nullptr, cs, e2);
+    }
+    TO* o1 = O1 + (size_t)t * TE;
+    TO* o2 = O2 + (size_t)t * TE;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      o1[out_off<V>(lane, r)] = (TO)a1[r];
+      o2[out_off<V>(lane, r)] = (TO)a2[r];
+    }
   }
 }
 
 // ------------------------------------------------------------------ S2: n x n projections
-template <typename TI, typename TM, typename TO, int NPROD, bool FILTER, int KS>
+// Groups of NT output tiles in one row g of the n x n pattern: per basis tile b
+// the C(b,g) and D(b,g) tiles are loaded once for NT tiles of HD and SD.
+template <typename TI, typename TM, typename TO, int NPROD, int KS, int NT>
 __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s2(
-    PlanView P, const int* __restrict__ orow, const int* __restrict__ ocol, const int* __restrict__ wrow_sys,
+    GroupView P, const int* __restrict__ orow, const int* __restrict__ ocol, const int* __restrict__ wrow_sys,
     const SysInfo* __restrict__ info, const SysState* __restrict__ st, int mask, const TI* __restrict__ Cm,
     const TI* __restrict__ Dm, const TM* __restrict__ HDm, const TM* __restrict__ SDm, TO* __restrict__ X,
     TO* __restrict__ Y, TO* __restrict__ S2o, TO* __restrict__ H2o, const uint8_t* __restrict__ wseg) {
   typedef typename Acc<TI>::V V;
   typedef Split<KS> SP;
-  __shared__ V red[SP::RED * NPROD * 64];
+  constexpr int W = 1 + NT;
+  __shared__ V red[SP::RED * NPROD * NT * 64];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int grp = wave / KS, wk = wave - grp * KS;
-  const int t = xcd_block() * SP::G + grp;
-  bool act = t < P.nout;
-  int s = 0;
+  const int g = xcd_block() * SP::G + grp;
+  bool act = g < P.ngroups;
+  int s = 0, o0 = 0, cnt = 0;
   if (act) {
-    s = wrow_sys[orow[t]];
+    o0 = P.go0[g];
+    cnt = P.gn[g];
+    s = wrow_sys[orow[o0]];
     act = on(st, s, mask);
   }
-  V acc[NPROD];
+  V acc[NPROD * NT];
 #pragma unroll
-  for (int a = 0; a < NPROD; ++a) acc[a] = vzero<V>();
+  for (int a = 0; a < NPROD * NT; ++a) acc[a] = vzero<V>();
   if (act) {
     int64_t b, e;
-    ks_chunk(P, t, wk, KS, b, e);
+    ks_chunk(P, g, wk, KS, b, e);
     if (b < e) {
-      int2 pr = P.pairs[b];
-      Frag<TI> fc, fd, fhd, fsd;
-      ld_col(fc, Cm + (size_t)pr.x * TE, lane);     // A = C^T
-      if (NPROD == 4) ld_col(fd, Dm + (size_t)pr.x * TE, lane);   // A = D^T
-      ld_col(fhd, HDm + (size_t)pr.y * TE, lane);
-      ld_col(fsd, SDm + (size_t)pr.y * TE, lane);
+      Frag<TI> fc, fd, fhd[NT], fsd[NT];
+      int bi[NT];
+      {
+        const int* en = P.ent + b * W;
+        ld_col(fc, Cm + (size_t)en[0] * TE, lane);                 // A = C^T
+        if (NPROD == 4) ld_col(fd, Dm + (size_t)en[0] * TE, lane);  // A = D^T
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+          bi[u] = en[1 + u];
+          if (bi[u] >= 0) {
+            ld_col(fhd[u], HDm + (size_t)bi[u] * TE, lane);
+            ld_col(fsd[u], SDm + (size_t)bi[u] * TE, lane);
+          }
+        }
+      }
       for (int64_t p = b; p < e; ++p) {
-        const int2 nx = P.pairs[p + 1 < e ? p + 1 : p];
-        Frag<TI> nc, nd, nhd, nsd;
-        ld_col(nc, Cm + (size_t)nx.x * TE, lane);
-        if (NPROD == 4) ld_col(nd, Dm + (size_t)nx.x * TE, lane);
-        ld_col(nhd, HDm + (size_t)nx.y * TE, lane);
-        ld_col(nsd, SDm + (size_t)nx.y * TE, lane);
-        mma(acc[0], fc, fsd);
-        mma(acc[1], fc, fhd);
-        if (NPROD == 4) {
-          mma(acc[2], fd, fsd);
-          mma(acc[3], fd, fhd);
+        const int* nx = P.ent + (p + 1 < e ? p + 1 : p) * W;
+        Frag<TI> nc, nd, nhd[NT], nsd[NT];
+        int ni[NT];
+        ld_col(nc, Cm + (size_t)nx[0] * TE, lane);
+        if (NPROD == 4) ld_col(nd, Dm + (size_t)nx[0] * TE, lane);
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+          ni[u] = nx[1 + u];
+          if (ni[u] >= 0) {
+            ld_col(nhd[u], HDm + (size_t)ni[u] * TE, lane);
+            ld_col(nsd[u], SDm + (size_t)ni[u] * TE, lane);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+          if (bi[u] >= 0) {
+            mma(acc[u], fc, fsd[u]);
+            mma(acc[NT + u], fc, fhd[u]);
+            if (NPROD == 4) {
+              mma(acc[2 * NT + u], fd, fsd[u]);
+              mma(acc[3 * NT + u], fd, fhd[u]);
+            }
+          }
         }
         fc = nc;
         fd = nd;
-        fhd = nhd;
-        fsd = nsd;
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+          fhd[u] = nhd[u];
+          fsd[u] = nsd[u];
+          bi[u] = ni[u];
+        }
       }
     }
   }
-  ks_reduce<KS, NPROD>(acc, red, grp, wk, lane);
+  ks_reduce<KS, NPROD * NT>(acc, red, grp, wk, lane);
   if (!act || wk != 0) return;
-  if (FILTER) {
-    const uint8_t* rs = wseg + 32 * (size_t)orow[t];
-    const uint8_t* cs = wseg + 32 * (size_t)ocol[t];
-    const double e2 = info[s].eps2;
+  const double e2 = info[s].eps2;
 #pragma unroll
-    for (int a = 0; a < NPROD; ++a) filter_tile(acc[a], lane, rs, cs, e2);
-  }
-  const size_t o = (size_t)t * TE;
+  for (int u = 0; u < NT; ++u) {
+    if (u >= cnt) break;
+    const int t = o0 + u;
+    if (e2 > 0.0) {
+      const uint8_t* rs = wseg + 32 * (size_t)orow[t];
+      const uint8_t* cs = wseg + 32 * (size_t)ocol[t];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int e = out_off<V>(lane, r);
-    X[o + e] = (TO)acc[0][r];
-    Y[o + e] = (TO)acc[1][r];
-    if (NPROD == 4) {
-      S2o[o + e] = (TO)acc[2][r];
-      H2o[o + e] = (TO)acc[3][r];
+      for (int a = 0; a < NPROD; ++a) filter_tile(acc[a * NT + u], lane, rs, cs, e2);
+    }
+    const size_t o = (size_t)t * TE;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = out_off<V>(lane, r);
+      X[o + e] = (TO)acc[u][r];
+      Y[o + e] = (TO)acc[NT + u][r];
+      if (NPROD == 4) {
+        S2o[o + e] = (TO)acc[2 * NT + u][r];
+        H2o[o + e] = (TO)acc[3 * NT + u][r];
+      }
     }
   }
 }
@@ -512,97 +583,9 @@ __global__ __launch_bounds__(256) void k_update(int nc, int nhc, const int* __re
   }
 }
 
-// ------------------------------------------------------------------ gradient on C's pattern
-template <typename TI, int KS>
-__global__ __launch_bounds__(Split<KS>::NW * 64) void k_grad(
-    PlanView P, const int* __restrict__ tc_row, const int* __restrict__ brow_sys, const SysState* __restrict__ st,
-    int mask, const TI* __restrict__ HCm, const TI* __restrict__ SCm, const TI* __restrict__ S0m,
-    const TI* __restrict__ H0m, const double* __restrict__ HC, const int* __restrict__ c_in_hc,
-    const uint32_t* __restrict__ cmask, const double* __restrict__ Gold, double* __restrict__ G,
-    double* __restrict__ gpart) {
-  typedef typename Acc<TI>::V V;
-  typedef Split<KS> SP;
-  __shared__ V red[SP::RED * 64];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int grp = wave / KS, wk = wave - grp * KS;
-  const int t = xcd_block() * SP::G + grp;
-  bool act = t < P.nout;
-  if (act) act = on(st, brow_sys[tc_row[t]], mask);
-  V acc[1] = {vzero<V>()};
-  if (act) {
-    int64_t b, e;
-    ks_chunk(P, t, wk, KS, b, e);
-    if (b < e) {
-      int2 pr = P.pairs[b];
-      Frag<TI> fh, fs, fw, fv;
-      ld_row(fh, HCm + (size_t)pr.x * TE, lane);
-      ld_row(fs, SCm + (size_t)pr.x * TE, lane);
-      ld_col(fw, S0m + (size_t)pr.y * TE, lane);
-      ld_col(fv, H0m + (size_t)pr.y * TE, lane);
-      for (int64_t p = b; p < e; ++p) {
-        const int2 nx = P.pairs[p + 1 < e ? p + 1 : p];
-        Frag<TI> nh, ns, nw, nv;
-        ld_row(nh, HCm + (size_t)nx.x * TE, lane);
-        ld_row(ns, SCm + (size_t)nx.x * TE, lane);
-        ld_col(nw, S0m + (size_t)nx.y * TE, lane);
-        ld_col(nv, H0m + (size_t)nx.y * TE, lane);
-        mma(acc[0], fh, fw);
-        mma(acc[0], fs, fv);
-        fh = nh;
-        fs = ns;
-        fw = nw;
-        fv = nv;
-      }
-    }
-  }
-  ks_reduce<KS, 1>(acc, red, grp, wk, lane);
-  if (!act || wk != 0) return;
-  const uint32_t mk = cmask[t];
-  const int j = lane & 15, q = lane >> 4;
-  const double* hc = HC + (size_t)c_in_hc[t] * TE;
-  double gg = 0.0, go = 0.0;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int row = Lay<V>::row(q, r);
-    const int e = row * 16 + j;
-    const bool in = ((mk >> row) & 1u) && ((mk >> (16 + j)) & 1u);
-    const double g = in ? 8.0 * hc[e] - 4.0 * (double)acc[0][r] : 0.0;
-    G[(size_t)t * TE + e] = g;
-    gg += g * g;
-    go += g * Gold[(size_t)t * TE + e];
-  }
-  gg = wave_sum(gg);
-  go = wave_sum(go);
-  if (lane == 0) {
-    gpart[2 * (size_t)t] = gg;
-    gpart[2 * (size_t)t + 1] = go;
-  }
-}
-
-// ------------------------------------------------------------------ beta, stop rules (one wave per system)
-__global__ __launch_bounds__(256) void k_beta(const SysInfo* __restrict__ info, SysState* __restrict__ st, int mask,
-                                            const double* __restrict__ gpart, int init, double* __restrict__ hist,
-                                            CGParams prm) {
-  __shared__ double red[2][4];
-  const int s = blockIdx.x;
-  if (!on(st, s, mask)) return;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  double gg = 0.0, go = 0.0;
-  for (int t = info[s].c0 + threadIdx.x; t < info[s].c1; t += blockDim.x) {
-    gg += gpart[2 * (size_t)t];
-    go += gpart[2 * (size_t)t + 1];
-  }
-  gg = wave_sum(gg);
-  go = wave_sum(go);
-  if (lane == 0) {
-    red[0][wv] = gg;
-    red[1][wv] = go;
-  }
-  __syncthreads();
-  if (threadIdx.x != 0) return;
-  gg = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
-  go = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
-  SysState& S = st[s];
+// ------------------------------------------------------------------ beta, stop rules (one thread per system)
+__device__ void beta_finish(SysState& S, int s, double gg, double go, int init, double* __restrict__ hist,
+                            const CGParams& prm) {
   const double gn = sqrt(gg);
   if (init) {
     S.gg = gg;
@@ -644,6 +627,139 @@ __global__ __launch_bounds__(256) void k_beta(const SysInfo* __restrict__ info, 
   S.gnorm = gn;
   S.steepest = (beta == 0.0) ? 1 : 0;
   S.restart = 0;
+}
+
+// <G,G> and <G,G_old> of one system summed in tile order, then beta and the stop rules
+__global__ __launch_bounds__(256) void k_beta(const SysInfo* __restrict__ info, SysState* __restrict__ st, int mask,
+                                            const double* __restrict__ gpart, int init, double* __restrict__ hist,
+                                            CGParams prm) {
+  __shared__ double red[2][4];
+  const int s = blockIdx.x;
+  if (!on(st, s, mask)) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double gg = 0.0, go = 0.0;
+  for (int t = info[s].c0 + threadIdx.x; t < info[s].c1; t += blockDim.x) {
+    gg += gpart[2 * (size_t)t];
+    go += gpart[2 * (size_t)t + 1];
+  }
+  gg = wave_sum(gg);
+  go = wave_sum(go);
+  if (lane == 0) {
+    red[0][wv] = gg;
+    red[1][wv] = go;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  gg = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
+  go = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
+  beta_finish(st[s], s, gg, go, init, hist, prm);
+}
+
+// ------------------------------------------------------------------ gradient on C's pattern
+// Groups of NT tiles of C's pattern in one basis row b: per k the HC(b,k) and
+// SC(b,k) tiles are loaded once for NT tiles of S_W and H_W.
+template <typename TI, int KS, int NT>
+__global__ __launch_bounds__(Split<KS>::NW * 64) void k_grad(
+    GroupView P, const int* __restrict__ tc_row, const int* __restrict__ brow_sys, const SysState* __restrict__ st,
+    int mask, const TI* __restrict__ HCm, const TI* __restrict__ SCm, const TI* __restrict__ S0m,
+    const TI* __restrict__ H0m, const double* __restrict__ HC, const int* __restrict__ c_in_hc,
+    const uint32_t* __restrict__ cmask, const double* __restrict__ Gold, double* __restrict__ G,
+    double* __restrict__ gpart) {
+  typedef typename Acc<TI>::V V;
+  typedef Split<KS> SP;
+  constexpr int W = 1 + NT;
+  __shared__ V red[SP::RED * NT * 64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int grp = wave / KS, wk = wave - grp * KS;
+  const int g = xcd_block() * SP::G + grp;
+  bool act = g < P.ngroups;
+  int o0 = 0, cnt = 0;
+  if (act) {
+    o0 = P.go0[g];
+    cnt = P.gn[g];
+    act = on(st, brow_sys[tc_row[o0]], mask);
+  }
+  V acc[NT];
+#pragma unroll
+  for (int a = 0; a < NT; ++a) acc[a] = vzero<V>();
+  if (act) {
+    int64_t b, e;
+    ks_chunk(P, g, wk, KS, b, e);
+    if (b < e) {
+      Frag<TI> fh, fs, fw[NT], fv[NT];
+      int bi[NT];
+      {
+        const int* en = P.ent + b * W;
+        ld_row(fh, HCm + (size_t)en[0] * TE, lane);
+        ld_row(fs, SCm + (size_t)en[0] * TE, lane);
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+          bi[u] = en[1 + u];
+          if (bi[u] >= 0) {
+            ld_col(fw[u], S0m + (size_t)bi[u] * TE, lane);
+            ld_col(fv[u], H0m + (size_t)bi[u] * TE, lane);
+          }
+        }
+      }
+      for (int64_t p = b; p < e; ++p) {
+        const int* nx = P.ent + (p + 1 < e ? p + 1 : p) * W;
+        Frag<TI> nh, ns, nw[NT], nv[NT];
+        int ni[NT];
+        ld_row(nh, HCm + (size_t)nx[0] * TE, lane);
+        ld_row(ns, SCm + (size_t)nx[0] * TE, lane);
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+          ni[u] = nx[1 + u];
+          if (ni[u] >= 0) {
+            ld_col(nw[u], S0m + (size_t)ni[u] * TE, lane);
+            ld_col(nv[u], H0m + (size_t)ni[u] * TE, lane);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+          if (bi[u] >= 0) {
+            mma(acc[u], fh, fw[u]);
+            mma(acc[u], fs, fv[u]);
+          }
+        }
+        fh = nh;
+        fs = ns;
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+          fw[u] = nw[u];
+          fv[u] = nv[u];
+          bi[u] = ni[u];
+        }
+      }
+    }
+  }
+  ks_reduce<KS, NT>(acc, red, grp, wk, lane);
+  if (!act || wk != 0) return;
+  const int j = lane & 15, q = lane >> 4;
+#pragma unroll
+  for (int u = 0; u < NT; ++u) {
+    if (u >= cnt) break;
+    const int t = o0 + u;
+    const uint32_t mk = cmask[t];
+    const double* hc = HC + (size_t)c_in_hc[t] * TE;
+    double gg = 0.0, go = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = Lay<V>::row(q, r);
+      const int e = row * 16 + j;
+      const bool in = ((mk >> row) & 1u) && ((mk >> (16 + j)) & 1u);
+      const double gv = in ? 8.0 * hc[e] - 4.0 * (double)acc[u][r] : 0.0;
+      G[(size_t)t * TE + e] = gv;
+      gg += gv * gv;
+      go += gv * Gold[(size_t)t * TE + e];
+    }
+    gg = wave_sum(gg);
+    go = wave_sum(go);
+    if (lane == 0) {
+      gpart[2 * (size_t)t] = gg;
+      gpart[2 * (size_t)t + 1] = go;
+    }
+  }
 }
 
 template <typename TL, bool LOW>
@@ -802,70 +918,73 @@ inline dim3 waves_grid(int n) { return dim3((unsigned)((n + 3) / 4)); }
     OMM_HIP(hipGetLastError());                                                 \
   } while (0)
 
-template <int KS> static dim3 grid_for(int nout) { return dim3((unsigned)((nout + Split<KS>::G - 1) / Split<KS>::G)); }
+template <int KS> static dim3 grid_for(int n) { return dim3((unsigned)((n + Split<KS>::G - 1) / Split<KS>::G)); }
 template <int KS> static dim3 block_for() { return dim3(Split<KS>::NW * 64); }
 
-#define KS_DISPATCH(ks, ...)                     \
-  switch (ks) {                                  \
-    case 8: { constexpr int K_ = 8; __VA_ARGS__; } break; \
-    case 4: { constexpr int K_ = 4; __VA_ARGS__; } break; \
-    case 2: { constexpr int K_ = 2; __VA_ARGS__; } break; \
-    default: { constexpr int K_ = 1; __VA_ARGS__; } break; \
-  }
-
-template <typename TI, typename TO>
-static void s1_go(hipStream_t s, const Bufs& b, int mask, bool filter, const TI* H, const TI* S, const TI* B,
-                  TO* O1, TO* O2) {
-  const int n = b.s1.nout;
-  if (filter) {
-    KS_DISPATCH(b.ks[0], LAUNCH((k_s1<TI, TO, true, K_>), grid_for<K_>(n), block_for<K_>(), s, b.s1, b.thc_row,
-                                b.thc_col, b.brow_sys, b.info, b.st, mask, H, S, B, O1, O2, b.hc_to_c, b.wseg))
+// (NT, KS) dispatch: NT is 1 or the step's group width; KS in {1,2,4,8} (at most 4 when NT > 1)
+template <int NTG, typename F>
+static void nt_ks(int nt, int ks, F&& f) {
+  if (nt == 1) {
+    switch (ks) {
+      case 8: f(std::integral_constant<int, 1>{}, std::integral_constant<int, 8>{}); break;
+      case 4: f(std::integral_constant<int, 1>{}, std::integral_constant<int, 4>{}); break;
+      case 2: f(std::integral_constant<int, 1>{}, std::integral_constant<int, 2>{}); break;
+      default: f(std::integral_constant<int, 1>{}, std::integral_constant<int, 1>{}); break;
+    }
   } else {
-    KS_DISPATCH(b.ks[0], LAUNCH((k_s1<TI, TO, false, K_>), grid_for<K_>(n), block_for<K_>(), s, b.s1, b.thc_row,
-                                b.thc_col, b.brow_sys, b.info, b.st, mask, H, S, B, O1, O2, b.hc_to_c, b.wseg))
+    switch (ks) {
+      case 8:
+      case 4: f(std::integral_constant<int, NTG>{}, std::integral_constant<int, 4>{}); break;
+      case 2: f(std::integral_constant<int, NTG>{}, std::integral_constant<int, 2>{}); break;
+      default: f(std::integral_constant<int, NTG>{}, std::integral_constant<int, 1>{}); break;
+    }
   }
 }
 
+template <typename TI, typename TO>
+static void s1_go(hipStream_t s, const Bufs& b, int mask, const TI* H, const TI* S, const TI* B, TO* O1, TO* O2) {
+  nt_ks<NT_S1>(b.s1.NT, b.ks[0], [&](auto ntc, auto ksc) {
+    constexpr int N_ = decltype(ntc)::value, K_ = decltype(ksc)::value;
+    LAUNCH((k_s1<TI, TO, K_, N_>), grid_for<K_>(b.s1.ngroups), block_for<K_>(), s, b.s1, b.thc_row, b.thc_col,
+           b.brow_sys, b.info, b.st, mask, H, S, B, O1, O2, b.hc_to_c, b.wseg);
+  });
+}
+
 void launch_s1(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init, bool filter) {
-  if (b.s1.nout <= 0) return;
+  (void)filter;
+  if (b.s1.ngroups <= 0) return;
   if (prec == P64) {
-    if (init) s1_go<double, double>(s, b, mask, filter, b.H, b.S, b.C, b.HC, b.SC);
-    else s1_go<double, double>(s, b, mask, filter, b.H, b.S, b.D, b.HD, b.SD);
+    if (init) s1_go<double, double>(s, b, mask, b.H, b.S, b.C, b.HC, b.SC);
+    else s1_go<double, double>(s, b, mask, b.H, b.S, b.D, b.HD, b.SD);
   } else if (prec == P32) {
-    s1_go<float, float>(s, b, mask, filter, (const float*)b.Hl, (const float*)b.Sl, (const float*)b.Dl, b.HDf,
-                        b.SDf);
+    s1_go<float, float>(s, b, mask, (const float*)b.Hl, (const float*)b.Sl, (const float*)b.Dl, b.HDf, b.SDf);
   } else {
-    s1_go<bf16, float>(s, b, mask, filter, (const bf16*)b.Hl, (const bf16*)b.Sl, (const bf16*)b.Dl, b.HDf,
-                       b.SDf);
+    s1_go<bf16, float>(s, b, mask, (const bf16*)b.Hl, (const bf16*)b.Sl, (const bf16*)b.Dl, b.HDf, b.SDf);
   }
 }
 
 template <typename TI, typename TM, typename TO, int NP>
-static void s2_go(hipStream_t s, const Bufs& b, int mask, bool filter, const TI* C, const TI* D, const TM* HD,
-                  const TM* SD, TO* X, TO* Y, TO* S2, TO* H2) {
-  const int n = b.s2.nout;
-  if (filter) {
-    KS_DISPATCH(b.ks[1], LAUNCH((k_s2<TI, TM, TO, NP, true, K_>), grid_for<K_>(n), block_for<K_>(), s, b.s2,
-                                b.tw_row, b.tw_col, b.wrow_sys, b.info, b.st, mask, C, D, HD, SD, X, Y, S2, H2,
-                                b.wseg))
-  } else {
-    KS_DISPATCH(b.ks[1], LAUNCH((k_s2<TI, TM, TO, NP, false, K_>), grid_for<K_>(n), block_for<K_>(), s, b.s2,
-                                b.tw_row, b.tw_col, b.wrow_sys, b.info, b.st, mask, C, D, HD, SD, X, Y, S2, H2,
-                                b.wseg))
-  }
+static void s2_go(hipStream_t s, const Bufs& b, int mask, const TI* C, const TI* D, const TM* HD, const TM* SD,
+                  TO* X, TO* Y, TO* S2, TO* H2) {
+  nt_ks<NT_S2>(b.s2.NT, b.ks[1], [&](auto ntc, auto ksc) {
+    constexpr int N_ = decltype(ntc)::value, K_ = decltype(ksc)::value;
+    LAUNCH((k_s2<TI, TM, TO, NP, K_, N_>), grid_for<K_>(b.s2.ngroups), block_for<K_>(), s, b.s2, b.tw_row,
+           b.tw_col, b.wrow_sys, b.info, b.st, mask, C, D, HD, SD, X, Y, S2, H2, b.wseg);
+  });
 }
 
 void launch_s2(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init, bool filter) {
-  if (b.s2.nout <= 0) return;
+  (void)filter;
+  if (b.s2.ngroups <= 0) return;
   if (prec == P64) {
-    if (init) s2_go<double, double, double, 2>(s, b, mask, filter, b.C, b.C, b.HC, b.SC, b.S0, b.H0, b.S2, b.H2);
-    else s2_go<double, double, double, 4>(s, b, mask, filter, b.C, b.D, b.HD, b.SD, b.X, b.Y, b.S2, b.H2);
+    if (init) s2_go<double, double, double, 2>(s, b, mask, b.C, b.C, b.HC, b.SC, b.S0, b.H0, b.S2, b.H2);
+    else s2_go<double, double, double, 4>(s, b, mask, b.C, b.D, b.HD, b.SD, b.X, b.Y, b.S2, b.H2);
   } else if (prec == P32) {
-    s2_go<float, float, float, 4>(s, b, mask, filter, (const float*)b.Cl, (const float*)b.Dl, b.HDf, b.SDf, b.Xf,
-                                  b.Yf, b.S2f, b.H2f);
+    s2_go<float, float, float, 4>(s, b, mask, (const float*)b.Cl, (const float*)b.Dl, b.HDf, b.SDf, b.Xf, b.Yf,
+                                  b.S2f, b.H2f);
   } else {
-    s2_go<bf16, float, float, 4>(s, b, mask, filter, (const bf16*)b.Cl, (const bf16*)b.Dl, b.HDf, b.SDf, b.Xf,
-                                 b.Yf, b.S2f, b.H2f);
+    s2_go<bf16, float, float, 4>(s, b, mask, (const bf16*)b.Cl, (const bf16*)b.Dl, b.HDf, b.SDf, b.Xf, b.Yf,
+                                 b.S2f, b.H2f);
   }
 }
 
@@ -909,14 +1028,16 @@ void launch_update(hipStream_t s, const Bufs& b, Prec prec, int mask) {
 
 template <typename TI>
 static void grad_go(hipStream_t s, const Bufs& b, int mask, const TI* HC, const TI* SC, const TI* S0, const TI* H0) {
-  const int n = b.grad.nout;
-  KS_DISPATCH(b.ks[2], LAUNCH((k_grad<TI, K_>), grid_for<K_>(n), block_for<K_>(), s, b.grad, b.tc_row, b.brow_sys,
-                              b.st, mask, HC, SC, S0, H0, b.HC, b.c_in_hc, b.cmask, b.Gold, b.G, b.gpart))
+  nt_ks<NT_GRAD>(b.grad.NT, b.ks[2], [&](auto ntc, auto ksc) {
+    constexpr int N_ = decltype(ntc)::value, K_ = decltype(ksc)::value;
+    LAUNCH((k_grad<TI, K_, N_>), grid_for<K_>(b.grad.ngroups), block_for<K_>(), s, b.grad, b.tc_row, b.brow_sys,
+           b.st, mask, HC, SC, S0, H0, b.HC, b.c_in_hc, b.cmask, b.Gold, b.G, b.gpart);
+  });
 }
 
 void launch_grad(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init) {
   (void)init;
-  if (b.grad.nout <= 0) return;
+  if (b.grad.ngroups <= 0) return;
   if (prec == P64) grad_go<double>(s, b, mask, b.HC, b.SC, b.S0, b.H0);
   else if (prec == P32)
     grad_go<float>(s, b, mask, (const float*)b.HCl, (const float*)b.SCl, (const float*)b.S0l, (const float*)b.H0l);

@@ -92,4 +92,16 @@ struct PlanView {
   const int2* pairs;
 };
 
+// Grouped work list: group g covers the output tiles go0[g] .. go0[g]+gn[g]-1 of
+// one output row; its entries gp[g] .. gp[g+1]-1 are rows of 1 + NT ints
+// (A tile, then NT B tiles or -1), in increasing k.
+struct GroupView {
+  int ngroups;
+  int NT;
+  const int* go0;
+  const int* gn;
+  const int64_t* gp;
+  const int* ent;
+};
+
 }  // namespace omm

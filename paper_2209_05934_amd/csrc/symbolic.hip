@@ -211,6 +211,93 @@ __global__ void k_rows_of(int nrows, const int* __restrict__ rp, int* __restrict
   for (int e = rp[r]; e < rp[r + 1]; ++e) rows[e] = r;
 }
 
+
+// ---------------------------------------------------------------- grouped work lists
+// Output tiles of one output row are taken NT at a time ("groups").  A group's
+// entries are the k of A.row(i), in increasing order, for which at least one
+// of the group's NT output columns j has B(k, j) stored; an entry holds the A
+// tile index and NT B tile indices (-1 where B(k, j) is absent).  A wave can
+// then load the A tile once per k for all NT outputs of its group.
+__device__ __forceinline__ int find_in_row(const PatView& B, int k, int j) {
+  int lo = B.rp[k], hi = B.rp[k + 1];
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (B.ci[mid] < j) lo = mid + 1; else hi = mid;
+  }
+  return (lo < B.rp[k + 1] && B.ci[lo] == j) ? lo : -1;
+}
+
+template <bool FILL>
+__global__ __launch_bounds__(SYM_THREADS) void k_group_lists(PatView A, PatView B, PatView O, int NT,
+                                                           const int* __restrict__ gbase, int64_t* __restrict__ gcnt,
+                                                           int64_t* __restrict__ gpres, const int64_t* __restrict__ gp,
+                                                           int* __restrict__ ent, int* __restrict__ go0,
+                                                           int* __restrict__ gn) {
+  const int i = blockIdx.x;
+  const int o0 = O.rp[i], no = O.rp[i + 1] - o0;
+  const int ng = (no + NT - 1) / NT;
+  for (int gl = threadIdx.x; gl < ng; gl += blockDim.x) {
+    const int g = gbase[i] + gl;
+    const int ob = o0 + gl * NT;
+    const int cnt = min(NT, o0 + no - ob);
+    int64_t m = 0, pres = 0;
+    const int64_t base = FILL ? gp[g] : 0;
+    for (int e = A.rp[i]; e < A.rp[i + 1]; ++e) {
+      const int k = A.ci[e];
+      int bidx[8];
+      bool any = false;
+      for (int u = 0; u < NT; ++u) {
+        bidx[u] = u < cnt ? find_in_row(B, k, O.ci[ob + u]) : -1;
+        if (bidx[u] >= 0) {
+          any = true;
+          ++pres;
+        }
+      }
+      if (!any) continue;
+      if (FILL) {
+        int* row = ent + (base + m) * (1 + NT);
+        row[0] = a_tile(A, e);
+        for (int u = 0; u < NT; ++u) row[1 + u] = bidx[u] >= 0 ? (B.ti ? B.ti[bidx[u]] : bidx[u]) : -1;
+      }
+      ++m;
+    }
+    if (!FILL) {
+      gcnt[g] = m;
+      gpres[g] = pres;
+      go0[g] = ob;
+      gn[g] = cnt;
+    }
+  }
+}
+
+__global__ void k_group_base(int nrows, const int* __restrict__ orp, int NT, int* __restrict__ ng) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrows) return;
+  const int no = orp[i + 1] - orp[i];
+  ng[i] = (no + NT - 1) / NT;
+}
+
+}  // namespace
+
+void group_counts(hipStream_t st, int nrows, const int* orp, int NT, int* ng) {
+  if (nrows <= 0) return;
+  hipLaunchKernelGGL(k_group_base, dim3((nrows + 255) / 256), dim3(256), 0, st, nrows, orp, NT, ng);
+  OMM_HIP(hipGetLastError());
+}
+
+void group_lists(hipStream_t st, int nrows, PatView A, PatView B, PatView O, int NT, const int* gbase,
+                 int64_t* gcnt, int64_t* gpres, const int64_t* gp, int* ent, int* go0, int* gn) {
+  if (nrows <= 0) return;
+  if (!gp)
+    hipLaunchKernelGGL(k_group_lists<false>, dim3(nrows), dim3(SYM_THREADS), 0, st, A, B, O, NT, gbase, gcnt, gpres,
+                       gp, ent, go0, gn);
+  else
+    hipLaunchKernelGGL(k_group_lists<true>, dim3(nrows), dim3(SYM_THREADS), 0, st, A, B, O, NT, gbase, gcnt, gpres,
+                       gp, ent, go0, gn);
+  OMM_HIP(hipGetLastError());
+}
+
+namespace {
 }  // namespace
 
 void sym_count(hipStream_t st, int nrows, int row0, PatView A, PatView B, const int2* win, int* cnt) {

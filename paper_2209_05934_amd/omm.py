@@ -61,7 +61,7 @@ class omm_sizes(C.Structure):
         ("pairs_s1", C.c_int64), ("pairs_s2", C.c_int64), ("pairs_grad", C.c_int64),
         ("flops_alg_iter", C.c_double), ("flops_exec_iter", C.c_double), ("bytes_alg_iter", C.c_double),
         ("flops_alg_step", C.c_double * 3), ("flops_exec_step", C.c_double * 3),
-        ("bytes_alg_step", C.c_double * 3),
+        ("bytes_alg_step", C.c_double * 3), ("tile_group", C.c_int32 * 3), ("tile_split", C.c_int32 * 3),
     ]
 
 

@@ -43,8 +43,8 @@ def test_struct_layouts_match_header():
 #include "omm.h"
 int main(void) {
   printf("%zu %zu %zu %zu\n", sizeof(omm_matrix), sizeof(omm_options), sizeof(omm_report), sizeof(omm_sizes));
-  printf("%zu %zu %zu\n", offsetof(omm_options, hip_stream), offsetof(omm_report, seconds),
-         offsetof(omm_sizes, bytes_alg_step));
+  printf("%zu %zu %zu %zu\n", offsetof(omm_options, hip_stream), offsetof(omm_report, seconds),
+         offsetof(omm_sizes, bytes_alg_step), offsetof(omm_sizes, tile_split));
   return 0;
 }
 '''
@@ -60,6 +60,7 @@ int main(void) {
     assert sizes[4] == L.omm_options.hip_stream.offset
     assert sizes[5] == L.omm_report.seconds.offset
     assert sizes[6] == L.omm_sizes.bytes_alg_step.offset
+    assert sizes[7] == L.omm_sizes.tile_split.offset
 
 
 def test_status_strings_and_defaults():
