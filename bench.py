@@ -56,10 +56,14 @@ MEASURED_TRAFFIC = {
 }
 
 
-def kernel_source_hash() -> str:
+STEP_SOURCES = ("dir_products.hip", "proj_products.hip", "grad_products.hip")
+
+
+def kernel_source_hash(step: int) -> str:
+    """Hash of the sources of one tile-product step's kernel (stored traffic is valid only for them)."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("numeric.hip", "tile_ops.hpp"):
+    for f in (STEP_SOURCES[step], "tile_sched.hpp", "tile_ops.hpp"):
         with open(os.path.join(ROOT, "paper_2209_05934_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -284,7 +288,7 @@ def main():
             roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                     "frac": achieved / peak, "traffic": None}
         tk = (args.workload, args.precision, k, int(sz.tile_group[k]), int(sz.tile_split[k]))
-        if tk in MEASURED_TRAFFIC and MEASURED_TRAFFIC[tk][1] == kernel_source_hash():
+        if tk in MEASURED_TRAFFIC and MEASURED_TRAFFIC[tk][1] == kernel_source_hash(k):
             roof["traffic"] = MEASURED_TRAFFIC[tk][0]
         roof.update({"kernel": names[k], "tile_group": int(sz.tile_group[k]), "tile_split": int(sz.tile_split[k]),
                      "avg_launch_us": avg_s * 1e6, "launches": int(n[k]),

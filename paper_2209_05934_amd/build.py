@@ -18,7 +18,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIBDIR = os.path.join(PKG, "lib")
 LIBNAME = "libomm_mi355x.so"
-SOURCES = ["symbolic.hip", "numeric.hip", "cholesky.hip", "engine.hip"]
+SOURCES = ["symbolic.hip", "dir_products.hip", "proj_products.hip", "grad_products.hip", "numeric.hip",
+           "cholesky.hip", "engine.hip"]
 ARCH = os.environ.get("OMM_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
@@ -43,7 +44,7 @@ def lib_path() -> str:
     return os.path.join(LIBDIR, LIBNAME)
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
+def build(verbose: bool = False, jobs: int = 0) -> str:
     hipcc = _hipcc()
     objdir = os.path.join(LIBDIR, "obj")
     os.makedirs(objdir, exist_ok=True)
@@ -58,7 +59,9 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
             print(f"compiled {src}", flush=True)
         return obj
 
-    with ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
+    if jobs <= 0:
+        jobs = min(len(SOURCES), os.cpu_count() or 4)
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(compile_one, SOURCES))
     out = lib_path()
     tmp = out + ".tmp"

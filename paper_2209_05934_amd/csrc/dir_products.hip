@@ -1,0 +1,115 @@
+// Direction products HD = H D and SD = S D of one CG iteration on the
+// functional of Eq. 4 (arXiv 2209.05934): they feed the quartic line search
+// and the updates.  FP64, FP32 or BF16 MFMA tiles over the tile-pair work
+// lists of the HC pattern.
+#include "tile_sched.hpp"
+
+namespace omm {
+
+namespace {
+
+// ------------------------------------------------------------------ S1: HD = H D, SD = S D
+// One wave-group per group of NT output tiles in one row of the HC pattern:
+// per k the H and S tiles are loaded once and multiply NT tiles of D.
+template <typename TI, typename TO, int KS, int NT>
+__global__ __launch_bounds__(Split<KS>::NW * 64) void k_s1(
+    GroupView P, const int* __restrict__ orow, const int* __restrict__ ocol, const int* __restrict__ brow_sys,
+    const SysInfo* __restrict__ info, const SysState* __restrict__ st, int mask, const TI* __restrict__ Hm,
+    const TI* __restrict__ Sm, const TI* __restrict__ Bm, TO* __restrict__ O1, TO* __restrict__ O2,
+    const int* __restrict__ hc_to_c, const uint8_t* __restrict__ wseg) {
+  typedef typename Acc<TI>::V V;
+  typedef Split<KS> SP;
+  constexpr int W = 1 + NT;
+  __shared__ V red[SP::RED * 2 * NT * 64];
+  const int wave = wave_id(), lane = threadIdx.x & 63;
+  const int grp = wave / KS, wk = wave - grp * KS;
+  const int g = xcd_block() * SP::G + grp;
+  bool act = g < P.ngroups;
+  int s = 0, o0 = 0, cnt = 0;
+  if (act) {
+    o0 = P.go0[g];
+    cnt = P.gn[g];
+    s = brow_sys[orow[o0]];
+    act = on(st, s, mask);
+  }
+  const bool ident = act && info[s].ident_s != 0;
+  V acc[2 * NT];
+#pragma unroll
+  for (int a = 0; a < 2 * NT; ++a) acc[a] = vzero<V>();
+  if (act) {
+    int64_t b, e;
+    ks_chunk(P, g, wk, KS, b, e);
+    struct Stage { Frag<TI> h, s, b[NT]; };
+    const TI* Sq = ident ? Hm : Sm;   // S = I: the S fragments are loaded but never used
+    run_entries<W, pipe_depth<TI>(2 + NT), Stage>(
+        P.ent, b, e, lane,
+        [&](Stage& f, const int (&id)[W]) {
+          ld_row(f.h, Hm + (size_t)id[0] * TE, lane);
+          ld_row(f.s, Sq + (size_t)id[0] * TE, lane);
+#pragma unroll
+          for (int u = 0; u < NT; ++u) ld_col(f.b[u], Bm + (size_t)max(id[1 + u], 0) * TE, lane);
+        },
+        [&](const Stage& f, const int (&id)[W]) {
+#pragma unroll
+          for (int u = 0; u < NT; ++u) {
+            if (id[1 + u] >= 0) {
+              mma(acc[u], f.h, f.b[u]);
+              if (!ident) mma(acc[NT + u], f.s, f.b[u]);
+            }
+          }
+        });
+  }
+  ks_reduce<KS, 2 * NT>(acc, red, grp, wk, lane);
+  if (!act || wk != 0) return;
+  const double e2 = info[s].eps2;
+#pragma unroll
+  for (int u = 0; u < NT; ++u) {
+    if (u >= cnt) break;
+    const int t = o0 + u;
+    V a1 = acc[u], a2 = acc[NT + u];
+    if (ident) {   // S = I: S B is B's own tile
+      typedef typename Acc<TI>::S AS;
+      const int ct = hc_to_c[t];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a2[r] = ct >= 0 ? cvt<AS, TI>(Bm[(size_t)ct * TE + out_off<V>(lane, r)]) : (AS)0;
+    }
+    if (e2 > 0.0) {
+      const uint8_t* cs = wseg + 32 * (size_t)ocol[t];
+      filter_tile(a1, lane, nullptr, cs, e2);
+      filter_tile(a2, lane, nullptr, cs, e2);
+    }
+    TO* o1 = O1 + (size_t)t * TE;
+    TO* o2 = O2 + (size_t)t * TE;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      o1[out_off<V>(lane, r)] = (TO)a1[r];
+      o2[out_off<V>(lane, r)] = (TO)a2[r];
+    }
+  }
+}
+
+}  // namespace
+
+template <typename TI, typename TO>
+static void s1_go(hipStream_t s, const Bufs& b, int mask, const TI* H, const TI* S, const TI* B, TO* O1, TO* O2) {
+  nt_ks<NT_S1>(b.s1.NT, b.ks[0], [&](auto ntc, auto ksc) {
+    constexpr int N_ = decltype(ntc)::value, K_ = decltype(ksc)::value;
+    LAUNCH((k_s1<TI, TO, K_, N_>), grid_for<K_>(b.s1.ngroups), block_for<K_>(), s, b.s1, b.thc_row, b.thc_col,
+           b.brow_sys, b.info, b.st, mask, H, S, B, O1, O2, b.hc_to_c, b.wseg);
+  });
+}
+
+void launch_s1(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init, bool filter) {
+  (void)filter;
+  if (b.s1.ngroups <= 0) return;
+  if (prec == P64) {
+    if (init) s1_go<double, double>(s, b, mask, b.H, b.S, b.C, b.HC, b.SC);
+    else s1_go<double, double>(s, b, mask, b.H, b.S, b.D, b.HD, b.SD);
+  } else if (prec == P32) {
+    s1_go<float, float>(s, b, mask, (const float*)b.Hl, (const float*)b.Sl, (const float*)b.Dl, b.HDf, b.SDf);
+  } else {
+    s1_go<bf16, float>(s, b, mask, (const bf16*)b.Hl, (const bf16*)b.Sl, (const bf16*)b.Dl, b.HDf, b.SDf);
+  }
+}
+
+}  // namespace omm

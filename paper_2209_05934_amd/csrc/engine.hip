@@ -111,6 +111,7 @@ struct omm_ctx {
   GPlan G[3][2];      // product steps (direction, n x n, gradient) x (NT = 1, NT = step width)
   int sel[3] = {0, 0, 0};
   int *brow_sys = nullptr, *wrow_sys = nullptr, *c_in_hc = nullptr, *hc_to_c = nullptr, *w_tr = nullptr;
+  int* upd_sys = nullptr;
   uint32_t* cmask = nullptr;
   uint8_t* wseg = nullptr;
   int4* chunks = nullptr;
@@ -781,10 +782,12 @@ void prepare(omm_ctx* c) {
     f.hc0 = c->THC.hrp[f.rb0]; f.hc1 = c->THC.hrp[f.rb1];
     f.w0 = c->TW.hrp[f.wb0]; f.w1 = c->TW.hrp[f.wb1];
     f.ch0 = (int)chunks.size();
-    // tiles per trace chunk: at least 8 (every workgroup issues one device-scope
-    // fence), up to 32 so that the last workgroup's final reduction stays short
+    // trace chunks (workgroups of 4 waves): one tile per wave for systems of
+    // up to 64 n x n tiles (at most FUSED_CHUNKS chunks: the update kernel
+    // solves their line search), else 4 to 64 tiles per chunk so that about
+    // 4096 / 4 chunks cover a large system
     const int ntw = f.w1 - f.w0;
-    const int CH = std::max(8, std::min(32, ntw / 1024));
+    const int CH = ntw <= 4 * FUSED_CHUNKS ? 4 : 4 * std::max(1, std::min(16, (ntw + 4095) / 4096));
     for (int t = f.w0; t < f.w1; t += CH) chunks.push_back(make_int4(t, std::min(t + CH, f.w1), i, 0));
     f.ch1 = (int)chunks.size();
     f.mode = s.mode;
@@ -828,6 +831,9 @@ void prepare(omm_ctx* c) {
   b.brow_sys = c->brow_sys; b.wrow_sys = c->wrow_sys;
   b.c_in_hc = c->c_in_hc; b.hc_to_c = c->hc_to_c; b.w_tr = c->w_tr;
   b.cmask = c->cmask; b.wseg = c->wseg; b.chunks = c->chunks; b.nchunks = c->nchunks;
+  b.multi_chunk = 0;
+  for (int i = 0; i < c->nsys; ++i)
+    if (c->h_info[i].ch1 - c->h_info[i].ch0 > FUSED_CHUNKS) b.multi_chunk = 1;
   b.n_th = (int)c->TH.nnz; b.n_tc = (int)ntc; b.n_thc = (int)nhc; b.n_tw = (int)ntw;
   pick_plans(c);
   b.H = c->H; b.S = c->S;
@@ -863,8 +869,16 @@ void prepare(omm_ctx* c) {
   }
   b.tpart = dalloc<double>(c, (size_t)std::max(1, c->nchunks) * NSUM, true);
   b.gpart = dalloc<double>(c, std::max<size_t>(1, ntc) * 2, true);
-  b.ticket = dalloc<int>(c, c->nsys, true);
-  OMM_HIP(hipMemsetAsync(b.ticket, 0, sizeof(int) * c->nsys, st));
+  {
+    std::vector<int> us(ntc + nhc + ntw);
+    for (int i = 0; i < c->nsys; ++i) {
+      const SysInfo& f = c->h_info[i];
+      for (int t = f.c0; t < f.c1; ++t) us[t] = i;
+      for (int t = f.hc0; t < f.hc1; ++t) us[ntc + t] = i;
+      for (int t = f.w0; t < f.w1; ++t) us[ntc + nhc + t] = i;
+    }
+    b.upd_sys = c->upd_sys = dupload(c, us, true);
+  }
   b.info = c->d_info;
   b.st = c->d_st;
   b.hist = c->d_hist;
@@ -1052,8 +1066,8 @@ void run_iteration(omm_ctx* c, Prec p, int mask, bool tm) {
   StepArg a{p, mask, any_filter(c)};
   timed(c, 0, tm, [](omm_ctx* cc, void* v) { auto* q = (StepArg*)v; launch_s1(cc->stream, cc->b, q->p, q->mask, false, q->filter); }, &a);
   timed(c, 1, tm, [](omm_ctx* cc, void* v) { auto* q = (StepArg*)v; launch_s2(cc->stream, cc->b, q->p, q->mask, false, q->filter); }, &a);
-  launch_traces_ls(s, b, p, mask, LS_STEP, prm);
-  launch_update(s, b, p, mask);
+  launch_traces(s, b, p, mask, false, LS_STEP, prm);
+  launch_update(s, b, p, mask, prm);
   timed(c, 2, tm, [](omm_ctx* cc, void* v) { auto* q = (StepArg*)v; launch_grad(cc->stream, cc->b, q->p, q->mask, false); }, &a);
   launch_beta(s, b, mask, false, prm);
   launch_update_d(s, b, p, mask);
@@ -1071,7 +1085,7 @@ void init_sequence(omm_ctx* c) {
   const bool filt = any_filter(c);
   launch_s1(s, b, P64, PH_INIT, true, filt);
   launch_s2(s, b, P64, PH_INIT, true, filt);
-  launch_traces_ls(s, b, P64, PH_INIT, LS_INIT, prm);
+  launch_traces(s, b, P64, PH_INIT, true, LS_INIT, prm);
   launch_grad(s, b, P64, PH_INIT, true);
   launch_beta(s, b, PH_INIT, true, prm);
   launch_update_d(s, b, P64, PH_INIT);
@@ -1185,7 +1199,7 @@ int minimize(omm_ctx* c, omm_report* reps) {
     steps += K;
   }
   // electron count at the final C
-  launch_traces_ls(st, c->b, P64, PH_DONE, LS_REPORT, params(c));
+  launch_traces(st, c->b, P64, PH_DONE, true, LS_REPORT, params(c));
   OMM_HIP(hipMemcpyAsync(c->h_st, c->d_st, sizeof(SysState) * c->nsys, hipMemcpyDeviceToHost, st));
   OMM_HIP(hipStreamSynchronize(st));
   c->ran = true;

@@ -1,0 +1,113 @@
+// Gradient of the OMM functional on C's pattern (Eq. 4 of arXiv 2209.05934):
+// G = 8 HC - 4 (HC S0 + SC H0), with the two sums <G, G> and <G, G_old> per
+// tile that the Polak-Ribiere step needs.
+#include "tile_sched.hpp"
+
+namespace omm {
+
+namespace {
+
+// ------------------------------------------------------------------ gradient on C's pattern
+// Groups of NT tiles of C's pattern in one basis row b: per k the HC(b,k) and
+// SC(b,k) tiles are loaded once for NT tiles of S_W and H_W.
+template <typename TI, int KS, int NT>
+__global__ __launch_bounds__(Split<KS>::NW * 64) void k_grad(
+    GroupView P, const int* __restrict__ tc_row, const int* __restrict__ brow_sys, const SysState* __restrict__ st,
+    int mask, const TI* __restrict__ HCm, const TI* __restrict__ SCm, const TI* __restrict__ S0m,
+    const TI* __restrict__ H0m, const double* __restrict__ HC, const int* __restrict__ c_in_hc,
+    const uint32_t* __restrict__ cmask, const double* __restrict__ Gold, double* __restrict__ G,
+    double* __restrict__ gpart) {
+  typedef typename Acc<TI>::V V;
+  typedef Split<KS> SP;
+  constexpr int W = 1 + NT;
+  __shared__ V red[SP::RED * NT * 64];
+  const int wave = wave_id(), lane = threadIdx.x & 63;
+  const int grp = wave / KS, wk = wave - grp * KS;
+  const int g = xcd_block() * SP::G + grp;
+  bool act = g < P.ngroups;
+  int o0 = 0, cnt = 0;
+  if (act) {
+    o0 = P.go0[g];
+    cnt = P.gn[g];
+    act = on(st, brow_sys[tc_row[o0]], mask);
+  }
+  V acc[NT];
+#pragma unroll
+  for (int a = 0; a < NT; ++a) acc[a] = vzero<V>();
+  if (act) {
+    int64_t b, e;
+    ks_chunk(P, g, wk, KS, b, e);
+    struct Stage { Frag<TI> h, s, w[NT], v[NT]; };
+    run_entries<W, pipe_depth<TI>(2 + 2 * NT), Stage>(
+        P.ent, b, e, lane,
+        [&](Stage& f, const int (&id)[W]) {
+          ld_row(f.h, HCm + (size_t)id[0] * TE, lane);
+          ld_row(f.s, SCm + (size_t)id[0] * TE, lane);
+#pragma unroll
+          for (int u = 0; u < NT; ++u) {
+            const size_t bt = (size_t)max(id[1 + u], 0) * TE;
+            ld_col(f.w[u], S0m + bt, lane);
+            ld_col(f.v[u], H0m + bt, lane);
+          }
+        },
+        [&](const Stage& f, const int (&id)[W]) {
+#pragma unroll
+          for (int u = 0; u < NT; ++u) {
+            if (id[1 + u] >= 0) {
+              mma(acc[u], f.h, f.w[u]);
+              mma(acc[u], f.s, f.v[u]);
+            }
+          }
+        });
+  }
+  ks_reduce<KS, NT>(acc, red, grp, wk, lane);
+  if (!act || wk != 0) return;
+  const int j = lane & 15, q = lane >> 4;
+#pragma unroll
+  for (int u = 0; u < NT; ++u) {
+    if (u >= cnt) break;
+    const int t = o0 + u;
+    const uint32_t mk = cmask[t];
+    const double* hc = HC + (size_t)c_in_hc[t] * TE;
+    double gg = 0.0, go = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = Lay<V>::row(q, r);
+      const int e = row * 16 + j;
+      const bool in = ((mk >> row) & 1u) && ((mk >> (16 + j)) & 1u);
+      const double gv = in ? 8.0 * hc[e] - 4.0 * (double)acc[u][r] : 0.0;
+      G[(size_t)t * TE + e] = gv;
+      gg += gv * gv;
+      go += gv * Gold[(size_t)t * TE + e];
+    }
+    gg = wave_sum(gg);
+    go = wave_sum(go);
+    if (lane == 0) {
+      gpart[2 * (size_t)t] = gg;
+      gpart[2 * (size_t)t + 1] = go;
+    }
+  }
+}
+
+}  // namespace
+
+template <typename TI>
+static void grad_go(hipStream_t s, const Bufs& b, int mask, const TI* HC, const TI* SC, const TI* S0, const TI* H0) {
+  nt_ks<NT_GRAD>(b.grad.NT, b.ks[2], [&](auto ntc, auto ksc) {
+    constexpr int N_ = decltype(ntc)::value, K_ = decltype(ksc)::value;
+    LAUNCH((k_grad<TI, K_, N_>), grid_for<K_>(b.grad.ngroups), block_for<K_>(), s, b.grad, b.tc_row, b.brow_sys,
+           b.st, mask, HC, SC, S0, H0, b.HC, b.c_in_hc, b.cmask, b.Gold, b.G, b.gpart);
+  });
+}
+
+void launch_grad(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init) {
+  (void)init;
+  if (b.grad.ngroups <= 0) return;
+  if (prec == P64) grad_go<double>(s, b, mask, b.HC, b.SC, b.S0, b.H0);
+  else if (prec == P32)
+    grad_go<float>(s, b, mask, (const float*)b.HCl, (const float*)b.SCl, (const float*)b.S0l, (const float*)b.H0l);
+  else
+    grad_go<bf16>(s, b, mask, (const bf16*)b.HCl, (const bf16*)b.SCl, (const bf16*)b.S0l, (const bf16*)b.H0l);
+}
+
+}  // namespace omm

@@ -38,10 +38,12 @@ struct Bufs {   // every device buffer the iteration kernels touch
   const int *th_row, *th_col, *tc_row, *tc_col, *thc_row, *thc_col, *tw_row, *tw_col;
   const int *brow_sys, *wrow_sys;
   const int *c_in_hc, *hc_to_c, *w_tr;
+  const int* upd_sys;            // system of each tile of [C tiles | HC tiles | n x n tiles]
   const uint32_t* cmask;
   const uint8_t* wseg;           // per wavefunction tile: lo[16], hi[16]
   const int4* chunks;            // trace chunks (tile begin, end, system)
   int nchunks;
+  int multi_chunk;               // some system spans more than FUSED_CHUNKS trace chunks
   int n_th, n_tc, n_thc, n_tw;   // tile counts
   GroupView s1, s2, grad;         // grouped work lists of the three product steps
   // FP64 masters
@@ -50,7 +52,6 @@ struct Bufs {   // every device buffer the iteration kernels touch
   void *Hl, *Sl, *Cl, *Dl, *HCl, *SCl, *H0l, *S0l;
   float *HDf, *SDf, *Xf, *Yf, *S2f, *H2f;
   double *tpart, *gpart;         // trace partials (nchunks x NSUM), gradient partials (n_tc x 2)
-  int* ticket;                   // per-system workgroup tickets of the trace kernel (zero between launches)
   SysInfo* info;
   SysState* st;
   double* hist;
@@ -62,10 +63,12 @@ struct Bufs {   // every device buffer the iteration kernels touch
 // one CG iteration step (all systems whose phase matches `mask`), arithmetic `prec`
 void launch_s1(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init, bool filter);
 void launch_s2(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init, bool filter);
-// traces of the n x n products and, in the last workgroup of each system, the
+// the 15 trace sums (init_inputs: of H0 and S0 alone) and from them the
 // line-search step (mode LS_STEP), the initial energy (LS_INIT) or the electron count (LS_REPORT)
-void launch_traces_ls(hipStream_t s, const Bufs& b, Prec prec, int mask, int mode, const CGParams& prm);
-void launch_update(hipStream_t s, const Bufs& b, Prec prec, int mask);   // C, HC, SC, H_W, S_W
+void launch_traces(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init_inputs, int mode,
+                   const CGParams& prm);
+// C, HC, SC, H_W, S_W with the step (solved in place for systems of at most FUSED_CHUNKS trace chunks)
+void launch_update(hipStream_t s, const Bufs& b, Prec prec, int mask, const CGParams& prm);
 void launch_grad(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init);
 void launch_beta(hipStream_t s, const Bufs& b, int mask, bool init, const CGParams& prm);
 void launch_update_d(hipStream_t s, const Bufs& b, Prec prec, int mask);
@@ -75,6 +78,8 @@ void launch_cast_hs(hipStream_t s, const Bufs& b, Prec prec);                // 
 
 // linesearch modes
 enum { LS_STEP = 0, LS_INIT = 1, LS_REPORT = 2 };
+// systems with at most this many trace chunks solve the line search inside the update kernel
+constexpr int FUSED_CHUNKS = 16;
 
 // density matrix: CM = C (2I - S0) on the CM plan, rho = 2 CM C^T on the H pattern
 void launch_cm(hipStream_t s, PlanView p, const int* orow, const int* brow_sys, int sys, const double* C,

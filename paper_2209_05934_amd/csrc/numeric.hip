@@ -6,7 +6,7 @@
 //   direction products   HD = H D, SD = S D                       (k_s1)
 //   n x n projections    X = C^T SD, Y = C^T HD, S2 = D^T SD, H2 = D^T HD  (k_s2)
 //   FP64 traces          15 Frobenius/trace sums -> quartic c0..c4 (k_traces)
-//   exact line search    first minimum of E~(C + xD) = sum c_k x^k  (k_linesearch)
+//   exact line search    first minimum of E~(C + xD) = sum c_k x^k  (in k_update)
 //   updates              C, HC, SC += x (D, HD, SD);  H0, S0 += x(Y+Y^T, X+X^T) + x^2 (H2, S2)
 //   gradient             G = P_C[8 HC - 4 (HC S0 + SC H0)]  (kept on C's pattern)  (k_grad)
 //   CG update            beta = max(0, <G, G - G_old>/<G_old, G_old>), D = -G + beta D  (k_beta, k_update_d)
@@ -15,318 +15,20 @@
 // follows from Eq. 3-4.  Tile products run on MFMA (FP64, FP32, or BF16 with
 // FP32 accumulation); every reduction feeding the line search is FP64 in a
 // fixed order.
-#include <type_traits>
+#include <cfloat>
 
-#include "kernels.hpp"
-#include "tile_ops.hpp"
+#include "tile_sched.hpp"
 
 namespace omm {
 
 namespace {
 
-template <Prec P> struct PT;
-template <> struct PT<P64> { typedef double TI; typedef double TO; };
-template <> struct PT<P32> { typedef float TI; typedef float TO; };
-template <> struct PT<PBF> { typedef bf16 TI; typedef float TO; };
-
-__device__ __forceinline__ bool on(const SysState* __restrict__ st, int s, int mask) {
-  return (st[s].phase & mask) != 0;
-}
-
-// Zero every atom block of the accumulator tile whose Frobenius norm^2 < eps2
-// (filtering of Sec. V).  Row/column segments give, for each tile row/column,
-// the [lo, hi) range of its block inside the tile; rseg == nullptr means the
-// whole tile height is one block.  Uniform shuffles, fixed summation order.
-template <typename V>
-__device__ void filter_tile(V& acc, int lane, const uint8_t* __restrict__ rseg,
-                            const uint8_t* __restrict__ cseg, double eps2) {
-  const int j = lane & 15, q = lane >> 4;
-  const int clo = cseg[j], chi = cseg[16 + j];
-  double rowpart[4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const double sq = (double)acc[r] * (double)acc[r];
-    double sum = 0.0;
-    for (int c = 0; c < 16; ++c) {
-      const double v = __shfl(sq, c + 16 * q, 64);
-      if (c >= clo && c < chi) sum += v;
-    }
-    rowpart[r] = sum;
-  }
-  double tot[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int qq = 0; qq < 4; ++qq) {
-#pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
-      const double v = __shfl(rowpart[rr], j + 16 * qq, 64);
-      const int rho = Lay<V>::row(qq, rr);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = Lay<V>::row(q, r);
-        const bool in = rseg ? (rho >= rseg[row] && rho < rseg[16 + row]) : true;
-        if (in) tot[r] += v;
-      }
-    }
-  }
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-    if (tot[r] < eps2) acc[r] = 0;
-}
-
-// Work distribution of the tile-product kernels.  A workgroup holds NW = max(4, KS)
-// waves; KS consecutive waves split the pair list of one output tile into KS
-// contiguous chunks and add their accumulators in a fixed tree through LDS, so
-// results are bitwise reproducible for a given KS.  Logical block ids are
-// renumbered so that consecutive ids (neighbouring output tiles, which share
-// operand tiles) run on the same XCD: the hardware deals workgroups to the 8
-// XCDs round-robin.
-__device__ __forceinline__ int xcd_block() {
-  const int nb = gridDim.x, b = blockIdx.x;
-  const int x = b & 7, q = nb >> 3, r = nb & 7;
-  return x * q + min(x, r) + (b >> 3);
-}
-
-template <int KS> struct Split {
-  static constexpr int NW = KS > 4 ? KS : 4;     // waves per workgroup
-  static constexpr int G = NW / KS;              // output tiles per workgroup
-  static constexpr int RED = KS > 1 ? NW / 2 : 1;   // LDS slots of the reduction tree
-};
-
-template <int KS, int NACC, typename V>
-__device__ __forceinline__ void ks_reduce(V (&acc)[NACC], V* buf, int grp, int wk, int lane) {
-  if (KS == 1) return;
-#pragma unroll
-  for (int stride = KS / 2; stride >= 1; stride >>= 1) {
-    if (wk >= stride && wk < 2 * stride) {
-#pragma unroll
-      for (int a = 0; a < NACC; ++a) buf[((grp * (KS / 2) + wk - stride) * NACC + a) * 64 + lane] = acc[a];
-    }
-    __syncthreads();
-    if (wk < stride) {
-#pragma unroll
-      for (int a = 0; a < NACC; ++a) acc[a] += buf[((grp * (KS / 2) + wk) * NACC + a) * 64 + lane];
-    }
-    __syncthreads();
-  }
-}
-
-// chunk [b, e) of group g's entry list handled by split-wave wk
-__device__ __forceinline__ void ks_chunk(const GroupView& P, int g, int wk, int KS, int64_t& b, int64_t& e) {
-  const int64_t p0 = P.gp[g], n = P.gp[g + 1] - p0;
-  b = p0 + (n * wk) / KS;
-  e = p0 + (n * (wk + 1)) / KS;
-}
-
-// ------------------------------------------------------------------ S1: HD = H D, SD = S D
-// One wave-group per group of NT output tiles in one row of the HC pattern:
-// per k the H and S tiles are loaded once and multiply NT tiles of D.
-template <typename TI, typename TO, int KS, int NT>
-__global__ __launch_bounds__(Split<KS>::NW * 64) void k_s1(
-    GroupView P, const int* __restrict__ orow, const int* __restrict__ ocol, const int* __restrict__ brow_sys,
-    const SysInfo* __restrict__ info, const SysState* __restrict__ st, int mask, const TI* __restrict__ Hm,
-    const TI* __restrict__ Sm, const TI* __restrict__ Bm, TO* __restrict__ O1, TO* __restrict__ O2,
-    const int* __restrict__ hc_to_c, const uint8_t* __restrict__ wseg) {
-  typedef typename Acc<TI>::V V;
-  typedef Split<KS> SP;
-  constexpr int W = 1 + NT;
-  __shared__ V red[SP::RED * 2 * NT * 64];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int grp = wave / KS, wk = wave - grp * KS;
-  const int g = xcd_block() * SP::G + grp;
-  bool act = g < P.ngroups;
-  int s = 0, o0 = 0, cnt = 0;
-  if (act) {
-    o0 = P.go0[g];
-    cnt = P.gn[g];
-    s = brow_sys[orow[o0]];
-    act = on(st, s, mask);
-  }
-  const bool ident = act && info[s].ident_s != 0;
-  V acc[2 * NT];
-#pragma unroll
-  for (int a = 0; a < 2 * NT; ++a) acc[a] = vzero<V>();
-  if (act) {
-    int64_t b, e;
-    ks_chunk(P, g, wk, KS, b, e);
-    if (b < e) {
-      Frag<TI> fh, fs, fb[NT];
-      int bi[NT];
-      {
-        const int* en = P.ent + b * W;
-        ld_row(fh, Hm + (size_t)en[0] * TE, lane);
-        if (!ident) ld_row(fs, Sm + (size_t)en[0] * TE, lane);
-#pragma unroll
-        for (int u = 0; u < NT; ++u) {
-          bi[u] = en[1 + u];
-          if (bi[u] >= 0) ld_col(fb[u], Bm + (size_t)bi[u] * TE, lane);
-        }
-      }
-      for (int64_t p = b; p < e; ++p) {
-        const int* nx = P.ent + (p + 1 < e ? p + 1 : p) * W;   // prefetch the next entry
-        Frag<TI> nh, ns, nb[NT];
-        int ni[NT];
-        ld_row(nh, Hm + (size_t)nx[0] * TE, lane);
-        if (!ident) ld_row(ns, Sm + (size_t)nx[0] * TE, lane);
-#pragma unroll
-        for (int u = 0; u < NT; ++u) {
-          ni[u] = nx[1 + u];
-          if (ni[u] >= 0) ld_col(nb[u], Bm + (size_t)ni[u] * TE, lane);
-        }
-#pragma unroll
-        for (int u = 0; u < NT; ++u) {
-          if (bi[u] >= 0) {
-            mma(acc[u], fh, fb[u]);
-            if (!ident) mma(acc[NT + u], fs, fb[u]);
-          }
-        }
-        fh = nh;
-        fs = ns;
-#pragma unroll
-        for (int u = 0; u < NT; ++u) {
-          fb[u] = nb[u];
-          bi[u] = ni[u];
-        }
-      }
-    }
-  }
-  ks_reduce<KS, 2 * NT>(acc, red, grp, wk, lane);
-  if (!act || wk != 0) return;
-  const double e2 = info[s].eps2;
-#pragma unroll
-  for (int u = 0; u < NT; ++u) {
-    if (u >= cnt) break;
-    const int t = o0 + u;
-    V a1 = acc[u], a2 = acc[NT + u];
-    if (ident) {   // S = I: S B is B's own tile
-      typedef typename Acc<TI>::S AS;
-      const int ct = hc_to_c[t];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) a2[r] = ct >= 0 ? cvt<AS, TI>(Bm[(size_t)ct * TE + out_off<V>(lane, r)]) : (AS)0;
-    }
-    if (e2 > 0.0) {
-      const uint8_t* cs = wseg + 32 * (size_t)ocol[t];
-      filter_tile(a1, lane, nullptr, cs, e2);
-      filter_tile(a2, lane, nullptr, cs, e2);
-    }
-    TO* o1 = O1 + (size_t)t * TE;
-    TO* o2 = O2 + (size_t)t * TE;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      o1[out_off<V>(lane, r)] = (TO)a1[r];
-      o2[out_off<V>(lane, r)] = (TO)a2[r];
-    }
-  }
-}
-
-// ------------------------------------------------------------------ S2: n x n projections
-// Groups of NT output tiles in one row g of the n x n pattern: per basis tile b
-// the C(b,g) and D(b,g) tiles are loaded once for NT tiles of HD and SD.
-template <typename TI, typename TM, typename TO, int NPROD, int KS, int NT>
-__global__ __launch_bounds__(Split<KS>::NW * 64) void k_s2(
-    GroupView P, const int* __restrict__ orow, const int* __restrict__ ocol, const int* __restrict__ wrow_sys,
-    const SysInfo* __restrict__ info, const SysState* __restrict__ st, int mask, const TI* __restrict__ Cm,
-    const TI* __restrict__ Dm, const TM* __restrict__ HDm, const TM* __restrict__ SDm, TO* __restrict__ X,
-    TO* __restrict__ Y, TO* __restrict__ S2o, TO* __restrict__ H2o, const uint8_t* __restrict__ wseg) {
-  typedef typename Acc<TI>::V V;
-  typedef Split<KS> SP;
-  constexpr int W = 1 + NT;
-  __shared__ V red[SP::RED * NPROD * NT * 64];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int grp = wave / KS, wk = wave - grp * KS;
-  const int g = xcd_block() * SP::G + grp;
-  bool act = g < P.ngroups;
-  int s = 0, o0 = 0, cnt = 0;
-  if (act) {
-    o0 = P.go0[g];
-    cnt = P.gn[g];
-    s = wrow_sys[orow[o0]];
-    act = on(st, s, mask);
-  }
-  V acc[NPROD * NT];
-#pragma unroll
-  for (int a = 0; a < NPROD * NT; ++a) acc[a] = vzero<V>();
-  if (act) {
-    int64_t b, e;
-    ks_chunk(P, g, wk, KS, b, e);
-    if (b < e) {
-      Frag<TI> fc, fd, fhd[NT], fsd[NT];
-      int bi[NT];
-      {
-        const int* en = P.ent + b * W;
-        ld_col(fc, Cm + (size_t)en[0] * TE, lane);                 // A = C^T
-        if (NPROD == 4) ld_col(fd, Dm + (size_t)en[0] * TE, lane);  // A = D^T
-#pragma unroll
-        for (int u = 0; u < NT; ++u) {
-          bi[u] = en[1 + u];
-          if (bi[u] >= 0) {
-            ld_col(fhd[u], HDm + (size_t)bi[u] * TE, lane);
-            ld_col(fsd[u], SDm + (size_t)bi[u] * TE, lane);
-          }
-        }
-      }
-      for (int64_t p = b; p < e; ++p) {
-        const int* nx = P.ent + (p + 1 < e ? p + 1 : p) * W;
-        Frag<TI> nc, nd, nhd[NT], nsd[NT];
-        int ni[NT];
-        ld_col(nc, Cm + (size_t)nx[0] * TE, lane);
-        if (NPROD == 4) ld_col(nd, Dm + (size_t)nx[0] * TE, lane);
-#pragma unroll
-        for (int u = 0; u < NT; ++u) {
-          ni[u] = nx[1 + u];
-          if (ni[u] >= 0) {
-            ld_col(nhd[u], HDm + (size_t)ni[u] * TE, lane);
-            ld_col(nsd[u], SDm + (size_t)ni[u] * TE, lane);
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < NT; ++u) {
-          if (bi[u] >= 0) {
-            mma(acc[u], fc, fsd[u]);
-            mma(acc[NT + u], fc, fhd[u]);
-            if (NPROD == 4) {
-              mma(acc[2 * NT + u], fd, fsd[u]);
-              mma(acc[3 * NT + u], fd, fhd[u]);
-            }
-          }
-        }
-        fc = nc;
-        fd = nd;
-#pragma unroll
-        for (int u = 0; u < NT; ++u) {
-          fhd[u] = nhd[u];
-          fsd[u] = nsd[u];
-          bi[u] = ni[u];
-        }
-      }
-    }
-  }
-  ks_reduce<KS, NPROD * NT>(acc, red, grp, wk, lane);
-  if (!act || wk != 0) return;
-  const double e2 = info[s].eps2;
-#pragma unroll
-  for (int u = 0; u < NT; ++u) {
-    if (u >= cnt) break;
-    const int t = o0 + u;
-    if (e2 > 0.0) {
-      const uint8_t* rs = wseg + 32 * (size_t)orow[t];
-      const uint8_t* cs = wseg + 32 * (size_t)ocol[t];
-#pragma unroll
-      for (int a = 0; a < NPROD; ++a) filter_tile(acc[a * NT + u], lane, rs, cs, e2);
-    }
-    const size_t o = (size_t)t * TE;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int e = out_off<V>(lane, r);
-      X[o + e] = (TO)acc[u][r];
-      Y[o + e] = (TO)acc[NT + u][r];
-      if (NPROD == 4) {
-        S2o[o + e] = (TO)acc[2 * NT + u][r];
-        H2o[o + e] = (TO)acc[3 * NT + u][r];
-      }
-    }
-  }
-}
-
-// ------------------------------------------------------------------ line search (scalar, one thread per system)
+// ------------------------------------------------------------------ line search (one wave per system)
+// Every lane holds the same coefficients and takes the same branches.  A root
+// bracket shrinks 64-fold per round: lane l evaluates p' at the l-th of 64
+// points and a ballot finds the first point at or past the root, so the step
+// costs about ten polynomial evaluations instead of a serial Newton chain of
+// FP64 divisions.
 __device__ __forceinline__ double pval(const double* c, double x) {
   return c[0] + x * (c[1] + x * (c[2] + x * (c[3] + x * c[4])));
 }
@@ -336,32 +38,46 @@ __device__ __forceinline__ double dp(const double* c, double x) {
 __device__ __forceinline__ double d2p(const double* c, double x) {
   return 2.0 * c[2] + x * (6.0 * c[3] + x * 12.0 * c[4]);
 }
+// 1/d: hardware reciprocal refined by one Newton step
+__device__ __forceinline__ double rcp64(double d) {
+  const double r = __builtin_amdgcn_rcp(d);
+  return fma(r, fma(-d, r, 1.0), r);
+}
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+// first lane whose predicate holds (64 when none)
+__device__ __forceinline__ int first_lane(bool p) {
+  const unsigned long long m = __ballot(p);
+  return m ? __builtin_ctzll(m) : 64;
+}
 
-// root of p' in (lo, hi] given p'(lo) < 0 <= p'(hi): safeguarded Newton + bisection
-__device__ double bracket_root(const double* c, double lo, double hi) {
-  double x = 0.5 * (lo + hi);
-  for (int it = 0; it < 300; ++it) {
-    const double f = dp(c, x);
-    if (f == 0.0) return x;
-    if (f < 0.0) lo = x; else hi = x;
-    const double d = d2p(c, x);
-    double xn = (d > 0.0) ? x - f / d : 0.5 * (lo + hi);
-    if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
-    if (fabs(xn - x) <= 1e-16 * fabs(x) || hi - lo <= 2e-16 * hi) { x = xn; break; }
-    x = xn;
+// root of p' in (lo, hi] given p'(lo) < 0 <= p'(hi), p' increasing there
+__device__ double root_wave(const double* c, double lo, double hi, int lane) {
+  for (int it = 0; it < 16 && hi - lo > 4.0 * DBL_EPSILON * hi; ++it) {
+    const double w = hi - lo;
+    const double xl = lane == 63 ? hi : fma(w, (double)(lane + 1) * (1.0 / 64.0), lo);
+    int f = first_lane(dp(c, xl) >= 0.0);
+    if (f == 64) f = 63;   // p'(hi) >= 0 is kept as an invariant; guard all the same
+    const double nhi = readlane_d(xl, f);
+    const double nlo = f == 0 ? lo : readlane_d(xl, f - 1);
+    lo = nlo;
+    hi = nhi;
   }
-  for (int k = 0; k < 2; ++k) {   // Newton polish
-    const double d = d2p(c, x);
-    if (!(d > 0.0)) break;
-    const double xn = x - dp(c, x) / d;
-    if (!(xn > 0.0)) break;
-    x = xn;
+  double x = 0.5 * (lo + hi);
+  const double d = d2p(c, x);
+  if (d > 0.0) {   // one Newton step inside the final bracket
+    const double xn = x - dp(c, x) * rcp64(d);
+    if (xn > lo && xn <= hi) x = xn;
   }
   return x;
 }
 
 // first minimum of p along x > 0 (p'(0) = c1 < 0); false when there is none
-__device__ bool line_min(const double* c, double& xs) {
+__device__ bool line_min_wave(const double* c, double& xs, int lane) {
   if (!(c[1] < 0.0)) return false;
   // critical points of p' : roots of p'' = 12 c4 x^2 + 6 c3 x + 2 c2
   const double A = 12.0 * c[4], B = 6.0 * c[3], Cq = 2.0 * c[2];
@@ -372,11 +88,11 @@ __device__ bool line_min(const double* c, double& xs) {
     if (disc >= 0.0) {
       const double sq = sqrt(disc);
       const double tq = -0.5 * (B + copysign(sq, B));
-      if (tq != 0.0) { r[nr++] = tq / A; r[nr++] = Cq / tq; }
+      if (tq != 0.0) { r[nr++] = tq * rcp64(A); r[nr++] = Cq * rcp64(tq); }
       else r[nr++] = 0.0;
     }
   } else if (B != 0.0) {
-    r[nr++] = -Cq / B;
+    r[nr++] = -Cq * rcp64(B);
   }
   if (nr == 2 && r[1] < r[0]) { const double tmp = r[0]; r[0] = r[1]; r[1] = tmp; }
   double lo = 0.0;
@@ -384,7 +100,7 @@ __device__ bool line_min(const double* c, double& xs) {
     const double b = r[k];
     if (!(b > lo)) continue;
     if (dp(c, b) >= 0.0) {
-      const double x = bracket_root(c, lo, b);
+      const double x = root_wave(c, lo, b, lane);
       if (d2p(c, x) > 0.0) { xs = x; return true; }
     }
     lo = b;
@@ -392,32 +108,44 @@ __device__ bool line_min(const double* c, double& xs) {
   // last, unbounded interval: sign of p' at +infinity
   const double lead = c[4] != 0.0 ? c[4] : (c[3] != 0.0 ? c[3] : (c[2] != 0.0 ? c[2] : c[1]));
   if (!(lead > 0.0)) return false;
-  double hi = lo > 0.0 ? 2.0 * lo : 1.0;
-  int guard = 0;
-  while (dp(c, hi) < 0.0) {
-    lo = hi;
-    hi *= 2.0;
-    if (++guard > 2000 || !isfinite(hi)) return false;
+  // 64 doublings per round from lo (or from 2^-40 when lo = 0), at most 32 rounds
+  double base = lo > 0.0 ? lo : 0x1p-40;
+  double hi = 0.0;
+  for (int round = 0; round < 32; ++round) {
+    const double xl = ldexp(base, lane + 1);
+    const int f = first_lane(dp(c, xl) >= 0.0);
+    if (f < 64) {
+      hi = readlane_d(xl, f);
+      if (f > 0) lo = readlane_d(xl, f - 1);
+      break;
+    }
+    lo = readlane_d(xl, 63);
+    base = lo;
+    if (!isfinite(base)) return false;
   }
-  const double x = bracket_root(c, lo, hi);
+  if (!(hi > 0.0)) return false;
+  const double x = root_wave(c, lo, hi, lane);
   if (!(d2p(c, x) > 0.0)) return false;
   xs = x;
   return true;
 }
 
-// quartic coefficients from the 15 sums, then the step (one thread)
-__device__ void ls_finish(SysState& S, const double* a, int mode, int refine_iters) {
-  double c[5];
+// quartic coefficients c0..c4 of E~(C + xD) and the electron count from the 15 sums
+__device__ __forceinline__ void quartic_of(const double* a, double* c, double& ne) {
   c[0] = 4.0 * a[0] - 2.0 * a[3];
   c[1] = 8.0 * a[1] - 4.0 * a[4] - 4.0 * a[5];
   c[2] = 4.0 * a[2] - 2.0 * (a[6] + 2.0 * a[7] + 2.0 * a[8] + a[9]);
   c[3] = -4.0 * a[10] - 4.0 * a[11];
   c[4] = -2.0 * a[12];
-  const double ne = 4.0 * a[13] - 2.0 * a[14];
+  ne = 4.0 * a[13] - 2.0 * a[14];
+}
+
+// records in the state of one system the quartic c, the electron count ne and
+// the line-search outcome (ok, x) of mode LS_STEP, or the initial energy
+// (LS_INIT) or electron count (LS_REPORT); one thread
+__device__ void ls_apply(SysState& S, const double* c, double ne, bool ok, double x, int mode, int refine_iters) {
   if (mode == LS_REPORT) { S.ne = ne; return; }
   if (mode == LS_INIT) { S.E = c[0]; S.E_prev = c[0]; S.ne = ne; return; }
-  double x = 0.0;
-  const bool ok = line_min(c, x);
   if (!ok) {
     if (S.steepest) {
       if (S.phase == PH_LOW) {            // low-precision noise: finish in FP64
@@ -448,39 +176,53 @@ __device__ void ls_finish(SysState& S, const double* a, int mode, int refine_ite
 // ------------------------------------------------------------------ FP64 traces
 // sums: 0 Tr H0, 1 Tr Y, 2 Tr H2, 3 <S0,H0>, 4 <S0,Y>, 5 <X,H0>, 6 <S0,H2>, 7 <X,Y>,
 //       8 <X,Y^T>, 9 <S2,H0>, 10 <X,H2>, 11 <S2,Y>, 12 <S2,H2>, 13 Tr S0, 14 <S0,S0>
-// Every workgroup reduces a chunk of n x n tiles of one system; the last
-// workgroup of a system to finish (integer ticket, release/acquire fences) sums
-// the system's chunk partials in chunk order and takes the line-search step.
+// Every workgroup reduces a chunk of n x n tiles of one system, one tile per
+// wave at a time (each lane holds four consecutive elements of one tile row),
+// into one partial per sum; the partials of a system are added in chunk order
+// by sum_partials wherever the quartic is needed.  A tile is on the block
+// diagonal exactly when its transpose is itself.
 template <typename TN>
-__global__ __launch_bounds__(256) void k_traces(const int4* __restrict__ chunks, const SysInfo* __restrict__ info,
-                                              SysState* __restrict__ st, int mask, const int* __restrict__ wrow,
-                                              const int* __restrict__ wcol, const int* __restrict__ wtr,
+__global__ __launch_bounds__(256) void k_traces(const int4* __restrict__ chunks, const SysState* __restrict__ st,
+                                              int mask, const int* __restrict__ wtr,
                                               const double* __restrict__ H0, const double* __restrict__ S0,
                                               const TN* __restrict__ X, const TN* __restrict__ Y,
                                               const TN* __restrict__ S2, const TN* __restrict__ H2,
-                                              double* __restrict__ part, int* __restrict__ ticket, int mode,
-                                              int refine_iters) {
+                                              double* __restrict__ part) {
   __shared__ double red[4][NSUM];
-  __shared__ int last;
   const int4 ch = chunks[blockIdx.x];
   if (!on(st, ch.z, mask)) return;
   double a[NSUM];
 #pragma unroll
   for (int k = 0; k < NSUM; ++k) a[k] = 0.0;
-  const int e = threadIdx.x, r = e >> 4, c = e & 15;
-  for (int t = ch.x; t < ch.y; ++t) {
-    const size_t o = (size_t)t * TE + e;
-    const double h0 = H0[o], s0 = S0[o];
-    const double x = (double)X[o], y = (double)Y[o], s2 = (double)S2[o], h2 = (double)H2[o];
-    const double yt = (double)Y[(size_t)wtr[t] * TE + c * 16 + r];
-    if (r == c && wrow[t] == wcol[t]) {
-      a[0] += h0; a[1] += y; a[2] += h2; a[13] += s0;
+  const int lane = threadIdx.x & 63, wv = wave_id();
+  const int r = lane >> 2, c0 = (lane & 3) * 4;   // row r, columns c0 .. c0 + 3
+#pragma unroll 2
+  for (int t = ch.x + wv; t < ch.y; t += 4) {
+    const int tt = wtr[t];
+    const size_t o = (size_t)t * TE + r * 16 + c0;
+    const size_t ot = (size_t)tt * TE + c0 * 16 + r;
+    const bool diag = tt == t && r >= c0 && r < c0 + 4;
+    double h0[4], s0[4], x[4], y[4], s2[4], h2[4], yt[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      h0[i] = H0[o + i];
+      s0[i] = S0[o + i];
+      x[i] = (double)X[o + i];
+      y[i] = (double)Y[o + i];
+      s2[i] = (double)S2[o + i];
+      h2[i] = (double)H2[o + i];
+      yt[i] = (double)Y[ot + 16 * i];
     }
-    a[3] += s0 * h0; a[4] += s0 * y; a[5] += x * h0; a[6] += s0 * h2; a[7] += x * y;
-    a[8] += x * yt; a[9] += s2 * h0; a[10] += x * h2; a[11] += s2 * y; a[12] += s2 * h2;
-    a[14] += s0 * s0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (diag && c0 + i == r) {
+        a[0] += h0[i]; a[1] += y[i]; a[2] += h2[i]; a[13] += s0[i];
+      }
+      a[3] += s0[i] * h0[i]; a[4] += s0[i] * y[i]; a[5] += x[i] * h0[i]; a[6] += s0[i] * h2[i];
+      a[7] += x[i] * y[i]; a[8] += x[i] * yt[i]; a[9] += s2[i] * h0[i]; a[10] += x[i] * h2[i];
+      a[11] += s2[i] * y[i]; a[12] += s2[i] * h2[i]; a[14] += s0[i] * s0[i];
+    }
   }
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < NSUM; ++k) {
     const double v = wave_sum(a[k]);
@@ -491,45 +233,54 @@ __global__ __launch_bounds__(256) void k_traces(const int4* __restrict__ chunks,
     const int k = threadIdx.x;
     part[(size_t)blockIdx.x * NSUM + k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
   }
-  __threadfence();
-  __syncthreads();
-  const int sy = ch.z;
-  if (threadIdx.x == 0) {
-    const int total = info[sy].ch1 - info[sy].ch0;
-    last = (atomicAdd(&ticket[sy], 1) == total - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-#pragma unroll
-  for (int k = 0; k < NSUM; ++k) a[k] = 0.0;
-  for (int c2 = info[sy].ch0 + threadIdx.x; c2 < info[sy].ch1; c2 += blockDim.x) {
-#pragma unroll
-    for (int k = 0; k < NSUM; ++k) a[k] += __builtin_nontemporal_load(&part[(size_t)c2 * NSUM + k]);
-  }
-#pragma unroll
-  for (int k = 0; k < NSUM; ++k) {
-    const double v = wave_sum(a[k]);
-    if (lane == 0) red[wv][k] = v;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double tot[NSUM];
-#pragma unroll
-    for (int k = 0; k < NSUM; ++k) tot[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
-    ls_finish(st[sy], tot, mode, refine_iters);
-    ticket[sy] = 0;
-  }
 }
 
-// ------------------------------------------------------------------ updates (one launch)
-// blocks [0, nc): C tiles; [nc, nc + nhc): HC/SC tiles; the rest: n x n tiles
+// The 15 sums of one system in every lane of the calling wave: lane l adds
+// chunks ch0 + l, ch0 + l + 64, ... in order, then a butterfly over the wave.
+__device__ __forceinline__ void sum_partials(const double* __restrict__ part, int ch0, int ch1, int lane,
+                                             double (&a)[NSUM]) {
+#pragma unroll
+  for (int k = 0; k < NSUM; ++k) a[k] = 0.0;
+  for (int c = ch0 + lane; c < ch1; c += 64) {
+#pragma unroll
+    for (int k = 0; k < NSUM; ++k) a[k] += part[(size_t)c * NSUM + k];
+  }
+#pragma unroll
+  for (int k = 0; k < NSUM; ++k) a[k] = wave_sum(a[k]);
+}
+
+// line-search step (LS_STEP; systems whose step the update kernel does not
+// solve itself), initial energy (LS_INIT) or electron count (LS_REPORT):
+// one wave per system
+__global__ __launch_bounds__(64) void k_ls_state(const SysInfo* __restrict__ info, SysState* __restrict__ st,
+                                                int mask, const double* __restrict__ part, int mode,
+                                                int refine_iters) {
+  const int s = blockIdx.x;
+  const int ch0 = info[s].ch0, ch1 = info[s].ch1;
+  if ((mode == LS_STEP && ch1 - ch0 <= FUSED_CHUNKS) || !on(st, s, mask)) return;
+  double a[NSUM];
+  sum_partials(part, ch0, ch1, threadIdx.x, a);
+  double c[5], ne, x = 0.0;
+  quartic_of(a, c, ne);
+  const bool ok = mode == LS_STEP && line_min_wave(c, x, threadIdx.x);
+  if (threadIdx.x == 0) ls_apply(st[s], c, ne, ok, x, mode, refine_iters);
+}
+
+// ------------------------------------------------------------------ line search + updates (one launch)
+// One wave per tile of the concatenated list [C tiles | HC/SC tiles | n x n
+// tiles]; each lane holds four consecutive elements of one tile row.  For a
+// system of at most FUSED_CHUNKS trace chunks every wave adds the chunk
+// partials and solves the line search itself (same inputs, same operations:
+// the same step in every wave, and its operand loads overlap the search); the
+// wave of the system's first C tile records the step in the state.  The state
+// changes phase only when the step is zero, so waves that read the phase
+// before or after that write do the same (nothing).  Larger systems take the
+// step k_ls_state left in the state.
 template <typename TL, typename TM, bool LOW>
-__global__ __launch_bounds__(256) void k_update(int nc, int nhc, const int* __restrict__ tc_row,
-                                              const int* __restrict__ thc_row, const int* __restrict__ tw_row,
-                                              const int* __restrict__ brow_sys, const int* __restrict__ wrow_sys,
-                                              const int* __restrict__ wtr, const SysState* __restrict__ st,
-                                              int mask, double* __restrict__ C, const double* __restrict__ D,
+__global__ __launch_bounds__(256) void k_update(int nc, int nhc, int ntot, const int* __restrict__ upd_sys,
+                                              const int* __restrict__ wtr, const SysInfo* __restrict__ info,
+                                              SysState* __restrict__ st, int mask, const double* __restrict__ part,
+                                              int refine_iters, double* __restrict__ C, const double* __restrict__ D,
                                               TL* __restrict__ Cl, double* __restrict__ HC, double* __restrict__ SC,
                                               const TM* __restrict__ HD, const TM* __restrict__ SD,
                                               TL* __restrict__ HCl, TL* __restrict__ SCl, double* __restrict__ H0,
@@ -537,48 +288,77 @@ __global__ __launch_bounds__(256) void k_update(int nc, int nhc, const int* __re
                                               const TM* __restrict__ Y, const TM* __restrict__ S2,
                                               const TM* __restrict__ H2, TL* __restrict__ H0l,
                                               TL* __restrict__ S0l) {
-  const int b = blockIdx.x;
-  const int e = threadIdx.x;
-  if (b < nc) {
-    const int s = brow_sys[tc_row[b]];
-    if (!on(st, s, mask)) return;
-    const double x = st[s].x;
-    if (x == 0.0) return;
-    const size_t o = (size_t)b * TE + e;
-    const double v = C[o] + x * D[o];
-    C[o] = v;
-    if (LOW) Cl[o] = cvt<TL, double>(v);
-  } else if (b < nc + nhc) {
-    const int t = b - nc;
-    const int s = brow_sys[thc_row[t]];
-    if (!on(st, s, mask)) return;
-    const double x = st[s].x;
-    if (x == 0.0) return;
-    const size_t o = (size_t)t * TE + e;
-    const double h = HC[o] + x * (double)HD[o];
-    const double g = SC[o] + x * (double)SD[o];
-    HC[o] = h;
-    SC[o] = g;
-    if (LOW) {
-      HCl[o] = cvt<TL, double>(h);
-      SCl[o] = cvt<TL, double>(g);
+  const int T = blockIdx.x * 4 + wave_id();
+  if (T >= ntot) return;
+  const int lane = threadIdx.x & 63;
+  const int s = upd_sys[T];
+  if (!on(st, s, mask)) return;
+  const int ch0 = info[s].ch0, ch1 = info[s].ch1;
+  const int kind = T < nc ? 0 : (T < nc + nhc ? 1 : 2);
+  const int t = kind == 0 ? T : (kind == 1 ? T - nc : T - nc - nhc);
+  const int r = lane >> 2, c0 = (lane & 3) * 4;
+  const size_t o = (size_t)t * TE + r * 16 + c0;
+  // operands first: their loads overlap the line search
+  double u[4], v[4], p[4], q[4], w[4], z[4];
+  if (kind == 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { u[i] = C[o + i]; p[i] = D[o + i]; }
+  } else if (kind == 1) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      u[i] = HC[o + i]; v[i] = SC[o + i]; p[i] = (double)HD[o + i]; q[i] = (double)SD[o + i];
     }
   } else {
-    const int t = b - nc - nhc;
-    const int s = wrow_sys[tw_row[t]];
-    if (!on(st, s, mask)) return;
-    const double x = st[s].x;
-    if (x == 0.0) return;
-    const int r = e >> 4, c = e & 15;
-    const size_t o = (size_t)t * TE + e;
-    const size_t ot = (size_t)wtr[t] * TE + c * 16 + r;
-    const double h = H0[o] + x * ((double)Y[o] + (double)Y[ot]) + x * x * (double)H2[o];
-    const double g = S0[o] + x * ((double)X[o] + (double)X[ot]) + x * x * (double)S2[o];
-    H0[o] = h;
-    S0[o] = g;
-    if (LOW) {
-      H0l[o] = cvt<TL, double>(h);
-      S0l[o] = cvt<TL, double>(g);
+    const size_t ot = (size_t)wtr[t] * TE + c0 * 16 + r;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      u[i] = H0[o + i]; v[i] = S0[o + i];
+      p[i] = (double)Y[o + i] + (double)Y[ot + 16 * i];
+      q[i] = (double)X[o + i] + (double)X[ot + 16 * i];
+      w[i] = (double)H2[o + i]; z[i] = (double)S2[o + i];
+    }
+  }
+  double x = 0.0;
+  if (ch1 - ch0 <= FUSED_CHUNKS) {
+    double a[NSUM], cq[5], ne;
+    sum_partials(part, ch0, ch1, lane, a);
+    quartic_of(a, cq, ne);
+    const bool ok = line_min_wave(cq, x, lane);
+    if (T == info[s].c0 && lane == 0) ls_apply(st[s], cq, ne, ok, x, LS_STEP, refine_iters);
+    if (!ok) return;
+  } else {
+    x = st[s].x;
+  }
+  if (x == 0.0) return;
+  if (kind == 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double nv = u[i] + x * p[i];
+      C[o + i] = nv;
+      if (LOW) Cl[o + i] = cvt<TL, double>(nv);
+    }
+  } else if (kind == 1) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double h = u[i] + x * p[i], g = v[i] + x * q[i];
+      HC[o + i] = h;
+      SC[o + i] = g;
+      if (LOW) {
+        HCl[o + i] = cvt<TL, double>(h);
+        SCl[o + i] = cvt<TL, double>(g);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double h = u[i] + x * p[i] + x * x * w[i];
+      const double g = v[i] + x * q[i] + x * x * z[i];
+      H0[o + i] = h;
+      S0[o + i] = g;
+      if (LOW) {
+        H0l[o + i] = cvt<TL, double>(h);
+        S0l[o + i] = cvt<TL, double>(g);
+      }
     }
   }
 }
@@ -653,113 +433,6 @@ __global__ __launch_bounds__(256) void k_beta(const SysInfo* __restrict__ info, 
   gg = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
   go = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
   beta_finish(st[s], s, gg, go, init, hist, prm);
-}
-
-// ------------------------------------------------------------------ gradient on C's pattern
-// Groups of NT tiles of C's pattern in one basis row b: per k the HC(b,k) and
-// SC(b,k) tiles are loaded once for NT tiles of S_W and H_W.
-template <typename TI, int KS, int NT>
-__global__ __launch_bounds__(Split<KS>::NW * 64) void k_grad(
-    GroupView P, const int* __restrict__ tc_row, const int* __restrict__ brow_sys, const SysState* __restrict__ st,
-    int mask, const TI* __restrict__ HCm, const TI* __restrict__ SCm, const TI* __restrict__ S0m,
-    const TI* __restrict__ H0m, const double* __restrict__ HC, const int* __restrict__ c_in_hc,
-    const uint32_t* __restrict__ cmask, const double* __restrict__ Gold, double* __restrict__ G,
-    double* __restrict__ gpart) {
-  typedef typename Acc<TI>::V V;
-  typedef Split<KS> SP;
-  constexpr int W = 1 + NT;
-  __shared__ V red[SP::RED * NT * 64];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int grp = wave / KS, wk = wave - grp * KS;
-  const int g = xcd_block() * SP::G + grp;
-  bool act = g < P.ngroups;
-  int o0 = 0, cnt = 0;
-  if (act) {
-    o0 = P.go0[g];
-    cnt = P.gn[g];
-    act = on(st, brow_sys[tc_row[o0]], mask);
-  }
-  V acc[NT];
-#pragma unroll
-  for (int a = 0; a < NT; ++a) acc[a] = vzero<V>();
-  if (act) {
-    int64_t b, e;
-    ks_chunk(P, g, wk, KS, b, e);
-    if (b < e) {
-      Frag<TI> fh, fs, fw[NT], fv[NT];
-      int bi[NT];
-      {
-        const int* en = P.ent + b * W;
-        ld_row(fh, HCm + (size_t)en[0] * TE, lane);
-        ld_row(fs, SCm + (size_t)en[0] * TE, lane);
-#pragma unroll
-        for (int u = 0; u < NT; ++u) {
-          bi[u] = en[1 + u];
-          if (bi[u] >= 0) {
-            ld_col(fw[u], S0m + (size_t)bi[u] * TE, lane);
-            ld_col(fv[u], H0m + (size_t)bi[u] * TE, lane);
-          }
-        }
-      }
-      for (int64_t p = b; p < e; ++p) {
-        const int* nx = P.ent + (p + 1 < e ? p + 1 : p) * W;
-        Frag<TI> nh, ns, nw[NT], nv[NT];
-        int ni[NT];
-        ld_row(nh, HCm + (size_t)nx[0] * TE, lane);
-        ld_row(ns, SCm + (size_t)nx[0] * TE, lane);
-#pragma unroll
-        for (int u = 0; u < NT; ++u) {
-          ni[u] = nx[1 + u];
-          if (ni[u] >= 0) {
-            ld_col(nw[u], S0m + (size_t)ni[u] * TE, lane);
-            ld_col(nv[u], H0m + (size_t)ni[u] * TE, lane);
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < NT; ++u) {
-          if (bi[u] >= 0) {
-            mma(acc[u], fh, fw[u]);
-            mma(acc[u], fs, fv[u]);
-          }
-        }
-        fh = nh;
-        fs = ns;
-#pragma unroll
-        for (int u = 0; u < NT; ++u) {
-          fw[u] = nw[u];
-          fv[u] = nv[u];
-          bi[u] = ni[u];
-        }
-      }
-    }
-  }
-  ks_reduce<KS, NT>(acc, red, grp, wk, lane);
-  if (!act || wk != 0) return;
-  const int j = lane & 15, q = lane >> 4;
-#pragma unroll
-  for (int u = 0; u < NT; ++u) {
-    if (u >= cnt) break;
-    const int t = o0 + u;
-    const uint32_t mk = cmask[t];
-    const double* hc = HC + (size_t)c_in_hc[t] * TE;
-    double gg = 0.0, go = 0.0;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = Lay<V>::row(q, r);
-      const int e = row * 16 + j;
-      const bool in = ((mk >> row) & 1u) && ((mk >> (16 + j)) & 1u);
-      const double gv = in ? 8.0 * hc[e] - 4.0 * (double)acc[u][r] : 0.0;
-      G[(size_t)t * TE + e] = gv;
-      gg += gv * gv;
-      go += gv * Gold[(size_t)t * TE + e];
-    }
-    gg = wave_sum(gg);
-    go = wave_sum(go);
-    if (lane == 0) {
-      gpart[2 * (size_t)t] = gg;
-      gpart[2 * (size_t)t + 1] = go;
-    }
-  }
 }
 
 template <typename TL, bool LOW>
@@ -912,137 +585,41 @@ inline dim3 waves_grid(int n) { return dim3((unsigned)((n + 3) / 4)); }
 }  // namespace
 
 // =================================================================== launchers
-#define LAUNCH(kern, grid, block, stream, ...)                                   \
-  do {                                                                          \
-    hipLaunchKernelGGL(kern, grid, block, 0, stream, __VA_ARGS__);              \
-    OMM_HIP(hipGetLastError());                                                 \
-  } while (0)
-
-template <int KS> static dim3 grid_for(int n) { return dim3((unsigned)((n + Split<KS>::G - 1) / Split<KS>::G)); }
-template <int KS> static dim3 block_for() { return dim3(Split<KS>::NW * 64); }
-
-// (NT, KS) dispatch: NT is 1 or the step's group width; KS in {1,2,4,8} (at most 4 when NT > 1)
-template <int NTG, typename F>
-static void nt_ks(int nt, int ks, F&& f) {
-  if (nt == 1) {
-    switch (ks) {
-      case 8: f(std::integral_constant<int, 1>{}, std::integral_constant<int, 8>{}); break;
-      case 4: f(std::integral_constant<int, 1>{}, std::integral_constant<int, 4>{}); break;
-      case 2: f(std::integral_constant<int, 1>{}, std::integral_constant<int, 2>{}); break;
-      default: f(std::integral_constant<int, 1>{}, std::integral_constant<int, 1>{}); break;
-    }
-  } else {
-    switch (ks) {
-      case 8:
-      case 4: f(std::integral_constant<int, NTG>{}, std::integral_constant<int, 4>{}); break;
-      case 2: f(std::integral_constant<int, NTG>{}, std::integral_constant<int, 2>{}); break;
-      default: f(std::integral_constant<int, NTG>{}, std::integral_constant<int, 1>{}); break;
-    }
-  }
-}
-
-template <typename TI, typename TO>
-static void s1_go(hipStream_t s, const Bufs& b, int mask, const TI* H, const TI* S, const TI* B, TO* O1, TO* O2) {
-  nt_ks<NT_S1>(b.s1.NT, b.ks[0], [&](auto ntc, auto ksc) {
-    constexpr int N_ = decltype(ntc)::value, K_ = decltype(ksc)::value;
-    LAUNCH((k_s1<TI, TO, K_, N_>), grid_for<K_>(b.s1.ngroups), block_for<K_>(), s, b.s1, b.thc_row, b.thc_col,
-           b.brow_sys, b.info, b.st, mask, H, S, B, O1, O2, b.hc_to_c, b.wseg);
-  });
-}
-
-void launch_s1(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init, bool filter) {
-  (void)filter;
-  if (b.s1.ngroups <= 0) return;
-  if (prec == P64) {
-    if (init) s1_go<double, double>(s, b, mask, b.H, b.S, b.C, b.HC, b.SC);
-    else s1_go<double, double>(s, b, mask, b.H, b.S, b.D, b.HD, b.SD);
-  } else if (prec == P32) {
-    s1_go<float, float>(s, b, mask, (const float*)b.Hl, (const float*)b.Sl, (const float*)b.Dl, b.HDf, b.SDf);
-  } else {
-    s1_go<bf16, float>(s, b, mask, (const bf16*)b.Hl, (const bf16*)b.Sl, (const bf16*)b.Dl, b.HDf, b.SDf);
-  }
-}
-
-template <typename TI, typename TM, typename TO, int NP>
-static void s2_go(hipStream_t s, const Bufs& b, int mask, const TI* C, const TI* D, const TM* HD, const TM* SD,
-                  TO* X, TO* Y, TO* S2, TO* H2) {
-  nt_ks<NT_S2>(b.s2.NT, b.ks[1], [&](auto ntc, auto ksc) {
-    constexpr int N_ = decltype(ntc)::value, K_ = decltype(ksc)::value;
-    LAUNCH((k_s2<TI, TM, TO, NP, K_, N_>), grid_for<K_>(b.s2.ngroups), block_for<K_>(), s, b.s2, b.tw_row,
-           b.tw_col, b.wrow_sys, b.info, b.st, mask, C, D, HD, SD, X, Y, S2, H2, b.wseg);
-  });
-}
-
-void launch_s2(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init, bool filter) {
-  (void)filter;
-  if (b.s2.ngroups <= 0) return;
-  if (prec == P64) {
-    if (init) s2_go<double, double, double, 2>(s, b, mask, b.C, b.C, b.HC, b.SC, b.S0, b.H0, b.S2, b.H2);
-    else s2_go<double, double, double, 4>(s, b, mask, b.C, b.D, b.HD, b.SD, b.X, b.Y, b.S2, b.H2);
-  } else if (prec == P32) {
-    s2_go<float, float, float, 4>(s, b, mask, (const float*)b.Cl, (const float*)b.Dl, b.HDf, b.SDf, b.Xf, b.Yf,
-                                  b.S2f, b.H2f);
-  } else {
-    s2_go<bf16, float, float, 4>(s, b, mask, (const bf16*)b.Cl, (const bf16*)b.Dl, b.HDf, b.SDf, b.Xf, b.Yf,
-                                 b.S2f, b.H2f);
-  }
-}
-
-static void traces_go(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init_inputs, int mode,
-                      int refine_iters) {
+void launch_traces(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init_inputs, int mode,
+                   const CGParams& prm) {
   if (b.nchunks <= 0) return;
   if (prec == P64) {
-    if (init_inputs)
-      LAUNCH(k_traces<double>, dim3(b.nchunks), dim3(256), s, b.chunks, b.info, b.st, mask, b.tw_row, b.tw_col,
-             b.w_tr, b.H0, b.S0, b.S0, b.H0, b.S0, b.H0, b.tpart, b.ticket, mode, refine_iters);
+    if (init_inputs)   // X = S0, Y = H0, S2 = S0, H2 = H0: the sums then hold Tr H0, <S0,H0>, Tr S0, <S0,S0>
+      LAUNCH(k_traces<double>, dim3(b.nchunks), dim3(256), s, b.chunks, b.st, mask, b.w_tr, b.H0, b.S0, b.S0,
+             b.H0, b.S0, b.H0, b.tpart);
     else
-      LAUNCH(k_traces<double>, dim3(b.nchunks), dim3(256), s, b.chunks, b.info, b.st, mask, b.tw_row, b.tw_col,
-             b.w_tr, b.H0, b.S0, b.X, b.Y, b.S2, b.H2, b.tpart, b.ticket, mode, refine_iters);
+      LAUNCH(k_traces<double>, dim3(b.nchunks), dim3(256), s, b.chunks, b.st, mask, b.w_tr, b.H0, b.S0, b.X, b.Y,
+             b.S2, b.H2, b.tpart);
   } else {
-    LAUNCH(k_traces<float>, dim3(b.nchunks), dim3(256), s, b.chunks, b.info, b.st, mask, b.tw_row, b.tw_col,
-           b.w_tr, b.H0, b.S0, b.Xf, b.Yf, b.S2f, b.H2f, b.tpart, b.ticket, mode, refine_iters);
+    LAUNCH(k_traces<float>, dim3(b.nchunks), dim3(256), s, b.chunks, b.st, mask, b.w_tr, b.H0, b.S0, b.Xf, b.Yf,
+           b.S2f, b.H2f, b.tpart);
   }
+  if (mode != LS_STEP || b.multi_chunk)
+    LAUNCH(k_ls_state, dim3(b.nsys), dim3(64), s, b.info, b.st, mask, b.tpart, mode, prm.refine_iters);
 }
 
-void launch_traces_ls(hipStream_t s, const Bufs& b, Prec prec, int mask, int mode, const CGParams& prm) {
-  traces_go(s, b, prec, mask, mode != LS_STEP, mode, prm.refine_iters);
-}
-
-void launch_update(hipStream_t s, const Bufs& b, Prec prec, int mask) {
-  const int nb = b.n_tc + b.n_thc + b.n_tw;
-  if (nb <= 0) return;
+void launch_update(hipStream_t s, const Bufs& b, Prec prec, int mask, const CGParams& prm) {
+  const int nt = b.n_tc + b.n_thc + b.n_tw;
+  if (nt <= 0) return;
+  const dim3 grid((unsigned)((nt + 3) / 4));
   if (prec == P64)
-    LAUNCH((k_update<double, double, false>), dim3(nb), dim3(256), s, b.n_tc, b.n_thc, b.tc_row, b.thc_row,
-           b.tw_row, b.brow_sys, b.wrow_sys, b.w_tr, b.st, mask, b.C, b.D, (double*)nullptr, b.HC, b.SC, b.HD,
-           b.SD, (double*)nullptr, (double*)nullptr, b.H0, b.S0, b.X, b.Y, b.S2, b.H2, (double*)nullptr,
+    LAUNCH((k_update<double, double, false>), grid, dim3(256), s, b.n_tc, b.n_thc, nt, b.upd_sys, b.w_tr, b.info,
+           b.st, mask, b.tpart, prm.refine_iters, b.C, b.D, (double*)nullptr, b.HC, b.SC, b.HD, b.SD,
+           (double*)nullptr, (double*)nullptr, b.H0, b.S0, b.X, b.Y, b.S2, b.H2, (double*)nullptr,
            (double*)nullptr);
   else if (prec == P32)
-    LAUNCH((k_update<float, float, true>), dim3(nb), dim3(256), s, b.n_tc, b.n_thc, b.tc_row, b.thc_row, b.tw_row,
-           b.brow_sys, b.wrow_sys, b.w_tr, b.st, mask, b.C, b.D, (float*)b.Cl, b.HC, b.SC, b.HDf, b.SDf,
+    LAUNCH((k_update<float, float, true>), grid, dim3(256), s, b.n_tc, b.n_thc, nt, b.upd_sys, b.w_tr, b.info,
+           b.st, mask, b.tpart, prm.refine_iters, b.C, b.D, (float*)b.Cl, b.HC, b.SC, b.HDf, b.SDf,
            (float*)b.HCl, (float*)b.SCl, b.H0, b.S0, b.Xf, b.Yf, b.S2f, b.H2f, (float*)b.H0l, (float*)b.S0l);
   else
-    LAUNCH((k_update<bf16, float, true>), dim3(nb), dim3(256), s, b.n_tc, b.n_thc, b.tc_row, b.thc_row, b.tw_row,
-           b.brow_sys, b.wrow_sys, b.w_tr, b.st, mask, b.C, b.D, (bf16*)b.Cl, b.HC, b.SC, b.HDf, b.SDf,
+    LAUNCH((k_update<bf16, float, true>), grid, dim3(256), s, b.n_tc, b.n_thc, nt, b.upd_sys, b.w_tr, b.info,
+           b.st, mask, b.tpart, prm.refine_iters, b.C, b.D, (bf16*)b.Cl, b.HC, b.SC, b.HDf, b.SDf,
            (bf16*)b.HCl, (bf16*)b.SCl, b.H0, b.S0, b.Xf, b.Yf, b.S2f, b.H2f, (bf16*)b.H0l, (bf16*)b.S0l);
-}
-
-template <typename TI>
-static void grad_go(hipStream_t s, const Bufs& b, int mask, const TI* HC, const TI* SC, const TI* S0, const TI* H0) {
-  nt_ks<NT_GRAD>(b.grad.NT, b.ks[2], [&](auto ntc, auto ksc) {
-    constexpr int N_ = decltype(ntc)::value, K_ = decltype(ksc)::value;
-    LAUNCH((k_grad<TI, K_, N_>), grid_for<K_>(b.grad.ngroups), block_for<K_>(), s, b.grad, b.tc_row, b.brow_sys,
-           b.st, mask, HC, SC, S0, H0, b.HC, b.c_in_hc, b.cmask, b.Gold, b.G, b.gpart);
-  });
-}
-
-void launch_grad(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init) {
-  (void)init;
-  if (b.grad.ngroups <= 0) return;
-  if (prec == P64) grad_go<double>(s, b, mask, b.HC, b.SC, b.S0, b.H0);
-  else if (prec == P32)
-    grad_go<float>(s, b, mask, (const float*)b.HCl, (const float*)b.SCl, (const float*)b.S0l, (const float*)b.H0l);
-  else
-    grad_go<bf16>(s, b, mask, (const bf16*)b.HCl, (const bf16*)b.SCl, (const bf16*)b.S0l, (const bf16*)b.H0l);
 }
 
 void launch_beta(hipStream_t s, const Bufs& b, int mask, bool init, const CGParams& prm) {

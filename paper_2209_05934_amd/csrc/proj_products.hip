@@ -1,0 +1,121 @@
+// n x n projections of one CG iteration (Sec. III B of arXiv 2209.05934):
+// X = C^T SD, Y = C^T HD, S2 = D^T SD, H2 = D^T HD, or at start-up S0 = C^T SC
+// and H0 = C^T HC; MFMA tiles over the tile-pair work lists of the n x n pattern.
+#include "tile_sched.hpp"
+
+namespace omm {
+
+namespace {
+
+// ------------------------------------------------------------------ S2: n x n projections
+// Groups of NT output tiles in one row g of the n x n pattern: per basis tile b
+// the C(b,g) and D(b,g) tiles are loaded once for NT tiles of HD and SD.
+template <typename TI, typename TM, typename TO, int NPROD, int KS, int NT>
+__global__ __launch_bounds__(Split<KS>::NW * 64) void k_s2(
+    GroupView P, const int* __restrict__ orow, const int* __restrict__ ocol, const int* __restrict__ wrow_sys,
+    const SysInfo* __restrict__ info, const SysState* __restrict__ st, int mask, const TI* __restrict__ Cm,
+    const TI* __restrict__ Dm, const TM* __restrict__ HDm, const TM* __restrict__ SDm, TO* __restrict__ X,
+    TO* __restrict__ Y, TO* __restrict__ S2o, TO* __restrict__ H2o, const uint8_t* __restrict__ wseg) {
+  typedef typename Acc<TI>::V V;
+  typedef Split<KS> SP;
+  constexpr int W = 1 + NT;
+  __shared__ V red[SP::RED * NPROD * NT * 64];
+  const int wave = wave_id(), lane = threadIdx.x & 63;
+  const int grp = wave / KS, wk = wave - grp * KS;
+  const int g = xcd_block() * SP::G + grp;
+  bool act = g < P.ngroups;
+  int s = 0, o0 = 0, cnt = 0;
+  if (act) {
+    o0 = P.go0[g];
+    cnt = P.gn[g];
+    s = wrow_sys[orow[o0]];
+    act = on(st, s, mask);
+  }
+  V acc[NPROD * NT];
+#pragma unroll
+  for (int a = 0; a < NPROD * NT; ++a) acc[a] = vzero<V>();
+  if (act) {
+    int64_t b, e;
+    ks_chunk(P, g, wk, KS, b, e);
+    struct Stage { Frag<TI> c, d, hd[NT], sd[NT]; };
+    run_entries<W, pipe_depth<TI>((NPROD == 4 ? 2 : 1) + 2 * NT), Stage>(
+        P.ent, b, e, lane,
+        [&](Stage& f, const int (&id)[W]) {
+          ld_col(f.c, Cm + (size_t)id[0] * TE, lane);                 // A = C^T
+          if (NPROD == 4) ld_col(f.d, Dm + (size_t)id[0] * TE, lane);  // A = D^T
+#pragma unroll
+          for (int u = 0; u < NT; ++u) {
+            const size_t bt = (size_t)max(id[1 + u], 0) * TE;
+            ld_col(f.hd[u], HDm + bt, lane);
+            ld_col(f.sd[u], SDm + bt, lane);
+          }
+        },
+        [&](const Stage& f, const int (&id)[W]) {
+#pragma unroll
+          for (int u = 0; u < NT; ++u) {
+            if (id[1 + u] >= 0) {
+              mma(acc[u], f.c, f.sd[u]);
+              mma(acc[NT + u], f.c, f.hd[u]);
+              if (NPROD == 4) {
+                mma(acc[2 * NT + u], f.d, f.sd[u]);
+                mma(acc[3 * NT + u], f.d, f.hd[u]);
+              }
+            }
+          }
+        });
+  }
+  ks_reduce<KS, NPROD * NT>(acc, red, grp, wk, lane);
+  if (!act || wk != 0) return;
+  const double e2 = info[s].eps2;
+#pragma unroll
+  for (int u = 0; u < NT; ++u) {
+    if (u >= cnt) break;
+    const int t = o0 + u;
+    if (e2 > 0.0) {
+      const uint8_t* rs = wseg + 32 * (size_t)orow[t];
+      const uint8_t* cs = wseg + 32 * (size_t)ocol[t];
+#pragma unroll
+      for (int a = 0; a < NPROD; ++a) filter_tile(acc[a * NT + u], lane, rs, cs, e2);
+    }
+    const size_t o = (size_t)t * TE;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = out_off<V>(lane, r);
+      X[o + e] = (TO)acc[u][r];
+      Y[o + e] = (TO)acc[NT + u][r];
+      if (NPROD == 4) {
+        S2o[o + e] = (TO)acc[2 * NT + u][r];
+        H2o[o + e] = (TO)acc[3 * NT + u][r];
+      }
+    }
+  }
+}
+
+}  // namespace
+
+template <typename TI, typename TM, typename TO, int NP>
+static void s2_go(hipStream_t s, const Bufs& b, int mask, const TI* C, const TI* D, const TM* HD, const TM* SD,
+                  TO* X, TO* Y, TO* S2, TO* H2) {
+  nt_ks<NT_S2>(b.s2.NT, b.ks[1], [&](auto ntc, auto ksc) {
+    constexpr int N_ = decltype(ntc)::value, K_ = decltype(ksc)::value;
+    LAUNCH((k_s2<TI, TM, TO, NP, K_, N_>), grid_for<K_>(b.s2.ngroups), block_for<K_>(), s, b.s2, b.tw_row,
+           b.tw_col, b.wrow_sys, b.info, b.st, mask, C, D, HD, SD, X, Y, S2, H2, b.wseg);
+  });
+}
+
+void launch_s2(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init, bool filter) {
+  (void)filter;
+  if (b.s2.ngroups <= 0) return;
+  if (prec == P64) {
+    if (init) s2_go<double, double, double, 2>(s, b, mask, b.C, b.C, b.HC, b.SC, b.S0, b.H0, b.S2, b.H2);
+    else s2_go<double, double, double, 4>(s, b, mask, b.C, b.D, b.HD, b.SD, b.X, b.Y, b.S2, b.H2);
+  } else if (prec == P32) {
+    s2_go<float, float, float, 4>(s, b, mask, (const float*)b.Cl, (const float*)b.Dl, b.HDf, b.SDf, b.Xf, b.Yf,
+                                  b.S2f, b.H2f);
+  } else {
+    s2_go<bf16, float, float, 4>(s, b, mask, (const bf16*)b.Cl, (const bf16*)b.Dl, b.HDf, b.SDf, b.Xf, b.Yf,
+                                 b.S2f, b.H2f);
+  }
+}
+
+}  // namespace omm

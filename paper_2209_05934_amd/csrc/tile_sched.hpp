@@ -1,0 +1,206 @@
+// Work scheduling shared by the tile-product kernels (direction products,
+// n x n projections, gradient): per-system activity, block filtering of
+// Sec. V, XCD-aware block numbering, split-K reduction and the software
+// pipeline over tile-pair work lists; plus the host-side launch helpers.
+#pragma once
+
+#include <type_traits>
+
+#include "kernels.hpp"
+#include "tile_ops.hpp"
+
+namespace omm {
+
+namespace {
+
+template <Prec P> struct PT;
+template <> struct PT<P64> { typedef double TI; typedef double TO; };
+template <> struct PT<P32> { typedef float TI; typedef float TO; };
+template <> struct PT<PBF> { typedef bf16 TI; typedef float TO; };
+
+__device__ __forceinline__ bool on(const SysState* __restrict__ st, int s, int mask) {
+  return (st[s].phase & mask) != 0;
+}
+
+// Zero every atom block of the accumulator tile whose Frobenius norm^2 < eps2
+// (filtering of Sec. V).  Row/column segments give, for each tile row/column,
+// the [lo, hi) range of its block inside the tile; rseg == nullptr means the
+// whole tile height is one block.  Uniform shuffles, fixed summation order.
+template <typename V>
+__device__ void filter_tile(V& acc, int lane, const uint8_t* __restrict__ rseg,
+                            const uint8_t* __restrict__ cseg, double eps2) {
+  const int j = lane & 15, q = lane >> 4;
+  const int clo = cseg[j], chi = cseg[16 + j];
+  double rowpart[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const double sq = (double)acc[r] * (double)acc[r];
+    double sum = 0.0;
+    for (int c = 0; c < 16; ++c) {
+      const double v = __shfl(sq, c + 16 * q, 64);
+      if (c >= clo && c < chi) sum += v;
+    }
+    rowpart[r] = sum;
+  }
+  double tot[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int qq = 0; qq < 4; ++qq) {
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const double v = __shfl(rowpart[rr], j + 16 * qq, 64);
+      const int rho = Lay<V>::row(qq, rr);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = Lay<V>::row(q, r);
+        const bool in = rseg ? (rho >= rseg[row] && rho < rseg[16 + row]) : true;
+        if (in) tot[r] += v;
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    if (tot[r] < eps2) acc[r] = 0;
+}
+
+// Work distribution of the tile-product kernels.  A workgroup holds NW = max(4, KS)
+// waves; KS consecutive waves split the pair list of one output tile into KS
+// contiguous chunks and add their accumulators in a fixed tree through LDS, so
+// results are bitwise reproducible for a given KS.  Logical block ids are
+// renumbered so that consecutive ids (neighbouring output tiles, which share
+// operand tiles) run on the same XCD: the hardware deals workgroups to the 8
+// XCDs round-robin.
+__device__ __forceinline__ int xcd_block() {
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int x = b & 7, q = nb >> 3, r = nb & 7;
+  return x * q + min(x, r) + (b >> 3);
+}
+
+template <int KS> struct Split {
+  static constexpr int NW = KS > 4 ? KS : 4;     // waves per workgroup
+  static constexpr int G = NW / KS;              // output tiles per workgroup
+  static constexpr int RED = KS > 1 ? NW / 2 : 1;   // LDS slots of the reduction tree
+};
+
+template <int KS, int NACC, typename V>
+__device__ __forceinline__ void ks_reduce(V (&acc)[NACC], V* buf, int grp, int wk, int lane) {
+  if (KS == 1) return;
+#pragma unroll
+  for (int stride = KS / 2; stride >= 1; stride >>= 1) {
+    if (wk >= stride && wk < 2 * stride) {
+#pragma unroll
+      for (int a = 0; a < NACC; ++a) buf[((grp * (KS / 2) + wk - stride) * NACC + a) * 64 + lane] = acc[a];
+    }
+    __syncthreads();
+    if (wk < stride) {
+#pragma unroll
+      for (int a = 0; a < NACC; ++a) acc[a] += buf[((grp * (KS / 2) + wk) * NACC + a) * 64 + lane];
+    }
+    __syncthreads();
+  }
+}
+
+// Wave index as a scalar: every per-wave quantity derived from it (group,
+// chunk bounds, entry indices, loop counters) then lives in scalar registers
+// and branches on it are scalar branches.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
+
+// Stages of operand fragments kept in flight by run_entries for a stage of
+// `tiles` fragments of type T (register budget about 96 VGPRs).
+template <typename T>
+constexpr int pipe_depth(int tiles) {
+  return tiles * (int)(sizeof(Frag<T>) / 4) <= 24 ? 4 : (tiles * (int)(sizeof(Frag<T>) / 4) <= 48 ? 3 : 2);
+}
+
+// Software pipeline over the entries [b, e) of a group list (W ints each).
+// Entries go in rounds of PB (a multiple of D, at most 64 / W): a round's
+// indices sit in one register per lane, the next round's in a second one
+// fetched a round ahead, and both are read with uniform lane reads, so no
+// tile address waits on an index load.  D stages of operand fragments are in
+// flight: load(stage, idx) issues the tile loads of one entry and
+// use(stage, idx) runs its MFMAs, in entry order.  A round is unrolled in
+// full and every step issues its loads unconditionally (past the end it
+// reloads the last entry), so the compiler knows at each use exactly how
+// many younger loads are in flight and waits for that stage alone; the
+// look-ahead runs across round boundaries, so the pipeline never drains.
+template <int W, int D, typename St, typename LoadF, typename UseF>
+__device__ __forceinline__ void run_entries(const int* __restrict__ ent, int64_t b, int64_t e, int lane,
+                                            LoadF&& load, UseF&& use) {
+  constexpr int PB = (64 / W) / D * D;
+  static_assert(PB >= D, "pipeline deeper than a round");
+  const int n = (int)(e - b);
+  if (n <= 0) return;
+  const int* base = ent + b * W;
+  auto batch = [&](int r0) -> int {
+    const int left = n - r0;
+    const int cnt = left <= 0 ? 0 : (left >= PB ? PB : left);
+    return lane < cnt * W ? base[(size_t)r0 * W + lane] : 0;
+  };
+  int cur = batch(0), nxt = batch(PB);
+  St stg[D];
+  int id[D][W];
+#pragma unroll
+  for (int s = 0; s < D; ++s) {
+    const int q = s < n ? s : n - 1;
+#pragma unroll
+    for (int w = 0; w < W; ++w) id[s][w] = __builtin_amdgcn_readlane(cur, q * W + w);
+    load(stg[s], id[s]);
+  }
+  for (int r0 = 0;; r0 += PB) {
+#pragma unroll
+    for (int k = 0; k < PB; ++k) {
+      if (r0 + k >= n) return;
+      use(stg[k % D], id[k % D]);
+      // entry r0 + k + D (clamped to the last one) lives in this round or the next
+      const int q = (r0 + k + D < n ? r0 + k + D : n - 1) - r0;
+      if (q < PB) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) id[k % D][w] = __builtin_amdgcn_readlane(cur, q * W + w);
+      } else {
+#pragma unroll
+        for (int w = 0; w < W; ++w) id[k % D][w] = __builtin_amdgcn_readlane(nxt, (q - PB) * W + w);
+      }
+      load(stg[k % D], id[k % D]);
+    }
+    cur = nxt;
+    nxt = batch(r0 + 2 * PB);
+  }
+}
+
+// chunk [b, e) of group g's entry list handled by split-wave wk
+__device__ __forceinline__ void ks_chunk(const GroupView& P, int g, int wk, int KS, int64_t& b, int64_t& e) {
+  const int64_t p0 = P.gp[g], n = P.gp[g + 1] - p0;
+  b = p0 + (n * wk) / KS;
+  e = p0 + (n * (wk + 1)) / KS;
+}
+
+}  // namespace
+
+#define LAUNCH(kern, grid, block, stream, ...)                                   \
+  do {                                                                          \
+    hipLaunchKernelGGL(kern, grid, block, 0, stream, __VA_ARGS__);              \
+    OMM_HIP(hipGetLastError());                                                 \
+  } while (0)
+
+template <int KS> static dim3 grid_for(int n) { return dim3((unsigned)((n + Split<KS>::G - 1) / Split<KS>::G)); }
+template <int KS> static dim3 block_for() { return dim3(Split<KS>::NW * 64); }
+
+// (NT, KS) dispatch: NT is 1 or the step's group width; KS in {1,2,4,8} (at most 4 when NT > 1)
+template <int NTG, typename F>
+static void nt_ks(int nt, int ks, F&& f) {
+  if (nt == 1) {
+    switch (ks) {
+      case 8: f(std::integral_constant<int, 1>{}, std::integral_constant<int, 8>{}); break;
+      case 4: f(std::integral_constant<int, 1>{}, std::integral_constant<int, 4>{}); break;
+      case 2: f(std::integral_constant<int, 1>{}, std::integral_constant<int, 2>{}); break;
+      default: f(std::integral_constant<int, 1>{}, std::integral_constant<int, 1>{}); break;
+    }
+  } else {
+    switch (ks) {
+      case 8:
+      case 4: f(std::integral_constant<int, NTG>{}, std::integral_constant<int, 4>{}); break;
+      case 2: f(std::integral_constant<int, NTG>{}, std::integral_constant<int, 2>{}); break;
+      default: f(std::integral_constant<int, NTG>{}, std::integral_constant<int, 1>{}); break;
+    }
+  }
+}
+
+}  // namespace omm
