@@ -18,8 +18,14 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIBDIR = os.path.join(PKG, "lib")
 LIBNAME = "libomm_mi355x.so"
-SOURCES = ["symbolic.hip", "dir_products.hip", "proj_products.hip", "grad_products.hip", "numeric.hip",
-           "cholesky.hip", "engine.hip"]
+# (source, object, extra flags): the three tile-product steps are compiled once
+# per arithmetic precision (OMM_PREC 0: FP64, 1: FP32, 2: BF16) so that their
+# many kernel instances build in parallel
+PRODUCT_SOURCES = ["dir_products.hip", "proj_products.hip", "grad_products.hip"]
+SOURCES = ([("symbolic.hip", "symbolic.o", [])]
+           + [(src, src.replace(".hip", f"_p{k}.o"), [f"-DOMM_PREC={k}"])
+              for src in PRODUCT_SOURCES for k in range(3)]
+           + [(src, src.replace(".hip", ".o"), []) for src in ("numeric.hip", "cholesky.hip", "engine.hip")])
 ARCH = os.environ.get("OMM_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
@@ -49,20 +55,23 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
     objdir = os.path.join(LIBDIR, "obj")
     os.makedirs(objdir, exist_ok=True)
 
-    def compile_one(src: str) -> str:
-        obj = os.path.join(objdir, src.replace(".hip", ".o"))
-        cmd = [hipcc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    def compile_one(item) -> str:
+        src, objname, extra = item
+        obj = os.path.join(objdir, objname)
+        cmd = [hipcc, *HIPCC_FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr}")
         if verbose:
-            print(f"compiled {src}", flush=True)
+            print(f"compiled {objname}", flush=True)
         return obj
 
     if jobs <= 0:
         jobs = min(len(SOURCES), os.cpu_count() or 4)
+    # longest first, so the slowest objects start at once
+    order = sorted(SOURCES, key=lambda it: 0 if it[0] in PRODUCT_SOURCES else 1)
     with ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(compile_one, SOURCES))
+        objs = list(ex.map(compile_one, order))
     out = lib_path()
     tmp = out + ".tmp"
     cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Wl,--no-undefined", "-o", tmp, *objs]

@@ -92,24 +92,28 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s1(
 
 template <typename TI, typename TO>
 static void s1_go(hipStream_t s, const Bufs& b, int mask, const TI* H, const TI* S, const TI* B, TO* O1, TO* O2) {
-  nt_ks<NT_S1>(b.s1.NT, b.ks[0], [&](auto ntc, auto ksc) {
+  if (b.s1.ngroups <= 0) return;
+  nt_ks(b.s1.NT, b.ks[0], [&](auto ntc, auto ksc) {
     constexpr int N_ = decltype(ntc)::value, K_ = decltype(ksc)::value;
     LAUNCH((k_s1<TI, TO, K_, N_>), grid_for<K_>(b.s1.ngroups), block_for<K_>(), s, b.s1, b.thc_row, b.thc_col,
            b.brow_sys, b.info, b.st, mask, H, S, B, O1, O2, b.hc_to_c, b.wseg);
   });
 }
 
-void launch_s1(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init, bool filter) {
-  (void)filter;
-  if (b.s1.ngroups <= 0) return;
-  if (prec == P64) {
-    if (init) s1_go<double, double>(s, b, mask, b.H, b.S, b.C, b.HC, b.SC);
-    else s1_go<double, double>(s, b, mask, b.H, b.S, b.D, b.HD, b.SD);
-  } else if (prec == P32) {
-    s1_go<float, float>(s, b, mask, (const float*)b.Hl, (const float*)b.Sl, (const float*)b.Dl, b.HDf, b.SDf);
-  } else {
-    s1_go<bf16, float>(s, b, mask, (const bf16*)b.Hl, (const bf16*)b.Sl, (const bf16*)b.Dl, b.HDf, b.SDf);
-  }
+// one precision per object file (OMM_PREC 0: FP64, 1: FP32, 2: BF16)
+#if OMM_PREC == 0
+void launch_s1_p64(hipStream_t s, const Bufs& b, int mask, bool init) {
+  if (init) s1_go<double, double>(s, b, mask, b.H, b.S, b.C, b.HC, b.SC);
+  else s1_go<double, double>(s, b, mask, b.H, b.S, b.D, b.HD, b.SD);
 }
+#elif OMM_PREC == 1
+void launch_s1_p32(hipStream_t s, const Bufs& b, int mask) {
+  s1_go<float, float>(s, b, mask, (const float*)b.Hl, (const float*)b.Sl, (const float*)b.Dl, b.HDf, b.SDf);
+}
+#else
+void launch_s1_pbf(hipStream_t s, const Bufs& b, int mask) {
+  s1_go<bf16, float>(s, b, mask, (const bf16*)b.Hl, (const bf16*)b.Sl, (const bf16*)b.Dl, b.HDf, b.SDf);
+}
+#endif
 
 }  // namespace omm

@@ -10,6 +10,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -108,7 +110,7 @@ struct omm_ctx {
   int NB = 0, NW = 0;
   Pat TH, TC, TCt, THC, TW, TCM;
   Plan Pcm, Prho;
-  GPlan G[3][2];      // product steps (direction, n x n, gradient) x (NT = 1, NT = step width)
+  GPlan G[3][NPLAN];  // product steps (direction, n x n, gradient) x group widths PLAN_NT
   int sel[3] = {0, 0, 0};
   int *brow_sys = nullptr, *wrow_sys = nullptr, *c_in_hc = nullptr, *hc_to_c = nullptr, *w_tr = nullptr;
   int* upd_sys = nullptr;
@@ -740,13 +742,11 @@ void prepare(omm_ctx* c) {
   sym_product(c, c->TCM, c->NB, c->TC, c->TW, c->win_bw);
   // work lists
   {
-    const int widths[3] = {NT_S1, NT_S2, NT_GRAD};
     const Pat* outs[3] = {&c->THC, &c->TW, &c->TC};
     const PatView As[3] = {c->TH.view(), c->TCt.view(), c->THC.view()};
     const PatView Bs[3] = {c->TC.view(), c->THC.view(), c->TW.view()};
     for (int k = 0; k < 3; ++k) {
-      make_gplan(c, c->G[k][0], *outs[k], As[k], Bs[k], 1);
-      make_gplan(c, c->G[k][1], *outs[k], As[k], Bs[k], widths[k]);
+      for (int q = 0; q < NPLAN; ++q) make_gplan(c, c->G[k][q], *outs[k], As[k], Bs[k], PLAN_NT[q]);
     }
   }
   make_plan(c, c->Pcm, c->TCM, c->TC.view(), c->TW.view(), c->win_bw);
@@ -834,6 +834,9 @@ void prepare(omm_ctx* c) {
   b.multi_chunk = 0;
   for (int i = 0; i < c->nsys; ++i)
     if (c->h_info[i].ch1 - c->h_info[i].ch0 > FUSED_CHUNKS) b.multi_chunk = 1;
+  b.multi_c = 0;
+  for (int i = 0; i < c->nsys; ++i)
+    if (c->h_info[i].c1 - c->h_info[i].c0 > FUSED_CTILES) b.multi_c = 1;
   b.n_th = (int)c->TH.nnz; b.n_tc = (int)ntc; b.n_thc = (int)nhc; b.n_tw = (int)ntw;
   pick_plans(c);
   b.H = c->H; b.S = c->S;
@@ -906,15 +909,18 @@ int pick_ks(int64_t ngroups, int64_t nent, int kmax) {
 
 // Grouped lists (a wave computes several output tiles of one row and loads the
 // shared operand once) when there are enough groups to fill the GPU, one tile
-// per wave otherwise.
+// per wave otherwise; the autotuner may choose differently.
 void pick_plans(omm_ctx* c) {
   for (int k = 0; k < 3; ++k) {
-    const GPlan& wide = c->G[k][1];
     // n x n projections keep one tile per wave by default: their grouped form
-    // holds twice the accumulators and loses occupancy (the autotuner may still pick it)
-    c->sel[k] = (k != 1 && wide.NT > 1 && wide.ngroups >= 2048) ? 1 : 0;
-    const GPlan& G = c->G[k][c->sel[k]];
-    c->b.ks[k] = pick_ks(G.ngroups, G.nent, G.NT > 1 ? 4 : 8);
+    // holds twice the accumulators and loses occupancy
+    int sel = 0;
+    if (k != 1)
+      for (int q = NPLAN - 1; q > 0; --q)
+        if (c->G[k][q].ngroups >= 2048) { sel = q; break; }
+    c->sel[k] = sel;
+    const GPlan& G = c->G[k][sel];
+    c->b.ks[k] = pick_ks(G.ngroups, G.nent, plan_ok(k, G.NT, 8) ? 8 : 4);
   }
   c->b.s1 = c->G[0][c->sel[0]].view();
   c->b.s2 = c->G[1][c->sel[1]].view();
@@ -954,7 +960,6 @@ void autotune(omm_ctx* c) {
   }
   const Prec p = c->prec;
   const int mask = PH_FP64 | PH_LOW;
-  const bool filt = any_filter(c);
   hipEvent_t e0, e1;
   OMM_HIP(hipEventCreate(&e0));
   OMM_HIP(hipEventCreate(&e1));
@@ -971,16 +976,15 @@ void autotune(omm_ctx* c) {
     }
     float best = 1e30f;
     int best_code = 10 * c->sel[cls] + c->b.ks[cls];
-    for (int sel = 0; sel < 2; ++sel) {
-      if (sel == 1 && c->G[cls][1].NT == 1) continue;
+    for (int sel = 0; sel < NPLAN; ++sel) {
       for (int ks : {1, 2, 4, 8}) {
-        if (sel == 1 && ks == 8) continue;
+        if (!plan_ok(cls, c->G[cls][sel].NT, ks)) continue;
         set_plan(c, cls, sel, ks);
         float tmin = 1e30f;
         for (int rep = 0; rep < 3; ++rep) {
           OMM_HIP(hipEventRecord(e0, c->stream));
-          if (cls == 0) launch_s1(c->stream, c->b, p, mask, false, filt);
-          else if (cls == 1) launch_s2(c->stream, c->b, p, mask, false, filt);
+          if (cls == 0) launch_s1(c->stream, c->b, p, mask, false);
+          else if (cls == 1) launch_s2(c->stream, c->b, p, mask, false);
           else launch_grad(c->stream, c->b, p, mask, false);
           OMM_HIP(hipEventRecord(e1, c->stream));
           OMM_HIP(hipEventSynchronize(e1));
@@ -1002,6 +1006,8 @@ void autotune(omm_ctx* c) {
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  if (const char* e = std::getenv("OMM_TUNE_LOG"))   // timings of every candidate shape, for inspection
+    if (*e) std::fprintf(stderr, "omm autotune: %s\n", c->tune_log.c_str());
   if (added && c->opt.tune_cache) {
     if (FILE* f = std::fopen(c->opt.tune_cache, "w")) {
       for (auto& kv : cache) std::fprintf(f, "%s %d\n", kv.first.c_str(), kv.second);
@@ -1064,13 +1070,13 @@ void run_iteration(omm_ctx* c, Prec p, int mask, bool tm) {
   const Bufs& b = c->b;
   const CGParams prm = params(c);
   StepArg a{p, mask, any_filter(c)};
-  timed(c, 0, tm, [](omm_ctx* cc, void* v) { auto* q = (StepArg*)v; launch_s1(cc->stream, cc->b, q->p, q->mask, false, q->filter); }, &a);
-  timed(c, 1, tm, [](omm_ctx* cc, void* v) { auto* q = (StepArg*)v; launch_s2(cc->stream, cc->b, q->p, q->mask, false, q->filter); }, &a);
+  timed(c, 0, tm, [](omm_ctx* cc, void* v) { auto* q = (StepArg*)v; launch_s1(cc->stream, cc->b, q->p, q->mask, false); }, &a);
+  timed(c, 1, tm, [](omm_ctx* cc, void* v) { auto* q = (StepArg*)v; launch_s2(cc->stream, cc->b, q->p, q->mask, false); }, &a);
   launch_traces(s, b, p, mask, false, LS_STEP, prm);
   launch_update(s, b, p, mask, prm);
   timed(c, 2, tm, [](omm_ctx* cc, void* v) { auto* q = (StepArg*)v; launch_grad(cc->stream, cc->b, q->p, q->mask, false); }, &a);
   launch_beta(s, b, mask, false, prm);
-  launch_update_d(s, b, p, mask);
+  launch_update_d(s, b, p, mask, false, prm);
 }
 
 void run_step(omm_ctx* c, bool tm) {
@@ -1082,13 +1088,12 @@ void init_sequence(omm_ctx* c) {
   hipStream_t s = c->stream;
   const Bufs& b = c->b;
   const CGParams prm = params(c);
-  const bool filt = any_filter(c);
-  launch_s1(s, b, P64, PH_INIT, true, filt);
-  launch_s2(s, b, P64, PH_INIT, true, filt);
+  launch_s1(s, b, P64, PH_INIT, true);
+  launch_s2(s, b, P64, PH_INIT, true);
   launch_traces(s, b, P64, PH_INIT, true, LS_INIT, prm);
   launch_grad(s, b, P64, PH_INIT, true);
   launch_beta(s, b, PH_INIT, true, prm);
-  launch_update_d(s, b, P64, PH_INIT);
+  launch_update_d(s, b, P64, PH_INIT, true, prm);
   if (c->prec != P64) launch_cast_state(s, b, c->prec, PH_INIT);
   launch_init_finish(s, b);
 }

@@ -93,21 +93,25 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_grad(
 
 template <typename TI>
 static void grad_go(hipStream_t s, const Bufs& b, int mask, const TI* HC, const TI* SC, const TI* S0, const TI* H0) {
-  nt_ks<NT_GRAD>(b.grad.NT, b.ks[2], [&](auto ntc, auto ksc) {
+  if (b.grad.ngroups <= 0) return;
+  nt_ks(b.grad.NT, b.ks[2], [&](auto ntc, auto ksc) {
     constexpr int N_ = decltype(ntc)::value, K_ = decltype(ksc)::value;
     LAUNCH((k_grad<TI, K_, N_>), grid_for<K_>(b.grad.ngroups), block_for<K_>(), s, b.grad, b.tc_row, b.brow_sys,
            b.st, mask, HC, SC, S0, H0, b.HC, b.c_in_hc, b.cmask, b.Gold, b.G, b.gpart);
   });
 }
 
-void launch_grad(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init) {
-  (void)init;
-  if (b.grad.ngroups <= 0) return;
-  if (prec == P64) grad_go<double>(s, b, mask, b.HC, b.SC, b.S0, b.H0);
-  else if (prec == P32)
-    grad_go<float>(s, b, mask, (const float*)b.HCl, (const float*)b.SCl, (const float*)b.S0l, (const float*)b.H0l);
-  else
-    grad_go<bf16>(s, b, mask, (const bf16*)b.HCl, (const bf16*)b.SCl, (const bf16*)b.S0l, (const bf16*)b.H0l);
+// one precision per object file (OMM_PREC 0: FP64, 1: FP32, 2: BF16)
+#if OMM_PREC == 0
+void launch_grad_p64(hipStream_t s, const Bufs& b, int mask) { grad_go<double>(s, b, mask, b.HC, b.SC, b.S0, b.H0); }
+#elif OMM_PREC == 1
+void launch_grad_p32(hipStream_t s, const Bufs& b, int mask) {
+  grad_go<float>(s, b, mask, (const float*)b.HCl, (const float*)b.SCl, (const float*)b.S0l, (const float*)b.H0l);
 }
+#else
+void launch_grad_pbf(hipStream_t s, const Bufs& b, int mask) {
+  grad_go<bf16>(s, b, mask, (const bf16*)b.HCl, (const bf16*)b.SCl, (const bf16*)b.S0l, (const bf16*)b.H0l);
+}
+#endif
 
 }  // namespace omm

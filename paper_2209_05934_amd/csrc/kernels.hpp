@@ -28,10 +28,13 @@ void excl_scan64(hipStream_t st, const int64_t* in, int64_t* out, int64_t n);
 // ---------------------------------------------------------------- numeric (numeric.hip)
 enum Prec { P64 = 0, P32 = 1, PBF = 2 };
 
-// group widths (output tiles per wave) of the grouped work lists
-constexpr int NT_S1 = 4;     // direction products: H, S tiles shared by 4 tiles of D
-constexpr int NT_S2 = 2;     // n x n projections: C, D tiles shared by 2 tiles of HD, SD
-constexpr int NT_GRAD = 4;   // gradient: HC, SC tiles shared by 4 tiles of S_W, H_W
+// group widths (output tiles per wave sharing one operand tile) of the
+// grouped work lists built for every product step
+constexpr int NPLAN = 3;
+constexpr int PLAN_NT[NPLAN] = {1, 2, 4};
+// launch shape (group width NT, split KS) a product step can run: the n x n
+// projections run grouped plans with at most 4 waves per group
+inline bool plan_ok(int step, int nt, int ks) { return !(step == 1 && nt > 1 && ks > 4); }
 
 struct Bufs {   // every device buffer the iteration kernels touch
   // patterns (global tile rows/cols)
@@ -44,6 +47,7 @@ struct Bufs {   // every device buffer the iteration kernels touch
   const int4* chunks;            // trace chunks (tile begin, end, system)
   int nchunks;
   int multi_chunk;               // some system spans more than FUSED_CHUNKS trace chunks
+  int multi_c;                   // some system has more than FUSED_CTILES C tiles
   int n_th, n_tc, n_thc, n_tw;   // tile counts
   GroupView s1, s2, grad;         // grouped work lists of the three product steps
   // FP64 masters
@@ -61,8 +65,18 @@ struct Bufs {   // every device buffer the iteration kernels touch
 };
 
 // one CG iteration step (all systems whose phase matches `mask`), arithmetic `prec`
-void launch_s1(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init, bool filter);
-void launch_s2(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init, bool filter);
+void launch_s1(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init);
+void launch_s2(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init);
+// the same per precision (each precision of a product step is its own object file)
+void launch_s1_p64(hipStream_t s, const Bufs& b, int mask, bool init);
+void launch_s1_p32(hipStream_t s, const Bufs& b, int mask);
+void launch_s1_pbf(hipStream_t s, const Bufs& b, int mask);
+void launch_s2_p64(hipStream_t s, const Bufs& b, int mask, bool init);
+void launch_s2_p32(hipStream_t s, const Bufs& b, int mask);
+void launch_s2_pbf(hipStream_t s, const Bufs& b, int mask);
+void launch_grad_p64(hipStream_t s, const Bufs& b, int mask);
+void launch_grad_p32(hipStream_t s, const Bufs& b, int mask);
+void launch_grad_pbf(hipStream_t s, const Bufs& b, int mask);
 // the 15 trace sums (init_inputs: of H0 and S0 alone) and from them the
 // line-search step (mode LS_STEP), the initial energy (LS_INIT) or the electron count (LS_REPORT)
 void launch_traces(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init_inputs, int mode,
@@ -71,7 +85,8 @@ void launch_traces(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init_
 void launch_update(hipStream_t s, const Bufs& b, Prec prec, int mask, const CGParams& prm);
 void launch_grad(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init);
 void launch_beta(hipStream_t s, const Bufs& b, int mask, bool init, const CGParams& prm);
-void launch_update_d(hipStream_t s, const Bufs& b, Prec prec, int mask);
+// beta (systems of at most FUSED_CTILES C tiles: in place), D = -G + beta D, G_old = G
+void launch_update_d(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init, const CGParams& prm);
 void launch_init_finish(hipStream_t s, const Bufs& b);
 void launch_cast_state(hipStream_t s, const Bufs& b, Prec prec, int mask);   // C, HC, SC, H0, S0 copies
 void launch_cast_hs(hipStream_t s, const Bufs& b, Prec prec);                // H, S copies
@@ -80,6 +95,8 @@ void launch_cast_hs(hipStream_t s, const Bufs& b, Prec prec);                // 
 enum { LS_STEP = 0, LS_INIT = 1, LS_REPORT = 2 };
 // systems with at most this many trace chunks solve the line search inside the update kernel
 constexpr int FUSED_CHUNKS = 16;
+// systems with at most this many C tiles take the CG beta inside the D update kernel
+constexpr int FUSED_CTILES = 1024;
 
 // density matrix: CM = C (2I - S0) on the CM plan, rho = 2 CM C^T on the H pattern
 void launch_cm(hipStream_t s, PlanView p, const int* orow, const int* brow_sys, int sys, const double* C,

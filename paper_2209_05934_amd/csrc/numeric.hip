@@ -9,7 +9,7 @@
 //   exact line search    first minimum of E~(C + xD) = sum c_k x^k  (in k_update)
 //   updates              C, HC, SC += x (D, HD, SD);  H0, S0 += x(Y+Y^T, X+X^T) + x^2 (H2, S2)
 //   gradient             G = P_C[8 HC - 4 (HC S0 + SC H0)]  (kept on C's pattern)  (k_grad)
-//   CG update            beta = max(0, <G, G - G_old>/<G_old, G_old>), D = -G + beta D  (k_beta, k_update_d)
+//   CG update            beta = max(0, <G, G - G_old>/<G_old, G_old>), D = -G + beta D  (k_update_d)
 // The expansion E~(C + xD) = 4 Tr H_W(x) - 2 <S_W(x), H_W(x)> with
 // H_W(x) = H0 + x(Y + Y^T) + x^2 H2 and S_W(x) = S0 + x(X + X^T) + x^2 S2
 // follows from Eq. 3-4.  Tile products run on MFMA (FP64, FP32, or BF16 with
@@ -160,9 +160,9 @@ __device__ void ls_apply(SysState& S, const double* c, double ne, bool ok, doubl
       return;
     }
     x = 0.0;
-    S.restart = 1;
     S.restarts += 1;
   }
+  S.restart = ok ? 0 : 1;   // set at every step: the next beta (in whichever kernel) reads it unchanged
 #pragma unroll
   for (int k = 0; k < 5; ++k) S.c[k] = c[k];
   S.x = x;
@@ -364,11 +364,20 @@ __global__ __launch_bounds__(256) void k_update(int nc, int nhc, int ntot, const
 }
 
 // ------------------------------------------------------------------ beta, stop rules (one thread per system)
+// <G_old,G_old> is read from the slot of the previous iteration and <G,G>
+// stored in the slot of this one, so that a kernel in which one wave records
+// the new value while others still read the old one has no conflict.
+__device__ __forceinline__ double gg_prev(const SysState& S) { return S.gg2[(S.iter + 1) & 1]; }
+__device__ __forceinline__ void gg_store(SysState& S, double v) { S.gg2[S.iter & 1] = v; }
+__device__ __forceinline__ double beta_of(const SysState& S, double gg, double go) {
+  return S.restart ? 0.0 : fmax(0.0, (gg - go) / gg_prev(S));
+}
+
 __device__ void beta_finish(SysState& S, int s, double gg, double go, int init, double* __restrict__ hist,
                             const CGParams& prm) {
   const double gn = sqrt(gg);
   if (init) {
-    S.gg = gg;
+    gg_store(S, gg);
     S.gnorm = gn;
     S.beta = 0.0;
     S.steepest = 1;
@@ -376,7 +385,7 @@ __device__ void beta_finish(SysState& S, int s, double gg, double go, int init, 
     S.conv_init = (gn <= prm.tol_grad) ? 1 : 0;
     return;
   }
-  const double beta = S.restart ? 0.0 : fmax(0.0, (gg - go) / S.gg);
+  const double beta = beta_of(S, gg, go);
   const int64_t row = S.iter - 1;
   if (prm.hist_on && row >= 0 && row < prm.hist_max) {
     double* h = hist + ((size_t)s * prm.hist_max + row) * HCOLS;
@@ -403,19 +412,20 @@ __device__ void beta_finish(SysState& S, int s, double gg, double go, int init, 
     S.phase = PH_DONE;
   }
   S.beta = beta;
-  S.gg = gg;
+  gg_store(S, gg);
   S.gnorm = gn;
   S.steepest = (beta == 0.0) ? 1 : 0;
-  S.restart = 0;
 }
 
-// <G,G> and <G,G_old> of one system summed in tile order, then beta and the stop rules
+// <G,G> and <G,G_old> of one system summed in tile order, then beta and the
+// stop rules: the start-up step, and in iterations the systems of more than
+// FUSED_CTILES C tiles (k_update_d takes the step of the others itself)
 __global__ __launch_bounds__(256) void k_beta(const SysInfo* __restrict__ info, SysState* __restrict__ st, int mask,
                                             const double* __restrict__ gpart, int init, double* __restrict__ hist,
                                             CGParams prm) {
   __shared__ double red[2][4];
   const int s = blockIdx.x;
-  if (!on(st, s, mask)) return;
+  if ((!init && info[s].c1 - info[s].c0 <= FUSED_CTILES) || !on(st, s, mask)) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double gg = 0.0, go = 0.0;
   for (int t = info[s].c0 + threadIdx.x; t < info[s].c1; t += blockDim.x) {
@@ -435,22 +445,54 @@ __global__ __launch_bounds__(256) void k_beta(const SysInfo* __restrict__ info, 
   beta_finish(st[s], s, gg, go, init, hist, prm);
 }
 
+// D = -G + beta D and G_old = G: one wave per C tile, four consecutive
+// elements of one tile row per lane.  For a system of at most FUSED_CTILES C
+// tiles every wave adds the per-tile <G,G>, <G,G_old> in tile order and forms
+// beta itself (the same value in every wave); the wave of the system's first
+// C tile also applies the stop rules and records the state.  Fields it writes
+// that others read are either double-buffered (<G,G>) or only change when the
+// system leaves this step's phase (then its D is no longer used).
 template <typename TL, bool LOW>
-__global__ __launch_bounds__(256) void k_update_d(const int* __restrict__ tc_row, const int* __restrict__ brow_sys,
-                                                const SysState* __restrict__ st, int mask, double* __restrict__ D,
-                                                const double* __restrict__ G, double* __restrict__ Gold,
-                                                TL* __restrict__ Dl) {
-  const int t = blockIdx.x;
-  const int s = brow_sys[tc_row[t]];
+__global__ __launch_bounds__(256) void k_update_d(int nc, const int* __restrict__ upd_sys,
+                                                const SysInfo* __restrict__ info, SysState* __restrict__ st, int mask,
+                                                double* __restrict__ D, const double* __restrict__ G,
+                                                double* __restrict__ Gold, TL* __restrict__ Dl,
+                                                const double* __restrict__ gpart, double* __restrict__ hist,
+                                                CGParams prm, int init) {
+  const int t = blockIdx.x * 4 + wave_id();
+  if (t >= nc) return;
+  const int lane = threadIdx.x & 63;
+  const int s = upd_sys[t];
   if (!on(st, s, mask)) return;
   if (LOW && st[s].prec == 0) return;
-  const double beta = st[s].beta;
-  const size_t o = (size_t)t * TE + threadIdx.x;
-  const double g = G[o];
-  const double d = -g + beta * D[o];
-  D[o] = d;
-  Gold[o] = g;
-  if (LOW) Dl[o] = cvt<TL, double>(d);
+  const int ci0 = info[s].c0, ci1 = info[s].c1;
+  const size_t o = (size_t)t * TE + (lane >> 2) * 16 + (lane & 3) * 4;
+  double g[4], dv[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) { g[i] = G[o + i]; dv[i] = D[o + i]; }
+  double beta;
+  if (init) {   // start-up: D = -G (k_beta has recorded the state)
+    beta = 0.0;
+  } else if (ci1 - ci0 <= FUSED_CTILES) {
+    double gg = 0.0, go = 0.0;
+    for (int u = ci0 + lane; u < ci1; u += 64) {
+      gg += gpart[2 * (size_t)u];
+      go += gpart[2 * (size_t)u + 1];
+    }
+    gg = wave_sum(gg);
+    go = wave_sum(go);
+    beta = beta_of(st[s], gg, go);
+    if (t == ci0 && lane == 0) beta_finish(st[s], s, gg, go, 0, hist, prm);
+  } else {
+    beta = st[s].beta;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double d = -g[i] + beta * dv[i];
+    D[o + i] = d;
+    Gold[o + i] = g[i];
+    if (LOW) Dl[o + i] = cvt<TL, double>(d);
+  }
 }
 
 __global__ void k_init_finish(SysState* __restrict__ st, int nsys) {
@@ -622,21 +664,43 @@ void launch_update(hipStream_t s, const Bufs& b, Prec prec, int mask, const CGPa
            (bf16*)b.HCl, (bf16*)b.SCl, b.H0, b.S0, b.Xf, b.Yf, b.S2f, b.H2f, (bf16*)b.H0l, (bf16*)b.S0l);
 }
 
+void launch_s1(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init) {
+  if (prec == P64) launch_s1_p64(s, b, mask, init);
+  else if (prec == P32) launch_s1_p32(s, b, mask);
+  else launch_s1_pbf(s, b, mask);
+}
+
+void launch_s2(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init) {
+  if (prec == P64) launch_s2_p64(s, b, mask, init);
+  else if (prec == P32) launch_s2_p32(s, b, mask);
+  else launch_s2_pbf(s, b, mask);
+}
+
+void launch_grad(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init) {
+  (void)init;
+  if (prec == P64) launch_grad_p64(s, b, mask);
+  else if (prec == P32) launch_grad_p32(s, b, mask);
+  else launch_grad_pbf(s, b, mask);
+}
+
 void launch_beta(hipStream_t s, const Bufs& b, int mask, bool init, const CGParams& prm) {
+  if (!init && !b.multi_c) return;   // every system takes its beta in k_update_d
   LAUNCH(k_beta, dim3(b.nsys), dim3(256), s, b.info, b.st, mask, b.gpart, init ? 1 : 0, b.hist, prm);
 }
 
-void launch_update_d(hipStream_t s, const Bufs& b, Prec prec, int mask) {
+void launch_update_d(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init, const CGParams& prm) {
   if (b.n_tc <= 0) return;
+  const dim3 grid((unsigned)((b.n_tc + 3) / 4));
+  const int in = init ? 1 : 0;
   if (prec == P64)
-    LAUNCH((k_update_d<double, false>), dim3(b.n_tc), dim3(256), s, b.tc_row, b.brow_sys, b.st, mask, b.D, b.G,
-           b.Gold, (double*)nullptr);
+    LAUNCH((k_update_d<double, false>), grid, dim3(256), s, b.n_tc, b.upd_sys, b.info, b.st, mask, b.D, b.G,
+           b.Gold, (double*)nullptr, b.gpart, b.hist, prm, in);
   else if (prec == P32)
-    LAUNCH((k_update_d<float, true>), dim3(b.n_tc), dim3(256), s, b.tc_row, b.brow_sys, b.st, mask, b.D, b.G,
-           b.Gold, (float*)b.Dl);
+    LAUNCH((k_update_d<float, true>), grid, dim3(256), s, b.n_tc, b.upd_sys, b.info, b.st, mask, b.D, b.G, b.Gold,
+           (float*)b.Dl, b.gpart, b.hist, prm, in);
   else
-    LAUNCH((k_update_d<bf16, true>), dim3(b.n_tc), dim3(256), s, b.tc_row, b.brow_sys, b.st, mask, b.D, b.G,
-           b.Gold, (bf16*)b.Dl);
+    LAUNCH((k_update_d<bf16, true>), grid, dim3(256), s, b.n_tc, b.upd_sys, b.info, b.st, mask, b.D, b.G, b.Gold,
+           (bf16*)b.Dl, b.gpart, b.hist, prm, in);
 }
 
 void launch_init_finish(hipStream_t s, const Bufs& b) {

@@ -50,7 +50,8 @@ struct SysInfo {          // read-only per-system description (device)
 };
 
 struct SysState {         // mutable per-system CG state (device)
-  double E, E_prev, x, beta, gg, gnorm, ne;
+  double E, E_prev, x, beta, gnorm, ne;
+  double gg2[2];          // <G,G> of the last two gradients, slot iter & 1 (see gg_prev / gg_store)
   double c[5];
   int64_t iter, iter_fp64, restarts, refine_left;
   int phase, status, restart, steepest, prec, conv_init, pad0, pad1;

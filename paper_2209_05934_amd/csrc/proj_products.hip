@@ -96,26 +96,30 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s2(
 template <typename TI, typename TM, typename TO, int NP>
 static void s2_go(hipStream_t s, const Bufs& b, int mask, const TI* C, const TI* D, const TM* HD, const TM* SD,
                   TO* X, TO* Y, TO* S2, TO* H2) {
-  nt_ks<NT_S2>(b.s2.NT, b.ks[1], [&](auto ntc, auto ksc) {
+  if (b.s2.ngroups <= 0) return;
+  nt_ks<false>(b.s2.NT, b.ks[1], [&](auto ntc, auto ksc) {
     constexpr int N_ = decltype(ntc)::value, K_ = decltype(ksc)::value;
     LAUNCH((k_s2<TI, TM, TO, NP, K_, N_>), grid_for<K_>(b.s2.ngroups), block_for<K_>(), s, b.s2, b.tw_row,
            b.tw_col, b.wrow_sys, b.info, b.st, mask, C, D, HD, SD, X, Y, S2, H2, b.wseg);
   });
 }
 
-void launch_s2(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init, bool filter) {
-  (void)filter;
-  if (b.s2.ngroups <= 0) return;
-  if (prec == P64) {
-    if (init) s2_go<double, double, double, 2>(s, b, mask, b.C, b.C, b.HC, b.SC, b.S0, b.H0, b.S2, b.H2);
-    else s2_go<double, double, double, 4>(s, b, mask, b.C, b.D, b.HD, b.SD, b.X, b.Y, b.S2, b.H2);
-  } else if (prec == P32) {
-    s2_go<float, float, float, 4>(s, b, mask, (const float*)b.Cl, (const float*)b.Dl, b.HDf, b.SDf, b.Xf, b.Yf,
-                                  b.S2f, b.H2f);
-  } else {
-    s2_go<bf16, float, float, 4>(s, b, mask, (const bf16*)b.Cl, (const bf16*)b.Dl, b.HDf, b.SDf, b.Xf, b.Yf,
-                                 b.S2f, b.H2f);
-  }
+// one precision per object file (OMM_PREC 0: FP64, 1: FP32, 2: BF16)
+#if OMM_PREC == 0
+void launch_s2_p64(hipStream_t s, const Bufs& b, int mask, bool init) {
+  if (init) s2_go<double, double, double, 2>(s, b, mask, b.C, b.C, b.HC, b.SC, b.S0, b.H0, b.S2, b.H2);
+  else s2_go<double, double, double, 4>(s, b, mask, b.C, b.D, b.HD, b.SD, b.X, b.Y, b.S2, b.H2);
 }
+#elif OMM_PREC == 1
+void launch_s2_p32(hipStream_t s, const Bufs& b, int mask) {
+  s2_go<float, float, float, 4>(s, b, mask, (const float*)b.Cl, (const float*)b.Dl, b.HDf, b.SDf, b.Xf, b.Yf,
+                                b.S2f, b.H2f);
+}
+#else
+void launch_s2_pbf(hipStream_t s, const Bufs& b, int mask) {
+  s2_go<bf16, float, float, 4>(s, b, mask, (const bf16*)b.Cl, (const bf16*)b.Dl, b.HDf, b.SDf, b.Xf, b.Yf, b.S2f,
+                               b.H2f);
+}
+#endif
 
 }  // namespace omm

@@ -183,24 +183,25 @@ __device__ __forceinline__ void ks_chunk(const GroupView& P, int g, int wk, int 
 template <int KS> static dim3 grid_for(int n) { return dim3((unsigned)((n + Split<KS>::G - 1) / Split<KS>::G)); }
 template <int KS> static dim3 block_for() { return dim3(Split<KS>::NW * 64); }
 
-// (NT, KS) dispatch: NT is 1 or the step's group width; KS in {1,2,4,8} (at most 4 when NT > 1)
-template <int NTG, typename F>
-static void nt_ks(int nt, int ks, F&& f) {
-  if (nt == 1) {
-    switch (ks) {
-      case 8: f(std::integral_constant<int, 1>{}, std::integral_constant<int, 8>{}); break;
-      case 4: f(std::integral_constant<int, 1>{}, std::integral_constant<int, 4>{}); break;
-      case 2: f(std::integral_constant<int, 1>{}, std::integral_constant<int, 2>{}); break;
-      default: f(std::integral_constant<int, 1>{}, std::integral_constant<int, 1>{}); break;
-    }
-  } else {
-    switch (ks) {
-      case 8:
-      case 4: f(std::integral_constant<int, NTG>{}, std::integral_constant<int, 4>{}); break;
-      case 2: f(std::integral_constant<int, NTG>{}, std::integral_constant<int, 2>{}); break;
-      default: f(std::integral_constant<int, NTG>{}, std::integral_constant<int, 1>{}); break;
-    }
+// (NT, KS) dispatch: NT output tiles per wave in {1, 2, 4}, KS waves per output group in {1, 2, 4, 8}
+template <int NT, typename F>
+static void ks_of(int ks, F&& f) {
+  switch (ks) {
+    case 8: f(std::integral_constant<int, NT>{}, std::integral_constant<int, 8>{}); break;
+    case 4: f(std::integral_constant<int, NT>{}, std::integral_constant<int, 4>{}); break;
+    case 2: f(std::integral_constant<int, NT>{}, std::integral_constant<int, 2>{}); break;
+    default: f(std::integral_constant<int, NT>{}, std::integral_constant<int, 1>{}); break;
   }
+}
+// WIDE8: whether grouped plans (NT > 1) may run with KS = 8 (eight waves of a
+// workgroup share a SIMD pair and get at most 256 registers each; the n x n
+// projections hold too many accumulators for that and stop at KS = 4)
+template <bool WIDE8 = true, typename F>
+static void nt_ks(int nt, int ks, F&& f) {
+  const int kw = (!WIDE8 && ks > 4) ? 4 : ks;
+  if (nt == 4) ks_of<4>(kw, f);
+  else if (nt == 2) ks_of<2>(kw, f);
+  else ks_of<1>(ks, f);
 }
 
 }  // namespace omm
