@@ -24,25 +24,31 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s1(
   const int wave = wave_id(), lane = threadIdx.x & 63;
   const int grp = wave / KS, wk = wave - grp * KS;
   const int g = xcd_block() * SP::G + grp;
-  bool act = g < P.ngroups;
-  int s = 0, o0 = 0, cnt = 0;
-  if (act) {
-    o0 = P.go0[g];
-    cnt = P.gn[g];
-    s = brow_sys[orow[o0]];
-    act = on(st, s, mask);
+  const bool valid = g < P.ngroups;
+  constexpr int D = pipe_depth<TI>(2 + NT);
+  // group record and work-list prefetch first; the system's phase, S = I flag
+  // and filter threshold are read while the indices are in flight
+  int4 m = make_int4(0, 0, 0, 0);
+  int64_t b = 0, e = 0;
+  if (valid) {
+    m = group_meta(P, g);
+    ks_chunk(P, g, wk, KS, b, e);
   }
-  const bool ident = act && info[s].ident_s != 0;
+  EntryRounds<W, D> er(P.ent, b, e, lane);
+  const int o0 = m.x, cnt = m.y, s = m.z;
+  const int phase = ld_early(&st[s].phase);
+  const int ident_raw = ld_early(&info[s].ident_s);
+  const double e2 = ld_early(&info[s].eps2);
+  const bool act = valid && (phase & mask) != 0;
+  const bool ident = act && ident_raw != 0;
   V acc[2 * NT];
 #pragma unroll
   for (int a = 0; a < 2 * NT; ++a) acc[a] = vzero<V>();
   if (act) {
-    int64_t b, e;
-    ks_chunk(P, g, wk, KS, b, e);
     struct Stage { Frag<TI> h, s, b[NT]; };
     const TI* Sq = ident ? Hm : Sm;   // S = I: the S fragments are loaded but never used
-    run_entries<W, pipe_depth<TI>(2 + NT), Stage>(
-        P.ent, b, e, lane,
+    run_entries<W, D, Stage>(
+        er, lane,
         [&](Stage& f, const int (&id)[W]) {
           ld_row(f.h, Hm + (size_t)id[0] * TE, lane);
           ld_row(f.s, Sq + (size_t)id[0] * TE, lane);
@@ -61,7 +67,6 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s1(
   }
   ks_reduce<KS, 2 * NT>(acc, red, grp, wk, lane);
   if (!act || wk != 0) return;
-  const double e2 = info[s].eps2;
 #pragma unroll
   for (int u = 0; u < NT; ++u) {
     if (u >= cnt) break;
@@ -93,7 +98,7 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s1(
 template <typename TI, typename TO>
 static void s1_go(hipStream_t s, const Bufs& b, int mask, const TI* H, const TI* S, const TI* B, TO* O1, TO* O2) {
   if (b.s1.ngroups <= 0) return;
-  nt_ks(b.s1.NT, b.ks[0], [&](auto ntc, auto ksc) {
+  nt_ks<0>(b.s1.NT, b.ks[0], [&](auto ntc, auto ksc) {
     constexpr int N_ = decltype(ntc)::value, K_ = decltype(ksc)::value;
     LAUNCH((k_s1<TI, TO, K_, N_>), grid_for<K_>(b.s1.ngroups), block_for<K_>(), s, b.s1, b.thc_row, b.thc_col,
            b.brow_sys, b.info, b.st, mask, H, S, B, O1, O2, b.hc_to_c, b.wseg);

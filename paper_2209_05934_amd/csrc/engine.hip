@@ -93,9 +93,10 @@ struct GPlan {   // grouped work list of one product step
   int64_t nent = 0, npairs = 0;
   int *gbase = nullptr, *go0 = nullptr, *gn = nullptr, *ent = nullptr;
   int64_t* gp = nullptr;
+  int4* meta = nullptr;
   std::vector<int> hgbase;          // first group of each output row (nrows + 1)
   std::vector<int64_t> hpairs;      // prefix of tile pairs over groups (ngroups + 1)
-  GroupView view() const { return GroupView{ngroups, NT, go0, gn, gp, ent}; }
+  GroupView view() const { return GroupView{ngroups, NT, go0, gn, gp, ent, meta}; }
 };
 
 }  // namespace
@@ -746,7 +747,12 @@ void prepare(omm_ctx* c) {
     const PatView As[3] = {c->TH.view(), c->TCt.view(), c->THC.view()};
     const PatView Bs[3] = {c->TC.view(), c->THC.view(), c->TW.view()};
     for (int k = 0; k < 3; ++k) {
-      for (int q = 0; q < NPLAN; ++q) make_gplan(c, c->G[k][q], *outs[k], As[k], Bs[k], PLAN_NT[q]);
+      for (int q = 0; q < NPLAN; ++q) {
+        GPlan& G = c->G[k][q];
+        make_gplan(c, G, *outs[k], As[k], Bs[k], PLAN_NT[q]);
+        G.meta = dalloc<int4>(c, std::max(1, G.ngroups), true);
+        group_meta(st, G.ngroups, G.go0, G.gn, outs[k]->row, k == 1 ? c->wrow_sys : c->brow_sys, G.meta);
+      }
     }
   }
   make_plan(c, c->Pcm, c->TCM, c->TC.view(), c->TW.view(), c->win_bw);

@@ -24,22 +24,25 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_grad(
   const int wave = wave_id(), lane = threadIdx.x & 63;
   const int grp = wave / KS, wk = wave - grp * KS;
   const int g = xcd_block() * SP::G + grp;
-  bool act = g < P.ngroups;
-  int o0 = 0, cnt = 0;
-  if (act) {
-    o0 = P.go0[g];
-    cnt = P.gn[g];
-    act = on(st, brow_sys[tc_row[o0]], mask);
+  const bool valid = g < P.ngroups;
+  constexpr int D = pipe_depth<TI>(2 + 2 * NT);
+  int4 m = make_int4(0, 0, 0, 0);
+  int64_t b = 0, e = 0;
+  if (valid) {
+    m = group_meta(P, g);
+    ks_chunk(P, g, wk, KS, b, e);
   }
+  EntryRounds<W, D> er(P.ent, b, e, lane);
+  const int o0 = m.x, cnt = m.y;
+  const int phase = ld_early(&st[m.z].phase);
+  const bool act = valid && (phase & mask) != 0;
   V acc[NT];
 #pragma unroll
   for (int a = 0; a < NT; ++a) acc[a] = vzero<V>();
   if (act) {
-    int64_t b, e;
-    ks_chunk(P, g, wk, KS, b, e);
     struct Stage { Frag<TI> h, s, w[NT], v[NT]; };
-    run_entries<W, pipe_depth<TI>(2 + 2 * NT), Stage>(
-        P.ent, b, e, lane,
+    run_entries<W, D, Stage>(
+        er, lane,
         [&](Stage& f, const int (&id)[W]) {
           ld_row(f.h, HCm + (size_t)id[0] * TE, lane);
           ld_row(f.s, SCm + (size_t)id[0] * TE, lane);
@@ -94,7 +97,7 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_grad(
 template <typename TI>
 static void grad_go(hipStream_t s, const Bufs& b, int mask, const TI* HC, const TI* SC, const TI* S0, const TI* H0) {
   if (b.grad.ngroups <= 0) return;
-  nt_ks(b.grad.NT, b.ks[2], [&](auto ntc, auto ksc) {
+  nt_ks<2>(b.grad.NT, b.ks[2], [&](auto ntc, auto ksc) {
     constexpr int N_ = decltype(ntc)::value, K_ = decltype(ksc)::value;
     LAUNCH((k_grad<TI, K_, N_>), grid_for<K_>(b.grad.ngroups), block_for<K_>(), s, b.grad, b.tc_row, b.brow_sys,
            b.st, mask, HC, SC, S0, H0, b.HC, b.c_in_hc, b.cmask, b.Gold, b.G, b.gpart);

@@ -22,6 +22,9 @@ void rows_of(hipStream_t st, int nrows, const int* rp, int* rows);
 void group_counts(hipStream_t st, int nrows, const int* orp, int NT, int* ng);
 void group_lists(hipStream_t st, int nrows, PatView A, PatView B, PatView O, int NT, const int* gbase,
                  int64_t* gcnt, int64_t* gpres, const int64_t* gp, int* ent, int* go0, int* gn);
+// per-group record (first output tile, output tiles, system of the output row)
+void group_meta(hipStream_t st, int ngroups, const int* go0, const int* gn, const int* orow, const int* row_sys,
+                int4* meta);
 void excl_scan(hipStream_t st, const int* in, int* out, int64_t n);
 void excl_scan64(hipStream_t st, const int64_t* in, int64_t* out, int64_t n);
 
@@ -32,9 +35,11 @@ enum Prec { P64 = 0, P32 = 1, PBF = 2 };
 // grouped work lists built for every product step
 constexpr int NPLAN = 3;
 constexpr int PLAN_NT[NPLAN] = {1, 2, 4};
-// launch shape (group width NT, split KS) a product step can run: the n x n
-// projections run grouped plans with at most 4 waves per group
-inline bool plan_ok(int step, int nt, int ks) { return !(step == 1 && nt > 1 && ks > 4); }
+// largest split KS of a product step (0 direction, 1 n x n, 2 gradient) at
+// group width NT: with KS = 8 a wave has at most 256 registers, too few for
+// four output tiles, or for two of the n x n projections (four products each)
+constexpr int max_split(int step, int nt) { return (nt >= 4 || (step == 1 && nt >= 2)) ? 4 : 8; }
+inline bool plan_ok(int step, int nt, int ks) { return ks <= max_split(step, nt); }
 
 struct Bufs {   // every device buffer the iteration kernels touch
   // patterns (global tile rows/cols)

@@ -103,6 +103,7 @@ struct GroupView {
   const int* gn;
   const int64_t* gp;
   const int* ent;
+  const int4* meta;   // per group: first output tile, output tiles, system, 0
 };
 
 }  // namespace omm

@@ -23,23 +23,26 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s2(
   const int wave = wave_id(), lane = threadIdx.x & 63;
   const int grp = wave / KS, wk = wave - grp * KS;
   const int g = xcd_block() * SP::G + grp;
-  bool act = g < P.ngroups;
-  int s = 0, o0 = 0, cnt = 0;
-  if (act) {
-    o0 = P.go0[g];
-    cnt = P.gn[g];
-    s = wrow_sys[orow[o0]];
-    act = on(st, s, mask);
+  const bool valid = g < P.ngroups;
+  constexpr int D = pipe_depth<TI>((NPROD == 4 ? 2 : 1) + 2 * NT);
+  int4 m = make_int4(0, 0, 0, 0);
+  int64_t b = 0, e = 0;
+  if (valid) {
+    m = group_meta(P, g);
+    ks_chunk(P, g, wk, KS, b, e);
   }
+  EntryRounds<W, D> er(P.ent, b, e, lane);
+  const int o0 = m.x, cnt = m.y, s = m.z;
+  const int phase = ld_early(&st[s].phase);
+  const double e2 = ld_early(&info[s].eps2);
+  const bool act = valid && (phase & mask) != 0;
   V acc[NPROD * NT];
 #pragma unroll
   for (int a = 0; a < NPROD * NT; ++a) acc[a] = vzero<V>();
   if (act) {
-    int64_t b, e;
-    ks_chunk(P, g, wk, KS, b, e);
     struct Stage { Frag<TI> c, d, hd[NT], sd[NT]; };
-    run_entries<W, pipe_depth<TI>((NPROD == 4 ? 2 : 1) + 2 * NT), Stage>(
-        P.ent, b, e, lane,
+    run_entries<W, D, Stage>(
+        er, lane,
         [&](Stage& f, const int (&id)[W]) {
           ld_col(f.c, Cm + (size_t)id[0] * TE, lane);                 // A = C^T
           if (NPROD == 4) ld_col(f.d, Dm + (size_t)id[0] * TE, lane);  // A = D^T
@@ -66,7 +69,6 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s2(
   }
   ks_reduce<KS, NPROD * NT>(acc, red, grp, wk, lane);
   if (!act || wk != 0) return;
-  const double e2 = info[s].eps2;
 #pragma unroll
   for (int u = 0; u < NT; ++u) {
     if (u >= cnt) break;
@@ -97,7 +99,7 @@ template <typename TI, typename TM, typename TO, int NP>
 static void s2_go(hipStream_t s, const Bufs& b, int mask, const TI* C, const TI* D, const TM* HD, const TM* SD,
                   TO* X, TO* Y, TO* S2, TO* H2) {
   if (b.s2.ngroups <= 0) return;
-  nt_ks<false>(b.s2.NT, b.ks[1], [&](auto ntc, auto ksc) {
+  nt_ks<1>(b.s2.NT, b.ks[1], [&](auto ntc, auto ksc) {
     constexpr int N_ = decltype(ntc)::value, K_ = decltype(ksc)::value;
     LAUNCH((k_s2<TI, TM, TO, NP, K_, N_>), grid_for<K_>(b.s2.ngroups), block_for<K_>(), s, b.s2, b.tw_row,
            b.tw_col, b.wrow_sys, b.info, b.st, mask, C, D, HD, SD, X, Y, S2, H2, b.wseg);

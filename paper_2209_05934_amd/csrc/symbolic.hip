@@ -298,7 +298,22 @@ void group_lists(hipStream_t st, int nrows, PatView A, PatView B, PatView O, int
 }
 
 namespace {
+__global__ void k_group_meta(int ngroups, const int* __restrict__ go0, const int* __restrict__ gn,
+                             const int* __restrict__ orow, const int* __restrict__ row_sys, int4* __restrict__ meta) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ngroups) return;
+  const int o0 = go0[g];
+  meta[g] = make_int4(o0, gn[g], row_sys[orow[o0]], 0);
+}
 }  // namespace
+
+void group_meta(hipStream_t st, int ngroups, const int* go0, const int* gn, const int* orow, const int* row_sys,
+                int4* meta) {
+  if (ngroups <= 0) return;
+  hipLaunchKernelGGL(k_group_meta, dim3((ngroups + 255) / 256), dim3(256), 0, st, ngroups, go0, gn, orow, row_sys,
+                     meta);
+  OMM_HIP(hipGetLastError());
+}
 
 void sym_count(hipStream_t st, int nrows, int row0, PatView A, PatView B, const int2* win, int* cnt) {
   if (nrows <= 0) return;

@@ -110,38 +110,61 @@ constexpr int pipe_depth(int tiles) {
   return tiles * (int)(sizeof(Frag<T>) / 4) <= 24 ? 4 : (tiles * (int)(sizeof(Frag<T>) / 4) <= 48 ? 3 : 2);
 }
 
-// Software pipeline over the entries [b, e) of a group list (W ints each).
-// Entries go in rounds of PB (a multiple of D, at most 64 / W): a round's
-// indices sit in one register per lane, the next round's in a second one
-// fetched a round ahead, and both are read with uniform lane reads, so no
-// tile address waits on an index load.  D stages of operand fragments are in
-// flight: load(stage, idx) issues the tile loads of one entry and
-// use(stage, idx) runs its MFMAs, in entry order.  A round is unrolled in
-// full and every step issues its loads unconditionally (past the end it
-// reloads the last entry), so the compiler knows at each use exactly how
-// many younger loads are in flight and waits for that stage alone; the
-// look-ahead runs across round boundaries, so the pipeline never drains.
-template <int W, int D, typename St, typename LoadF, typename UseF>
-__device__ __forceinline__ void run_entries(const int* __restrict__ ent, int64_t b, int64_t e, int lane,
-                                            LoadF&& load, UseF&& use) {
-  constexpr int PB = (64 / W) / D * D;
+// A load issued where it is written: relaxed atomic loads are ordered memory
+// operations, which the compiler does not sink past the branches that follow,
+// so operands of later work are in flight while a data-dependent test (the
+// system's phase) resolves.
+template <typename T>
+__device__ __forceinline__ T ld_early(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
+// The entry indices of a wave's chunk [b, e) of a group list (W ints per
+// entry), in rounds of PB entries (a multiple of D, at most 64 / W): a round
+// sits in one register per lane and the next one is fetched a round ahead.
+// Constructing it issues the first two rounds' loads.
+template <int W, int D>
+struct EntryRounds {
+  static constexpr int PB = (64 / W) / D * D;
   static_assert(PB >= D, "pipeline deeper than a round");
-  const int n = (int)(e - b);
-  if (n <= 0) return;
-  const int* base = ent + b * W;
-  auto batch = [&](int r0) -> int {
+  const int* ent;
+  const int* base;
+  int n, cur, nxt;
+  // every lane loads (lanes past the round's end read the list's first word,
+  // which always exists), so the loads are not held behind a lane mask
+  __device__ __forceinline__ int batch(int r0, int lane) const {
     const int left = n - r0;
     const int cnt = left <= 0 ? 0 : (left >= PB ? PB : left);
-    return lane < cnt * W ? base[(size_t)r0 * W + lane] : 0;
-  };
-  int cur = batch(0), nxt = batch(PB);
+    return ld_early(lane < cnt * W ? base + (size_t)r0 * W + lane : ent);
+  }
+  __device__ __forceinline__ EntryRounds(const int* list, int64_t b, int64_t e, int lane)
+      : ent(list), base(list + b * W), n((int)(e - b)) {
+    cur = batch(0, lane);
+    nxt = batch(PB, lane);
+  }
+};
+
+// Software pipeline over the entries of an EntryRounds: D stages of operand
+// fragments are in flight; load(stage, idx) issues the tile loads of one
+// entry and use(stage, idx) runs its MFMAs, in entry order.  Indices are read
+// from the round registers with uniform lane reads, so no tile address waits
+// on an index load.  A round is unrolled in full and every step issues its
+// loads unconditionally (past the end it reloads the last entry), so the
+// compiler knows at each use exactly how many younger loads are in flight and
+// waits for that stage alone; the look-ahead runs across round boundaries, so
+// the pipeline never drains.
+template <int W, int D, typename St, typename LoadF, typename UseF>
+__device__ __forceinline__ void run_entries(EntryRounds<W, D>& er, int lane, LoadF&& load, UseF&& use) {
+  constexpr int PB = EntryRounds<W, D>::PB;
+  const int n = er.n;
+  if (n <= 0) return;
   St stg[D];
   int id[D][W];
 #pragma unroll
   for (int s = 0; s < D; ++s) {
     const int q = s < n ? s : n - 1;
 #pragma unroll
-    for (int w = 0; w < W; ++w) id[s][w] = __builtin_amdgcn_readlane(cur, q * W + w);
+    for (int w = 0; w < W; ++w) id[s][w] = __builtin_amdgcn_readlane(er.cur, q * W + w);
     load(stg[s], id[s]);
   }
   for (int r0 = 0;; r0 += PB) {
@@ -153,21 +176,27 @@ __device__ __forceinline__ void run_entries(const int* __restrict__ ent, int64_t
       const int q = (r0 + k + D < n ? r0 + k + D : n - 1) - r0;
       if (q < PB) {
 #pragma unroll
-        for (int w = 0; w < W; ++w) id[k % D][w] = __builtin_amdgcn_readlane(cur, q * W + w);
+        for (int w = 0; w < W; ++w) id[k % D][w] = __builtin_amdgcn_readlane(er.cur, q * W + w);
       } else {
 #pragma unroll
-        for (int w = 0; w < W; ++w) id[k % D][w] = __builtin_amdgcn_readlane(nxt, (q - PB) * W + w);
+        for (int w = 0; w < W; ++w) id[k % D][w] = __builtin_amdgcn_readlane(er.nxt, (q - PB) * W + w);
       }
       load(stg[k % D], id[k % D]);
     }
-    cur = nxt;
-    nxt = batch(r0 + 2 * PB);
+    er.cur = er.nxt;
+    er.nxt = er.batch(r0 + 2 * PB, lane);
   }
+}
+
+// group record (first output tile, output tiles, system) via early loads
+__device__ __forceinline__ int4 group_meta(const GroupView& P, int g) {
+  const int* m = reinterpret_cast<const int*>(P.meta + g);
+  return make_int4(ld_early(m), ld_early(m + 1), ld_early(m + 2), 0);
 }
 
 // chunk [b, e) of group g's entry list handled by split-wave wk
 __device__ __forceinline__ void ks_chunk(const GroupView& P, int g, int wk, int KS, int64_t& b, int64_t& e) {
-  const int64_t p0 = P.gp[g], n = P.gp[g + 1] - p0;
+  const int64_t p0 = ld_early(P.gp + g), n = ld_early(P.gp + g + 1) - p0;
   b = p0 + (n * wk) / KS;
   e = p0 + (n * (wk + 1)) / KS;
 }
@@ -183,25 +212,22 @@ __device__ __forceinline__ void ks_chunk(const GroupView& P, int g, int wk, int 
 template <int KS> static dim3 grid_for(int n) { return dim3((unsigned)((n + Split<KS>::G - 1) / Split<KS>::G)); }
 template <int KS> static dim3 block_for() { return dim3(Split<KS>::NW * 64); }
 
-// (NT, KS) dispatch: NT output tiles per wave in {1, 2, 4}, KS waves per output group in {1, 2, 4, 8}
-template <int NT, typename F>
+// (NT, KS) dispatch: NT output tiles per wave in {1, 2, 4}, KS waves per
+// output group in {1, 2, 4, 8} up to max_split(step, NT) (eight waves of a
+// workgroup get at most 256 registers each, too few for the widest groups);
+// shapes beyond the limit are neither compiled nor launched
+template <int NT, int MAXKS, typename F>
 static void ks_of(int ks, F&& f) {
-  switch (ks) {
-    case 8: f(std::integral_constant<int, NT>{}, std::integral_constant<int, 8>{}); break;
-    case 4: f(std::integral_constant<int, NT>{}, std::integral_constant<int, 4>{}); break;
-    case 2: f(std::integral_constant<int, NT>{}, std::integral_constant<int, 2>{}); break;
-    default: f(std::integral_constant<int, NT>{}, std::integral_constant<int, 1>{}); break;
-  }
+  if (MAXKS >= 8 && ks >= 8) f(std::integral_constant<int, NT>{}, std::integral_constant<int, (MAXKS >= 8 ? 8 : 1)>{});
+  else if (ks >= 4) f(std::integral_constant<int, NT>{}, std::integral_constant<int, 4>{});
+  else if (ks >= 2) f(std::integral_constant<int, NT>{}, std::integral_constant<int, 2>{});
+  else f(std::integral_constant<int, NT>{}, std::integral_constant<int, 1>{});
 }
-// WIDE8: whether grouped plans (NT > 1) may run with KS = 8 (eight waves of a
-// workgroup share a SIMD pair and get at most 256 registers each; the n x n
-// projections hold too many accumulators for that and stop at KS = 4)
-template <bool WIDE8 = true, typename F>
+template <int STEP, typename F>
 static void nt_ks(int nt, int ks, F&& f) {
-  const int kw = (!WIDE8 && ks > 4) ? 4 : ks;
-  if (nt == 4) ks_of<4>(kw, f);
-  else if (nt == 2) ks_of<2>(kw, f);
-  else ks_of<1>(ks, f);
+  if (nt == 4) ks_of<4, max_split(STEP, 4)>(ks, f);
+  else if (nt == 2) ks_of<2, max_split(STEP, 2)>(ks, f);
+  else ks_of<1, max_split(STEP, 1)>(ks, f);
 }
 
 }  // namespace omm
