@@ -133,9 +133,11 @@ struct omm_ctx {
   bool prepared = false, hs_cast = false, ran = false;
   Prec prec = P64;
   std::vector<void*> alloc_init, alloc_prep;
-  hipGraphExec_t gexec = nullptr;
+  hipGraphExec_t gexec = nullptr;       // graph_iters iterations
   hipGraph_t graph = nullptr;
-  int graph_iters = 0;
+  hipGraphExec_t gexec_small = nullptr; // graph_small iterations, for the last few
+  hipGraph_t graph_small_h = nullptr;
+  int graph_iters = 0, graph_small = 0;
   bool tuned = false;
   std::string tune_log;
   // timing
@@ -576,18 +578,24 @@ void ingest(omm_ctx* c, int count, const omm_matrix* H, const omm_matrix* S, con
   OMM_HIP(hipStreamSynchronize(st));
 }
 
+void drop_graphs(omm_ctx* c) {
+  for (hipGraphExec_t* e : {&c->gexec, &c->gexec_small})
+    if (*e) {
+      (void)hipGraphExecDestroy(*e);
+      *e = nullptr;
+    }
+  for (hipGraph_t* g : {&c->graph, &c->graph_small_h})
+    if (*g) {
+      (void)hipGraphDestroy(*g);
+      *g = nullptr;
+    }
+}
+
 // ----------------------------------------------------------------- prepare (C pattern dependent)
 void prepare(omm_ctx* c) {
   hipStream_t st = c->stream;
   OMM_HIP(hipStreamSynchronize(st));
-  if (c->gexec) {
-    (void)hipGraphExecDestroy(c->gexec);
-    c->gexec = nullptr;
-  }
-  if (c->graph) {
-    (void)hipGraphDestroy(c->graph);
-    c->graph = nullptr;
-  }
+  drop_graphs(c);
   free_list(c->alloc_prep);
   c->hs_cast = false;
   const bool low = c->prec != P64;
@@ -1021,15 +1029,8 @@ void autotune(omm_ctx* c) {
     }
   }
   c->tuned = true;
-  // the graph holds the launch shapes: capture again with the tuned choice
-  if (c->gexec) {
-    (void)hipGraphExecDestroy(c->gexec);
-    c->gexec = nullptr;
-  }
-  if (c->graph) {
-    (void)hipGraphDestroy(c->graph);
-    c->graph = nullptr;
-  }
+  // the graphs hold the launch shapes: capture again with the tuned choice
+  drop_graphs(c);
 }
 
 CGParams params(const omm_ctx* c) {
@@ -1135,8 +1136,7 @@ void scatter_c0(omm_ctx* c) {
   }
 }
 
-void capture_graph(omm_ctx* c) {
-  const int K = c->opt.graph_iters;
+void capture_graph(omm_ctx* c, int K, hipGraph_t* graph, hipGraphExec_t* exec) {
   OMM_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
   try {
     for (int k = 0; k < K; ++k) run_step(c, false);
@@ -1146,9 +1146,36 @@ void capture_graph(omm_ctx* c) {
     if (g) (void)hipGraphDestroy(g);
     throw;
   }
-  OMM_HIP(hipStreamEndCapture(c->stream, &c->graph));
-  OMM_HIP(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+  OMM_HIP(hipStreamEndCapture(c->stream, graph));
+  OMM_HIP(hipGraphInstantiate(exec, *graph, nullptr, nullptr, 0));
+}
+
+void capture_graphs(omm_ctx* c) {
+  const int K = c->opt.graph_iters;
+  capture_graph(c, K, &c->graph, &c->gexec);
   c->graph_iters = K;
+  c->graph_small = std::max(1, K / 4);
+  if (c->graph_small < K) capture_graph(c, c->graph_small, &c->graph_small_h, &c->gexec_small);
+}
+
+// Iterations a system still needs, predicted from the state read after the
+// previous replay: the FP64 refinement count when it is refining, else the
+// iterations the gradient norm needs to reach the tolerance at its observed
+// rate of decrease (a large number when that rate is unknown or not < 1).
+double predict_left(const SysState& now, const SysState& before, double tol_grad, int64_t max_iter) {
+  const double big = 1e30;
+  if (now.phase == PH_FP64 && now.refine_left > 0) return (double)now.refine_left;
+  double left = (double)(max_iter - now.iter);
+  const int64_t di = now.iter - before.iter;
+  if (di > 0 && now.gnorm > 0.0 && before.gnorm > now.gnorm && tol_grad > 0.0) {
+    const double rate = std::pow(now.gnorm / before.gnorm, 1.0 / (double)di);
+    if (rate < 1.0) left = std::min(left, std::log(tol_grad / now.gnorm) / std::log(rate));
+  } else if (now.phase == PH_LOW || !(now.gnorm > 0.0)) {
+    return big;
+  } else {
+    left = std::min(left, big);
+  }
+  return std::max(0.0, left);
 }
 
 int minimize(omm_ctx* c, omm_report* reps) {
@@ -1179,11 +1206,14 @@ int minimize(omm_ctx* c, omm_report* reps) {
   init_sequence(c);
   if (c->opt.autotune && !c->tuned) autotune(c);
   const bool use_graph = c->opt.graph_iters > 0 && !c->timing;
-  if (use_graph && !c->gexec) capture_graph(c);
+  if (use_graph && !c->gexec) capture_graphs(c);
   const int K = use_graph ? c->graph_iters : std::max(1, c->opt.graph_iters > 0 ? c->opt.graph_iters : 1);
   int64_t steps = 0, reinits = 0, waited = 0;
   const int64_t max_steps = c->opt.max_iter + 8 * (int64_t)K + 64;
+  std::vector<SysState> before(c->nsys);
+  int last_k = 0;
   while (true) {
+    if (last_k > 0) std::copy(c->h_st, c->h_st + c->nsys, before.begin());
     OMM_HIP(hipMemcpyAsync(c->h_st, c->d_st, sizeof(SysState) * c->nsys, hipMemcpyDeviceToHost, st));
     OMM_HIP(hipStreamSynchronize(st));
     if (c->timing) collect_timing(c);
@@ -1204,10 +1234,20 @@ int minimize(omm_ctx* c, omm_report* reps) {
       continue;
     }
     if (steps >= max_steps) throw DeviceError("iteration loop exceeded its bound");
-    if (use_graph) OMM_HIP(hipGraphLaunch(c->gexec, st));
+    int k_run = K;
+    if (use_graph && c->gexec_small && last_k > 0) {
+      // the long graph unless every active system is predicted to finish within it
+      double left = 0.0;
+      for (int i = 0; i < c->nsys; ++i)
+        if ((c->h_st[i].phase & (PH_LOW | PH_FP64)) != 0)
+          left = std::max(left, predict_left(c->h_st[i], before[i], c->opt.tol_grad, c->opt.max_iter));
+      if (left < (double)K) k_run = c->graph_small;
+    }
+    if (use_graph) OMM_HIP(hipGraphLaunch(k_run == K ? c->gexec : c->gexec_small, st));
     else
       for (int k = 0; k < K; ++k) run_step(c, c->timing);
-    steps += K;
+    steps += k_run;
+    last_k = k_run;
   }
   // electron count at the final C
   launch_traces(st, c->b, P64, PH_DONE, true, LS_REPORT, params(c));
@@ -1654,8 +1694,7 @@ void omm_destroy(omm_ctx* c) {
     (void)hipEventDestroy(c->ev[k]);
     (void)hipEventDestroy(c->ev[k + 1]);
   }
-  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
-  if (c->graph) (void)hipGraphDestroy(c->graph);
+  drop_graphs(c);
   free_list(c->alloc_prep);
   free_list(c->alloc_init);
   if (c->h_st) (void)hipHostFree(c->h_st);
