@@ -65,13 +65,20 @@ __device__ void filter_tile(V& acc, int lane, const uint8_t* __restrict__ rseg,
 // waves; KS consecutive waves split the pair list of one output tile into KS
 // contiguous chunks and add their accumulators in a fixed tree through LDS, so
 // results are bitwise reproducible for a given KS.  Logical block ids are
-// renumbered so that consecutive ids (neighbouring output tiles, which share
-// operand tiles) run on the same XCD: the hardware deals workgroups to the 8
-// XCDs round-robin.
+// renumbered so that runs of XCD_RUN consecutive ids (neighbouring output
+// tiles, which share operand tiles) run on one XCD while successive runs go to
+// successive XCDs: the hardware deals workgroups to the 8 XCDs round-robin, so
+// physical block p runs on XCD p % 8 as its (p / 8)-th block there.  Every
+// part of the grid (every system of a batch) is thereby spread over all XCDs.
+// Blocks of an incomplete last round of 8 runs keep their own id, which keeps
+// the renumbering a bijection.
+constexpr int XCD_RUN = 16;
 __device__ __forceinline__ int xcd_block() {
-  const int nb = gridDim.x, b = blockIdx.x;
-  const int x = b & 7, q = nb >> 3, r = nb & 7;
-  return x * q + min(x, r) + (b >> 3);
+  const int nb = gridDim.x, p = blockIdx.x;
+  const int full = nb - nb % (8 * XCD_RUN);
+  if (p >= full) return p;
+  const int x = p & 7, k = p >> 3;
+  return ((k / XCD_RUN) * 8 + x) * XCD_RUN + (k % XCD_RUN);
 }
 
 template <int KS> struct Split {
