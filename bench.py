@@ -48,11 +48,42 @@ BATCH_DESC = ("64 independent systems, n^3 cubic lattices with n uniform in 3..7
 PEAKS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}   # dense TFLOP/s of MI355X
 
 # HBM bytes per launch of a product step from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
-# (calibrated against a plain copy; profiles/traffic_*.md), keyed by workload,
-# precision, step, group width and split, and valid only for the kernel sources
-# they were taken with (sha256 prefix of numeric.hip + tile_ops.hpp)
+# (calibrated against a plain device copy), keyed by workload, precision, step,
+# group width and split, and valid only for the kernel sources they were taken
+# with (sha256 prefix of the step's source file, tile_sched.hpp and tile_ops.hpp)
 MEASURED_TRAFFIC = {
-    ("cubic4_dense", "fp64", 0, 1, 8): (20.714e6, "9f77ea518ff88d7f"),
+    ("cubic4_dense", "fp64", 0, 1, 1): (2.7736e+07, "86cde6dee51aac85"),
+    ("cubic4_dense", "fp64", 0, 1, 2): (3.2829e+07, "86cde6dee51aac85"),
+    ("cubic4_dense", "fp64", 0, 1, 4): (2.5921e+07, "86cde6dee51aac85"),
+    ("cubic4_dense", "fp64", 0, 1, 8): (2.5887e+07, "86cde6dee51aac85"),
+    ("cubic4_dense", "fp64", 0, 2, 1): (1.9993e+07, "86cde6dee51aac85"),
+    ("cubic4_dense", "fp64", 0, 2, 2): (2.7699e+07, "86cde6dee51aac85"),
+    ("cubic4_dense", "fp64", 0, 2, 4): (3.2755e+07, "86cde6dee51aac85"),
+    ("cubic4_dense", "fp64", 0, 2, 8): (3.2710e+07, "86cde6dee51aac85"),
+    ("cubic4_dense", "fp64", 0, 4, 1): (2.0025e+07, "86cde6dee51aac85"),
+    ("cubic4_dense", "fp64", 0, 4, 2): (2.0056e+07, "86cde6dee51aac85"),
+    ("cubic4_dense", "fp64", 0, 4, 4): (2.7787e+07, "86cde6dee51aac85"),
+    ("cubic4_dense", "fp64", 1, 1, 1): (1.1065e+07, "1d3bc30ee9289b9a"),
+    ("cubic4_dense", "fp64", 1, 1, 2): (1.1054e+07, "1d3bc30ee9289b9a"),
+    ("cubic4_dense", "fp64", 1, 1, 4): (1.6097e+07, "1d3bc30ee9289b9a"),
+    ("cubic4_dense", "fp64", 1, 1, 8): (1.6044e+07, "1d3bc30ee9289b9a"),
+    ("cubic4_dense", "fp64", 1, 2, 1): (1.6211e+07, "1d3bc30ee9289b9a"),
+    ("cubic4_dense", "fp64", 1, 2, 2): (1.1130e+07, "1d3bc30ee9289b9a"),
+    ("cubic4_dense", "fp64", 1, 2, 4): (1.1078e+07, "1d3bc30ee9289b9a"),
+    ("cubic4_dense", "fp64", 1, 4, 1): (9.2577e+06, "1d3bc30ee9289b9a"),
+    ("cubic4_dense", "fp64", 1, 4, 2): (1.6346e+07, "1d3bc30ee9289b9a"),
+    ("cubic4_dense", "fp64", 1, 4, 4): (1.1292e+07, "1d3bc30ee9289b9a"),
+    ("cubic4_dense", "fp64", 2, 1, 1): (6.3694e+06, "48f45cd5311d578b"),
+    ("cubic4_dense", "fp64", 2, 1, 2): (7.6624e+06, "48f45cd5311d578b"),
+    ("cubic4_dense", "fp64", 2, 1, 4): (6.5919e+06, "48f45cd5311d578b"),
+    ("cubic4_dense", "fp64", 2, 1, 8): (6.5827e+06, "48f45cd5311d578b"),
+    ("cubic4_dense", "fp64", 2, 2, 1): (5.7386e+06, "48f45cd5311d578b"),
+    ("cubic4_dense", "fp64", 2, 2, 2): (6.3734e+06, "48f45cd5311d578b"),
+    ("cubic4_dense", "fp64", 2, 2, 4): (7.6829e+06, "48f45cd5311d578b"),
+    ("cubic4_dense", "fp64", 2, 2, 8): (7.6593e+06, "48f45cd5311d578b"),
+    ("cubic4_dense", "fp64", 2, 4, 1): (5.8111e+06, "48f45cd5311d578b"),
+    ("cubic4_dense", "fp64", 2, 4, 2): (5.7575e+06, "48f45cd5311d578b"),
+    ("cubic4_dense", "fp64", 2, 4, 4): (6.4368e+06, "48f45cd5311d578b"),
 }
 
 
@@ -68,6 +99,7 @@ def kernel_source_hash(step: int) -> str:
             h.update(fh.read())
     return h.hexdigest()[:16]
 HBM_PEAK = 8000.0                                         # GB/s
+TIMING_REPS = 20                                          # back-to-back launches per timed product step
 
 
 def parse():
@@ -266,18 +298,15 @@ def main():
     value = iters / dt
     flops_iter = sz.flops_alg_iter
 
-    # per-kernel device time with HIP events on the library's stream
+    # per-launch device time of each product step with HIP events on the
+    # library's stream: TIMING_REPS launches back to back (the tuned shape, the
+    # operands of the last solve)
     roof = None
     if not args.no_kernel_timing:
-        ctx.set_timing(True)
-        nstep = max(1, min(args.steps, 5))
-        for _ in range(nstep):
-            step()
-        ctx.set_timing(False)
-        ms, n = ctx.kernel_times()
         names = ["direction products (H D, S D)", "n x n projections", "gradient products"]
-        k = int(np.argmax(ms))
-        avg_s = ms[k] / max(1, n[k]) / 1e3
+        avg_ms = [ctx.time_step(i, TIMING_REPS) for i in range(3)]
+        k = int(np.argmax(avg_ms))
+        avg_s = avg_ms[k] / 1e3
         if args.precision == "bf16":
             achieved = sz.bytes_alg_step[k] / avg_s / 1e9
             roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK, "unit": "GB/s",
@@ -291,11 +320,11 @@ def main():
         if tk in MEASURED_TRAFFIC and MEASURED_TRAFFIC[tk][1] == kernel_source_hash(k):
             roof["traffic"] = MEASURED_TRAFFIC[tk][0]
         roof.update({"kernel": names[k], "tile_group": int(sz.tile_group[k]), "tile_split": int(sz.tile_split[k]),
-                     "avg_launch_us": avg_s * 1e6, "launches": int(n[k]),
+                     "avg_launch_us": avg_s * 1e6, "launches": TIMING_REPS,
                      "alg_flops_per_launch": sz.flops_alg_step[k],
                      "exec_flops_per_launch": sz.flops_exec_step[k],
                      "alg_bytes_per_launch": sz.bytes_alg_step[k],
-                     "class_ms": {names[i]: ms[i] for i in range(3)}})
+                     "step_us": {names[i]: avg_ms[i] * 1e3 for i in range(3)}})
 
     out = {
         "metric": METRIC,

@@ -218,6 +218,17 @@ int omm_query(const omm_ctx* ctx, int32_t sys, omm_sizes* sizes);
 int omm_set_timing(omm_ctx* ctx, int32_t enable);
 int omm_kernel_times(const omm_ctx* ctx, double* ms, int64_t* launches);
 
+/* Average device time in milliseconds (*avg_ms) of one launch of product step
+ * `step` (0: direction products H D, S D; 1: n x n projections; 2: gradient
+ * products), over `reps` (1..100000) launches issued back to back on the
+ * context's stream between two HIP events, after one untimed launch.  It uses
+ * the context's tuned launch shape and its product precision (the low
+ * precision of a mixed run) on the operands of the last omm_minimize, which
+ * must have run (else OMM_ERR_STATE); it overwrites only intermediate
+ * products, so coefficients, energies and density matrices are unchanged.
+ * Blocks until the timing is done. */
+int omm_time_step(omm_ctx* ctx, int32_t step, int32_t reps, double* avg_ms);
+
 /* Name of a status code. */
 const char* omm_status_str(int32_t status);
 

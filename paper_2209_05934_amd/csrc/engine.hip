@@ -1687,6 +1687,44 @@ int omm_kernel_times(const omm_ctx* c, double* ms, int64_t* launches) {
   return OMM_OK;
 }
 
+int omm_time_step(omm_ctx* c, int32_t step, int32_t reps, double* avg_ms) {
+  if (!c) return OMM_ERR_ARG;
+  if (step < 0 || step > 2 || reps < 1 || reps > 100000 || !avg_ms) {
+    c->err = "bad argument";
+    return OMM_ERR_ARG;
+  }
+  if (!c->ran) {
+    c->err = "omm_minimize must run before omm_time_step";
+    return OMM_ERR_STATE;
+  }
+  struct A { int step, reps; double* out; } a{step, reps, avg_ms};
+  return guard(c, [](omm_ctx* cc, void* v) -> int {
+    auto* q = (A*)v;
+    // every phase: after the solve all systems are done, and the products of
+    // the final operands are recomputed in full (outputs no result depends on)
+    const int mask = PH_INIT | PH_LOW | PH_FP64 | PH_DONE;
+    hipEvent_t e0, e1;
+    OMM_HIP(hipEventCreate(&e0));
+    OMM_HIP(hipEventCreate(&e1));
+    auto launch = [&]() {
+      if (q->step == 0) launch_s1(cc->stream, cc->b, cc->prec, mask, false);
+      else if (q->step == 1) launch_s2(cc->stream, cc->b, cc->prec, mask, false);
+      else launch_grad(cc->stream, cc->b, cc->prec, mask, false);
+    };
+    launch();   // warm
+    OMM_HIP(hipEventRecord(e0, cc->stream));
+    for (int r = 0; r < q->reps; ++r) launch();
+    OMM_HIP(hipEventRecord(e1, cc->stream));
+    OMM_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    OMM_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *q->out = (double)ms / q->reps;
+    return OMM_OK;
+  }, &a);
+}
+
 void omm_destroy(omm_ctx* c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);

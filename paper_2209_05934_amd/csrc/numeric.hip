@@ -187,10 +187,10 @@ __global__ __launch_bounds__(256) void k_traces(const int4* __restrict__ chunks,
                                               const double* __restrict__ H0, const double* __restrict__ S0,
                                               const TN* __restrict__ X, const TN* __restrict__ Y,
                                               const TN* __restrict__ S2, const TN* __restrict__ H2,
-                                              double* __restrict__ part) {
+                                              double* __restrict__ part, int single) {
   __shared__ double red[4][NSUM];
   const int4 ch = chunks[blockIdx.x];
-  if (!on(st, ch.z, mask)) return;
+  if (!on(st, single ? 0 : ch.z, mask)) return;   // one system: the phase load need not wait for the chunk
   double a[NSUM];
 #pragma unroll
   for (int k = 0; k < NSUM; ++k) a[k] = 0.0;
@@ -291,7 +291,7 @@ __global__ __launch_bounds__(256) void k_update(int nc, int nhc, int ntot, const
   const int T = blockIdx.x * 4 + wave_id();
   if (T >= ntot) return;
   const int lane = threadIdx.x & 63;
-  const int s = upd_sys[T];
+  const int s = upd_sys ? upd_sys[T] : 0;   // null: a single system
   if (!on(st, s, mask)) return;
   const int ch0 = info[s].ch0, ch1 = info[s].ch1;
   const int kind = T < nc ? 0 : (T < nc + nhc ? 1 : 2);
@@ -462,7 +462,7 @@ __global__ __launch_bounds__(256) void k_update_d(int nc, const int* __restrict_
   const int t = blockIdx.x * 4 + wave_id();
   if (t >= nc) return;
   const int lane = threadIdx.x & 63;
-  const int s = upd_sys[t];
+  const int s = upd_sys ? upd_sys[t] : 0;   // null: a single system
   if (!on(st, s, mask)) return;
   if (LOW && st[s].prec == 0) return;
   const int ci0 = info[s].c0, ci1 = info[s].c1;
@@ -633,13 +633,13 @@ void launch_traces(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init_
   if (prec == P64) {
     if (init_inputs)   // X = S0, Y = H0, S2 = S0, H2 = H0: the sums then hold Tr H0, <S0,H0>, Tr S0, <S0,S0>
       LAUNCH(k_traces<double>, dim3(b.nchunks), dim3(256), s, b.chunks, b.st, mask, b.w_tr, b.H0, b.S0, b.S0,
-             b.H0, b.S0, b.H0, b.tpart);
+             b.H0, b.S0, b.H0, b.tpart, b.nsys == 1 ? 1 : 0);
     else
       LAUNCH(k_traces<double>, dim3(b.nchunks), dim3(256), s, b.chunks, b.st, mask, b.w_tr, b.H0, b.S0, b.X, b.Y,
-             b.S2, b.H2, b.tpart);
+             b.S2, b.H2, b.tpart, b.nsys == 1 ? 1 : 0);
   } else {
     LAUNCH(k_traces<float>, dim3(b.nchunks), dim3(256), s, b.chunks, b.st, mask, b.w_tr, b.H0, b.S0, b.Xf, b.Yf,
-           b.S2f, b.H2f, b.tpart);
+           b.S2f, b.H2f, b.tpart, b.nsys == 1 ? 1 : 0);
   }
   if (mode != LS_STEP || b.multi_chunk)
     LAUNCH(k_ls_state, dim3(b.nsys), dim3(64), s, b.info, b.st, mask, b.tpart, mode, prm.refine_iters);
@@ -650,16 +650,16 @@ void launch_update(hipStream_t s, const Bufs& b, Prec prec, int mask, const CGPa
   if (nt <= 0) return;
   const dim3 grid((unsigned)((nt + 3) / 4));
   if (prec == P64)
-    LAUNCH((k_update<double, double, false>), grid, dim3(256), s, b.n_tc, b.n_thc, nt, b.upd_sys, b.w_tr, b.info,
+    LAUNCH((k_update<double, double, false>), grid, dim3(256), s, b.n_tc, b.n_thc, nt, b.nsys == 1 ? nullptr : b.upd_sys, b.w_tr, b.info,
            b.st, mask, b.tpart, prm.refine_iters, b.C, b.D, (double*)nullptr, b.HC, b.SC, b.HD, b.SD,
            (double*)nullptr, (double*)nullptr, b.H0, b.S0, b.X, b.Y, b.S2, b.H2, (double*)nullptr,
            (double*)nullptr);
   else if (prec == P32)
-    LAUNCH((k_update<float, float, true>), grid, dim3(256), s, b.n_tc, b.n_thc, nt, b.upd_sys, b.w_tr, b.info,
+    LAUNCH((k_update<float, float, true>), grid, dim3(256), s, b.n_tc, b.n_thc, nt, b.nsys == 1 ? nullptr : b.upd_sys, b.w_tr, b.info,
            b.st, mask, b.tpart, prm.refine_iters, b.C, b.D, (float*)b.Cl, b.HC, b.SC, b.HDf, b.SDf,
            (float*)b.HCl, (float*)b.SCl, b.H0, b.S0, b.Xf, b.Yf, b.S2f, b.H2f, (float*)b.H0l, (float*)b.S0l);
   else
-    LAUNCH((k_update<bf16, float, true>), grid, dim3(256), s, b.n_tc, b.n_thc, nt, b.upd_sys, b.w_tr, b.info,
+    LAUNCH((k_update<bf16, float, true>), grid, dim3(256), s, b.n_tc, b.n_thc, nt, b.nsys == 1 ? nullptr : b.upd_sys, b.w_tr, b.info,
            b.st, mask, b.tpart, prm.refine_iters, b.C, b.D, (bf16*)b.Cl, b.HC, b.SC, b.HDf, b.SDf,
            (bf16*)b.HCl, (bf16*)b.SCl, b.H0, b.S0, b.Xf, b.Yf, b.S2f, b.H2f, (bf16*)b.H0l, (bf16*)b.S0l);
 }
@@ -693,13 +693,13 @@ void launch_update_d(hipStream_t s, const Bufs& b, Prec prec, int mask, bool ini
   const dim3 grid((unsigned)((b.n_tc + 3) / 4));
   const int in = init ? 1 : 0;
   if (prec == P64)
-    LAUNCH((k_update_d<double, false>), grid, dim3(256), s, b.n_tc, b.upd_sys, b.info, b.st, mask, b.D, b.G,
+    LAUNCH((k_update_d<double, false>), grid, dim3(256), s, b.n_tc, b.nsys == 1 ? nullptr : b.upd_sys, b.info, b.st, mask, b.D, b.G,
            b.Gold, (double*)nullptr, b.gpart, b.hist, prm, in);
   else if (prec == P32)
-    LAUNCH((k_update_d<float, true>), grid, dim3(256), s, b.n_tc, b.upd_sys, b.info, b.st, mask, b.D, b.G, b.Gold,
+    LAUNCH((k_update_d<float, true>), grid, dim3(256), s, b.n_tc, b.nsys == 1 ? nullptr : b.upd_sys, b.info, b.st, mask, b.D, b.G, b.Gold,
            (float*)b.Dl, b.gpart, b.hist, prm, in);
   else
-    LAUNCH((k_update_d<bf16, true>), grid, dim3(256), s, b.n_tc, b.upd_sys, b.info, b.st, mask, b.D, b.G, b.Gold,
+    LAUNCH((k_update_d<bf16, true>), grid, dim3(256), s, b.n_tc, b.nsys == 1 ? nullptr : b.upd_sys, b.info, b.st, mask, b.D, b.G, b.Gold,
            (bf16*)b.Dl, b.gpart, b.hist, prm, in);
 }
 

@@ -93,6 +93,7 @@ def load(path: Optional[str] = None) -> C.CDLL:
         "omm_query": (I32, [P, I32, C.POINTER(omm_sizes)]),
         "omm_set_timing": (I32, [P, I32]),
         "omm_kernel_times": (I32, [P, C.POINTER(D), C.POINTER(I64)]),
+        "omm_time_step": (I32, [P, I32, I32, C.POINTER(D)]),
         "omm_status_str": (C.c_char_p, [I32]),
         "omm_last_error": (C.c_char_p, [P]),
         "omm_destroy": (None, [P]),
@@ -107,7 +108,7 @@ def load(path: Optional[str] = None) -> C.CDLL:
 
 EXPORTED = ("omm_default_options", "omm_init", "omm_init_batch", "omm_set_coeffs", "omm_minimize",
             "omm_density_matrix", "omm_get_coeffs", "omm_get_projected", "omm_get_history", "omm_query",
-            "omm_set_timing", "omm_kernel_times", "omm_status_str", "omm_last_error", "omm_destroy")
+            "omm_set_timing", "omm_kernel_times", "omm_time_step", "omm_status_str", "omm_last_error", "omm_destroy")
 
 
 class OmmError(RuntimeError):
@@ -250,6 +251,13 @@ def omm_kernel_times(ctx):
     n = (C.c_int64 * 3)()
     _check(ctx, load().omm_kernel_times(ctx, ms, n))
     return list(ms), list(n)
+
+
+def omm_time_step(ctx, step: int, reps: int = 20) -> float:
+    """Average milliseconds of one launch of product step `step` (see omm.h)."""
+    v = C.c_double()
+    _check(ctx, load().omm_time_step(ctx, int(step), int(reps), C.byref(v)))
+    return v.value
 
 
 def omm_destroy(ctx) -> None:

@@ -96,6 +96,9 @@ class Context:
     def kernel_times(self):
         return L.omm_kernel_times(self.ctx)
 
+    def time_step(self, step: int, reps: int = 20) -> float:
+        return L.omm_time_step(self.ctx, step, reps)
+
     def close(self) -> None:
         if getattr(self, "ctx", None):
             L.omm_destroy(self.ctx)

@@ -194,3 +194,24 @@ def test_call_order_and_electron_count_check():
     assert r.status == L.OMM_ERR_ELECTRON_COUNT
     assert abs(r.electron_count - 2 * s.n) > 1e-12
     ctx.close()
+
+
+def test_time_step_leaves_the_solution_unchanged():
+    s = system("cubic4_dense")
+    ctx = Context([Problem(s.H, s.S, s.C0, s.n, L.OMM_DENSE)])
+    with pytest.raises(L.OmmError) as e:   # no solve yet
+        ctx.time_step(0, 2)
+    assert e.value.status == L.OMM_ERR_STATE
+    rc, reps = ctx.minimize()
+    c0, rho0 = ctx.coeffs(0), ctx.density_matrix(0)
+    HW0, SW0 = ctx.projected(0)
+    ms = [ctx.time_step(k, 5) for k in range(3)]
+    assert all(m > 0.0 for m in ms), ms
+    assert np.array_equal(ctx.coeffs(0), c0)
+    assert np.array_equal(ctx.density_matrix(0), rho0)
+    HW1, SW1 = ctx.projected(0)
+    assert np.array_equal(HW1, HW0) and np.array_equal(SW1, SW0)
+    with pytest.raises(L.OmmError) as e:   # bad step index
+        ctx.time_step(3, 2)
+    assert e.value.status == L.OMM_ERR_ARG
+    ctx.close()
