@@ -98,7 +98,9 @@ typedef struct {
   int32_t fp64_refine_iters;/* mixed precision: FP64 iterations after the low-precision
                                phase; <= 0 means FP64 until the stop rule; default 5 */
   double lowprec_rel_switch;/* mixed precision: relative energy change that ends the
-                               low-precision phase; <= 0 picks 1e-7 (FP32) / 1e-5 (BF16) */
+                               low-precision phase (so does meeting the stop rule, a
+                               failed steepest-descent line search, or lowprec_max_iter);
+                               <= 0 picks 1e-9 (FP32) / 1e-5 (BF16) */
   int64_t lowprec_max_iter; /* mixed precision: cap on low-precision iterations; default max_iter */
   int32_t graph_iters;      /* CG iterations per captured hipGraph replay; <= 0: eager
                                launches; default 16 */

@@ -1037,7 +1037,7 @@ CGParams params(const omm_ctx* c) {
   CGParams p{};
   p.tol_grad = c->opt.tol_grad;
   p.rel_tol = c->opt.rel_tol;
-  p.low_switch = c->opt.lowprec_rel_switch > 0 ? c->opt.lowprec_rel_switch : (c->prec == PBF ? 1e-5 : 1e-7);
+  p.low_switch = c->opt.lowprec_rel_switch > 0 ? c->opt.lowprec_rel_switch : (c->prec == PBF ? 1e-5 : 1e-9);
   p.filter_eps = c->opt.filter_eps;
   p.max_iter = c->opt.max_iter;
   p.low_max_iter = c->opt.lowprec_max_iter > 0 ? c->opt.lowprec_max_iter : c->opt.max_iter;

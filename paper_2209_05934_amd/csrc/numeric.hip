@@ -394,16 +394,15 @@ __device__ void beta_finish(SysState& S, int s, double gg, double go, int init, 
     h[6] = S.x; h[7] = gn; h[8] = beta; h[9] = (double)S.restart; h[10] = (double)S.prec;
   }
   const double rel = (S.E + S.E_prev) != 0.0 ? fabs(2.0 * (S.E - S.E_prev) / (S.E + S.E_prev)) : 0.0;
-  if (gn <= prm.tol_grad) {
-    S.status = OMM_OK;
-    S.phase = PH_DONE;
-  } else if (prm.rel_tol > 0.0 && !S.restart && rel < prm.rel_tol) {
-    S.status = OMM_OK;
-    S.phase = PH_DONE;
-  } else if (S.phase == PH_LOW && ((!S.restart && rel < prm.low_switch) || S.iter >= prm.low_max_iter)) {
-    S.phase = PH_INIT;          // recompute everything in FP64 from C, then refine
-    S.prec = 0;
+  const bool stop = gn <= prm.tol_grad || (prm.rel_tol > 0.0 && !S.restart && rel < prm.rel_tol);
+  if (S.phase == PH_LOW &&
+      (stop || (!S.restart && rel < prm.low_switch) || S.iter >= prm.low_max_iter)) {
+    S.phase = PH_INIT;          // recompute everything in FP64 from C, then refine: the
+    S.prec = 0;                 // stop rule ends a run only in FP64
     S.refine_left = prm.refine_iters > 0 ? prm.refine_iters : -1;
+  } else if (stop) {
+    S.status = OMM_OK;
+    S.phase = PH_DONE;
   } else if (S.phase == PH_FP64 && S.refine_left > 0 && --S.refine_left == 0) {
     S.status = OMM_OK;
     S.phase = PH_DONE;
