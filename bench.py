@@ -12,6 +12,7 @@ steps.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import tempfile
 import json
 import os
 import sys
@@ -118,6 +119,9 @@ def parse():
                     help="only run 5 device-to-device copies of BYTES (HBM counter calibration)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the heuristic work split of the tile products instead of timing the variants")
+    ap.add_argument("--to-accuracy", action="store_true",
+                    help="sparse workloads: time FP64, FP32 + 5 FP64 and BF16 + 5 FP64 solves to the same "
+                         "stop rule (relative energy change < 1e-9) and report each energy/atom against FP64")
     return ap.parse_args()
 
 
@@ -234,6 +238,76 @@ def batch_main(args):
     print(json.dumps(out), flush=True)
 
 
+def accuracy_main(args):
+    """Time to the same accuracy: FP64, FP32 + 5 FP64 and BF16 + 5 FP64 solves of one sparse system to
+    the stop rule |2(E_n - E_n-1)/(E_n + E_n-1)| < 1e-9, each energy/atom against the FP64 one (the
+    mixed-precision target is 1e-5 Ha/atom).  Each solve is timed from a fresh context, minus the time
+    of a one-iteration solve of the same kind (set-up: symbolic phase, graph capture)."""
+    import torch
+    from ommgen import config_spec, make_system
+    from paper_2209_05934_amd import omm as L
+    from paper_2209_05934_amd.solver import Context, Problem
+
+    wl = WORKLOADS[args.workload]
+    if wl["mode"] != "sparse":
+        raise SystemExit("--to-accuracy applies to the block-sparse workloads")
+    spec = config_spec(wl["cfg"])
+    system = make_system(spec)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    Hv, Sv, C0v = (torch.from_numpy(a).to(dev) for a in (system.H.val, system.S.val, system.C0.val))
+    max_iter = args.max_iter or 20000
+    cache = os.path.join(tempfile.gettempdir(), f"omm_tune_{os.getpid()}.txt")
+    prec_of = {"fp64": L.OMM_FP64, "fp32": L.OMM_FP32, "bf16": L.OMM_BF16}
+
+    def solve(prec, mi):
+        prob = Problem(system.H, system.S, system.C0, system.n, L.OMM_BLOCK_SPARSE, H_val=Hv, S_val=Sv,
+                       C0_val=C0v)
+        ctx = Context([prob], eta=spec.eta, tol_grad=1e-9, rel_tol=1e-9, max_iter=mi, precision=prec_of[prec],
+                      filter_eps=spec.filter_eps, fp64_refine_iters=5, lowprec_max_iter=max(1, mi - 10),
+                      graph_iters=args.graph_iters, history=0, hip_stream=stream.cuda_stream,
+                      autotune=0 if args.no_autotune else 1, tune_cache=cache.encode())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.set_coeffs(0, system.C0, C0v)
+        rc, reps = ctx.minimize()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ctx.close()
+        return dt, reps[0]
+
+    res = {}
+    for prec in ("fp64", "fp32", "bf16"):
+        solve(prec, 2)                   # fills the autotune cache for this precision
+        t1, _ = solve(prec, 1)
+        tn, r = solve(prec, max_iter)
+        res[prec] = {"seconds": tn - t1, "iters": int(r.iters_total), "iters_fp64": int(r.iters_fp64),
+                     "energy_per_atom": r.energy / system.natoms, "status": L.omm_status_str(r.status)}
+        print(f"{prec}: {res[prec]['iters']} iterations in {res[prec]['seconds']:.2f} s", file=sys.stderr,
+              flush=True)
+    e64 = res["fp64"]["energy_per_atom"]
+    for prec, v in res.items():
+        v["abs_dE_per_atom_vs_fp64"] = abs(v["energy_per_atom"] - e64)
+        v["within_1e-5"] = v["abs_dE_per_atom_vs_fp64"] <= 1e-5
+        v["speedup_vs_fp64"] = res["fp64"]["seconds"] / v["seconds"]
+        v["cg_iters_per_s"] = v["iters"] / v["seconds"]
+    try:
+        os.remove(cache)
+    except OSError:
+        pass
+    out = {
+        "metric": METRIC, "value": res["fp32"]["cg_iters_per_s"], "unit": "CG iters/s", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": res["fp32"]["seconds"] * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 products (then f64 iterations), f64 traces/line search", "data": "synthetic",
+        "config": {"workload": args.workload + ": " + wl["desc"].rsplit(", ", 1)[0]
+                   + ", each precision to the stop rule |dE/E| < 1e-9", "atoms": int(system.natoms)},
+        "to_accuracy": res,
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -252,6 +326,8 @@ def main():
         return
     if args.workload == "batch64":
         return batch_main(args)
+    if args.to_accuracy:
+        return accuracy_main(args)
     import numpy as np
     import torch
     from ommgen import config_spec, make_system
