@@ -37,6 +37,10 @@ WORKLOADS = {
     "cubic8_sparse": dict(cfg="cubic8_sparse", mode="sparse", max_iter=200,
                           desc="8x8x8 lattice, 512 atoms x 13 orbitals, N_basis 6656, N_occ 1024, "
                                "atom-block sparse, C radius 3.0, eta 1.5, filter 1e-6, 200 CG iterations"),
+    "cubic8_kim": dict(cfg="cubic8_kim", mode="sparse", max_iter=200,
+                       desc="8x8x8 lattice, 512 atoms x 13 orbitals, N_basis 6656, Kim functional with "
+                            "3 wavefunctions per atom (1536) for N_occ 1024, atom-block sparse, C radius 3.0, "
+                            "eta -0.25 (in the gap), filter 1e-6, 200 CG iterations"),
     "cubic16_mixed": dict(cfg="cubic16_mixed", mode="sparse", max_iter=20,
                           desc="16x16x16 lattice, 4096 atoms x 13 orbitals, N_basis 53248, N_occ 8192, "
                                "atom-block sparse, C radius 3.0, eta 1.5, filter 1e-6, 20 CG iterations"),
@@ -347,7 +351,8 @@ def main():
     Sv = torch.from_numpy(system.S.val).to(dev)
     C0v = torch.from_numpy(system.C0.val).to(dev)
     rho = torch.zeros(system.S.val.size, dtype=torch.float64, device=dev)
-    prob = Problem(system.H, system.S, system.C0, system.n, mode, H_val=Hv, S_val=Sv, C0_val=C0v)
+    prob = Problem(system.H, system.S, system.C0, system.n, mode, H_val=Hv, S_val=Sv, C0_val=C0v,
+                   n_occupied=system.n_occupied)
     ctx = Context([prob], eta=spec.eta, tol_grad=1e-9, max_iter=max_iter, precision=prec,
                   filter_eps=spec.filter_eps, graph_iters=args.graph_iters, history=0,
                   hip_stream=stream.cuda_stream, autotune=0 if args.no_autotune else 1)
@@ -373,6 +378,17 @@ def main():
     sz = ctx.sizes(0)
     value = iters / dt
     flops_iter = sz.flops_alg_iter
+
+    # the two density outputs of a finished solve (Eq. 5 and the energy density of
+    # Eq. 6), each a blocking call into a device buffer, host-timed
+    rho_e = torch.zeros_like(rho)
+    outputs_ms = {}
+    for name, fn, buf in (("rho", LL.omm_density_matrix, rho), ("rho_E", LL.omm_energy_density, rho_e)):
+        fn(ctx.ctx, 0, buf)
+        t1 = time.perf_counter()
+        for _ in range(5):
+            fn(ctx.ctx, 0, buf)
+        outputs_ms[name] = (time.perf_counter() - t1) / 5 * 1e3
 
     # per-launch device time of each product step with HIP events on the
     # library's stream: TIMING_REPS launches back to back (the tuned shape, the
@@ -417,15 +433,18 @@ def main():
                   "bf16": "bf16 products (f32 accumulate), f64 traces/line search"}[args.precision],
         "data": "synthetic",
         "config": {"workload": args.workload + ": " + wl["desc"], "mode": wl["mode"],
-                   "precision": args.precision, "N_basis": int(system.m), "N_occ": int(system.n),
-                   "atoms": int(system.natoms)},
+                   "precision": args.precision, "N_basis": int(system.m), "N_occ": int(system.n_occupied),
+                   "N_wf": int(system.n), "atoms": int(system.natoms)},
         "cg_iters_per_step": iters / args.steps,
         "gflops_alg": flops_iter * value / 1e9,
         "alg_flops_per_iter": flops_iter,
         "exec_flops_per_iter": sz.flops_exec_iter,
         "energy": last.energy,
         "energy_per_atom": last.energy / system.natoms,
+        "energy_band_per_atom": last.energy_band / system.natoms,
+        "electron_count": last.electron_count,
         "status": LL.omm_status_str(last.status),
+        "output_call_ms": outputs_ms,
         "roofline": roof,
         "cpu_baseline": None,
     }

@@ -43,7 +43,8 @@ typedef enum {
   OMM_ERR_NOT_SPD = 3,        /* Cholesky factorization of S failed (Sec. II) */
   OMM_ERR_NO_LINE_MIN = 4,    /* quartic has no minimum along steepest descent (Sec. IV C) */
   OMM_ERR_NOT_CONVERGED = 5,  /* soft: max_iter reached, results readable */
-  OMM_ERR_ELECTRON_COUNT = 6, /* soft: |2Tr[(2I-S_W)S_W] - 2n| above ne_tol (Sec. II, Kim) */
+  OMM_ERR_ELECTRON_COUNT = 6, /* soft: |2Tr[(2I-S_W)S_W] - 2n| above ne_tol (Sec. II, Kim;
+                                 n = n_occupied, see omm_set_occupied) */
   OMM_ERR_DEVICE = 7,         /* HIP runtime error */
   OMM_ERR_OOM = 8             /* device allocation failed */
 } omm_status;
@@ -116,7 +117,8 @@ typedef struct {
 /* Per-system results of omm_minimize. */
 typedef struct {
   double energy;         /* shifted functional E~ (Eq. 4 with H - eta S) */
-  double energy_band;    /* E~ + 2 eta n (Kim correction with spin factor 2, Sec. II) */
+  double energy_band;    /* E~ + 2 eta n (Kim correction with spin factor 2, Sec. II;
+                            n = n_occupied, see omm_set_occupied) */
   double grad_norm;      /* ||G||_F of the projected real gradient at the result */
   double electron_count; /* 2 Tr[(2I - S_W) S_W] (Listing 1) */
   int64_t iters_total;   /* CG iterations (line searches taken) */
@@ -183,6 +185,15 @@ int omm_init_batch(omm_ctx** out, int32_t count, const omm_matrix* H, const omm_
  * Column blocks must be at most 16 wide in OMM_BLOCK_SPARSE mode. */
 int omm_set_coeffs(omm_ctx* ctx, int32_t sys, const omm_matrix* C0);
 
+/* Kim functional with more wavefunctions than occupied states (Sec. II, step
+ * 2: C is m x n' with n' > n): the n_occ given at init is the column count n'
+ * of C, and this call declares that only n_occupied of them are occupied
+ * (2 n_occupied electrons).  It changes what is reported, not what is
+ * minimized: energy_band = E~ + 2 eta n_occupied and the electron-count check
+ * against 2 n_occupied.  Default n_occupied = n'.  Requires
+ * 1 <= n_occupied <= n'; otherwise OMM_ERR_ARG.  May be called at any time. */
+int omm_set_occupied(omm_ctx* ctx, int32_t sys, int64_t n_occupied);
+
 /* Runs CG on every system of the context until each one stops (tol_grad,
  * rel_tol, max_iter, or a failed line search).  reports[count] receives the
  * per-system results (may be NULL).  Returns the worst per-system status.
@@ -193,6 +204,13 @@ int omm_minimize(omm_ctx* ctx, omm_report* reports);
  * block pattern of S and in the value layout (val_off) of the S passed at init:
  * `rho` holds s_nval doubles in host or device memory (omm_memspace `where`). */
 int omm_density_matrix(omm_ctx* ctx, int32_t sys, double* rho, int32_t where);
+
+/* Energy density rho_E = 2 C H_W C^T (Eq. 6, the S-derivative term of the
+ * forces) with the Kim correction rho_E + eta rho (Sec. II), where H_W =
+ * C^T (H - eta S) C and eta is the system's shift; at eta = 0 this is plain
+ * 2 C H_W C^T.  Same pattern, layout, memory spaces, call order and errors as
+ * omm_density_matrix: `rho_e` holds s_nval doubles owned by the caller. */
+int omm_energy_density(omm_ctx* ctx, int32_t sys, double* rho_e, int32_t where);
 
 /* Current C of system `sys` in the layout of its C0 (c_nval doubles).  For
  * OMM_DENSE_CHOLESKY this is the back-transformed C = U^-1 C~. */

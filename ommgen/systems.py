@@ -164,6 +164,7 @@ class SystemSpec:
     onsite_noise: float = 0.02
     c0_scale: float = 0.1
     c0_ref_nnz: float = 32.0
+    occ_per_atom: int = 2          # occupied states per atom (the two low on-site levels)
 
     @property
     def natoms(self) -> int:
@@ -177,12 +178,20 @@ class SystemSpec:
     def n(self) -> int:
         return self.natoms * self.wf_per_atom
 
+    @property
+    def n_occupied(self) -> int:
+        return self.natoms * self.occ_per_atom
+
 
 def _onsite13() -> Tuple[float, ...]:
     return tuple([-1.0] * 2 + [1.0] * 11)
 
 
-CONFIG_NAMES = ("chain8", "cubic4_dense", "cubic8_sparse", "cubic16_mixed", "batch64")
+CONFIG_NAMES = ("chain8", "cubic4_dense", "cubic8_sparse", "cubic16_mixed", "batch64", "cubic8_kim")
+
+# Kim shift inside the gap of the 13-orbital lattices (occupied levels end near
+# -0.76, empty ones start near +0.30)
+KIM_ETA13 = -0.25
 
 
 def config_spec(name: str, **overrides) -> SystemSpec:
@@ -197,6 +206,9 @@ def config_spec(name: str, **overrides) -> SystemSpec:
     elif name == "cubic16_mixed":  # 16^3 x 13, same recipe as cubic8_sparse
         spec = SystemSpec(name, (16, 16, 16), 13, 2, _onsite13(), seed=4, rc=3.0,
                           eta=1.5, filter_eps=1e-6, dense=False)
+    elif name == "cubic8_kim":     # 8^3 x 13, 3 wavefunctions per atom for 2 occupied states
+        spec = SystemSpec(name, (8, 8, 8), 13, 3, _onsite13(), seed=6, rc=3.0,
+                          eta=KIM_ETA13, filter_eps=1e-6, dense=False)
     else:
         raise ValueError(f"unknown config {name!r}")
     return replace(spec, **overrides) if overrides else spec
@@ -262,6 +274,10 @@ class System:
     @property
     def n(self) -> int:
         return self.spec.n
+
+    @property
+    def n_occupied(self) -> int:
+        return self.spec.n_occupied
 
 
 def _min_image(d: np.ndarray, box: np.ndarray) -> np.ndarray:

@@ -8,7 +8,10 @@ shares no code with it.  Every function cites the passage of arXiv 2209.05934
 Pins (see tests/test_oracle_*.py): finite-difference gradient, exactness of
 the quartic along a line, line-search root choice against a brute-force grid,
 converged dense energy and density matrix against the generalized
-eigendecomposition, the identities of Eqs. 1, 2, 5 and Listing 1, Cholesky
+eigendecomposition (also with more wavefunctions than occupied states, Kim
+functional), the energy density as minus the derivative of the functional with
+respect to S and its eigen form at the minimum, the identities of Eqs. 1, 2, 5
+and Listing 1, Cholesky
 variant == plain variant, unlimited localization radius == dense, and a
 brute-force BFGS minimum on tiny localized inputs.  Product filtering with a
 positive threshold is "parity unpinned" (no closed form; only reported).
@@ -27,6 +30,7 @@ from .omm import (  # noqa: F401
     cholesky_reduce,
     cg_minimize_cholesky,
     density_matrix,
+    energy_density_matrix,
     electron_count,
     exact_band_energy,
     filter_blocks,

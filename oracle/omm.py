@@ -29,7 +29,9 @@ Readings where the paper is silent (each is also listed in the design doc):
   paper's relative energy change |2(E_n - E_{n-1})/(E_n + E_{n-1})| < rel_tol
   (Table 1, OMM.RelTol).
 * Kim correction: the reported band energy is E~ + 2 eta n (2n electrons,
-  Sec. II), i.e. the paper's "E~ + eta n" with its spin factor.
+  Sec. II), i.e. the paper's "E~ + eta n" with its spin factor; n counts the
+  occupied states, which may be fewer than the n' columns of C.  The energy
+  density gets the matching correction rho_E + eta rho.
 * filtering (Sec. V): with filter_eps > 0, every product of H or S with C or
   D and every n x n projection has its atom blocks of Frobenius norm < eps set
   to zero; C, D, G, H and S are never filtered.  eps = 0 filters nothing.
@@ -116,6 +118,17 @@ def density_matrix(C: np.ndarray, SW: np.ndarray, pattern: Optional[np.ndarray] 
     n = SW.shape[0]
     rho = 2.0 * C @ (2.0 * np.eye(n) - SW) @ C.T
     return rho if pattern is None else np.where(pattern, rho, 0.0)
+
+
+def energy_density_matrix(C: np.ndarray, HW: np.ndarray, SW: np.ndarray, eta: float = 0.0,
+                          pattern: Optional[np.ndarray] = None) -> np.ndarray:
+    """rho_E = 2 C H_W C^T (Eq. 6), plus eta rho under the Kim shift (Sec. II, step 3).
+
+    H_W here is C^T (H - eta S) C, the projection of the shifted Hamiltonian the
+    functional is minimized with.  Kept on S's pattern when given (Sec. III B).
+    """
+    rho_e = 2.0 * C @ HW @ C.T + eta * density_matrix(C, SW)
+    return rho_e if pattern is None else np.where(pattern, rho_e, 0.0)
 
 
 # ---------------------------------------------------------------- filtering
@@ -242,17 +255,20 @@ def _energy_and_gradient(H, S, C, mask, filt):
 def cg_minimize(H, S, C0: np.ndarray, *, mask: Optional[np.ndarray] = None, eta: float = 0.0,
                 tol_grad: float = 1e-9, rel_tol: float = 0.0, max_iter: int = 10000,
                 filter_eps: float = 0.0, row_blocks=None, col_blocks=None,
-                keep_history: bool = True) -> CGResult:
+                keep_history: bool = True, n_occupied: Optional[int] = None) -> CGResult:
     """Minimize E~ (Eq. 4, with the Kim shift of Sec. II) by conjugate gradients.
 
     H, S: unshifted Hamiltonian and overlap; the shift H - eta S is applied here.
-    C0: initial guess; `mask` is its sparsity pattern (None = dense).
+    C0: initial guess; `mask` is its sparsity pattern (None = dense).  Its
+    column count n' may exceed the number n_occupied of occupied states (Kim
+    functional, Sec. II step 2); n_occupied (default n') only enters the
+    reported band energy E~ + 2 eta n_occupied.
     row_blocks/col_blocks: atom block sizes of the basis and of the
     wavefunctions, used only by filtering.
     """
     Heta = kim_shift(H, S, eta)
     C = project(np.array(C0, dtype=np.float64, copy=True), mask)
-    n = C.shape[1]
+    n = C.shape[1] if n_occupied is None else int(n_occupied)
     filt = _block_filters(filter_eps, row_blocks, col_blocks)
     E, G, HW, SW = _energy_and_gradient(Heta, S, C, mask, filt)
     D = -G
@@ -321,7 +337,7 @@ def cg_minimize_cholesky(H, S, C0: np.ndarray, *, eta: float = 0.0, **kw) -> CGR
     Ct0 = U @ np.asarray(C0, dtype=np.float64)
     res = cg_minimize(Ht, np.eye(m), Ct0, eta=0.0, **kw)
     C = scipy.linalg.solve_triangular(U, res.C, lower=False)
-    n = C.shape[1]
+    n = kw.get("n_occupied") or C.shape[1]
     res.C = C
     res.energy_band = res.energy + 2.0 * eta * n
     return res

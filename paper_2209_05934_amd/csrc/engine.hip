@@ -46,6 +46,7 @@ struct DevMap {    // device copies of one matrix's block structure for scatter/
 struct SysHost {
   int mode = OMM_DENSE;
   int64_t m = 0, n = 0;
+  int64_t n_occupied = 0;   // occupied states (Kim: fewer than the n columns of C); 0 = n
   double eta = 0.0;
   MatDesc H, S, C0;
   bool has_c0 = false;
@@ -1261,14 +1262,15 @@ int minimize(omm_ctx* c, omm_report* reps) {
   };
   for (int i = 0; i < c->nsys; ++i) {
     const SysState& S = c->h_st[i];
+    const double nocc = (double)(c->sys[i].n_occupied > 0 ? c->sys[i].n_occupied : c->sys[i].n);
     int status = S.status;
-    if (status == OMM_OK && c->opt.ne_tol > 0 && std::fabs(S.ne - 2.0 * c->sys[i].n) > c->opt.ne_tol)
+    if (status == OMM_OK && c->opt.ne_tol > 0 && std::fabs(S.ne - 2.0 * nocc) > c->opt.ne_tol)
       status = OMM_ERR_ELECTRON_COUNT;
     if (rank(status) > rank(worst)) worst = status;
     if (reps) {
       omm_report& r = reps[i];
       r.energy = S.E;
-      r.energy_band = S.E + 2.0 * c->sys[i].eta * (double)c->sys[i].n;
+      r.energy_band = S.E + 2.0 * c->sys[i].eta * nocc;
       r.grad_norm = S.gnorm;
       r.electron_count = S.ne;
       r.iters_total = S.iter;
@@ -1515,36 +1517,59 @@ int omm_set_coeffs(omm_ctx* c, int32_t sys, const omm_matrix* C0) {
   }, &a);
 }
 
+int omm_set_occupied(omm_ctx* c, int32_t sys, int64_t n_occupied) {
+  if (!c) return OMM_ERR_ARG;
+  if (sys < 0 || sys >= c->nsys || n_occupied < 1 || n_occupied > c->sys[sys].n) {
+    c->err = "n_occupied must satisfy 1 <= n_occupied <= n_occ of the system";
+    return OMM_ERR_ARG;
+  }
+  c->sys[sys].n_occupied = n_occupied;
+  c->err.clear();
+  return OMM_OK;
+}
+
 int omm_minimize(omm_ctx* c, omm_report* reps) {
   if (!c) return OMM_ERR_ARG;
   struct A { omm_report* r; } a{reps};
   return guard(c, [](omm_ctx* cc, void* v) -> int { return minimize(cc, ((A*)v)->r); }, &a);
 }
 
-int omm_density_matrix(omm_ctx* c, int32_t sys, double* rho, int32_t where) {
+// 2 C M C^T on S's pattern with M = ch H_W + cs (2I - S_W), for rho (Eq. 5) and rho_E
+// (Eq. 6 with the Kim correction of Sec. II)
+static int density_like(omm_ctx* c, int32_t sys, double* out, int32_t where, bool energy, const char* name) {
   if (!c) return OMM_ERR_ARG;
-  if (sys < 0 || sys >= c->nsys || !rho || (where != OMM_HOST && where != OMM_DEVICE)) {
+  if (sys < 0 || sys >= c->nsys || !out || (where != OMM_HOST && where != OMM_DEVICE)) {
     c->err = "bad argument";
     return OMM_ERR_ARG;
   }
   if (!c->ran) {
-    c->err = "omm_minimize must run before omm_density_matrix";
+    c->err = std::string("omm_minimize must run before ") + name;
     return OMM_ERR_STATE;
   }
-  struct A { int sys; double* rho; int where; } a{sys, rho, where};
+  struct A { int sys; double* out; int where; bool energy; } a{sys, out, where, energy};
   return guard(c, [](omm_ctx* cc, void* v) -> int {
     auto* q = (A*)v;
     SysHost& s = cc->sys[q->sys];
     hipStream_t st = cc->stream;
     const double* C = current_c(cc, q->sys);
-    launch_cm(st, cc->Pcm.view(), cc->TCM.row, cc->brow_sys, q->sys, C, cc->b.S0, cc->TW.row, cc->TW.ci, cc->CM);
+    const double ch = q->energy ? 1.0 : 0.0, cs = q->energy ? s.eta : 1.0;
+    launch_cm(st, cc->Pcm.view(), cc->TCM.row, cc->brow_sys, q->sys, C, cc->b.S0, cc->b.H0, ch, cs, cc->TW.row,
+              cc->TW.ci, cc->CM);
     launch_rho(st, cc->Prho.view(), cc->TH.row, cc->brow_sys, q->sys, cc->CM, C, cc->rho);
     std::vector<void*> tmp;
-    double* dst = out_buffer(cc, q->rho, q->where, s.S.nval, tmp);
+    double* dst = out_buffer(cc, q->out, q->where, s.S.nval, tmp);
     launch_gather(st, blkmap(s.mh, s.s_voff, s, false, cc->TH), cc->rho, dst);
-    finish_out(cc, q->rho, q->where, dst, s.S.nval, tmp);
+    finish_out(cc, q->out, q->where, dst, s.S.nval, tmp);
     return OMM_OK;
   }, &a);
+}
+
+int omm_density_matrix(omm_ctx* c, int32_t sys, double* rho, int32_t where) {
+  return density_like(c, sys, rho, where, false, "omm_density_matrix");
+}
+
+int omm_energy_density(omm_ctx* c, int32_t sys, double* rho_e, int32_t where) {
+  return density_like(c, sys, rho_e, where, true, "omm_energy_density");
 }
 
 int omm_get_coeffs(omm_ctx* c, int32_t sys, double* C, int32_t where) {

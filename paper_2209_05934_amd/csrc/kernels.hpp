@@ -103,9 +103,11 @@ constexpr int FUSED_CHUNKS = 16;
 // systems with at most this many C tiles take the CG beta inside the D update kernel
 constexpr int FUSED_CTILES = 1024;
 
-// density matrix: CM = C (2I - S0) on the CM plan, rho = 2 CM C^T on the H pattern
+// density matrices: CM = C (ch H0 + cs (2I - S0)) on the CM plan, then 2 CM C^T on
+// the H pattern; rho takes (ch, cs) = (0, 1), the energy density (1, eta)
 void launch_cm(hipStream_t s, PlanView p, const int* orow, const int* brow_sys, int sys, const double* C,
-               const double* S0, const int* tw_row, const int* tw_col, double* CM);
+               const double* S0, const double* H0, double ch, double cs, const int* tw_row, const int* tw_col,
+               double* CM);
 void launch_rho(hipStream_t s, PlanView p, const int* orow, const int* brow_sys, int sys, const double* CM,
                 const double* C, double* rho);
 

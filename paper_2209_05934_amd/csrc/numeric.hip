@@ -519,10 +519,13 @@ __global__ __launch_bounds__(256) void k_cast(int ntiles, const int* __restrict_
   dst[o] = cvt<TL, double>(src[o]);
 }
 
-// ------------------------------------------------------------------ density matrix (Eq. 5)
+// ------------------------------------------------------------------ density matrices (Eq. 5, Eq. 6)
+// CM = C M with the n x n matrix M = ch H_W + cs (2I - S_W): rho takes (0, 1), the
+// energy density rho_E = 2 C H_W C^T + eta rho (Kim correction, Sec. II) takes (1, eta)
 __global__ __launch_bounds__(256) void k_cm(PlanView P, const int* __restrict__ orow,
                                           const int* __restrict__ brow_sys, int sys, const double* __restrict__ C,
-                                          const double* __restrict__ S0, const int* __restrict__ tw_row,
+                                          const double* __restrict__ S0, const double* __restrict__ H0, double ch,
+                                          double cs, const int* __restrict__ tw_row,
                                           const int* __restrict__ tw_col, double* __restrict__ CM) {
   const int lane = threadIdx.x & 63;
   const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -537,7 +540,14 @@ __global__ __launch_bounds__(256) void k_cm(PlanView P, const int* __restrict__ 
     ld_col(fb, S0 + (size_t)pr.y * TE, lane);
     const bool dg = tw_row[pr.y] == tw_col[pr.y];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) fb.v[s] = ((dg && KMap<double>::k(q, s) == j) ? 2.0 : 0.0) - fb.v[s];   // 2I - S_W
+    for (int s = 0; s < 4; ++s)   // cs (2I - S_W)
+      fb.v[s] = cs * (((dg && KMap<double>::k(q, s) == j) ? 2.0 : 0.0) - fb.v[s]);
+    if (ch != 0.0) {
+      Frag<double> fh;
+      ld_col(fh, H0 + (size_t)pr.y * TE, lane);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) fb.v[s] += ch * fh.v[s];
+    }
     mma(acc, fa, fb);
   }
 #pragma unroll
@@ -743,9 +753,10 @@ void launch_cast_hs(hipStream_t s, const Bufs& b, Prec prec) {
 }
 
 void launch_cm(hipStream_t s, PlanView p, const int* orow, const int* brow_sys, int sys, const double* C,
-               const double* S0, const int* tw_row, const int* tw_col, double* CM) {
+               const double* S0, const double* H0, double ch, double cs, const int* tw_row, const int* tw_col,
+               double* CM) {
   if (p.nout <= 0) return;
-  LAUNCH(k_cm, waves_grid(p.nout), dim3(256), s, p, orow, brow_sys, sys, C, S0, tw_row, tw_col, CM);
+  LAUNCH(k_cm, waves_grid(p.nout), dim3(256), s, p, orow, brow_sys, sys, C, S0, H0, ch, cs, tw_row, tw_col, CM);
 }
 
 void launch_rho(hipStream_t s, PlanView p, const int* orow, const int* brow_sys, int sys, const double* CM,

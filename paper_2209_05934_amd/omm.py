@@ -87,6 +87,8 @@ def load(path: Optional[str] = None) -> C.CDLL:
         "omm_set_coeffs": (I32, [P, I32, MP]),
         "omm_minimize": (I32, [P, C.POINTER(omm_report)]),
         "omm_density_matrix": (I32, [P, I32, P, I32]),
+        "omm_energy_density": (I32, [P, I32, P, I32]),
+        "omm_set_occupied": (I32, [P, I32, I64]),
         "omm_get_coeffs": (I32, [P, I32, P, I32]),
         "omm_get_projected": (I32, [P, I32, P, P, I32]),
         "omm_get_history": (I32, [P, I32, P, I64, C.POINTER(I64)]),
@@ -107,8 +109,9 @@ def load(path: Optional[str] = None) -> C.CDLL:
 
 
 EXPORTED = ("omm_default_options", "omm_init", "omm_init_batch", "omm_set_coeffs", "omm_minimize",
-            "omm_density_matrix", "omm_get_coeffs", "omm_get_projected", "omm_get_history", "omm_query",
-            "omm_set_timing", "omm_kernel_times", "omm_time_step", "omm_status_str", "omm_last_error", "omm_destroy")
+            "omm_density_matrix", "omm_energy_density", "omm_get_coeffs", "omm_get_projected",
+            "omm_get_history", "omm_query", "omm_set_occupied", "omm_set_timing", "omm_kernel_times", "omm_time_step",
+            "omm_status_str", "omm_last_error", "omm_destroy")
 
 
 class OmmError(RuntimeError):
@@ -215,6 +218,15 @@ def omm_minimize(ctx, count: int = 1, soft_ok: bool = True):
 def omm_density_matrix(ctx, sys: int, out) -> int:
     p, where = _addr(out)
     return _check(ctx, load().omm_density_matrix(ctx, int(sys), C.c_void_p(p), where))
+
+
+def omm_set_occupied(ctx, sys: int, n_occupied: int) -> int:
+    return _check(ctx, load().omm_set_occupied(ctx, int(sys), int(n_occupied)))
+
+
+def omm_energy_density(ctx, sys: int, out) -> int:
+    p, where = _addr(out)
+    return _check(ctx, load().omm_energy_density(ctx, int(sys), C.c_void_p(p), where))
 
 
 def omm_get_coeffs(ctx, sys: int, out) -> int:

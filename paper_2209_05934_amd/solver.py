@@ -20,9 +20,10 @@ class Problem:
     H: Any            # block-sparse H (unshifted)
     S: Any            # block-sparse S, same block structure
     C0: Any           # block-sparse initial guess (its pattern is kept fixed)
-    n: int            # number of wavefunctions
+    n: int            # number of wavefunctions (columns of C)
     mode: int = L.OMM_DENSE
     eta: Optional[float] = None  # Kim shift of this system (None: the context option)
+    n_occupied: Optional[int] = None  # occupied states when fewer than n (Kim); None: n
     H_val: Any = None  # optional device tensors replacing the host values
     S_val: Any = None
     C0_val: Any = None
@@ -54,6 +55,8 @@ class Context:
                                         [p.mode for p in self.problems], etas, self.opt)
         for i, p in enumerate(self.problems):
             self.set_coeffs(i, p.C0, p.C0_val)
+            if p.n_occupied is not None:
+                L.omm_set_occupied(self.ctx, i, p.n_occupied)
 
     @property
     def count(self) -> int:
@@ -70,6 +73,12 @@ class Context:
         if out is None:
             out = np.zeros(self.problems[sys].S.val.size)
         L.omm_density_matrix(self.ctx, sys, out)
+        return out
+
+    def energy_density(self, sys: int = 0, out=None) -> np.ndarray:
+        if out is None:
+            out = np.zeros(self.problems[sys].S.val.size)
+        L.omm_energy_density(self.ctx, sys, out)
         return out
 
     def coeffs(self, sys: int = 0, out=None) -> np.ndarray:

@@ -267,3 +267,75 @@ def test_no_line_minimum_failure():
     C0[0, 0] = C0[1, 1] = 3.0
     r = O.cg_minimize(H, S, C0)
     assert r.status == "no_line_min" and not r.converged and r.iterations == 0
+
+
+# ------------------------------------------------------------ rho and rho_E as derivatives
+def _sym(rng, m, scale):
+    A = rng.standard_normal((m, m)) * scale
+    return 0.5 * (A + A.T)
+
+
+@pytest.mark.parametrize("eta", [0.0, 0.3])
+def test_density_matrices_are_derivatives_of_the_functional(eta):
+    # E~(C; H - eta S, S) at fixed C: dE~/dH = rho (Eq. 5) and dE~/dS = -rho_E, the
+    # energy density of Eq. 6 with the Kim correction rho_E + eta rho (Sec. II); these
+    # are the two traces of the force expression (Eq. 6)
+    H, S, C, _ = _rand_problem(m=9, n=4, seed=3)
+    rng = np.random.default_rng(7)
+    dH, dS = _sym(rng, 9, 1.0), _sym(rng, 9, 1.0)
+    f = lambda Hm, Sm: O.om_energy(O.kim_shift(Hm, Sm, eta), Sm, C)      # noqa: E731
+    h = 1e-5
+    dE_dH = (f(H + h * dH, S) - f(H - h * dH, S)) / (2 * h)
+    dE_dS = (f(H, S + h * dS) - f(H, S - h * dS)) / (2 * h)
+    HW, SW = O.projections(O.kim_shift(H, S, eta), S, C)
+    rho = O.density_matrix(C, SW)
+    rho_e = O.energy_density_matrix(C, HW, SW, eta)
+    assert abs(dE_dH - np.sum(rho * dH)) <= 1e-8 * max(1.0, abs(dE_dH))
+    assert abs(dE_dS + np.sum(rho_e * dS)) <= 1e-8 * max(1.0, abs(dE_dS))
+    # a dropped Kim term would miss by eta <rho, dS>
+    if eta:
+        assert abs(eta * np.sum(rho * dS)) > 1e-3
+
+
+@pytest.mark.parametrize("eta", [0.0, 0.1])
+def test_energy_density_at_the_dense_minimum(chain, eta):
+    # at the unconstrained minimum rho_E is the energy-weighted density matrix
+    # 2 sum_i eps_i x_i x_i^T over the occupied states, eps_i unshifted
+    s, H, S, C0 = chain
+    res = O.cg_minimize(H, S, C0, eta=eta, tol_grad=1e-9)
+    assert res.converged
+    w, X = scipy.linalg.eigh(H, S)
+    Xn = X[:, :s.n]
+    ref = 2.0 * Xn @ np.diag(w[:s.n]) @ Xn.T
+    rho_e = O.energy_density_matrix(res.C, res.HW, res.SW, eta)
+    assert np.max(np.abs(rho_e - ref)) <= 1e-8
+    # pattern restriction keeps exactly the pattern entries
+    pat = S != 0.0
+    assert np.array_equal(O.energy_density_matrix(res.C, res.HW, res.SW, eta, pat), np.where(pat, rho_e, 0.0))
+
+
+# ------------------------------------------------------------ Kim functional with n' > n
+@pytest.mark.parametrize("eta", [0.1, -0.3])
+def test_kim_more_wavefunctions_than_occupied_states(eta):
+    # Sec. II: with eta in the gap and n' > n columns, the minimum occupies the n
+    # states below eta (shifted energy 2 sum_{i<=n} (eps_i - eta)); the spare columns
+    # go to zero norm, so S_W has n eigenvalues 1 and n' - n eigenvalues 0 and the
+    # electron count is 2n
+    from dataclasses import replace
+    s = make_system(replace(config_spec("chain8"), wf_per_atom=3))
+    n, nocc = s.n, s.n_occupied
+    assert (n, nocc) == (24, 16)
+    H, S, C0 = s.H.to_dense(), s.S.to_dense(), s.C0.to_dense()
+    w, X = scipy.linalg.eigh(H, S)
+    assert w[nocc - 1] < eta < w[nocc]
+    res = O.cg_minimize(H, S, C0, eta=eta, tol_grad=1e-9, max_iter=20000, n_occupied=nocc)
+    assert res.converged
+    assert abs(res.energy - 2.0 * (w[:nocc] - eta).sum()) / s.natoms <= 1e-10
+    assert abs(res.energy_band - 2.0 * w[:nocc].sum()) / s.natoms <= 1e-10
+    ev = np.linalg.eigvalsh(res.SW)
+    assert np.max(np.abs(ev[:n - nocc])) <= 1e-6 and np.max(np.abs(ev[n - nocc:] - 1.0)) <= 1e-8
+    assert abs(O.electron_count(res.SW) - 2 * nocc) <= 1e-8
+    Xn = X[:, :nocc]
+    assert np.max(np.abs(O.density_matrix(res.C, res.SW) - 2.0 * Xn @ Xn.T)) <= 1e-8
+    rho_e = O.energy_density_matrix(res.C, res.HW, res.SW, eta)
+    assert np.max(np.abs(rho_e - 2.0 * Xn @ np.diag(w[:nocc]) @ Xn.T)) <= 1e-8
