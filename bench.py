@@ -31,6 +31,10 @@ WORKLOADS = {
     "cubic4_cholesky": dict(cfg="cubic4_dense", mode="cholesky", max_iter=10000,
                             desc="same 64-atom system, dense OMM on the Cholesky-reduced problem, "
                                  "CG to ||G||_F <= 1e-9"),
+    "cubic4_precon": dict(cfg="cubic4_dense", mode="dense", max_iter=10000, spec={"kinetic": 30.0}, tau=5.0,
+                          desc="64-atom dense system with a synthetic kinetic matrix T (levels up to 30) added "
+                               "to H, N_basis 832, N_occ 128, kinetic preconditioning P = (S + T/5)^-1, "
+                               "CG to ||G||_F <= 1e-9"),
     "chain8": dict(cfg="chain8", mode="dense", max_iter=10000,
                    desc="periodic chain of 8 atoms x 4 orbitals, N_basis 32, N_occ 16, dense, "
                         "CG to ||G||_F <= 1e-9"),
@@ -129,7 +133,7 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(system, spec, mode, max_iter, budget_s):
+def cpu_baseline(system, spec, mode, max_iter, budget_s, tau=0.0):
     """The CPU oracle as it stands, on a bounded sample of the same workload."""
     import numpy as np
     import oracle as O
@@ -142,6 +146,8 @@ def cpu_baseline(system, spec, mode, max_iter, budget_s):
     mask = None if spec.dense else system.C0.pattern_mask()
     kw = dict(eta=spec.eta, tol_grad=1e-9, max_iter=max_iter, keep_history=False)
     iters, solves, t0 = 0, 0, time.perf_counter()
+    if tau > 0.0:
+        kw["precon"] = O.kinetic_preconditioner(S, system.T.to_dense(), tau)
     while True:
         if mode == "cholesky":
             r = O.cg_minimize_cholesky(H, S, C0, **kw)
@@ -339,8 +345,9 @@ def main():
     from paper_2209_05934_amd.solver import Context, Problem
 
     wl = WORKLOADS[args.workload]
-    spec = config_spec(wl["cfg"])
+    spec = config_spec(wl["cfg"], **wl.get("spec", {}))
     system = make_system(spec)
+    tau = wl.get("tau", 0.0)
     mode = {"dense": L.OMM_DENSE, "cholesky": L.OMM_DENSE_CHOLESKY, "sparse": L.OMM_BLOCK_SPARSE}[wl["mode"]]
     prec = {"fp64": L.OMM_FP64, "fp32": L.OMM_FP32, "bf16": L.OMM_BF16}[args.precision]
     max_iter = args.max_iter or wl["max_iter"]
@@ -352,7 +359,7 @@ def main():
     C0v = torch.from_numpy(system.C0.val).to(dev)
     rho = torch.zeros(system.S.val.size, dtype=torch.float64, device=dev)
     prob = Problem(system.H, system.S, system.C0, system.n, mode, H_val=Hv, S_val=Sv, C0_val=C0v,
-                   n_occupied=system.n_occupied)
+                   n_occupied=system.n_occupied, T=system.T if tau > 0.0 else None, tau=tau)
     ctx = Context([prob], eta=spec.eta, tol_grad=1e-9, max_iter=max_iter, precision=prec,
                   filter_eps=spec.filter_eps, graph_iters=args.graph_iters, history=0,
                   hip_stream=stream.cuda_stream, autotune=0 if args.no_autotune else 1)
@@ -378,6 +385,26 @@ def main():
     sz = ctx.sizes(0)
     value = iters / dt
     flops_iter = sz.flops_alg_iter
+
+    plain_cg = None
+    if tau > 0.0:   # the same solves without the preconditioner, for the time to solution
+        pctx = Context([Problem(system.H, system.S, system.C0, system.n, mode, H_val=Hv, S_val=Sv, C0_val=C0v)],
+                       eta=spec.eta, tol_grad=1e-9, max_iter=max_iter, graph_iters=args.graph_iters, history=0,
+                       hip_stream=stream.cuda_stream, autotune=0 if args.no_autotune else 1)
+        for _ in range(args.warmup):
+            pctx.minimize()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        pit = 0
+        for _ in range(args.steps):
+            rc, preps = pctx.minimize()
+            pit += preps[0].iters_total
+        torch.cuda.synchronize()
+        pdt = time.perf_counter() - t1
+        plain_cg = {"cg_iters_per_solve": pit / args.steps, "ms_per_solve": pdt / args.steps * 1e3,
+                    "cg_iters_per_s": pit / pdt, "energy": preps[0].energy,
+                    "solve_time_ratio_plain_over_preconditioned": pdt / dt}
+        pctx.close()
 
     # the two density outputs of a finished solve (Eq. 5 and the energy density of
     # Eq. 6), each a blocking call into a device buffer, host-timed
@@ -445,11 +472,12 @@ def main():
         "electron_count": last.electron_count,
         "status": LL.omm_status_str(last.status),
         "output_call_ms": outputs_ms,
+        "plain_cg": plain_cg,
         "roofline": roof,
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(system, spec, wl["mode"], max_iter, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(system, spec, wl["mode"], max_iter, args.cpu_seconds, tau)
     ctx.close()
     print(json.dumps(out), flush=True)
 

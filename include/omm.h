@@ -137,7 +137,8 @@ typedef struct {
   int64_t tiles_h, tiles_c, tiles_hc, tiles_w;  /* 16x16 tiles of H/S, C, HC, H_W */
   int64_t pairs_s1, pairs_s2, pairs_grad;       /* tile products per CG iteration step */
   double flops_alg_iter;    /* algorithmic flops of one CG iteration: 2*r*k*c summed
-                               over the unpadded atom-block products */
+                               over the unpadded atom-block products (with kinetic
+                               preconditioning: plus the product P G, 2 m^2 n) */
   double flops_exec_iter;   /* flops the tile kernels execute per iteration */
   double bytes_alg_iter;    /* algorithmic HBM bytes of one iteration's products
                                (each unpadded operand and output element moved once,
@@ -193,6 +194,19 @@ int omm_set_coeffs(omm_ctx* ctx, int32_t sys, const omm_matrix* C0);
  * against 2 n_occupied.  Default n_occupied = n'.  Requires
  * 1 <= n_occupied <= n'; otherwise OMM_ERR_ARG.  May be called at any time. */
 int omm_set_occupied(omm_ctx* ctx, int32_t sys, int64_t n_occupied);
+
+/* Kinetic-energy preconditioning (Sec. II, Eq. 7; Table 1 OMM.Precon and
+ * OMM.TPreconScale): computes P = (S + T/tau)^-1 once on the device (Cholesky
+ * factorization and explicit inverse) and from the next omm_minimize on
+ * multiplies every CG gradient by P: the direction follows -P G and
+ * beta = max(0, <P G, G - G_old> / <P G_old, G_old>).  The minimum is the
+ * same; only the path to it changes.  T is the kinetic-energy matrix on the
+ * block structure of H and S (values host or device, borrowed for the call),
+ * tau > 0 its scale.  Dense only, like the paper: the context must hold one
+ * OMM_DENSE system and use FP64 products, else OMM_ERR_ARG.  S + T/tau not
+ * positive definite: OMM_ERR_NOT_SPD.  T == NULL removes the preconditioner.
+ * The library owns P (m x m doubles) until omm_destroy. */
+int omm_set_preconditioner(omm_ctx* ctx, const omm_matrix* T, double tau);
 
 /* Runs CG on every system of the context until each one stops (tol_grad,
  * rel_tol, max_iter, or a failed line search).  reports[count] receives the

@@ -165,6 +165,7 @@ class SystemSpec:
     c0_scale: float = 0.1
     c0_ref_nnz: float = 32.0
     occ_per_atom: int = 2          # occupied states per atom (the two low on-site levels)
+    kinetic: float = 0.0           # > 0: add a kinetic matrix T (largest level `kinetic`) to H
 
     @property
     def natoms(self) -> int:
@@ -261,6 +262,7 @@ class System:
     S: BlockMatrix           # overlap, same block pattern as H
     C0: BlockMatrix          # initial guess on the C pattern (norb x wf blocks)
     pair_images: int = 0
+    T: Optional[BlockMatrix] = None   # kinetic matrix (already part of H), when spec.kinetic > 0
     extra: dict = field(default_factory=dict)
 
     @property
@@ -347,6 +349,11 @@ def make_system(spec: SystemSpec) -> System:
     Hblk = np.concatenate([Hd, HB, np.transpose(HB, (0, 2, 1))])
     Sblk = np.concatenate([Sd, SB, np.transpose(SB, (0, 2, 1))])
     o = np.lexsort((cols, rows))
+    T = None
+    if spec.kinetic > 0.0:
+        Tblk = _kinetic_blocks(spec, PI, PJ, PR, first, N)
+        T = _uniform_bcsr(N, N, norb, norb, rows[o], cols[o], Tblk[o])
+        Hblk = Hblk + Tblk
     H = _uniform_bcsr(N, N, norb, norb, rows[o], cols[o], Hblk[o])
     S = _uniform_bcsr(N, N, norb, norb, rows[o], cols[o], Sblk[o])
 
@@ -366,5 +373,36 @@ def make_system(spec: SystemSpec) -> System:
     rng2 = np.random.default_rng(spec.seed + 10**6)
     cblk = rng2.normal(0.0, sigma, size=(crow.shape[0], norb, nwf))
     C0 = _uniform_bcsr(N, N, norb, nwf, crow, ccol, cblk)
-    return System(spec=spec, pos=pos, box=box, H=H, S=S, C0=C0, pair_images=npi,
+    return System(spec=spec, pos=pos, box=box, H=H, S=S, C0=C0, pair_images=npi, T=T,
                   extra={"c0_sigma": sigma})
+
+
+def _kinetic_blocks(spec: SystemSpec, PI, PJ, PR, first, N) -> np.ndarray:
+    """Blocks of a synthetic kinetic matrix T on H's pattern, in the block order
+    [on-site (N), pairs I<J, their transposes], like H's before sorting.
+
+    The high orbitals carry large kinetic energies (the broad upper spectrum
+    behind the ill-conditioning that kinetic preconditioning targets, Sec. II):
+    level t_k = kinetic * (0.002 + (k / (norb - 1))^2) for orbital k; pair-image
+    blocks (T_IJ)_kl = -0.001 exp(-r / decay) sqrt(t_k t_l) K_kl^(n), K ~ N(0, 1)
+    drawn from PCG64 seeded with seed + 2 * 10**6 in pair-image order, summed
+    over images; on-site blocks diagonal, t_k plus the absolute sum of the
+    row's off-diagonal entries, so T is strictly diagonally dominant and
+    therefore positive definite.
+    """
+    norb = spec.norb
+    rng = np.random.default_rng(spec.seed + 2 * 10**6)
+    npi = PI.shape[0]
+    K = rng.standard_normal((npi, norb, norb))
+    t = spec.kinetic * (0.002 + (np.arange(norb) / max(1, norb - 1)) ** 2)
+    st = np.sqrt(t)
+    wT = (-0.001 * np.exp(-PR / spec.decay))[:, None, None] * (st[:, None] * st[None, :])[None]
+    TB = np.add.reduceat(wT * K, first, axis=0) if npi else np.zeros((0, norb, norb))
+    upair = (PI * N + PJ)[first] if npi else np.zeros(0, dtype=np.int64)
+    UI, UJ = upair // N, upair % N
+    rowsum = np.zeros((N, norb))
+    np.add.at(rowsum, UI, np.abs(TB).sum(axis=2))
+    np.add.at(rowsum, UJ, np.abs(TB).sum(axis=1))
+    Td = np.zeros((N, norb, norb))
+    Td[:, np.arange(norb), np.arange(norb)] = t[None, :] + rowsum
+    return np.concatenate([Td, TB, np.transpose(TB, (0, 2, 1))])

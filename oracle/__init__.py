@@ -28,6 +28,7 @@ from .omm import (  # noqa: F401
     line_minimum,
     cg_minimize,
     cholesky_reduce,
+    kinetic_preconditioner,
     cg_minimize_cholesky,
     density_matrix,
     energy_density_matrix,

@@ -18,7 +18,9 @@ Readings where the paper is silent (each is also listed in the design doc):
   iterates do not depend on that factor; only the norm threshold does.
 * the gradient is projected on the sparsity pattern of the initial C
   ("keep_sparsity", Sec. III B); products are never restricted otherwise.
-* CG direction update: Polak-Ribiere, beta = max(0, <G, G - G_old>/<G_old, G_old>).
+* CG direction update: Polak-Ribiere, beta = max(0, <G, G - G_old>/<G_old, G_old>);
+  with kinetic preconditioning (Eq. 7) the gradient is multiplied by P, the
+  direction follows -P G and beta = max(0, <P G, G - G_old>/<P G_old, G_old>).
 * line search: the exact minimum of the quartic E~(C + xD) (Sec. I, ref. to
   the analytic quartic) reached by going downhill from x = 0: the smallest
   positive critical point with positive curvature.  When the quartic has no
@@ -255,7 +257,8 @@ def _energy_and_gradient(H, S, C, mask, filt):
 def cg_minimize(H, S, C0: np.ndarray, *, mask: Optional[np.ndarray] = None, eta: float = 0.0,
                 tol_grad: float = 1e-9, rel_tol: float = 0.0, max_iter: int = 10000,
                 filter_eps: float = 0.0, row_blocks=None, col_blocks=None,
-                keep_history: bool = True, n_occupied: Optional[int] = None) -> CGResult:
+                keep_history: bool = True, n_occupied: Optional[int] = None,
+                precon: Optional[np.ndarray] = None) -> CGResult:
     """Minimize E~ (Eq. 4, with the Kim shift of Sec. II) by conjugate gradients.
 
     H, S: unshifted Hamiltonian and overlap; the shift H - eta S is applied here.
@@ -265,15 +268,21 @@ def cg_minimize(H, S, C0: np.ndarray, *, mask: Optional[np.ndarray] = None, eta:
     reported band energy E~ + 2 eta n_occupied.
     row_blocks/col_blocks: atom block sizes of the basis and of the
     wavefunctions, used only by filtering.
+    precon: an m x m preconditioning matrix P (Eq. 7, `kinetic_preconditioner`)
+    that multiplies the gradient (Sec. II); the direction then follows -P G and
+    beta uses the preconditioned products <P G, G - G_old> / <P G_old, G_old>.
     """
     Heta = kim_shift(H, S, eta)
     C = project(np.array(C0, dtype=np.float64, copy=True), mask)
     n = C.shape[1] if n_occupied is None else int(n_occupied)
     filt = _block_filters(filter_eps, row_blocks, col_blocks)
     E, G, HW, SW = _energy_and_gradient(Heta, S, C, mask, filt)
-    D = -G
+    pre = (lambda A: A) if precon is None else (lambda A: precon @ A)      # noqa: E731
+    Z = pre(G)
+    D = -Z
     steepest = True
     gg = _frob(G, G)
+    zg = _frob(Z, G)
     history: List[dict] = []
     status, converged, it, restarts = "not_converged", False, 0, 0
     if np.sqrt(gg) <= tol_grad:
@@ -294,11 +303,13 @@ def cg_minimize(H, S, C0: np.ndarray, *, mask: Optional[np.ndarray] = None, eta:
         E_old = E
         E, G_new, HW, SW = _energy_and_gradient(Heta, S, C, mask, filt)
         gg_new = _frob(G_new, G_new)
-        beta = 0.0 if restart else max(0.0, _frob(G_new, G_new - G) / gg)
+        Z = pre(G_new)
+        zg_new = _frob(Z, G_new)
+        beta = 0.0 if restart else max(0.0, _frob(Z, G_new - G) / zg)
         if keep_history:
             history.append(dict(E=E, c=c.copy(), x=x, gnorm=np.sqrt(gg_new), beta=beta,
                                 restart=restart))
-        G, gg = G_new, gg_new
+        G, gg, zg = G_new, gg_new, zg_new
         if np.sqrt(gg) <= tol_grad:
             status, converged = "ok", True
             break
@@ -306,11 +317,18 @@ def cg_minimize(H, S, C0: np.ndarray, *, mask: Optional[np.ndarray] = None, eta:
                 abs(2.0 * (E - E_old) / (E + E_old)) < rel_tol:
             status, converged = "ok", True
             break
-        D = -G + beta * D
+        D = -Z + beta * D
         steepest = (beta == 0.0)
     return CGResult(C=C, energy=E, energy_band=E + 2.0 * eta * n, iterations=it,
                     converged=converged, status=status, grad_norm=float(np.sqrt(gg)),
                     restarts=restarts, HW=HW, SW=SW, history=history)
+
+
+# ---------------------------------------------------------------- kinetic preconditioning
+def kinetic_preconditioner(S, T, tau: float) -> np.ndarray:
+    """P = (S + T / tau_T)^-1 (Eq. 7): T the kinetic-energy matrix, tau_T its scale
+    (Table 1, OMM.TPreconScale).  Dense; cubic-scaling OMM only (Sec. II)."""
+    return np.linalg.inv(_dense(S) + _dense(T) / tau)
 
 
 # ---------------------------------------------------------------- Cholesky variant

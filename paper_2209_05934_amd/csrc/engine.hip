@@ -126,6 +126,7 @@ struct omm_ctx {
   void *Hl = nullptr, *Sl = nullptr;
   Bufs b{};
   double *CM = nullptr, *rho = nullptr, *Cb = nullptr;
+  double* P = nullptr;        // kinetic preconditioner (S + T/tau)^-1 on H's tiles, or null
   SysInfo* d_info = nullptr;
   SysState* d_st = nullptr;
   SysState* h_st = nullptr;   // pinned
@@ -887,6 +888,11 @@ void prepare(omm_ctx* c) {
   }
   b.tpart = dalloc<double>(c, (size_t)std::max(1, c->nchunks) * NSUM, true);
   b.gpart = dalloc<double>(c, std::max<size_t>(1, ntc) * 2, true);
+  if (c->P) {
+    b.P = c->P;
+    b.Z = dalloc<double>(c, ntc * TE, true);
+    b.zpart = dalloc<double>(c, std::max<size_t>(1, ntc) * 2, true);
+  }
   {
     std::vector<int> us(ntc + nhc + ntw);
     for (int i = 0; i < c->nsys; ++i) {
@@ -1083,6 +1089,7 @@ void run_iteration(omm_ctx* c, Prec p, int mask, bool tm) {
   launch_traces(s, b, p, mask, false, LS_STEP, prm);
   launch_update(s, b, p, mask, prm);
   timed(c, 2, tm, [](omm_ctx* cc, void* v) { auto* q = (StepArg*)v; launch_grad(cc->stream, cc->b, q->p, q->mask, false); }, &a);
+  if (b.P) launch_precon(s, b, mask);
   launch_beta(s, b, mask, false, prm);
   launch_update_d(s, b, p, mask, false, prm);
 }
@@ -1100,6 +1107,7 @@ void init_sequence(omm_ctx* c) {
   launch_s2(s, b, P64, PH_INIT, true);
   launch_traces(s, b, P64, PH_INIT, true, LS_INIT, prm);
   launch_grad(s, b, P64, PH_INIT, true);
+  if (b.P) launch_precon(s, b, PH_INIT);
   launch_beta(s, b, PH_INIT, true, prm);
   launch_update_d(s, b, P64, PH_INIT, true, prm);
   if (c->prec != P64) launch_cast_state(s, b, c->prec, PH_INIT);
@@ -1318,8 +1326,9 @@ int guard(omm_ctx* c, int (*fn)(omm_ctx*, void*), void* arg) {
   try {
     return fn(c, arg);
   } catch (const ArgError& e) {
-    if (e.msg == "__NOT_SPD__") {
-      set_err(c, "Cholesky factorization of S failed (S not positive definite)");
+    if (e.msg.rfind("__NOT_SPD__", 0) == 0) {
+      set_err(c, e.msg.size() > 11 ? e.msg.substr(11)
+                                   : std::string("Cholesky factorization of S failed (S not positive definite)"));
       return OMM_ERR_NOT_SPD;
     }
     if (e.msg.rfind("__STATE__", 0) == 0) {
@@ -1528,6 +1537,82 @@ int omm_set_occupied(omm_ctx* c, int32_t sys, int64_t n_occupied) {
   return OMM_OK;
 }
 
+int omm_set_preconditioner(omm_ctx* c, const omm_matrix* T, double tau) {
+  if (!c) return OMM_ERR_ARG;
+  struct A { const omm_matrix* T; double tau; } a{T, tau};
+  return guard(c, [](omm_ctx* cc, void* v) -> int {
+    auto* q = (A*)v;
+    if (!q->T) {   // back to plain CG
+      if (cc->P) {
+        auto it = std::find(cc->alloc_init.begin(), cc->alloc_init.end(), (void*)cc->P);
+        if (it != cc->alloc_init.end()) cc->alloc_init.erase(it);
+        OMM_HIP(hipStreamSynchronize(cc->stream));
+        (void)hipFree(cc->P);
+        cc->P = nullptr;
+        cc->prepared = false;
+      }
+      return OMM_OK;
+    }
+    if (cc->nsys != 1 || cc->sys[0].mode != OMM_DENSE)
+      throw ArgError("kinetic preconditioning needs a single system in OMM_DENSE mode");
+    if (cc->prec != P64) throw ArgError("kinetic preconditioning runs with FP64 products only");
+    if (!(q->tau > 0.0) || !std::isfinite(q->tau)) throw ArgError("tau must be positive and finite");
+    SysHost& s = cc->sys[0];
+    MatDesc d;
+    copy_desc(d, q->T, "T");
+    if (!d.same_pattern(s.H)) throw ArgError("T must share the block structure of H and S");
+    hipStream_t st = cc->stream;
+    const int RT = s.RT;
+    const size_t nt = (size_t)RT * RT;
+    if ((size_t)cc->TH.nnz != nt) throw ArgError("dense system expected to fill its tile grid");
+    if (!cc->P) cc->P = dalloc<double>(cc, nt * TE, false);
+    // scratch: A = S + T/tau (then its Cholesky factor), the identity grid, one work grid
+    std::vector<void*> tmp;
+    auto scratch = [&](size_t n) {
+      void* p = nullptr;
+      if (hipMalloc(&p, n * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        for (void* t : tmp) (void)hipFree(t);
+        throw OomError("preconditioner scratch");
+      }
+      tmp.push_back(p);
+      return (double*)p;
+    };
+    double* Ag = scratch(nt * TE);
+    double* Tg = scratch(nt * TE);
+    double* Id = scratch(nt * TE);
+    double* Linv = scratch((size_t)RT * TE);
+    int* flag_d = (int*)scratch(1);
+    int64_t* t_voff = (int64_t*)scratch(std::max<size_t>(1, d.voff.size()));
+    try {
+      const double* tv = values_on_device(cc, q->T, tmp);
+      OMM_HIP(hipMemcpyAsync(t_voff, d.voff.data(), d.voff.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+      OMM_HIP(hipMemsetAsync(Tg, 0, nt * TE * sizeof(double), st));
+      OMM_HIP(hipMemsetAsync(Id, 0, nt * TE * sizeof(double), st));
+      OMM_HIP(hipMemsetAsync(flag_d, 0, sizeof(int), st));
+      launch_scatter(st, blkmap(s.mh, t_voff, s, false, cc->TH), tv, Tg);
+      OMM_HIP(hipMemcpyAsync(Ag, cc->S, nt * TE * sizeof(double), hipMemcpyDeviceToDevice, st));
+      launch_axpy_tiles(st, (int64_t)nt, 1.0 / q->tau, Tg, Ag);   // S + T / tau
+      launch_pad_identity(st, Ag, 0, RT, s.m);                     // padding rows: identity
+      launch_pad_identity(st, Id, 0, RT, 0);
+      chol_factor(st, Ag, 0, RT, Linv, flag_d);
+      int flag = 0;
+      OMM_HIP(hipMemcpyAsync(&flag, flag_d, sizeof(int), hipMemcpyDeviceToHost, st));
+      OMM_HIP(hipStreamSynchronize(st));
+      if (flag) throw ArgError("__NOT_SPD__S + T/tau is not positive definite");
+      chol_inverse(st, Ag, RT, Linv, Id, Tg, cc->P);
+      OMM_HIP(hipStreamSynchronize(st));
+    } catch (...) {
+      (void)hipStreamSynchronize(st);
+      for (void* t : tmp) (void)hipFree(t);
+      throw;
+    }
+    for (void* t : tmp) (void)hipFree(t);
+    cc->prepared = false;   // the next minimize re-plans with the preconditioned step
+    return OMM_OK;
+  }, &a);
+}
+
 int omm_minimize(omm_ctx* c, omm_report* reps) {
   if (!c) return OMM_ERR_ARG;
   struct A { omm_report* r; } a{reps};
@@ -1692,6 +1777,12 @@ int omm_query(const omm_ctx* cc, int32_t sys, omm_sizes* z) {
       z->flops_alg_iter += s.flops_alg[k];
       z->flops_exec_iter += s.flops_exec[k];
       z->bytes_alg_iter += by;
+    }
+    if (c->P) {   // Z = P G of kinetic preconditioning (dense m x m times m x n)
+      const double fp = 2.0 * (double)s.m * s.m * s.n;
+      z->flops_alg_iter += fp;
+      z->flops_exec_iter += 2.0 * 16 * 16 * 16 * s.pairs[0];
+      z->bytes_alg_iter += ((double)s.m * s.m + 2.0 * s.m * s.n) * 8.0;
     }
   }
   return OMM_OK;

@@ -61,6 +61,10 @@ struct Bufs {   // every device buffer the iteration kernels touch
   void *Hl, *Sl, *Cl, *Dl, *HCl, *SCl, *H0l, *S0l;
   float *HDf, *SDf, *Xf, *Yf, *S2f, *H2f;
   double *tpart, *gpart;         // trace partials (nchunks x NSUM), gradient partials (n_tc x 2)
+  // kinetic preconditioning (dense, FP64): P = (S + T/tau)^-1 on H's tiles, Z = P G on C's
+  // tiles and its per-tile sums <Z,G>, <Z,G_old>; P == nullptr: no preconditioning
+  const double* P;
+  double *Z, *zpart;
   SysInfo* info;
   SysState* st;
   double* hist;
@@ -82,6 +86,8 @@ void launch_s2_pbf(hipStream_t s, const Bufs& b, int mask);
 void launch_grad_p64(hipStream_t s, const Bufs& b, int mask);
 void launch_grad_p32(hipStream_t s, const Bufs& b, int mask);
 void launch_grad_pbf(hipStream_t s, const Bufs& b, int mask);
+// Z = P G with the sums <Z,G>, <Z,G_old> per C tile (kinetic preconditioning, FP64)
+void launch_precon(hipStream_t s, const Bufs& b, int mask);
 // the 15 trace sums (init_inputs: of H0 and S0 alone) and from them the
 // line-search step (mode LS_STEP), the initial energy (LS_INIT) or the electron count (LS_REPORT)
 void launch_traces(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init_inputs, int mode,
@@ -142,5 +148,7 @@ void chol_apply_lt(hipStream_t s, const double* L, int lbase, int RT, const doub
                    int WT);     // Cout = L^T Cin
 void chol_solve_lt(hipStream_t s, const double* L, int lbase, int RT, const double* Linv, const double* Cin,
                    double* Cout, int cbase, int WT);   // Cout = L^-T Cin
+void chol_inverse(hipStream_t s, const double* L, int RT, const double* Linv, const double* Id, double* work,
+                  double* P);   // P = (L L^T)^-1 on a grid at offset 0
 
 }  // namespace omm

@@ -364,20 +364,23 @@ __global__ __launch_bounds__(256) void k_update(int nc, int nhc, int ntot, const
 }
 
 // ------------------------------------------------------------------ beta, stop rules (one thread per system)
-// <G_old,G_old> is read from the slot of the previous iteration and <G,G>
+// Polak-Ribiere beta = <Z, G - G_old> / <Z_old, G_old> with Z = G, or Z = P G
+// under kinetic preconditioning (Eq. 7): the sums a = <Z,G>, bo = <Z,G_old>.
+// <Z_old,G_old> is read from the slot of the previous iteration and <Z,G>
 // stored in the slot of this one, so that a kernel in which one wave records
 // the new value while others still read the old one has no conflict.
 __device__ __forceinline__ double gg_prev(const SysState& S) { return S.gg2[(S.iter + 1) & 1]; }
 __device__ __forceinline__ void gg_store(SysState& S, double v) { S.gg2[S.iter & 1] = v; }
-__device__ __forceinline__ double beta_of(const SysState& S, double gg, double go) {
-  return S.restart ? 0.0 : fmax(0.0, (gg - go) / gg_prev(S));
+__device__ __forceinline__ double beta_of(const SysState& S, double a, double bo) {
+  return S.restart ? 0.0 : fmax(0.0, (a - bo) / gg_prev(S));
 }
 
-__device__ void beta_finish(SysState& S, int s, double gg, double go, int init, double* __restrict__ hist,
-                            const CGParams& prm) {
+// gg = <G,G> for the stop rule
+__device__ void beta_finish(SysState& S, int s, double gg, double a, double bo, int init,
+                            double* __restrict__ hist, const CGParams& prm) {
   const double gn = sqrt(gg);
   if (init) {
-    gg_store(S, gg);
+    gg_store(S, a);
     S.gnorm = gn;
     S.beta = 0.0;
     S.steepest = 1;
@@ -385,7 +388,7 @@ __device__ void beta_finish(SysState& S, int s, double gg, double go, int init, 
     S.conv_init = (gn <= prm.tol_grad) ? 1 : 0;
     return;
   }
-  const double beta = beta_of(S, gg, go);
+  const double beta = beta_of(S, a, bo);
   const int64_t row = S.iter - 1;
   if (prm.hist_on && row >= 0 && row < prm.hist_max) {
     double* h = hist + ((size_t)s * prm.hist_max + row) * HCOLS;
@@ -411,52 +414,67 @@ __device__ void beta_finish(SysState& S, int s, double gg, double go, int init, 
     S.phase = PH_DONE;
   }
   S.beta = beta;
-  gg_store(S, gg);
+  gg_store(S, a);
   S.gnorm = gn;
   S.steepest = (beta == 0.0) ? 1 : 0;
+}
+
+// the three sums of tile u: <G,G> and (a, bo) from the preconditioned sums or the plain ones
+__device__ __forceinline__ void tile_sums(const double* __restrict__ gpart, const double* __restrict__ zpart,
+                                          size_t u, double& gg, double& a, double& bo) {
+  gg += gpart[2 * u];
+  if (zpart) {
+    a += zpart[2 * u];
+    bo += zpart[2 * u + 1];
+  } else {
+    a += gpart[2 * u];
+    bo += gpart[2 * u + 1];
+  }
 }
 
 // <G,G> and <G,G_old> of one system summed in tile order, then beta and the
 // stop rules: the start-up step, and in iterations the systems of more than
 // FUSED_CTILES C tiles (k_update_d takes the step of the others itself)
 __global__ __launch_bounds__(256) void k_beta(const SysInfo* __restrict__ info, SysState* __restrict__ st, int mask,
-                                            const double* __restrict__ gpart, int init, double* __restrict__ hist,
-                                            CGParams prm) {
-  __shared__ double red[2][4];
+                                            const double* __restrict__ gpart, const double* __restrict__ zpart,
+                                            int init, double* __restrict__ hist, CGParams prm) {
+  __shared__ double red[3][4];
   const int s = blockIdx.x;
   if ((!init && info[s].c1 - info[s].c0 <= FUSED_CTILES) || !on(st, s, mask)) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  double gg = 0.0, go = 0.0;
-  for (int t = info[s].c0 + threadIdx.x; t < info[s].c1; t += blockDim.x) {
-    gg += gpart[2 * (size_t)t];
-    go += gpart[2 * (size_t)t + 1];
-  }
+  double gg = 0.0, a = 0.0, bo = 0.0;
+  for (int t = info[s].c0 + threadIdx.x; t < info[s].c1; t += blockDim.x) tile_sums(gpart, zpart, t, gg, a, bo);
   gg = wave_sum(gg);
-  go = wave_sum(go);
+  a = wave_sum(a);
+  bo = wave_sum(bo);
   if (lane == 0) {
     red[0][wv] = gg;
-    red[1][wv] = go;
+    red[1][wv] = a;
+    red[2][wv] = bo;
   }
   __syncthreads();
   if (threadIdx.x != 0) return;
   gg = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
-  go = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
-  beta_finish(st[s], s, gg, go, init, hist, prm);
+  a = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
+  bo = ((red[2][0] + red[2][1]) + red[2][2]) + red[2][3];
+  beta_finish(st[s], s, gg, a, bo, init, hist, prm);
 }
 
-// D = -G + beta D and G_old = G: one wave per C tile, four consecutive
-// elements of one tile row per lane.  For a system of at most FUSED_CTILES C
-// tiles every wave adds the per-tile <G,G>, <G,G_old> in tile order and forms
-// beta itself (the same value in every wave); the wave of the system's first
-// C tile also applies the stop rules and records the state.  Fields it writes
-// that others read are either double-buffered (<G,G>) or only change when the
-// system leaves this step's phase (then its D is no longer used).
+// D = -Z + beta D (Z = G, or P G under kinetic preconditioning) and G_old = G:
+// one wave per C tile, four consecutive elements of one tile row per lane.
+// For a system of at most FUSED_CTILES C tiles every wave adds the per-tile
+// sums in tile order and forms beta itself (the same value in every wave); the
+// wave of the system's first C tile also applies the stop rules and records
+// the state.  Fields it writes that others read are either double-buffered
+// (<Z,G>) or only change when the system leaves this step's phase (then its D
+// is no longer used).
 template <typename TL, bool LOW>
 __global__ __launch_bounds__(256) void k_update_d(int nc, const int* __restrict__ upd_sys,
                                                 const SysInfo* __restrict__ info, SysState* __restrict__ st, int mask,
                                                 double* __restrict__ D, const double* __restrict__ G,
-                                                double* __restrict__ Gold, TL* __restrict__ Dl,
-                                                const double* __restrict__ gpart, double* __restrict__ hist,
+                                                const double* __restrict__ Z, double* __restrict__ Gold,
+                                                TL* __restrict__ Dl, const double* __restrict__ gpart,
+                                                const double* __restrict__ zpart, double* __restrict__ hist,
                                                 CGParams prm, int init) {
   const int t = blockIdx.x * 4 + wave_id();
   if (t >= nc) return;
@@ -466,28 +484,27 @@ __global__ __launch_bounds__(256) void k_update_d(int nc, const int* __restrict_
   if (LOW && st[s].prec == 0) return;
   const int ci0 = info[s].c0, ci1 = info[s].c1;
   const size_t o = (size_t)t * TE + (lane >> 2) * 16 + (lane & 3) * 4;
-  double g[4], dv[4];
+  const double* Zs = zpart ? Z : G;
+  double g[4], z[4], dv[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) { g[i] = G[o + i]; dv[i] = D[o + i]; }
+  for (int i = 0; i < 4; ++i) { g[i] = G[o + i]; z[i] = Zs[o + i]; dv[i] = D[o + i]; }
   double beta;
-  if (init) {   // start-up: D = -G (k_beta has recorded the state)
+  if (init) {   // start-up: D = -Z (k_beta has recorded the state)
     beta = 0.0;
   } else if (ci1 - ci0 <= FUSED_CTILES) {
-    double gg = 0.0, go = 0.0;
-    for (int u = ci0 + lane; u < ci1; u += 64) {
-      gg += gpart[2 * (size_t)u];
-      go += gpart[2 * (size_t)u + 1];
-    }
+    double gg = 0.0, a = 0.0, bo = 0.0;
+    for (int u = ci0 + lane; u < ci1; u += 64) tile_sums(gpart, zpart, u, gg, a, bo);
     gg = wave_sum(gg);
-    go = wave_sum(go);
-    beta = beta_of(st[s], gg, go);
-    if (t == ci0 && lane == 0) beta_finish(st[s], s, gg, go, 0, hist, prm);
+    a = wave_sum(a);
+    bo = wave_sum(bo);
+    beta = beta_of(st[s], a, bo);
+    if (t == ci0 && lane == 0) beta_finish(st[s], s, gg, a, bo, 0, hist, prm);
   } else {
     beta = st[s].beta;
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const double d = -g[i] + beta * dv[i];
+    const double d = -z[i] + beta * dv[i];
     D[o + i] = d;
     Gold[o + i] = g[i];
     if (LOW) Dl[o + i] = cvt<TL, double>(d);
@@ -694,22 +711,26 @@ void launch_grad(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init) {
 
 void launch_beta(hipStream_t s, const Bufs& b, int mask, bool init, const CGParams& prm) {
   if (!init && !b.multi_c) return;   // every system takes its beta in k_update_d
-  LAUNCH(k_beta, dim3(b.nsys), dim3(256), s, b.info, b.st, mask, b.gpart, init ? 1 : 0, b.hist, prm);
+  LAUNCH(k_beta, dim3(b.nsys), dim3(256), s, b.info, b.st, mask, b.gpart, b.P ? b.zpart : nullptr, init ? 1 : 0,
+         b.hist, prm);
 }
 
+// kinetic preconditioning runs in FP64 only (the library rejects it with low precision)
 void launch_update_d(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init, const CGParams& prm) {
   if (b.n_tc <= 0) return;
   const dim3 grid((unsigned)((b.n_tc + 3) / 4));
   const int in = init ? 1 : 0;
+  const int* us = b.nsys == 1 ? nullptr : b.upd_sys;
+  const double* zp = b.P ? b.zpart : nullptr;
   if (prec == P64)
-    LAUNCH((k_update_d<double, false>), grid, dim3(256), s, b.n_tc, b.nsys == 1 ? nullptr : b.upd_sys, b.info, b.st, mask, b.D, b.G,
-           b.Gold, (double*)nullptr, b.gpart, b.hist, prm, in);
+    LAUNCH((k_update_d<double, false>), grid, dim3(256), s, b.n_tc, us, b.info, b.st, mask, b.D, b.G, b.Z, b.Gold,
+           (double*)nullptr, b.gpart, zp, b.hist, prm, in);
   else if (prec == P32)
-    LAUNCH((k_update_d<float, true>), grid, dim3(256), s, b.n_tc, b.nsys == 1 ? nullptr : b.upd_sys, b.info, b.st, mask, b.D, b.G, b.Gold,
-           (float*)b.Dl, b.gpart, b.hist, prm, in);
+    LAUNCH((k_update_d<float, true>), grid, dim3(256), s, b.n_tc, us, b.info, b.st, mask, b.D, b.G,
+           (const double*)nullptr, b.Gold, (float*)b.Dl, b.gpart, (const double*)nullptr, b.hist, prm, in);
   else
-    LAUNCH((k_update_d<bf16, true>), grid, dim3(256), s, b.n_tc, b.nsys == 1 ? nullptr : b.upd_sys, b.info, b.st, mask, b.D, b.G, b.Gold,
-           (bf16*)b.Dl, b.gpart, b.hist, prm, in);
+    LAUNCH((k_update_d<bf16, true>), grid, dim3(256), s, b.n_tc, us, b.info, b.st, mask, b.D, b.G,
+           (const double*)nullptr, b.Gold, (bf16*)b.Dl, b.gpart, (const double*)nullptr, b.hist, prm, in);
 }
 
 void launch_init_finish(hipStream_t s, const Bufs& b) {

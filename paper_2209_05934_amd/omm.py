@@ -89,6 +89,7 @@ def load(path: Optional[str] = None) -> C.CDLL:
         "omm_density_matrix": (I32, [P, I32, P, I32]),
         "omm_energy_density": (I32, [P, I32, P, I32]),
         "omm_set_occupied": (I32, [P, I32, I64]),
+        "omm_set_preconditioner": (I32, [P, MP, D]),
         "omm_get_coeffs": (I32, [P, I32, P, I32]),
         "omm_get_projected": (I32, [P, I32, P, P, I32]),
         "omm_get_history": (I32, [P, I32, P, I64, C.POINTER(I64)]),
@@ -110,7 +111,7 @@ def load(path: Optional[str] = None) -> C.CDLL:
 
 EXPORTED = ("omm_default_options", "omm_init", "omm_init_batch", "omm_set_coeffs", "omm_minimize",
             "omm_density_matrix", "omm_energy_density", "omm_get_coeffs", "omm_get_projected",
-            "omm_get_history", "omm_query", "omm_set_occupied", "omm_set_timing", "omm_kernel_times", "omm_time_step",
+            "omm_get_history", "omm_query", "omm_set_occupied", "omm_set_preconditioner", "omm_set_timing", "omm_kernel_times", "omm_time_step",
             "omm_status_str", "omm_last_error", "omm_destroy")
 
 
@@ -222,6 +223,12 @@ def omm_density_matrix(ctx, sys: int, out) -> int:
 
 def omm_set_occupied(ctx, sys: int, n_occupied: int) -> int:
     return _check(ctx, load().omm_set_occupied(ctx, int(sys), int(n_occupied)))
+
+
+def omm_set_preconditioner(ctx, T, tau: float) -> int:
+    """T: BlockArgs of the kinetic matrix (None removes the preconditioner)."""
+    ref = C.byref(T.struct) if T is not None else None
+    return _check(ctx, load().omm_set_preconditioner(ctx, ref, float(tau)))
 
 
 def omm_energy_density(ctx, sys: int, out) -> int:

@@ -24,6 +24,9 @@ class Problem:
     mode: int = L.OMM_DENSE
     eta: Optional[float] = None  # Kim shift of this system (None: the context option)
     n_occupied: Optional[int] = None  # occupied states when fewer than n (Kim); None: n
+    T: Any = None      # kinetic matrix for preconditioning (dense, single system)
+    tau: float = 0.0   # its scale tau_T (> 0 with T)
+    T_val: Any = None
     H_val: Any = None  # optional device tensors replacing the host values
     S_val: Any = None
     C0_val: Any = None
@@ -57,6 +60,9 @@ class Context:
             self.set_coeffs(i, p.C0, p.C0_val)
             if p.n_occupied is not None:
                 L.omm_set_occupied(self.ctx, i, p.n_occupied)
+            if p.T is not None:
+                self._T = L.BlockArgs.from_block_matrix(p.T, p.T_val)
+                L.omm_set_preconditioner(self.ctx, self._T, p.tau)
 
     @property
     def count(self) -> int:

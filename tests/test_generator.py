@@ -84,3 +84,17 @@ def test_batch_specs():
     assert min(sides) >= 3 and max(sides) <= 7
     assert sum(sp.dense for sp in specs) == 32
     assert len({sp.seed for sp in specs}) == 64
+
+
+def test_kinetic_matrix():
+    from dataclasses import replace
+    base = make_system(config_spec("chain8"))
+    s = make_system(replace(config_spec("chain8"), kinetic=10.0))
+    T = s.T.to_dense()
+    assert np.array_equal(T, T.T)
+    assert np.linalg.eigvalsh(T).min() > 0.0
+    # T has H's block pattern and is the only change to the inputs
+    assert np.array_equal(s.T.col_idx, s.H.col_idx) and np.array_equal(s.T.row_ptr, s.H.row_ptr)
+    assert np.allclose(s.H.to_dense() - base.H.to_dense(), T, atol=1e-14, rtol=0)
+    assert np.array_equal(s.S.val, base.S.val) and np.array_equal(s.C0.val, base.C0.val)
+    assert base.T is None

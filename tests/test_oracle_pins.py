@@ -339,3 +339,37 @@ def test_kim_more_wavefunctions_than_occupied_states(eta):
     assert np.max(np.abs(O.density_matrix(res.C, res.SW) - 2.0 * Xn @ Xn.T)) <= 1e-8
     rho_e = O.energy_density_matrix(res.C, res.HW, res.SW, eta)
     assert np.max(np.abs(rho_e - 2.0 * Xn @ np.diag(w[:nocc]) @ Xn.T)) <= 1e-8
+
+
+# ------------------------------------------------------------ kinetic preconditioning (Eq. 7)
+@pytest.fixture(scope="module")
+def kinetic4():
+    from dataclasses import replace
+    s = make_system(replace(config_spec("cubic4_dense"), kinetic=30.0))
+    return s, s.H.to_dense(), s.S.to_dense(), s.C0.to_dense(), s.T.to_dense()
+
+
+def test_identity_preconditioner_is_plain_cg(chain):
+    s, H, S, C0 = chain
+    plain = O.cg_minimize(H, S, C0, tol_grad=1e-9)
+    ident = O.cg_minimize(H, S, C0, tol_grad=1e-9, precon=np.eye(s.m))
+    assert ident.iterations == plain.iterations
+    for a, b in zip(plain.history, ident.history):
+        assert a["E"] == b["E"] and a["x"] == b["x"] and a["beta"] == b["beta"]
+
+
+def test_preconditioned_cg_reaches_the_same_minimum_faster(kinetic4):
+    # Sec. II: preconditioning changes the path, not the minimum; with the kinetic
+    # scale of Table 1's default order it needs far fewer CG iterations here
+    s, H, S, C0, T = kinetic4
+    P = O.kinetic_preconditioner(S, T, 5.0)
+    assert np.max(np.abs(P @ (S + T / 5.0) - np.eye(s.m))) <= 1e-10
+    plain = O.cg_minimize(H, S, C0, tol_grad=1e-9, max_iter=5000)
+    pre = O.cg_minimize(H, S, C0, tol_grad=1e-9, max_iter=5000, precon=P)
+    assert plain.converged and pre.converged
+    Estar, rho_star, _ = _eigen(H, S, s.n)
+    assert abs(pre.energy - Estar) / s.natoms <= 1e-10
+    assert np.max(np.abs(O.density_matrix(pre.C, pre.SW) - rho_star)) <= 1e-8
+    assert pre.iterations * 2 < plain.iterations
+    # every step is a descent step: c1 = <dE/dC, D> < 0
+    assert all(h["c"][1] < 0.0 for h in pre.history)
