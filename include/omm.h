@@ -186,6 +186,42 @@ int omm_init_batch(omm_ctx** out, int32_t count, const omm_matrix* H, const omm_
  * Column blocks must be at most 16 wide in OMM_BLOCK_SPARSE mode. */
 int omm_set_coeffs(omm_ctx* ctx, int32_t sys, const omm_matrix* C0);
 
+/* New values of H and S for system `sys` on the block structure and value
+ * layout (val_off) given at init: the next SCF step (new H) or MD step (new H
+ * and S) reuses the context, its symbolic phase, tuned kernels and captured
+ * graphs (Sec. III A, Fig. 2: the solver is called again at every SCF step).
+ * The Kim shift and, in OMM_DENSE_CHOLESKY mode, the Cholesky reduction are
+ * redone; a kinetic preconditioner is removed (it depends on S: set it again).
+ * Values host or device, borrowed for the call.  A warm start from the
+ * previous solution is omm_set_coeffs with the C of omm_get_coeffs.  Outputs
+ * (rho, C, ...) wait for the next omm_minimize (OMM_ERR_STATE before it).
+ * Different structure or layout: OMM_ERR_ARG; S not positive definite in
+ * Cholesky mode: OMM_ERR_NOT_SPD. */
+int omm_update_hs(omm_ctx* ctx, int32_t sys, const omm_matrix* H, const omm_matrix* S);
+
+/* Coefficient reuse across MD steps (Sec. III C; Table 1 OMM.Extrapolate),
+ * host memory only, no context: writes into out (to->nval doubles, in the
+ * layout of to->val_off) the guess for the pattern `to` of the new geometry.
+ * Blocks of `to` missing from `cur` start at zero (atoms that came within the
+ * localization radius); blocks of `cur` missing from `to` are dropped.  With
+ * prev != NULL (the step before cur) a block present in both takes the linear
+ * extrapolation 2 cur - prev; otherwise the value of cur.  cur, prev and to
+ * must have the same block rows and columns and block sizes.  Errors:
+ * OMM_ERR_ARG, message in omm_last_error(NULL). */
+int omm_remap_coeffs(const omm_matrix* cur, const omm_matrix* prev, const omm_matrix* to, double* out);
+
+/* Restart file of C (Sec. III D, the m_write / m_read pair): omm_write_coeffs
+ * stores the block structure and values of C (host memory) in a binary file
+ * (magic "OMMCOEF1", little-endian: int32 nbrow, nbcol; int64 nnzb, nval;
+ * int32 row_bsz[nbrow], col_bsz[nbcol]; int64 row_ptr[nbrow+1]; int32
+ * col_idx[nnzb]; then each block's row-major doubles in block order).
+ * omm_read_coeffs reads such a file and, as omm_remap_coeffs does, corrects
+ * its pattern to `to` (the current geometry's): out receives to->nval
+ * doubles.  File or format errors: OMM_ERR_ARG, message in
+ * omm_last_error(NULL). */
+int omm_write_coeffs(const char* path, const omm_matrix* C);
+int omm_read_coeffs(const char* path, const omm_matrix* to, double* out);
+
 /* Kim functional with more wavefunctions than occupied states (Sec. II, step
  * 2: C is m x n' with n' > n): the n_occ given at init is the column count n'
  * of C, and this call declares that only n_occupied of them are occupied

@@ -25,6 +25,12 @@ namespace {
 
 thread_local std::string g_last_init_error;
 
+}  // namespace
+
+void omm::set_global_error(const std::string& msg) { g_last_init_error = msg; }
+
+namespace {
+
 struct MatDesc {   // host copy of an input matrix's block structure
   int nbrow = 0, nbcol = 0;
   std::vector<int> rbs, cbs;
@@ -450,6 +456,42 @@ void count_dense_work(SysHost& s) {
 }
 
 // ----------------------------------------------------------------- init (H, S ingest)
+// values of system i's H and S into their tiles (the tiles' other entries stay as they are)
+void scatter_hs(omm_ctx* c, int i, const omm_matrix* H, const omm_matrix* S, std::vector<void*>& tmp) {
+  SysHost& s = c->sys[i];
+  const double* hv = values_on_device(c, H, tmp);
+  const double* sv = values_on_device(c, S, tmp);
+  launch_scatter(c->stream, blkmap(s.mh, nullptr, s, false, c->TH), hv, c->H);
+  launch_scatter(c->stream, blkmap(s.mh, s.s_voff, s, false, c->TH), sv, c->S);
+}
+
+// Kim shift (Sec. II) and, in OMM_DENSE_CHOLESKY mode, the Cholesky reduction of system i
+void shift_reduce(omm_ctx* c, int i) {
+  hipStream_t st = c->stream;
+  SysHost& s = c->sys[i];
+  const int h0 = c->TH.hrp[s.rb0], h1 = c->TH.hrp[s.rb0 + s.RT];
+  if (s.eta != 0.0)
+    launch_axpy_tiles(st, h1 - h0, -s.eta, c->S + (size_t)h0 * TE, c->H + (size_t)h0 * TE);
+  if (s.mode != OMM_DENSE_CHOLESKY) return;
+  launch_pad_identity(st, c->S, h0, s.RT, s.m);
+  if (!s.Linv) s.Linv = dalloc<double>(c, (size_t)s.RT * TE, false);
+  if (!s.chol_status) s.chol_status = dalloc<int>(c, 1, false);
+  OMM_HIP(hipMemsetAsync(s.chol_status, 0, sizeof(int), st));
+  chol_factor(st, c->S, h0, s.RT, s.Linv, s.chol_status);
+  int flag = 0;
+  OMM_HIP(hipMemcpyAsync(&flag, s.chol_status, sizeof(int), hipMemcpyDeviceToHost, st));
+  OMM_HIP(hipStreamSynchronize(st));
+  if (flag) throw ArgError("__NOT_SPD__");
+  double* work = nullptr;
+  if (hipMalloc(&work, (size_t)s.RT * s.RT * TE * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    throw OomError("Cholesky work buffer");
+  }
+  chol_reduce_h(st, c->S, h0, s.RT, s.Linv, c->H, h0, work);
+  OMM_HIP(hipStreamSynchronize(st));
+  (void)hipFree(work);
+}
+
 void ingest(omm_ctx* c, int count, const omm_matrix* H, const omm_matrix* S, const int64_t* n_occ,
             const int32_t* modes, const double* etas) {
   c->nsys = count;
@@ -544,39 +586,11 @@ void ingest(omm_ctx* c, int count, const omm_matrix* H, const omm_matrix* S, con
     s.roff = dupload(c, roff, false);
     s.mh = upload_map(c, s.H, false);
     s.s_voff = dupload(c, s.S.voff, false);
-    const double* hv = values_on_device(c, &H[i], tmp);
-    const double* sv = values_on_device(c, &S[i], tmp);
-    launch_scatter(st, blkmap(s.mh, nullptr, s, false, c->TH), hv, c->H);
-    launch_scatter(st, blkmap(s.mh, s.s_voff, s, false, c->TH), sv, c->S);
+    scatter_hs(c, i, &H[i], &S[i], tmp);
   }
   OMM_HIP(hipStreamSynchronize(st));
   for (void* p : tmp) (void)hipFree(p);
-  // Kim shift and Cholesky reduction
-  for (int i = 0; i < count; ++i) {
-    SysHost& s = c->sys[i];
-    const int h0 = c->TH.hrp[s.rb0], h1 = c->TH.hrp[s.rb0 + s.RT];
-    if (s.eta != 0.0)
-      launch_axpy_tiles(st, h1 - h0, -s.eta, c->S + (size_t)h0 * TE, c->H + (size_t)h0 * TE);
-    if (s.mode == OMM_DENSE_CHOLESKY) {
-      launch_pad_identity(st, c->S, h0, s.RT, s.m);
-      s.Linv = dalloc<double>(c, (size_t)s.RT * TE, false);
-      s.chol_status = dalloc<int>(c, 1, false);
-      OMM_HIP(hipMemsetAsync(s.chol_status, 0, sizeof(int), st));
-      chol_factor(st, c->S, h0, s.RT, s.Linv, s.chol_status);
-      int flag = 0;
-      OMM_HIP(hipMemcpyAsync(&flag, s.chol_status, sizeof(int), hipMemcpyDeviceToHost, st));
-      OMM_HIP(hipStreamSynchronize(st));
-      if (flag) throw ArgError("__NOT_SPD__");
-      double* work = nullptr;
-      if (hipMalloc(&work, (size_t)s.RT * s.RT * TE * sizeof(double)) != hipSuccess) {
-        (void)hipGetLastError();
-        throw OomError("Cholesky work buffer");
-      }
-      chol_reduce_h(st, c->S, h0, s.RT, s.Linv, c->H, h0, work);
-      OMM_HIP(hipStreamSynchronize(st));
-      (void)hipFree(work);
-    }
-  }
+  for (int i = 0; i < count; ++i) shift_reduce(c, i);
   OMM_HIP(hipStreamSynchronize(st));
 }
 
@@ -1394,6 +1408,43 @@ const char* omm_status_str(int32_t s) {
 }
 
 const char* omm_last_error(const omm_ctx* c) { return c ? c->err.c_str() : g_last_init_error.c_str(); }
+
+int omm_update_hs(omm_ctx* c, int32_t sys, const omm_matrix* H, const omm_matrix* S) {
+  if (!c) return OMM_ERR_ARG;
+  struct A { int sys; const omm_matrix* H; const omm_matrix* S; } a{sys, H, S};
+  return guard(c, [](omm_ctx* cc, void* v) -> int {
+    auto* q = (A*)v;
+    if (q->sys < 0 || q->sys >= cc->nsys) throw ArgError("system index out of range");
+    SysHost& s = cc->sys[q->sys];
+    MatDesc dh, ds;
+    copy_desc(dh, q->H, "H");
+    copy_desc(ds, q->S, "S");
+    if (!dh.same_pattern(s.H) || !ds.same_pattern(s.S) || dh.voff != s.H.voff || ds.voff != s.S.voff)
+      throw ArgError("H and S must keep the block structure and value layout given at init");
+    hipStream_t st = cc->stream;
+    OMM_HIP(hipStreamSynchronize(st));
+    if (cc->P) {   // P = (S + T/tau)^-1 belongs to the old S
+      auto it = std::find(cc->alloc_init.begin(), cc->alloc_init.end(), (void*)cc->P);
+      if (it != cc->alloc_init.end()) cc->alloc_init.erase(it);
+      (void)hipFree(cc->P);
+      cc->P = nullptr;
+      cc->prepared = false;
+    }
+    std::vector<void*> tmp;
+    try {
+      scatter_hs(cc, q->sys, q->H, q->S, tmp);
+      OMM_HIP(hipStreamSynchronize(st));
+    } catch (...) {
+      for (void* p : tmp) (void)hipFree(p);
+      throw;
+    }
+    for (void* p : tmp) (void)hipFree(p);
+    cc->ran = false;        // outputs wait for the next minimize
+    cc->hs_cast = false;    // low-precision copies of H and S are stale
+    shift_reduce(cc, q->sys);
+    return OMM_OK;
+  }, &a);
+}
 
 int omm_init_batch(omm_ctx** out, int32_t count, const omm_matrix* H, const omm_matrix* S, const int64_t* n_occ,
                    const int32_t* modes, const double* etas, const omm_options* opt) {

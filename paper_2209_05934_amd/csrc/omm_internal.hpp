@@ -22,6 +22,9 @@
 
 namespace omm {
 
+// the message omm_last_error(NULL) returns (per host thread)
+void set_global_error(const std::string& msg);
+
 constexpr int T = 16;          // tile edge
 constexpr int TE = T * T;      // tile elements
 constexpr int MAXW = 8192;     // largest per-system tile window of the symbolic kernels

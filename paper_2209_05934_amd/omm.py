@@ -90,6 +90,10 @@ def load(path: Optional[str] = None) -> C.CDLL:
         "omm_energy_density": (I32, [P, I32, P, I32]),
         "omm_set_occupied": (I32, [P, I32, I64]),
         "omm_set_preconditioner": (I32, [P, MP, D]),
+        "omm_update_hs": (I32, [P, I32, MP, MP]),
+        "omm_remap_coeffs": (I32, [MP, MP, MP, P]),
+        "omm_write_coeffs": (I32, [C.c_char_p, MP]),
+        "omm_read_coeffs": (I32, [C.c_char_p, MP, P]),
         "omm_get_coeffs": (I32, [P, I32, P, I32]),
         "omm_get_projected": (I32, [P, I32, P, P, I32]),
         "omm_get_history": (I32, [P, I32, P, I64, C.POINTER(I64)]),
@@ -111,7 +115,8 @@ def load(path: Optional[str] = None) -> C.CDLL:
 
 EXPORTED = ("omm_default_options", "omm_init", "omm_init_batch", "omm_set_coeffs", "omm_minimize",
             "omm_density_matrix", "omm_energy_density", "omm_get_coeffs", "omm_get_projected",
-            "omm_get_history", "omm_query", "omm_set_occupied", "omm_set_preconditioner", "omm_set_timing", "omm_kernel_times", "omm_time_step",
+            "omm_get_history", "omm_query", "omm_set_occupied", "omm_set_preconditioner", "omm_update_hs",
+            "omm_remap_coeffs", "omm_write_coeffs", "omm_read_coeffs", "omm_set_timing", "omm_kernel_times", "omm_time_step",
             "omm_status_str", "omm_last_error", "omm_destroy")
 
 
@@ -229,6 +234,38 @@ def omm_set_preconditioner(ctx, T, tau: float) -> int:
     """T: BlockArgs of the kinetic matrix (None removes the preconditioner)."""
     ref = C.byref(T.struct) if T is not None else None
     return _check(ctx, load().omm_set_preconditioner(ctx, ref, float(tau)))
+
+
+def omm_update_hs(ctx, sys: int, H, S) -> int:
+    """H, S: BlockArgs with the new values on the structure given at init."""
+    return _check(ctx, load().omm_update_hs(ctx, int(sys), C.byref(H.struct), C.byref(S.struct)))
+
+
+def _host_call(rc: int) -> int:
+    if rc != OMM_OK:
+        raise OmmError(rc, omm_last_error(None))
+    return rc
+
+
+def omm_remap_coeffs(cur, prev, to):
+    """Guess on pattern `to` from `cur` (and linear extrapolation with `prev`); block matrices in host memory."""
+    a, b, t = (BlockArgs.from_block_matrix(m) if m is not None else None for m in (cur, prev, to))
+    out = np.zeros(to.val.size)
+    _host_call(load().omm_remap_coeffs(C.byref(a.struct), C.byref(b.struct) if b else None, C.byref(t.struct),
+                                       out.ctypes.data))
+    return out
+
+
+def omm_write_coeffs(path: str, Cm) -> None:
+    a = BlockArgs.from_block_matrix(Cm)
+    _host_call(load().omm_write_coeffs(os.fsencode(path), C.byref(a.struct)))
+
+
+def omm_read_coeffs(path: str, to):
+    t = BlockArgs.from_block_matrix(to)
+    out = np.zeros(to.val.size)
+    _host_call(load().omm_read_coeffs(os.fsencode(path), C.byref(t.struct), out.ctypes.data))
+    return out
 
 
 def omm_energy_density(ctx, sys: int, out) -> int:

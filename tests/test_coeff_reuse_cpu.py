@@ -1,0 +1,97 @@
+"""Coefficient reuse across SCF/MD steps (host functions of the C ABI, no GPU):
+pattern update, linear extrapolation and the restart file (Sec. III C-D).
+Expected values come from dense NumPy arithmetic on the same block matrices."""
+
+import os
+import tempfile
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+from ommgen import BlockMatrix
+from ommgen.systems import cubic_spec, make_system
+from paper_2209_05934_amd import omm as L
+
+
+def _with_blocks(bm: BlockMatrix, keep, add, seed=0) -> BlockMatrix:
+    """Block matrix with bm's block sizes on a new pattern: bm's blocks minus `keep`==False, plus `add`."""
+    rows = bm.block_rows()
+    blocks = {(int(rows[k]), int(bm.col_idx[k])) for k in range(bm.nnzb) if keep[k]} | set(add)
+    blocks = sorted(blocks)
+    rp = np.zeros(bm.nbrow + 1, dtype=np.int64)
+    for i, _ in blocks:
+        rp[i + 1] += 1
+    rp = np.cumsum(rp)
+    ci = np.array([j for _, j in blocks], dtype=np.int32)
+    sizes = [int(bm.row_bsz[i]) * int(bm.col_bsz[j]) for i, j in blocks]
+    off = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    val = np.random.default_rng(seed).standard_normal(int(sum(sizes)))
+    return BlockMatrix(bm.row_bsz.copy(), bm.col_bsz.copy(), rp, ci, off, val)
+
+
+@pytest.fixture(scope="module")
+def mats():
+    s = make_system(replace(cubic_spec(3, 5, dense=False), rc=1.2))
+    cur = s.C0
+    rng = np.random.default_rng(1)
+    keep = rng.random(cur.nnzb) > 0.2
+    rows = cur.block_rows()
+    present = {(int(rows[k]), int(cur.col_idx[k])) for k in range(cur.nnzb)}
+    absent = [(i, j) for i in range(cur.nbrow) for j in range(cur.nbcol) if (i, j) not in present]
+    add = [absent[k] for k in rng.choice(len(absent), size=min(15, len(absent)), replace=False)]
+    to = _with_blocks(cur, keep, add, seed=2)
+    prev = _with_blocks(cur, rng.random(cur.nnzb) > 0.3, [], seed=3)
+    assert set(add) and not keep.all()
+    return cur, prev, to
+
+
+def test_remap_same_pattern_is_identity(mats):
+    cur, _, _ = mats
+    assert np.array_equal(L.omm_remap_coeffs(cur, None, cur), cur.val)
+
+
+def test_remap_drops_and_zero_fills(mats):
+    cur, _, to = mats
+    out = L.omm_remap_coeffs(cur, None, to)
+    assert np.array_equal(out, to.gather_from_dense(cur.to_dense()))
+    # the new blocks are exactly zero, the kept ones exactly cur's
+    new = to.pattern_mask() & ~cur.pattern_mask()
+    assert new.any() and np.all(to.with_values(out).to_dense()[new] == 0.0)
+
+
+def test_linear_extrapolation(mats):
+    cur, prev, to = mats
+    out = L.omm_remap_coeffs(cur, prev, to)
+    cd, pd = cur.to_dense(), prev.to_dense()
+    want = np.where(prev.pattern_mask(), 2.0 * cd - pd, cd)
+    assert np.array_equal(out, to.gather_from_dense(want))
+
+
+def test_restart_file_roundtrip_and_pattern_correction(mats):
+    cur, _, to = mats
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "c.ommc")
+        L.omm_write_coeffs(path, cur)
+        assert os.path.getsize(path) == 8 + 8 + 16 + 4 * (cur.nbrow + cur.nbcol) + 8 * (cur.nbrow + 1) \
+            + 4 * cur.nnzb + 8 * cur.val.size
+        assert np.array_equal(L.omm_read_coeffs(path, cur), cur.val)
+        assert np.array_equal(L.omm_read_coeffs(path, to), L.omm_remap_coeffs(cur, None, to))
+        # corrupt files are refused with a message
+        raw = open(path, "rb").read()
+        open(path, "wb").write(b"XXXX" + raw[4:])
+        with pytest.raises(L.OmmError, match="not a coefficient file"):
+            L.omm_read_coeffs(path, cur)
+        open(path, "wb").write(raw[:len(raw) // 2])
+        with pytest.raises(L.OmmError, match="truncated"):
+            L.omm_read_coeffs(path, cur)
+        with pytest.raises(L.OmmError, match="cannot open"):
+            L.omm_read_coeffs(os.path.join(d, "missing"), cur)
+
+
+def test_block_sizes_must_match(mats):
+    cur, _, _ = mats
+    other = BlockMatrix(cur.row_bsz.copy(), cur.col_bsz.copy() + 1, cur.row_ptr, cur.col_idx,
+                        cur.val_off, np.zeros(cur.val.size * 2))
+    with pytest.raises(L.OmmError, match="same block"):
+        L.omm_remap_coeffs(cur, None, other)
