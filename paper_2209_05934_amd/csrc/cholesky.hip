@@ -121,7 +121,8 @@ __global__ __launch_bounds__(256) void k_trsm_fwd(const double* __restrict__ L, 
     const double bv = transB ? B[tix(bbase, ncols, J, I) + j * 16 + row] : B[tix(bbase, ncols, I, J) + row * 16 + j];
     rhs[r] = bv - acc[r];
   }
-  Frag<double> fa, fb = acc_as_b<double>(rhs);
+  __shared__ double lt[4][TE];
+  Frag<double> fa, fb = acc_as_b_lds(rhs, lt[threadIdx.x >> 6], lane);
   ld_row(fa, Linv + (size_t)I * TE, lane);
   d4 out = vzero<d4>();
   mma(out, fa, fb);
@@ -166,7 +167,8 @@ __global__ __launch_bounds__(256) void k_trsm_bwd_t(const double* __restrict__ L
   d4 rhs;
 #pragma unroll
   for (int r = 0; r < 4; ++r) rhs[r] = Cin[tix(cbase, WT, I, g) + out_off<d4>(lane, r)] - acc[r];
-  Frag<double> fa, fb = acc_as_b<double>(rhs);
+  __shared__ double lt[4][TE];
+  Frag<double> fa, fb = acc_as_b_lds(rhs, lt[threadIdx.x >> 6], lane);
   ld_col(fa, Linv + (size_t)I * TE, lane);         // A = Linv_I^T
   d4 out = vzero<d4>();
   mma(out, fa, fb);

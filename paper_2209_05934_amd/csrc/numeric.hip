@@ -237,13 +237,26 @@ __global__ __launch_bounds__(256) void k_traces(const int4* __restrict__ chunks,
 
 // The 15 sums of one system in every lane of the calling wave: lane l adds
 // chunks ch0 + l, ch0 + l + 64, ... in order, then a butterfly over the wave.
+// Four chunks per lane are loaded before any is added (index clamped, value
+// masked), so their loads are in flight together.
 __device__ __forceinline__ void sum_partials(const double* __restrict__ part, int ch0, int ch1, int lane,
                                              double (&a)[NSUM]) {
 #pragma unroll
   for (int k = 0; k < NSUM; ++k) a[k] = 0.0;
-  for (int c = ch0 + lane; c < ch1; c += 64) {
+  for (int c = ch0 + lane; c < ch1; c += 4 * 64) {
+    double v[4][NSUM];
 #pragma unroll
-    for (int k = 0; k < NSUM; ++k) a[k] += part[(size_t)c * NSUM + k];
+    for (int q = 0; q < 4; ++q) {
+      const int cc = min(c + 64 * q, ch1 - 1);
+#pragma unroll
+      for (int k = 0; k < NSUM; ++k) v[q][k] = part[(size_t)cc * NSUM + k];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (c + 64 * q < ch1) {
+#pragma unroll
+        for (int k = 0; k < NSUM; ++k) a[k] += v[q][k];
+      }
   }
 #pragma unroll
   for (int k = 0; k < NSUM; ++k) a[k] = wave_sum(a[k]);
@@ -419,16 +432,30 @@ __device__ void beta_finish(SysState& S, int s, double gg, double a, double bo, 
   S.steepest = (beta == 0.0) ? 1 : 0;
 }
 
-// the three sums of tile u: <G,G> and (a, bo) from the preconditioned sums or the plain ones
-__device__ __forceinline__ void tile_sums(const double* __restrict__ gpart, const double* __restrict__ zpart,
-                                          size_t u, double& gg, double& a, double& bo) {
-  gg += gpart[2 * u];
-  if (zpart) {
-    a += zpart[2 * u];
-    bo += zpart[2 * u + 1];
-  } else {
-    a += gpart[2 * u];
-    bo += gpart[2 * u + 1];
+// the three sums over tiles u0 + STRIDE q (q = 0, 1, ...) below u1 of one lane:
+// <G,G> and (a, bo) from the preconditioned sums or the plain ones; eight
+// tiles' values are loaded before any is added (index clamped, value masked),
+// so their loads are in flight together, and are added in tile order
+template <int STRIDE>
+__device__ __forceinline__ void lane_sums(const double* __restrict__ gpart, const double* __restrict__ zpart,
+                                          int u0, int u1, double& gg, double& a, double& bo) {
+  const double* ab = zpart ? zpart : gpart;
+  for (int u = u0; u < u1; u += 8 * STRIDE) {
+    double g[8], x[8], y[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const size_t uu = (size_t)min(u + STRIDE * q, u1 - 1);
+      g[q] = gpart[2 * uu];
+      x[q] = ab[2 * uu];
+      y[q] = ab[2 * uu + 1];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (u + STRIDE * q < u1) {
+        gg += g[q];
+        a += x[q];
+        bo += y[q];
+      }
   }
 }
 
@@ -443,7 +470,7 @@ __global__ __launch_bounds__(256) void k_beta(const SysInfo* __restrict__ info, 
   if ((!init && info[s].c1 - info[s].c0 <= FUSED_CTILES) || !on(st, s, mask)) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double gg = 0.0, a = 0.0, bo = 0.0;
-  for (int t = info[s].c0 + threadIdx.x; t < info[s].c1; t += blockDim.x) tile_sums(gpart, zpart, t, gg, a, bo);
+  lane_sums<256>(gpart, zpart, info[s].c0 + threadIdx.x, info[s].c1, gg, a, bo);
   gg = wave_sum(gg);
   a = wave_sum(a);
   bo = wave_sum(bo);
@@ -493,7 +520,7 @@ __global__ __launch_bounds__(256) void k_update_d(int nc, const int* __restrict_
     beta = 0.0;
   } else if (ci1 - ci0 <= FUSED_CTILES) {
     double gg = 0.0, a = 0.0, bo = 0.0;
-    for (int u = ci0 + lane; u < ci1; u += 64) tile_sums(gpart, zpart, u, gg, a, bo);
+    lane_sums<64>(gpart, zpart, ci0 + lane, ci1, gg, a, bo);
     gg = wave_sum(gg);
     a = wave_sum(a);
     bo = wave_sum(bo);

@@ -3,12 +3,11 @@
 // One 64-lane wavefront multiplies two 16x16 row-major tiles.  Lane
 // l = i + 16*q (i = l & 15, q = l >> 4) supplies, at MFMA step s = 0..3,
 // A[i][k] and B[k][j=i] for one tile index k = K(q, s).  The pairing of k with
-// (q, s) is free as long as A and B agree, and is chosen per instruction so
-// that the accumulator can feed the next product as a B fragment:
-//   v_mfma_f64_16x16x4f64 : accumulator register r of lane (j, q) holds row 4r+q
-//                            -> K(q, s) = 4s + q
-//   v_mfma_f32_16x16x4f32 and v_mfma_f32_16x16x16bf16_1k : register r of lane
-//                            (j, q) holds row 4q+r -> K(q, s) = 4q + s
+// (q, s) is free as long as A and B agree; K(q, s) = 4q + s gives each lane
+// four consecutive elements of an A row, which the compiler loads as wide
+// vector loads.  Accumulator register r of lane (j, q) holds output row
+//   v_mfma_f64_16x16x4f64 : 4r + q
+//   v_mfma_f32_16x16x4f32 and v_mfma_f32_16x16x16bf16_1k : 4q + r
 // (the f64 placement was measured on gfx950 with delta operands).
 #pragma once
 
@@ -53,7 +52,6 @@ template <typename T> struct Frag { T v[4]; };
 
 // tile index k supplied by lane-quad q at step s
 template <typename T> struct KMap { static __device__ __forceinline__ int k(int q, int s) { return 4 * q + s; } };
-template <> struct KMap<double> { static __device__ __forceinline__ int k(int q, int s) { return 4 * s + q; } };
 
 // output row of accumulator register r in lane-quad q
 template <typename V> struct Lay;
@@ -99,12 +97,17 @@ template <> __device__ __forceinline__ f4 vzero<f4>() { return f4{0.f, 0.f, 0.f,
 template <typename V>
 __device__ __forceinline__ int out_off(int lane, int r) { return Lay<V>::row(lane >> 4, r) * 16 + (lane & 15); }
 
-// use an accumulator as a B fragment of the next product
-template <typename T, typename V>
-__device__ __forceinline__ Frag<T> acc_as_b(const V& a) {
-  Frag<T> f;
+// an FP64 accumulator tile as the B operand of the next product, through a
+// 16x16 LDS tile owned by the calling wave (LDS operations of one wave
+// complete in order, so the reads see the writes)
+__device__ __forceinline__ Frag<double> acc_as_b_lds(const d4& a, double* t, int lane) {
 #pragma unroll
-  for (int s = 0; s < 4; ++s) f.v[s] = cvt<T, typename Acc<T>::S>((typename Acc<T>::S)a[s]);
+  for (int r = 0; r < 4; ++r) t[out_off<d4>(lane, r)] = a[r];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  Frag<double> f;
+  ld_col(f, t, lane);
   return f;
 }
 
