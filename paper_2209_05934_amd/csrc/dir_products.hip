@@ -10,7 +10,9 @@ namespace {
 
 // ------------------------------------------------------------------ S1: HD = H D, SD = S D
 // One wave-group per group of NT output tiles in one row of the HC pattern:
-// per k the H and S tiles are loaded once and multiply NT tiles of D.
+// per k the H and S tiles are loaded once and multiply NT tiles of D.  H and S
+// are symmetric: the work list names tile (k, i) for A(i, k), loaded down its
+// columns.
 // ONE: the single product Z = P G of kinetic preconditioning (Eq. 7; dense
 // systems, whose HC and C patterns coincide): Hm = P, Bm = G, Z written in C's
 // tile layout with the per-tile sums <Z, G> and <Z, G_old> in zpart.
@@ -54,7 +56,7 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s1(
     run_entries<W, D, Stage>(
         er, lane,
         [&](Stage& f, const int (&id)[W]) {
-          ld_row(f.h, Hm + (size_t)id[0] * TE, lane);
+          ld_col(f.h, Hm + (size_t)id[0] * TE, lane);
 #pragma unroll
           for (int u = 0; u < NT; ++u) ld_col(f.b[u], Bm + (size_t)max(id[1 + u], 0) * TE, lane);
         },
@@ -69,8 +71,8 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s1(
     run_entries<W, D, Stage>(
         er, lane,
         [&](Stage& f, const int (&id)[W]) {
-          ld_row(f.h, Hm + (size_t)id[0] * TE, lane);
-          ld_row(f.s, Sq + (size_t)id[0] * TE, lane);
+          ld_col(f.h, Hm + (size_t)id[0] * TE, lane);   // tile (k, i) of the symmetric H: A(i, k)
+          ld_col(f.s, Sq + (size_t)id[0] * TE, lane);
 #pragma unroll
           for (int u = 0; u < NT; ++u) ld_col(f.b[u], Bm + (size_t)max(id[1 + u], 0) * TE, lane);
         },

@@ -119,6 +119,22 @@ def test_rejects_bad_mode_and_offsets(chain):
     assert rc == L.OMM_ERR_ARG and "val_off" in msg
 
 
+def test_rejects_unsymmetric_pattern():
+    from dataclasses import replace
+    s = make_system(replace(config_spec("cubic4_dense"), rc=1.2, dense=False))
+    H = s.H
+    rows = H.block_rows()
+    # drop one off-diagonal block (i, j) but keep (j, i)
+    k = next(k for k in range(H.nnzb) if rows[k] != H.col_idx[k])
+    keep = np.ones(H.nnzb, dtype=bool)
+    keep[k] = False
+    rp = np.concatenate([[0], np.cumsum(np.bincount(rows[keep], minlength=H.nbrow))]).astype(np.int64)
+    Hb = _args(H, row_ptr=rp, col_idx=H.col_idx[keep].copy(), val_off=H.val_off[keep].copy())
+    Sb = _args(s.S, row_ptr=rp, col_idx=H.col_idx[keep].copy(), val_off=s.S.val_off[keep].copy())
+    rc, msg = _init_rc(Hb, Sb, s.n, mode=L.OMM_BLOCK_SPARSE)
+    assert rc == L.OMM_ERR_ARG and "symmetric" in msg
+
+
 def test_rejects_non_square_blocks(chain):
     H = chain.H
     cb = H.col_bsz.copy()
