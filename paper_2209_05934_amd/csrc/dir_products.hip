@@ -22,7 +22,7 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s1(
     const SysInfo* __restrict__ info, const SysState* __restrict__ st, int mask, const TI* __restrict__ Hm,
     const TI* __restrict__ Sm, const TI* __restrict__ Bm, TO* __restrict__ O1, TO* __restrict__ O2,
     const int* __restrict__ hc_to_c, const uint8_t* __restrict__ wseg, const double* __restrict__ Gold,
-    double* __restrict__ zpart) {
+    double* __restrict__ zpart, int trans_out) {
   typedef typename Acc<TI>::V V;
   typedef Split<KS> SP;
   constexpr int W = 1 + NT;
@@ -131,9 +131,10 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s1(
       TO* o1 = O1 + (size_t)t * TE;
       TO* o2 = O2 + (size_t)t * TE;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        o1[out_off<V>(lane, r)] = (TO)a1[r];
-        o2[out_off<V>(lane, r)] = (TO)a2[r];
+      for (int r = 0; r < 4; ++r) {   // HC, SC (trans_out) are stored with each tile transposed
+        const int e = trans_out ? out_off_t<V>(lane, r) : out_off<V>(lane, r);
+        o1[e] = (TO)a1[r];
+        o2[e] = (TO)a2[r];
       }
     }
   }
@@ -142,19 +143,21 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s1(
 }  // namespace
 
 template <typename TI, typename TO, bool ONE = false>
-static void s1_go(hipStream_t s, const Bufs& b, int mask, const TI* H, const TI* S, const TI* B, TO* O1, TO* O2) {
+static void s1_go(hipStream_t s, const Bufs& b, int mask, const TI* H, const TI* S, const TI* B, TO* O1, TO* O2,
+                  int trans_out = 0) {
   if (b.s1.ngroups <= 0) return;
   nt_ks<0>(b.s1.NT, b.ks[0], [&](auto ntc, auto ksc) {
     constexpr int N_ = decltype(ntc)::value, K_ = decltype(ksc)::value;
     LAUNCH((k_s1<TI, TO, K_, N_, ONE>), grid_for<K_>(b.s1.ngroups), block_for<K_>(), s, b.s1, b.thc_row,
-           b.thc_col, b.brow_sys, b.info, b.st, mask, H, S, B, O1, O2, b.hc_to_c, b.wseg, b.Gold, b.zpart);
+           b.thc_col, b.brow_sys, b.info, b.st, mask, H, S, B, O1, O2, b.hc_to_c, b.wseg, b.Gold, b.zpart,
+           trans_out);
   });
 }
 
 // one precision per object file (OMM_PREC 0: FP64, 1: FP32, 2: BF16)
 #if OMM_PREC == 0
 void launch_s1_p64(hipStream_t s, const Bufs& b, int mask, bool init) {
-  if (init) s1_go<double, double>(s, b, mask, b.H, b.S, b.C, b.HC, b.SC);
+  if (init) s1_go<double, double>(s, b, mask, b.H, b.S, b.C, b.HC, b.SC, 1);
   else s1_go<double, double>(s, b, mask, b.H, b.S, b.D, b.HD, b.SD);
 }
 

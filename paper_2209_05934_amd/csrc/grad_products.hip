@@ -44,8 +44,8 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_grad(
     run_entries<W, D, Stage>(
         er, lane,
         [&](Stage& f, const int (&id)[W]) {
-          ld_row(f.h, HCm + (size_t)id[0] * TE, lane);
-          ld_row(f.s, SCm + (size_t)id[0] * TE, lane);
+          ld_col(f.h, HCm + (size_t)id[0] * TE, lane);   // HC, SC tiles are stored transposed
+          ld_col(f.s, SCm + (size_t)id[0] * TE, lane);
 #pragma unroll
           for (int u = 0; u < NT; ++u) {
             const size_t bt = (size_t)max(id[1 + u], 0) * TE;
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_grad(
       const int row = Lay<V>::row(q, r);
       const int e = row * 16 + j;
       const bool in = ((mk >> row) & 1u) && ((mk >> (16 + j)) & 1u);
-      const double gv = in ? 8.0 * hc[e] - 4.0 * (double)acc[u][r] : 0.0;
+      const double gv = in ? 8.0 * hc[j * 16 + row] - 4.0 * (double)acc[u][r] : 0.0;
       G[(size_t)t * TE + e] = gv;
       gg += gv * gv;
       go += gv * Gold[(size_t)t * TE + e];

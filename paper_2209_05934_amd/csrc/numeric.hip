@@ -316,10 +316,11 @@ __global__ __launch_bounds__(256) void k_update(int nc, int nhc, int ntot, const
   if (kind == 0) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) { u[i] = C[o + i]; p[i] = D[o + i]; }
-  } else if (kind == 1) {
+  } else if (kind == 1) {   // HC, SC tiles are stored transposed: element (r, c) at c * 16 + r
+    const size_t ot = (size_t)t * TE + c0 * 16 + r;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      u[i] = HC[o + i]; v[i] = SC[o + i]; p[i] = (double)HD[o + i]; q[i] = (double)SD[o + i];
+      u[i] = HC[ot + 16 * i]; v[i] = SC[ot + 16 * i]; p[i] = (double)HD[o + i]; q[i] = (double)SD[o + i];
     }
   } else {
     const size_t ot = (size_t)wtr[t] * TE + c0 * 16 + r;
@@ -351,14 +352,15 @@ __global__ __launch_bounds__(256) void k_update(int nc, int nhc, int ntot, const
       if (LOW) Cl[o + i] = cvt<TL, double>(nv);
     }
   } else if (kind == 1) {
+    const size_t ot = (size_t)t * TE + c0 * 16 + r;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const double h = u[i] + x * p[i], g = v[i] + x * q[i];
-      HC[o + i] = h;
-      SC[o + i] = g;
+      HC[ot + 16 * i] = h;
+      SC[ot + 16 * i] = g;
       if (LOW) {
-        HCl[o + i] = cvt<TL, double>(h);
-        SCl[o + i] = cvt<TL, double>(g);
+        HCl[ot + 16 * i] = cvt<TL, double>(h);
+        SCl[ot + 16 * i] = cvt<TL, double>(g);
       }
     }
   } else {

@@ -49,8 +49,13 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s2(
 #pragma unroll
           for (int u = 0; u < NT; ++u) {
             const size_t bt = (size_t)max(id[1 + u], 0) * TE;
-            ld_col(f.hd[u], HDm + bt, lane);
-            ld_col(f.sd[u], SDm + bt, lane);
+            if (NPROD == 4) {
+              ld_col(f.hd[u], HDm + bt, lane);
+              ld_col(f.sd[u], SDm + bt, lane);
+            } else {   // HC, SC: tiles stored transposed
+              ld_row(f.hd[u], HDm + bt, lane);
+              ld_row(f.sd[u], SDm + bt, lane);
+            }
           }
         },
         [&](const Stage& f, const int (&id)[W]) {

@@ -96,6 +96,9 @@ template <> __device__ __forceinline__ f4 vzero<f4>() { return f4{0.f, 0.f, 0.f,
 // accumulator register r of this lane sits at tile offset out_off<V>(lane, r)
 template <typename V>
 __device__ __forceinline__ int out_off(int lane, int r) { return Lay<V>::row(lane >> 4, r) * 16 + (lane & 15); }
+// the same element in a tile stored transposed
+template <typename V>
+__device__ __forceinline__ int out_off_t(int lane, int r) { return (lane & 15) * 16 + Lay<V>::row(lane >> 4, r); }
 
 // an FP64 accumulator tile as the B operand of the next product, through a
 // 16x16 LDS tile owned by the calling wave (LDS operations of one wave
