@@ -114,11 +114,32 @@ __device__ __forceinline__ Frag<double> acc_as_b_lds(const d4& a, double* t, int
   return f;
 }
 
-// deterministic full-wave sum
+// a double moved across lanes by a DPP pattern (both 32-bit halves)
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ __forceinline__ double lane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Deterministic full-wave sum, the same value in every lane (call with the
+// whole wave active).  Within each row of 16 lanes: pairs (quad_perm 1,0,3,2),
+// quads (quad_perm 2,3,0,1), then the mirrored half-row and row; every step
+// adds two equal-shaped partial sums, so all lanes of a row agree.  The four
+// row sums are then added in a fixed order from uniform lane reads.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_mov<0xB1>(v);
+  v += dpp_mov<0x4E>(v);
+  v += dpp_mov<0x141>(v);
+  v += dpp_mov<0x140>(v);
+  return (lane_d(v, 0) + lane_d(v, 16)) + (lane_d(v, 32) + lane_d(v, 48));
 }
 
 }  // namespace omm
