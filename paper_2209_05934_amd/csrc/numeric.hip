@@ -187,7 +187,7 @@ __global__ __launch_bounds__(256) void k_traces(const int4* __restrict__ chunks,
                                               const double* __restrict__ H0, const double* __restrict__ S0,
                                               const TN* __restrict__ X, const TN* __restrict__ Y,
                                               const TN* __restrict__ S2, const TN* __restrict__ H2,
-                                              double* __restrict__ part, int single) {
+                                              double* __restrict__ part, int single, int sym2) {
   __shared__ double red[4][NSUM];
   const int4 ch = chunks[blockIdx.x];
   if (!on(st, single ? 0 : ch.z, mask)) return;   // one system: the phase load need not wait for the chunk
@@ -202,6 +202,7 @@ __global__ __launch_bounds__(256) void k_traces(const int4* __restrict__ chunks,
     const size_t o = (size_t)t * TE + r * 16 + c0;
     const size_t ot = (size_t)tt * TE + c0 * 16 + r;
     const bool diag = tt == t && r >= c0 && r < c0 + 4;
+    const bool mir = sym2 && tt < t;   // S2, H2 below the diagonal: transpose of the mirror tile
     double h0[4], s0[4], x[4], y[4], s2[4], h2[4], yt[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -209,8 +210,8 @@ __global__ __launch_bounds__(256) void k_traces(const int4* __restrict__ chunks,
       s0[i] = S0[o + i];
       x[i] = (double)X[o + i];
       y[i] = (double)Y[o + i];
-      s2[i] = (double)S2[o + i];
-      h2[i] = (double)H2[o + i];
+      s2[i] = (double)(mir ? S2[ot + 16 * i] : S2[o + i]);
+      h2[i] = (double)(mir ? H2[ot + 16 * i] : H2[o + i]);
       yt[i] = (double)Y[ot + 16 * i];
     }
 #pragma unroll
@@ -323,13 +324,16 @@ __global__ __launch_bounds__(256) void k_update(int nc, int nhc, int ntot, const
       u[i] = HC[ot + 16 * i]; v[i] = SC[ot + 16 * i]; p[i] = (double)HD[o + i]; q[i] = (double)SD[o + i];
     }
   } else {
-    const size_t ot = (size_t)wtr[t] * TE + c0 * 16 + r;
+    const int tt = wtr[t];
+    const size_t ot = (size_t)tt * TE + c0 * 16 + r;
+    const bool mir = tt < t;   // H2, S2 below the diagonal: transpose of the mirror tile
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       u[i] = H0[o + i]; v[i] = S0[o + i];
       p[i] = (double)Y[o + i] + (double)Y[ot + 16 * i];
       q[i] = (double)X[o + i] + (double)X[ot + 16 * i];
-      w[i] = (double)H2[o + i]; z[i] = (double)S2[o + i];
+      w[i] = (double)(mir ? H2[ot + 16 * i] : H2[o + i]);
+      z[i] = (double)(mir ? S2[ot + 16 * i] : S2[o + i]);
     }
   }
   double x = 0.0;
@@ -688,13 +692,13 @@ void launch_traces(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init_
   if (prec == P64) {
     if (init_inputs)   // X = S0, Y = H0, S2 = S0, H2 = H0: the sums then hold Tr H0, <S0,H0>, Tr S0, <S0,S0>
       LAUNCH(k_traces<double>, dim3(b.nchunks), dim3(256), s, b.chunks, b.st, mask, b.w_tr, b.H0, b.S0, b.S0,
-             b.H0, b.S0, b.H0, b.tpart, b.nsys == 1 ? 1 : 0);
+             b.H0, b.S0, b.H0, b.tpart, b.nsys == 1 ? 1 : 0, 0);
     else
       LAUNCH(k_traces<double>, dim3(b.nchunks), dim3(256), s, b.chunks, b.st, mask, b.w_tr, b.H0, b.S0, b.X, b.Y,
-             b.S2, b.H2, b.tpart, b.nsys == 1 ? 1 : 0);
+             b.S2, b.H2, b.tpart, b.nsys == 1 ? 1 : 0, 1);
   } else {
     LAUNCH(k_traces<float>, dim3(b.nchunks), dim3(256), s, b.chunks, b.st, mask, b.w_tr, b.H0, b.S0, b.Xf, b.Yf,
-           b.S2f, b.H2f, b.tpart, b.nsys == 1 ? 1 : 0);
+           b.S2f, b.H2f, b.tpart, b.nsys == 1 ? 1 : 0, 1);
   }
   if (mode != LS_STEP || b.multi_chunk)
     LAUNCH(k_ls_state, dim3(b.nsys), dim3(64), s, b.info, b.st, mask, b.tpart, mode, prm.refine_iters);

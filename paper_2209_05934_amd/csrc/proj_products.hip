@@ -10,6 +10,9 @@ namespace {
 // ------------------------------------------------------------------ S2: n x n projections
 // Groups of NT output tiles in one row g of the n x n pattern: per basis tile b
 // the C(b,g) and D(b,g) tiles are loaded once for NT tiles of HD and SD.
+// S2 = D^T S D and H2 = D^T H D are symmetric: they are formed and stored for
+// tiles on or above the diagonal only, and readers take a tile below it as the
+// transpose of its mirror (X and Y are not symmetric and are formed in full).
 template <typename TI, typename TM, typename TO, int NPROD, int KS, int NT>
 __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s2(
     GroupView P, const int* __restrict__ orow, const int* __restrict__ ocol, const int* __restrict__ wrow_sys,
@@ -35,17 +38,27 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s2(
   const int o0 = m.x, cnt = m.y, s = m.z;
   const int phase = ld_early(&st[s].phase);
   const double e2 = ld_early(&info[s].eps2);
+  bool low[NT];   // output tile below the diagonal: no S2, H2 products
+#pragma unroll
+  for (int u = 0; u < NT; ++u) {
+    const int t = min(o0 + u, o0 + max(cnt, 1) - 1);
+    low[u] = NPROD == 4 && valid && ld_early(&orow[t]) > ld_early(&ocol[t]);
+  }
   const bool act = valid && (phase & mask) != 0;
   V acc[NPROD * NT];
 #pragma unroll
   for (int a = 0; a < NPROD * NT; ++a) acc[a] = vzero<V>();
-  if (act) {
-    struct Stage { Frag<TI> c, d, hd[NT], sd[NT]; };
+  bool all_low = NPROD == 4;   // every output tile of the group below the diagonal: no D loads
+#pragma unroll
+  for (int u = 0; u < NT; ++u) all_low = all_low && (u >= cnt || low[u]);
+  struct Stage { Frag<TI> c, d, hd[NT], sd[NT]; };
+  auto body = [&](auto skip_d) {
+    constexpr bool SKIP = decltype(skip_d)::value;
     run_entries<W, D, Stage>(
         er, lane,
         [&](Stage& f, const int (&id)[W]) {
           ld_col(f.c, Cm + (size_t)id[0] * TE, lane);                 // A = C^T
-          if (NPROD == 4) ld_col(f.d, Dm + (size_t)id[0] * TE, lane);  // A = D^T
+          if constexpr (NPROD == 4 && !SKIP) ld_col(f.d, Dm + (size_t)id[0] * TE, lane);  // A = D^T
 #pragma unroll
           for (int u = 0; u < NT; ++u) {
             const size_t bt = (size_t)max(id[1 + u], 0) * TE;
@@ -64,13 +77,19 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s2(
             if (id[1 + u] >= 0) {
               mma(acc[u], f.c, f.sd[u]);
               mma(acc[NT + u], f.c, f.hd[u]);
-              if (NPROD == 4) {
-                mma(acc[2 * NT + u], f.d, f.sd[u]);
-                mma(acc[3 * NT + u], f.d, f.hd[u]);
+              if constexpr (NPROD == 4 && !SKIP) {
+                if (!low[u]) {
+                  mma(acc[2 * NT + u], f.d, f.sd[u]);
+                  mma(acc[3 * NT + u], f.d, f.hd[u]);
+                }
               }
             }
           }
         });
+  };
+  if (act) {
+    if (all_low) body(std::true_type{});
+    else body(std::false_type{});
   }
   ks_reduce<KS, NPROD * NT>(acc, red, grp, wk, lane);
   if (!act || wk != 0) return;
@@ -90,7 +109,7 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s2(
       const int e = out_off<V>(lane, r);
       X[o + e] = (TO)acc[u][r];
       Y[o + e] = (TO)acc[NT + u][r];
-      if (NPROD == 4) {
+      if (NPROD == 4 && !low[u]) {
         S2o[o + e] = (TO)acc[2 * NT + u][r];
         H2o[o + e] = (TO)acc[3 * NT + u][r];
       }
