@@ -3,9 +3,8 @@
 // One 64-lane wavefront multiplies two 16x16 row-major tiles.  Lane
 // l = i + 16*q (i = l & 15, q = l >> 4) supplies, at MFMA step s = 0..3,
 // A[i][k] and B[k][j=i] for one tile index k = K(q, s).  The pairing of k with
-// (q, s) is free as long as A and B agree; K(q, s) = 4q + s gives each lane
-// four consecutive elements of an A row, which the compiler loads as wide
-// vector loads.  Accumulator register r of lane (j, q) holds output row
+// (q, s) is free as long as A and B agree (KMap).  Accumulator register r of
+// lane (j, q) holds output row
 //   v_mfma_f64_16x16x4f64 : 4r + q
 //   v_mfma_f32_16x16x4f32 and v_mfma_f32_16x16x16bf16_1k : 4q + r
 // (the f64 placement was measured on gfx950 with delta operands).
@@ -51,7 +50,12 @@ template <> struct Acc<bf16> { typedef f4 V; typedef float S; };
 template <typename T> struct Frag { T v[4]; };
 
 // tile index k supplied by lane-quad q at step s
-template <typename T> struct KMap { static __device__ __forceinline__ int k(int q, int s) { return 4 * q + s; } };
+// FP64: a lane's four k are consecutive, so a row load is two 16-byte vector
+// loads.  FP32/BF16 (whose products load every operand down columns): the four
+// quads of one step take consecutive k, so a column load reads four
+// consecutive rows, which share cache lines at 4- and 2-byte elements.
+template <typename T> struct KMap { static __device__ __forceinline__ int k(int q, int s) { return 4 * s + q; } };
+template <> struct KMap<double> { static __device__ __forceinline__ int k(int q, int s) { return 4 * q + s; } };
 
 // output row of accumulator register r in lane-quad q
 template <typename V> struct Lay;
