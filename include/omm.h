@@ -161,7 +161,8 @@ void omm_default_options(omm_options* opt);
 
 /* Creates a context for one system (Sec. III B solver input).
  *   H, S  : m x m, identical block structure, square diagonal blocks, both symmetric
- *           (all blocks stored, not one triangle).  H is shifted to H - eta S here.
+ *           (all blocks stored, not one triangle; a block pattern that is not
+ *           symmetric is OMM_ERR_ARG).  H is shifted to H - eta S here.
  *   n_occ : number of wavefunction columns n (1 <= n <= m).
  *   mode  : omm_mode.  OMM_DENSE_CHOLESKY factorizes S (OMM_ERR_NOT_SPD if it fails).
  *   opt   : may be NULL for defaults.
@@ -169,8 +170,8 @@ void omm_default_options(omm_options* opt);
 int omm_init(omm_ctx** out, const omm_matrix* H, const omm_matrix* S, int64_t n_occ,
              int32_t mode, const omm_options* opt);
 
-/* Creates one context holding `count` independent systems (k-points, snapshots,
- * separate structures) that every later call advances together, each with its
+/* Creates one context holding `count` independent systems (snapshots, separate
+ * structures) that every later call advances together, each with its
  * own H[i], S[i], n_occ[i], modes[i] and Kim shift etas[i] (etas may be NULL:
  * opt->eta for all); the other options are shared (filter_eps applies to the
  * block-sparse systems only).  System indices 0..count-1 are used by the
@@ -303,7 +304,8 @@ int omm_time_step(omm_ctx* ctx, int32_t step, int32_t reps, double* avg_ms);
 const char* omm_status_str(int32_t status);
 
 /* Message of the last error on this context ("" if none); ctx may be NULL for
- * errors of a failed omm_init/omm_init_batch on the calling thread. */
+ * errors of a failed omm_init/omm_init_batch or of the context-free calls
+ * (omm_remap_coeffs, omm_write_coeffs, omm_read_coeffs) on the calling thread. */
 const char* omm_last_error(const omm_ctx* ctx);
 
 /* Releases every device buffer of the context. */
