@@ -61,38 +61,38 @@ PEAKS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}   # dense TFLOP/s of MI355
 # group width and split, and valid only for the kernel sources they were taken
 # with (sha256 prefix of the step's source file, tile_sched.hpp and tile_ops.hpp)
 MEASURED_TRAFFIC = {
-    ("cubic4_dense", "fp64", 0, 1, 1): (2.7732e+07, "e48e5a365c0f709c"),
-    ("cubic4_dense", "fp64", 0, 1, 2): (3.2831e+07, "e48e5a365c0f709c"),
-    ("cubic4_dense", "fp64", 0, 1, 4): (2.5916e+07, "e48e5a365c0f709c"),
-    ("cubic4_dense", "fp64", 0, 1, 8): (2.5889e+07, "e48e5a365c0f709c"),
-    ("cubic4_dense", "fp64", 0, 2, 1): (1.9991e+07, "e48e5a365c0f709c"),
-    ("cubic4_dense", "fp64", 0, 2, 2): (2.7698e+07, "e48e5a365c0f709c"),
-    ("cubic4_dense", "fp64", 0, 2, 4): (3.2765e+07, "e48e5a365c0f709c"),
-    ("cubic4_dense", "fp64", 0, 2, 8): (3.2715e+07, "e48e5a365c0f709c"),
-    ("cubic4_dense", "fp64", 0, 4, 1): (2.0027e+07, "e48e5a365c0f709c"),
-    ("cubic4_dense", "fp64", 0, 4, 2): (2.0073e+07, "e48e5a365c0f709c"),
-    ("cubic4_dense", "fp64", 0, 4, 4): (2.7791e+07, "e48e5a365c0f709c"),
-    ("cubic4_dense", "fp64", 1, 1, 1): (1.1065e+07, "2c93864317e5ed6d"),
-    ("cubic4_dense", "fp64", 1, 1, 2): (1.1059e+07, "2c93864317e5ed6d"),
-    ("cubic4_dense", "fp64", 1, 1, 4): (1.6113e+07, "2c93864317e5ed6d"),
-    ("cubic4_dense", "fp64", 1, 1, 8): (1.6050e+07, "2c93864317e5ed6d"),
-    ("cubic4_dense", "fp64", 1, 2, 1): (1.6219e+07, "2c93864317e5ed6d"),
-    ("cubic4_dense", "fp64", 1, 2, 2): (1.1147e+07, "2c93864317e5ed6d"),
-    ("cubic4_dense", "fp64", 1, 2, 4): (1.1095e+07, "2c93864317e5ed6d"),
-    ("cubic4_dense", "fp64", 1, 4, 1): (9.2685e+06, "2c93864317e5ed6d"),
-    ("cubic4_dense", "fp64", 1, 4, 2): (1.6322e+07, "2c93864317e5ed6d"),
-    ("cubic4_dense", "fp64", 1, 4, 4): (1.1275e+07, "2c93864317e5ed6d"),
-    ("cubic4_dense", "fp64", 2, 1, 1): (6.3766e+06, "c5f2a7eabce47353"),
-    ("cubic4_dense", "fp64", 2, 1, 2): (7.6573e+06, "c5f2a7eabce47353"),
-    ("cubic4_dense", "fp64", 2, 1, 4): (6.5929e+06, "c5f2a7eabce47353"),
-    ("cubic4_dense", "fp64", 2, 1, 8): (6.5827e+06, "c5f2a7eabce47353"),
-    ("cubic4_dense", "fp64", 2, 2, 1): (5.7273e+06, "c5f2a7eabce47353"),
-    ("cubic4_dense", "fp64", 2, 2, 2): (6.3980e+06, "c5f2a7eabce47353"),
-    ("cubic4_dense", "fp64", 2, 2, 4): (7.6880e+06, "c5f2a7eabce47353"),
-    ("cubic4_dense", "fp64", 2, 2, 8): (7.6736e+06, "c5f2a7eabce47353"),
-    ("cubic4_dense", "fp64", 2, 4, 1): (5.8183e+06, "c5f2a7eabce47353"),
-    ("cubic4_dense", "fp64", 2, 4, 2): (5.7831e+06, "c5f2a7eabce47353"),
-    ("cubic4_dense", "fp64", 2, 4, 4): (6.4470e+06, "c5f2a7eabce47353"),
+    ("cubic4_dense", "fp64", 0, 1, 1): (2.7737e+07, "b00d1fcdf35814e1"),
+    ("cubic4_dense", "fp64", 0, 1, 2): (3.2831e+07, "b00d1fcdf35814e1"),
+    ("cubic4_dense", "fp64", 0, 1, 4): (2.5927e+07, "b00d1fcdf35814e1"),
+    ("cubic4_dense", "fp64", 0, 1, 8): (2.5889e+07, "b00d1fcdf35814e1"),
+    ("cubic4_dense", "fp64", 0, 2, 1): (2.0007e+07, "b00d1fcdf35814e1"),
+    ("cubic4_dense", "fp64", 0, 2, 2): (2.7695e+07, "b00d1fcdf35814e1"),
+    ("cubic4_dense", "fp64", 0, 2, 4): (3.2778e+07, "b00d1fcdf35814e1"),
+    ("cubic4_dense", "fp64", 0, 2, 8): (3.2715e+07, "b00d1fcdf35814e1"),
+    ("cubic4_dense", "fp64", 0, 4, 1): (2.0039e+07, "b00d1fcdf35814e1"),
+    ("cubic4_dense", "fp64", 0, 4, 2): (2.0082e+07, "b00d1fcdf35814e1"),
+    ("cubic4_dense", "fp64", 0, 4, 4): (2.7779e+07, "b00d1fcdf35814e1"),
+    ("cubic4_dense", "fp64", 1, 1, 1): (1.0661e+07, "66a2bb137ab4577d"),
+    ("cubic4_dense", "fp64", 1, 1, 2): (9.8108e+06, "66a2bb137ab4577d"),
+    ("cubic4_dense", "fp64", 1, 1, 4): (1.3115e+07, "66a2bb137ab4577d"),
+    ("cubic4_dense", "fp64", 1, 1, 8): (1.3026e+07, "66a2bb137ab4577d"),
+    ("cubic4_dense", "fp64", 1, 2, 1): (1.6271e+07, "66a2bb137ab4577d"),
+    ("cubic4_dense", "fp64", 1, 2, 2): (1.0771e+07, "66a2bb137ab4577d"),
+    ("cubic4_dense", "fp64", 1, 2, 4): (9.8419e+06, "66a2bb137ab4577d"),
+    ("cubic4_dense", "fp64", 1, 4, 1): (9.2175e+06, "66a2bb137ab4577d"),
+    ("cubic4_dense", "fp64", 1, 4, 2): (1.6351e+07, "66a2bb137ab4577d"),
+    ("cubic4_dense", "fp64", 1, 4, 4): (1.0894e+07, "66a2bb137ab4577d"),
+    ("cubic4_dense", "fp64", 2, 1, 1): (6.3797e+06, "22ef4ceb77692a2f"),
+    ("cubic4_dense", "fp64", 2, 1, 2): (7.6685e+06, "22ef4ceb77692a2f"),
+    ("cubic4_dense", "fp64", 2, 1, 4): (6.5929e+06, "22ef4ceb77692a2f"),
+    ("cubic4_dense", "fp64", 2, 1, 8): (6.5694e+06, "22ef4ceb77692a2f"),
+    ("cubic4_dense", "fp64", 2, 2, 1): (5.7355e+06, "22ef4ceb77692a2f"),
+    ("cubic4_dense", "fp64", 2, 2, 2): (6.3990e+06, "22ef4ceb77692a2f"),
+    ("cubic4_dense", "fp64", 2, 2, 4): (7.6777e+06, "22ef4ceb77692a2f"),
+    ("cubic4_dense", "fp64", 2, 2, 8): (7.6644e+06, "22ef4ceb77692a2f"),
+    ("cubic4_dense", "fp64", 2, 4, 1): (5.8183e+06, "22ef4ceb77692a2f"),
+    ("cubic4_dense", "fp64", 2, 4, 2): (5.7821e+06, "22ef4ceb77692a2f"),
+    ("cubic4_dense", "fp64", 2, 4, 4): (6.4501e+06, "22ef4ceb77692a2f"),
 }
 
 

@@ -18,8 +18,7 @@ namespace {
 // tile layout with the per-tile sums <Z, G> and <Z, G_old> in zpart.
 template <typename TI, typename TO, int KS, int NT, bool ONE>
 __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s1(
-    GroupView P, const int* __restrict__ orow, const int* __restrict__ ocol, const int* __restrict__ brow_sys,
-    const SysInfo* __restrict__ info, const SysState* __restrict__ st, int mask, const TI* __restrict__ Hm,
+    GroupView P, const int* __restrict__ ocol, const SysInfo* __restrict__ info, const SysState* __restrict__ st, int mask, const TI* __restrict__ Hm,
     const TI* __restrict__ Sm, const TI* __restrict__ Bm, TO* __restrict__ O1, TO* __restrict__ O2,
     const int* __restrict__ hc_to_c, const uint8_t* __restrict__ wseg, const double* __restrict__ Gold,
     double* __restrict__ zpart, int trans_out) {
@@ -148,9 +147,8 @@ static void s1_go(hipStream_t s, const Bufs& b, int mask, const TI* H, const TI*
   if (b.s1.ngroups <= 0) return;
   nt_ks<0>(b.s1.NT, b.ks[0], [&](auto ntc, auto ksc) {
     constexpr int N_ = decltype(ntc)::value, K_ = decltype(ksc)::value;
-    LAUNCH((k_s1<TI, TO, K_, N_, ONE>), grid_for<K_>(b.s1.ngroups), block_for<K_>(), s, b.s1, b.thc_row,
-           b.thc_col, b.brow_sys, b.info, b.st, mask, H, S, B, O1, O2, b.hc_to_c, b.wseg, b.Gold, b.zpart,
-           trans_out);
+    LAUNCH((k_s1<TI, TO, K_, N_, ONE>), grid_for<K_>(b.s1.ngroups), block_for<K_>(), s, b.s1, b.thc_col, b.info,
+           b.st, mask, H, S, B, O1, O2, b.hc_to_c, b.wseg, b.Gold, b.zpart, trans_out);
   });
 }
 

@@ -12,9 +12,9 @@ namespace {
 // SC(b,k) tiles are loaded once for NT tiles of S_W and H_W.
 template <typename TI, int KS, int NT>
 __global__ __launch_bounds__(Split<KS>::NW * 64) void k_grad(
-    GroupView P, const int* __restrict__ tc_row, const int* __restrict__ brow_sys, const SysState* __restrict__ st,
-    int mask, const TI* __restrict__ HCm, const TI* __restrict__ SCm, const TI* __restrict__ S0m,
-    const TI* __restrict__ H0m, const double* __restrict__ HC, const int* __restrict__ c_in_hc,
+    GroupView P, const SysState* __restrict__ st, int mask, const TI* __restrict__ HCm,
+    const TI* __restrict__ SCm, const TI* __restrict__ S0m, const TI* __restrict__ H0m,
+    const double* __restrict__ HC, const int* __restrict__ c_in_hc,
     const uint32_t* __restrict__ cmask, const double* __restrict__ Gold, double* __restrict__ G,
     double* __restrict__ gpart) {
   typedef typename Acc<TI>::V V;
@@ -99,8 +99,8 @@ static void grad_go(hipStream_t s, const Bufs& b, int mask, const TI* HC, const 
   if (b.grad.ngroups <= 0) return;
   nt_ks<2>(b.grad.NT, b.ks[2], [&](auto ntc, auto ksc) {
     constexpr int N_ = decltype(ntc)::value, K_ = decltype(ksc)::value;
-    LAUNCH((k_grad<TI, K_, N_>), grid_for<K_>(b.grad.ngroups), block_for<K_>(), s, b.grad, b.tc_row, b.brow_sys,
-           b.st, mask, HC, SC, S0, H0, b.HC, b.c_in_hc, b.cmask, b.Gold, b.G, b.gpart);
+    LAUNCH((k_grad<TI, K_, N_>), grid_for<K_>(b.grad.ngroups), block_for<K_>(), s, b.grad, b.st, mask, HC, SC, S0,
+           H0, b.HC, b.c_in_hc, b.cmask, b.Gold, b.G, b.gpart);
   });
 }
 

@@ -15,8 +15,7 @@ namespace {
 // transpose of its mirror (X and Y are not symmetric and are formed in full).
 template <typename TI, typename TM, typename TO, int NPROD, int KS, int NT>
 __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s2(
-    GroupView P, const int* __restrict__ orow, const int* __restrict__ ocol, const int* __restrict__ wrow_sys,
-    const SysInfo* __restrict__ info, const SysState* __restrict__ st, int mask, const TI* __restrict__ Cm,
+    GroupView P, const int* __restrict__ orow, const int* __restrict__ ocol, const SysInfo* __restrict__ info, const SysState* __restrict__ st, int mask, const TI* __restrict__ Cm,
     const TI* __restrict__ Dm, const TM* __restrict__ HDm, const TM* __restrict__ SDm, TO* __restrict__ X,
     TO* __restrict__ Y, TO* __restrict__ S2o, TO* __restrict__ H2o, const uint8_t* __restrict__ wseg) {
   typedef typename Acc<TI>::V V;
@@ -126,7 +125,7 @@ static void s2_go(hipStream_t s, const Bufs& b, int mask, const TI* C, const TI*
   nt_ks<1>(b.s2.NT, b.ks[1], [&](auto ntc, auto ksc) {
     constexpr int N_ = decltype(ntc)::value, K_ = decltype(ksc)::value;
     LAUNCH((k_s2<TI, TM, TO, NP, K_, N_>), grid_for<K_>(b.s2.ngroups), block_for<K_>(), s, b.s2, b.tw_row,
-           b.tw_col, b.wrow_sys, b.info, b.st, mask, C, D, HD, SD, X, Y, S2, H2, b.wseg);
+           b.tw_col, b.info, b.st, mask, C, D, HD, SD, X, Y, S2, H2, b.wseg);
   });
 }
 
