@@ -133,35 +133,77 @@ def parse():
     return ap.parse_args()
 
 
+def _scipy_csr(bm):
+    """scipy.sparse CSR of an atom-block matrix (input conversion for the CPU leg)."""
+    import numpy as np
+    import scipy.sparse
+    ro, co = bm.row_offsets(), bm.col_offsets()
+    rows = bm.block_rows()
+    r_list, c_list = [], []
+    for k in range(bm.nnzb):
+        i, j = int(rows[k]), int(bm.col_idx[k])
+        rr, cc = np.meshgrid(np.arange(ro[i], ro[i + 1]), np.arange(co[j], co[j + 1]), indexing="ij")
+        r_list.append(rr.ravel())
+        c_list.append(cc.ravel())
+    order = np.concatenate([np.arange(bm.val_off[k], bm.val_off[k] + (ro[int(rows[k]) + 1] - ro[int(rows[k])])
+                                      * (co[int(bm.col_idx[k]) + 1] - co[int(bm.col_idx[k])]))
+                            for k in range(bm.nnzb)])
+    return scipy.sparse.csr_matrix((bm.val[order], (np.concatenate(r_list), np.concatenate(c_list))),
+                                   shape=(int(ro[-1]), int(co[-1])))
+
+
 def cpu_baseline(system, spec, mode, max_iter, budget_s, tau=0.0):
-    """The CPU oracle as it stands, on a bounded sample of the same workload."""
+    """The CPU oracle as it stands, on a bounded sample of the same workload: full
+    solves for the dense systems; for the block-sparse ones repeated two-iteration
+    samples from C0, since one solve runs far past the budget (H and S dense for
+    BLAS speed, as scipy.sparse above 20000 basis functions, where dense copies
+    would not fit)."""
+    import platform
     import numpy as np
     import oracle as O
+    threads, blas = os.cpu_count() or 1, "unknown"
     try:
         from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        info = threadpool_info()
+        threads = max([i.get("num_threads", 1) for i in info] or [1])
+        blas = ", ".join(sorted({f"{i.get('internal_api')} {i.get('version')}" for i in info
+                                 if i.get("user_api") == "blas"})) or blas
     except Exception:
-        threads = os.cpu_count() or 1
-    H, S, C0 = system.H.to_dense(), system.S.to_dense(), system.C0.to_dense()
-    mask = None if spec.dense else system.C0.pattern_mask()
-    kw = dict(eta=spec.eta, tol_grad=1e-9, max_iter=max_iter, keep_history=False)
-    iters, solves, t0 = 0, 0, time.perf_counter()
+        pass
+    cpu = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), cpu)
+    except OSError:
+        pass
+    sparse = mode == "sparse"
+    if sparse and system.m > 20000:
+        H, S = _scipy_csr(system.H), _scipy_csr(system.S)
+    else:
+        H, S = system.H.to_dense(), system.S.to_dense()
+    C0 = system.C0.to_dense()
+    mask = system.C0.pattern_mask() if sparse else None
+    per = 2 if sparse else max_iter
+    kw = dict(eta=spec.eta, tol_grad=1e-9, max_iter=per, keep_history=False)
     if tau > 0.0:
         kw["precon"] = O.kinetic_preconditioner(S, system.T.to_dense(), tau)
+    iters, runs, t0 = 0, 0, time.perf_counter()
     while True:
         if mode == "cholesky":
             r = O.cg_minimize_cholesky(H, S, C0, **kw)
         else:
             r = O.cg_minimize(H, S, C0, mask=mask, **kw)
         iters += r.iterations
-        solves += 1
-        if time.perf_counter() - t0 >= budget_s or solves >= 200:
+        runs += 1
+        if time.perf_counter() - t0 >= budget_s or runs >= 200:
             break
     dt = time.perf_counter() - t0
+    what = (f"{runs} run(s) of the first {per} CG iterations from C0" if sparse
+            else f"{runs} full solve(s) of the same workload")
     return {"value": iters / dt, "unit": "CG iters/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{solves} full solve(s) of the same workload ({iters} CG iterations, "
-                      f"{dt:.1f} s) with the NumPy/OpenBLAS FP64 oracle, every product recomputed "
-                      f"each iteration"}
+            "sample": f"{what} ({iters} CG iterations, {dt:.1f} s) with the NumPy/SciPy FP64 oracle, "
+                      f"every product recomputed each iteration",
+            "cpu": cpu, "blas": blas}
 
 
 def batch_main(args):
