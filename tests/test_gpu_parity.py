@@ -215,3 +215,27 @@ def test_time_step_leaves_the_solution_unchanged():
         ctx.time_step(3, 2)
     assert e.value.status == L.OMM_ERR_ARG
     ctx.close()
+
+
+def test_smallest_system_and_start_at_the_minimum():
+    # one basis function, one wavefunction: E~ = 4 h c^2 - 2 s h c^4 with s = 1,
+    # minimum at c^2 = 1/s, E* = 2 h (the eigenvalue, spin 2)
+    from ommgen import BlockMatrix
+    one = lambda v: BlockMatrix(np.array([1], np.int32), np.array([1], np.int32),   # noqa: E731
+                                np.array([0, 1], np.int64), np.array([0], np.int32),
+                                np.array([0], np.int64), np.array([v], np.float64))
+    H, S, C0 = one(-0.7), one(1.0), one(0.3)
+    for mode in (L.OMM_DENSE, L.OMM_DENSE_CHOLESKY, L.OMM_BLOCK_SPARSE):
+        ctx = Context([Problem(H, S, C0, 1, mode)])
+        rc, reps = ctx.minimize()
+        assert reps[0].status == L.OMM_OK
+        assert abs(reps[0].energy - 2.0 * -0.7) <= 1e-12
+        c = ctx.coeffs(0)
+        assert abs(abs(c[0]) - 1.0) <= 1e-9
+        assert np.allclose(ctx.density_matrix(0), [2.0], atol=1e-9)
+        # restarting at the minimum: the gradient is already below tol_grad
+        ctx.set_coeffs(0, C0.with_values(c))
+        rc, reps = ctx.minimize()
+        assert reps[0].status == L.OMM_OK and reps[0].iters_total <= 1
+        assert abs(reps[0].energy - 2.0 * -0.7) <= 1e-12
+        ctx.close()
