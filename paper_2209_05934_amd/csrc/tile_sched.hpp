@@ -70,15 +70,18 @@ __device__ void filter_tile(V& acc, int lane, const uint8_t* __restrict__ rseg,
 // successive XCDs: the hardware deals workgroups to the 8 XCDs round-robin, so
 // physical block p runs on XCD p % 8 as its (p / 8)-th block there.  Every
 // part of the grid (every system of a batch) is thereby spread over all XCDs.
-// Blocks of an incomplete last round of 8 runs keep their own id, which keeps
-// the renumbering a bijection.
+// The t blocks of an incomplete last round of 8 runs are cut into 8 contiguous
+// ranges, one per XCD (t / 8 blocks, one more for the first t % 8 XCDs), so the
+// groups of one output row stay on one XCD there too; the renumbering stays a
+// bijection on [0, gridDim.x).
 constexpr int XCD_RUN = 16;
 __device__ __forceinline__ int xcd_block() {
   const int nb = gridDim.x, p = blockIdx.x;
   const int full = nb - nb % (8 * XCD_RUN);
-  if (p >= full) return p;
   const int x = p & 7, k = p >> 3;
-  return ((k / XCD_RUN) * 8 + x) * XCD_RUN + (k % XCD_RUN);
+  if (p < full) return ((k / XCD_RUN) * 8 + x) * XCD_RUN + (k % XCD_RUN);
+  const int t = nb - full, q = t >> 3, r = t & 7;
+  return full + x * q + min(x, r) + ((p - full) >> 3);
 }
 
 template <int KS> struct Split {
