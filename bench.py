@@ -61,38 +61,38 @@ PEAKS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}   # dense TFLOP/s of MI355
 # group width and split, and valid only for the kernel sources they were taken
 # with (sha256 prefix of the step's source file, tile_sched.hpp and tile_ops.hpp)
 MEASURED_TRAFFIC = {
-    ("cubic4_dense", "fp64", 0, 1, 1): (2.7737e+07, "b00d1fcdf35814e1"),
-    ("cubic4_dense", "fp64", 0, 1, 2): (3.2831e+07, "b00d1fcdf35814e1"),
-    ("cubic4_dense", "fp64", 0, 1, 4): (2.5927e+07, "b00d1fcdf35814e1"),
-    ("cubic4_dense", "fp64", 0, 1, 8): (2.5889e+07, "b00d1fcdf35814e1"),
-    ("cubic4_dense", "fp64", 0, 2, 1): (2.0007e+07, "b00d1fcdf35814e1"),
-    ("cubic4_dense", "fp64", 0, 2, 2): (2.7695e+07, "b00d1fcdf35814e1"),
-    ("cubic4_dense", "fp64", 0, 2, 4): (3.2778e+07, "b00d1fcdf35814e1"),
-    ("cubic4_dense", "fp64", 0, 2, 8): (3.2715e+07, "b00d1fcdf35814e1"),
-    ("cubic4_dense", "fp64", 0, 4, 1): (2.0039e+07, "b00d1fcdf35814e1"),
-    ("cubic4_dense", "fp64", 0, 4, 2): (2.0082e+07, "b00d1fcdf35814e1"),
-    ("cubic4_dense", "fp64", 0, 4, 4): (2.7779e+07, "b00d1fcdf35814e1"),
-    ("cubic4_dense", "fp64", 1, 1, 1): (1.0661e+07, "66a2bb137ab4577d"),
-    ("cubic4_dense", "fp64", 1, 1, 2): (9.8108e+06, "66a2bb137ab4577d"),
-    ("cubic4_dense", "fp64", 1, 1, 4): (1.3115e+07, "66a2bb137ab4577d"),
-    ("cubic4_dense", "fp64", 1, 1, 8): (1.3026e+07, "66a2bb137ab4577d"),
-    ("cubic4_dense", "fp64", 1, 2, 1): (1.6271e+07, "66a2bb137ab4577d"),
-    ("cubic4_dense", "fp64", 1, 2, 2): (1.0771e+07, "66a2bb137ab4577d"),
-    ("cubic4_dense", "fp64", 1, 2, 4): (9.8419e+06, "66a2bb137ab4577d"),
-    ("cubic4_dense", "fp64", 1, 4, 1): (9.2175e+06, "66a2bb137ab4577d"),
-    ("cubic4_dense", "fp64", 1, 4, 2): (1.6351e+07, "66a2bb137ab4577d"),
-    ("cubic4_dense", "fp64", 1, 4, 4): (1.0894e+07, "66a2bb137ab4577d"),
-    ("cubic4_dense", "fp64", 2, 1, 1): (6.3797e+06, "22ef4ceb77692a2f"),
-    ("cubic4_dense", "fp64", 2, 1, 2): (7.6685e+06, "22ef4ceb77692a2f"),
-    ("cubic4_dense", "fp64", 2, 1, 4): (6.5929e+06, "22ef4ceb77692a2f"),
-    ("cubic4_dense", "fp64", 2, 1, 8): (6.5694e+06, "22ef4ceb77692a2f"),
-    ("cubic4_dense", "fp64", 2, 2, 1): (5.7355e+06, "22ef4ceb77692a2f"),
-    ("cubic4_dense", "fp64", 2, 2, 2): (6.3990e+06, "22ef4ceb77692a2f"),
-    ("cubic4_dense", "fp64", 2, 2, 4): (7.6777e+06, "22ef4ceb77692a2f"),
-    ("cubic4_dense", "fp64", 2, 2, 8): (7.6644e+06, "22ef4ceb77692a2f"),
-    ("cubic4_dense", "fp64", 2, 4, 1): (5.8183e+06, "22ef4ceb77692a2f"),
-    ("cubic4_dense", "fp64", 2, 4, 2): (5.7821e+06, "22ef4ceb77692a2f"),
-    ("cubic4_dense", "fp64", 2, 4, 4): (6.4501e+06, "22ef4ceb77692a2f"),
+    ("cubic4_dense", "fp64", 0, 1, 1): (2.0894e+07, "d36de78506d04001"),
+    ("cubic4_dense", "fp64", 0, 1, 2): (2.0885e+07, "d36de78506d04001"),
+    ("cubic4_dense", "fp64", 0, 1, 4): (2.0804e+07, "d36de78506d04001"),
+    ("cubic4_dense", "fp64", 0, 1, 8): (2.0771e+07, "d36de78506d04001"),
+    ("cubic4_dense", "fp64", 0, 2, 1): (1.9988e+07, "d36de78506d04001"),
+    ("cubic4_dense", "fp64", 0, 2, 2): (2.0865e+07, "d36de78506d04001"),
+    ("cubic4_dense", "fp64", 0, 2, 4): (2.0826e+07, "d36de78506d04001"),
+    ("cubic4_dense", "fp64", 0, 2, 8): (2.0770e+07, "d36de78506d04001"),
+    ("cubic4_dense", "fp64", 0, 4, 1): (2.0034e+07, "d36de78506d04001"),
+    ("cubic4_dense", "fp64", 0, 4, 2): (2.0059e+07, "d36de78506d04001"),
+    ("cubic4_dense", "fp64", 0, 4, 4): (2.0950e+07, "d36de78506d04001"),
+    ("cubic4_dense", "fp64", 1, 1, 1): (1.6204e+07, "88f4557412d1c0f9"),
+    ("cubic4_dense", "fp64", 1, 1, 2): (1.6194e+07, "88f4557412d1c0f9"),
+    ("cubic4_dense", "fp64", 1, 1, 4): (1.6064e+07, "88f4557412d1c0f9"),
+    ("cubic4_dense", "fp64", 1, 1, 8): (1.5971e+07, "88f4557412d1c0f9"),
+    ("cubic4_dense", "fp64", 1, 2, 1): (1.6273e+07, "88f4557412d1c0f9"),
+    ("cubic4_dense", "fp64", 1, 2, 2): (1.6305e+07, "88f4557412d1c0f9"),
+    ("cubic4_dense", "fp64", 1, 2, 4): (1.6217e+07, "88f4557412d1c0f9"),
+    ("cubic4_dense", "fp64", 1, 4, 1): (9.2083e+06, "88f4557412d1c0f9"),
+    ("cubic4_dense", "fp64", 1, 4, 2): (1.6362e+07, "88f4557412d1c0f9"),
+    ("cubic4_dense", "fp64", 1, 4, 4): (1.6424e+07, "88f4557412d1c0f9"),
+    ("cubic4_dense", "fp64", 2, 1, 1): (5.8135e+06, "95500563d589b4a9"),
+    ("cubic4_dense", "fp64", 2, 1, 2): (5.8032e+06, "95500563d589b4a9"),
+    ("cubic4_dense", "fp64", 2, 1, 4): (5.7930e+06, "95500563d589b4a9"),
+    ("cubic4_dense", "fp64", 2, 1, 8): (5.7889e+06, "95500563d589b4a9"),
+    ("cubic4_dense", "fp64", 2, 2, 1): (5.7166e+06, "95500563d589b4a9"),
+    ("cubic4_dense", "fp64", 2, 2, 2): (5.8323e+06, "95500563d589b4a9"),
+    ("cubic4_dense", "fp64", 2, 2, 4): (5.8231e+06, "95500563d589b4a9"),
+    ("cubic4_dense", "fp64", 2, 2, 8): (5.7944e+06, "95500563d589b4a9"),
+    ("cubic4_dense", "fp64", 2, 4, 1): (5.8147e+06, "95500563d589b4a9"),
+    ("cubic4_dense", "fp64", 2, 4, 2): (5.7615e+06, "95500563d589b4a9"),
+    ("cubic4_dense", "fp64", 2, 4, 4): (5.8831e+06, "95500563d589b4a9"),
 }
 
 

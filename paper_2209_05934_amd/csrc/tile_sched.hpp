@@ -70,7 +70,7 @@ __device__ void filter_tile(V& acc, int lane, const uint8_t* __restrict__ rseg,
 // successive XCDs: the hardware deals workgroups to the 8 XCDs round-robin, so
 // physical block p runs on XCD p % 8 as its (p / 8)-th block there.  Every
 // part of the grid (every system of a batch) is thereby spread over all XCDs.
-// The t blocks of an incomplete last round of 8 runs are cut into 8 contiguous
+// The t blocks of an incomplete last cycle of 8 runs are cut into 8 contiguous
 // ranges, one per XCD (t / 8 blocks, one more for the first t % 8 XCDs), so the
 // groups of one output row stay on one XCD there too; the renumbering stays a
 // bijection on [0, gridDim.x).
