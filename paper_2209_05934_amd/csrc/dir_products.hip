@@ -66,24 +66,29 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s1(
         });
   } else if (act) {
     struct Stage { Frag<TI> h, s, b[NT]; };
-    const TI* Sq = ident ? Hm : Sm;   // S = I: the S fragments are loaded but never used
-    run_entries<W, D, Stage>(
-        er, lane,
-        [&](Stage& f, const int (&id)[W]) {
-          ld_col(f.h, Hm + (size_t)id[0] * TE, lane);   // tile (k, i) of the symmetric H: A(i, k)
-          ld_col(f.s, Sq + (size_t)id[0] * TE, lane);
+    // IDENT (S = I): neither S loads nor S products; S B is B's own tile
+    auto body = [&](auto identc) {
+      constexpr bool IDENT = decltype(identc)::value;
+      run_entries<W, D, Stage>(
+          er, lane,
+          [&](Stage& f, const int (&id)[W]) {
+            ld_col(f.h, Hm + (size_t)id[0] * TE, lane);   // tile (k, i) of the symmetric H: A(i, k)
+            if constexpr (!IDENT) ld_col(f.s, Sm + (size_t)id[0] * TE, lane);
 #pragma unroll
-          for (int u = 0; u < NT; ++u) ld_col(f.b[u], Bm + (size_t)max(id[1 + u], 0) * TE, lane);
-        },
-        [&](const Stage& f, const int (&id)[W]) {
+            for (int u = 0; u < NT; ++u) ld_col(f.b[u], Bm + (size_t)max(id[1 + u], 0) * TE, lane);
+          },
+          [&](const Stage& f, const int (&id)[W]) {
 #pragma unroll
-          for (int u = 0; u < NT; ++u) {
-            if (id[1 + u] >= 0) {
-              mma(acc[u], f.h, f.b[u]);
-              if (!ident) mma(acc[NT + u], f.s, f.b[u]);
+            for (int u = 0; u < NT; ++u) {
+              if (id[1 + u] >= 0) {
+                mma(acc[u], f.h, f.b[u]);
+                if constexpr (!IDENT) mma(acc[NT + u], f.s, f.b[u]);
+              }
             }
-          }
-        });
+          });
+    };
+    if (ident) body(std::true_type{});
+    else body(std::false_type{});
   }
   ks_reduce<KS, NA>(acc, red, grp, wk, lane);
   if (!act || wk != 0) return;
