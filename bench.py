@@ -61,17 +61,17 @@ PEAKS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}   # dense TFLOP/s of MI355
 # group width and split, and valid only for the kernel sources they were taken
 # with (sha256 prefix of the step's source file, tile_sched.hpp and tile_ops.hpp)
 MEASURED_TRAFFIC = {
-    ("cubic4_dense", "fp64", 0, 1, 1): (2.0894e+07, "d36de78506d04001"),
-    ("cubic4_dense", "fp64", 0, 1, 2): (2.0885e+07, "d36de78506d04001"),
-    ("cubic4_dense", "fp64", 0, 1, 4): (2.0804e+07, "d36de78506d04001"),
-    ("cubic4_dense", "fp64", 0, 1, 8): (2.0771e+07, "d36de78506d04001"),
-    ("cubic4_dense", "fp64", 0, 2, 1): (1.9988e+07, "d36de78506d04001"),
-    ("cubic4_dense", "fp64", 0, 2, 2): (2.0865e+07, "d36de78506d04001"),
-    ("cubic4_dense", "fp64", 0, 2, 4): (2.0826e+07, "d36de78506d04001"),
-    ("cubic4_dense", "fp64", 0, 2, 8): (2.0770e+07, "d36de78506d04001"),
-    ("cubic4_dense", "fp64", 0, 4, 1): (2.0034e+07, "d36de78506d04001"),
-    ("cubic4_dense", "fp64", 0, 4, 2): (2.0059e+07, "d36de78506d04001"),
-    ("cubic4_dense", "fp64", 0, 4, 4): (2.0950e+07, "d36de78506d04001"),
+    ("cubic4_dense", "fp64", 0, 1, 1): (2.0903e+07, "575bc51cd6fe1caf"),
+    ("cubic4_dense", "fp64", 0, 1, 2): (2.0878e+07, "575bc51cd6fe1caf"),
+    ("cubic4_dense", "fp64", 0, 1, 4): (2.0818e+07, "575bc51cd6fe1caf"),
+    ("cubic4_dense", "fp64", 0, 1, 8): (2.0782e+07, "575bc51cd6fe1caf"),
+    ("cubic4_dense", "fp64", 0, 2, 1): (2.0007e+07, "575bc51cd6fe1caf"),
+    ("cubic4_dense", "fp64", 0, 2, 2): (2.0881e+07, "575bc51cd6fe1caf"),
+    ("cubic4_dense", "fp64", 0, 2, 4): (2.0820e+07, "575bc51cd6fe1caf"),
+    ("cubic4_dense", "fp64", 0, 2, 8): (2.0783e+07, "575bc51cd6fe1caf"),
+    ("cubic4_dense", "fp64", 0, 4, 1): (2.0040e+07, "575bc51cd6fe1caf"),
+    ("cubic4_dense", "fp64", 0, 4, 2): (2.0058e+07, "575bc51cd6fe1caf"),
+    ("cubic4_dense", "fp64", 0, 4, 4): (2.0940e+07, "575bc51cd6fe1caf"),
     ("cubic4_dense", "fp64", 1, 1, 1): (1.6204e+07, "88f4557412d1c0f9"),
     ("cubic4_dense", "fp64", 1, 1, 2): (1.6194e+07, "88f4557412d1c0f9"),
     ("cubic4_dense", "fp64", 1, 1, 4): (1.6064e+07, "88f4557412d1c0f9"),
