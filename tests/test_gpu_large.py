@@ -4,7 +4,9 @@
   boolean product of the atom-level patterns (exact integers);
 * the first CG iterations of the 512-atom localized system agree with the
   oracle (same C0, filter 0), and a long run ends at a point where the oracle's
-  own functional and projected gradient agree with what the library reports.
+  own functional and projected gradient agree with what the library reports;
+* at 4096 atoms, properties that hold at any size (repeatability, energy
+  descent, FP32 tracking FP64).
 """
 
 import numpy as np
@@ -106,3 +108,32 @@ def test_cubic8_kim_first_iterations_and_energy_density():
     want = s.S.gather_from_dense(O.energy_density_matrix(ref.C, ref.HW, ref.SW, s.spec.eta))
     assert np.max(np.abs(ctx.energy_density(0) - want)) <= 1e-9
     ctx.close()
+
+
+def test_cubic16_full_size_properties():
+    """4096 atoms (N_basis 53248, N_occ 8192) with the filter of the bench workload
+    (too large for the dense oracle, so properties that hold at any size): two
+    FP64 runs are bitwise identical, the energy never rises, the outputs are
+    finite, and FP32 products track the FP64 energies of the same iterations
+    within 1e-5 Ha/atom (the mixed-precision tracking target)."""
+    s = system("cubic16_mixed")
+    k = 6
+
+    def run(**o):
+        ctx = Context([Problem(s.H, s.S, s.C0, s.n, L.OMM_BLOCK_SPARSE)], eta=s.spec.eta, max_iter=k,
+                      filter_eps=s.spec.filter_eps, **o)
+        rc, reps = ctx.minimize()
+        out = (reps[0], ctx.history(0).copy(), ctx.coeffs(0).copy())
+        ctx.close()
+        return out
+
+    r1, h1, c1 = run()
+    r2, h2, c2 = run()
+    assert r1.iters_total == k == len(h1)
+    assert np.array_equal(c1, c2) and np.array_equal(h1[:, 0], h2[:, 0]) and r1.energy == r2.energy
+    E = h1[:, 0]
+    assert np.all(np.diff(E) <= 1e-10 * s.natoms)
+    assert np.all(np.isfinite(c1)) and np.isfinite(r1.grad_norm) and r1.grad_norm > 0
+    r3, h3, _ = run(precision=L.OMM_FP32, fp64_refine_iters=0, lowprec_max_iter=1000)
+    assert len(h3) == k and np.all(h3[:, 10] == L.OMM_FP32)
+    assert np.max(np.abs(h3[:, 0] - E)) / s.natoms <= 1e-5
