@@ -16,7 +16,7 @@ namespace {
 // ONE: the single product Z = P G of kinetic preconditioning (Eq. 7; dense
 // systems, whose HC and C patterns coincide): Hm = P, Bm = G, Z written in C's
 // tile layout with the per-tile sums <Z, G> and <Z, G_old> in zpart.
-template <typename TI, typename TO, int KS, int NT, bool ONE>
+template <typename TI, typename TO, int KS, int NT, bool ONE, bool ROLL>
 __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s1(
     GroupView P, const int* __restrict__ ocol, const SysInfo* __restrict__ info, const SysState* __restrict__ st, int mask, const TI* __restrict__ Hm,
     const TI* __restrict__ Sm, const TI* __restrict__ Bm, TO* __restrict__ O1, TO* __restrict__ O2,
@@ -52,7 +52,7 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s1(
   for (int a = 0; a < NA; ++a) acc[a] = vzero<V>();
   if (act && ONE) {
     struct Stage { Frag<TI> h, b[NT]; };
-    run_entries<W, D, Stage>(
+    run_entries<W, D, Stage, ROLL>(
         er, lane,
         [&](Stage& f, const int (&id)[W]) {
           ld_col(f.h, Hm + (size_t)id[0] * TE, lane);
@@ -69,7 +69,7 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s1(
     // IDENT (S = I): neither S loads nor S products; S B is B's own tile
     auto body = [&](auto identc) {
       constexpr bool IDENT = decltype(identc)::value;
-      run_entries<W, D, Stage>(
+      run_entries<W, D, Stage, ROLL>(
           er, lane,
           [&](Stage& f, const int (&id)[W]) {
             ld_col(f.h, Hm + (size_t)id[0] * TE, lane);   // tile (k, i) of the symmetric H: A(i, k)
@@ -152,8 +152,12 @@ static void s1_go(hipStream_t s, const Bufs& b, int mask, const TI* H, const TI*
   if (b.s1.ngroups <= 0) return;
   nt_ks<0>(b.s1.NT, b.ks[0], [&](auto ntc, auto ksc) {
     constexpr int N_ = decltype(ntc)::value, K_ = decltype(ksc)::value;
-    LAUNCH((k_s1<TI, TO, K_, N_, ONE>), grid_for<K_>(b.s1.ngroups), block_for<K_>(), s, b.s1, b.thc_col, b.info,
-           b.st, mask, H, S, B, O1, O2, b.hc_to_c, b.wseg, b.Gold, b.zpart, trans_out);
+    if (b.roll)
+      LAUNCH((k_s1<TI, TO, K_, N_, ONE, true>), grid_for<K_>(b.s1.ngroups), block_for<K_>(), s, b.s1, b.thc_col,
+             b.info, b.st, mask, H, S, B, O1, O2, b.hc_to_c, b.wseg, b.Gold, b.zpart, trans_out);
+    else
+      LAUNCH((k_s1<TI, TO, K_, N_, ONE, false>), grid_for<K_>(b.s1.ngroups), block_for<K_>(), s, b.s1, b.thc_col,
+             b.info, b.st, mask, H, S, B, O1, O2, b.hc_to_c, b.wseg, b.Gold, b.zpart, trans_out);
   });
 }
 

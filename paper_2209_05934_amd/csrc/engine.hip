@@ -875,6 +875,7 @@ void prepare(omm_ctx* c) {
     if (c->h_info[i].c1 - c->h_info[i].c0 > FUSED_CTILES) b.multi_c = 1;
   b.n_th = (int)c->TH.nnz; b.n_tc = (int)ntc; b.n_thc = (int)nhc; b.n_tw = (int)ntw;
   pick_plans(c);
+  b.roll = c->nsys > 1 ? 1 : 0;
   b.H = c->H; b.S = c->S;
   b.C = dalloc<double>(c, ntc * TE, true);
   b.D = dalloc<double>(c, ntc * TE, true);

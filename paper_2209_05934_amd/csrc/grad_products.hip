@@ -10,7 +10,7 @@ namespace {
 // ------------------------------------------------------------------ gradient on C's pattern
 // Groups of NT tiles of C's pattern in one basis row b: per k the HC(b,k) and
 // SC(b,k) tiles are loaded once for NT tiles of S_W and H_W.
-template <typename TI, int KS, int NT>
+template <typename TI, int KS, int NT, bool ROLL>
 __global__ __launch_bounds__(Split<KS>::NW * 64) void k_grad(
     GroupView P, const SysState* __restrict__ st, int mask, const TI* __restrict__ HCm,
     const TI* __restrict__ SCm, const TI* __restrict__ S0m, const TI* __restrict__ H0m,
@@ -41,7 +41,7 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_grad(
   for (int a = 0; a < NT; ++a) acc[a] = vzero<V>();
   if (act) {
     struct Stage { Frag<TI> h, s, w[NT], v[NT]; };
-    run_entries<W, D, Stage>(
+    run_entries<W, D, Stage, ROLL>(
         er, lane,
         [&](Stage& f, const int (&id)[W]) {
           ld_col(f.h, HCm + (size_t)id[0] * TE, lane);   // HC, SC tiles are stored transposed
@@ -99,8 +99,12 @@ static void grad_go(hipStream_t s, const Bufs& b, int mask, const TI* HC, const 
   if (b.grad.ngroups <= 0) return;
   nt_ks<2>(b.grad.NT, b.ks[2], [&](auto ntc, auto ksc) {
     constexpr int N_ = decltype(ntc)::value, K_ = decltype(ksc)::value;
-    LAUNCH((k_grad<TI, K_, N_>), grid_for<K_>(b.grad.ngroups), block_for<K_>(), s, b.grad, b.st, mask, HC, SC, S0,
-           H0, b.HC, b.c_in_hc, b.cmask, b.Gold, b.G, b.gpart);
+    if (b.roll)
+      LAUNCH((k_grad<TI, K_, N_, true>), grid_for<K_>(b.grad.ngroups), block_for<K_>(), s, b.grad, b.st, mask, HC,
+             SC, S0, H0, b.HC, b.c_in_hc, b.cmask, b.Gold, b.G, b.gpart);
+    else
+      LAUNCH((k_grad<TI, K_, N_, false>), grid_for<K_>(b.grad.ngroups), block_for<K_>(), s, b.grad, b.st, mask, HC,
+             SC, S0, H0, b.HC, b.c_in_hc, b.cmask, b.Gold, b.G, b.gpart);
   });
 }
 

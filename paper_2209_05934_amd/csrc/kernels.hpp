@@ -71,6 +71,7 @@ struct Bufs {   // every device buffer the iteration kernels touch
   int nsys;
   double eps2;                   // filter threshold squared (block-sparse products)
   int ks[3];                     // waves splitting one output tile: direction, n x n, gradient products
+  int roll;                      // product kernels with the rolled work-list loop (multi-system contexts)
 };
 
 // one CG iteration step (all systems whose phase matches `mask`), arithmetic `prec`

@@ -13,7 +13,7 @@ namespace {
 // S2 = D^T S D and H2 = D^T H D are symmetric: they are formed and stored for
 // tiles on or above the diagonal only, and readers take a tile below it as the
 // transpose of its mirror (X and Y are not symmetric and are formed in full).
-template <typename TI, typename TM, typename TO, int NPROD, int KS, int NT>
+template <typename TI, typename TM, typename TO, int NPROD, int KS, int NT, bool ROLL>
 __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s2(
     GroupView P, const int* __restrict__ orow, const int* __restrict__ ocol, const SysInfo* __restrict__ info, const SysState* __restrict__ st, int mask, const TI* __restrict__ Cm,
     const TI* __restrict__ Dm, const TM* __restrict__ HDm, const TM* __restrict__ SDm, TO* __restrict__ X,
@@ -53,7 +53,7 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s2(
   struct Stage { Frag<TI> c, d, hd[NT], sd[NT]; };
   auto body = [&](auto skip_d) {
     constexpr bool SKIP = decltype(skip_d)::value;
-    run_entries<W, D, Stage>(
+    run_entries<W, D, Stage, ROLL>(
         er, lane,
         [&](Stage& f, const int (&id)[W]) {
           ld_col(f.c, Cm + (size_t)id[0] * TE, lane);                 // A = C^T
@@ -124,8 +124,12 @@ static void s2_go(hipStream_t s, const Bufs& b, int mask, const TI* C, const TI*
   if (b.s2.ngroups <= 0) return;
   nt_ks<1>(b.s2.NT, b.ks[1], [&](auto ntc, auto ksc) {
     constexpr int N_ = decltype(ntc)::value, K_ = decltype(ksc)::value;
-    LAUNCH((k_s2<TI, TM, TO, NP, K_, N_>), grid_for<K_>(b.s2.ngroups), block_for<K_>(), s, b.s2, b.tw_row,
-           b.tw_col, b.info, b.st, mask, C, D, HD, SD, X, Y, S2, H2, b.wseg);
+    if (b.roll)
+      LAUNCH((k_s2<TI, TM, TO, NP, K_, N_, true>), grid_for<K_>(b.s2.ngroups), block_for<K_>(), s, b.s2, b.tw_row,
+             b.tw_col, b.info, b.st, mask, C, D, HD, SD, X, Y, S2, H2, b.wseg);
+    else
+      LAUNCH((k_s2<TI, TM, TO, NP, K_, N_, false>), grid_for<K_>(b.s2.ngroups), block_for<K_>(), s, b.s2, b.tw_row,
+             b.tw_col, b.info, b.st, mask, C, D, HD, SD, X, Y, S2, H2, b.wseg);
   });
 }
 

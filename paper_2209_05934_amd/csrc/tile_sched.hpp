@@ -162,8 +162,11 @@ struct EntryRounds {
 // loads unconditionally (past the end it reloads the last entry), so the
 // compiler knows at each use exactly how many younger loads are in flight and
 // waits for that stage alone; the look-ahead runs across round boundaries, so
-// the pipeline never drains.
-template <int W, int D, typename St, typename LoadF, typename UseF>
+// the pipeline never drains.  ROLL: a round is a loop over groups of D entries
+// with only the D stages unrolled, several times less code (multi-system
+// launches, which run many kernels and shapes per iteration, are faster with
+// it; single systems are faster unrolled).
+template <int W, int D, typename St, bool ROLL = false, typename LoadF, typename UseF>
 __device__ __forceinline__ void run_entries(EntryRounds<W, D>& er, int lane, LoadF&& load, UseF&& use) {
   constexpr int PB = EntryRounds<W, D>::PB;
   const int n = er.n;
@@ -177,24 +180,49 @@ __device__ __forceinline__ void run_entries(EntryRounds<W, D>& er, int lane, Loa
     for (int w = 0; w < W; ++w) id[s][w] = __builtin_amdgcn_readlane(er.cur, q * W + w);
     load(stg[s], id[s]);
   }
-  for (int r0 = 0;; r0 += PB) {
+  if constexpr (ROLL) {
+    for (int r0 = 0;; r0 += PB) {
+#pragma unroll 1
+      for (int k0 = 0; k0 < PB; k0 += D) {
 #pragma unroll
-    for (int k = 0; k < PB; ++k) {
-      if (r0 + k >= n) return;
-      use(stg[k % D], id[k % D]);
-      // entry r0 + k + D (clamped to the last one) lives in this round or the next
-      const int q = (r0 + k + D < n ? r0 + k + D : n - 1) - r0;
-      if (q < PB) {
+        for (int j = 0; j < D; ++j) {   // entry k0 + j in stage j (k0 is a multiple of D)
+          const int k = k0 + j;
+          if (r0 + k >= n) return;
+          use(stg[j], id[j]);
+          const int q = (r0 + k + D < n ? r0 + k + D : n - 1) - r0;
+          if (q < PB) {
 #pragma unroll
-        for (int w = 0; w < W; ++w) id[k % D][w] = __builtin_amdgcn_readlane(er.cur, q * W + w);
-      } else {
+            for (int w = 0; w < W; ++w) id[j][w] = __builtin_amdgcn_readlane(er.cur, q * W + w);
+          } else {
 #pragma unroll
-        for (int w = 0; w < W; ++w) id[k % D][w] = __builtin_amdgcn_readlane(er.nxt, (q - PB) * W + w);
+            for (int w = 0; w < W; ++w) id[j][w] = __builtin_amdgcn_readlane(er.nxt, (q - PB) * W + w);
+          }
+          load(stg[j], id[j]);
+        }
       }
-      load(stg[k % D], id[k % D]);
+      er.cur = er.nxt;
+      er.nxt = er.batch(r0 + 2 * PB, lane);
     }
-    er.cur = er.nxt;
-    er.nxt = er.batch(r0 + 2 * PB, lane);
+  } else {
+    for (int r0 = 0;; r0 += PB) {
+#pragma unroll
+      for (int k = 0; k < PB; ++k) {
+        if (r0 + k >= n) return;
+        use(stg[k % D], id[k % D]);
+        // entry r0 + k + D (clamped to the last one) lives in this round or the next
+        const int q = (r0 + k + D < n ? r0 + k + D : n - 1) - r0;
+        if (q < PB) {
+#pragma unroll
+          for (int w = 0; w < W; ++w) id[k % D][w] = __builtin_amdgcn_readlane(er.cur, q * W + w);
+        } else {
+#pragma unroll
+          for (int w = 0; w < W; ++w) id[k % D][w] = __builtin_amdgcn_readlane(er.nxt, (q - PB) * W + w);
+        }
+        load(stg[k % D], id[k % D]);
+      }
+      er.cur = er.nxt;
+      er.nxt = er.batch(r0 + 2 * PB, lane);
+    }
   }
 }
 
