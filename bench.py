@@ -61,38 +61,38 @@ PEAKS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}   # dense TFLOP/s of MI355
 # group width and split, and valid only for the kernel sources they were taken
 # with (sha256 prefix of the step's source file, tile_sched.hpp and tile_ops.hpp)
 MEASURED_TRAFFIC = {
-    ("cubic4_dense", "fp64", 0, 1, 1): (2.0903e+07, "575bc51cd6fe1caf"),
-    ("cubic4_dense", "fp64", 0, 1, 2): (2.0878e+07, "575bc51cd6fe1caf"),
-    ("cubic4_dense", "fp64", 0, 1, 4): (2.0818e+07, "575bc51cd6fe1caf"),
-    ("cubic4_dense", "fp64", 0, 1, 8): (2.0782e+07, "575bc51cd6fe1caf"),
-    ("cubic4_dense", "fp64", 0, 2, 1): (2.0007e+07, "575bc51cd6fe1caf"),
-    ("cubic4_dense", "fp64", 0, 2, 2): (2.0881e+07, "575bc51cd6fe1caf"),
-    ("cubic4_dense", "fp64", 0, 2, 4): (2.0820e+07, "575bc51cd6fe1caf"),
-    ("cubic4_dense", "fp64", 0, 2, 8): (2.0783e+07, "575bc51cd6fe1caf"),
-    ("cubic4_dense", "fp64", 0, 4, 1): (2.0040e+07, "575bc51cd6fe1caf"),
-    ("cubic4_dense", "fp64", 0, 4, 2): (2.0058e+07, "575bc51cd6fe1caf"),
-    ("cubic4_dense", "fp64", 0, 4, 4): (2.0940e+07, "575bc51cd6fe1caf"),
-    ("cubic4_dense", "fp64", 1, 1, 1): (1.6204e+07, "88f4557412d1c0f9"),
-    ("cubic4_dense", "fp64", 1, 1, 2): (1.6194e+07, "88f4557412d1c0f9"),
-    ("cubic4_dense", "fp64", 1, 1, 4): (1.6064e+07, "88f4557412d1c0f9"),
-    ("cubic4_dense", "fp64", 1, 1, 8): (1.5971e+07, "88f4557412d1c0f9"),
-    ("cubic4_dense", "fp64", 1, 2, 1): (1.6273e+07, "88f4557412d1c0f9"),
-    ("cubic4_dense", "fp64", 1, 2, 2): (1.6305e+07, "88f4557412d1c0f9"),
-    ("cubic4_dense", "fp64", 1, 2, 4): (1.6217e+07, "88f4557412d1c0f9"),
-    ("cubic4_dense", "fp64", 1, 4, 1): (9.2083e+06, "88f4557412d1c0f9"),
-    ("cubic4_dense", "fp64", 1, 4, 2): (1.6362e+07, "88f4557412d1c0f9"),
-    ("cubic4_dense", "fp64", 1, 4, 4): (1.6424e+07, "88f4557412d1c0f9"),
-    ("cubic4_dense", "fp64", 2, 1, 1): (5.8135e+06, "95500563d589b4a9"),
-    ("cubic4_dense", "fp64", 2, 1, 2): (5.8032e+06, "95500563d589b4a9"),
-    ("cubic4_dense", "fp64", 2, 1, 4): (5.7930e+06, "95500563d589b4a9"),
-    ("cubic4_dense", "fp64", 2, 1, 8): (5.7889e+06, "95500563d589b4a9"),
-    ("cubic4_dense", "fp64", 2, 2, 1): (5.7166e+06, "95500563d589b4a9"),
-    ("cubic4_dense", "fp64", 2, 2, 2): (5.8323e+06, "95500563d589b4a9"),
-    ("cubic4_dense", "fp64", 2, 2, 4): (5.8231e+06, "95500563d589b4a9"),
-    ("cubic4_dense", "fp64", 2, 2, 8): (5.7944e+06, "95500563d589b4a9"),
-    ("cubic4_dense", "fp64", 2, 4, 1): (5.8147e+06, "95500563d589b4a9"),
-    ("cubic4_dense", "fp64", 2, 4, 2): (5.7615e+06, "95500563d589b4a9"),
-    ("cubic4_dense", "fp64", 2, 4, 4): (5.8831e+06, "95500563d589b4a9"),
+    ("cubic4_dense", "fp64", 0, 1, 1): (2.0901e+07, "8bed00890865259c"),
+    ("cubic4_dense", "fp64", 0, 1, 2): (2.0877e+07, "8bed00890865259c"),
+    ("cubic4_dense", "fp64", 0, 1, 4): (2.0816e+07, "8bed00890865259c"),
+    ("cubic4_dense", "fp64", 0, 1, 8): (2.0777e+07, "8bed00890865259c"),
+    ("cubic4_dense", "fp64", 0, 2, 1): (1.9986e+07, "8bed00890865259c"),
+    ("cubic4_dense", "fp64", 0, 2, 2): (2.0861e+07, "8bed00890865259c"),
+    ("cubic4_dense", "fp64", 0, 2, 4): (2.0834e+07, "8bed00890865259c"),
+    ("cubic4_dense", "fp64", 0, 2, 8): (2.0785e+07, "8bed00890865259c"),
+    ("cubic4_dense", "fp64", 0, 4, 1): (2.0021e+07, "8bed00890865259c"),
+    ("cubic4_dense", "fp64", 0, 4, 2): (2.0058e+07, "8bed00890865259c"),
+    ("cubic4_dense", "fp64", 0, 4, 4): (2.0952e+07, "8bed00890865259c"),
+    ("cubic4_dense", "fp64", 1, 1, 1): (1.6204e+07, "fa69ae1cfaaafee5"),
+    ("cubic4_dense", "fp64", 1, 1, 2): (1.6196e+07, "fa69ae1cfaaafee5"),
+    ("cubic4_dense", "fp64", 1, 1, 4): (1.6078e+07, "fa69ae1cfaaafee5"),
+    ("cubic4_dense", "fp64", 1, 1, 8): (1.5991e+07, "fa69ae1cfaaafee5"),
+    ("cubic4_dense", "fp64", 1, 2, 1): (1.6273e+07, "fa69ae1cfaaafee5"),
+    ("cubic4_dense", "fp64", 1, 2, 2): (1.6305e+07, "fa69ae1cfaaafee5"),
+    ("cubic4_dense", "fp64", 1, 2, 4): (1.6217e+07, "fa69ae1cfaaafee5"),
+    ("cubic4_dense", "fp64", 1, 4, 1): (9.2129e+06, "fa69ae1cfaaafee5"),
+    ("cubic4_dense", "fp64", 1, 4, 2): (1.6375e+07, "fa69ae1cfaaafee5"),
+    ("cubic4_dense", "fp64", 1, 4, 4): (1.6417e+07, "fa69ae1cfaaafee5"),
+    ("cubic4_dense", "fp64", 2, 1, 1): (5.8124e+06, "4f4585e2f31cc914"),
+    ("cubic4_dense", "fp64", 2, 1, 2): (5.7909e+06, "4f4585e2f31cc914"),
+    ("cubic4_dense", "fp64", 2, 1, 4): (5.7858e+06, "4f4585e2f31cc914"),
+    ("cubic4_dense", "fp64", 2, 1, 8): (5.7889e+06, "4f4585e2f31cc914"),
+    ("cubic4_dense", "fp64", 2, 2, 1): (5.7248e+06, "4f4585e2f31cc914"),
+    ("cubic4_dense", "fp64", 2, 2, 2): (5.8323e+06, "4f4585e2f31cc914"),
+    ("cubic4_dense", "fp64", 2, 2, 4): (5.8190e+06, "4f4585e2f31cc914"),
+    ("cubic4_dense", "fp64", 2, 2, 8): (5.8046e+06, "4f4585e2f31cc914"),
+    ("cubic4_dense", "fp64", 2, 4, 1): (5.8147e+06, "4f4585e2f31cc914"),
+    ("cubic4_dense", "fp64", 2, 4, 2): (5.7666e+06, "4f4585e2f31cc914"),
+    ("cubic4_dense", "fp64", 2, 4, 4): (5.8821e+06, "4f4585e2f31cc914"),
 }
 
 
