@@ -110,7 +110,11 @@ typedef struct {
   double ne_tol;            /* electron-count check tolerance; <= 0 disables; default 0 */
   int32_t autotune;         /* 1: time kernel variants at first minimize and keep the
                                fastest (cached in tune_cache when set); default 0 */
-  const char* tune_cache;   /* path of the autotuner cache file, or NULL */
+  const char* tune_cache;   /* path of the autotuner cache file, or NULL: one line per
+                               product step and work-list size, "key code" with
+                               code = 10 * group-width plan (0: 1, 1: 2, 2: 4 tiles)
+                               + waves per group; a line whose shape this library
+                               cannot launch is ignored and tuned again */
   void* hip_stream;         /* hipStream_t to run on; NULL: the library makes its own */
 } omm_options;
 

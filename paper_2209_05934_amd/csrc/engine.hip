@@ -1012,9 +1012,14 @@ void autotune(omm_ctx* c) {
     int found = -1;
     for (auto& kv : cache)
       if (kv.first == key) found = kv.second;
-    if (found >= 0) {      // cached as 10 * plan + KS
-      set_plan(c, cls, found / 10, found % 10);
-      continue;
+    if (found >= 0) {      // cached as 10 * plan + KS; an entry this build cannot launch is tuned again
+      const int sel = found / 10, ks = found % 10;
+      if (sel < NPLAN && (ks == 1 || ks == 2 || ks == 4 || ks == 8) && plan_ok(cls, c->G[cls][sel].NT, ks)) {
+        set_plan(c, cls, sel, ks);
+        continue;
+      }
+      cache.erase(std::remove_if(cache.begin(), cache.end(), [&](const auto& kv) { return kv.first == key; }),
+                  cache.end());
     }
     float best = 1e30f;
     int best_code = 10 * c->sel[cls] + c->b.ks[cls];

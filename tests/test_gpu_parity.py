@@ -239,3 +239,25 @@ def test_smallest_system_and_start_at_the_minimum():
         assert reps[0].status == L.OMM_OK and reps[0].iters_total <= 1
         assert abs(reps[0].energy - 2.0 * -0.7) <= 1e-12
         ctx.close()
+
+
+def test_corrupt_tune_cache_is_tuned_again(tmp_path):
+    """Cache lines naming shapes the library cannot launch (plan 9, 7 waves, plan 3)
+    are ignored: the steps are tuned again and the solve is unchanged."""
+    s = system("cubic4_dense")
+    cache = tmp_path / "tune.txt"
+    c0, r0 = gpu_run(s, "dense", autotune=1, tune_cache=str(cache).encode())
+    keys = [line.split()[0] for line in open(cache) if line.strip()]
+    assert len(keys) == 3
+    c0.close()
+    with open(cache, "w") as f:
+        for k, code in zip(keys, (99, 7, 38)):
+            f.write(f"{k} {code}\n")
+    ctx, r = gpu_run(s, "dense", autotune=1, tune_cache=str(cache).encode())
+    z = ctx.sizes()
+    assert all(g in (1, 2, 4) for g in z.tile_group) and all(k in (1, 2, 4, 8) for k in z.tile_split)
+    assert r.status == L.OMM_OK and abs(r.energy - r0.energy) / s.natoms <= 1e-10
+    codes = {k: int(v) for k, v in (line.split() for line in open(cache) if line.strip())}
+    assert set(codes) == set(keys)
+    assert all(c // 10 < 3 and c % 10 in (1, 2, 4, 8) for c in codes.values())
+    ctx.close()
