@@ -364,7 +364,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              f"(the multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+              f"(sharding over several GPUs is not built)", file=sys.stderr)
         sys.exit(2)
     if args.copy_probe:
         import torch

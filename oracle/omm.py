@@ -12,7 +12,7 @@ matrix (columns = wavefunctions, Eq. 3), H_W = C^T H C and S_W = C^T S C
 real (Gamma point, Sec. IV A).  H and S may be dense numpy arrays or
 scipy.sparse matrices; C-shaped matrices are dense.
 
-Readings where the paper is silent (each is also listed in the design doc):
+Readings where the paper is silent:
 * gradient: the real gradient dE~/dC = 8HC - 4(HC S_W + SC H_W); the paper's
   G = dE~/d(C*) (Sec. III B) is half of it.  With an exact line search the CG
   iterates do not depend on that factor; only the norm threshold does.

@@ -1012,7 +1012,7 @@ void autotune(omm_ctx* c) {
     int found = -1;
     for (auto& kv : cache)
       if (kv.first == key) found = kv.second;
-    if (found >= 0) {      // cached as 10 * plan + KS; an entry this build cannot launch is tuned again
+    if (found >= 0) {      // cached as 10 * plan + KS; an entry naming a shape the library cannot launch is tuned again
       const int sel = found / 10, ks = found % 10;
       if (sel < NPLAN && (ks == 1 || ks == 2 || ks == 4 || ks == 8) && plan_ok(cls, c->G[cls][sel].NT, ks)) {
         set_plan(c, cls, sel, ks);
