@@ -107,6 +107,17 @@ class BlockMatrix:
             out[ro[i]:ro[i + 1], co[j]:co[j + 1]] = True
         return out
 
+    def to_bsr(self):
+        """scipy.sparse BSR matrix of the same blocks (uniform block sizes only)."""
+        import scipy.sparse
+        rb, cb = int(self.row_bsz[0]), int(self.col_bsz[0])
+        if np.any(self.row_bsz != rb) or np.any(self.col_bsz != cb):
+            raise ValueError("BSR needs uniform block sizes")
+        idx = self.val_off[:, None] + np.arange(rb * cb)[None, :]
+        data = self.val[idx].reshape(self.nnzb, rb, cb)
+        return scipy.sparse.bsr_matrix((data, self.col_idx.astype(np.int32), self.row_ptr.astype(np.int32)),
+                                       shape=self.shape)
+
     def with_values(self, val: np.ndarray) -> "BlockMatrix":
         return replace(self, val=np.ascontiguousarray(val, dtype=np.float64))
 

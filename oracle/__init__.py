@@ -14,7 +14,9 @@ respect to S and its eigen form at the minimum, the identities of Eqs. 1, 2, 5
 and Listing 1, Cholesky
 variant == plain variant, unlimited localization radius == dense, and a
 brute-force BFGS minimum on tiny localized inputs.  Product filtering with a
-positive threshold is "parity unpinned" (no closed form; only reported).
+positive threshold follows one definition (`cg_minimize_filtered`): at
+threshold 0 it is the plain method; above it, "parity unpinned" against any
+closed form (the difference from the unfiltered minimum is only reported).
 """
 
 from .omm import (  # noqa: F401
@@ -24,9 +26,12 @@ from .omm import (  # noqa: F401
     om_gradient,
     project,
     quartic_coefficients,
+    quartic_from_projections,
     quartic_value,
     line_minimum,
     cg_minimize,
+    cg_minimize_sparse,
+    cg_minimize_filtered,
     cholesky_reduce,
     kinetic_preconditioner,
     cg_minimize_cholesky,

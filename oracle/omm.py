@@ -34,13 +34,19 @@ Readings where the paper is silent:
   Sec. II), i.e. the paper's "E~ + eta n" with its spin factor; n counts the
   occupied states, which may be fewer than the n' columns of C.  The energy
   density gets the matching correction rho_E + eta rho.
-* filtering (Sec. V): with filter_eps > 0, every product of H or S with C or
-  D and every n x n projection has its atom blocks of Frobenius norm < eps set
-  to zero; C, D, G, H and S are never filtered.  eps = 0 filters nothing.
+* filtering (Sec. V): the paper filters the block products it forms; which
+  products a CG iteration forms is libOMM's business (only cited).  The reading
+  taken (`cg_minimize_filtered`): each iteration forms the direction products
+  H D, S D and the n x n projections C^T S D, C^T H D, D^T S D, D^T H D, and
+  filters each of them (atom blocks of Frobenius norm < eps set to zero); H C,
+  S C, H_W and S_W are formed and filtered once from C0 and afterwards follow
+  the line steps as exact sums of those filtered products.  C, D, G, H and S
+  are never filtered.  With eps = 0 this is the plain method.
 """
 
 from __future__ import annotations
 
+import time
 from dataclasses import dataclass, field
 from typing import List, Optional, Sequence, Tuple
 
@@ -167,6 +173,12 @@ def quartic_coefficients(H, S, C, D, filt=None) -> np.ndarray:
     H1 = f_nn(C.T @ HD) + f_nn(D.T @ HC)
     S1 = f_nn(C.T @ SD) + f_nn(D.T @ SC)
     H2, S2 = f_nn(D.T @ HD), f_nn(D.T @ SD)
+    return quartic_from_projections(H0, S0, H1, S1, H2, S2)
+
+
+def quartic_from_projections(H0, S0, H1, S1, H2, S2) -> np.ndarray:
+    """c0..c4 of E~(x) = 4 Tr H_W(x) - 2 <S_W(x), H_W(x)> (Eq. 4) for
+    H_W(x) = H0 + x H1 + x^2 H2 and S_W(x) = S0 + x S1 + x^2 S2, collected by powers of x."""
     c0 = 4.0 * np.trace(H0) - 2.0 * _frob(S0, H0)
     c1 = 4.0 * np.trace(H1) - 2.0 * (_frob(S0, H1) + _frob(S1, H0))
     c2 = 4.0 * np.trace(H2) - 2.0 * (_frob(S0, H2) + _frob(S1, H1) + _frob(S2, H0))
@@ -272,10 +284,16 @@ def cg_minimize(H, S, C0: np.ndarray, *, mask: Optional[np.ndarray] = None, eta:
     that multiplies the gradient (Sec. II); the direction then follows -P G and
     beta uses the preconditioned products <P G, G - G_old> / <P G_old, G_old>.
     """
+    filt = _block_filters(filter_eps, row_blocks, col_blocks)
+    if filt is not None:
+        if precon is not None:
+            raise ValueError("filtering applies to the block-sparse method, preconditioning to the dense one")
+        return cg_minimize_filtered(H, S, C0, mask=mask, eta=eta, tol_grad=tol_grad, rel_tol=rel_tol,
+                                    max_iter=max_iter, filter_eps=filter_eps, row_blocks=row_blocks,
+                                    col_blocks=col_blocks, keep_history=keep_history, n_occupied=n_occupied)
     Heta = kim_shift(H, S, eta)
     C = project(np.array(C0, dtype=np.float64, copy=True), mask)
     n = C.shape[1] if n_occupied is None else int(n_occupied)
-    filt = _block_filters(filter_eps, row_blocks, col_blocks)
     E, G, HW, SW = _energy_and_gradient(Heta, S, C, mask, filt)
     pre = (lambda A: A) if precon is None else (lambda A: precon @ A)      # noqa: E731
     Z = pre(G)
@@ -324,6 +342,85 @@ def cg_minimize(H, S, C0: np.ndarray, *, mask: Optional[np.ndarray] = None, eta:
                     restarts=restarts, HW=HW, SW=SW, history=history)
 
 
+# ---------------------------------------------------------------- filtered method (Sec. V)
+def cg_minimize_filtered(H, S, C0: np.ndarray, *, mask: Optional[np.ndarray] = None, eta: float = 0.0,
+                         tol_grad: float = 1e-9, rel_tol: float = 0.0, max_iter: int = 10000,
+                         filter_eps: float = 0.0, row_blocks=None, col_blocks=None,
+                         keep_history: bool = True, n_occupied: Optional[int] = None) -> CGResult:
+    """CG on Eq. 4 with filtering of the block products (Sec. V), in the form that
+    forms each iteration only the products the line search needs.
+
+    Start: HC = f(H C), SC = f(S C), H_W = f(C^T HC), S_W = f(C^T SC).  Iteration:
+    HD = f(H D), SD = f(S D); X = f(C^T SD), Y = f(C^T HD), S2 = f(D^T SD),
+    H2 = f(D^T HD); the quartic of Eq. 4 along D has H1 = Y + Y^T, S1 = X + X^T
+    (the symmetric H, S make D^T HC = (C^T HD)^T); after the step x,
+    C += x D, HC += x HD, SC += x SD, H_W += x H1 + x^2 H2, S_W += x S1 + x^2 S2,
+    and the energy and projected gradient G = P[8 HC - 4 (HC S_W + SC H_W)] are
+    those of the maintained products.  f zeroes the atom blocks of Frobenius norm
+    below filter_eps (m x n products: basis x wavefunction blocks; n x n:
+    wavefunction x wavefunction blocks).  Line search, beta and stop rules as in
+    `cg_minimize`.  With filter_eps = 0 this is the plain method up to rounding.
+    """
+    f_mn = (lambda A: filter_blocks(A, row_blocks, col_blocks, filter_eps))   # noqa: E731
+    f_nn = (lambda A: filter_blocks(A, col_blocks, col_blocks, filter_eps))   # noqa: E731
+    Heta = kim_shift(H, S, eta)
+    C = project(np.array(C0, dtype=np.float64, copy=True), mask)
+    n = C.shape[1] if n_occupied is None else int(n_occupied)
+    HC, SC = f_mn(_dense(Heta @ C)), f_mn(_dense(S @ C))
+    HW, SW = f_nn(C.T @ HC), f_nn(C.T @ SC)
+
+    def energy_gradient():
+        E = 4.0 * float(np.trace(HW)) - 2.0 * _frob(SW, HW)
+        return E, project(8.0 * HC - 4.0 * (HC @ SW + SC @ HW), mask)
+
+    E, G = energy_gradient()
+    D = -G
+    steepest = True
+    gg = _frob(G, G)
+    history: List[dict] = []
+    status, converged, it, restarts = "not_converged", False, 0, 0
+    if np.sqrt(gg) <= tol_grad:
+        status, converged = "ok", True
+    while not converged and it < max_iter:
+        it += 1
+        HD, SD = f_mn(_dense(Heta @ D)), f_mn(_dense(S @ D))
+        X, Y = f_nn(C.T @ SD), f_nn(C.T @ HD)
+        S2, H2 = f_nn(D.T @ SD), f_nn(D.T @ HD)
+        H1, S1 = Y + Y.T, X + X.T
+        c = quartic_from_projections(HW, SW, H1, S1, H2, S2)
+        x, ok = line_minimum(c)
+        restart = False
+        if not ok or c[1] >= 0.0:
+            if steepest:
+                status = "no_line_min"
+                it -= 1
+                break
+            x, restart = 0.0, True
+            restarts += 1
+        C = C + x * D
+        HC, SC = HC + x * HD, SC + x * SD
+        HW, SW = HW + x * H1 + x * x * H2, SW + x * S1 + x * x * S2
+        E_old = E
+        E, G_new = energy_gradient()
+        gg_new = _frob(G_new, G_new)
+        beta = 0.0 if restart else max(0.0, _frob(G_new, G_new - G) / gg)
+        if keep_history:
+            history.append(dict(E=E, c=c.copy(), x=x, gnorm=np.sqrt(gg_new), beta=beta, restart=restart))
+        G, gg = G_new, gg_new
+        if np.sqrt(gg) <= tol_grad:
+            status, converged = "ok", True
+            break
+        if rel_tol > 0.0 and not restart and (E + E_old) != 0.0 and \
+                abs(2.0 * (E - E_old) / (E + E_old)) < rel_tol:
+            status, converged = "ok", True
+            break
+        D = -G + beta * D
+        steepest = (beta == 0.0)
+    return CGResult(C=C, energy=E, energy_band=E + 2.0 * eta * n, iterations=it,
+                    converged=converged, status=status, grad_norm=float(np.sqrt(gg)),
+                    restarts=restarts, HW=HW, SW=SW, history=history)
+
+
 # ---------------------------------------------------------------- kinetic preconditioning
 def kinetic_preconditioner(S, T, tau: float) -> np.ndarray:
     """P = (S + T / tau_T)^-1 (Eq. 7): T the kinetic-energy matrix, tau_T its scale
@@ -359,3 +456,123 @@ def cg_minimize_cholesky(H, S, C0: np.ndarray, *, eta: float = 0.0, **kw) -> CGR
     res.C = C
     res.energy_band = res.energy + 2.0 * eta * n
     return res
+
+
+# ---------------------------------------------------------------- block-sparse form
+# The same CG for a localized C held as a scipy.sparse BSR matrix (atom blocks,
+# Sec. III B: zero blocks not stored), for systems whose dense m x n matrices
+# are too large for the plain form above (the 4096-atom lattice).  Every
+# product is still recomputed from C and D at every iteration; the only
+# difference from `cg_minimize` is that the products of H and S with C and D
+# are scipy.sparse products and that the projected gradient is evaluated only
+# on the stored blocks of C (which is what the projection keeps).  No filtering
+# (threshold 0) and no preconditioner.
+def _bsr_on(P, data):
+    """A BSR matrix with the block structure of P and the given block values."""
+    return scipy.sparse.bsr_matrix((data, P.indices, P.indptr), shape=P.shape)
+
+
+def _nn(A, B) -> np.ndarray:
+    """A^T B as a dense n x n array (A, B sparse m x n)."""
+    return (A.T @ B).toarray()
+
+
+def _projected_gradient_blocks(P, HC, SC, HW, SW) -> np.ndarray:
+    """Blocks of G = 8 HC - 4 (HC S_W + SC H_W) at the stored blocks of P (Sec. III B).
+
+    Block row I of G needs row I of HC and SC (their stored WF blocks b) and the
+    rows b, columns a (a the WF blocks of P in row I) of the dense S_W, H_W.
+    """
+    rb, cb = P.blocksize
+    out = np.zeros_like(P.data)
+    for I in range(P.shape[0] // rb):
+        a_blk = P.indices[P.indptr[I]:P.indptr[I + 1]]
+        if a_blk.size == 0:
+            continue
+        h0, h1 = HC.indptr[I], HC.indptr[I + 1]
+        b_blk = HC.indices[h0:h1]
+        assert np.array_equal(b_blk, SC.indices[SC.indptr[I]:SC.indptr[I + 1]])
+        hc = HC.data[h0:h1].transpose(1, 0, 2).reshape(rb, -1)      # the blocks side by side: rb x (cb |b|)
+        sc = SC.data[h0:h1].transpose(1, 0, 2).reshape(rb, -1)
+        bcols = (b_blk[:, None] * cb + np.arange(cb)[None, :]).ravel()
+        acols = (a_blk[:, None] * cb + np.arange(cb)[None, :]).ravel()
+        g = -4.0 * (hc @ SW[np.ix_(bcols, acols)] + sc @ HW[np.ix_(bcols, acols)])
+        pos = np.searchsorted(b_blk, a_blk)                         # P's blocks inside HC's row
+        assert np.array_equal(b_blk[pos], a_blk), "C pattern outside H C's pattern"
+        g += 8.0 * HC.data[h0:h1][pos].transpose(1, 0, 2).reshape(rb, -1)
+        out[P.indptr[I]:P.indptr[I + 1]] = g.reshape(rb, a_blk.size, cb).transpose(1, 0, 2)
+    return out
+
+
+def cg_minimize_sparse(H, S, C0, *, eta: float = 0.0, tol_grad: float = 1e-9, rel_tol: float = 0.0,
+                       max_iter: int = 10000, keep_history: bool = True) -> CGResult:
+    """`cg_minimize` for a localized C given as a scipy.sparse BSR matrix (atom blocks).
+
+    H, S: unshifted Hamiltonian and overlap as BSR matrices with square atom
+    blocks; C0: BSR with blocks (basis atom) x (wavefunction atom), whose block
+    pattern is kept fixed (Sec. III B).  Same functional (Eq. 4 with the Kim
+    shift of Sec. II), gradient projection, quartic line search, Polak-Ribiere
+    beta and stop rules as `cg_minimize`; the returned CGResult holds C as a
+    BSR matrix and H_W, S_W as dense arrays.
+    """
+    Heta = scipy.sparse.bsr_matrix(H - eta * S, blocksize=H.blocksize)
+    S = scipy.sparse.bsr_matrix(S, blocksize=H.blocksize)
+    P = scipy.sparse.bsr_matrix(C0)
+    P.sort_indices()
+    C = _bsr_on(P, np.array(P.data, dtype=np.float64, copy=True))
+
+    def energy_gradient(C):
+        HC, SC = Heta @ C, S @ C
+        HC.sort_indices()
+        SC.sort_indices()
+        HW, SW = _nn(C, HC), _nn(C, SC)
+        n = HW.shape[0]
+        E = 4.0 * np.trace(HW) - 2.0 * _frob(SW, HW)
+        return E, _bsr_on(P, _projected_gradient_blocks(P, HC, SC, HW, SW)), HW, SW, n
+
+    E, G, HW, SW, n = energy_gradient(C)
+    D = _bsr_on(P, -G.data)
+    steepest = True
+    gg = float(np.sum(G.data * G.data))
+    history: List[dict] = []
+    status, converged, it, restarts = "not_converged", False, 0, 0
+    if np.sqrt(gg) <= tol_grad:
+        status, converged = "ok", True
+    t_prev = time.perf_counter()
+    while not converged and it < max_iter:
+        it += 1
+        HC, SC, HD, SD = Heta @ C, S @ C, Heta @ D, S @ D
+        c = quartic_from_projections(_nn(C, HC), _nn(C, SC), _nn(C, HD) + _nn(D, HC),
+                                     _nn(C, SD) + _nn(D, SC), _nn(D, HD), _nn(D, SD))
+        x, ok = line_minimum(c)
+        restart = False
+        if not ok or c[1] >= 0.0:
+            if steepest:
+                status = "no_line_min"
+                it -= 1
+                break
+            x, restart = 0.0, True
+            restarts += 1
+        C = _bsr_on(P, C.data + x * D.data)
+        E_old = E
+        E, G_new, HW, SW, n = energy_gradient(C)
+        gg_new = float(np.sum(G_new.data * G_new.data))
+        beta = 0.0 if restart else max(0.0, float(np.sum(G_new.data * (G_new.data - G.data))) / gg)
+        t_now = time.perf_counter()
+        if keep_history:   # `seconds`: wall time of the iteration (instrumentation only)
+            history.append(dict(E=E, c=c.copy(), x=x, gnorm=np.sqrt(gg_new), beta=beta, restart=restart,
+                                seconds=t_now - t_prev))
+        t_prev = t_now
+        G, gg = G_new, gg_new
+        if np.sqrt(gg) <= tol_grad:
+            status, converged = "ok", True
+            break
+        if rel_tol > 0.0 and not restart and (E + E_old) != 0.0 and \
+                abs(2.0 * (E - E_old) / (E + E_old)) < rel_tol:
+            status, converged = "ok", True
+            break
+        D = _bsr_on(P, -G.data + beta * D.data)
+        steepest = (beta == 0.0)
+    return CGResult(C=C, energy=E, energy_band=E + 2.0 * eta * n, iterations=it,
+                    converged=converged, status=status, grad_norm=float(np.sqrt(gg)),
+                    restarts=restarts, HW=HW, SW=SW, history=history)

@@ -373,3 +373,104 @@ def test_preconditioned_cg_reaches_the_same_minimum_faster(kinetic4):
     assert pre.iterations * 2 < plain.iterations
     # every step is a descent step: c1 = <dE/dC, D> < 0
     assert all(h["c"][1] < 0.0 for h in pre.history)
+
+
+# Preconditioned CG with P = (U^T U)^-1 is plain CG on the problem transformed by U
+# (Sec. II, Eq. 7 and the Cholesky reduction): with C = U^-1 C~ the functional is
+# the same, the gradient maps as G~ = U^-T G, so -G~ + beta D~ maps back to
+# -P G + beta D and the plain Polak-Ribiere ratio <G~, G~ - G~_old>/<G~_old, G~_old>
+# equals <P G, G - G_old>/<P G_old, G_old>.  Step lengths, energies and betas must
+# agree iteration by iteration.
+def _same_trajectory(a, b, k, rtol=1e-9):
+    assert len(a.history) == len(b.history) == k
+    for ha, hb in zip(a.history, b.history):
+        assert abs(ha["E"] - hb["E"]) <= 1e-12 * abs(hb["E"])
+        assert abs(ha["x"] - hb["x"]) <= rtol * abs(hb["x"])
+        assert abs(ha["beta"] - hb["beta"]) <= rtol * max(abs(hb["beta"]), 1e-3)
+
+
+def _transformed_plain_cg(H, S, C0, U, k):
+    """Plain CG on H~ = U^-T H U^-1, S~ = U^-T S U^-1 from C~0 = U C0 (oracle, no preconditioner)."""
+    Ui = scipy.linalg.solve_triangular(U, np.eye(U.shape[0]), lower=False)
+    Ht = Ui.T @ H @ Ui
+    St = Ui.T @ S @ Ui
+    return O.cg_minimize(0.5 * (Ht + Ht.T), 0.5 * (St + St.T), U @ C0, tol_grad=0.0, max_iter=k)
+
+
+@pytest.mark.parametrize("which", ["chain", "cube4"])
+def test_preconditioner_inverse_overlap_is_the_cholesky_path(which, request):
+    s, H, S, C0 = request.getfixturevalue(which)
+    k = 12
+    pre = O.cg_minimize(H, S, C0, tol_grad=0.0, max_iter=k, precon=np.linalg.inv(S))
+    chol = O.cg_minimize_cholesky(H, S, C0, tol_grad=0.0, max_iter=k)
+    _same_trajectory(pre, chol, k)
+
+
+def test_kinetic_preconditioner_is_plain_cg_on_the_transformed_problem(kinetic4):
+    s, H, S, C0, T = kinetic4
+    k = 10
+    U = scipy.linalg.cholesky(S + T / 5.0, lower=False)
+    pre = O.cg_minimize(H, S, C0, tol_grad=0.0, max_iter=k, precon=O.kinetic_preconditioner(S, T, 5.0))
+    ref = _transformed_plain_cg(H, S, C0, U, k)
+    _same_trajectory(pre, ref, k)
+    # the iterate maps back: C = U^-1 C~
+    Cb = scipy.linalg.solve_triangular(U, ref.C, lower=False)
+    assert np.max(np.abs(pre.C - Cb)) <= 1e-10 * np.max(np.abs(Cb))
+
+
+def test_wrong_preconditioned_beta_is_detected(kinetic4):
+    # the pin above separates the preconditioned Polak-Ribiere ratio from a
+    # plausible slip: <P G, G - G_old> / <G_old, G_old> (unpreconditioned denominator)
+    s, H, S, C0, T = kinetic4
+    k = 6
+    P = O.kinetic_preconditioner(S, T, 5.0)
+    U = scipy.linalg.cholesky(S + T / 5.0, lower=False)
+    ref = _transformed_plain_cg(H, S, C0, U, k)
+    C = C0.copy()
+    G = O.om_gradient(H, S, C)
+    D = -(P @ G)
+    hist = []
+    for it in range(k):
+        c = O.quartic_coefficients(H, S, C, D)
+        x, ok = O.line_minimum(c)
+        assert ok
+        C = C + x * D
+        E, Gn = O.om_energy(H, S, C), O.om_gradient(H, S, C)
+        Z = P @ Gn
+        beta = max(0.0, float(np.sum(Z * (Gn - G))) / float(np.sum(G * G)))   # the slip
+        hist.append(dict(E=E, x=x, beta=beta))
+        D = -Z + beta * D
+        G = Gn
+    with pytest.raises(AssertionError):
+        assert len(hist) == k
+        for ha, hb in zip(hist, ref.history):
+            assert abs(ha["E"] - hb["E"]) <= 1e-12 * abs(hb["E"])
+            assert abs(ha["x"] - hb["x"]) <= 1e-9 * abs(hb["x"])
+            assert abs(ha["beta"] - hb["beta"]) <= 1e-9 * max(abs(hb["beta"]), 1e-3)
+
+
+# ------------------------------------------------------------ block-sparse form of the oracle
+# The scipy.sparse form (used where dense m x n matrices do not fit, the 4096-atom
+# lattice) computes the same iterates as the plain dense form, which the tests above
+# pin; it must follow it step for step on localized systems.
+@pytest.mark.parametrize("name,k", [("cubic3_sparse", 25), ("cubic5_sparse", 12)])
+def test_block_sparse_form_follows_the_dense_oracle(name, k):
+    import sys
+    import os
+    sys.path.insert(0, os.path.dirname(__file__))
+    from _helpers import history_array, oracle_run, system
+    s = system(name)
+    ref = oracle_run(s, "sparse", tol_grad=0.0, max_iter=k)
+    sp = O.cg_minimize_sparse(s.H.to_bsr(), s.S.to_bsr(), s.C0.to_bsr(), eta=s.spec.eta, tol_grad=0.0,
+                              max_iter=k)
+    a = history_array(ref)
+    b = np.array([[h["E"], *h["c"], h["x"], h["gnorm"], h["beta"], float(h["restart"])] for h in sp.history])
+    assert a.shape == b.shape == (k, 10)
+    assert np.all(np.abs(a[:, 0] - b[:, 0]) <= 1e-12 * np.abs(a[:, 0]))            # E
+    assert np.all(np.abs(a[:, 6] - b[:, 6]) <= 1e-9 * np.abs(a[:, 6]))             # x
+    scale = np.max(np.abs(a[:, 1:6]), axis=0)
+    assert np.all(np.abs(a[:, 1:6] - b[:, 1:6]) <= 1e-10 * scale)                   # c0..c4
+    assert np.all(np.abs(a[:, 7] - b[:, 7]) <= 1e-9 * np.abs(a[:, 7]))             # ||G||
+    assert np.array_equal(a[:, 9], b[:, 9])
+    assert np.max(np.abs(sp.C.toarray() - ref.C)) <= 1e-12 * np.max(np.abs(ref.C))
+    assert abs(sp.energy - ref.energy) <= 1e-12 * abs(ref.energy)
