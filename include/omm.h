@@ -91,13 +91,19 @@ typedef struct {
   double eta;               /* Kim shift H -> H - eta S (OMM.Eta, Sec. II); default 0 */
   double tol_grad;          /* stop when ||G||_F <= tol_grad (projected real gradient); 1e-9 */
   double rel_tol;           /* stop when |2(E_n-E_{n-1})/(E_n+E_{n-1})| < rel_tol
-                               (OMM.RelTol, Table 1); <= 0 disables; default 0 */
+                               (OMM.RelTol, Table 1, whose default is 1e-9); <= 0
+                               disables; default 0 here: the default stop rule is the
+                               gradient norm, which bounds the distance to the minimum
+                               where a small energy change does not (set 1e-9 for the
+                               paper's rule) */
   int64_t max_iter;         /* CG iteration cap; default 10000 */
   double filter_eps;        /* block-sparse mode: product blocks with Frobenius norm
                                < eps are dropped (Sec. V); default 0 */
   int32_t precision;        /* omm_precision of the CG block products; default FP64 */
   int32_t fp64_refine_iters;/* mixed precision: FP64 iterations after the low-precision
-                               phase; <= 0 means FP64 until the stop rule; default 5 */
+                               phase; <= 0 means FP64 until the stop rule; default 5.
+                               A run that spends them without meeting the stop rule
+                               ends with OMM_ERR_NOT_CONVERGED (results readable) */
   double lowprec_rel_switch;/* mixed precision: relative energy change that ends the
                                low-precision phase (so does meeting the stop rule, a
                                failed steepest-descent line search, or lowprec_max_iter);
@@ -116,6 +122,16 @@ typedef struct {
                                + waves per group; a line whose shape this library
                                cannot launch is ignored and tuned again */
   void* hip_stream;         /* hipStream_t to run on; NULL: the library makes its own */
+  int32_t tile_group[3];    /* launch shape of the tile products (direction products,
+                               n x n projections, gradient): output tiles per wave
+                               (1, 2 or 4) and waves per output group (1, 2, 4 or 8,
+                               at most 4 with 4 tiles per wave or for the n x n
+                               projections at 2); 0 = chosen by the library (heuristic
+                               or autotuner).  A step given either value is not tuned.
+                               Any shape gives the same result up to the order of
+                               the sums; one shape gives bitwise repeatable results.
+                               Default 0 */
+  int32_t tile_split[3];
 } omm_options;
 
 /* Per-system results of omm_minimize. */
@@ -184,7 +200,7 @@ int omm_init_batch(omm_ctx** out, int32_t count, const omm_matrix* H, const omm_
                    const int64_t* n_occ, const int32_t* modes, const double* etas,
                    const omm_options* opt);
 
-/* Sets the initial guess of system `sys` (Sec. III C/D: random values inside the
+/* Sets the initial guess of system `sys` (Sec. III D: random values inside the
  * localization radius).  C0 is m x n with the same block rows as H; its block
  * pattern is the pattern kept fixed during minimization (Sec. III B) and must
  * include every column block once; in dense modes every block must be stored.
@@ -204,7 +220,7 @@ int omm_set_coeffs(omm_ctx* ctx, int32_t sys, const omm_matrix* C0);
  * Cholesky mode: OMM_ERR_NOT_SPD. */
 int omm_update_hs(omm_ctx* ctx, int32_t sys, const omm_matrix* H, const omm_matrix* S);
 
-/* Coefficient reuse across MD steps (Sec. III C; Table 1 OMM.Extrapolate),
+/* Coefficient reuse across MD steps (Sec. III D; Table 1 OMM.Extrapolate),
  * host memory only, no context: writes into out (to->nval doubles, in the
  * layout of to->val_off) the guess for the pattern `to` of the new geometry.
  * Blocks of `to` missing from `cur` start at zero (atoms that came within the
@@ -215,7 +231,7 @@ int omm_update_hs(omm_ctx* ctx, int32_t sys, const omm_matrix* H, const omm_matr
  * OMM_ERR_ARG, message in omm_last_error(NULL). */
 int omm_remap_coeffs(const omm_matrix* cur, const omm_matrix* prev, const omm_matrix* to, double* out);
 
-/* Restart file of C (Sec. III D, the m_write / m_read pair): omm_write_coeffs
+/* Restart file of C (Sec. III E, the m_write / m_read pair): omm_write_coeffs
  * stores the block structure and values of C (host memory) in a binary file
  * (magic "OMMCOEF1", little-endian: int32 nbrow, nbcol; int64 nnzb, nval;
  * int32 row_bsz[nbrow], col_bsz[nbcol]; int64 row_ptr[nbrow+1]; int32
@@ -254,6 +270,24 @@ int omm_set_preconditioner(omm_ctx* ctx, const omm_matrix* T, double tau);
  * per-system results (may be NULL).  Returns the worst per-system status.
  * Calling it again restarts from the coefficients set by omm_set_coeffs. */
 int omm_minimize(omm_ctx* ctx, omm_report* reports);
+
+/* omm_minimize for `count` independently built contexts in one go (the solver
+ * contract of Sec. III B, applied to many problems at once: separate
+ * structures, SCF snapshots).  Each context keeps its own systems, options,
+ * tuned kernels and outputs; their CG iterations are captured together into
+ * one hipGraph (the contexts dealt to 4 branch streams, so the kernels of
+ * different contexts may run concurrently), one replay runs graph_iters
+ * iterations of all of them (the smallest graph_iters of the list), and the
+ * host reads the states of all contexts once per replay.  Contexts that
+ * finish early idle (their kernels exit at once) until all are done.  The
+ * graph is kept by ctxs[0] and reused while the same contexts are passed in
+ * the same order and none of them has been re-planned.  The call runs on the
+ * stream of ctxs[0] and returns when every context is done; all contexts
+ * must live on the current device.  reports receives the reports of
+ * ctxs[0]'s systems, then ctxs[1]'s, ... (may be NULL).  Returns the worst
+ * status; messages in omm_last_error(ctxs[0]).  Contexts built together with
+ * omm_init_batch run faster still (one launch per kernel for all systems). */
+int omm_batch_minimize(omm_ctx* const* ctxs, int32_t count, omm_report* reports);
 
 /* rho = 2 C (2I - S_W) C^T (Eq. 5) of system `sys` at the current C, on the
  * block pattern of S and in the value layout (val_off) of the S passed at init:

@@ -1,8 +1,9 @@
 """Compile the HIP sources of the OMM library for gfx950 into an in-tree shared library.
 
-    python -m paper_2209_05934_amd.build
+    python -m paper_2209_05934_amd.build [source ...]
 
-writes paper_2209_05934_amd/lib/libomm_mi355x.so.  Every call recompiles.
+writes paper_2209_05934_amd/lib/libomm_mi355x.so.  Every call recompiles every
+source (or only the named ones, reusing the other objects of an earlier build).
 """
 
 from __future__ import annotations
@@ -51,7 +52,9 @@ def lib_path() -> str:
     return os.path.join(LIBDIR, LIBNAME)
 
 
-def build(verbose: bool = False, jobs: int = 0) -> str:
+def build(verbose: bool = False, jobs: int = 0, only: tuple = ()) -> str:
+    """Compile every source (or, with `only`, just those sources, reusing the other
+    objects of an earlier build) and link the library."""
     hipcc = _hipcc()
     objdir = os.path.join(LIBDIR, "obj")
     os.makedirs(objdir, exist_ok=True)
@@ -71,8 +74,13 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
         jobs = min(len(SOURCES), os.cpu_count() or 4)
     # longest first, so the slowest objects start at once
     order = sorted(SOURCES, key=lambda it: 0 if it[0] in PRODUCT_SOURCES else 1)
+    todo = [it for it in order if not only or it[0] in only]
     with ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(compile_one, order))
+        list(ex.map(compile_one, todo))
+    objs = [os.path.join(objdir, it[1]) for it in SOURCES]
+    missing = [o for o in objs if not os.path.exists(o)]
+    if missing:
+        raise RuntimeError(f"objects missing (build everything first): {missing}")
     out = lib_path()
     tmp = out + ".tmp"
     cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Wl,--no-undefined", "-o", tmp, *objs]
@@ -86,5 +94,6 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    # python -m paper_2209_05934_amd.build [source ...]: all sources, or only the named ones
+    build(verbose=True, only=tuple(sys.argv[1:]))
     sys.exit(0)

@@ -1,5 +1,5 @@
 // Reuse of the coefficient matrix between SCF and MD steps (arXiv 2209.05934,
-// Sec. III C and III D, Table 1 OMM.Extrapolate): the pattern update of a new
+// Sec. III D and III E, Table 1 OMM.Extrapolate): the pattern update of a new
 // geometry (blocks that left the localization radius are dropped, new ones
 // start at zero), linear extrapolation from the two previous MD steps, and
 // the restart file of C, whose pattern is corrected to the current one when it
@@ -135,18 +135,14 @@ int omm_write_coeffs(const char* path, const omm_matrix* C) {
   return ok ? OMM_OK : fail(std::string("write to ") + path + " failed");
 }
 
-int omm_read_coeffs(const char* path, const omm_matrix* to, double* out) {
-  omm::set_global_error("");
-  if (!path) return fail("path is NULL");
-  const std::string e = check(to, "to");
-  if (!e.empty()) return fail(e);
-  if (!out) return fail("out is NULL");
-  FILE* f = std::fopen(path, "rb");
+static int read_coeffs(const char* path, const omm_matrix* to, double* out) {
+  struct File {   // closed on every way out, exceptions included
+    FILE* f;
+    ~File() { if (f) std::fclose(f); }
+  } file{std::fopen(path, "rb")};
+  FILE* f = file.f;
   if (!f) return fail(std::string("cannot open ") + path);
-  auto bad = [&](const char* what) {
-    std::fclose(f);
-    return fail(std::string(path) + ": " + what);
-  };
+  auto bad = [&](const char* what) { return fail(std::string(path) + ": " + what); };
   char magic[8];
   int32_t dims[2];
   int64_t counts[2];
@@ -156,13 +152,18 @@ int omm_read_coeffs(const char* path, const omm_matrix* to, double* out) {
   if (dims[0] != to->nbrow || dims[1] != to->nbcol) return bad("block rows/columns differ from the target's");
   const int64_t nnzb = counts[0], nv = counts[1];
   if (nnzb < 0 || nnzb > (int64_t)dims[0] * dims[1] || nv < 0) return bad("corrupt counts");
-  omm_matrix src{};
-  std::vector<int32_t> rbs(dims[0]), cbs(dims[1]), ci(nnzb);
-  std::vector<int64_t> rp(dims[0] + 1), voff(nnzb);
-  std::vector<double> val(nv);
+  // block sizes first: they must be the target's, which bounds every size read after them
+  std::vector<int32_t> rbs(dims[0]), cbs(dims[1]);
   if (std::fread(rbs.data(), sizeof(int32_t), dims[0], f) != (size_t)dims[0] ||
-      std::fread(cbs.data(), sizeof(int32_t), dims[1], f) != (size_t)dims[1] ||
-      std::fread(rp.data(), sizeof(int64_t), dims[0] + 1, f) != (size_t)dims[0] + 1 ||
+      std::fread(cbs.data(), sizeof(int32_t), dims[1], f) != (size_t)dims[1])
+    return bad("truncated structure");
+  for (int i = 0; i < dims[0]; ++i)
+    if (rbs[i] != to->row_bsz[i]) return bad("block sizes differ from the target's");
+  for (int j = 0; j < dims[1]; ++j)
+    if (cbs[j] != to->col_bsz[j]) return bad("block sizes differ from the target's");
+  std::vector<int32_t> ci(nnzb);
+  std::vector<int64_t> rp(dims[0] + 1), voff(nnzb);
+  if (std::fread(rp.data(), sizeof(int64_t), dims[0] + 1, f) != (size_t)dims[0] + 1 ||
       std::fread(ci.data(), sizeof(int32_t), nnzb, f) != (size_t)nnzb)
     return bad("truncated structure");
   if (rp[0] != 0 || rp[dims[0]] != nnzb) return bad("corrupt row pointers");
@@ -175,9 +176,11 @@ int omm_read_coeffs(const char* path, const omm_matrix* to, double* out) {
       o += (int64_t)rbs[i] * cbs[ci[k]];
     }
   }
+  // the value count follows from the structure; only a file that agrees with it is read on
   if (o != nv) return bad("value count does not match the blocks");
+  std::vector<double> val(nv);
   if (std::fread(val.data(), sizeof(double), nv, f) != (size_t)nv) return bad("truncated values");
-  std::fclose(f);
+  omm_matrix src{};
   src.nbrow = dims[0];
   src.nbcol = dims[1];
   src.row_bsz = rbs.data();
@@ -192,6 +195,22 @@ int omm_read_coeffs(const char* path, const omm_matrix* to, double* out) {
   if (!es.empty()) return fail(es);
   if (!same_blocks(&src, to)) return fail(std::string(path) + ": block sizes differ from the target's");
   return remap(&src, nullptr, to, out);
+}
+
+int omm_read_coeffs(const char* path, const omm_matrix* to, double* out) {
+  omm::set_global_error("");
+  if (!path) return fail("path is NULL");
+  const std::string e = check(to, "to");
+  if (!e.empty()) return fail(e);
+  if (!out) return fail("out is NULL");
+  try {   // no C++ exception leaves the C ABI
+    return read_coeffs(path, to, out);
+  } catch (const std::bad_alloc&) {
+    omm::set_global_error(std::string(path) + ": host allocation failed");
+    return OMM_ERR_OOM;
+  } catch (...) {
+    return fail(std::string(path) + ": unreadable coefficient file");
+  }
 }
 
 }  // extern "C"

@@ -8,6 +8,7 @@
 // step, beta, stop flags) stays on the device, and the host only reads one
 // small state array per replay of a captured graph of several iterations.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -108,6 +109,9 @@ struct GPlan {   // grouped work list of one product step
 
 }  // namespace
 
+// a captured hipGraph of several contexts (omm_batch_minimize), kept by the first of them
+struct MultiGraph;
+
 struct omm_ctx {
   omm_options opt;
   hipStream_t stream = nullptr;
@@ -148,6 +152,11 @@ struct omm_ctx {
   int graph_iters = 0, graph_small = 0;
   bool tuned = false;
   std::string tune_log;
+  int dev = -1;                 // device the context lives on
+  uint64_t gen = 0;             // bumped whenever the context's kernels or buffers change
+  std::chrono::steady_clock::time_point solve_t0;
+  double setup_secs = 0.0;
+  std::unique_ptr<MultiGraph> multi;   // graph of omm_batch_minimize led by this context
   // timing
   bool timing = false;
   double kt_ms[3] = {0, 0, 0};
@@ -155,7 +164,23 @@ struct omm_ctx {
   std::vector<hipEvent_t> ev;
 };
 
+struct MultiGraph {
+  std::vector<omm_ctx*> ctxs;
+  std::vector<uint64_t> gens;
+  int K = 0;
+  hipGraph_t g = nullptr;
+  hipGraphExec_t e = nullptr;
+  ~MultiGraph() {
+    if (e) (void)hipGraphExecDestroy(e);
+    if (g) (void)hipGraphDestroy(g);
+  }
+};
+
 namespace {
+
+// generations are unique over the process: a context rebuilt at a freed one's
+// address never matches a graph captured for the old one
+std::atomic<uint64_t> g_generation{1};
 
 template <typename T>
 T* dalloc(omm_ctx* c, size_t n, bool prep) {
@@ -595,6 +620,7 @@ void ingest(omm_ctx* c, int count, const omm_matrix* H, const omm_matrix* S, con
 }
 
 void drop_graphs(omm_ctx* c) {
+  c->gen = g_generation.fetch_add(1);
   for (hipGraphExec_t* e : {&c->gexec, &c->gexec_small})
     if (*e) {
       (void)hipGraphExecDestroy(*e);
@@ -967,6 +993,27 @@ void pick_plans(omm_ctx* c) {
   c->b.s1 = c->G[0][c->sel[0]].view();
   c->b.s2 = c->G[1][c->sel[1]].view();
   c->b.grad = c->G[2][c->sel[2]].view();
+  // launch shapes given in the options replace the heuristic choice
+  for (int k = 0; k < 3; ++k) {
+    const int gw = c->opt.tile_group[k], sp = c->opt.tile_split[k];
+    if (gw <= 0 && sp <= 0) continue;
+    int sel = c->sel[k];
+    if (gw > 0) {
+      sel = -1;
+      for (int q = 0; q < NPLAN; ++q)
+        if (PLAN_NT[q] == gw) sel = q;
+      if (sel < 0) throw ArgError("tile_group must be 1, 2 or 4");
+    }
+    const GPlan& G = c->G[k][sel];
+    const int ks = sp > 0 ? sp : pick_ks(G.ngroups, G.nent, plan_ok(k, G.NT, 8) ? 8 : 4);
+    if (!(ks == 1 || ks == 2 || ks == 4 || ks == 8) || !plan_ok(k, G.NT, ks))
+      throw ArgError("tile_split must be 1, 2, 4 or 8 and fit the group width");
+    c->sel[k] = sel;
+    c->b.ks[k] = ks;
+  }
+  c->b.s1 = c->G[0][c->sel[0]].view();
+  c->b.s2 = c->G[1][c->sel[1]].view();
+  c->b.grad = c->G[2][c->sel[2]].view();
 }
 
 CGParams params(const omm_ctx* c);
@@ -1008,6 +1055,7 @@ void autotune(omm_ctx* c) {
   bool added = false;
   c->tune_log.clear();
   for (int cls = 0; cls < 3; ++cls) {
+    if (c->opt.tile_group[cls] > 0 || c->opt.tile_split[cls] > 0) continue;   // shape given by the caller
     const std::string key = tune_key(cls, (int)p, c->G[cls][0]);
     int found = -1;
     for (auto& kv : cache)
@@ -1220,8 +1268,9 @@ double predict_left(const SysState& now, const SysState& before, double tol_grad
   return std::max(0.0, left);
 }
 
-int minimize(omm_ctx* c, omm_report* reps) {
-  auto t0 = std::chrono::steady_clock::now();
+// Start of a solve: coefficients in place, states reset, start-up products,
+// tuning; the per-system phases are then PH_LOW/PH_FP64 (or done).
+void begin_solve(omm_ctx* c) {
   for (auto& s : c->sys)
     if (!s.has_c0) throw ArgError("__STATE__omm_set_coeffs must be called for every system before omm_minimize");
   if (!c->prepared) prepare(c);
@@ -1247,56 +1296,38 @@ int minimize(omm_ctx* c, omm_report* reps) {
   }
   init_sequence(c);
   if (c->opt.autotune && !c->tuned) autotune(c);
-  const bool use_graph = c->opt.graph_iters > 0 && !c->timing;
-  if (use_graph && !c->gexec) capture_graphs(c);
-  const int K = use_graph ? c->graph_iters : std::max(1, c->opt.graph_iters > 0 ? c->opt.graph_iters : 1);
-  int64_t steps = 0, reinits = 0, waited = 0;
-  const int64_t max_steps = c->opt.max_iter + 8 * (int64_t)K + 64;
-  std::vector<SysState> before(c->nsys);
-  int last_k = 0;
-  while (true) {
-    if (last_k > 0) std::copy(c->h_st, c->h_st + c->nsys, before.begin());
-    OMM_HIP(hipMemcpyAsync(c->h_st, c->d_st, sizeof(SysState) * c->nsys, hipMemcpyDeviceToHost, st));
-    OMM_HIP(hipStreamSynchronize(st));
-    if (c->timing) collect_timing(c);
-    bool all_done = true, any_init = false, any_active = false;
-    for (int i = 0; i < c->nsys; ++i) {
-      all_done &= c->h_st[i].phase == PH_DONE;
-      any_init |= c->h_st[i].phase == PH_INIT;
-      any_active |= (c->h_st[i].phase & (PH_LOW | PH_FP64)) != 0;
-    }
-    if (all_done) break;
-    // Systems that switch precision wait in the INIT phase; one re-initialization
-    // serves every waiting system, run when nothing else is active or after a
-    // few replays, so a batch does not pay one full-batch re-init per system.
-    if (any_init && (!any_active || ++waited >= 4)) {
-      if (++reinits > 4 * (int64_t)c->nsys + 4) throw DeviceError("phase switching did not settle");
-      waited = 0;
-      init_sequence(c);
-      continue;
-    }
-    if (steps >= max_steps) throw DeviceError("iteration loop exceeded its bound");
-    int k_run = K;
-    if (use_graph && c->gexec_small && last_k > 0) {
-      // the long graph unless every active system is predicted to finish within it
-      double left = 0.0;
-      for (int i = 0; i < c->nsys; ++i)
-        if ((c->h_st[i].phase & (PH_LOW | PH_FP64)) != 0)
-          left = std::max(left, predict_left(c->h_st[i], before[i], c->opt.tol_grad, c->opt.max_iter));
-      if (left < (double)K) k_run = c->graph_small;
-    }
-    if (use_graph) OMM_HIP(hipGraphLaunch(k_run == K ? c->gexec : c->gexec_small, st));
-    else
-      for (int k = 0; k < K; ++k) run_step(c, c->timing);
-    steps += k_run;
-    last_k = k_run;
+  c->solve_t0 = std::chrono::steady_clock::now();
+}
+
+struct Poll { bool all_done, any_init, any_active; };
+Poll poll_states(const omm_ctx* c) {
+  Poll p{true, false, false};
+  for (int i = 0; i < c->nsys; ++i) {
+    p.all_done &= c->h_st[i].phase == PH_DONE;
+    p.any_init |= c->h_st[i].phase == PH_INIT;
+    p.any_active |= (c->h_st[i].phase & (PH_LOW | PH_FP64)) != 0;
   }
-  // electron count at the final C
+  return p;
+}
+
+// largest predicted number of iterations any active system still needs
+double left_of(const omm_ctx* c, const std::vector<SysState>& before) {
+  double left = 0.0;
+  for (int i = 0; i < c->nsys; ++i)
+    if ((c->h_st[i].phase & (PH_LOW | PH_FP64)) != 0)
+      left = std::max(left, predict_left(c->h_st[i], before[i], c->opt.tol_grad, c->opt.max_iter));
+  return left;
+}
+
+// End of a solve: the electron count at the final C and the per-system reports.
+int end_solve(omm_ctx* c, omm_report* reps) {
+  hipStream_t st = c->stream;
   launch_traces(st, c->b, P64, PH_DONE, true, LS_REPORT, params(c));
   OMM_HIP(hipMemcpyAsync(c->h_st, c->d_st, sizeof(SysState) * c->nsys, hipMemcpyDeviceToHost, st));
   OMM_HIP(hipStreamSynchronize(st));
   c->ran = true;
-  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - c->solve_t0).count() +
+                      c->setup_secs;
   int worst = OMM_OK;
   auto rank = [](int s) {   // hard errors outrank soft ones
     return s == OMM_OK ? 0 : (s == OMM_ERR_ELECTRON_COUNT ? 1 : (s == OMM_ERR_NOT_CONVERGED ? 2 : 3));
@@ -1322,8 +1353,182 @@ int minimize(omm_ctx* c, omm_report* reps) {
       r.seconds = secs;
     }
   }
-  if (worst != OMM_OK) {
-    c->err = "at least one system ended with status " + std::string(omm_status_str(worst));
+  if (worst != OMM_OK) c->err = "at least one system ended with status " + std::string(omm_status_str(worst));
+  else c->err.clear();
+  return worst;
+}
+
+int minimize(omm_ctx* c, omm_report* reps) {
+  const auto t0 = std::chrono::steady_clock::now();
+  begin_solve(c);
+  c->setup_secs = std::chrono::duration<double>(c->solve_t0 - t0).count();
+  hipStream_t st = c->stream;
+  const bool use_graph = c->opt.graph_iters > 0 && !c->timing;
+  if (use_graph && !c->gexec) capture_graphs(c);
+  const int K = use_graph ? c->graph_iters : std::max(1, c->opt.graph_iters > 0 ? c->opt.graph_iters : 1);
+  int64_t steps = 0, reinits = 0, waited = 0;
+  const int64_t max_steps = c->opt.max_iter + 8 * (int64_t)K + 64;
+  std::vector<SysState> before(c->nsys);
+  int last_k = 0;
+  while (true) {
+    if (last_k > 0) std::copy(c->h_st, c->h_st + c->nsys, before.begin());
+    OMM_HIP(hipMemcpyAsync(c->h_st, c->d_st, sizeof(SysState) * c->nsys, hipMemcpyDeviceToHost, st));
+    OMM_HIP(hipStreamSynchronize(st));
+    if (c->timing) collect_timing(c);
+    const Poll p = poll_states(c);
+    if (p.all_done) break;
+    // Systems that switch precision wait in the INIT phase; one re-initialization
+    // serves every waiting system, run when nothing else is active or after a
+    // few replays, so a batch does not pay one full-batch re-init per system.
+    if (p.any_init && (!p.any_active || ++waited >= 4)) {
+      if (++reinits > 4 * (int64_t)c->nsys + 4) throw DeviceError("phase switching did not settle");
+      waited = 0;
+      init_sequence(c);
+      continue;
+    }
+    if (steps >= max_steps) throw DeviceError("iteration loop exceeded its bound");
+    int k_run = K;
+    // the long graph unless every active system is predicted to finish within it
+    if (use_graph && c->gexec_small && last_k > 0 && left_of(c, before) < (double)K) k_run = c->graph_small;
+    if (use_graph) OMM_HIP(hipGraphLaunch(k_run == K ? c->gexec : c->gexec_small, st));
+    else
+      for (int k = 0; k < K; ++k) run_step(c, c->timing);
+    steps += k_run;
+    last_k = k_run;
+  }
+  return end_solve(c, reps);
+}
+
+// ----------------------------------------------------------------- several contexts, one graph
+// The CG iterations of independently built contexts captured into one hipGraph:
+// the contexts are dealt round-robin to NBR branch streams forked from the
+// first context's stream, so the kernels of different contexts may run
+// concurrently, and K iterations of all of them are one graph launch.
+constexpr int NBR = 4;
+
+void capture_multi(omm_ctx* const* ctxs, int count, int K, MultiGraph& mg) {
+  hipStream_t origin = ctxs[0]->stream;
+  hipStream_t br[NBR] = {};
+  hipEvent_t fork = nullptr, join[NBR] = {};
+  const int nb = std::min(count, NBR);
+  std::vector<hipStream_t> saved(count);
+  auto cleanup = [&] {
+    for (int i = 0; i < count; ++i) ctxs[i]->stream = saved[i];
+    for (int b = 0; b < nb; ++b) {
+      if (join[b]) (void)hipEventDestroy(join[b]);
+      if (br[b]) (void)hipStreamDestroy(br[b]);
+    }
+    if (fork) (void)hipEventDestroy(fork);
+  };
+  for (int i = 0; i < count; ++i) saved[i] = ctxs[i]->stream;
+  try {
+    for (int b = 0; b < nb; ++b) {
+      OMM_HIP(hipStreamCreateWithFlags(&br[b], hipStreamNonBlocking));
+      OMM_HIP(hipEventCreateWithFlags(&join[b], hipEventDisableTiming));
+    }
+    OMM_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    OMM_HIP(hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal));
+    try {
+      OMM_HIP(hipEventRecord(fork, origin));
+      for (int b = 0; b < nb; ++b) OMM_HIP(hipStreamWaitEvent(br[b], fork, 0));
+      for (int i = 0; i < count; ++i) ctxs[i]->stream = br[i % nb];
+      for (int k = 0; k < K; ++k)
+        for (int i = 0; i < count; ++i) run_step(ctxs[i], false);
+      for (int b = 0; b < nb; ++b) {
+        OMM_HIP(hipEventRecord(join[b], br[b]));
+        OMM_HIP(hipStreamWaitEvent(origin, join[b], 0));
+      }
+    } catch (...) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(origin, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    OMM_HIP(hipStreamEndCapture(origin, &mg.g));
+    OMM_HIP(hipGraphInstantiate(&mg.e, mg.g, nullptr, nullptr, 0));
+  } catch (...) {
+    cleanup();
+    throw;
+  }
+  cleanup();
+}
+
+int batch_minimize(omm_ctx* const* ctxs, int count, omm_report* reps) {
+  omm_ctx* c0 = ctxs[0];
+  int dev0 = -1;
+  OMM_HIP(hipGetDevice(&dev0));
+  for (int i = 0; i < count; ++i)
+    if (ctxs[i]->dev != dev0) throw ArgError("every context must live on the current device");
+  // every context runs on the first one's stream for the call (restored at the end)
+  std::vector<hipStream_t> saved(count);
+  for (int i = 0; i < count; ++i) saved[i] = ctxs[i]->stream;
+  struct Restore {
+    omm_ctx* const* c; int n; std::vector<hipStream_t>& s;
+    ~Restore() { for (int i = 0; i < n; ++i) c[i]->stream = s[i]; }
+  } restore{ctxs, count, saved};
+  for (int i = 0; i < count; ++i) {
+    OMM_HIP(hipStreamSynchronize(saved[i]));
+    ctxs[i]->stream = c0->stream;
+  }
+  hipStream_t st = c0->stream;
+  for (int i = 0; i < count; ++i) {
+    const auto t0 = std::chrono::steady_clock::now();
+    begin_solve(ctxs[i]);
+    ctxs[i]->setup_secs = std::chrono::duration<double>(ctxs[i]->solve_t0 - t0).count();
+  }
+  int K = 1 << 30;
+  for (int i = 0; i < count; ++i) K = std::min(K, std::max(1, ctxs[i]->opt.graph_iters));
+  // the captured graph of these contexts, kept in the first one while none of them re-plans
+  std::vector<uint64_t> gens(count);
+  for (int i = 0; i < count; ++i) gens[i] = ctxs[i]->gen;
+  MultiGraph* mg = c0->multi.get();
+  if (!mg || mg->K != K || mg->ctxs != std::vector<omm_ctx*>(ctxs, ctxs + count) || mg->gens != gens) {
+    c0->multi.reset();
+    auto fresh = std::make_unique<MultiGraph>();
+    capture_multi(ctxs, count, K, *fresh);
+    fresh->ctxs.assign(ctxs, ctxs + count);
+    fresh->gens = gens;
+    fresh->K = K;
+    c0->multi = std::move(fresh);
+    mg = c0->multi.get();
+    for (int i = 0; i < count; ++i) ctxs[i]->stream = st;   // capture_multi restored the pre-capture streams
+  }
+  int64_t max_iter = 0;
+  for (int i = 0; i < count; ++i) max_iter = std::max(max_iter, ctxs[i]->opt.max_iter);
+  const int64_t max_steps = max_iter + 8 * (int64_t)K + 64;
+  int64_t steps = 0;
+  std::vector<int64_t> reinits(count, 0), waited(count, 0);
+  while (true) {
+    for (int i = 0; i < count; ++i)
+      OMM_HIP(hipMemcpyAsync(ctxs[i]->h_st, ctxs[i]->d_st, sizeof(SysState) * ctxs[i]->nsys,
+                             hipMemcpyDeviceToHost, st));
+    OMM_HIP(hipStreamSynchronize(st));
+    bool all_done = true, reinit = false;
+    for (int i = 0; i < count; ++i) {
+      const Poll p = poll_states(ctxs[i]);
+      all_done &= p.all_done;
+      if (p.any_init && (!p.any_active || ++waited[i] >= 4)) {
+        if (++reinits[i] > 4 * (int64_t)ctxs[i]->nsys + 4) throw DeviceError("phase switching did not settle");
+        waited[i] = 0;
+        init_sequence(ctxs[i]);
+        reinit = true;
+      }
+    }
+    if (all_done) break;
+    if (reinit) continue;
+    if (steps >= max_steps) throw DeviceError("iteration loop exceeded its bound");
+    OMM_HIP(hipGraphLaunch(mg->e, st));
+    steps += K;
+  }
+  int worst = OMM_OK;
+  auto rank = [](int s) {
+    return s == OMM_OK ? 0 : (s == OMM_ERR_ELECTRON_COUNT ? 1 : (s == OMM_ERR_NOT_CONVERGED ? 2 : 3));
+  };
+  int64_t r0 = 0;
+  for (int i = 0; i < count; ++i) {
+    const int rc = end_solve(ctxs[i], reps ? reps + r0 : nullptr);
+    r0 += ctxs[i]->nsys;
+    if (rank(rc) > rank(worst)) worst = rc;
   }
   return worst;
 }
@@ -1488,6 +1693,14 @@ int omm_init_batch(omm_ctx** out, int32_t count, const omm_matrix* H, const omm_
     g_last_init_error = "invalid option value";
     return OMM_ERR_ARG;
   }
+  for (int k = 0; k < 3; ++k) {
+    const int gw = o.tile_group[k], sp = o.tile_split[k];
+    if (!(gw == 0 || gw == 1 || gw == 2 || gw == 4) || !(sp == 0 || sp == 1 || sp == 2 || sp == 4 || sp == 8) ||
+        (gw > 0 && sp > 0 && !plan_ok(k, gw, sp))) {
+      g_last_init_error = "invalid tile_group / tile_split";
+      return OMM_ERR_ARG;
+    }
+  }
   // argument validation needs no device: do it before touching HIP
   {
     std::vector<MatDesc> dh(count), ds(count);
@@ -1523,10 +1736,12 @@ int omm_init_batch(omm_ctx** out, int32_t count, const omm_matrix* H, const omm_
   }
   c->opt = o;
   c->prec = (Prec)o.precision;
+  c->gen = g_generation.fetch_add(1);
   struct A { int count; const omm_matrix *H, *S; const int64_t* n; const int32_t* modes; const double* etas; } a{
       count, H, S, n_occ, modes, etas};
   int rc = guard(c, [](omm_ctx* cc, void* v) -> int {
     auto* q = (A*)v;
+    OMM_HIP(hipGetDevice(&cc->dev));
     if (cc->opt.hip_stream) cc->stream = (hipStream_t)cc->opt.hip_stream;
     else {
       OMM_HIP(hipStreamCreateWithFlags(&cc->stream, hipStreamNonBlocking));
@@ -1694,6 +1909,29 @@ int omm_minimize(omm_ctx* c, omm_report* reps) {
   if (!c) return OMM_ERR_ARG;
   struct A { omm_report* r; } a{reps};
   return guard(c, [](omm_ctx* cc, void* v) -> int { return minimize(cc, ((A*)v)->r); }, &a);
+}
+
+int omm_batch_minimize(omm_ctx* const* ctxs, int32_t count, omm_report* reports) {
+  if (!ctxs || count <= 0 || !ctxs[0]) {
+    g_last_init_error = "ctxs must hold count >= 1 contexts";
+    return OMM_ERR_ARG;
+  }
+  for (int i = 0; i < count; ++i) {
+    if (!ctxs[i]) {
+      ctxs[0]->err = "NULL context in the list";
+      return OMM_ERR_ARG;
+    }
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) {
+        ctxs[0]->err = "a context appears twice in the list";
+        return OMM_ERR_ARG;
+      }
+  }
+  struct A { omm_ctx* const* c; int n; omm_report* r; } a{ctxs, count, reports};
+  return guard(ctxs[0], [](omm_ctx*, void* v) -> int {
+    auto* q = (A*)v;
+    return batch_minimize(q->c, q->n, q->r);
+  }, &a);
 }
 
 // 2 C M C^T on S's pattern with M = ch H_W + cs (2I - S_W), for rho (Eq. 5) and rho_E

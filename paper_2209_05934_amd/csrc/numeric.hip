@@ -426,7 +426,9 @@ __device__ void beta_finish(SysState& S, int s, double gg, double a, double bo, 
     S.status = OMM_OK;
     S.phase = PH_DONE;
   } else if (S.phase == PH_FP64 && S.refine_left > 0 && --S.refine_left == 0) {
-    S.status = OMM_OK;
+    // the FP64 refinement iterations are spent without the stop rule holding:
+    // the run ends, but it has not converged (soft status, results readable)
+    S.status = OMM_ERR_NOT_CONVERGED;
     S.phase = PH_DONE;
   } else if (S.iter >= prm.max_iter) {
     S.status = OMM_ERR_NOT_CONVERGED;

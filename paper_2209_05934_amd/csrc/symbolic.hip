@@ -11,8 +11,6 @@
 // product-pattern bookkeeping of a block-sparse library; restricted outputs
 // (the gradient kept on C's pattern, rho on S's pattern, Sec. III B) reuse
 // the pair kernels with a given output pattern.
-#include <hipcub/hipcub.hpp>
-
 #include "kernels.hpp"
 
 namespace omm {
@@ -369,14 +367,75 @@ void rows_of(hipStream_t st, int nrows, const int* rp, int* rows) {
   OMM_HIP(hipGetLastError());
 }
 
+// Exclusive prefix sums of integer counts (row pointers, work-list offsets).
+// Three passes: each workgroup scans SCAN_ITEMS consecutive values per thread
+// (a thread's own running sum, then the workgroup's thread totals by a
+// Hillis-Steele scan in LDS) and writes its total; the totals are scanned the
+// same way (recursively); a last pass adds each workgroup's offset.  Integer
+// sums, so the result is exact whatever the order.
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_ITEMS = 8;
+constexpr int64_t SCAN_TILE = (int64_t)SCAN_THREADS * SCAN_ITEMS;
+
+template <typename I>
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_tiles(const I* __restrict__ in, I* __restrict__ out,
+                                                           I* __restrict__ totals, int64_t n) {
+  __shared__ I sh[SCAN_THREADS];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+  I v[SCAN_ITEMS];
+  I run = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    v[k] = base + k < n ? in[base + k] : (I)0;
+    run += v[k];
+  }
+  sh[threadIdx.x] = run;
+  __syncthreads();
+  for (int d = 1; d < SCAN_THREADS; d <<= 1) {   // inclusive scan of the thread totals
+    const I add = threadIdx.x >= (unsigned)d ? sh[threadIdx.x - d] : (I)0;
+    __syncthreads();
+    sh[threadIdx.x] += add;
+    __syncthreads();
+  }
+  I acc = threadIdx.x > 0 ? sh[threadIdx.x - 1] : (I)0;
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    if (base + k < n) out[base + k] = acc;
+    acc += v[k];
+  }
+  if (threadIdx.x == SCAN_THREADS - 1 && totals) totals[blockIdx.x] = sh[SCAN_THREADS - 1];
+}
+
+template <typename I>
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_add(I* __restrict__ out, const I* __restrict__ offs,
+                                                         int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * SCAN_TILE + threadIdx.x;
+  const I o = offs[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    const int64_t e = i + (int64_t)k * SCAN_THREADS;
+    if (e < n) out[e] += o;
+  }
+}
+
 template <typename I>
 static void excl_scan_impl(hipStream_t st, const I* in, I* out, int64_t n) {
   if (n <= 0) return;
-  size_t tmp = 0;
-  OMM_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, in, out, (int)n, st));
+  const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+  if (nb == 1) {
+    hipLaunchKernelGGL(k_scan_tiles<I>, dim3(1), dim3(SCAN_THREADS), 0, st, in, out, (I*)nullptr, n);
+    OMM_HIP(hipGetLastError());
+    return;
+  }
   void* buf = nullptr;
-  OMM_HIP(hipMallocAsync(&buf, tmp, st));
-  OMM_HIP(hipcub::DeviceScan::ExclusiveSum(buf, tmp, in, out, (int)n, st));
+  OMM_HIP(hipMallocAsync(&buf, 2 * nb * sizeof(I), st));
+  I* totals = (I*)buf;
+  I* offs = totals + nb;
+  hipLaunchKernelGGL(k_scan_tiles<I>, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, st, in, out, totals, n);
+  OMM_HIP(hipGetLastError());
+  excl_scan_impl<I>(st, totals, offs, nb);
+  hipLaunchKernelGGL(k_scan_add<I>, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, st, out, (const I*)offs, n);
+  OMM_HIP(hipGetLastError());
   OMM_HIP(hipFreeAsync(buf, st));
 }
 

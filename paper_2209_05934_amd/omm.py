@@ -42,6 +42,7 @@ class omm_options(C.Structure):
         ("lowprec_max_iter", C.c_int64), ("graph_iters", C.c_int32), ("history", C.c_int32),
         ("history_max", C.c_int32), ("ne_tol", C.c_double), ("autotune", C.c_int32),
         ("tune_cache", C.c_char_p), ("hip_stream", C.c_void_p),
+        ("tile_group", C.c_int32 * 3), ("tile_split", C.c_int32 * 3),
     ]
 
 
@@ -86,6 +87,7 @@ def load(path: Optional[str] = None) -> C.CDLL:
                                  C.POINTER(D), C.POINTER(omm_options)]),
         "omm_set_coeffs": (I32, [P, I32, MP]),
         "omm_minimize": (I32, [P, C.POINTER(omm_report)]),
+        "omm_batch_minimize": (I32, [C.POINTER(P), I32, C.POINTER(omm_report)]),
         "omm_density_matrix": (I32, [P, I32, P, I32]),
         "omm_energy_density": (I32, [P, I32, P, I32]),
         "omm_set_occupied": (I32, [P, I32, I64]),
@@ -114,6 +116,7 @@ def load(path: Optional[str] = None) -> C.CDLL:
 
 
 EXPORTED = ("omm_default_options", "omm_init", "omm_init_batch", "omm_set_coeffs", "omm_minimize",
+            "omm_batch_minimize",
             "omm_density_matrix", "omm_energy_density", "omm_get_coeffs", "omm_get_projected",
             "omm_get_history", "omm_query", "omm_set_occupied", "omm_set_preconditioner", "omm_update_hs",
             "omm_remap_coeffs", "omm_write_coeffs", "omm_read_coeffs", "omm_set_timing", "omm_kernel_times", "omm_time_step",
@@ -218,6 +221,15 @@ def omm_minimize(ctx, count: int = 1, soft_ok: bool = True):
     reps = (omm_report * count)()
     rc = load().omm_minimize(ctx, reps)
     _check(ctx, rc, soft_ok=soft_ok)
+    return rc, list(reps)
+
+
+def omm_batch_minimize(ctxs, counts, soft_ok: bool = True):
+    """ctxs: context handles; counts: systems of each (for the report array)."""
+    arr = (C.c_void_p * len(ctxs))(*[c.value for c in ctxs])
+    reps = (omm_report * int(sum(counts)))()
+    rc = load().omm_batch_minimize(arr, len(ctxs), reps)
+    _check(ctxs[0], rc, soft_ok=soft_ok)
     return rc, list(reps)
 
 

@@ -37,6 +37,8 @@ def options(**kw) -> L.omm_options:
     for k, v in kw.items():
         if not hasattr(o, k):
             raise KeyError(k)
+        if k in ("tile_group", "tile_split"):
+            v = (L.C.c_int32 * 3)(*v)
         setattr(o, k, v)
     return o
 

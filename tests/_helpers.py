@@ -50,3 +50,45 @@ def c_values(s, res):
 def history_array(res) -> np.ndarray:
     rows = [[h["E"], *h["c"], h["x"], h["gnorm"], h["beta"], float(h["restart"])] for h in res.history]
     return np.array(rows) if rows else np.zeros((0, 10))
+
+
+def hetero_system(seed: int = 9):
+    """A 27-atom system whose atoms carry 13, 9 or 5 orbitals (heterogeneous atom
+    blocks): the 13-orbital lattice with the last orbitals of some atoms removed
+    (rows and columns dropped from H and S, which stay symmetric and positive
+    definite), 2 wavefunctions per atom, C localized to radius 1.2 (block pattern
+    of the full lattice).  Returns (H, S, C0) as BlockMatrix plus the block sizes."""
+    from types import SimpleNamespace
+    from ommgen.systems import BlockMatrix
+    base = system("cubic3_sparse")
+    N, norb, nwf = base.natoms, base.spec.norb, base.spec.wf_per_atom
+    sizes = np.array([13, 9, 5])[np.arange(N) % 3].astype(np.int32)
+    keep = np.concatenate([a * norb + np.arange(sizes[a]) for a in range(N)])
+    H = base.H.to_dense()[np.ix_(keep, keep)]
+    S = base.S.to_dense()[np.ix_(keep, keep)]
+    C0 = base.C0.to_dense()[keep]
+    cpat = np.zeros((N, N), dtype=bool)
+    cpat[base.C0.block_rows(), base.C0.col_idx] = True
+    hpat = np.zeros((N, N), dtype=bool)
+    hpat[base.H.block_rows(), base.H.col_idx] = True
+
+    def pack(A, rbs, cbs, pat):
+        ro = np.concatenate([[0], np.cumsum(rbs)])
+        co = np.concatenate([[0], np.cumsum(cbs)])
+        rp, ci, vo, vals, off = [0], [], [], [], 0
+        for i in range(len(rbs)):
+            for j in np.nonzero(pat[i])[0]:
+                blk = A[ro[i]:ro[i + 1], co[j]:co[j + 1]]
+                ci.append(j)
+                vo.append(off)
+                vals.append(blk.ravel())
+                off += blk.size
+            rp.append(len(ci))
+        return BlockMatrix(row_bsz=np.asarray(rbs, np.int32), col_bsz=np.asarray(cbs, np.int32),
+                           row_ptr=np.asarray(rp, np.int64), col_idx=np.asarray(ci, np.int32),
+                           val_off=np.asarray(vo, np.int64), val=np.concatenate(vals))
+
+    wbs = np.full(N, nwf, np.int32)
+    return SimpleNamespace(H=pack(H, sizes, sizes, hpat), S=pack(S, sizes, sizes, hpat),
+                           C0=pack(C0, sizes, wbs, cpat), n=N * nwf, natoms=N, eta=base.spec.eta,
+                           row_blocks=sizes, col_blocks=wbs, m=int(sizes.sum()))

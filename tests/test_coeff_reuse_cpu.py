@@ -1,5 +1,5 @@
 """Coefficient reuse across SCF/MD steps (host functions of the C ABI, no GPU):
-pattern update, linear extrapolation and the restart file (Sec. III C-D).
+pattern update, linear extrapolation and the restart file (Sec. III D-E).
 Expected values come from dense NumPy arithmetic on the same block matrices."""
 
 import os

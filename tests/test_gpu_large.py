@@ -68,6 +68,12 @@ def test_cubic8_first_iterations_and_stationary_end():
     for i in range(k):
         assert abs(h[i, 0] - ho[i, 0]) <= 1e-11 * abs(ho[i, 0])
         assert abs(h[i, 6] - ho[i, 6]) <= 1e-9 * abs(ho[i, 6])
+        cs = np.max(np.abs(ho[i, 1:6]))
+        assert np.max(np.abs(h[i, 1:6] - ho[i, 1:6])) <= 1e-9 * cs
+    # element by element: C on its pattern and rho on S's pattern after the k iterations
+    assert np.max(np.abs(ctx.coeffs(0) - s.C0.gather_from_dense(ref.C))) <= 1e-9
+    rho_ref = s.S.gather_from_dense(O.density_matrix(ref.C, ref.SW))
+    assert np.max(np.abs(ctx.density_matrix(0) - rho_ref)) <= 1e-9
     ctx.close()
     # a longer run: the reported energy and gradient norm are those of the returned C
     # (evaluated here with plain NumPy from Eq. 4 and its derivative; the oracle is
@@ -137,3 +143,31 @@ def test_cubic16_full_size_properties():
     r3, h3, _ = run(precision=L.OMM_FP32, fp64_refine_iters=0, lowprec_max_iter=1000)
     assert len(h3) == k and np.all(h3[:, 10] == L.OMM_FP32)
     assert np.max(np.abs(h3[:, 0] - E)) / s.natoms <= 1e-5
+
+
+def test_cubic16_first_iterations_match_the_oracle():
+    """4096 atoms, filter 0: the first FP64 iterations against the oracle's block-sparse
+    form (energies, quartic coefficients, steps, gradient norms and betas stored by
+    tests/golden/make_cubic16.py, which calls only the oracle and the generator)."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "cubic16_first_iterations.json")
+    with open(path) as f:
+        gold = json.load(f)
+    ho = np.array(gold["history"])
+    k = len(ho)
+    s = system("cubic16_mixed", filter_eps=0.0)
+    assert [s.m, s.n, s.spec.seed] == [gold["system"]["N_basis"], gold["system"]["N_occ"], gold["system"]["seed"]]
+    ctx = Context([Problem(s.H, s.S, s.C0, s.n, L.OMM_BLOCK_SPARSE)], eta=s.spec.eta, max_iter=k)
+    rc, reps = ctx.minimize()
+    h = ctx.history(0)
+    assert len(h) == k
+    for i in range(k):
+        assert abs(h[i, 0] - ho[i, 0]) <= 1e-11 * abs(ho[i, 0])                 # E
+        cs = np.max(np.abs(ho[i, 1:6]))
+        assert np.max(np.abs(h[i, 1:6] - ho[i, 1:6])) <= 1e-10 * cs              # c0..c4
+        assert abs(h[i, 6] - ho[i, 6]) <= 1e-9 * abs(ho[i, 6])                  # x
+        assert abs(h[i, 7] - ho[i, 7]) <= 1e-9 * ho[i, 7]                       # ||G||
+        assert abs(h[i, 8] - ho[i, 8]) <= 1e-9 * max(ho[i, 8], 1e-3)            # beta
+        assert h[i, 9] == ho[i, 9]
+    ctx.close()

@@ -95,12 +95,43 @@ def test_sparse_converged_parity():
     ctx.close()
 
 
-def test_sparse_filtering_is_a_small_perturbation():
+def test_sparse_filtered_trajectory_parity():
+    # filtering (Sec. V) as the oracle defines it (`cg_minimize_filtered`): the
+    # direction products and n x n projections of each iteration are filtered and
+    # H C, S C, H_W, S_W follow as sums of the filtered products.  At 1e-3 about
+    # 0.3 % of the atom blocks of this system fall below the threshold.
     s = system("cubic5_sparse")
-    _, r0 = gpu_run(s, "sparse", max_iter=40)
-    _, r1 = gpu_run(s, "sparse", max_iter=40, filter_eps=1e-6)
-    # parity unpinned for eps > 0: only the size of the change is checked
-    assert abs(r1.energy - r0.energy) / s.natoms <= 1e-5
+    eps, k = 1e-3, 40
+    ctx, r = gpu_run(s, "sparse", max_iter=k, filter_eps=eps)
+    ref = oracle_run(s, "sparse", max_iter=k, tol_grad=1e-9, filter_eps=eps)
+    assert r.iters_total == k == ref.iterations
+    check_trajectory(ctx.history(0), ref)
+    assert np.max(np.abs(ctx.coeffs(0) - c_values(s, ref))) <= 1e-9
+    # the filter acts: the same iterations without it end elsewhere
+    _, r0 = gpu_run(s, "sparse", max_iter=k)
+    assert abs(r0.energy - r.energy) > 1e3 * 1e-11 * abs(r.energy)
+    ctx.close()
+
+
+# every launch shape of every tile-product step (one step varied at a time, the
+# others at the library's choice) follows the oracle's trajectory
+SHAPES = [(step, nt, ks) for step in range(3) for nt in (1, 2, 4) for ks in (1, 2, 4, 8)
+          if ks <= (4 if (nt >= 4 or (step == 1 and nt >= 2)) else 8)]
+
+
+@pytest.mark.parametrize("name,mode,k", [("cubic4_dense", "dense", 12), ("cubic5_sparse", "sparse", 12)])
+def test_every_launch_shape_follows_the_oracle(name, mode, k):
+    s = system(name)
+    ref = oracle_run(s, mode, max_iter=k, tol_grad=1e-9)
+    for step, nt, ks in SHAPES:
+        group, split = [0, 0, 0], [0, 0, 0]
+        group[step], split[step] = nt, ks
+        ctx, r = gpu_run(s, mode, max_iter=k, tile_group=group, tile_split=split)
+        z = ctx.sizes(0)
+        assert (z.tile_group[step], z.tile_split[step]) == (nt, ks)
+        check_trajectory(ctx.history(0), ref, k=k)
+        assert np.max(np.abs(ctx.coeffs(0) - c_values(s, ref))) <= 1e-9, (step, nt, ks)
+        ctx.close()
 
 
 def test_deterministic_and_graph_equals_eager():
@@ -128,11 +159,36 @@ def test_batch_equals_standalone():
         cs, rs = gpu_run(s, m, max_iter=300)
         # the batch and the standalone run may pick different split factors for the tile
         # products (they depend on the work-list length), i.e. a different summation
-        # order: equal up to rounding, not bitwise
+        # order: equal up to rounding, not bitwise (bitwise at one launch shape: below)
         assert reps[i].iters_total == rs.iters_total
         assert abs(reps[i].energy - rs.energy) <= 1e-12 * abs(rs.energy)
         assert np.max(np.abs(ctx.density_matrix(i) - cs.density_matrix(0))) <= 1e-10
         cs.close()
+    ctx.close()
+
+
+def test_batch_of_sixteen_uneven_systems_is_bitwise_standalone():
+    # 16 systems of the 64-system batch workload (27 to 343 atoms, half dense, half
+    # localized and filtered), at one launch shape: each system's sums run in the
+    # same order in the batch as alone, so every result is bitwise the same
+    from ommgen import batch_specs, make_system
+    specs = batch_specs()
+    pick = list(range(0, 64, 4))
+    systems = [make_system(specs[k]) for k in pick]
+    shape = dict(tile_group=[2, 1, 1], tile_split=[2, 2, 2])
+    probs = [Problem(s.H, s.S, s.C0, s.n, L.OMM_DENSE if s.spec.dense else L.OMM_BLOCK_SPARSE,
+                     eta=s.spec.eta) for s in systems]
+    opts = dict(max_iter=60, filter_eps=1e-6, **shape)
+    ctx = Context(probs, **opts)
+    rc, reps = ctx.minimize()
+    for i, (s, p) in enumerate(zip(systems, probs)):
+        one = Context([p], **opts)
+        rc1, r1 = one.minimize()
+        assert reps[i].iters_total == r1[0].iters_total
+        assert reps[i].energy == r1[0].energy and reps[i].grad_norm == r1[0].grad_norm
+        assert np.array_equal(ctx.history(i), one.history(0))
+        assert np.array_equal(ctx.density_matrix(i), one.density_matrix(0))
+        one.close()
     ctx.close()
 
 
@@ -260,4 +316,79 @@ def test_corrupt_tune_cache_is_tuned_again(tmp_path):
     codes = {k: int(v) for k, v in (line.split() for line in open(cache) if line.strip())}
     assert set(codes) == set(keys)
     assert all(c // 10 < 3 and c % 10 in (1, 2, 4, 8) for c in codes.values())
+    ctx.close()
+
+
+def test_batch_minimize_of_independent_contexts():
+    # contexts built one by one (different modes, a batch context among them, one in
+    # FP32) solved together through omm_batch_minimize: every result is bitwise the
+    # one the context gives alone, and the outputs of each context stay usable
+    cases = [("chain8", "dense", {}), ("cubic3_dense", "cholesky", {}),
+             ("cubic5_sparse", "sparse", dict(max_iter=80)), ("cubic3_dense", "dense", dict(precision=L.OMM_FP32))]
+
+    def build():
+        out = []
+        for name, mode, o in cases:
+            s = system(name)
+            out.append(Context([Problem(s.H, s.S, s.C0, s.n, MODES[mode], eta=s.spec.eta)], **o))
+        s1, s2 = system("chain8"), system("cubic3_sparse")
+        out.append(Context([Problem(s1.H, s1.S, s1.C0, s1.n, L.OMM_DENSE),
+                            Problem(s2.H, s2.S, s2.C0, s2.n, L.OMM_BLOCK_SPARSE, eta=s2.spec.eta)], max_iter=400))
+        return out
+
+    together = build()
+    for rep in range(2):    # the second call replays the kept graph
+        rc, reps = L.omm_batch_minimize([c.ctx for c in together], [c.count for c in together])
+        alone = build()
+        k = 0
+        for ct, ca in zip(together, alone):
+            rc1, r1 = ca.minimize()
+            for i in range(ct.count):
+                a, b = reps[k], r1[i]
+                assert a.iters_total == b.iters_total and a.status == b.status
+                assert a.energy == b.energy and a.grad_norm == b.grad_norm
+                assert np.array_equal(ct.history(i), ca.history(i))
+                assert np.array_equal(ct.density_matrix(i), ca.density_matrix(i))
+                k += 1
+            ca.close()
+    with pytest.raises(L.OmmError):
+        L.omm_batch_minimize([together[0].ctx, together[0].ctx], [1, 1])
+    for c in together:
+        c.close()
+
+
+@pytest.mark.parametrize("mode", ["dense", "sparse"])
+def test_heterogeneous_atom_blocks(mode):
+    # atoms with 13, 9 and 5 orbitals: block rows of different heights in both modes
+    from _helpers import hetero_system
+    import oracle as O
+    h = hetero_system()
+    H, S = h.H.to_dense(), h.S.to_dense()
+    if mode == "dense":   # every block of C0 stored
+        full = np.ones((h.natoms, h.natoms), dtype=bool)
+        C0d = h.C0.to_dense()
+        C0d[C0d == 0.0] = 0.01
+        ro = np.concatenate([[0], np.cumsum(h.row_blocks)])
+        co = np.concatenate([[0], np.cumsum(h.col_blocks)])
+        vals = [C0d[ro[i]:ro[i + 1], co[j]:co[j + 1]].ravel() for i in range(h.natoms) for j in range(h.natoms)]
+        from ommgen.systems import BlockMatrix
+        offs = np.concatenate([[0], np.cumsum([v.size for v in vals])[:-1]])
+        C0 = BlockMatrix(row_bsz=h.row_blocks, col_bsz=h.col_blocks,
+                         row_ptr=np.arange(0, h.natoms * h.natoms + 1, h.natoms, dtype=np.int64),
+                         col_idx=np.tile(np.arange(h.natoms, dtype=np.int32), h.natoms),
+                         val_off=offs.astype(np.int64), val=np.concatenate(vals))
+        mask, k, eta = None, None, 0.0
+    else:
+        C0, mask, k, eta = h.C0, h.C0.pattern_mask(), 60, h.eta
+    ref = O.cg_minimize(H, S, C0.to_dense(), mask=mask, eta=eta, tol_grad=1e-9, max_iter=k or 10000)
+    ctx = Context([Problem(h.H, h.S, C0, h.n, MODES[mode], eta=eta)], max_iter=k or 10000)
+    rc, reps = ctx.minimize()
+    check_trajectory(ctx.history(0), ref)
+    assert reps[0].iters_total == ref.iterations or (k is None and abs(reps[0].iters_total - ref.iterations) <= 1)
+    assert abs(reps[0].energy - ref.energy) / h.natoms <= 1e-10
+    assert np.max(np.abs(ctx.coeffs(0) - C0.gather_from_dense(ref.C))) <= 1e-9
+    assert np.max(np.abs(ctx.density_matrix(0) - h.S.gather_from_dense(O.density_matrix(ref.C, ref.SW)))) <= 1e-9
+    if mode == "dense":
+        w = scipy.linalg.eigh(H, S, eigvals_only=True)
+        assert abs(reps[0].energy - 2.0 * w[:h.n].sum()) / h.natoms <= 1e-10
     ctx.close()
