@@ -1,10 +1,16 @@
 #!/usr/bin/env python3
 """Throughput of the conjugate-gradient OMM hot path on one MI355X.
 
-A step is one whole solve of the workload: reset C to the initial guess (held
-in HBM), run CG to the stop rule through the C ABI, form the density matrix
-(Eq. 5) in device memory.  `value` = CG iterations per second over the timed
-steps.  Prints one JSON line.
+Default workload: the 4096-atom lattice (16x16x16 atoms x 13 orbitals, N_basis
+53248, N_occ 8192, C localized to radius 3.0, eta 1.5, filter 1e-6).  A step is
+a fixed number of CG iterations (20) from the initial guess held in HBM: C
+reset, the iterations through the C ABI, the density matrix (Eq. 5) into device
+memory.  `value` = FP64 CG iterations per second over the timed steps.  Beside
+it, for the block-sparse workloads, `to_accuracy` times the FP64, FP32 + FP64
+and BF16 + FP64 forms to the same stop rule (relative energy change < 1e-9)
+and gives each one's energy/atom error against the FP64 result, while the CPU
+oracle times one CG iteration of the same system in a child process.  Prints
+one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--workload NAME] [--precision fp64|fp32|bf16]
 """
@@ -47,7 +53,8 @@ WORKLOADS = {
                             "eta -0.25 (in the gap), filter 1e-6, 200 CG iterations"),
     "cubic16_mixed": dict(cfg="cubic16_mixed", mode="sparse", max_iter=20,
                           desc="16x16x16 lattice, 4096 atoms x 13 orbitals, N_basis 53248, N_occ 8192, "
-                               "atom-block sparse, C radius 3.0, eta 1.5, filter 1e-6, 20 CG iterations"),
+                               "atom-block sparse, C radius 3.0, eta 1.5, filter 1e-6, 20 CG iterations "
+                               "per step from the initial guess"),
 }
 
 BATCH_DESC = ("64 independent systems, n^3 cubic lattices with n uniform in 3..7 (27-343 atoms x 13 "
@@ -114,9 +121,9 @@ TIMING_REPS = 20                                          # back-to-back launche
 def parse():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cubic4_dense", choices=sorted(WORKLOADS) + ["batch64"])
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 10; 20 for the small workloads)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default 2; 3 for the small workloads)")
+    ap.add_argument("--workload", default="cubic16_mixed", choices=sorted(WORKLOADS) + ["batch64"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
     ap.add_argument("--max-iter", type=int, default=None)
     ap.add_argument("--graph-iters", type=int, default=16)
@@ -128,9 +135,17 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the heuristic work split of the tile products instead of timing the variants")
     ap.add_argument("--to-accuracy", action="store_true",
-                    help="sparse workloads: time FP64, FP32 + 5 FP64 and BF16 + 5 FP64 solves to the same "
-                         "stop rule (relative energy change < 1e-9) and report each energy/atom against FP64")
-    return ap.parse_args()
+                    help="only the time-to-accuracy comparison (FP64, FP32 + FP64, BF16 + FP64 to the stop rule "
+                         "|dE/E| < 1e-9), as its own JSON line")
+    ap.add_argument("--no-to-accuracy", action="store_true",
+                    help="skip the time-to-accuracy comparison of the block-sparse workloads")
+    args = ap.parse_args()
+    small = args.workload not in ("cubic16_mixed", "batch64")
+    if args.steps is None:
+        args.steps = 20 if small else 10
+    if args.warmup is None:
+        args.warmup = 3 if small else 2
+    return args
 
 
 def _scipy_csr(bm):
@@ -152,15 +167,8 @@ def _scipy_csr(bm):
                                    shape=(int(ro[-1]), int(co[-1])))
 
 
-def cpu_baseline(system, spec, mode, max_iter, budget_s, tau=0.0):
-    """The CPU oracle as it stands, on a bounded sample of the same workload: full
-    solves for the dense systems; for the block-sparse ones repeated two-iteration
-    samples from C0, since one solve runs far past the budget (H and S dense for
-    BLAS speed, as scipy.sparse above 20000 basis functions, where dense copies
-    would not fit)."""
+def _cpu_info():
     import platform
-    import numpy as np
-    import oracle as O
     threads, blas = os.cpu_count() or 1, "unknown"
     try:
         from threadpoolctl import threadpool_info
@@ -176,15 +184,18 @@ def cpu_baseline(system, spec, mode, max_iter, budget_s, tau=0.0):
             cpu = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), cpu)
     except OSError:
         pass
-    sparse = mode == "sparse"
-    if sparse and system.m > 20000:
-        H, S = _scipy_csr(system.H), _scipy_csr(system.S)
-    else:
-        H, S = system.H.to_dense(), system.S.to_dense()
+    return threads, blas, cpu
+
+
+def cpu_baseline(system, spec, mode, max_iter, budget_s, tau=0.0):
+    """The CPU oracle as it stands on a bounded sample of a dense workload: full
+    solves of the same system, as many as fit the time budget."""
+    import numpy as np
+    import oracle as O
+    threads, blas, cpu = _cpu_info()
+    H, S = system.H.to_dense(), system.S.to_dense()
     C0 = system.C0.to_dense()
-    mask = system.C0.pattern_mask() if sparse else None
-    per = 2 if sparse else max_iter
-    kw = dict(eta=spec.eta, tol_grad=1e-9, max_iter=per, keep_history=False)
+    kw = dict(eta=spec.eta, tol_grad=1e-9, max_iter=max_iter, keep_history=False)
     if tau > 0.0:
         kw["precon"] = O.kinetic_preconditioner(S, system.T.to_dense(), tau)
     iters, runs, t0 = 0, 0, time.perf_counter()
@@ -192,18 +203,75 @@ def cpu_baseline(system, spec, mode, max_iter, budget_s, tau=0.0):
         if mode == "cholesky":
             r = O.cg_minimize_cholesky(H, S, C0, **kw)
         else:
-            r = O.cg_minimize(H, S, C0, mask=mask, **kw)
+            r = O.cg_minimize(H, S, C0, **kw)
         iters += r.iterations
         runs += 1
         if time.perf_counter() - t0 >= budget_s or runs >= 200:
             break
     dt = time.perf_counter() - t0
-    what = (f"{runs} run(s) of the first {per} CG iterations from C0" if sparse
-            else f"{runs} full solve(s) of the same workload")
     return {"value": iters / dt, "unit": "CG iters/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{what} ({iters} CG iterations, {dt:.1f} s) with the NumPy/SciPy FP64 oracle, "
-                      f"every product recomputed each iteration",
+            "sample": f"{runs} full solve(s) of the same workload ({iters} CG iterations, {dt:.1f} s) with the "
+                      f"NumPy/SciPy FP64 oracle, every product recomputed each iteration",
             "cpu": cpu, "blas": blas}
+
+
+def cpu_leg_child(workload, out_path, budget_s):
+    """Child process of the block-sparse workloads: the oracle's block-sparse form
+    (scipy.sparse products, every product recomputed from C and D each
+    iteration) on the same system from the same C0, one BLAS thread: the start-up
+    evaluation, then CG iterations until the time budget is spent (at least
+    one).  Writes the JSON of the cpu_baseline object to out_path."""
+    import oracle as O
+    from ommgen import config_spec, make_system
+    wl = WORKLOADS[workload]
+    spec = config_spec(wl["cfg"])
+    system = make_system(spec)
+    threads, blas, cpu = _cpu_info()
+    H, S, C0 = system.H.to_bsr(), system.S.to_bsr(), system.C0.to_bsr()
+    t0 = time.perf_counter()
+    k = 1
+    while True:   # runs of 1, 2, 4 ... iterations: the iteration times come from the history
+        r = O.cg_minimize_sparse(H, S, C0, eta=spec.eta, tol_grad=0.0, max_iter=k)
+        if time.perf_counter() - t0 >= budget_s or k >= wl["max_iter"]:
+            break
+        k *= 2
+    secs = sum(h["seconds"] for h in r.history)
+    out = {"value": len(r.history) / secs, "unit": "CG iters/s", "cores": 1, "kind": "oracle",
+           "sample": f"{len(r.history)} CG iteration(s) of the same {system.natoms}-atom system from the same "
+                     f"C0 with the oracle's block-sparse form (scipy.sparse products, every product "
+                     f"recomputed from C and D each iteration, filter 0, one BLAS thread), {secs:.1f} s of "
+                     f"iterations (the start-up evaluation before them not counted; "
+                     f"{time.perf_counter() - t0:.0f} s of oracle time in all), run in a child process "
+                     f"beside the GPU legs",
+           "cpu": cpu, "blas": blas, "threads_available": os.cpu_count()}
+    with open(out_path, "w") as f:
+        json.dump(out, f)
+
+
+def start_cpu_leg(workload, budget_s):
+    import subprocess
+    out = os.path.join(tempfile.gettempdir(), f"omm_cpu_leg_{os.getpid()}.json")
+    env = dict(os.environ, OPENBLAS_NUM_THREADS="1", OMP_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    p = subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-leg", workload, out,
+                          str(budget_s)], env=env, stdout=subprocess.DEVNULL, stderr=subprocess.PIPE)
+    return p, out
+
+
+def finish_cpu_leg(handle, timeout_s=600.0):
+    p, out = handle
+    try:
+        _, err = p.communicate(timeout=timeout_s)
+    except Exception:
+        p.kill()
+        p.communicate()
+        return None
+    if p.returncode != 0 or not os.path.exists(out):
+        print(f"cpu leg failed: {err.decode(errors='replace')[-400:]}", file=sys.stderr)
+        return None
+    with open(out) as f:
+        res = json.load(f)
+    os.remove(out)
+    return res
 
 
 def batch_main(args):
@@ -290,25 +358,20 @@ def batch_main(args):
     print(json.dumps(out), flush=True)
 
 
-def accuracy_main(args):
-    """Time to the same accuracy: FP64, FP32 + 5 FP64 and BF16 + 5 FP64 solves of one sparse system to
-    the stop rule |2(E_n - E_n-1)/(E_n + E_n-1)| < 1e-9, each energy/atom against the FP64 one (the
-    mixed-precision target is 1e-5 Ha/atom).  Each solve is timed from a fresh context, minus the time
-    of a one-iteration solve of the same kind (set-up: symbolic phase, graph capture)."""
+def to_accuracy_legs(args, system, spec, Hv, Sv, C0v, stream):
+    """Time to the same accuracy: FP64, FP32 + FP64 and BF16 + FP64 solves of one
+    block-sparse system to the stop rule |2(E_n - E_n-1)/(E_n + E_n-1)| < 1e-9,
+    each energy/atom against the FP64 one (the mixed-precision target is 1e-5
+    Ha/atom).  A low-precision run switches to FP64 when its relative energy
+    change falls below its switch point (1e-9 FP32, 1e-5 BF16) and ends after
+    5 FP64 iterations or the stop rule.  Each solve is timed from a fresh context,
+    minus the time of a one-iteration solve of the same kind (set-up: symbolic
+    phase, graph capture)."""
     import torch
-    from ommgen import config_spec, make_system
     from paper_2209_05934_amd import omm as L
     from paper_2209_05934_amd.solver import Context, Problem
 
-    wl = WORKLOADS[args.workload]
-    if wl["mode"] != "sparse":
-        raise SystemExit("--to-accuracy applies to the block-sparse workloads")
-    spec = config_spec(wl["cfg"])
-    system = make_system(spec)
-    dev = torch.device("cuda:0")
-    stream = torch.cuda.current_stream(dev)
-    Hv, Sv, C0v = (torch.from_numpy(a).to(dev) for a in (system.H.val, system.S.val, system.C0.val))
-    max_iter = args.max_iter or 20000
+    max_iter = 20000
     cache = os.path.join(tempfile.gettempdir(), f"omm_tune_{os.getpid()}.txt")
     prec_of = {"fp64": L.OMM_FP64, "fp32": L.OMM_FP32, "bf16": L.OMM_BF16}
 
@@ -334,7 +397,8 @@ def accuracy_main(args):
         t1, _ = solve(prec, 1)
         tn, r = solve(prec, max_iter)
         res[prec] = {"seconds": tn - t1, "iters": int(r.iters_total), "iters_fp64": int(r.iters_fp64),
-                     "energy_per_atom": r.energy / system.natoms, "status": L.omm_status_str(r.status)}
+                     "energy_per_atom": r.energy / system.natoms, "grad_norm": r.grad_norm,
+                     "status": L.omm_status_str(r.status)}
         print(f"{prec}: {res[prec]['iters']} iterations in {res[prec]['seconds']:.2f} s", file=sys.stderr,
               flush=True)
     e64 = res["fp64"]["energy_per_atom"]
@@ -347,6 +411,23 @@ def accuracy_main(args):
         os.remove(cache)
     except OSError:
         pass
+    return res
+
+
+def accuracy_main(args):
+    """Only the time-to-accuracy comparison, as its own JSON line."""
+    import torch
+    from ommgen import config_spec, make_system
+
+    wl = WORKLOADS[args.workload]
+    if wl["mode"] != "sparse":
+        raise SystemExit("--to-accuracy applies to the block-sparse workloads")
+    spec = config_spec(wl["cfg"])
+    system = make_system(spec)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    Hv, Sv, C0v = (torch.from_numpy(a).to(dev) for a in (system.H.val, system.S.val, system.C0.val))
+    res = to_accuracy_legs(args, system, spec, Hv, Sv, C0v, stream)
     out = {
         "metric": METRIC, "value": res["fp32"]["cg_iters_per_s"], "unit": "CG iters/s", "n_gpus": 1,
         "steps": 1, "warmup": 1, "ms_per_step": res["fp32"]["seconds"] * 1e3, "higher_is_better": True,
@@ -361,6 +442,9 @@ def accuracy_main(args):
 
 
 def main():
+    if len(sys.argv) == 5 and sys.argv[1] == "--cpu-leg":   # child process of the CPU leg
+        cpu_leg_child(sys.argv[2], sys.argv[3], float(sys.argv[4]))
+        return
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -487,6 +571,14 @@ def main():
                      "alg_bytes_per_launch": sz.bytes_alg_step[k],
                      "step_us": {names[i]: avg_ms[i] * 1e3 for i in range(3)}})
 
+    sparse = wl["mode"] == "sparse"
+    cpu_leg = None
+    if sparse and not args.no_cpu_baseline:    # the oracle runs beside the GPU legs below
+        cpu_leg = start_cpu_leg(args.workload, args.cpu_seconds)
+    to_acc = None
+    if sparse and not args.no_to_accuracy:
+        to_acc = to_accuracy_legs(args, system, spec, Hv, Sv, C0v, stream)
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -515,10 +607,13 @@ def main():
         "status": LL.omm_status_str(last.status),
         "output_call_ms": outputs_ms,
         "plain_cg": plain_cg,
+        "to_accuracy": to_acc,
         "roofline": roof,
         "cpu_baseline": None,
     }
-    if not args.no_cpu_baseline:
+    if cpu_leg is not None:
+        out["cpu_baseline"] = finish_cpu_leg(cpu_leg)
+    elif not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(system, spec, wl["mode"], max_iter, args.cpu_seconds, tau)
     ctx.close()
     print(json.dumps(out), flush=True)
