@@ -40,5 +40,6 @@ from .omm import (  # noqa: F401
     electron_count,
     exact_band_energy,
     filter_blocks,
+    upper_mirror,
     CGResult,
 )

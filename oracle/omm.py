@@ -40,8 +40,12 @@ Readings where the paper is silent:
   H D, S D and the n x n projections C^T S D, C^T H D, D^T S D, D^T H D, and
   filters each of them (atom blocks of Frobenius norm < eps set to zero); H C,
   S C, H_W and S_W are formed and filtered once from C0 and afterwards follow
-  the line steps as exact sums of those filtered products.  C, D, G, H and S
-  are never filtered.  With eps = 0 this is the plain method.
+  the line steps as exact sums of those filtered products.  The n x n products
+  that are symmetric without filtering (H_W, S_W, D^T H D, D^T S D) are kept
+  symmetric, as in symmetric block storage: their blocks on and above the
+  block diagonal are formed and filtered, each block below is the transpose of
+  its mirror.  C, D, G, H and S are never filtered.  With eps = 0 this is the
+  plain method.
 """
 
 from __future__ import annotations
@@ -343,6 +347,13 @@ def cg_minimize(H, S, C0: np.ndarray, *, mask: Optional[np.ndarray] = None, eta:
 
 
 # ---------------------------------------------------------------- filtered method (Sec. V)
+def upper_mirror(A: np.ndarray) -> np.ndarray:
+    """The symmetric matrix holding A's upper triangle (diagonal included): what a
+    symmetric product keeps when only its blocks on and above the block diagonal
+    are stored (blocks are contiguous, so that is the element-wise upper triangle)."""
+    return np.triu(A) + np.triu(A, 1).T
+
+
 def cg_minimize_filtered(H, S, C0: np.ndarray, *, mask: Optional[np.ndarray] = None, eta: float = 0.0,
                          tol_grad: float = 1e-9, rel_tol: float = 0.0, max_iter: int = 10000,
                          filter_eps: float = 0.0, row_blocks=None, col_blocks=None,
@@ -350,10 +361,13 @@ def cg_minimize_filtered(H, S, C0: np.ndarray, *, mask: Optional[np.ndarray] = N
     """CG on Eq. 4 with filtering of the block products (Sec. V), in the form that
     forms each iteration only the products the line search needs.
 
-    Start: HC = f(H C), SC = f(S C), H_W = f(C^T HC), S_W = f(C^T SC).  Iteration:
-    HD = f(H D), SD = f(S D); X = f(C^T SD), Y = f(C^T HD), S2 = f(D^T SD),
-    H2 = f(D^T HD); the quartic of Eq. 4 along D has H1 = Y + Y^T, S1 = X + X^T
-    (the symmetric H, S make D^T HC = (C^T HD)^T); after the step x,
+    Start: HC = f(H C), SC = f(S C), H_W = u(f(C^T HC)), S_W = u(f(C^T SC)).
+    Iteration: HD = f(H D), SD = f(S D); X = f(C^T SD), Y = f(C^T HD),
+    S2 = u(f(D^T SD)), H2 = u(f(D^T HD)); the quartic of Eq. 4 along D has
+    H1 = Y + Y^T, S1 = X + X^T (the symmetric H, S make D^T HC = (C^T HD)^T);
+    u keeps the products that are symmetric without filtering symmetric
+    (`upper_mirror`, after the block filter), so H_W and S_W stay symmetric;
+    after the step x,
     C += x D, HC += x HD, SC += x SD, H_W += x H1 + x^2 H2, S_W += x S1 + x^2 S2,
     and the energy and projected gradient G = P[8 HC - 4 (HC S_W + SC H_W)] are
     those of the maintained products.  f zeroes the atom blocks of Frobenius norm
@@ -363,11 +377,12 @@ def cg_minimize_filtered(H, S, C0: np.ndarray, *, mask: Optional[np.ndarray] = N
     """
     f_mn = (lambda A: filter_blocks(A, row_blocks, col_blocks, filter_eps))   # noqa: E731
     f_nn = (lambda A: filter_blocks(A, col_blocks, col_blocks, filter_eps))   # noqa: E731
+    f_sym = (lambda A: upper_mirror(f_nn(A)))                                # noqa: E731
     Heta = kim_shift(H, S, eta)
     C = project(np.array(C0, dtype=np.float64, copy=True), mask)
     n = C.shape[1] if n_occupied is None else int(n_occupied)
     HC, SC = f_mn(_dense(Heta @ C)), f_mn(_dense(S @ C))
-    HW, SW = f_nn(C.T @ HC), f_nn(C.T @ SC)
+    HW, SW = f_sym(C.T @ HC), f_sym(C.T @ SC)
 
     def energy_gradient():
         E = 4.0 * float(np.trace(HW)) - 2.0 * _frob(SW, HW)
@@ -385,7 +400,7 @@ def cg_minimize_filtered(H, S, C0: np.ndarray, *, mask: Optional[np.ndarray] = N
         it += 1
         HD, SD = f_mn(_dense(Heta @ D)), f_mn(_dense(S @ D))
         X, Y = f_nn(C.T @ SD), f_nn(C.T @ HD)
-        S2, H2 = f_nn(D.T @ SD), f_nn(D.T @ HD)
+        S2, H2 = f_sym(D.T @ SD), f_sym(D.T @ HD)
         H1, S1 = Y + Y.T, X + X.T
         c = quartic_from_projections(HW, SW, H1, S1, H2, S2)
         x, ok = line_minimum(c)

@@ -1186,6 +1186,7 @@ void init_sequence(omm_ctx* c) {
   const CGParams prm = params(c);
   launch_s1(s, b, P64, PH_INIT, true);
   launch_s2(s, b, P64, PH_INIT, true);
+  launch_mirror_w(s, b, PH_INIT);
   launch_traces(s, b, P64, PH_INIT, true, LS_INIT, prm);
   launch_grad(s, b, P64, PH_INIT, true);
   if (b.P) launch_precon(s, b, PH_INIT);

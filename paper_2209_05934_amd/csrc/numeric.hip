@@ -546,6 +546,35 @@ __global__ __launch_bounds__(256) void k_update_d(int nc, const int* __restrict_
   }
 }
 
+// H_W and S_W as formed at start-up are made exactly symmetric from their upper
+// triangle (the symmetric products keep the blocks on and above the block
+// diagonal): a tile below the diagonal becomes the transpose of its mirror, and
+// inside a diagonal tile each element below the diagonal takes its mirror
+// element.  Only elements below the diagonal are written, only elements on or
+// above it are read.  One wave per n x n tile, four elements per lane.
+__global__ __launch_bounds__(256) void k_mirror_w(int ntw, int woff, const int* __restrict__ upd_sys,
+                                                const int* __restrict__ tw_row, const int* __restrict__ tw_col,
+                                                const int* __restrict__ wtr, const SysState* __restrict__ st,
+                                                int mask, double* __restrict__ H0, double* __restrict__ S0) {
+  const int t = blockIdx.x * 4 + wave_id();
+  if (t >= ntw) return;
+  const int s = upd_sys ? upd_sys[woff + t] : 0;
+  if (!on(st, s, mask)) return;
+  const int rt = tw_row[t], ct = tw_col[t];
+  if (rt < ct) return;
+  const int lane = threadIdx.x & 63;
+  const int r = lane >> 2, c0 = (lane & 3) * 4;
+  const size_t src = (size_t)(rt == ct ? t : wtr[t]) * TE;
+  const size_t dst = (size_t)t * TE;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int c = c0 + i;
+    if (rt == ct && r <= c) continue;
+    H0[dst + r * 16 + c] = H0[src + c * 16 + r];
+    S0[dst + r * 16 + c] = S0[src + c * 16 + r];
+  }
+}
+
 __global__ void k_init_finish(SysState* __restrict__ st, int nsys) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nsys) return;
@@ -766,6 +795,12 @@ void launch_update_d(hipStream_t s, const Bufs& b, Prec prec, int mask, bool ini
   else
     LAUNCH((k_update_d<bf16, true>), grid, dim3(256), s, b.n_tc, us, b.info, b.st, mask, b.D, b.G,
            (const double*)nullptr, b.Gold, (bf16*)b.Dl, b.gpart, (const double*)nullptr, b.hist, prm, in);
+}
+
+void launch_mirror_w(hipStream_t s, const Bufs& b, int mask) {
+  if (b.n_tw <= 0) return;
+  LAUNCH(k_mirror_w, waves_grid(b.n_tw), dim3(256), s, b.n_tw, b.n_tc + b.n_thc, b.nsys > 1 ? b.upd_sys : nullptr,
+         b.tw_row, b.tw_col, b.w_tr, b.st, mask, b.H0, b.S0);
 }
 
 void launch_init_finish(hipStream_t s, const Bufs& b) {

@@ -13,6 +13,9 @@ namespace {
 // S2 = D^T S D and H2 = D^T H D are symmetric: they are formed and stored for
 // tiles on or above the diagonal only, and readers take a tile below it as the
 // transpose of its mirror (X and Y are not symmetric and are formed in full).
+// Inside a diagonal tile the elements below the diagonal take their mirror
+// elements (after the block filter), so the kept product is exactly the
+// symmetric matrix of its upper triangle, filtered or not.
 template <typename TI, typename TM, typename TO, int NPROD, int KS, int NT, bool ROLL>
 __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s2(
     GroupView P, const int* __restrict__ orow, const int* __restrict__ ocol, const SysInfo* __restrict__ info, const SysState* __restrict__ st, int mask, const TI* __restrict__ Cm,
@@ -101,6 +104,15 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s2(
       const uint8_t* cs = wseg + 32 * (size_t)ocol[t];
 #pragma unroll
       for (int a = 0; a < NPROD; ++a) filter_tile(acc[a * NT + u], lane, rs, cs, e2);
+    }
+    if (NPROD == 4 && orow[t] == ocol[t]) {   // diagonal tile of S2, H2: upper triangle mirrored
+#pragma unroll
+      for (int a = 2; a < 4; ++a) {
+        const V tr = transposed_tile(acc[a * NT + u], lane);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (Lay<V>::row(lane >> 4, r) > (lane & 15)) acc[a * NT + u][r] = tr[r];
+      }
     }
     const size_t o = (size_t)t * TE;
 #pragma unroll

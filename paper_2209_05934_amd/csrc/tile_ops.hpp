@@ -104,6 +104,27 @@ __device__ __forceinline__ int out_off(int lane, int r) { return Lay<V>::row(lan
 template <typename V>
 __device__ __forceinline__ int out_off_t(int lane, int r) { return (lane & 15) * 16 + Lay<V>::row(lane >> 4, r); }
 
+// The transpose of an accumulator tile, in the same register layout: lane
+// (j, q) register r receives element (j, row) with row = Lay<V>::row(q, r),
+// which sits in lane row + 16 q' register r' with Lay<V>::row(q', r') = j.
+// Shuffles of the whole wave (call with every lane active).
+template <typename V>
+__device__ __forceinline__ V transposed_tile(const V& a, int lane) {
+  const int j = lane & 15, q = lane >> 4;
+  constexpr bool F64 = sizeof(a[0]) == 8;
+  const int qs = F64 ? (j & 3) : (j >> 2);   // Lay<d4>::row(q, r) = 4r + q, Lay<f4>::row(q, r) = 4q + r
+  const int rs = F64 ? (j >> 2) : (j & 3);
+  V out;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int src = Lay<V>::row(q, r) + 16 * qs;
+    const auto v0 = __shfl(a[0], src, 64), v1 = __shfl(a[1], src, 64);
+    const auto v2 = __shfl(a[2], src, 64), v3 = __shfl(a[3], src, 64);
+    out[r] = rs == 0 ? v0 : (rs == 1 ? v1 : (rs == 2 ? v2 : v3));
+  }
+  return out;
+}
+
 // an FP64 accumulator tile as the B operand of the next product, through a
 // 16x16 LDS tile owned by the calling wave (LDS operations of one wave
 // complete in order, so the reads see the writes)

@@ -383,7 +383,9 @@ def test_heterogeneous_atom_blocks(mode):
     ref = O.cg_minimize(H, S, C0.to_dense(), mask=mask, eta=eta, tol_grad=1e-9, max_iter=k or 10000)
     ctx = Context([Problem(h.H, h.S, C0, h.n, MODES[mode], eta=eta)], max_iter=k or 10000)
     rc, reps = ctx.minimize()
-    check_trajectory(ctx.history(0), ref)
+    # the converging dense run: step lengths near the minimum carry less relative
+    # precision (c1 -> 0), so its first ten steps are compared, as for the other dense runs
+    check_trajectory(ctx.history(0), ref, k=min(10, ref.iterations) if mode == "dense" else None)
     assert reps[0].iters_total == ref.iterations or (k is None and abs(reps[0].iters_total - ref.iterations) <= 1)
     assert abs(reps[0].energy - ref.energy) / h.natoms <= 1e-10
     assert np.max(np.abs(ctx.coeffs(0) - C0.gather_from_dense(ref.C))) <= 1e-9

@@ -474,3 +474,46 @@ def test_block_sparse_form_follows_the_dense_oracle(name, k):
     assert np.array_equal(a[:, 9], b[:, 9])
     assert np.max(np.abs(sp.C.toarray() - ref.C)) <= 1e-12 * np.max(np.abs(ref.C))
     assert abs(sp.energy - ref.energy) <= 1e-12 * abs(ref.energy)
+
+
+# ------------------------------------------------------------ filtering definition (Sec. V)
+def test_filtered_method_at_threshold_zero_is_the_plain_method():
+    import os
+    import sys
+    sys.path.insert(0, os.path.dirname(__file__))
+    from _helpers import history_array, system
+    s = system("cubic3_sparse")
+    H, S, C0, mask = s.H.to_dense(), s.S.to_dense(), s.C0.to_dense(), s.C0.pattern_mask()
+    blocks = dict(row_blocks=[s.spec.norb] * s.natoms, col_blocks=[s.spec.wf_per_atom] * s.natoms)
+    k = 30
+    plain = O.cg_minimize(H, S, C0, mask=mask, eta=s.spec.eta, tol_grad=0.0, max_iter=k)
+    filt = O.cg_minimize_filtered(H, S, C0, mask=mask, eta=s.spec.eta, tol_grad=0.0, max_iter=k, filter_eps=0.0,
+                                  **blocks)
+    a, b = history_array(plain), history_array(filt)
+    assert np.all(np.abs(a[:, 0] - b[:, 0]) <= 1e-12 * np.abs(a[:, 0]))
+    assert np.all(np.abs(a[:, 6] - b[:, 6]) <= 1e-9 * np.abs(a[:, 6]))
+    assert np.max(np.abs(plain.C - filt.C)) <= 1e-12
+
+
+def test_filtered_method_keeps_projections_symmetric_and_drops_small_blocks():
+    import os
+    import sys
+    sys.path.insert(0, os.path.dirname(__file__))
+    from _helpers import system
+    s = system("cubic3_sparse")
+    H, S, C0, mask = s.H.to_dense(), s.S.to_dense(), s.C0.to_dense(), s.C0.pattern_mask()
+    rb, cb = [s.spec.norb] * s.natoms, [s.spec.wf_per_atom] * s.natoms
+    eps = 3e-3
+    r = O.cg_minimize_filtered(H, S, C0, mask=mask, eta=s.spec.eta, tol_grad=0.0, max_iter=10, filter_eps=eps,
+                               row_blocks=rb, col_blocks=cb)
+    assert np.array_equal(r.SW, r.SW.T) and np.array_equal(r.HW, r.HW.T)
+    # the start-up S_W is the filtered C^T f(S C) with its upper triangle mirrored: no
+    # block of it (off the zero blocks) is below the threshold, some are zero
+    SC = O.filter_blocks(S @ C0, rb, cb, eps)
+    SW0 = O.upper_mirror(O.filter_blocks(C0.T @ SC, cb, cb, eps))
+    n = SW0.shape[0]
+    norms = np.sqrt((SW0.reshape(n // 2, 2, n // 2, 2) ** 2).sum(axis=(1, 3)))
+    assert np.all((norms == 0.0) | (norms >= eps)) and np.any(norms == 0.0)
+    # and the filtered run differs from the plain one
+    p = O.cg_minimize(H, S, C0, mask=mask, eta=s.spec.eta, tol_grad=0.0, max_iter=10)
+    assert abs(p.energy - r.energy) > 1e-9 * abs(p.energy)
