@@ -294,6 +294,20 @@ int omm_batch_minimize(omm_ctx* const* ctxs, int32_t count, omm_report* reports)
  * `rho` holds s_nval doubles in host or device memory (omm_memspace `where`). */
 int omm_density_matrix(omm_ctx* ctx, int32_t sys, double* rho, int32_t where);
 
+/* omm_density_matrix for callers that cannot allocate memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and the same result, with the intermediate C (2I - S_W) and
+ * rho tiles in a fixed device scratch array of the library (32 MiB per GPU,
+ * held until the process ends) instead of context buffers, and no host
+ * staging: `rho_dev` is device memory (s_nval doubles, caller-owned) on the
+ * context's device, which must be current.  The call allocates and frees
+ * nothing.  A context needing more than 16384 scratch tiles (the C M tiles
+ * plus the tiles of S's block pattern, 16 x 16 doubles each) gets
+ * OMM_ERR_ARG.  All calls on one GPU share its scratch array: calls that
+ * overlap in time on one GPU (from several host threads or streams) race and
+ * must be serialized by the caller.  Returns when the result is in rho_dev. */
+int omm_density_matrix_noalloc(omm_ctx* ctx, int32_t sys, double* rho_dev);
+
 /* Energy density rho_E = 2 C H_W C^T (Eq. 6, the S-derivative term of the
  * forces) with the Kim correction rho_E + eta rho (Sec. II), where H_W =
  * C^T (H - eta S) C and eta is the system's shift; at eta = 0 this is plain

@@ -15,6 +15,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -109,6 +110,35 @@ struct GPlan {   // grouped work list of one product step
 
 }  // namespace
 
+// Scratch of omm_density_matrix_noalloc: the C M and rho tiles of the density
+// matrix live in this file-scope device array instead of context buffers.  Each
+// GPU the library runs on holds its own copy (32 MiB) until the process ends.
+// Host code never passes the array's name to a kernel (on the host it is only a
+// stand-in): the device address of each GPU's copy comes from
+// hipGetSymbolAddress at context creation, with that GPU current.
+constexpr size_t NOALLOC_TILES = 16384;                      // FP64 16 x 16 tiles
+static __device__ __align__(256) double scratch[NOALLOC_TILES * omm::TE];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[MAX_DEVICES] = {};
+
+// address of this GPU's copy of `scratch`, looked up once per device (the device must be current)
+double* scratch_of_device(int dev) {
+  if (dev < 0 || dev >= MAX_DEVICES) throw omm::DeviceError("device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      throw omm::DeviceError(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_dev[dev] = (double*)p;
+  }
+  return g_scratch_dev[dev];
+}
+}  // namespace
+
 // a captured hipGraph of several contexts (omm_batch_minimize), kept by the first of them
 struct MultiGraph;
 
@@ -153,6 +183,7 @@ struct omm_ctx {
   bool tuned = false;
   std::string tune_log;
   int dev = -1;                 // device the context lives on
+  double* scratch_dev = nullptr;  // this device's copy of `scratch` (device address)
   uint64_t gen = 0;             // bumped whenever the context's kernels or buffers change
   std::chrono::steady_clock::time_point solve_t0;
   double setup_secs = 0.0;
@@ -1743,6 +1774,7 @@ int omm_init_batch(omm_ctx** out, int32_t count, const omm_matrix* H, const omm_
   int rc = guard(c, [](omm_ctx* cc, void* v) -> int {
     auto* q = (A*)v;
     OMM_HIP(hipGetDevice(&cc->dev));
+    cc->scratch_dev = scratch_of_device(cc->dev);
     if (cc->opt.hip_stream) cc->stream = (hipStream_t)cc->opt.hip_stream;
     else {
       OMM_HIP(hipStreamCreateWithFlags(&cc->stream, hipStreamNonBlocking));
@@ -1961,6 +1993,43 @@ static int density_like(omm_ctx* c, int32_t sys, double* out, int32_t where, boo
     double* dst = out_buffer(cc, q->out, q->where, s.S.nval, tmp);
     launch_gather(st, blkmap(s.mh, s.s_voff, s, false, cc->TH), cc->rho, dst);
     finish_out(cc, q->out, q->where, dst, s.S.nval, tmp);
+    return OMM_OK;
+  }, &a);
+}
+
+int omm_density_matrix_noalloc(omm_ctx* c, int32_t sys, double* rho_dev) {
+  if (!c) return OMM_ERR_ARG;
+  if (sys < 0 || sys >= c->nsys || !rho_dev) {
+    c->err = "bad argument";
+    return OMM_ERR_ARG;
+  }
+  if (!c->ran) {
+    c->err = "omm_minimize must run before omm_density_matrix_noalloc";
+    return OMM_ERR_STATE;
+  }
+  const size_t need = (size_t)std::max<int64_t>(1, c->TCM.nnz) + (size_t)std::max<int64_t>(1, c->TH.nnz);
+  if (need > NOALLOC_TILES) {
+    c->err = "omm_density_matrix_noalloc: the context needs " + std::to_string(need) +
+             " scratch tiles of 16 x 16 doubles, more than the " + std::to_string(NOALLOC_TILES) +
+             " of the fixed scratch; use omm_density_matrix";
+    return OMM_ERR_ARG;
+  }
+  struct A { int sys; double* out; } a{sys, rho_dev};
+  return guard(c, [](omm_ctx* cc, void* v) -> int {
+    auto* q = (A*)v;
+    int dev = -1;
+    OMM_HIP(hipGetDevice(&dev));
+    if (dev != cc->dev) throw ArgError("the context's device must be current");
+    SysHost& s = cc->sys[q->sys];
+    hipStream_t st = cc->stream;
+    double* CM = cc->scratch_dev;                                            // TCM tiles, then
+    double* rho = cc->scratch_dev + (size_t)std::max<int64_t>(1, cc->TCM.nnz) * TE;   // H-pattern tiles
+    const double* C = current_c(cc, q->sys);
+    launch_cm(st, cc->Pcm.view(), cc->TCM.row, cc->brow_sys, q->sys, C, cc->b.S0, cc->b.H0, 0.0, 1.0, cc->TW.row,
+              cc->TW.ci, CM);
+    launch_rho(st, cc->Prho.view(), cc->TH.row, cc->brow_sys, q->sys, CM, C, rho);
+    launch_gather(st, blkmap(s.mh, s.s_voff, s, false, cc->TH), rho, q->out);
+    OMM_HIP(hipStreamSynchronize(st));
     return OMM_OK;
   }, &a);
 }

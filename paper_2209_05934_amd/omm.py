@@ -89,6 +89,7 @@ def load(path: Optional[str] = None) -> C.CDLL:
         "omm_minimize": (I32, [P, C.POINTER(omm_report)]),
         "omm_batch_minimize": (I32, [C.POINTER(P), I32, C.POINTER(omm_report)]),
         "omm_density_matrix": (I32, [P, I32, P, I32]),
+        "omm_density_matrix_noalloc": (I32, [P, I32, P]),
         "omm_energy_density": (I32, [P, I32, P, I32]),
         "omm_set_occupied": (I32, [P, I32, I64]),
         "omm_set_preconditioner": (I32, [P, MP, D]),
@@ -117,7 +118,7 @@ def load(path: Optional[str] = None) -> C.CDLL:
 
 EXPORTED = ("omm_default_options", "omm_init", "omm_init_batch", "omm_set_coeffs", "omm_minimize",
             "omm_batch_minimize",
-            "omm_density_matrix", "omm_energy_density", "omm_get_coeffs", "omm_get_projected",
+            "omm_density_matrix", "omm_density_matrix_noalloc", "omm_energy_density", "omm_get_coeffs", "omm_get_projected",
             "omm_get_history", "omm_query", "omm_set_occupied", "omm_set_preconditioner", "omm_update_hs",
             "omm_remap_coeffs", "omm_write_coeffs", "omm_read_coeffs", "omm_set_timing", "omm_kernel_times", "omm_time_step",
             "omm_status_str", "omm_last_error", "omm_destroy")
@@ -236,6 +237,14 @@ def omm_batch_minimize(ctxs, counts, soft_ok: bool = True):
 def omm_density_matrix(ctx, sys: int, out) -> int:
     p, where = _addr(out)
     return _check(ctx, load().omm_density_matrix(ctx, int(sys), C.c_void_p(p), where))
+
+
+def omm_density_matrix_noalloc(ctx, sys: int, out) -> int:
+    """out: a device tensor of s_nval doubles."""
+    p, where = _addr(out)
+    if where != OMM_DEVICE:
+        raise ValueError("omm_density_matrix_noalloc writes device memory only")
+    return _check(ctx, load().omm_density_matrix_noalloc(ctx, int(sys), C.c_void_p(p)))
 
 
 def omm_set_occupied(ctx, sys: int, n_occupied: int) -> int:
