@@ -88,7 +88,7 @@ class BlockMatrix:
 
     def to_dense(self) -> np.ndarray:
         ro, co = self.row_offsets(), self.col_offsets()
-        out = np.zeros((int(ro[-1]), int(co[-1])))
+        out = np.zeros((int(ro[-1]), int(co[-1])), dtype=self.val.dtype)
         rows = self.block_rows()
         for k in range(self.nnzb):
             i, j = int(rows[k]), int(self.col_idx[k])
@@ -119,12 +119,13 @@ class BlockMatrix:
                                        shape=self.shape)
 
     def with_values(self, val: np.ndarray) -> "BlockMatrix":
-        return replace(self, val=np.ascontiguousarray(val, dtype=np.float64))
+        return replace(self, val=np.ascontiguousarray(
+            val, dtype=np.complex128 if np.iscomplexobj(val) else np.float64))
 
     def gather_from_dense(self, A: np.ndarray) -> np.ndarray:
         """Values of dense A on this matrix's block pattern, in `val` layout."""
         ro, co = self.row_offsets(), self.col_offsets()
-        out = np.zeros_like(self.val)
+        out = np.zeros(self.val.shape, dtype=np.result_type(self.val, A))
         rows = self.block_rows()
         for k in range(self.nnzb):
             i, j = int(rows[k]), int(self.col_idx[k])
@@ -147,7 +148,8 @@ def _uniform_bcsr(nbrow: int, nbcol: int, rb: int, cb: int,
         row_ptr=row_ptr.astype(np.int64),
         col_idx=cols.astype(np.int32),
         val_off=(np.arange(nnzb, dtype=np.int64) * rb * cb),
-        val=np.ascontiguousarray(blocks.reshape(-1), dtype=np.float64),
+        val=np.ascontiguousarray(blocks.reshape(-1),
+                                 dtype=np.complex128 if np.iscomplexobj(blocks) else np.float64),
     )
 
 
@@ -298,6 +300,23 @@ def _min_image(d: np.ndarray, box: np.ndarray) -> np.ndarray:
 
 
 def make_system(spec: SystemSpec) -> System:
+    return _build(spec, None)
+
+
+def make_bloch_system(spec: SystemSpec, kfrac: Sequence[float]) -> System:
+    """The system at the k-point k = 2 pi kfrac / box (kfrac in units of the
+    reciprocal lattice of the periodic box, components in [0, 1); kfrac = 0 is
+    the Gamma point): every periodic image n of a pair block gets its Bloch phase,
+    H(k)_IJ = sum_n exp(i k . R_n) H_IJ^(n), S(k) likewise, with R_n the lattice
+    translation of the image and H(k)_JI = H(k)_IJ^dagger, so H(k) and S(k) are
+    complex Hermitian (values complex128).  The random numbers are those of
+    `make_system` (kfrac = 0 gives the same real matrices); C0 is complex: real
+    part `make_system`'s C0 / sqrt 2, imaginary part N(0, sigma^2 / 2) drawn
+    after it (the same mean square |C0_ij|^2 as the real guess)."""
+    return _build(spec, np.asarray(kfrac, dtype=np.float64))
+
+
+def _build(spec: SystemSpec, kfrac) -> System:
     rng = np.random.default_rng(spec.seed)
     dim = len(spec.dims)
     N, norb, nwf = spec.natoms, spec.norb, spec.wf_per_atom
@@ -339,6 +358,13 @@ def make_system(spec: SystemSpec) -> System:
     Q = rng.standard_normal((npi, norb, norb))
     wH = (spec.hop * np.exp(-PR / spec.decay))[:, None, None]
     wS = (spec.ovl * np.exp(-PR / spec.decay))[:, None, None]
+    if kfrac is not None and npi:   # Bloch phase of each image: exp(i k . R), R the lattice translation
+        kvec = 2.0 * np.pi * kfrac / box
+        d_img = _min_image(pos[PJ] - pos[PI], box) + shifts[PS] * box
+        R = d_img - (pos[PJ] - pos[PI])
+        ph = np.exp(1j * (R @ kvec))[:, None, None]
+        wH = wH * ph
+        wS = wS * ph
     # sum images of the same pair
     pair_key = PI * N + PJ
     upair, first = np.unique(pair_key, return_index=True)
@@ -357,8 +383,8 @@ def make_system(spec: SystemSpec) -> System:
     # assemble full (both triangles) block lists sorted by (row, col)
     rows = np.concatenate([np.arange(N), UI, UJ])
     cols = np.concatenate([np.arange(N), UJ, UI])
-    Hblk = np.concatenate([Hd, HB, np.transpose(HB, (0, 2, 1))])
-    Sblk = np.concatenate([Sd, SB, np.transpose(SB, (0, 2, 1))])
+    Hblk = np.concatenate([Hd, HB, np.conj(np.transpose(HB, (0, 2, 1)))])
+    Sblk = np.concatenate([Sd, SB, np.conj(np.transpose(SB, (0, 2, 1)))])
     o = np.lexsort((cols, rows))
     T = None
     if spec.kinetic > 0.0:
@@ -383,6 +409,8 @@ def make_system(spec: SystemSpec) -> System:
     sigma = spec.c0_scale * np.sqrt(spec.c0_ref_nnz / nnz_col)
     rng2 = np.random.default_rng(spec.seed + 10**6)
     cblk = rng2.normal(0.0, sigma, size=(crow.shape[0], norb, nwf))
+    if kfrac is not None:   # complex entries of the same mean square as the real ones
+        cblk = (cblk + 1j * rng2.normal(0.0, sigma, size=cblk.shape)) / np.sqrt(2.0)
     C0 = _uniform_bcsr(N, N, norb, nwf, crow, ccol, cblk)
     return System(spec=spec, pos=pos, box=box, H=H, S=S, C0=C0, pair_images=npi, T=T,
                   extra={"c0_sigma": sigma})

@@ -32,6 +32,11 @@ from .omm import (  # noqa: F401
     cg_minimize,
     cg_minimize_sparse,
     cg_minimize_filtered,
+    cg_minimize_complex,
+    quartic_coefficients_complex,
+    om_energy_complex,
+    om_gradient_complex,
+    density_matrix_complex,
     cholesky_reduce,
     kinetic_preconditioner,
     cg_minimize_cholesky,

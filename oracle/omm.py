@@ -591,3 +591,118 @@ def cg_minimize_sparse(H, S, C0, *, eta: float = 0.0, tol_grad: float = 1e-9, re
     return CGResult(C=C, energy=E, energy_band=E + 2.0 * eta * n, iterations=it,
                     converged=converged, status=status, grad_norm=float(np.sqrt(gg)),
                     restarts=restarts, HW=HW, SW=SW, history=history)
+
+
+# ---------------------------------------------------------------- complex Hermitian (k-points)
+# The functional of Eq. 4 for complex Hermitian H, S (a k-point; the paper writes
+# C^dagger throughout, Sec. II-III): H_W = C^dagger H C, S_W = C^dagger S C and
+# E~ = 2 Tr[(2I - S_W) H_W], which is real.  The variables are the real and
+# imaginary parts of C; with the real inner product Re <A, B> = Re sum conj(A) B
+# the gradient is G = 8 HC - 4 (HC S_W + SC H_W) (dE~ = Re <G, dC>), twice the
+# Wirtinger derivative dE~/dC*.  CG, line search and stop rules as in
+# `cg_minimize`, with every inner product taken as Re <., .>.
+def _rdot(A, B) -> float:
+    """Re <A, B> = Re sum_ij conj(A_ij) B_ij."""
+    return float(np.real(np.vdot(A, B)))
+
+
+def _trace_prod(A, B) -> float:
+    """Re Tr(A B) = Re sum_ij A_ij B_ji."""
+    return float(np.real(np.sum(A * B.T)))
+
+
+def quartic_coefficients_complex(H, S, C, D) -> np.ndarray:
+    """c0..c4 with E~(C + xD) = sum_k c_k x^k for complex Hermitian H, S: H_W(x) =
+    H0 + x H1 + x^2 H2 with H0 = C^+ H C, H1 = C^+ H D + D^+ H C, H2 = D^+ H D
+    (S likewise) and E~(x) = 4 Re Tr H_W(x) - 2 Re Tr(S_W(x) H_W(x))."""
+    Ch, Dh = C.conj().T, D.conj().T
+    HC, SC, HD, SD = H @ C, S @ C, H @ D, S @ D
+    H0, S0 = Ch @ HC, Ch @ SC
+    H1, S1 = Ch @ HD + Dh @ HC, Ch @ SD + Dh @ SC
+    H2, S2 = Dh @ HD, Dh @ SD
+    tr = lambda A: float(np.real(np.trace(A)))   # noqa: E731
+    c0 = 4.0 * tr(H0) - 2.0 * _trace_prod(S0, H0)
+    c1 = 4.0 * tr(H1) - 2.0 * (_trace_prod(S0, H1) + _trace_prod(S1, H0))
+    c2 = 4.0 * tr(H2) - 2.0 * (_trace_prod(S0, H2) + _trace_prod(S1, H1) + _trace_prod(S2, H0))
+    c3 = -2.0 * (_trace_prod(S1, H2) + _trace_prod(S2, H1))
+    c4 = -2.0 * _trace_prod(S2, H2)
+    return np.array([c0, c1, c2, c3, c4], dtype=np.float64)
+
+
+def om_energy_complex(H, S, C) -> float:
+    """E~ = 2 Tr[(2I - S_W) H_W] with H_W = C^+ H C, S_W = C^+ S C (Eq. 3-4), real part."""
+    Ch = C.conj().T
+    HW, SW = Ch @ H @ C, Ch @ S @ C
+    n = HW.shape[0]
+    return 2.0 * float(np.real(np.trace((2.0 * np.eye(n) - SW) @ HW)))
+
+
+def om_gradient_complex(H, S, C) -> np.ndarray:
+    """G = 8 HC - 4 (HC S_W + SC H_W): dE~ = Re <G, dC> for Hermitian H, S."""
+    HC, SC = H @ C, S @ C
+    Ch = C.conj().T
+    return 8.0 * HC - 4.0 * (HC @ (Ch @ SC) + SC @ (Ch @ HC))
+
+
+def cg_minimize_complex(H, S, C0: np.ndarray, *, mask: Optional[np.ndarray] = None, eta: float = 0.0,
+                        tol_grad: float = 1e-9, rel_tol: float = 0.0, max_iter: int = 10000,
+                        keep_history: bool = True, n_occupied: Optional[int] = None) -> CGResult:
+    """`cg_minimize` for complex Hermitian H, S (dense arrays) and complex C0."""
+    Heta = np.asarray(H, dtype=np.complex128) - eta * np.asarray(S, dtype=np.complex128)
+    S = np.asarray(S, dtype=np.complex128)
+    C = project(np.array(C0, dtype=np.complex128, copy=True), mask)
+    n = C.shape[1] if n_occupied is None else int(n_occupied)
+
+    def energy_gradient(C):
+        HC, SC = Heta @ C, S @ C
+        Ch = C.conj().T
+        HW, SW = Ch @ HC, Ch @ SC
+        E = 4.0 * float(np.real(np.trace(HW))) - 2.0 * _trace_prod(SW, HW)
+        return E, project(8.0 * HC - 4.0 * (HC @ SW + SC @ HW), mask), HW, SW
+
+    E, G, HW, SW = energy_gradient(C)
+    D = -G
+    steepest = True
+    gg = _rdot(G, G)
+    history: List[dict] = []
+    status, converged, it, restarts = "not_converged", False, 0, 0
+    if np.sqrt(gg) <= tol_grad:
+        status, converged = "ok", True
+    while not converged and it < max_iter:
+        it += 1
+        c = quartic_coefficients_complex(Heta, S, C, D)
+        x, ok = line_minimum(c)
+        restart = False
+        if not ok or c[1] >= 0.0:
+            if steepest:
+                status = "no_line_min"
+                it -= 1
+                break
+            x, restart = 0.0, True
+            restarts += 1
+        C = C + x * D
+        E_old = E
+        E, G_new, HW, SW = energy_gradient(C)
+        gg_new = _rdot(G_new, G_new)
+        beta = 0.0 if restart else max(0.0, _rdot(G_new, G_new - G) / gg)
+        if keep_history:
+            history.append(dict(E=E, c=c.copy(), x=x, gnorm=np.sqrt(gg_new), beta=beta, restart=restart))
+        G, gg = G_new, gg_new
+        if np.sqrt(gg) <= tol_grad:
+            status, converged = "ok", True
+            break
+        if rel_tol > 0.0 and not restart and (E + E_old) != 0.0 and \
+                abs(2.0 * (E - E_old) / (E + E_old)) < rel_tol:
+            status, converged = "ok", True
+            break
+        D = -G + beta * D
+        steepest = (beta == 0.0)
+    return CGResult(C=C, energy=E, energy_band=E + 2.0 * eta * n, iterations=it,
+                    converged=converged, status=status, grad_norm=float(np.sqrt(gg)),
+                    restarts=restarts, HW=HW, SW=SW, history=history)
+
+
+def density_matrix_complex(C: np.ndarray, SW: np.ndarray) -> np.ndarray:
+    """rho = 2 C (2I - S_W) C^+ (Eq. 5 with C^dagger)."""
+    n = SW.shape[0]
+    return 2.0 * C @ (2.0 * np.eye(n) - SW) @ C.conj().T

@@ -517,3 +517,71 @@ def test_filtered_method_keeps_projections_symmetric_and_drops_small_blocks():
     # and the filtered run differs from the plain one
     p = O.cg_minimize(H, S, C0, mask=mask, eta=s.spec.eta, tol_grad=0.0, max_iter=10)
     assert abs(p.energy - r.energy) > 1e-9 * abs(p.energy)
+
+
+# ------------------------------------------------------------ complex Hermitian (k-points)
+def _rand_complex_problem(m=9, n=3, seed=3):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))
+    H = 0.5 * (A + A.conj().T)
+    B = 0.1 * (rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m)))
+    S = np.eye(m) + 0.5 * (B + B.conj().T)
+    C = 0.3 * (rng.standard_normal((m, n)) + 1j * rng.standard_normal((m, n)))
+    D = 0.3 * (rng.standard_normal((m, n)) + 1j * rng.standard_normal((m, n)))
+    return H, S, C, D
+
+
+def test_complex_gradient_finite_differences():
+    # dE = Re <G, dC>: the real and imaginary parts of G are the derivatives along
+    # the real and imaginary parts of each entry of C
+    H, S, C, _ = _rand_complex_problem()
+    G = O.om_gradient_complex(H, S, C)
+    h = 1e-5
+    num = np.zeros_like(C)
+    for idx in np.ndindex(C.shape):
+        for unit in (1.0, 1j):
+            Cp, Cm = C.copy(), C.copy()
+            Cp[idx] += h * unit
+            Cm[idx] -= h * unit
+            d = (O.om_energy_complex(H, S, Cp) - O.om_energy_complex(H, S, Cm)) / (2 * h)
+            num[idx] += d * unit
+    assert np.max(np.abs(num - G)) <= 1e-7 * np.max(np.abs(G))
+
+
+def test_complex_quartic_exact():
+    H, S, C, D = _rand_complex_problem(seed=4)
+    c = O.quartic_coefficients_complex(H, S, C, D)
+    for x in (-1.0, -0.5, 0.3, 1.0, 2.0):
+        E = O.om_energy_complex(H, S, C + x * D)
+        assert abs(O.quartic_value(c, x) - E) <= 1e-11 * max(1.0, abs(E))
+    # c1 is the directional derivative Re <G, D>
+    assert abs(c[1] - float(np.real(np.vdot(O.om_gradient_complex(H, S, C), D)))) <= 1e-10 * abs(c[1])
+
+
+def test_complex_form_on_real_input_is_the_real_method(chain):
+    s, H, S, C0 = chain
+    k = 15
+    a = O.cg_minimize(H, S, C0, tol_grad=0.0, max_iter=k)
+    b = O.cg_minimize_complex(H.astype(complex), S.astype(complex), C0.astype(complex), tol_grad=0.0, max_iter=k)
+    for ha, hb in zip(a.history, b.history):
+        assert abs(ha["E"] - hb["E"]) <= 1e-13 * abs(ha["E"])
+        assert abs(ha["x"] - hb["x"]) <= 1e-9 * abs(ha["x"])
+    assert np.max(np.abs(a.C - b.C)) <= 1e-12
+
+
+@pytest.mark.parametrize("kfrac", [(0.25, 0.0, 0.0), (0.25, 0.25, 0.5)])
+def test_complex_k_point_converges_to_the_eigen_solution(kfrac):
+    # Sec. II at a k-point: the minimum of Eq. 4 is 2 sum of the n lowest eigenvalues of
+    # the Hermitian pencil (H(k), S(k)), with rho = 2 X X^+ (S-orthonormal X)
+    from ommgen.systems import cubic_spec, make_bloch_system
+    s = make_bloch_system(cubic_spec(3, 31, dense=True), kfrac)
+    H, S, C0 = s.H.to_dense(), s.S.to_dense(), s.C0.to_dense()
+    assert np.max(np.abs(H - H.conj().T)) == 0.0 and np.max(np.abs(H.imag)) > 1e-3
+    r = O.cg_minimize_complex(H, S, C0, tol_grad=1e-9, max_iter=5000)
+    assert r.converged
+    w, X = scipy.linalg.eigh(H, S)
+    n = s.n
+    assert abs(r.energy - 2.0 * w[:n].sum()) / s.natoms <= 1e-10
+    rho = O.density_matrix_complex(r.C, r.SW)
+    assert np.max(np.abs(rho - 2.0 * X[:, :n] @ X[:, :n].conj().T)) <= 1e-8
+    assert np.max(np.abs(r.SW - np.eye(n))) <= 1e-8
