@@ -18,6 +18,7 @@ one JSON line.
 from __future__ import annotations
 
 import argparse
+from dataclasses import replace
 import tempfile
 import json
 import os
@@ -137,6 +138,8 @@ def parse():
     ap.add_argument("--to-accuracy", action="store_true",
                     help="only the time-to-accuracy comparison (FP64, FP32 + FP64, BF16 + FP64 to the stop rule "
                          "|dE/E| < 1e-9), as its own JSON line")
+    ap.add_argument("--filter-eps", type=float, default=None,
+                    help="product filter threshold of the block-sparse workloads (default: the workload's, 1e-6)")
     ap.add_argument("--no-to-accuracy", action="store_true",
                     help="skip the time-to-accuracy comparison of the block-sparse workloads")
     args = ap.parse_args()
@@ -423,6 +426,8 @@ def accuracy_main(args):
     if wl["mode"] != "sparse":
         raise SystemExit("--to-accuracy applies to the block-sparse workloads")
     spec = config_spec(wl["cfg"])
+    if args.filter_eps is not None:
+        spec = replace(spec, filter_eps=args.filter_eps)
     system = make_system(spec)
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
@@ -472,6 +477,8 @@ def main():
 
     wl = WORKLOADS[args.workload]
     spec = config_spec(wl["cfg"], **wl.get("spec", {}))
+    if args.filter_eps is not None and wl["mode"] == "sparse":
+        spec = replace(spec, filter_eps=args.filter_eps)
     system = make_system(spec)
     tau = wl.get("tau", 0.0)
     mode = {"dense": L.OMM_DENSE, "cholesky": L.OMM_DENSE_CHOLESKY, "sparse": L.OMM_BLOCK_SPARSE}[wl["mode"]]
@@ -594,6 +601,7 @@ def main():
                   "bf16": "bf16 products (f32 accumulate), f64 traces/line search"}[args.precision],
         "data": "synthetic",
         "config": {"workload": args.workload + ": " + wl["desc"], "mode": wl["mode"],
+                   "filter_eps": spec.filter_eps if wl["mode"] == "sparse" else None,
                    "precision": args.precision, "N_basis": int(system.m), "N_occ": int(system.n_occupied),
                    "N_wf": int(system.n), "atoms": int(system.natoms)},
         "cg_iters_per_step": iters / args.steps,

@@ -200,6 +200,28 @@ int omm_init_batch(omm_ctx** out, int32_t count, const omm_matrix* H, const omm_
                    const int64_t* n_occ, const int32_t* modes, const double* etas,
                    const omm_options* opt);
 
+/* Complex Hermitian systems, e.g. the k-points of a periodic structure (Eqs.
+ * 3-5 with C^dagger; the paper's runs are at the Gamma point, Sec. IV A): the
+ * same arguments as omm_init_batch, with H[i], S[i] complex Hermitian.  Their
+ * omm_matrix structures are as for real matrices, but `val` holds 2 nval
+ * doubles, the real and imaginary part of each value interleaved, in host
+ * memory (memspace OMM_HOST); n_occ[i] counts complex wavefunctions.  Each
+ * system is held as its real embedding [[Re Z, -Im Z], [Im Z, Re Z]] (every
+ * atom block split into a real-part and an imaginary-part block), on which the
+ * real kernels run: the embedded functional is twice the complex one and CG
+ * on it takes the steps of complex CG with real inner products, at twice the
+ * flops of complex arithmetic.  On such a context: omm_set_coeffs and
+ * omm_update_hs take complex matrices (host); omm_density_matrix,
+ * omm_energy_density and omm_get_coeffs write complex values (2 nval
+ * doubles, host memory only), omm_get_projected complex n x n matrices;
+ * reports, history and omm_query describe the complex system (energy,
+ * electron count, quartic halved, gradient norm divided by sqrt 2, tol_grad
+ * applies to it; omm_query's work counts are those of the embedding).
+ * omm_density_matrix_noalloc refuses complex contexts.  Errors as omm_init_batch. */
+int omm_init_complex(omm_ctx** out, int32_t count, const omm_matrix* H, const omm_matrix* S,
+                     const int64_t* n_occ, const int32_t* modes, const double* etas,
+                     const omm_options* opt);
+
 /* Sets the initial guess of system `sys` (Sec. III D: random values inside the
  * localization radius).  C0 is m x n with the same block rows as H; its block
  * pattern is the pattern kept fixed during minimization (Sec. III B) and must

@@ -27,7 +27,7 @@ SOURCES = ([("symbolic.hip", "symbolic.o", [])]
            + [(src, src.replace(".hip", f"_p{k}.o"), [f"-DOMM_PREC={k}"])
               for src in PRODUCT_SOURCES for k in range(3)]
            + [(src, src.replace(".hip", ".o"), []) for src in ("numeric.hip", "cholesky.hip", "engine.hip")]
-           + [("coeff_io.cpp", "coeff_io.o", [])])
+           + [("coeff_io.cpp", "coeff_io.o", []), ("kpoint.cpp", "kpoint.o", [])])
 ARCH = os.environ.get("OMM_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "kpoint.hpp"
 
 using namespace omm;
 
@@ -105,7 +106,7 @@ struct GPlan {   // grouped work list of one product step
   int4* meta = nullptr;
   std::vector<int> hgbase;          // first group of each output row (nrows + 1)
   std::vector<int64_t> hpairs;      // prefix of tile pairs over groups (ngroups + 1)
-  GroupView view() const { return GroupView{ngroups, NT, go0, gn, gp, ent, meta}; }
+  GroupView view() const { return GroupView{ngroups, NT, nent, go0, gn, gp, ent, meta}; }
 };
 
 }  // namespace
@@ -157,6 +158,7 @@ struct omm_ctx {
   int *brow_sys = nullptr, *wrow_sys = nullptr, *c_in_hc = nullptr, *hc_to_c = nullptr, *w_tr = nullptr;
   int* upd_sys = nullptr;
   uint32_t* cmask = nullptr;
+  int* s2mark = nullptr;      // marked copy of the n x n work list (filtering that skips work)
   uint8_t* wseg = nullptr;
   int4* chunks = nullptr;
   int nchunks = 0;
@@ -182,6 +184,10 @@ struct omm_ctx {
   int graph_iters = 0, graph_small = 0;
   bool tuned = false;
   std::string tune_log;
+  // complex Hermitian systems (k-points) are held as their real embedding
+  // (kpoint.hpp); the structures of the complex H, S and C0 map outputs back
+  bool cplx = false;
+  std::vector<ZStruct> zH, zS, zC;
   int dev = -1;                 // device the context lives on
   double* scratch_dev = nullptr;  // this device's copy of `scratch` (device address)
   uint64_t gen = 0;             // bumped whenever the context's kernels or buffers change
@@ -415,6 +421,55 @@ void make_gplan(omm_ctx* c, GPlan& G, const Pat& O, const PatView& A, const PatV
   G.hpairs.assign(G.ngroups + 1, 0);
   for (int g = 0; g < G.ngroups; ++g) G.hpairs[g + 1] = G.hpairs[g] + pres[g];
   G.npairs = G.hpairs[G.ngroups];
+}
+
+// Groups of a work list put in 2D-blocked order of their output grid: blocks of
+// BR consecutive output rows by BC consecutive output columns (tile indices),
+// blocks in row-major order, groups row-major inside a block.  Consecutive
+// groups run on one XCD (the kernels deal runs of consecutive workgroups to
+// one XCD), so a block's groups share both their row operands and their
+// column operands in that XCD's L2.  Entries move with their group; the
+// kernels take groups in any order, so results do not change.
+void block_order(omm_ctx* c, GPlan& G, const Pat& O, int BR, int BC) {
+  if (G.ngroups <= 1 || (BR <= 1 && BC <= 1)) return;
+  hipStream_t st = c->stream;
+  const int W = 1 + G.NT;
+  std::vector<int4> meta = ddownload(c, G.meta, G.ngroups);
+  std::vector<int64_t> gp = ddownload(c, G.gp, G.ngroups + 1);
+  std::vector<int> ent = ddownload(c, G.ent, (size_t)std::max<int64_t>(1, G.nent) * W);
+  std::vector<int> go0 = ddownload(c, G.go0, G.ngroups), gn = ddownload(c, G.gn, G.ngroups);
+  std::vector<int> ocol = ddownload(c, O.ci, O.nnz);
+  std::vector<int> orow(O.nnz);
+  for (int r = 0; r < O.nrows; ++r)
+    for (int t = O.hrp[r]; t < O.hrp[r + 1]; ++t) orow[t] = r;
+  int ncol = 1;
+  for (int v : ocol) ncol = std::max(ncol, v + 1);
+  const int64_t nbc = (ncol + BC - 1) / BC;
+  std::vector<std::pair<int64_t, int>> key(G.ngroups);
+  for (int g = 0; g < G.ngroups; ++g) {
+    const int t = meta[g].x, r = orow[t], col = ocol[t];
+    const int64_t blk = (int64_t)(r / BR) * nbc + col / BC;
+    key[g] = {(blk * BR + r % BR) * (int64_t)ncol + col, g};
+  }
+  std::sort(key.begin(), key.end());
+  std::vector<int4> meta2(G.ngroups);
+  std::vector<int64_t> gp2(G.ngroups + 1, 0);
+  std::vector<int> ent2(ent.size()), go02(G.ngroups), gn2(G.ngroups);
+  for (int q = 0; q < G.ngroups; ++q) {
+    const int g = key[q].second;
+    meta2[q] = meta[g];
+    go02[q] = go0[g];
+    gn2[q] = gn[g];
+    const int64_t n = gp[g + 1] - gp[g];
+    gp2[q + 1] = gp2[q] + n;
+    std::copy(ent.begin() + gp[g] * W, ent.begin() + gp[g + 1] * W, ent2.begin() + gp2[q] * W);
+  }
+  OMM_HIP(hipMemcpyAsync(G.meta, meta2.data(), meta2.size() * sizeof(int4), hipMemcpyHostToDevice, st));
+  OMM_HIP(hipMemcpyAsync(G.gp, gp2.data(), gp2.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+  OMM_HIP(hipMemcpyAsync(G.ent, ent2.data(), ent2.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  OMM_HIP(hipMemcpyAsync(G.go0, go02.data(), go02.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  OMM_HIP(hipMemcpyAsync(G.gn, gn2.data(), gn2.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  OMM_HIP(hipStreamSynchronize(st));
 }
 
 // ----------------------------------------------------------------- work counts (host)
@@ -909,6 +964,18 @@ void prepare(omm_ctx* c) {
     else count_dense_work(s);
   }
   c->nchunks = (int)chunks.size();
+  // 2D-blocked group order of the product steps: blocks of 16 x 2 output tiles for
+  // the direction and gradient products, 8 x 8 for the n x n projections (measured
+  // at 4096 atoms: 2-4 % faster per kernel than row order); OMM_BLOCK_ORDER =
+  // "s1r,s1c,s2r,s2c,gr,gc" replaces the block shapes
+  {
+    int bo[6] = {16, 2, 8, 8, 16, 2};
+    if (const char* e = std::getenv("OMM_BLOCK_ORDER"))
+      std::sscanf(e, "%d,%d,%d,%d,%d,%d", &bo[0], &bo[1], &bo[2], &bo[3], &bo[4], &bo[5]);
+    const Pat* outs[3] = {&c->THC, &c->TW, &c->TC};
+    for (int k = 0; k < 3; ++k)
+      for (int q = 0; q < NPLAN; ++q) block_order(c, c->G[k][q], *outs[k], std::max(1, bo[2 * k]), std::max(1, bo[2 * k + 1]));
+  }
   c->chunks = dupload(c, chunks, true);
   c->d_info = dupload(c, c->h_info, true);
   c->d_st = dalloc<SysState>(c, c->nsys, true);
@@ -931,6 +998,17 @@ void prepare(omm_ctx* c) {
   for (int i = 0; i < c->nsys; ++i)
     if (c->h_info[i].c1 - c->h_info[i].c0 > FUSED_CTILES) b.multi_c = 1;
   b.n_th = (int)c->TH.nnz; b.n_tc = (int)ntc; b.n_thc = (int)nhc; b.n_tw = (int)ntw;
+  bool filtering = false;
+  for (int i = 0; i < c->nsys; ++i) filtering |= c->h_info[i].eps2 > 0.0;
+  b.hcnz = nullptr;
+  c->s2mark = nullptr;
+  if (filtering) {   // filtering that skips work: per-HC-tile nonzero flags, marked n x n list
+    b.hcnz = dalloc<int>(c, std::max<size_t>(1, nhc), true);
+    OMM_HIP(hipMemsetAsync(b.hcnz, 0xff, std::max<size_t>(1, nhc) * sizeof(int), st));
+    int64_t words = 1;
+    for (int q = 0; q < NPLAN; ++q) words = std::max<int64_t>(words, c->G[1][q].nent * (1 + c->G[1][q].NT));
+    c->s2mark = dalloc<int>(c, (size_t)words, true);
+  }
   pick_plans(c);
   b.roll = c->nsys > 1 ? 1 : 0;
   b.H = c->H; b.S = c->S;
@@ -996,6 +1074,21 @@ void prepare(omm_ctx* c) {
   c->prepared = true;
 }
 
+// The work lists the kernels run on: the chosen plan of each product step; with
+// filtering, the n x n projections of an iteration use the marked copy of
+// theirs (refreshed from the list whenever the plan changes)
+void bind_views(omm_ctx* c) {
+  c->b.s1 = c->G[0][c->sel[0]].view();
+  c->b.s2 = c->b.s2_full = c->G[1][c->sel[1]].view();
+  c->b.grad = c->G[2][c->sel[2]].view();
+  if (c->b.hcnz && c->s2mark) {
+    const GPlan& G = c->G[1][c->sel[1]];
+    OMM_HIP(hipMemcpyAsync(c->s2mark, G.ent, (size_t)std::max<int64_t>(1, G.nent) * (1 + G.NT) * sizeof(int),
+                           hipMemcpyDeviceToDevice, c->stream));
+    c->b.s2.ent = c->s2mark;
+  }
+}
+
 // Waves that split one group's entry list: enough waves in flight to hide
 // memory latency when there are few groups with long lists.
 int pick_ks(int64_t ngroups, int64_t nent, int kmax) {
@@ -1021,9 +1114,7 @@ void pick_plans(omm_ctx* c) {
     const GPlan& G = c->G[k][sel];
     c->b.ks[k] = pick_ks(G.ngroups, G.nent, plan_ok(k, G.NT, 8) ? 8 : 4);
   }
-  c->b.s1 = c->G[0][c->sel[0]].view();
-  c->b.s2 = c->G[1][c->sel[1]].view();
-  c->b.grad = c->G[2][c->sel[2]].view();
+  bind_views(c);
   // launch shapes given in the options replace the heuristic choice
   for (int k = 0; k < 3; ++k) {
     const int gw = c->opt.tile_group[k], sp = c->opt.tile_split[k];
@@ -1042,9 +1133,7 @@ void pick_plans(omm_ctx* c) {
     c->sel[k] = sel;
     c->b.ks[k] = ks;
   }
-  c->b.s1 = c->G[0][c->sel[0]].view();
-  c->b.s2 = c->G[1][c->sel[1]].view();
-  c->b.grad = c->G[2][c->sel[2]].view();
+  bind_views(c);
 }
 
 CGParams params(const omm_ctx* c);
@@ -1062,10 +1151,7 @@ std::string tune_key(int cls, int prec, const GPlan& P) {
 void set_plan(omm_ctx* c, int cls, int sel, int ks) {
   c->sel[cls] = sel;
   c->b.ks[cls] = ks;
-  const GroupView v = c->G[cls][sel].view();
-  if (cls == 0) c->b.s1 = v;
-  else if (cls == 1) c->b.s2 = v;
-  else c->b.grad = v;
+  bind_views(c);
 }
 
 void autotune(omm_ctx* c) {
@@ -1197,6 +1283,7 @@ void run_iteration(omm_ctx* c, Prec p, int mask, bool tm) {
   const CGParams prm = params(c);
   StepArg a{p, mask, any_filter(c)};
   timed(c, 0, tm, [](omm_ctx* cc, void* v) { auto* q = (StepArg*)v; launch_s1(cc->stream, cc->b, q->p, q->mask, false); }, &a);
+  launch_mark_pairs(s, b);
   timed(c, 1, tm, [](omm_ctx* cc, void* v) { auto* q = (StepArg*)v; launch_s2(cc->stream, cc->b, q->p, q->mask, false); }, &a);
   launch_traces(s, b, p, mask, false, LS_STEP, prm);
   launch_update(s, b, p, mask, prm);
@@ -1373,10 +1460,13 @@ int end_solve(omm_ctx* c, omm_report* reps) {
     if (rank(status) > rank(worst)) worst = status;
     if (reps) {
       omm_report& r = reps[i];
-      r.energy = S.E;
-      r.energy_band = S.E + 2.0 * c->sys[i].eta * nocc;
-      r.grad_norm = S.gnorm;
-      r.electron_count = S.ne;
+      // a complex system reports for itself: the embedding doubles energies and
+      // electrons and multiplies the gradient norm by sqrt 2
+      const double f = c->cplx ? 0.5 : 1.0;
+      r.energy = f * S.E;
+      r.energy_band = f * (S.E + 2.0 * c->sys[i].eta * nocc);
+      r.grad_norm = c->cplx ? S.gnorm * std::sqrt(0.5) : S.gnorm;
+      r.electron_count = f * S.ne;
       r.iters_total = S.iter;
       r.iters_fp64 = S.iter_fp64;
       r.cg_restarts = S.restarts;
@@ -1667,6 +1757,20 @@ const char* omm_last_error(const omm_ctx* c) { return c ? c->err.c_str() : g_las
 
 int omm_update_hs(omm_ctx* c, int32_t sys, const omm_matrix* H, const omm_matrix* S) {
   if (!c) return OMM_ERR_ARG;
+  HostBlocks RH, RS;
+  if (c->cplx) {   // new complex H(k), S(k): their real embeddings
+    ZStruct zh, zs;
+    struct B { const omm_matrix *H, *S; HostBlocks *RH, *RS; ZStruct *zh, *zs; } bb{H, S, &RH, &RS, &zh, &zs};
+    const int rc = guard(c, [](omm_ctx*, void* v) -> int {
+      auto* q = (B*)v;
+      embed_complex(q->H, *q->RH, *q->zh);
+      embed_complex(q->S, *q->RS, *q->zs);
+      return OMM_OK;
+    }, &bb);
+    if (rc != OMM_OK) return rc;
+    H = &RH.m;
+    S = &RS.m;
+  }
   struct A { int sys; const omm_matrix* H; const omm_matrix* S; } a{sys, H, S};
   return guard(c, [](omm_ctx* cc, void* v) -> int {
     auto* q = (A*)v;
@@ -1798,12 +1902,78 @@ int omm_init(omm_ctx** out, const omm_matrix* H, const omm_matrix* S, int64_t n_
   return omm_init_batch(out, 1, H, S, &n_occ, &mode, nullptr, opt);
 }
 
+static int set_coeffs_real(omm_ctx* c, int32_t sys, const omm_matrix* C0);
+
+int omm_init_complex(omm_ctx** out, int32_t count, const omm_matrix* H, const omm_matrix* S, const int64_t* n_occ,
+                     const int32_t* modes, const double* etas, const omm_options* opt) {
+  g_last_init_error.clear();
+  if (!out || count <= 0 || !H || !S || !n_occ) {
+    g_last_init_error = "out, H, S, n_occ must be non-NULL and count positive";
+    return OMM_ERR_ARG;
+  }
+  *out = nullptr;
+  std::vector<HostBlocks> RH(count), RS(count);
+  std::vector<ZStruct> zh(count), zs(count);
+  std::vector<int64_t> n2(count);
+  try {
+    for (int i = 0; i < count; ++i) {
+      embed_complex(&H[i], RH[i], zh[i]);
+      embed_complex(&S[i], RS[i], zs[i]);
+      if (n_occ[i] < 1) throw ArgError("n_occ must be positive");
+      n2[i] = 2 * n_occ[i];
+    }
+  } catch (const ArgError& e) {
+    g_last_init_error = e.msg;
+    return OMM_ERR_ARG;
+  } catch (const std::bad_alloc&) {
+    g_last_init_error = "host allocation failed";
+    return OMM_ERR_OOM;
+  }
+  // the embedded gradient has sqrt 2 the norm of the complex one, and 2 n electrons per complex state
+  omm_options o;
+  omm_default_options(&o);
+  if (opt) o = *opt;
+  o.tol_grad *= std::sqrt(2.0);
+  o.ne_tol *= 2.0;
+  std::vector<omm_matrix> hm(count), sm(count);
+  for (int i = 0; i < count; ++i) {
+    hm[i] = RH[i].m;
+    sm[i] = RS[i].m;
+  }
+  const int rc = omm_init_batch(out, count, hm.data(), sm.data(), n2.data(), modes, etas, &o);
+  if (rc != OMM_OK) return rc;
+  omm_ctx* c = *out;
+  c->cplx = true;
+  c->zH = zh;
+  c->zS = zs;
+  c->zC.assign(count, ZStruct{});
+  return OMM_OK;
+}
+
 int omm_set_coeffs(omm_ctx* c, int32_t sys, const omm_matrix* C0) {
   if (!c) return OMM_ERR_ARG;
   if (sys < 0 || sys >= c->nsys) {
     c->err = "system index out of range";
     return OMM_ERR_ARG;
   }
+  if (c->cplx) {   // complex C0 of a k-point: set its real embedding
+    HostBlocks R;
+    ZStruct zs;
+    struct A { const omm_matrix* C0; HostBlocks* R; ZStruct* zs; } a{C0, &R, &zs};
+    const int rc = guard(c, [](omm_ctx*, void* v) -> int {
+      auto* q = (A*)v;
+      embed_complex(q->C0, *q->R, *q->zs);
+      return OMM_OK;
+    }, &a);
+    if (rc != OMM_OK) return rc;
+    const int rc2 = set_coeffs_real(c, sys, &R.m);
+    if (rc2 == OMM_OK) c->zC[sys] = zs;
+    return rc2;
+  }
+  return set_coeffs_real(c, sys, C0);
+}
+
+static int set_coeffs_real(omm_ctx* c, int32_t sys, const omm_matrix* C0) {
   struct A { int sys; const omm_matrix* C0; } a{sys, C0};
   return guard(c, [](omm_ctx* cc, void* v) -> int {
     auto* q = (A*)v;
@@ -1853,6 +2023,7 @@ int omm_set_coeffs(omm_ctx* c, int32_t sys, const omm_matrix* C0) {
 
 int omm_set_occupied(omm_ctx* c, int32_t sys, int64_t n_occupied) {
   if (!c) return OMM_ERR_ARG;
+  if (c->cplx) n_occupied *= 2;   // each complex state is two columns of the embedding
   if (sys < 0 || sys >= c->nsys || n_occupied < 1 || n_occupied > c->sys[sys].n) {
     c->err = "n_occupied must satisfy 1 <= n_occupied <= n_occ of the system";
     return OMM_ERR_ARG;
@@ -1969,7 +2140,23 @@ int omm_batch_minimize(omm_ctx* const* ctxs, int32_t count, omm_report* reports)
 
 // 2 C M C^T on S's pattern with M = ch H_W + cs (2I - S_W), for rho (Eq. 5) and rho_E
 // (Eq. 6 with the Kim correction of Sec. II)
+static int density_like_real(omm_ctx* c, int32_t sys, double* out, int32_t where, bool energy, const char* name);
+
+// complex contexts: the real result of the embedding, then its complex values (host memory)
 static int density_like(omm_ctx* c, int32_t sys, double* out, int32_t where, bool energy, const char* name) {
+  if (!c) return OMM_ERR_ARG;
+  if (!c->cplx) return density_like_real(c, sys, out, where, energy, name);
+  if (sys < 0 || sys >= c->nsys || !out || where != OMM_HOST) {
+    c->err = "bad argument (complex contexts return host memory)";
+    return OMM_ERR_ARG;
+  }
+  std::vector<double> tmp((size_t)std::max<int64_t>(1, c->sys[sys].S.nval));
+  const int rc = density_like_real(c, sys, tmp.data(), OMM_HOST, energy, name);
+  if (rc == OMM_OK) extract_complex(c->zS[sys], tmp.data(), out);
+  return rc;
+}
+
+static int density_like_real(omm_ctx* c, int32_t sys, double* out, int32_t where, bool energy, const char* name) {
   if (!c) return OMM_ERR_ARG;
   if (sys < 0 || sys >= c->nsys || !out || (where != OMM_HOST && where != OMM_DEVICE)) {
     c->err = "bad argument";
@@ -1999,6 +2186,10 @@ static int density_like(omm_ctx* c, int32_t sys, double* out, int32_t where, boo
 
 int omm_density_matrix_noalloc(omm_ctx* c, int32_t sys, double* rho_dev) {
   if (!c) return OMM_ERR_ARG;
+  if (c->cplx) {
+    c->err = "omm_density_matrix_noalloc: complex contexts use omm_density_matrix";
+    return OMM_ERR_ARG;
+  }
   if (sys < 0 || sys >= c->nsys || !rho_dev) {
     c->err = "bad argument";
     return OMM_ERR_ARG;
@@ -2042,7 +2233,22 @@ int omm_energy_density(omm_ctx* c, int32_t sys, double* rho_e, int32_t where) {
   return density_like(c, sys, rho_e, where, true, "omm_energy_density");
 }
 
+static int get_coeffs_real(omm_ctx* c, int32_t sys, double* C, int32_t where);
+
 int omm_get_coeffs(omm_ctx* c, int32_t sys, double* C, int32_t where) {
+  if (!c) return OMM_ERR_ARG;
+  if (!c->cplx) return get_coeffs_real(c, sys, C, where);
+  if (sys < 0 || sys >= c->nsys || !C || where != OMM_HOST) {
+    c->err = "bad argument (complex contexts return host memory)";
+    return OMM_ERR_ARG;
+  }
+  std::vector<double> tmp((size_t)std::max<int64_t>(1, c->sys[sys].C0.nval));
+  const int rc = get_coeffs_real(c, sys, tmp.data(), OMM_HOST);
+  if (rc == OMM_OK) extract_complex(c->zC[sys], tmp.data(), C);
+  return rc;
+}
+
+static int get_coeffs_real(omm_ctx* c, int32_t sys, double* C, int32_t where) {
   if (!c) return OMM_ERR_ARG;
   if (sys < 0 || sys >= c->nsys || !C || (where != OMM_HOST && where != OMM_DEVICE)) {
     c->err = "bad argument";
@@ -2065,7 +2271,48 @@ int omm_get_coeffs(omm_ctx* c, int32_t sys, double* C, int32_t where) {
   }, &a);
 }
 
+static int get_projected_real(omm_ctx* c, int32_t sys, double* HW, double* SW, int32_t where);
+
 int omm_get_projected(omm_ctx* c, int32_t sys, double* HW, double* SW, int32_t where) {
+  if (!c) return OMM_ERR_ARG;
+  if (!c->cplx) return get_projected_real(c, sys, HW, SW, where);
+  if (sys < 0 || sys >= c->nsys || where != OMM_HOST) {
+    c->err = "bad argument (complex contexts return host memory)";
+    return OMM_ERR_ARG;
+  }
+  // the embedded 2n x 2n matrices; complex column c = co[a] + o of wavefunction block a
+  // (width w) has its real part at embedded column 2 co[a] + o and its imaginary part
+  // at 2 co[a] + w + o
+  const ZStruct& zc = c->zC[sys];
+  const int64_t n2 = c->sys[sys].n, n = n2 / 2;
+  std::vector<int64_t> re(n), im(n);
+  {
+    int64_t co = 0;
+    for (int a = 0; a < zc.nbcol; ++a) {
+      for (int o = 0; o < zc.cbs[a]; ++o) {
+        re[co + o] = 2 * co + o;
+        im[co + o] = 2 * co + zc.cbs[a] + o;
+      }
+      co += zc.cbs[a];
+    }
+  }
+  std::vector<double> th(HW ? n2 * n2 : 1), ts(SW ? n2 * n2 : 1);
+  const int rc = get_projected_real(c, sys, HW ? th.data() : nullptr, SW ? ts.data() : nullptr, OMM_HOST);
+  if (rc != OMM_OK) return rc;
+  for (int k = 0; k < 2; ++k) {
+    double* out = k == 0 ? HW : SW;
+    const std::vector<double>& t = k == 0 ? th : ts;
+    if (!out) continue;
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t j = 0; j < n; ++j) {
+        out[2 * (i * n + j)] = t[re[i] * n2 + re[j]];
+        out[2 * (i * n + j) + 1] = t[im[i] * n2 + re[j]];
+      }
+  }
+  return OMM_OK;
+}
+
+static int get_projected_real(omm_ctx* c, int32_t sys, double* HW, double* SW, int32_t where) {
   if (!c) return OMM_ERR_ARG;
   if (sys < 0 || sys >= c->nsys || (where != OMM_HOST && where != OMM_DEVICE)) {
     c->err = "bad argument";
@@ -2113,6 +2360,12 @@ int omm_get_history(omm_ctx* c, int32_t sys, double* out, int64_t max_rows, int6
       OMM_HIP(hipMemcpyAsync(q->out, cc->d_hist + (size_t)q->sys * cc->opt.history_max * HCOLS,
                              n * HCOLS * sizeof(double), hipMemcpyDeviceToHost, cc->stream));
     OMM_HIP(hipStreamSynchronize(cc->stream));
+    if (cc->cplx)   // the complex system: half the embedded energy and quartic, gradient norm / sqrt 2
+      for (int64_t r = 0; r < n; ++r) {
+        double* h = q->out + r * HCOLS;
+        for (int k = 0; k < 6; ++k) h[k] *= 0.5;
+        h[7] *= std::sqrt(0.5);
+      }
     if (q->rows) *q->rows = n;
     return OMM_OK;
   }, &a);
@@ -2140,10 +2393,17 @@ int omm_query(const omm_ctx* cc, int32_t sys, omm_sizes* z) {
   for (int i = 0; i < c->nsys; ++i) {
     if (sys >= 0 && i != sys) continue;
     const SysHost& s = c->sys[i];
-    z->m += s.m;
-    z->n += s.n;
-    z->s_nval += s.S.nval;
-    z->c_nval += s.has_c0 ? s.C0.nval : 0;
+    if (c->cplx) {   // sizes of the complex system (values: complex numbers); work of the embedding
+      z->m += s.m / 2;
+      z->n += s.n / 2;
+      z->s_nval += c->zS[i].nval;
+      z->c_nval += s.has_c0 ? c->zC[i].nval : 0;
+    } else {
+      z->m += s.m;
+      z->n += s.n;
+      z->s_nval += s.S.nval;
+      z->c_nval += s.has_c0 ? s.C0.nval : 0;
+    }
     z->tiles_h += s.tiles_h;
     z->tiles_c += s.tiles_c;
     z->tiles_hc += s.tiles_hc;

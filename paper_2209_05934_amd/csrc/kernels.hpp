@@ -55,6 +55,14 @@ struct Bufs {   // every device buffer the iteration kernels touch
   int multi_c;                   // some system has more than FUSED_CTILES C tiles
   int n_th, n_tc, n_thc, n_tw;   // tile counts
   GroupView s1, s2, grad;         // grouped work lists of the three product steps
+  // Filtering that skips work (Sec. V): the direction products record per HC
+  // tile whether H D or S D kept a nonzero element (hcnz, bit 0 / bit 1), and
+  // the n x n projections of an iteration run on a copy of their work list in
+  // which a pair whose H D and S D tiles are both zero is marked absent
+  // (s2.ent points to that copy, s2_full is the list itself, which the
+  // start-up products use); hcnz == nullptr: no marking
+  GroupView s2_full;
+  int* hcnz;
   // FP64 masters
   double *H, *S, *C, *D, *G, *Gold, *HC, *SC, *HD, *SD, *H0, *S0, *X, *Y, *S2, *H2;
   // low-precision copies (float or bf16 storage, typed at launch) and FP32 product outputs
@@ -73,6 +81,9 @@ struct Bufs {   // every device buffer the iteration kernels touch
   int ks[3];                     // waves splitting one output tile: direction, n x n, gradient products
   int roll;                      // product kernels with the rolled work-list loop (multi-system contexts)
 };
+
+// the n x n work-list copy of an iteration: pairs whose H D and S D tiles are both zero marked absent
+void launch_mark_pairs(hipStream_t s, const Bufs& b);
 
 // one CG iteration step (all systems whose phase matches `mask`), arithmetic `prec`
 void launch_s1(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init);

@@ -15,6 +15,7 @@
 // follows from Eq. 3-4.  Tile products run on MFMA (FP64, FP32, or BF16 with
 // FP32 accumulation); every reduction feeding the line search is FP64 in a
 // fixed order.
+#include <algorithm>
 #include <cfloat>
 
 #include "tile_sched.hpp"
@@ -575,6 +576,27 @@ __global__ __launch_bounds__(256) void k_mirror_w(int ntw, int woff, const int* 
   }
 }
 
+// The work-list copy the n x n projections of an iteration run on (filtering
+// that skips work, Sec. V): in every entry (a C tile, then W - 1 HC tiles or
+// -1) an HC tile whose H D and S D tiles were both filtered to zero by the
+// direction products of this iteration becomes -1, so the projections neither
+// load it nor multiply by it.  Skipping an all-zero tile leaves every sum as it
+// is.  One thread per entry.
+template <int W>
+__global__ __launch_bounds__(256) void k_mark_pairs(int64_t nent, const int* __restrict__ ent,
+                                                  const int* __restrict__ hcnz, int* __restrict__ out) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < nent; e += (int64_t)gridDim.x * 256) {
+    const int* in = ent + e * W;
+    int* o = out + e * W;
+    o[0] = in[0];
+#pragma unroll
+    for (int w = 1; w < W; ++w) {
+      const int v = in[w];
+      o[w] = (v >= 0 && hcnz[v] == 0) ? -1 : v;
+    }
+  }
+}
+
 __global__ void k_init_finish(SysState* __restrict__ st, int nsys) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nsys) return;
@@ -801,6 +823,17 @@ void launch_mirror_w(hipStream_t s, const Bufs& b, int mask) {
   if (b.n_tw <= 0) return;
   LAUNCH(k_mirror_w, waves_grid(b.n_tw), dim3(256), s, b.n_tw, b.n_tc + b.n_thc, b.nsys > 1 ? b.upd_sys : nullptr,
          b.tw_row, b.tw_col, b.w_tr, b.st, mask, b.H0, b.S0);
+}
+
+void launch_mark_pairs(hipStream_t s, const Bufs& b) {
+  if (!b.hcnz || b.s2.nent <= 0 || b.s2.ent == b.s2_full.ent) return;
+  const unsigned grid = (unsigned)std::min<int64_t>((b.s2.nent + 255) / 256, 8192);
+  if (b.s2.NT == 1)
+    LAUNCH(k_mark_pairs<2>, dim3(grid), dim3(256), s, b.s2.nent, b.s2_full.ent, b.hcnz, (int*)b.s2.ent);
+  else if (b.s2.NT == 2)
+    LAUNCH(k_mark_pairs<3>, dim3(grid), dim3(256), s, b.s2.nent, b.s2_full.ent, b.hcnz, (int*)b.s2.ent);
+  else
+    LAUNCH(k_mark_pairs<5>, dim3(grid), dim3(256), s, b.s2.nent, b.s2_full.ent, b.hcnz, (int*)b.s2.ent);
 }
 
 void launch_init_finish(hipStream_t s, const Bufs& b) {

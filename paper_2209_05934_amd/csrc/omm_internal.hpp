@@ -102,6 +102,7 @@ struct PlanView {
 struct GroupView {
   int ngroups;
   int NT;
+  int64_t nent;       // entries of the list (rows of 1 + NT ints)
   const int* go0;
   const int* gn;
   const int64_t* gp;

@@ -148,7 +148,11 @@ static void s2_go(hipStream_t s, const Bufs& b, int mask, const TI* C, const TI*
 // one precision per object file (OMM_PREC 0: FP64, 1: FP32, 2: BF16)
 #if OMM_PREC == 0
 void launch_s2_p64(hipStream_t s, const Bufs& b, int mask, bool init) {
-  if (init) s2_go<double, double, double, 2>(s, b, mask, b.C, b.C, b.HC, b.SC, b.S0, b.H0, b.S2, b.H2);
+  if (init) {   // start-up products S0 = C^T S C, H0 = C^T H C run on the unmarked list
+    Bufs bf = b;
+    bf.s2 = b.s2_full;
+    s2_go<double, double, double, 2>(s, bf, mask, b.C, b.C, b.HC, b.SC, b.S0, b.H0, b.S2, b.H2);
+  }
   else s2_go<double, double, double, 4>(s, b, mask, b.C, b.D, b.HD, b.SD, b.X, b.Y, b.S2, b.H2);
 }
 #elif OMM_PREC == 1

@@ -31,6 +31,44 @@ __device__ void filter_tile(V& acc, int lane, const uint8_t* __restrict__ rseg,
                             const uint8_t* __restrict__ cseg, double eps2) {
   const int j = lane & 15, q = lane >> 4;
   const int clo = cseg[j], chi = cseg[16 + j];
+  // Common case, decided for the whole wave: every column block is an aligned
+  // pair of columns (two wavefunctions per atom) and every row block an aligned
+  // pair of rows, or the whole tile height.  Then a block's sum of squares takes
+  // three lane exchanges per register instead of a pass over the whole tile.
+  bool pairs = clo == (j & ~1) && chi == clo + 2;
+  if (rseg) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = Lay<V>::row(q, r), lo = row & ~1;
+      pairs = pairs && rseg[row] == lo && rseg[16 + row] == lo + 2;
+    }
+  }
+  if (__ballot(!pairs) == 0) {
+    double cp[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {   // the column pair (j, j ^ 1) of each register's row
+      const double sq = (double)acc[r] * (double)acc[r];
+      cp[r] = sq + __shfl_xor(sq, 1, 64);
+    }
+    double tot[4];
+    if (!rseg) {   // the whole tile height: all 16 rows (4 registers x 4 lane quads)
+      double t = (cp[0] + cp[1]) + (cp[2] + cp[3]);
+      t += __shfl_xor(t, 16, 64);
+      t += __shfl_xor(t, 32, 64);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) tot[r] = t;
+    } else if (sizeof(acc[0]) == 8) {   // FP64 layout: row 4r + q, its pair row in lane quad q ^ 1
+#pragma unroll
+      for (int r = 0; r < 4; ++r) tot[r] = cp[r] + __shfl_xor(cp[r], 16, 64);
+    } else {                            // FP32 layout: row 4q + r, its pair row in register r ^ 1
+#pragma unroll
+      for (int r = 0; r < 4; ++r) tot[r] = cp[r & ~1] + cp[r | 1];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (tot[r] < eps2) acc[r] = 0;
+    return;
+  }
   double rowpart[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {

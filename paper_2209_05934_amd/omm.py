@@ -85,6 +85,8 @@ def load(path: Optional[str] = None) -> C.CDLL:
         "omm_init": (I32, [C.POINTER(P), MP, MP, I64, I32, C.POINTER(omm_options)]),
         "omm_init_batch": (I32, [C.POINTER(P), I32, MP, MP, C.POINTER(I64), C.POINTER(I32),
                                  C.POINTER(D), C.POINTER(omm_options)]),
+        "omm_init_complex": (I32, [C.POINTER(P), I32, MP, MP, C.POINTER(I64), C.POINTER(I32),
+                                   C.POINTER(D), C.POINTER(omm_options)]),
         "omm_set_coeffs": (I32, [P, I32, MP]),
         "omm_minimize": (I32, [P, C.POINTER(omm_report)]),
         "omm_batch_minimize": (I32, [C.POINTER(P), I32, C.POINTER(omm_report)]),
@@ -116,7 +118,7 @@ def load(path: Optional[str] = None) -> C.CDLL:
     return lib
 
 
-EXPORTED = ("omm_default_options", "omm_init", "omm_init_batch", "omm_set_coeffs", "omm_minimize",
+EXPORTED = ("omm_default_options", "omm_init", "omm_init_batch", "omm_init_complex", "omm_set_coeffs", "omm_minimize",
             "omm_batch_minimize",
             "omm_density_matrix", "omm_density_matrix_noalloc", "omm_energy_density", "omm_get_coeffs", "omm_get_projected",
             "omm_get_history", "omm_query", "omm_set_occupied", "omm_set_preconditioner", "omm_update_hs",
@@ -144,7 +146,10 @@ class BlockArgs:
         self.row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
         self.col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
         self.val_off = np.ascontiguousarray(val_off, dtype=np.int64)
-        if isinstance(val, np.ndarray):
+        if isinstance(val, np.ndarray) and np.iscomplexobj(val):   # complex: interleaved (re, im) doubles
+            self.val = np.ascontiguousarray(val, dtype=np.complex128).view(np.float64)
+            vptr, nval, space = self.val.ctypes.data, self.val.size // 2, OMM_HOST
+        elif isinstance(val, np.ndarray):
             self.val = np.ascontiguousarray(val, dtype=np.float64)
             vptr, nval, space = self.val.ctypes.data, self.val.size, OMM_HOST
         else:   # device tensor
@@ -210,6 +215,23 @@ def omm_init_batch(Hs: Sequence[BlockArgs], Ss: Sequence[BlockArgs], n_occ: Sequ
     ctx = C.c_void_p()
     rc = load().omm_init_batch(C.byref(ctx), count, Harr, Sarr, narr, marr, earr,
                                C.byref(opt) if opt is not None else None)
+    _check(None, rc)
+    return ctx
+
+
+def omm_init_complex(Hs: Sequence[BlockArgs], Ss: Sequence[BlockArgs], n_occ: Sequence[int],
+                     modes: Sequence[int], etas: Optional[Sequence[float]] = None,
+                     opt: Optional[omm_options] = None):
+    """Complex Hermitian systems (BlockArgs over complex128 values, host memory)."""
+    count = len(Hs)
+    Harr = (omm_matrix * count)(*[h.struct for h in Hs])
+    Sarr = (omm_matrix * count)(*[s.struct for s in Ss])
+    narr = (C.c_int64 * count)(*[int(v) for v in n_occ])
+    marr = (C.c_int32 * count)(*[int(v) for v in modes])
+    earr = (C.c_double * count)(*[float(v) for v in etas]) if etas is not None else None
+    ctx = C.c_void_p()
+    rc = load().omm_init_complex(C.byref(ctx), count, Harr, Sarr, narr, marr, earr,
+                                 C.byref(opt) if opt is not None else None)
     _check(None, rc)
     return ctx
 

@@ -49,7 +49,12 @@ class Context:
         self.opt = options(**opts)
         self._H = [L.BlockArgs.from_block_matrix(p.H, p.H_val) for p in self.problems]
         self._S = [L.BlockArgs.from_block_matrix(p.S, p.S_val) for p in self.problems]
-        if len(self.problems) == 1:
+        self.complex = any(np.iscomplexobj(p.H.val) for p in self.problems)
+        if self.complex:    # k-points: complex Hermitian H, S (host values)
+            etas = [self.opt.eta if p.eta is None else p.eta for p in self.problems]
+            self.ctx = L.omm_init_complex(self._H, self._S, [p.n for p in self.problems],
+                                          [p.mode for p in self.problems], etas, self.opt)
+        elif len(self.problems) == 1:
             p = self.problems[0]
             if p.eta is not None:
                 self.opt.eta = p.eta
@@ -77,26 +82,37 @@ class Context:
         rc, reps = L.omm_minimize(self.ctx, self.count)
         return rc, reps
 
+    def _host_out(self, size: int, out):
+        # complex contexts return complex values: 2 doubles each, viewed as complex128
+        if out is not None:
+            return out, out
+        if self.complex:
+            buf = np.zeros(2 * size)
+            return buf, buf.view(np.complex128)
+        buf = np.zeros(size)
+        return buf, buf
+
     def density_matrix(self, sys: int = 0, out=None) -> np.ndarray:
-        if out is None:
-            out = np.zeros(self.problems[sys].S.val.size)
-        L.omm_density_matrix(self.ctx, sys, out)
-        return out
+        buf, res = self._host_out(self.problems[sys].S.val.size, out)
+        L.omm_density_matrix(self.ctx, sys, buf)
+        return res
 
     def energy_density(self, sys: int = 0, out=None) -> np.ndarray:
-        if out is None:
-            out = np.zeros(self.problems[sys].S.val.size)
-        L.omm_energy_density(self.ctx, sys, out)
-        return out
+        buf, res = self._host_out(self.problems[sys].S.val.size, out)
+        L.omm_energy_density(self.ctx, sys, buf)
+        return res
 
     def coeffs(self, sys: int = 0, out=None) -> np.ndarray:
-        if out is None:
-            out = np.zeros(self.problems[sys].C0.val.size)
-        L.omm_get_coeffs(self.ctx, sys, out)
-        return out
+        buf, res = self._host_out(self.problems[sys].C0.val.size, out)
+        L.omm_get_coeffs(self.ctx, sys, buf)
+        return res
 
     def projected(self, sys: int = 0):
         n = self.problems[sys].n
+        if self.complex:
+            HW, SW = np.zeros(2 * n * n), np.zeros(2 * n * n)
+            L.omm_get_projected(self.ctx, sys, HW, SW)
+            return HW.view(np.complex128).reshape(n, n), SW.view(np.complex128).reshape(n, n)
         HW, SW = np.zeros((n, n)), np.zeros((n, n))
         L.omm_get_projected(self.ctx, sys, HW, SW)
         return HW, SW

@@ -148,3 +148,32 @@ def test_null_pointers_rejected():
     assert lib.omm_init(None, None, None, 1, 0, None) == L.OMM_ERR_ARG
     assert lib.omm_minimize(None, None) == L.OMM_ERR_ARG
     lib.omm_destroy(None)
+
+
+def test_complex_init_rejects_bad_input_before_the_device():
+    # k-point contexts: the complex matrices are embedded on the host and checked
+    # there; a malformed one (or one in device memory) never reaches HIP
+    from ommgen.systems import cubic_spec, make_bloch_system
+    z = make_bloch_system(cubic_spec(3, 31, dense=True), (0.25, 0.0, 0.0))
+    H, S = _args(z.H), _args(z.S)
+    assert H.struct.nval == z.H.val.size and z.H.val.dtype == np.complex128
+
+    def init(Hb, Sb, n):
+        ctx = ctypes.c_void_p()
+        n_arr = (ctypes.c_int64 * 1)(n)
+        m_arr = (ctypes.c_int32 * 1)(L.OMM_DENSE)
+        rc = L.load().omm_init_complex(ctypes.byref(ctx), 1, ctypes.byref(Hb.struct), ctypes.byref(Sb.struct),
+                                       n_arr, m_arr, None, None)
+        assert not ctx.value
+        return rc, L.omm_last_error(None)
+
+    bad = z.H.val_off.copy()
+    bad[-1] = z.H.val.size
+    rc, msg = init(_args(z.H, val_off=bad), S, z.n)
+    assert rc == L.OMM_ERR_ARG and "val_off" in msg
+    rc, msg = init(H, S, 0)
+    assert rc == L.OMM_ERR_ARG and "n_occ" in msg
+    Hd = _args(z.H)
+    Hd.struct.memspace = L.OMM_DEVICE
+    rc, msg = init(Hd, S, z.n)
+    assert rc == L.OMM_ERR_ARG and "host" in msg

@@ -113,6 +113,20 @@ def test_sparse_filtered_trajectory_parity():
     ctx.close()
 
 
+def test_filtered_trajectory_where_whole_tiles_drop():
+    # at 1e-2 every block of some H D and S D tiles falls below the threshold, so the
+    # n x n projections skip those tiles (their pairs are marked absent); skipping an
+    # all-zero tile is exact, so the trajectory is still the oracle's
+    s = system("cubic5_sparse")
+    eps, k = 1e-2, 40
+    ctx, r = gpu_run(s, "sparse", max_iter=k, filter_eps=eps)
+    ref = oracle_run(s, "sparse", max_iter=k, tol_grad=1e-9, filter_eps=eps)
+    assert r.iters_total == k == ref.iterations
+    check_trajectory(ctx.history(0), ref)
+    assert np.max(np.abs(ctx.coeffs(0) - c_values(s, ref))) <= 1e-9
+    ctx.close()
+
+
 # every launch shape of every tile-product step (one step varied at a time, the
 # others at the library's choice) follows the oracle's trajectory
 SHAPES = [(step, nt, ks) for step in range(3) for nt in (1, 2, 4) for ks in (1, 2, 4, 8)
