@@ -29,7 +29,7 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s1(
   __shared__ V red[SP::RED * NA * 64];
   const int wave = wave_id(), lane = threadIdx.x & 63;
   const int grp = wave / KS, wk = wave - grp * KS;
-  const int g = xcd_block() * SP::G + grp;
+  const int g = xcd_block(P.xrun) * SP::G + grp;
   const bool valid = g < P.ngroups;
   constexpr int D = pipe_depth<TI>((ONE ? 1 : 2) + NT);
   // group record and work-list prefetch first; the system's phase, S = I flag

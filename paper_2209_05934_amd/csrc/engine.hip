@@ -101,12 +101,13 @@ struct GPlan {   // grouped work list of one product step
   int NT = 1;
   int ngroups = 0;
   int64_t nent = 0, npairs = 0;
+  int xrun = 16;
   int *gbase = nullptr, *go0 = nullptr, *gn = nullptr, *ent = nullptr;
   int64_t* gp = nullptr;
   int4* meta = nullptr;
   std::vector<int> hgbase;          // first group of each output row (nrows + 1)
   std::vector<int64_t> hpairs;      // prefix of tile pairs over groups (ngroups + 1)
-  GroupView view() const { return GroupView{ngroups, NT, nent, go0, gn, gp, ent, meta}; }
+  GroupView view() const { return GroupView{ngroups, NT, nent, xrun, go0, gn, gp, ent, meta}; }
 };
 
 }  // namespace
@@ -964,17 +965,26 @@ void prepare(omm_ctx* c) {
     else count_dense_work(s);
   }
   c->nchunks = (int)chunks.size();
-  // 2D-blocked group order of the product steps: blocks of 16 x 2 output tiles for
-  // the direction and gradient products, 8 x 8 for the n x n projections (measured
-  // at 4096 atoms: 2-4 % faster per kernel than row order); OMM_BLOCK_ORDER =
-  // "s1r,s1c,s2r,s2c,gr,gc" replaces the block shapes
+  // Group order and XCD runs of the product steps: the direction and gradient
+  // products take their groups in blocks of 16 x 2 output tiles, the n x n
+  // projections in row order, and each XCD takes runs of 96 consecutive
+  // workgroups (about the workgroups one XCD holds at a time), so the groups in
+  // flight on one XCD are neighbours and share operand tiles in its L2 while
+  // the eight XCDs work on neighbouring runs, whose shared tiles the memory-side
+  // cache keeps (measured at 4096 atoms: 3-4 % faster n x n projections than
+  // 8 x 8 blocks in runs of 16).  OMM_BLOCK_ORDER = "s1r,s1c,s2r,s2c,gr,gc" and
+  // OMM_XCD_RUN = "s1,s2,grad" replace the block shapes and run lengths.
   {
-    int bo[6] = {16, 2, 8, 8, 16, 2};
+    int bo[6] = {16, 2, 1, 1, 16, 2};
     if (const char* e = std::getenv("OMM_BLOCK_ORDER"))
       std::sscanf(e, "%d,%d,%d,%d,%d,%d", &bo[0], &bo[1], &bo[2], &bo[3], &bo[4], &bo[5]);
     const Pat* outs[3] = {&c->THC, &c->TW, &c->TC};
     for (int k = 0; k < 3; ++k)
       for (int q = 0; q < NPLAN; ++q) block_order(c, c->G[k][q], *outs[k], std::max(1, bo[2 * k]), std::max(1, bo[2 * k + 1]));
+    int xr[3] = {96, 96, 96};
+    if (const char* e = std::getenv("OMM_XCD_RUN")) std::sscanf(e, "%d,%d,%d", &xr[0], &xr[1], &xr[2]);
+    for (int k = 0; k < 3; ++k)
+      for (int q = 0; q < NPLAN; ++q) c->G[k][q].xrun = std::max(1, xr[k]);
   }
   c->chunks = dupload(c, chunks, true);
   c->d_info = dupload(c, c->h_info, true);

@@ -23,7 +23,7 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_grad(
   __shared__ V red[SP::RED * NT * 64];
   const int wave = wave_id(), lane = threadIdx.x & 63;
   const int grp = wave / KS, wk = wave - grp * KS;
-  const int g = xcd_block() * SP::G + grp;
+  const int g = xcd_block(P.xrun) * SP::G + grp;
   const bool valid = g < P.ngroups;
   constexpr int D = pipe_depth<TI>(2 + 2 * NT);
   int4 m = make_int4(0, 0, 0, 0);

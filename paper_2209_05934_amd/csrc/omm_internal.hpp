@@ -103,6 +103,7 @@ struct GroupView {
   int ngroups;
   int NT;
   int64_t nent;       // entries of the list (rows of 1 + NT ints)
+  int xrun;           // consecutive workgroups of a run on one XCD (block numbering)
   const int* go0;
   const int* gn;
   const int64_t* gp;

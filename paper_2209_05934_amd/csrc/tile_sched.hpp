@@ -103,7 +103,7 @@ __device__ void filter_tile(V& acc, int lane, const uint8_t* __restrict__ rseg,
 // waves; KS consecutive waves split the pair list of one output tile into KS
 // contiguous chunks and add their accumulators in a fixed tree through LDS, so
 // results are bitwise reproducible for a given KS.  Logical block ids are
-// renumbered so that runs of XCD_RUN consecutive ids (neighbouring output
+// renumbered so that runs of `run` consecutive ids (neighbouring output
 // tiles, which share operand tiles) run on one XCD while successive runs go to
 // successive XCDs: the hardware deals workgroups to the 8 XCDs round-robin, so
 // physical block p runs on XCD p % 8 as its (p / 8)-th block there.  Every
@@ -112,12 +112,11 @@ __device__ void filter_tile(V& acc, int lane, const uint8_t* __restrict__ rseg,
 // ranges, one per XCD (t / 8 blocks, one more for the first t % 8 XCDs), so the
 // groups of one output row stay on one XCD there too; the renumbering stays a
 // bijection on [0, gridDim.x).
-constexpr int XCD_RUN = 16;
-__device__ __forceinline__ int xcd_block() {
+__device__ __forceinline__ int xcd_block(int run) {
   const int nb = gridDim.x, p = blockIdx.x;
-  const int full = nb - nb % (8 * XCD_RUN);
+  const int full = nb - nb % (8 * run);
   const int x = p & 7, k = p >> 3;
-  if (p < full) return ((k / XCD_RUN) * 8 + x) * XCD_RUN + (k % XCD_RUN);
+  if (p < full) return ((k / run) * 8 + x) * run + (k % run);
   const int t = nb - full, q = t >> 3, r = t & 7;
   return full + x * q + min(x, r) + ((p - full) >> 3);
 }
