@@ -21,7 +21,7 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s1(
     GroupView P, const int* __restrict__ ocol, const SysInfo* __restrict__ info, const SysState* __restrict__ st, int mask, const TI* __restrict__ Hm,
     const TI* __restrict__ Sm, const TI* __restrict__ Bm, TO* __restrict__ O1, TO* __restrict__ O2,
     const int* __restrict__ hc_to_c, const uint8_t* __restrict__ wseg, const double* __restrict__ Gold,
-    double* __restrict__ zpart, int trans_out, int* __restrict__ hcnz) {
+    double* __restrict__ zpart, int* __restrict__ hcnz) {
   typedef typename Acc<TI>::V V;
   typedef Split<KS> SP;
   constexpr int W = 1 + NT;
@@ -145,8 +145,8 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s1(
       TO* o1 = O1 + (size_t)t * TE;
       TO* o2 = O2 + (size_t)t * TE;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {   // HC, SC (trans_out) are stored with each tile transposed
-        const int e = trans_out ? out_off_t<V>(lane, r) : out_off<V>(lane, r);
+      for (int r = 0; r < 4; ++r) {
+        const int e = out_off<V>(lane, r);
         o1[e] = (TO)a1[r];
         o2[e] = (TO)a2[r];
       }
@@ -158,24 +158,24 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s1(
 
 template <typename TI, typename TO, bool ONE = false>
 static void s1_go(hipStream_t s, const Bufs& b, int mask, const TI* H, const TI* S, const TI* B, TO* O1, TO* O2,
-                  int trans_out = 0, int* hcnz = nullptr) {
+                  int* hcnz = nullptr) {
   if (b.s1.ngroups <= 0) return;
   nt_ks<0>(b.s1.NT, b.ks[0], [&](auto ntc, auto ksc) {
     constexpr int N_ = decltype(ntc)::value, K_ = decltype(ksc)::value;
     if (b.roll)
       LAUNCH((k_s1<TI, TO, K_, N_, ONE, true>), grid_for<K_>(b.s1.ngroups), block_for<K_>(), s, b.s1, b.thc_col,
-             b.info, b.st, mask, H, S, B, O1, O2, b.hc_to_c, b.wseg, b.Gold, b.zpart, trans_out, hcnz);
+             b.info, b.st, mask, H, S, B, O1, O2, b.hc_to_c, b.wseg, b.Gold, b.zpart, hcnz);
     else
       LAUNCH((k_s1<TI, TO, K_, N_, ONE, false>), grid_for<K_>(b.s1.ngroups), block_for<K_>(), s, b.s1, b.thc_col,
-             b.info, b.st, mask, H, S, B, O1, O2, b.hc_to_c, b.wseg, b.Gold, b.zpart, trans_out, hcnz);
+             b.info, b.st, mask, H, S, B, O1, O2, b.hc_to_c, b.wseg, b.Gold, b.zpart, hcnz);
   });
 }
 
 // one precision per object file (OMM_PREC 0: FP64, 1: FP32, 2: BF16)
 #if OMM_PREC == 0
 void launch_s1_p64(hipStream_t s, const Bufs& b, int mask, bool init) {
-  if (init) s1_go<double, double>(s, b, mask, b.H, b.S, b.C, b.HC, b.SC, 1);
-  else s1_go<double, double>(s, b, mask, b.H, b.S, b.D, b.HD, b.SD, 0, b.hcnz);
+  if (init) s1_go<double, double>(s, b, mask, b.H, b.S, b.C, b.HD, b.SD);   // H C, S C (row-major tiles)
+  else s1_go<double, double>(s, b, mask, b.H, b.S, b.D, b.HD, b.SD, b.hcnz);
 }
 
 void launch_precon(hipStream_t s, const Bufs& b, int mask) {
@@ -183,11 +183,11 @@ void launch_precon(hipStream_t s, const Bufs& b, int mask) {
 }
 #elif OMM_PREC == 1
 void launch_s1_p32(hipStream_t s, const Bufs& b, int mask) {
-  s1_go<float, float>(s, b, mask, (const float*)b.Hl, (const float*)b.Sl, (const float*)b.Dl, b.HDf, b.SDf, 0, b.hcnz);
+  s1_go<float, float>(s, b, mask, (const float*)b.Hl, (const float*)b.Sl, (const float*)b.Dl, b.HDf, b.SDf, b.hcnz);
 }
 #else
 void launch_s1_pbf(hipStream_t s, const Bufs& b, int mask) {
-  s1_go<bf16, float>(s, b, mask, (const bf16*)b.Hl, (const bf16*)b.Sl, (const bf16*)b.Dl, b.HDf, b.SDf, 0, b.hcnz);
+  s1_go<bf16, float>(s, b, mask, (const bf16*)b.Hl, (const bf16*)b.Sl, (const bf16*)b.Dl, b.HDf, b.SDf, b.hcnz);
 }
 #endif
 

@@ -152,7 +152,7 @@ struct omm_ctx {
   int nsys = 0;
   std::vector<SysHost> sys;
   int NB = 0, NW = 0;
-  Pat TH, TC, TCt, THC, TW, TCM;
+  Pat TH, TC, TCt, THC, TW;
   Plan Pcm, Prho;
   GPlan G[3][NPLAN];  // product steps (direction, n x n, gradient) x group widths PLAN_NT
   int sel[3] = {0, 0, 0};
@@ -877,7 +877,6 @@ void prepare(omm_ctx* c) {
     At.ti = nullptr;   // pattern only
     sym_product(c, c->TW, c->NW, At, c->THC, c->win_ww);
   }
-  sym_product(c, c->TCM, c->NB, c->TC, c->TW, c->win_bw);
   // (col, row) of each n x n tile, with rows/cols in the same WF index space
   c->w_tr = dalloc<int>(c, c->TW.nnz, true);
   find_tiles(st, c->TW.nnz, c->TW.ci, c->TW.row, c->TW.view(), c->w_tr);
@@ -900,8 +899,12 @@ void prepare(omm_ctx* c) {
       }
     }
   }
-  make_plan(c, c->Pcm, c->TCM, c->TC.view(), c->TW.view(), c->win_bw);
-  make_plan(c, c->Prho, c->TH, c->TCM.view(), c->TCt.view(), c->win_bb);
+  // density matrix rho = 2 C M C^T on H's pattern (Eq. 5): rho(b, b') sums
+  // CM(b, g) C(b', g) over the WF tiles g of C's row b', and with H(b, b') != 0
+  // every such (b, g) lies in the pattern of H C, so CM = C M is formed on the
+  // HC pattern alone (a quarter of the full C M pattern at 4096 atoms)
+  make_plan(c, c->Pcm, c->THC, c->TC.view(), c->TW.view(), c->win_bw);
+  make_plan(c, c->Prho, c->TH, c->THC.view(), c->TCt.view(), c->win_bb);
   // lookups
   c->c_in_hc = dalloc<int>(c, c->TC.nnz, true);
   find_tiles(st, c->TC.nnz, c->TC.row, c->TC.ci, c->THC.view(), c->c_in_hc);
@@ -1075,7 +1078,7 @@ void prepare(omm_ctx* c) {
   b.nsys = c->nsys;
   b.eps2 = 0.0;
   c->tuned = false;
-  c->CM = dalloc<double>(c, std::max<int64_t>(1, c->TCM.nnz) * TE, true);
+  c->CM = dalloc<double>(c, std::max<int64_t>(1, c->THC.nnz) * TE, true);
   c->rho = dalloc<double>(c, std::max<int64_t>(1, c->TH.nnz) * TE, true);
   bool any_chol = false;
   for (auto& s : c->sys) any_chol |= s.mode == OMM_DENSE_CHOLESKY;
@@ -1314,6 +1317,7 @@ void init_sequence(omm_ctx* c) {
   const CGParams prm = params(c);
   launch_s1(s, b, P64, PH_INIT, true);
   launch_s2(s, b, P64, PH_INIT, true);
+  launch_hc_from_hd(s, b, PH_INIT);
   launch_mirror_w(s, b, PH_INIT);
   launch_traces(s, b, P64, PH_INIT, true, LS_INIT, prm);
   launch_grad(s, b, P64, PH_INIT, true);
@@ -2183,7 +2187,7 @@ static int density_like_real(omm_ctx* c, int32_t sys, double* out, int32_t where
     hipStream_t st = cc->stream;
     const double* C = current_c(cc, q->sys);
     const double ch = q->energy ? 1.0 : 0.0, cs = q->energy ? s.eta : 1.0;
-    launch_cm(st, cc->Pcm.view(), cc->TCM.row, cc->brow_sys, q->sys, C, cc->b.S0, cc->b.H0, ch, cs, cc->TW.row,
+    launch_cm(st, cc->Pcm.view(), cc->THC.row, cc->brow_sys, q->sys, C, cc->b.S0, cc->b.H0, ch, cs, cc->TW.row,
               cc->TW.ci, cc->CM);
     launch_rho(st, cc->Prho.view(), cc->TH.row, cc->brow_sys, q->sys, cc->CM, C, cc->rho);
     std::vector<void*> tmp;
@@ -2208,7 +2212,7 @@ int omm_density_matrix_noalloc(omm_ctx* c, int32_t sys, double* rho_dev) {
     c->err = "omm_minimize must run before omm_density_matrix_noalloc";
     return OMM_ERR_STATE;
   }
-  const size_t need = (size_t)std::max<int64_t>(1, c->TCM.nnz) + (size_t)std::max<int64_t>(1, c->TH.nnz);
+  const size_t need = (size_t)std::max<int64_t>(1, c->THC.nnz) + (size_t)std::max<int64_t>(1, c->TH.nnz);
   if (need > NOALLOC_TILES) {
     c->err = "omm_density_matrix_noalloc: the context needs " + std::to_string(need) +
              " scratch tiles of 16 x 16 doubles, more than the " + std::to_string(NOALLOC_TILES) +
@@ -2223,10 +2227,10 @@ int omm_density_matrix_noalloc(omm_ctx* c, int32_t sys, double* rho_dev) {
     if (dev != cc->dev) throw ArgError("the context's device must be current");
     SysHost& s = cc->sys[q->sys];
     hipStream_t st = cc->stream;
-    double* CM = cc->scratch_dev;                                            // TCM tiles, then
-    double* rho = cc->scratch_dev + (size_t)std::max<int64_t>(1, cc->TCM.nnz) * TE;   // H-pattern tiles
+    double* CM = cc->scratch_dev;                                            // HC-pattern tiles, then
+    double* rho = cc->scratch_dev + (size_t)std::max<int64_t>(1, cc->THC.nnz) * TE;   // H-pattern tiles
     const double* C = current_c(cc, q->sys);
-    launch_cm(st, cc->Pcm.view(), cc->TCM.row, cc->brow_sys, q->sys, C, cc->b.S0, cc->b.H0, 0.0, 1.0, cc->TW.row,
+    launch_cm(st, cc->Pcm.view(), cc->THC.row, cc->brow_sys, q->sys, C, cc->b.S0, cc->b.H0, 0.0, 1.0, cc->TW.row,
               cc->TW.ci, CM);
     launch_rho(st, cc->Prho.view(), cc->TH.row, cc->brow_sys, q->sys, CM, C, rho);
     launch_gather(st, blkmap(s.mh, s.s_voff, s, false, cc->TH), rho, q->out);

@@ -111,6 +111,8 @@ void launch_beta(hipStream_t s, const Bufs& b, int mask, bool init, const CGPara
 // beta (systems of at most FUSED_CTILES C tiles: in place), D = -G + beta D, G_old = G
 void launch_update_d(hipStream_t s, const Bufs& b, Prec prec, int mask, bool init, const CGParams& prm);
 void launch_init_finish(hipStream_t s, const Bufs& b);
+// start-up: HC, SC (tiles stored transposed) from the H C, S C products formed in H D, S D
+void launch_hc_from_hd(hipStream_t s, const Bufs& b, int mask);
 // H_W, S_W made symmetric from their upper triangle (start-up products)
 void launch_mirror_w(hipStream_t s, const Bufs& b, int mask);
 void launch_cast_state(hipStream_t s, const Bufs& b, Prec prec, int mask);   // C, HC, SC, H0, S0 copies

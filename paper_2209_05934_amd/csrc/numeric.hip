@@ -576,6 +576,28 @@ __global__ __launch_bounds__(256) void k_mirror_w(int ntw, int woff, const int* 
   }
 }
 
+// Start-up: H C and S C were formed into the H D and S D tiles (row-major, the
+// layout the n x n projections read down columns); the maintained HC and SC are
+// stored with each tile transposed, the layout the gradient products read down
+// columns.  One wave per HC tile of a system in the masked phase.
+__global__ __launch_bounds__(256) void k_hc_from_hd(int nhc, int hoff, const int* __restrict__ upd_sys,
+                                                  const SysState* __restrict__ st, int mask,
+                                                  const double* __restrict__ HD, const double* __restrict__ SD,
+                                                  double* __restrict__ HC, double* __restrict__ SC) {
+  const int t = blockIdx.x * 4 + wave_id();
+  if (t >= nhc) return;
+  const int s = upd_sys ? upd_sys[hoff + t] : 0;
+  if (!on(st, s, mask)) return;
+  const int lane = threadIdx.x & 63;
+  const size_t base = (size_t)t * TE;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {   // element e = 64 i + lane: row e / 16, column e % 16
+    const int e = 64 * i + lane, r = e >> 4, c = e & 15;
+    HC[base + c * 16 + r] = HD[base + e];
+    SC[base + c * 16 + r] = SD[base + e];
+  }
+}
+
 // The work-list copy the n x n projections of an iteration run on (filtering
 // that skips work, Sec. V): in every entry (a C tile, then W - 1 HC tiles or
 // -1) an HC tile whose H D and S D tiles were both filtered to zero by the
@@ -823,6 +845,12 @@ void launch_mirror_w(hipStream_t s, const Bufs& b, int mask) {
   if (b.n_tw <= 0) return;
   LAUNCH(k_mirror_w, waves_grid(b.n_tw), dim3(256), s, b.n_tw, b.n_tc + b.n_thc, b.nsys > 1 ? b.upd_sys : nullptr,
          b.tw_row, b.tw_col, b.w_tr, b.st, mask, b.H0, b.S0);
+}
+
+void launch_hc_from_hd(hipStream_t s, const Bufs& b, int mask) {
+  if (b.n_thc <= 0) return;
+  LAUNCH(k_hc_from_hd, waves_grid(b.n_thc), dim3(256), s, b.n_thc, b.n_tc, b.nsys > 1 ? b.upd_sys : nullptr, b.st,
+         mask, b.HD, b.SD, b.HC, b.SC);
 }
 
 void launch_mark_pairs(hipStream_t s, const Bufs& b) {

@@ -64,13 +64,8 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s2(
 #pragma unroll
           for (int u = 0; u < NT; ++u) {
             const size_t bt = (size_t)max(id[1 + u], 0) * TE;
-            if (NPROD == 4) {
-              ld_col(f.hd[u], HDm + bt, lane);
-              ld_col(f.sd[u], SDm + bt, lane);
-            } else {   // HC, SC: tiles stored transposed
-              ld_row(f.hd[u], HDm + bt, lane);
-              ld_row(f.sd[u], SDm + bt, lane);
-            }
+            ld_col(f.hd[u], HDm + bt, lane);
+            ld_col(f.sd[u], SDm + bt, lane);
           }
         },
         [&](const Stage& f, const int (&id)[W]) {
@@ -148,10 +143,11 @@ static void s2_go(hipStream_t s, const Bufs& b, int mask, const TI* C, const TI*
 // one precision per object file (OMM_PREC 0: FP64, 1: FP32, 2: BF16)
 #if OMM_PREC == 0
 void launch_s2_p64(hipStream_t s, const Bufs& b, int mask, bool init) {
-  if (init) {   // start-up products S0 = C^T S C, H0 = C^T H C run on the unmarked list
+  if (init) {   // start-up products S0 = C^T S C, H0 = C^T H C (S C, H C in the S D, H D
+                // tiles, row-major) run on the unmarked list
     Bufs bf = b;
     bf.s2 = b.s2_full;
-    s2_go<double, double, double, 2>(s, bf, mask, b.C, b.C, b.HC, b.SC, b.S0, b.H0, b.S2, b.H2);
+    s2_go<double, double, double, 2>(s, bf, mask, b.C, b.C, b.HD, b.SD, b.S0, b.H0, b.S2, b.H2);
   }
   else s2_go<double, double, double, 4>(s, b, mask, b.C, b.D, b.HD, b.SD, b.X, b.Y, b.S2, b.H2);
 }
