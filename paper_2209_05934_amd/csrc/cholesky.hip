@@ -214,13 +214,18 @@ void chol_solve_lt(hipStream_t s, const double* L, int lbase, int RT, const doub
     CLAUNCH(k_trsm_bwd_t, dim3((WT + 3) / 4), L, lbase, RT, Linv, Cin, Cout, cbase, WT, I);
 }
 
+void chol_lower_inverse(hipStream_t s, const double* L, int lbase, int RT, const double* Linv, const double* Id,
+                        double* X) {
+  for (int I = 0; I < RT; ++I)
+    CLAUNCH(k_trsm_fwd, dim3((RT + 3) / 4), L, lbase, RT, Linv, Id, 0, 0, X, 0, RT, I);
+}
+
 // P = (L L^T)^-1 = L^-T (L^-1 I) on a dense RT x RT grid at offset 0: forward
 // substitution against the identity grid Id, then backward substitution with
 // L^T (the explicit inverse of kinetic preconditioning, Eq. 7)
 void chol_inverse(hipStream_t s, const double* L, int RT, const double* Linv, const double* Id, double* work,
                   double* P) {
-  for (int I = 0; I < RT; ++I)
-    CLAUNCH(k_trsm_fwd, dim3((RT + 3) / 4), L, 0, RT, Linv, Id, 0, 0, work, 0, RT, I);
+  chol_lower_inverse(s, L, 0, RT, Linv, Id, work);
   chol_solve_lt(s, L, 0, RT, Linv, work, P, 0, RT);
 }
 

@@ -69,6 +69,7 @@ struct SysHost {
   int64_t* s_voff = nullptr;
   double* c0_dev = nullptr;
   double* Linv = nullptr;
+  double* Lfull_inv = nullptr;   // L^-1 as a dense tile grid (C = L^-T C~ in one product)
   int* chol_status = nullptr;
   int64_t c_nval = 0;
   // work counts
@@ -600,6 +601,12 @@ void shift_reduce(omm_ctx* c, int i) {
     throw OomError("Cholesky work buffer");
   }
   chol_reduce_h(st, c->S, h0, s.RT, s.Linv, c->H, h0, work);
+  // L^-1 once (forward substitution against the identity, in the work grid),
+  // so that every back-transform C = L^-T C~ is a single tile product
+  if (!s.Lfull_inv) s.Lfull_inv = dalloc<double>(c, (size_t)s.RT * s.RT * TE, false);
+  OMM_HIP(hipMemsetAsync(work, 0, (size_t)s.RT * s.RT * TE * sizeof(double), st));
+  launch_pad_identity(st, work, 0, s.RT, 0);
+  chol_lower_inverse(st, c->S, h0, s.RT, s.Linv, work, s.Lfull_inv);
   OMM_HIP(hipStreamSynchronize(st));
   (void)hipFree(work);
 }
@@ -1692,7 +1699,7 @@ const double* current_c(omm_ctx* c, int sys) {
   SysHost& s = c->sys[sys];
   if (s.mode != OMM_DENSE_CHOLESKY) return c->b.C;
   const SysInfo& f = c->h_info[sys];
-  chol_solve_lt(c->stream, c->S, f.h0, s.RT, s.Linv, c->b.C, c->Cb, f.c0, s.WT);
+  chol_apply_lt(c->stream, s.Lfull_inv, 0, s.RT, c->b.C, c->Cb, f.c0, s.WT);   // (L^-1)^T C~
   return c->Cb;
 }
 

@@ -166,5 +166,7 @@ void chol_solve_lt(hipStream_t s, const double* L, int lbase, int RT, const doub
                    double* Cout, int cbase, int WT);   // Cout = L^-T Cin
 void chol_inverse(hipStream_t s, const double* L, int RT, const double* Linv, const double* Id, double* work,
                   double* P);   // P = (L L^T)^-1 on a grid at offset 0
+void chol_lower_inverse(hipStream_t s, const double* L, int lbase, int RT, const double* Linv, const double* Id,
+                        double* X);   // X = L^-1 (lower triangular) on a grid at offset 0, Id the identity grid
 
 }  // namespace omm
