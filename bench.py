@@ -101,6 +101,38 @@ MEASURED_TRAFFIC = {
     ("cubic4_dense", "fp64", 2, 4, 1): (5.8147e+06, "4f4585e2f31cc914"),
     ("cubic4_dense", "fp64", 2, 4, 2): (5.7666e+06, "4f4585e2f31cc914"),
     ("cubic4_dense", "fp64", 2, 4, 4): (5.8821e+06, "4f4585e2f31cc914"),
+    ("cubic16_mixed", "fp64", 0, 1, 1): (2.3555e+10, "fee259386d9a7875"),
+    ("cubic16_mixed", "fp64", 0, 1, 2): (2.1094e+10, "fee259386d9a7875"),
+    ("cubic16_mixed", "fp64", 0, 1, 4): (1.9359e+10, "fee259386d9a7875"),
+    ("cubic16_mixed", "fp64", 0, 1, 8): (1.7973e+10, "fee259386d9a7875"),
+    ("cubic16_mixed", "fp64", 0, 2, 1): (1.9884e+10, "fee259386d9a7875"),
+    ("cubic16_mixed", "fp64", 0, 2, 2): (1.7804e+10, "fee259386d9a7875"),
+    ("cubic16_mixed", "fp64", 0, 2, 4): (1.8124e+10, "fee259386d9a7875"),
+    ("cubic16_mixed", "fp64", 0, 2, 8): (1.7241e+10, "fee259386d9a7875"),
+    ("cubic16_mixed", "fp64", 0, 4, 1): (1.4678e+10, "fee259386d9a7875"),
+    ("cubic16_mixed", "fp64", 0, 4, 2): (1.4406e+10, "fee259386d9a7875"),
+    ("cubic16_mixed", "fp64", 0, 4, 4): (1.6218e+10, "fee259386d9a7875"),
+    ("cubic16_mixed", "fp64", 1, 1, 1): (5.5683e+10, "34587538f1ff5b2c"),
+    ("cubic16_mixed", "fp64", 1, 1, 2): (5.4447e+10, "34587538f1ff5b2c"),
+    ("cubic16_mixed", "fp64", 1, 1, 4): (5.4191e+10, "34587538f1ff5b2c"),
+    ("cubic16_mixed", "fp64", 1, 1, 8): (5.3463e+10, "34587538f1ff5b2c"),
+    ("cubic16_mixed", "fp64", 1, 2, 1): (5.5339e+10, "34587538f1ff5b2c"),
+    ("cubic16_mixed", "fp64", 1, 2, 2): (5.4137e+10, "34587538f1ff5b2c"),
+    ("cubic16_mixed", "fp64", 1, 2, 4): (5.3796e+10, "34587538f1ff5b2c"),
+    ("cubic16_mixed", "fp64", 1, 4, 1): (5.7109e+10, "34587538f1ff5b2c"),
+    ("cubic16_mixed", "fp64", 1, 4, 2): (5.5666e+10, "34587538f1ff5b2c"),
+    ("cubic16_mixed", "fp64", 1, 4, 4): (5.4750e+10, "34587538f1ff5b2c"),
+    ("cubic16_mixed", "fp64", 2, 1, 1): (2.4120e+10, "d22014008889e396"),
+    ("cubic16_mixed", "fp64", 2, 1, 2): (3.1782e+10, "d22014008889e396"),
+    ("cubic16_mixed", "fp64", 2, 1, 4): (4.0030e+10, "d22014008889e396"),
+    ("cubic16_mixed", "fp64", 2, 1, 8): (3.8186e+10, "d22014008889e396"),
+    ("cubic16_mixed", "fp64", 2, 2, 1): (3.7021e+10, "d22014008889e396"),
+    ("cubic16_mixed", "fp64", 2, 2, 2): (3.3489e+10, "d22014008889e396"),
+    ("cubic16_mixed", "fp64", 2, 2, 4): (3.5007e+10, "d22014008889e396"),
+    ("cubic16_mixed", "fp64", 2, 2, 8): (3.4275e+10, "d22014008889e396"),
+    ("cubic16_mixed", "fp64", 2, 4, 1): (1.9879e+10, "d22014008889e396"),
+    ("cubic16_mixed", "fp64", 2, 4, 2): (2.2211e+10, "d22014008889e396"),
+    ("cubic16_mixed", "fp64", 2, 4, 4): (2.8669e+10, "d22014008889e396"),
 }
 
 
