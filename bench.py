@@ -18,6 +18,7 @@ one JSON line.
 from __future__ import annotations
 
 import argparse
+import collections
 from dataclasses import replace
 import tempfile
 import json
@@ -385,6 +386,12 @@ def batch_main(args):
         "speedup_vs_sequential": (it_b / dt_b) / (it_s / dt_s),
         "max_abs_dE_per_atom_batch_vs_sequential": dE,
         "avg_alg_flops_per_iter_per_system": flops_iter_avg,
+        # a fixed iteration budget, not a fixed accuracy: how far each system of the batch got
+        "status_counts": dict(collections.Counter(L.omm_status_str(r.status) for r in reps_b)),
+        "grad_norm_max": max(r.grad_norm for r in reps_b),
+        "per_system": [{"atoms": int(s.natoms), "dense": bool(s.spec.dense), "iters": int(r.iters_total),
+                        "iters_fp64": int(r.iters_fp64), "status": L.omm_status_str(r.status),
+                        "grad_norm": r.grad_norm} for r, s in zip(reps_b, systems)],
         "roofline": None, "cpu_baseline": None,
     }
     for c in singles:
@@ -632,7 +639,8 @@ def main():
         "dtype": {"fp64": "f64", "fp32": "f32 products, f64 traces/line search",
                   "bf16": "bf16 products (f32 accumulate), f64 traces/line search"}[args.precision],
         "data": "synthetic",
-        "config": {"workload": args.workload + ": " + wl["desc"], "mode": wl["mode"],
+        "config": {"workload": args.workload + ": " + wl["desc"].replace("filter 1e-6", f"filter {spec.filter_eps:g}"),
+                   "mode": wl["mode"],
                    "filter_eps": spec.filter_eps if wl["mode"] == "sparse" else None,
                    "precision": args.precision, "N_basis": int(system.m), "N_occ": int(system.n_occupied),
                    "N_wf": int(system.n), "atoms": int(system.natoms)},

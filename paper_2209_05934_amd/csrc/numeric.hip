@@ -325,16 +325,19 @@ __global__ __launch_bounds__(256) void k_update(int nc, int nhc, int ntot, const
       u[i] = HC[ot + 16 * i]; v[i] = SC[ot + 16 * i]; p[i] = (double)HD[o + i]; q[i] = (double)SD[o + i];
     }
   } else {
+    // H_W and S_W stay symmetric, and so do their increments: the wave of a tile
+    // on or above the diagonal also writes the transposed result into the mirror
+    // tile (the sum Y + Y^T commutes bitwise), and waves below the diagonal stop
     const int tt = wtr[t];
+    if (tt < t) return;
     const size_t ot = (size_t)tt * TE + c0 * 16 + r;
-    const bool mir = tt < t;   // H2, S2 below the diagonal: transpose of the mirror tile
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       u[i] = H0[o + i]; v[i] = S0[o + i];
       p[i] = (double)Y[o + i] + (double)Y[ot + 16 * i];
       q[i] = (double)X[o + i] + (double)X[ot + 16 * i];
-      w[i] = (double)(mir ? H2[ot + 16 * i] : H2[o + i]);
-      z[i] = (double)(mir ? S2[ot + 16 * i] : S2[o + i]);
+      w[i] = (double)H2[o + i];
+      z[i] = (double)S2[o + i];
     }
   }
   double x = 0.0;
@@ -369,6 +372,8 @@ __global__ __launch_bounds__(256) void k_update(int nc, int nhc, int ntot, const
       }
     }
   } else {
+    const int tt = wtr[t];
+    const size_t ot = (size_t)tt * TE + c0 * 16 + r;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const double h = u[i] + x * p[i] + x * x * w[i];
@@ -378,6 +383,14 @@ __global__ __launch_bounds__(256) void k_update(int nc, int nhc, int ntot, const
       if (LOW) {
         H0l[o + i] = cvt<TL, double>(h);
         S0l[o + i] = cvt<TL, double>(g);
+      }
+      if (tt != t) {   // element (r, c0 + i) of the mirror tile's transpose
+        H0[ot + 16 * i] = h;
+        S0[ot + 16 * i] = g;
+        if (LOW) {
+          H0l[ot + 16 * i] = cvt<TL, double>(h);
+          S0l[ot + 16 * i] = cvt<TL, double>(g);
+        }
       }
     }
   }
