@@ -427,7 +427,8 @@ def to_accuracy_legs(args, system, spec, Hv, Sv, C0v, stream):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ctx.set_coeffs(0, system.C0, C0v)
-        rc, reps = ctx.minimize()
+        reps = (L.omm_report * 1)()      # a failed solve (e.g. no line minimum) is reported, not raised
+        L.load().omm_minimize(ctx.ctx, reps)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         ctx.close()
@@ -539,7 +540,8 @@ def main():
 
     def step():
         ctx.set_coeffs(0, system.C0, C0v)
-        rc, reps = ctx.minimize()
+        reps = (LL.omm_report * 1)()     # a failed solve (e.g. no line minimum) shows in "status"
+        LL.load().omm_minimize(ctx.ctx, reps)
         LL.omm_density_matrix(ctx.ctx, 0, rho)
         return reps[0]
 
