@@ -2194,9 +2194,10 @@ static int density_like_real(omm_ctx* c, int32_t sys, double* out, int32_t where
     hipStream_t st = cc->stream;
     const double* C = current_c(cc, q->sys);
     const double ch = q->energy ? 1.0 : 0.0, cs = q->energy ? s.eta : 1.0;
-    launch_cm(st, cc->Pcm.view(), cc->THC.row, cc->brow_sys, q->sys, C, cc->b.S0, cc->b.H0, ch, cs, cc->TW.row,
-              cc->TW.ci, cc->CM);
-    launch_rho(st, cc->Prho.view(), cc->TH.row, cc->brow_sys, q->sys, cc->CM, C, cc->rho);
+    // the H D tiles serve as scratch for C's transposed tiles (recomputed by every iteration)
+    launch_cm(st, cc->Pcm.view(), cc->THC.row, cc->brow_sys, q->sys, C, cc->b.n_tc, cc->b.HD, cc->b.S0, cc->b.H0,
+              ch, cs, cc->TW.row, cc->TW.ci, cc->CM);
+    launch_rho(st, cc->Prho.view(), cc->TH.row, cc->brow_sys, q->sys, cc->CM, cc->b.HD, cc->rho);
     std::vector<void*> tmp;
     double* dst = out_buffer(cc, q->out, q->where, s.S.nval, tmp);
     launch_gather(st, blkmap(s.mh, s.s_voff, s, false, cc->TH), cc->rho, dst);
@@ -2237,9 +2238,9 @@ int omm_density_matrix_noalloc(omm_ctx* c, int32_t sys, double* rho_dev) {
     double* CM = cc->scratch_dev;                                            // HC-pattern tiles, then
     double* rho = cc->scratch_dev + (size_t)std::max<int64_t>(1, cc->THC.nnz) * TE;   // H-pattern tiles
     const double* C = current_c(cc, q->sys);
-    launch_cm(st, cc->Pcm.view(), cc->THC.row, cc->brow_sys, q->sys, C, cc->b.S0, cc->b.H0, 0.0, 1.0, cc->TW.row,
-              cc->TW.ci, CM);
-    launch_rho(st, cc->Prho.view(), cc->TH.row, cc->brow_sys, q->sys, CM, C, rho);
+    launch_cm(st, cc->Pcm.view(), cc->THC.row, cc->brow_sys, q->sys, C, cc->b.n_tc, cc->b.HD, cc->b.S0, cc->b.H0,
+              0.0, 1.0, cc->TW.row, cc->TW.ci, CM);   // C^T tiles in the H D tiles, as above
+    launch_rho(st, cc->Prho.view(), cc->TH.row, cc->brow_sys, q->sys, CM, cc->b.HD, rho);
     launch_gather(st, blkmap(s.mh, s.s_voff, s, false, cc->TH), rho, q->out);
     OMM_HIP(hipStreamSynchronize(st));
     return OMM_OK;

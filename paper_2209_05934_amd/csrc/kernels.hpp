@@ -126,12 +126,15 @@ constexpr int FUSED_CHUNKS = 16;
 constexpr int FUSED_CTILES = 1024;
 
 // density matrices: CM = C (ch H0 + cs (2I - S0)) on the CM plan, then 2 CM C^T on
-// the H pattern; rho takes (ch, cs) = (0, 1), the energy density (1, eta)
+// the H pattern; rho takes (ch, cs) = (0, 1), the energy density (1, eta).  Both
+// read their operands down tile columns: launch_cm first transposes the ntc tiles
+// of C into the scratch Ct (left there for launch_rho) and writes CM with every
+// tile transposed (CMt)
 void launch_cm(hipStream_t s, PlanView p, const int* orow, const int* brow_sys, int sys, const double* C,
-               const double* S0, const double* H0, double ch, double cs, const int* tw_row, const int* tw_col,
-               double* CM);
-void launch_rho(hipStream_t s, PlanView p, const int* orow, const int* brow_sys, int sys, const double* CM,
-                const double* C, double* rho);
+               int64_t ntc, double* Ct, const double* S0, const double* H0, double ch, double cs, const int* tw_row,
+               const int* tw_col, double* CMt);
+void launch_rho(hipStream_t s, PlanView p, const int* orow, const int* brow_sys, int sys, const double* CMt,
+                const double* Ct, double* rho);
 
 // block <-> tile maps for one input matrix of one system
 struct BlkMap {

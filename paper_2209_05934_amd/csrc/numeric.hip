@@ -661,10 +661,10 @@ __global__ __launch_bounds__(256) void k_cast(int ntiles, const int* __restrict_
 // CM = C M with the n x n matrix M = ch H_W + cs (2I - S_W): rho takes (0, 1), the
 // energy density rho_E = 2 C H_W C^T + eta rho (Kim correction, Sec. II) takes (1, eta)
 __global__ __launch_bounds__(256) void k_cm(PlanView P, const int* __restrict__ orow,
-                                          const int* __restrict__ brow_sys, int sys, const double* __restrict__ C,
+                                          const int* __restrict__ brow_sys, int sys, const double* __restrict__ Ct,
                                           const double* __restrict__ S0, const double* __restrict__ H0, double ch,
                                           double cs, const int* __restrict__ tw_row,
-                                          const int* __restrict__ tw_col, double* __restrict__ CM) {
+                                          const int* __restrict__ tw_col, double* __restrict__ CMt) {
   const int lane = threadIdx.x & 63;
   const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (t >= P.nout) return;
@@ -674,7 +674,7 @@ __global__ __launch_bounds__(256) void k_cm(PlanView P, const int* __restrict__ 
   for (int64_t p = P.pp[t]; p < P.pp[t + 1]; ++p) {
     const int2 pr = P.pairs[p];
     Frag<double> fa, fb;
-    ld_row(fa, C + (size_t)pr.x * TE, lane);
+    ld_col(fa, Ct + (size_t)pr.x * TE, lane);      // A = C, from its transposed tile
     ld_col(fb, S0 + (size_t)pr.y * TE, lane);
     const bool dg = tw_row[pr.y] == tw_col[pr.y];
 #pragma unroll
@@ -689,12 +689,12 @@ __global__ __launch_bounds__(256) void k_cm(PlanView P, const int* __restrict__ 
     mma(acc, fa, fb);
   }
 #pragma unroll
-  for (int r = 0; r < 4; ++r) CM[(size_t)t * TE + out_off<d4>(lane, r)] = acc[r];
+  for (int r = 0; r < 4; ++r) CMt[(size_t)t * TE + out_off_t<d4>(lane, r)] = acc[r];   // stored transposed
 }
 
 __global__ __launch_bounds__(256) void k_rho(PlanView P, const int* __restrict__ orow,
                                            const int* __restrict__ brow_sys, int sys,
-                                           const double* __restrict__ CM, const double* __restrict__ C,
+                                           const double* __restrict__ CMt, const double* __restrict__ Ct,
                                            double* __restrict__ rho) {
   const int lane = threadIdx.x & 63;
   const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -704,12 +704,26 @@ __global__ __launch_bounds__(256) void k_rho(PlanView P, const int* __restrict__
   for (int64_t p = P.pp[t]; p < P.pp[t + 1]; ++p) {
     const int2 pr = P.pairs[p];
     Frag<double> fa, fb;
-    ld_row(fa, CM + (size_t)pr.x * TE, lane);
-    ld_row(fb, C + (size_t)pr.y * TE, lane);      // B = C^T
+    ld_col(fa, CMt + (size_t)pr.x * TE, lane);    // A = C M, from its transposed tile
+    ld_col(fb, Ct + (size_t)pr.y * TE, lane);     // B = C^T
     mma(acc, fa, fb);
   }
 #pragma unroll
   for (int r = 0; r < 4; ++r) rho[(size_t)t * TE + out_off<d4>(lane, r)] = 2.0 * acc[r];
+}
+
+// every tile of src transposed into dst (one wave per tile)
+__global__ __launch_bounds__(256) void k_transpose_tiles(int64_t n, const double* __restrict__ src,
+                                                       double* __restrict__ dst) {
+  const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t >= n) return;
+  const int lane = threadIdx.x & 63;
+  const size_t base = (size_t)t * TE;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int e = 64 * i + lane, r = e >> 4, c = e & 15;
+    dst[base + c * 16 + r] = src[base + e];
+  }
 }
 
 // ------------------------------------------------------------------ layout conversion
@@ -918,16 +932,17 @@ void launch_cast_hs(hipStream_t s, const Bufs& b, Prec prec) {
 }
 
 void launch_cm(hipStream_t s, PlanView p, const int* orow, const int* brow_sys, int sys, const double* C,
-               const double* S0, const double* H0, double ch, double cs, const int* tw_row, const int* tw_col,
-               double* CM) {
+               int64_t ntc, double* Ct, const double* S0, const double* H0, double ch, double cs, const int* tw_row,
+               const int* tw_col, double* CMt) {
+  if (ntc > 0) LAUNCH(k_transpose_tiles, dim3((unsigned)((ntc + 3) / 4)), dim3(256), s, ntc, C, Ct);
   if (p.nout <= 0) return;
-  LAUNCH(k_cm, waves_grid(p.nout), dim3(256), s, p, orow, brow_sys, sys, C, S0, H0, ch, cs, tw_row, tw_col, CM);
+  LAUNCH(k_cm, waves_grid(p.nout), dim3(256), s, p, orow, brow_sys, sys, Ct, S0, H0, ch, cs, tw_row, tw_col, CMt);
 }
 
-void launch_rho(hipStream_t s, PlanView p, const int* orow, const int* brow_sys, int sys, const double* CM,
-                const double* C, double* rho) {
+void launch_rho(hipStream_t s, PlanView p, const int* orow, const int* brow_sys, int sys, const double* CMt,
+                const double* Ct, double* rho) {
   if (p.nout <= 0) return;
-  LAUNCH(k_rho, waves_grid(p.nout), dim3(256), s, p, orow, brow_sys, sys, CM, C, rho);
+  LAUNCH(k_rho, waves_grid(p.nout), dim3(256), s, p, orow, brow_sys, sys, CMt, Ct, rho);
 }
 
 void launch_scatter(hipStream_t s, const BlkMap& m, const double* val, double* tiles) {
