@@ -179,10 +179,11 @@ struct omm_ctx {
   bool prepared = false, hs_cast = false, ran = false;
   Prec prec = P64;
   std::vector<void*> alloc_init, alloc_prep;
-  hipGraphExec_t gexec = nullptr;       // graph_iters iterations
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec_small = nullptr; // graph_small iterations, for the last few
-  hipGraph_t graph_small_h = nullptr;
+  // graphs of graph_iters iterations and of graph_small iterations (for the last
+  // few), per set of kernel sets they launch (index: 1 the low-precision set,
+  // 2 the FP64 set, 3 both); captured when first needed
+  hipGraphExec_t gexec[4] = {}, gexec_small[4] = {};
+  hipGraph_t graph[4] = {}, graph_small_h[4] = {};
   int graph_iters = 0, graph_small = 0;
   bool tuned = false;
   std::string tune_log;
@@ -715,16 +716,18 @@ void ingest(omm_ctx* c, int count, const omm_matrix* H, const omm_matrix* S, con
 
 void drop_graphs(omm_ctx* c) {
   c->gen = g_generation.fetch_add(1);
-  for (hipGraphExec_t* e : {&c->gexec, &c->gexec_small})
-    if (*e) {
-      (void)hipGraphExecDestroy(*e);
-      *e = nullptr;
-    }
-  for (hipGraph_t* g : {&c->graph, &c->graph_small_h})
-    if (*g) {
-      (void)hipGraphDestroy(*g);
-      *g = nullptr;
-    }
+  for (int k = 0; k < 4; ++k)
+    for (hipGraphExec_t* e : {&c->gexec[k], &c->gexec_small[k]})
+      if (*e) {
+        (void)hipGraphExecDestroy(*e);
+        *e = nullptr;
+      }
+  for (int k = 0; k < 4; ++k)
+    for (hipGraph_t* g : {&c->graph[k], &c->graph_small_h[k]})
+      if (*g) {
+        (void)hipGraphDestroy(*g);
+        *g = nullptr;
+      }
 }
 
 // ----------------------------------------------------------------- prepare (C pattern dependent)
@@ -1313,9 +1316,11 @@ void run_iteration(omm_ctx* c, Prec p, int mask, bool tm) {
   launch_update_d(s, b, p, mask, false, prm);
 }
 
-void run_step(omm_ctx* c, bool tm) {
-  if (c->prec != P64) run_iteration(c, c->prec, PH_LOW, tm);
-  run_iteration(c, P64, PH_FP64, tm);
+// one CG iteration of the kernel sets in `sets` (1: the low-precision set, for
+// systems in PH_LOW; 2: the FP64 set, for systems in PH_FP64)
+void run_step(omm_ctx* c, bool tm, int sets = 3) {
+  if (c->prec != P64 && (sets & 1)) run_iteration(c, c->prec, PH_LOW, tm);
+  if (sets & 2) run_iteration(c, P64, PH_FP64, tm);
 }
 
 void init_sequence(omm_ctx* c) {
@@ -1366,10 +1371,10 @@ void scatter_c0(omm_ctx* c) {
   }
 }
 
-void capture_graph(omm_ctx* c, int K, hipGraph_t* graph, hipGraphExec_t* exec) {
+void capture_graph(omm_ctx* c, int K, int sets, hipGraph_t* graph, hipGraphExec_t* exec) {
   OMM_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
   try {
-    for (int k = 0; k < K; ++k) run_step(c, false);
+    for (int k = 0; k < K; ++k) run_step(c, false, sets);
   } catch (...) {
     hipGraph_t g = nullptr;
     (void)hipStreamEndCapture(c->stream, &g);
@@ -1380,12 +1385,27 @@ void capture_graph(omm_ctx* c, int K, hipGraph_t* graph, hipGraphExec_t* exec) {
   OMM_HIP(hipGraphInstantiate(exec, *graph, nullptr, nullptr, 0));
 }
 
-void capture_graphs(omm_ctx* c) {
+void capture_graphs(omm_ctx* c, int sets) {
   const int K = c->opt.graph_iters;
-  capture_graph(c, K, &c->graph, &c->gexec);
+  capture_graph(c, K, sets, &c->graph[sets], &c->gexec[sets]);
   c->graph_iters = K;
   c->graph_small = std::max(1, K / 4);
-  if (c->graph_small < K) capture_graph(c, c->graph_small, &c->graph_small_h, &c->gexec_small);
+  if (c->graph_small < K)
+    capture_graph(c, c->graph_small, sets, &c->graph_small_h[sets], &c->gexec_small[sets]);
+}
+
+// The kernel sets a replay needs: a system changes precision only through the
+// INIT phase, which the host resolves between replays (init_sequence), so the
+// phases present when a replay starts are the only ones its kernels can find.
+// Replaying only those skips the launches that would exit at once.
+int sets_needed(const omm_ctx* c) {
+  if (c->prec == P64) return 2;
+  int sets = 0;
+  for (int i = 0; i < c->nsys; ++i) {
+    if (c->h_st[i].phase == PH_LOW) sets |= 1;
+    if (c->h_st[i].phase == PH_FP64) sets |= 2;
+  }
+  return sets ? sets : 3;
 }
 
 // Iterations a system still needs, predicted from the state read after the
@@ -1507,8 +1527,7 @@ int minimize(omm_ctx* c, omm_report* reps) {
   c->setup_secs = std::chrono::duration<double>(c->solve_t0 - t0).count();
   hipStream_t st = c->stream;
   const bool use_graph = c->opt.graph_iters > 0 && !c->timing;
-  if (use_graph && !c->gexec) capture_graphs(c);
-  const int K = use_graph ? c->graph_iters : std::max(1, c->opt.graph_iters > 0 ? c->opt.graph_iters : 1);
+  const int K = std::max(1, c->opt.graph_iters);
   int64_t steps = 0, reinits = 0, waited = 0;
   const int64_t max_steps = c->opt.max_iter + 8 * (int64_t)K + 64;
   std::vector<SysState> before(c->nsys);
@@ -1531,11 +1550,13 @@ int minimize(omm_ctx* c, omm_report* reps) {
     }
     if (steps >= max_steps) throw DeviceError("iteration loop exceeded its bound");
     int k_run = K;
+    const int sets = sets_needed(c);
+    if (use_graph && !c->gexec[sets]) capture_graphs(c, sets);
     // the long graph unless every active system is predicted to finish within it
-    if (use_graph && c->gexec_small && last_k > 0 && left_of(c, before) < (double)K) k_run = c->graph_small;
-    if (use_graph) OMM_HIP(hipGraphLaunch(k_run == K ? c->gexec : c->gexec_small, st));
+    if (use_graph && c->gexec_small[sets] && last_k > 0 && left_of(c, before) < (double)K) k_run = c->graph_small;
+    if (use_graph) OMM_HIP(hipGraphLaunch(k_run == K ? c->gexec[sets] : c->gexec_small[sets], st));
     else
-      for (int k = 0; k < K; ++k) run_step(c, c->timing);
+      for (int k = 0; k < K; ++k) run_step(c, c->timing, sets);
     steps += k_run;
     last_k = k_run;
   }
