@@ -132,6 +132,14 @@ typedef struct {
                                the sums; one shape gives bitwise repeatable results.
                                Default 0 */
   int32_t tile_split[3];
+  const char* log_jsonl_path; /* NULL, or a file each omm_minimize appends one JSON line
+                               per CG iteration and system to, after the solve (the
+                               iteration state lives on the device during it):
+                               {"solve", "system", "iter", "energy", "c" (the quartic's
+                               c0..c4), "x", "grad_norm", "beta", "restart", "fp64"};
+                               turns history on.  The library copies this path and
+                               tune_cache; omm_init returns OMM_ERR_ARG when it cannot
+                               open the file for appending.  Default NULL */
 } omm_options;
 
 /* Per-system results of omm_minimize. */

@@ -29,6 +29,7 @@ SOURCES = ([("symbolic.hip", "symbolic.o", [])]
            + [(src, src.replace(".hip", ".o"), []) for src in ("numeric.hip", "cholesky.hip", "engine.hip")]
            + [("coeff_io.cpp", "coeff_io.o", []), ("kpoint.cpp", "kpoint.o", [])])
 ARCH = os.environ.get("OMM_OFFLOAD_ARCH", "gfx950")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}",
@@ -83,7 +84,8 @@ def build(verbose: bool = False, jobs: int = 0, only: tuple = ()) -> str:
         raise RuntimeError(f"objects missing (build everything first): {missing}")
     out = lib_path()
     tmp = out + ".tmp"
-    cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Wl,--no-undefined", "-o", tmp, *objs]
+    cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Wl,--no-undefined", "-o", tmp, *objs,
+           "-L" + os.path.join(ROCM, "lib"), "-lrocprofiler-sdk-roctx", "-Wl,-rpath," + os.path.join(ROCM, "lib")]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")

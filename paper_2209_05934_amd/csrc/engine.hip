@@ -19,6 +19,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "kernels.hpp"
 #include "kpoint.hpp"
 
@@ -33,6 +35,15 @@ thread_local std::string g_last_init_error;
 void omm::set_global_error(const std::string& msg) { g_last_init_error = msg; }
 
 namespace {
+
+// A named range on the host timeline for tracers (rocprofv3 --marker-trace):
+// the solver phases, each replay of the iteration graph, the output calls.
+struct Range {
+  explicit Range(const char* name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 
 struct MatDesc {   // host copy of an input matrix's block structure
   int nbrow = 0, nbcol = 0;
@@ -187,6 +198,8 @@ struct omm_ctx {
   int graph_iters = 0, graph_small = 0;
   bool tuned = false;
   std::string tune_log;
+  std::string tune_path, log_path;   // copies of the option strings (opt points at them)
+  int64_t nsolves = 0;
   // complex Hermitian systems (k-points) are held as their real embedding
   // (kpoint.hpp); the structures of the complex H, S and C0 map outputs back
   bool cplx = false;
@@ -732,6 +745,7 @@ void drop_graphs(omm_ctx* c) {
 
 // ----------------------------------------------------------------- prepare (C pattern dependent)
 void prepare(omm_ctx* c) {
+  Range rg("omm prepare (symbolic phase, work lists)");
   hipStream_t st = c->stream;
   OMM_HIP(hipStreamSynchronize(st));
   drop_graphs(c);
@@ -1178,6 +1192,7 @@ void set_plan(omm_ctx* c, int cls, int sel, int ks) {
 }
 
 void autotune(omm_ctx* c) {
+  Range rg("omm autotune");
   std::vector<std::pair<std::string, int>> cache;
   if (c->opt.tune_cache) {
     if (FILE* f = std::fopen(c->opt.tune_cache, "r")) {
@@ -1324,6 +1339,7 @@ void run_step(omm_ctx* c, bool tm, int sets = 3) {
 }
 
 void init_sequence(omm_ctx* c) {
+  Range rg("omm start-up products");
   hipStream_t s = c->stream;
   const Bufs& b = c->b;
   const CGParams prm = params(c);
@@ -1479,6 +1495,35 @@ double left_of(const omm_ctx* c, const std::vector<SysState>& before) {
   return left;
 }
 
+// The per-iteration history rows of the last solve appended to log_jsonl_path,
+// one JSON line per iteration and system (complex systems scaled as in
+// omm_get_history).  A write failure leaves the solve's results untouched.
+void write_log(omm_ctx* c) {
+  const int64_t hm = c->opt.history_max;
+  std::vector<double> rows;
+  FILE* f = std::fopen(c->log_path.c_str(), "a");
+  if (!f) return;
+  for (int i = 0; i < c->nsys; ++i) {
+    const int64_t n = std::min<int64_t>(c->h_st[i].iter, hm);
+    if (n <= 0) continue;
+    rows.resize((size_t)n * HCOLS);
+    OMM_HIP(hipMemcpyAsync(rows.data(), c->d_hist + (size_t)i * hm * HCOLS, n * HCOLS * sizeof(double),
+                           hipMemcpyDeviceToHost, c->stream));
+    OMM_HIP(hipStreamSynchronize(c->stream));
+    const double f1 = c->cplx ? 0.5 : 1.0, fg = c->cplx ? std::sqrt(0.5) : 1.0;
+    for (int64_t r = 0; r < n; ++r) {
+      const double* h = rows.data() + r * HCOLS;
+      std::fprintf(f,
+                   "{\"solve\": %lld, \"system\": %d, \"iter\": %lld, \"energy\": %.17g, \"c\": [%.17g, %.17g, "
+                   "%.17g, %.17g, %.17g], \"x\": %.17g, \"grad_norm\": %.17g, \"beta\": %.17g, \"restart\": %d, "
+                   "\"fp64\": %s}\n",
+                   (long long)c->nsolves, i, (long long)(r + 1), f1 * h[0], f1 * h[1], f1 * h[2], f1 * h[3], f1 * h[4],
+                   f1 * h[5], h[6], fg * h[7], h[8], (int)h[9], h[10] == 0.0 ? "true" : "false");
+    }
+  }
+  std::fclose(f);
+}
+
 // End of a solve: the electron count at the final C and the per-system reports.
 int end_solve(omm_ctx* c, omm_report* reps) {
   hipStream_t st = c->stream;
@@ -1518,10 +1563,13 @@ int end_solve(omm_ctx* c, omm_report* reps) {
   }
   if (worst != OMM_OK) c->err = "at least one system ended with status " + std::string(omm_status_str(worst));
   else c->err.clear();
+  c->nsolves += 1;
+  if (!c->log_path.empty()) write_log(c);
   return worst;
 }
 
 int minimize(omm_ctx* c, omm_report* reps) {
+  Range rg("omm_minimize");
   const auto t0 = std::chrono::steady_clock::now();
   begin_solve(c);
   c->setup_secs = std::chrono::duration<double>(c->solve_t0 - t0).count();
@@ -1554,6 +1602,7 @@ int minimize(omm_ctx* c, omm_report* reps) {
     if (use_graph && !c->gexec[sets]) capture_graphs(c, sets);
     // the long graph unless every active system is predicted to finish within it
     if (use_graph && c->gexec_small[sets] && last_k > 0 && left_of(c, before) < (double)K) k_run = c->graph_small;
+    Range rr("omm CG replay");
     if (use_graph) OMM_HIP(hipGraphLaunch(k_run == K ? c->gexec[sets] : c->gexec_small[sets], st));
     else
       for (int k = 0; k < K; ++k) run_step(c, c->timing, sets);
@@ -1913,6 +1962,23 @@ int omm_init_batch(omm_ctx** out, int32_t count, const omm_matrix* H, const omm_
     return OMM_ERR_OOM;
   }
   c->opt = o;
+  if (o.tune_cache) {
+    c->tune_path = o.tune_cache;
+    c->opt.tune_cache = c->tune_path.c_str();
+  }
+  if (o.log_jsonl_path) {
+    c->log_path = o.log_jsonl_path;
+    c->opt.log_jsonl_path = c->log_path.c_str();
+    FILE* f = std::fopen(c->log_path.c_str(), "a");
+    if (!f) {
+      g_last_init_error = "cannot open log_jsonl_path for appending: " + c->log_path;
+      delete c;
+      return OMM_ERR_ARG;
+    }
+    std::fclose(f);
+    if (c->opt.history <= 0) c->opt.history = 1;
+    if (c->opt.history_max <= 0) c->opt.history_max = 20000;
+  }
   c->prec = (Prec)o.precision;
   c->gen = g_generation.fetch_add(1);
   struct A { int count; const omm_matrix *H, *S; const int64_t* n; const int32_t* modes; const double* etas; } a{
@@ -2186,6 +2252,7 @@ static int density_like_real(omm_ctx* c, int32_t sys, double* out, int32_t where
 
 // complex contexts: the real result of the embedding, then its complex values (host memory)
 static int density_like(omm_ctx* c, int32_t sys, double* out, int32_t where, bool energy, const char* name) {
+  Range rg(name);
   if (!c) return OMM_ERR_ARG;
   if (!c->cplx) return density_like_real(c, sys, out, where, energy, name);
   if (sys < 0 || sys >= c->nsys || !out || where != OMM_HOST) {

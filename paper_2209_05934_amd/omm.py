@@ -42,7 +42,7 @@ class omm_options(C.Structure):
         ("lowprec_max_iter", C.c_int64), ("graph_iters", C.c_int32), ("history", C.c_int32),
         ("history_max", C.c_int32), ("ne_tol", C.c_double), ("autotune", C.c_int32),
         ("tune_cache", C.c_char_p), ("hip_stream", C.c_void_p),
-        ("tile_group", C.c_int32 * 3), ("tile_split", C.c_int32 * 3),
+        ("tile_group", C.c_int32 * 3), ("tile_split", C.c_int32 * 3), ("log_jsonl_path", C.c_char_p),
     ]
 
 

@@ -43,8 +43,9 @@ def test_struct_layouts_match_header():
 #include "omm.h"
 int main(void) {
   printf("%zu %zu %zu %zu\n", sizeof(omm_matrix), sizeof(omm_options), sizeof(omm_report), sizeof(omm_sizes));
-  printf("%zu %zu %zu %zu\n", offsetof(omm_options, hip_stream), offsetof(omm_report, seconds),
-         offsetof(omm_sizes, bytes_alg_step), offsetof(omm_sizes, tile_split));
+  printf("%zu %zu %zu %zu %zu\n", offsetof(omm_options, hip_stream), offsetof(omm_report, seconds),
+         offsetof(omm_sizes, bytes_alg_step), offsetof(omm_sizes, tile_split),
+         offsetof(omm_options, log_jsonl_path));
   return 0;
 }
 '''
@@ -61,6 +62,7 @@ int main(void) {
     assert sizes[5] == L.omm_report.seconds.offset
     assert sizes[6] == L.omm_sizes.bytes_alg_step.offset
     assert sizes[7] == L.omm_sizes.tile_split.offset
+    assert sizes[8] == L.omm_options.log_jsonl_path.offset
 
 
 def test_status_strings_and_defaults():
@@ -84,11 +86,20 @@ def _args(bm, **over):
     return L.BlockArgs(**d)
 
 
-def _init_rc(H, S, n, mode=L.OMM_DENSE):
+def _init_rc(H, S, n, mode=L.OMM_DENSE, opt=None):
     ctx = ctypes.c_void_p()
-    rc = L.load().omm_init(ctypes.byref(ctx), ctypes.byref(H.struct), ctypes.byref(S.struct), n, mode, None)
+    rc = L.load().omm_init(ctypes.byref(ctx), ctypes.byref(H.struct), ctypes.byref(S.struct), n, mode,
+                           ctypes.byref(opt) if opt is not None else None)
     assert not ctx.value
     return rc, L.omm_last_error(None)
+
+
+def test_unwritable_log_path_rejected_before_the_device(chain):
+    # the JSONL iteration log is opened for appending at omm_init, before any HIP call
+    opt = L.omm_default_options()
+    opt.log_jsonl_path = b"/nonexistent-directory/omm-log.jsonl"
+    rc, msg = _init_rc(_args(chain.H), _args(chain.S), chain.n, opt=opt)
+    assert rc == L.OMM_ERR_ARG and "log_jsonl_path" in msg
 
 
 # every rejected call below fails in host-side validation, before any HIP call
