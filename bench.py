@@ -617,7 +617,16 @@ def main():
                      "alg_flops_per_launch": sz.flops_alg_step[k],
                      "exec_flops_per_launch": sz.flops_exec_step[k],
                      "alg_bytes_per_launch": sz.bytes_alg_step[k],
-                     "step_us": {names[i]: avg_ms[i] * 1e3 for i in range(3)}})
+                     "step_us": {names[i]: avg_ms[i] * 1e3 for i in range(3)},
+                     # every product step against the peak of its arithmetic: algorithmic
+                     # (unpadded atom blocks) and executed (16 x 16 tiles) flops per launch
+                     "steps": {names[i]: {"us": avg_ms[i] * 1e3, "alg_flops": sz.flops_alg_step[i],
+                                          "exec_flops": sz.flops_exec_step[i],
+                                          "alg_frac": sz.flops_alg_step[i] / (avg_ms[i] * 1e-3) / 1e12
+                                          / PEAKS[args.precision],
+                                          "exec_frac": sz.flops_exec_step[i] / (avg_ms[i] * 1e-3) / 1e12
+                                          / PEAKS[args.precision],
+                                          "alg_bytes": sz.bytes_alg_step[i]} for i in range(3)}})
 
     sparse = wl["mode"] == "sparse"
     cpu_leg = None

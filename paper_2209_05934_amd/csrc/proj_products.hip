@@ -40,17 +40,19 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s2(
   const int o0 = m.x, cnt = m.y, s = m.z;
   const int phase = ld_early(&st[s].phase);
   const double e2 = ld_early(&info[s].eps2);
-  bool low[NT];   // output tile below the diagonal: no S2, H2 products
+  // output tile below the diagonal: no S2, H2 products; at start-up (S0, H0,
+  // both symmetric) no products at all, the tile is mirrored from above afterwards
+  bool low[NT];
 #pragma unroll
   for (int u = 0; u < NT; ++u) {
     const int t = min(o0 + u, o0 + max(cnt, 1) - 1);
-    low[u] = NPROD == 4 && valid && ld_early(&orow[t]) > ld_early(&ocol[t]);
+    low[u] = valid && ld_early(&orow[t]) > ld_early(&ocol[t]);
   }
   const bool act = valid && (phase & mask) != 0;
   V acc[NPROD * NT];
 #pragma unroll
   for (int a = 0; a < NPROD * NT; ++a) acc[a] = vzero<V>();
-  bool all_low = NPROD == 4;   // every output tile of the group below the diagonal: no D loads
+  bool all_low = true;   // every output tile of the group below the diagonal: no D loads (no loads at start-up)
 #pragma unroll
   for (int u = 0; u < NT; ++u) all_low = all_low && (u >= cnt || low[u]);
   struct Stage { Frag<TI> c, d, hd[NT], sd[NT]; };
@@ -71,7 +73,7 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s2(
         [&](const Stage& f, const int (&id)[W]) {
 #pragma unroll
           for (int u = 0; u < NT; ++u) {
-            if (id[1 + u] >= 0) {
+            if (id[1 + u] >= 0 && !(NPROD == 2 && low[u])) {
               mma(acc[u], f.c, f.sd[u]);
               mma(acc[NT + u], f.c, f.hd[u]);
               if constexpr (NPROD == 4 && !SKIP) {
@@ -84,8 +86,8 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s2(
           }
         });
   };
-  if (act) {
-    if (all_low) body(std::true_type{});
+  if (act && !(NPROD == 2 && all_low)) {
+    if (NPROD == 4 && all_low) body(std::true_type{});
     else body(std::false_type{});
   }
   ks_reduce<KS, NPROD * NT>(acc, red, grp, wk, lane);
@@ -93,6 +95,7 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s2(
 #pragma unroll
   for (int u = 0; u < NT; ++u) {
     if (u >= cnt) break;
+    if (NPROD == 2 && low[u]) continue;   // start-up: mirrored from above afterwards
     const int t = o0 + u;
     if (e2 > 0.0) {
       const uint8_t* rs = wseg + 32 * (size_t)orow[t];
