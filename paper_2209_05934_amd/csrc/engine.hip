@@ -23,6 +23,7 @@
 
 #include "kernels.hpp"
 #include "kpoint.hpp"
+#include "tile_ops.hpp"
 
 using namespace omm;
 
@@ -743,6 +744,93 @@ void drop_graphs(omm_ctx* c) {
       }
 }
 
+// MFMA steps of the gradient products that the atom-block structure makes zero.
+// A gradient pair multiplies HC(b, k) by S_W(k, g) (and SC by H_W) over the 16
+// wavefunctions of tile k, four per MFMA step (two atoms of two wavefunctions).
+// Step s contributes only where some wavefunction 4s..4s+3 is a nonzero column of
+// HC(b, k) (its atom couples to basis atom b through H C) and a nonzero row of
+// S_W(k, g) (its atom couples to an atom of tile g through C^T H C): per-tile
+// masks from the block patterns, combined per entry on the device.  Dense
+// systems keep every step.  The executed gradient flops count the kept steps.
+void grad_step_masks(omm_ctx* c) {
+  const int64_t nhc = c->THC.nnz, ntw = c->TW.nnz;
+  if (nhc <= 0 || ntw <= 0) return;
+  if (ntw > ENT_TILE_MASK) throw ArgError("n x n pattern too large for the work-list encoding");
+  std::vector<int> hc_ci = ddownload(c, c->THC.ci, nhc), tw_ci = ddownload(c, c->TW.ci, ntw);
+  std::vector<uint32_t> acm(nhc, 0xffffu), brm(ntw, 0xffffu);
+  for (int i = 0; i < c->nsys; ++i) {
+    SysHost& s = c->sys[i];
+    if (s.mode != OMM_BLOCK_SPARSE) continue;
+    const MatDesc& H = s.H;
+    const MatDesc& C = s.C0;
+    const int nb = H.nbrow, na = C.nbcol, nw = (na + 63) / 64;
+    // block patterns: C rows, HC = H C rows, W = C^T HC rows (wavefunction atoms)
+    std::vector<uint64_t> crow((size_t)nb * nw, 0), hc((size_t)nb * nw, 0), w((size_t)na * nw, 0);
+    for (int b = 0; b < nb; ++b)
+      for (int64_t e = C.rp[b]; e < C.rp[b + 1]; ++e) crow[(size_t)b * nw + (C.ci[e] >> 6)] |= 1ull << (C.ci[e] & 63);
+    for (int b = 0; b < nb; ++b)
+      for (int64_t e = H.rp[b]; e < H.rp[b + 1]; ++e)
+        for (int q = 0; q < nw; ++q) hc[(size_t)b * nw + q] |= crow[(size_t)H.ci[e] * nw + q];
+    for (int k = 0; k < nb; ++k)
+      for (int64_t e = C.rp[k]; e < C.rp[k + 1]; ++e)
+        for (int q = 0; q < nw; ++q) w[(size_t)C.ci[e] * nw + q] |= hc[(size_t)k * nw + q];
+    // the atoms of each local wavefunction tile, with their column bits, and the
+    // tile's atom range (consecutive atoms)
+    std::vector<int> co(na + 1, 0);
+    for (int a = 0; a < na; ++a) co[a + 1] = co[a] + C.cbs[a];
+    std::vector<std::vector<std::pair<int, uint32_t>>> atoms(s.WT);
+    std::vector<int> alo(s.WT, na), ahi(s.WT, -1);
+    for (int a = 0; a < na; ++a)
+      for (int e = co[a]; e < co[a + 1]; ++e) {
+        const int g = s.w_tile[e];
+        if (atoms[g].empty() || atoms[g].back().first != a) atoms[g].emplace_back(a, 0u);
+        atoms[g].back().second |= 1u << s.w_off[e];
+        alo[g] = std::min(alo[g], a);
+        ahi[g] = std::max(ahi[g], a);
+      }
+    auto any_in = [&](const uint64_t* row, int lo, int hi) {
+      for (int a = lo; a <= hi; ++a)
+        if ((row[a >> 6] >> (a & 63)) & 1ull) return true;
+      return false;
+    };
+    for (int b = 0; b < nb; ++b) {   // HC tiles (b, g): nonzero columns
+      const int R = s.rb0 + b;
+      for (int t = c->THC.hrp[R]; t < c->THC.hrp[R + 1]; ++t) {
+        const int g = hc_ci[t] - s.wb0;
+        uint32_t m = 0;
+        for (auto& ab : atoms[g])
+          if ((hc[(size_t)b * nw + (ab.first >> 6)] >> (ab.first & 63)) & 1ull) m |= ab.second;
+        acm[t] = m;
+      }
+    }
+    for (int g1 = 0; g1 < s.WT; ++g1) {   // S_W, H_W tiles (g1, g2): nonzero rows
+      const int R = s.wb0 + g1;
+      for (int t = c->TW.hrp[R]; t < c->TW.hrp[R + 1]; ++t) {
+        const int g2 = tw_ci[t] - s.wb0;
+        uint32_t m = 0;
+        for (auto& ab : atoms[g1])
+          if (any_in(&w[(size_t)ab.first * nw], alo[g2], ahi[g2])) m |= ab.second;
+        brm[t] = m;
+      }
+    }
+  }
+  // small buffers of this pattern, released with the plans
+  uint32_t* d_acm = dupload(c, acm, true);
+  uint32_t* d_brm = dupload(c, brm, true);
+  unsigned long long* d_act = dalloc<unsigned long long>(c, c->nsys, true);
+  for (int q = 0; q < NPLAN; ++q) {
+    const GPlan& G = c->G[2][q];
+    OMM_HIP(hipMemsetAsync(d_act, 0, c->nsys * sizeof(unsigned long long), c->stream));
+    entry_steps(c->stream, G.ngroups, G.NT, G.gp, G.meta, G.ent, d_acm, d_brm, d_act);
+    if (q == 0) {   // the kept steps do not depend on the grouping
+      std::vector<unsigned long long> act = ddownload(c, d_act, c->nsys);
+      for (int i = 0; i < c->nsys; ++i)
+        c->sys[i].flops_exec[2] = 2.0 * (2.0 * 16 * 16 * 4) * (double)act[i];
+    }
+  }
+  OMM_HIP(hipStreamSynchronize(c->stream));
+}
+
 // ----------------------------------------------------------------- prepare (C pattern dependent)
 void prepare(omm_ctx* c) {
   Range rg("omm prepare (symbolic phase, work lists)");
@@ -1013,6 +1101,7 @@ void prepare(omm_ctx* c) {
     for (int k = 0; k < 3; ++k)
       for (int q = 0; q < NPLAN; ++q) c->G[k][q].xrun = std::max(1, xr[k]);
   }
+  grad_step_masks(c);
   c->chunks = dupload(c, chunks, true);
   c->d_info = dupload(c, c->h_info, true);
   c->d_st = dalloc<SysState>(c, c->nsys, true);

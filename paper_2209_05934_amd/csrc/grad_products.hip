@@ -9,7 +9,10 @@ namespace {
 
 // ------------------------------------------------------------------ gradient on C's pattern
 // Groups of NT tiles of C's pattern in one basis row b: per k the HC(b,k) and
-// SC(b,k) tiles are loaded once for NT tiles of S_W and H_W.
+// SC(b,k) tiles are loaded once for NT tiles of S_W and H_W.  An entry's S_W/H_W
+// tile index carries the MFMA steps (groups of four wavefunctions of tile k)
+// where HC(b,k) has no nonzero column or S_W(k,g) no nonzero row: those steps
+// are skipped.
 template <typename TI, int KS, int NT, bool ROLL>
 __global__ __launch_bounds__(Split<KS>::NW * 64) void k_grad(
     GroupView P, const SysState* __restrict__ st, int mask, const TI* __restrict__ HCm,
@@ -48,7 +51,7 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_grad(
           ld_col(f.s, SCm + (size_t)id[0] * TE, lane);
 #pragma unroll
           for (int u = 0; u < NT; ++u) {
-            const size_t bt = (size_t)max(id[1 + u], 0) * TE;
+            const size_t bt = (size_t)ent_tile(id[1 + u]) * TE;
             ld_col(f.w[u], S0m + bt, lane);
             ld_col(f.v[u], H0m + bt, lane);
           }
@@ -56,9 +59,10 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_grad(
         [&](const Stage& f, const int (&id)[W]) {
 #pragma unroll
           for (int u = 0; u < NT; ++u) {
-            if (id[1 + u] >= 0) {
-              mma(acc[u], f.h, f.w[u]);
-              mma(acc[u], f.s, f.v[u]);
+            if (id[1 + u] >= 0) {   // only the MFMA steps whose wavefunction pairs couple
+              const int act = ent_steps(id[1 + u]);
+              mma(acc[u], f.h, f.w[u], act);
+              mma(acc[u], f.s, f.v[u], act);
             }
           }
         });

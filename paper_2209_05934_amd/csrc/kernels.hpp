@@ -25,6 +25,12 @@ void group_lists(hipStream_t st, int nrows, PatView A, PatView B, PatView O, int
 // per-group record (first output tile, output tiles, system of the output row)
 void group_meta(hipStream_t st, int ngroups, const int* go0, const int* gn, const int* orow, const int* row_sys,
                 int4* meta);
+// the skipped MFMA steps of every entry of a gradient work list (bits 27-30 of
+// its B tile indices): step s is kept where the A tile's 16-bit column mask
+// (acm) and the B tile's 16-bit row mask (brm) share a bit in 4s .. 4s+3; the
+// kept steps are added per system to act
+void entry_steps(hipStream_t st, int ngroups, int NT, const int64_t* gp, const int4* meta, int* ent,
+                 const uint32_t* acm, const uint32_t* brm, unsigned long long* act);
 void excl_scan(hipStream_t st, const int* in, int* out, int64_t n);
 void excl_scan64(hipStream_t st, const int64_t* in, int64_t* out, int64_t n);
 

@@ -296,6 +296,28 @@ void group_lists(hipStream_t st, int nrows, PatView A, PatView B, PatView O, int
 }
 
 namespace {
+__global__ void k_entry_steps(int ngroups, int NT, const int64_t* __restrict__ gp, const int4* __restrict__ meta,
+                              int* __restrict__ ent, const uint32_t* __restrict__ acm,
+                              const uint32_t* __restrict__ brm, unsigned long long* __restrict__ act) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ngroups) return;
+  const int W = 1 + NT;
+  unsigned long long kept = 0;
+  for (int64_t e = gp[g]; e < gp[g + 1]; ++e) {
+    int* row = ent + e * W;
+    const uint32_t am = acm[row[0]];
+    for (int u = 0; u < NT; ++u) {
+      const int bt = row[1 + u];
+      if (bt < 0) continue;
+      const uint32_t m = am & brm[bt];
+      const int steps = ((m & 0xfu) ? 1 : 0) | ((m & 0xf0u) ? 2 : 0) | ((m & 0xf00u) ? 4 : 0) | ((m & 0xf000u) ? 8 : 0);
+      row[1 + u] = bt | ((~steps & 15) << 27);
+      kept += __popc(steps);
+    }
+  }
+  atomicAdd(act + meta[g].z, kept);
+}
+
 __global__ void k_group_meta(int ngroups, const int* __restrict__ go0, const int* __restrict__ gn,
                              const int* __restrict__ orow, const int* __restrict__ row_sys, int4* __restrict__ meta) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -304,6 +326,14 @@ __global__ void k_group_meta(int ngroups, const int* __restrict__ go0, const int
   meta[g] = make_int4(o0, gn[g], row_sys[orow[o0]], 0);
 }
 }  // namespace
+
+void entry_steps(hipStream_t st, int ngroups, int NT, const int64_t* gp, const int4* meta, int* ent,
+                 const uint32_t* acm, const uint32_t* brm, unsigned long long* act) {
+  if (ngroups <= 0) return;
+  hipLaunchKernelGGL(k_entry_steps, dim3((ngroups + 255) / 256), dim3(256), 0, st, ngroups, NT, gp, meta, ent, acm,
+                     brm, act);
+  OMM_HIP(hipGetLastError());
+}
 
 void group_meta(hipStream_t st, int ngroups, const int* go0, const int* gn, const int* orow, const int* row_sys,
                 int4* meta) {

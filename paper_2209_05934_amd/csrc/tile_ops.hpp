@@ -49,13 +49,12 @@ template <> struct Acc<bf16> { typedef f4 V; typedef float S; };
 
 template <typename T> struct Frag { T v[4]; };
 
-// tile index k supplied by lane-quad q at step s
-// FP64: a lane's four k are consecutive, so a row load is two 16-byte vector
-// loads.  FP32/BF16 (whose products load every operand down columns): the four
-// quads of one step take consecutive k, so a column load reads four
-// consecutive rows, which share cache lines at 4- and 2-byte elements.
+// tile index k supplied by lane-quad q at step s: the four quads of step s take
+// the consecutive k = 4s .. 4s+3, so a column load reads four whole rows per
+// instruction (four cache lines of an FP64 tile) and MFMA step s contracts over
+// one aligned group of four k, which a work-list entry can mark as all zero
+// (chunk masks below)
 template <typename T> struct KMap { static __device__ __forceinline__ int k(int q, int s) { return 4 * s + q; } };
-template <> struct KMap<double> { static __device__ __forceinline__ int k(int q, int s) { return 4 * q + s; } };
 
 // output row of accumulator register r in lane-quad q
 template <typename V> struct Lay;
@@ -87,11 +86,32 @@ __device__ __forceinline__ void mma(f4& acc, const Frag<float>& a, const Frag<fl
 #pragma unroll
   for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[s], b.v[s], acc, 0, 0, 0);
 }
+// the same, only the steps s whose bit (act >> s) & 1 is set (act wave-uniform):
+// a step whose four k hold no nonzero product contributes exact zeros
+__device__ __forceinline__ void mma(d4& acc, const Frag<double>& a, const Frag<double>& b, int act) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+    if ((act >> s) & 1) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.v[s], b.v[s], acc, 0, 0, 0);
+}
+__device__ __forceinline__ void mma(f4& acc, const Frag<float>& a, const Frag<float>& b, int act) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+    if ((act >> s) & 1) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[s], b.v[s], acc, 0, 0, 0);
+}
 __device__ __forceinline__ void mma(f4& acc, const Frag<bf16>& a, const Frag<bf16>& b) {
   s4 av = {(short)a.v[0], (short)a.v[1], (short)a.v[2], (short)a.v[3]};
   s4 bv = {(short)b.v[0], (short)b.v[1], (short)b.v[2], (short)b.v[3]};
   acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
 }
+// one instruction covers all 16 k: the step mask cannot skip part of it
+__device__ __forceinline__ void mma(f4& acc, const Frag<bf16>& a, const Frag<bf16>& b, int) { mma(acc, a, b); }
+
+// Work-list entries may carry, in bits 27-30 of a B tile index, the MFMA steps
+// whose four k hold no structurally nonzero product (set: skip); -1 is an absent
+// tile.  Tile indices stay below 2^27.
+constexpr int ENT_TILE_MASK = (1 << 27) - 1;
+__device__ __forceinline__ int ent_tile(int id) { return id < 0 ? 0 : (id & ENT_TILE_MASK); }
+__device__ __forceinline__ int ent_steps(int id) { return ~(id >> 27) & 15; }
 
 template <typename V> __device__ __forceinline__ V vzero();
 template <> __device__ __forceinline__ d4 vzero<d4>() { return d4{0.0, 0.0, 0.0, 0.0}; }
