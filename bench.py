@@ -102,38 +102,38 @@ MEASURED_TRAFFIC = {
     ("cubic4_dense", "fp64", 2, 4, 1): (5.8147e+06, "4f4585e2f31cc914"),
     ("cubic4_dense", "fp64", 2, 4, 2): (5.7666e+06, "4f4585e2f31cc914"),
     ("cubic4_dense", "fp64", 2, 4, 4): (5.8821e+06, "4f4585e2f31cc914"),
-    ("cubic16_mixed", "fp64", 0, 1, 1): (2.3555e+10, "fee259386d9a7875"),
-    ("cubic16_mixed", "fp64", 0, 1, 2): (2.1094e+10, "fee259386d9a7875"),
-    ("cubic16_mixed", "fp64", 0, 1, 4): (1.9359e+10, "fee259386d9a7875"),
-    ("cubic16_mixed", "fp64", 0, 1, 8): (1.7973e+10, "fee259386d9a7875"),
-    ("cubic16_mixed", "fp64", 0, 2, 1): (1.9884e+10, "fee259386d9a7875"),
-    ("cubic16_mixed", "fp64", 0, 2, 2): (1.7804e+10, "fee259386d9a7875"),
-    ("cubic16_mixed", "fp64", 0, 2, 4): (1.8124e+10, "fee259386d9a7875"),
-    ("cubic16_mixed", "fp64", 0, 2, 8): (1.7241e+10, "fee259386d9a7875"),
-    ("cubic16_mixed", "fp64", 0, 4, 1): (1.4678e+10, "fee259386d9a7875"),
-    ("cubic16_mixed", "fp64", 0, 4, 2): (1.4406e+10, "fee259386d9a7875"),
-    ("cubic16_mixed", "fp64", 0, 4, 4): (1.6218e+10, "fee259386d9a7875"),
-    ("cubic16_mixed", "fp64", 1, 1, 1): (5.5683e+10, "34587538f1ff5b2c"),
-    ("cubic16_mixed", "fp64", 1, 1, 2): (5.4447e+10, "34587538f1ff5b2c"),
-    ("cubic16_mixed", "fp64", 1, 1, 4): (5.4191e+10, "34587538f1ff5b2c"),
-    ("cubic16_mixed", "fp64", 1, 1, 8): (5.3463e+10, "34587538f1ff5b2c"),
-    ("cubic16_mixed", "fp64", 1, 2, 1): (5.5339e+10, "34587538f1ff5b2c"),
-    ("cubic16_mixed", "fp64", 1, 2, 2): (5.4137e+10, "34587538f1ff5b2c"),
-    ("cubic16_mixed", "fp64", 1, 2, 4): (5.3796e+10, "34587538f1ff5b2c"),
-    ("cubic16_mixed", "fp64", 1, 4, 1): (5.7109e+10, "34587538f1ff5b2c"),
-    ("cubic16_mixed", "fp64", 1, 4, 2): (5.5666e+10, "34587538f1ff5b2c"),
-    ("cubic16_mixed", "fp64", 1, 4, 4): (5.4750e+10, "34587538f1ff5b2c"),
-    ("cubic16_mixed", "fp64", 2, 1, 1): (2.4120e+10, "d22014008889e396"),
-    ("cubic16_mixed", "fp64", 2, 1, 2): (3.1782e+10, "d22014008889e396"),
-    ("cubic16_mixed", "fp64", 2, 1, 4): (4.0030e+10, "d22014008889e396"),
-    ("cubic16_mixed", "fp64", 2, 1, 8): (3.8186e+10, "d22014008889e396"),
-    ("cubic16_mixed", "fp64", 2, 2, 1): (3.7021e+10, "d22014008889e396"),
-    ("cubic16_mixed", "fp64", 2, 2, 2): (3.3489e+10, "d22014008889e396"),
-    ("cubic16_mixed", "fp64", 2, 2, 4): (3.5007e+10, "d22014008889e396"),
-    ("cubic16_mixed", "fp64", 2, 2, 8): (3.4275e+10, "d22014008889e396"),
-    ("cubic16_mixed", "fp64", 2, 4, 1): (1.9879e+10, "d22014008889e396"),
-    ("cubic16_mixed", "fp64", 2, 4, 2): (2.2211e+10, "d22014008889e396"),
-    ("cubic16_mixed", "fp64", 2, 4, 4): (2.8669e+10, "d22014008889e396"),
+    ("cubic16_mixed", "fp64", 0, 1, 1): (2.3527e+10, "1cc333543b883126"),
+    ("cubic16_mixed", "fp64", 0, 1, 2): (2.1077e+10, "1cc333543b883126"),
+    ("cubic16_mixed", "fp64", 0, 1, 4): (1.9356e+10, "1cc333543b883126"),
+    ("cubic16_mixed", "fp64", 0, 1, 8): (1.7973e+10, "1cc333543b883126"),
+    ("cubic16_mixed", "fp64", 0, 2, 1): (1.9861e+10, "1cc333543b883126"),
+    ("cubic16_mixed", "fp64", 0, 2, 2): (1.7820e+10, "1cc333543b883126"),
+    ("cubic16_mixed", "fp64", 0, 2, 4): (1.8122e+10, "1cc333543b883126"),
+    ("cubic16_mixed", "fp64", 0, 2, 8): (1.7239e+10, "1cc333543b883126"),
+    ("cubic16_mixed", "fp64", 0, 4, 1): (1.4682e+10, "1cc333543b883126"),
+    ("cubic16_mixed", "fp64", 0, 4, 2): (1.4407e+10, "1cc333543b883126"),
+    ("cubic16_mixed", "fp64", 0, 4, 4): (1.6220e+10, "1cc333543b883126"),
+    ("cubic16_mixed", "fp64", 1, 1, 1): (5.5674e+10, "b81941651f0f1835"),
+    ("cubic16_mixed", "fp64", 1, 1, 2): (5.4450e+10, "b81941651f0f1835"),
+    ("cubic16_mixed", "fp64", 1, 1, 4): (5.4177e+10, "b81941651f0f1835"),
+    ("cubic16_mixed", "fp64", 1, 1, 8): (5.3462e+10, "b81941651f0f1835"),
+    ("cubic16_mixed", "fp64", 1, 2, 1): (5.5336e+10, "b81941651f0f1835"),
+    ("cubic16_mixed", "fp64", 1, 2, 2): (5.4144e+10, "b81941651f0f1835"),
+    ("cubic16_mixed", "fp64", 1, 2, 4): (5.3778e+10, "b81941651f0f1835"),
+    ("cubic16_mixed", "fp64", 1, 4, 1): (5.7077e+10, "b81941651f0f1835"),
+    ("cubic16_mixed", "fp64", 1, 4, 2): (5.5693e+10, "b81941651f0f1835"),
+    ("cubic16_mixed", "fp64", 1, 4, 4): (5.4744e+10, "b81941651f0f1835"),
+    ("cubic16_mixed", "fp64", 2, 1, 1): (2.3709e+10, "5a14ee69c8294660"),
+    ("cubic16_mixed", "fp64", 2, 1, 2): (3.1277e+10, "5a14ee69c8294660"),
+    ("cubic16_mixed", "fp64", 2, 1, 4): (3.9439e+10, "5a14ee69c8294660"),
+    ("cubic16_mixed", "fp64", 2, 1, 8): (3.8033e+10, "5a14ee69c8294660"),
+    ("cubic16_mixed", "fp64", 2, 2, 1): (3.1357e+10, "5a14ee69c8294660"),
+    ("cubic16_mixed", "fp64", 2, 2, 2): (3.0449e+10, "5a14ee69c8294660"),
+    ("cubic16_mixed", "fp64", 2, 2, 4): (3.5065e+10, "5a14ee69c8294660"),
+    ("cubic16_mixed", "fp64", 2, 2, 8): (3.4673e+10, "5a14ee69c8294660"),
+    ("cubic16_mixed", "fp64", 2, 4, 1): (1.9672e+10, "5a14ee69c8294660"),
+    ("cubic16_mixed", "fp64", 2, 4, 2): (3.3038e+10, "5a14ee69c8294660"),
+    ("cubic16_mixed", "fp64", 2, 4, 4): (3.3510e+10, "5a14ee69c8294660"),
 }
 
 
