@@ -394,6 +394,8 @@ void sym_product(omm_ctx* c, Pat& O, int nrows, const Pat& A, const Pat& B, cons
 
 void make_plan(omm_ctx* c, Plan& P, const Pat& O, const PatView& A, const PatView& B, const int2* win) {
   hipStream_t s = c->stream;
+  for (int r = 0; r < O.nrows; ++r)   // the pair kernels count one output row in LDS
+    if (O.hrp[r + 1] - O.hrp[r] > MAXW) throw ArgError("more than 8192 output tiles in one row of a density product");
   P.nout = (int)O.nnz;
   int64_t* cnt = dalloc<int64_t>(c, O.nnz + 1, true);
   OMM_HIP(hipMemsetAsync(cnt, 0, (O.nnz + 1) * sizeof(int64_t), s));
@@ -680,7 +682,8 @@ void ingest(omm_ctx* c, int count, const omm_matrix* H, const omm_matrix* S, con
       }
       s.RT = (int)((s.m + 15) / 16);
     }
-    if (s.RT > MAXW) throw ArgError("system too large for one symbolic window");
+    // dense systems: a density-product row holds all RT tiles (at most MAXW)
+    if (s.mode != OMM_BLOCK_SPARSE && s.RT > MAXW) throw ArgError("dense system too large for the symbolic phase");
     s.rb0 = rb;
     rb += s.RT;
   }

@@ -93,25 +93,34 @@ __global__ __launch_bounds__(SYM_THREADS) void k_sym_fill(int row0, PatView A, P
   }
 }
 
+// position of column c in output row i (its sorted columns O.ci[o0 .. o0 + no)), or -1
+__device__ __forceinline__ int out_pos(const PatView& O, int o0, int no, int c) {
+  int lo = 0, hi = no;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (O.ci[o0 + mid] < c) lo = mid + 1; else hi = mid;
+  }
+  return (lo < no && O.ci[o0 + lo] == c) ? lo : -1;
+}
+
+// Pair lists of the density-matrix products: per output tile of row i, its
+// (A, B) tile pairs in increasing k.  Output positions are found by binary
+// search in the row, so only the row's output count (at most MAXW, checked on
+// the host) bounds the LDS counters, not the width of the column window.
 __global__ __launch_bounds__(SYM_THREADS) void k_pair_count(int row0, PatView A, PatView B, PatView O,
                                                           const int2* __restrict__ win,
                                                           int64_t* __restrict__ pcnt) {
-  __shared__ int pos[MAXW];
   __shared__ int cnt[MAXW];
   const int i = row0 + blockIdx.x;
   const int2 w = win[i];
-  const int width = w.y - w.x;
   const int o0 = O.rp[i], no = O.rp[i + 1] - o0;
-  for (int t = threadIdx.x; t < width; t += blockDim.x) pos[t] = -1;
   for (int t = threadIdx.x; t < no; t += blockDim.x) cnt[t] = 0;
-  __syncthreads();
-  for (int t = threadIdx.x; t < no; t += blockDim.x) pos[O.ci[o0 + t] - w.x] = t;
   __syncthreads();
   for (int e = A.rp[i] + threadIdx.x; e < A.rp[i + 1]; e += blockDim.x) {
     const int k = A.ci[e];
     for (int jj = B.rp[k]; jj < B.rp[k + 1]; ++jj) {
-      const int c = B.ci[jj] - w.x;
-      const int p = (c >= 0 && c < width) ? pos[c] : -1;
+      const int c = B.ci[jj];
+      const int p = (c >= w.x && c < w.y) ? out_pos(O, o0, no, c) : -1;
       if (p >= 0) atomicAdd(&cnt[p], 1);
     }
   }
@@ -123,24 +132,19 @@ __global__ __launch_bounds__(SYM_THREADS) void k_pair_fill(int row0, PatView A, 
                                                          const int2* __restrict__ win,
                                                          const int64_t* __restrict__ pp,
                                                          int2* __restrict__ pairs) {
-  __shared__ int pos[MAXW];
   __shared__ int fill[MAXW];
   const int i = row0 + blockIdx.x;
   const int2 w = win[i];
-  const int width = w.y - w.x;
   const int o0 = O.rp[i], no = O.rp[i + 1] - o0;
-  for (int t = threadIdx.x; t < width; t += blockDim.x) pos[t] = -1;
   for (int t = threadIdx.x; t < no; t += blockDim.x) fill[t] = 0;
-  __syncthreads();
-  for (int t = threadIdx.x; t < no; t += blockDim.x) pos[O.ci[o0 + t] - w.x] = t;
   __syncthreads();
   // k in increasing order; within one k every output column is hit at most once
   for (int e = A.rp[i]; e < A.rp[i + 1]; ++e) {
     const int k = A.ci[e];
     const int at = a_tile(A, e);
     for (int jj = B.rp[k] + threadIdx.x; jj < B.rp[k + 1]; jj += blockDim.x) {
-      const int c = B.ci[jj] - w.x;
-      const int p = (c >= 0 && c < width) ? pos[c] : -1;
+      const int c = B.ci[jj];
+      const int p = (c >= w.x && c < w.y) ? out_pos(O, o0, no, c) : -1;
       if (p >= 0) {
         const int64_t slot = pp[o0 + p] + fill[p];
         fill[p] += 1;

@@ -171,3 +171,34 @@ def test_cubic16_first_iterations_match_the_oracle():
         assert abs(h[i, 8] - ho[i, 8]) <= 1e-9 * max(ho[i, 8], 1e-3)            # beta
         assert h[i, 9] == ho[i, 9]
     ctx.close()
+
+
+def test_chain_beyond_the_old_symbolic_window():
+    # A 9000-atom periodic chain (4 orbitals and 2 wavefunctions per atom, R_C 3.0):
+    # 9000 basis tile rows, more than the 8192 the symbolic phase's windows once
+    # allowed.  Pinned by sparse products on the CPU: the start-up energy
+    # E0 = 2 Tr[(2I - S_W) H_W] is the quartic's c0 of the first iteration, and its
+    # c1 is the directional derivative <G0, D0> = -||G0||^2 along D0 = -G0
+    # (G0 projected on C's pattern, Sec. III B).
+    import scipy.sparse as sp
+    from ommgen.systems import SystemSpec, make_system
+    spec = SystemSpec("chain9000", (9000,), 4, 2, (-1.0, -1.0, 1.0, 1.0), seed=41, rc=3.0, eta=1.5, dense=False)
+    s = make_system(spec)
+    ctx = Context([Problem(s.H, s.S, s.C0, s.n, L.OMM_BLOCK_SPARSE)], eta=spec.eta, max_iter=3)
+    rc, reps = ctx.minimize()
+    h = ctx.history(0)
+    assert h.shape[0] == 3 and np.all(np.isfinite(h[:, :8]))
+    H = s.H.to_bsr().tocsr()
+    S = s.S.to_bsr().tocsr()
+    C = s.C0.to_bsr().tocsr()
+    Hs = H - spec.eta * S
+    HC, SC = Hs @ C, S @ C
+    HW, SW = (C.T @ HC).tocsr(), (C.T @ SC).tocsr()
+    E0 = 2.0 * (2.0 * HW.diagonal().sum() - SW.multiply(HW.T).sum())
+    G0 = (8.0 * HC - 4.0 * (HC @ SW + SC @ HW)).tocsr()
+    mask = (abs(C) > 0).astype(float)   # C0's stored blocks are dense random: its pattern
+    G0 = G0.multiply(mask)
+    assert abs(h[0, 1] - E0) <= 1e-10 * abs(E0)
+    assert abs(h[0, 2] + G0.multiply(G0).sum()) <= 1e-9 * G0.multiply(G0).sum()
+    assert h[2, 0] < h[1, 0] < h[0, 0] < E0   # the energy decreases at every step
+    ctx.close()
