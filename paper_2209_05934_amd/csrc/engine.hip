@@ -1140,6 +1140,9 @@ void prepare(omm_ctx* c) {
   }
   pick_plans(c);
   b.roll = c->nsys > 1 ? 1 : 0;
+  b.grad_steps = 0;
+  for (int i = 0; i < c->nsys; ++i)
+    if (c->sys[i].mode == OMM_BLOCK_SPARSE) b.grad_steps = 1;
   b.H = c->H; b.S = c->S;
   b.C = dalloc<double>(c, ntc * TE, true);
   b.D = dalloc<double>(c, ntc * TE, true);

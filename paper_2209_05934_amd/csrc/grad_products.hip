@@ -12,8 +12,9 @@ namespace {
 // SC(b,k) tiles are loaded once for NT tiles of S_W and H_W.  An entry's S_W/H_W
 // tile index carries the MFMA steps (groups of four wavefunctions of tile k)
 // where HC(b,k) has no nonzero column or S_W(k,g) no nonzero row: those steps
-// are skipped.
-template <typename TI, int KS, int NT, bool ROLL>
+// are skipped (STEPS: contexts with block-sparse systems; dense ones keep every
+// step and run the straight-line form, whose MFMAs are not split by branches).
+template <typename TI, int KS, int NT, bool ROLL, bool STEPS>
 __global__ __launch_bounds__(Split<KS>::NW * 64) void k_grad(
     GroupView P, const SysState* __restrict__ st, int mask, const TI* __restrict__ HCm,
     const TI* __restrict__ SCm, const TI* __restrict__ S0m, const TI* __restrict__ H0m,
@@ -59,10 +60,15 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_grad(
         [&](const Stage& f, const int (&id)[W]) {
 #pragma unroll
           for (int u = 0; u < NT; ++u) {
-            if (id[1 + u] >= 0) {   // only the MFMA steps whose wavefunction pairs couple
-              const int act = ent_steps(id[1 + u]);
-              mma(acc[u], f.h, f.w[u], act);
-              mma(acc[u], f.s, f.v[u], act);
+            if (id[1 + u] >= 0) {
+              if constexpr (STEPS) {   // only the MFMA steps whose wavefunction pairs couple
+                const int act = ent_steps(id[1 + u]);
+                mma(acc[u], f.h, f.w[u], act);
+                mma(acc[u], f.s, f.v[u], act);
+              } else {
+                mma(acc[u], f.h, f.w[u]);
+                mma(acc[u], f.s, f.v[u]);
+              }
             }
           }
         });
@@ -103,12 +109,18 @@ static void grad_go(hipStream_t s, const Bufs& b, int mask, const TI* HC, const 
   if (b.grad.ngroups <= 0) return;
   nt_ks<2>(b.grad.NT, b.ks[2], [&](auto ntc, auto ksc) {
     constexpr int N_ = decltype(ntc)::value, K_ = decltype(ksc)::value;
-    if (b.roll)
-      LAUNCH((k_grad<TI, K_, N_, true>), grid_for<K_>(b.grad.ngroups), block_for<K_>(), s, b.grad, b.st, mask, HC,
+    auto go = [&](auto rollc, auto stepsc) {
+      constexpr bool R_ = decltype(rollc)::value, S_ = decltype(stepsc)::value;
+      LAUNCH((k_grad<TI, K_, N_, R_, S_>), grid_for<K_>(b.grad.ngroups), block_for<K_>(), s, b.grad, b.st, mask, HC,
              SC, S0, H0, b.HC, b.c_in_hc, b.cmask, b.Gold, b.G, b.gpart);
-    else
-      LAUNCH((k_grad<TI, K_, N_, false>), grid_for<K_>(b.grad.ngroups), block_for<K_>(), s, b.grad, b.st, mask, HC,
-             SC, S0, H0, b.HC, b.c_in_hc, b.cmask, b.Gold, b.G, b.gpart);
+    };
+    if (b.roll) {
+      if (b.grad_steps) go(std::true_type{}, std::true_type{});
+      else go(std::true_type{}, std::false_type{});
+    } else {
+      if (b.grad_steps) go(std::false_type{}, std::true_type{});
+      else go(std::false_type{}, std::false_type{});
+    }
   });
 }
 

@@ -86,6 +86,7 @@ struct Bufs {   // every device buffer the iteration kernels touch
   double eps2;                   // filter threshold squared (block-sparse products)
   int ks[3];                     // waves splitting one output tile: direction, n x n, gradient products
   int roll;                      // product kernels with the rolled work-list loop (multi-system contexts)
+  int grad_steps;                // gradient entries carry skipped MFMA steps (a block-sparse system present)
 };
 
 // the n x n work-list copy of an iteration: pairs whose H D and S D tiles are both zero marked absent
