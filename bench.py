@@ -70,70 +70,70 @@ PEAKS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}   # dense TFLOP/s of MI355
 # group width and split, and valid only for the kernel sources they were taken
 # with (sha256 prefix of the step's source file, tile_sched.hpp and tile_ops.hpp)
 MEASURED_TRAFFIC = {
-    ("cubic4_dense", "fp64", 0, 1, 1): (2.0901e+07, "8bed00890865259c"),
-    ("cubic4_dense", "fp64", 0, 1, 2): (2.0877e+07, "8bed00890865259c"),
-    ("cubic4_dense", "fp64", 0, 1, 4): (2.0816e+07, "8bed00890865259c"),
-    ("cubic4_dense", "fp64", 0, 1, 8): (2.0777e+07, "8bed00890865259c"),
-    ("cubic4_dense", "fp64", 0, 2, 1): (1.9986e+07, "8bed00890865259c"),
-    ("cubic4_dense", "fp64", 0, 2, 2): (2.0861e+07, "8bed00890865259c"),
-    ("cubic4_dense", "fp64", 0, 2, 4): (2.0834e+07, "8bed00890865259c"),
-    ("cubic4_dense", "fp64", 0, 2, 8): (2.0785e+07, "8bed00890865259c"),
-    ("cubic4_dense", "fp64", 0, 4, 1): (2.0021e+07, "8bed00890865259c"),
-    ("cubic4_dense", "fp64", 0, 4, 2): (2.0058e+07, "8bed00890865259c"),
-    ("cubic4_dense", "fp64", 0, 4, 4): (2.0952e+07, "8bed00890865259c"),
-    ("cubic4_dense", "fp64", 1, 1, 1): (1.6204e+07, "fa69ae1cfaaafee5"),
-    ("cubic4_dense", "fp64", 1, 1, 2): (1.6196e+07, "fa69ae1cfaaafee5"),
-    ("cubic4_dense", "fp64", 1, 1, 4): (1.6078e+07, "fa69ae1cfaaafee5"),
-    ("cubic4_dense", "fp64", 1, 1, 8): (1.5991e+07, "fa69ae1cfaaafee5"),
-    ("cubic4_dense", "fp64", 1, 2, 1): (1.6273e+07, "fa69ae1cfaaafee5"),
-    ("cubic4_dense", "fp64", 1, 2, 2): (1.6305e+07, "fa69ae1cfaaafee5"),
-    ("cubic4_dense", "fp64", 1, 2, 4): (1.6217e+07, "fa69ae1cfaaafee5"),
-    ("cubic4_dense", "fp64", 1, 4, 1): (9.2129e+06, "fa69ae1cfaaafee5"),
-    ("cubic4_dense", "fp64", 1, 4, 2): (1.6375e+07, "fa69ae1cfaaafee5"),
-    ("cubic4_dense", "fp64", 1, 4, 4): (1.6417e+07, "fa69ae1cfaaafee5"),
-    ("cubic4_dense", "fp64", 2, 1, 1): (5.8124e+06, "4f4585e2f31cc914"),
-    ("cubic4_dense", "fp64", 2, 1, 2): (5.7909e+06, "4f4585e2f31cc914"),
-    ("cubic4_dense", "fp64", 2, 1, 4): (5.7858e+06, "4f4585e2f31cc914"),
-    ("cubic4_dense", "fp64", 2, 1, 8): (5.7889e+06, "4f4585e2f31cc914"),
-    ("cubic4_dense", "fp64", 2, 2, 1): (5.7248e+06, "4f4585e2f31cc914"),
-    ("cubic4_dense", "fp64", 2, 2, 2): (5.8323e+06, "4f4585e2f31cc914"),
-    ("cubic4_dense", "fp64", 2, 2, 4): (5.8190e+06, "4f4585e2f31cc914"),
-    ("cubic4_dense", "fp64", 2, 2, 8): (5.8046e+06, "4f4585e2f31cc914"),
-    ("cubic4_dense", "fp64", 2, 4, 1): (5.8147e+06, "4f4585e2f31cc914"),
-    ("cubic4_dense", "fp64", 2, 4, 2): (5.7666e+06, "4f4585e2f31cc914"),
-    ("cubic4_dense", "fp64", 2, 4, 4): (5.8821e+06, "4f4585e2f31cc914"),
-    ("cubic16_mixed", "fp64", 0, 1, 1): (2.3527e+10, "1cc333543b883126"),
-    ("cubic16_mixed", "fp64", 0, 1, 2): (2.1077e+10, "1cc333543b883126"),
-    ("cubic16_mixed", "fp64", 0, 1, 4): (1.9356e+10, "1cc333543b883126"),
+    ("cubic4_dense", "fp64", 0, 1, 1): (3.6251e+07, "1cc333543b883126"),
+    ("cubic4_dense", "fp64", 0, 1, 2): (3.6231e+07, "1cc333543b883126"),
+    ("cubic4_dense", "fp64", 0, 1, 4): (3.6524e+07, "1cc333543b883126"),
+    ("cubic4_dense", "fp64", 0, 1, 8): (3.8230e+07, "1cc333543b883126"),
+    ("cubic4_dense", "fp64", 0, 2, 1): (3.6204e+07, "1cc333543b883126"),
+    ("cubic4_dense", "fp64", 0, 2, 2): (3.6218e+07, "1cc333543b883126"),
+    ("cubic4_dense", "fp64", 0, 2, 4): (3.6185e+07, "1cc333543b883126"),
+    ("cubic4_dense", "fp64", 0, 2, 8): (3.6124e+07, "1cc333543b883126"),
+    ("cubic4_dense", "fp64", 0, 4, 1): (2.8147e+07, "1cc333543b883126"),
+    ("cubic4_dense", "fp64", 0, 4, 2): (2.9006e+07, "1cc333543b883126"),
+    ("cubic4_dense", "fp64", 0, 4, 4): (2.9465e+07, "1cc333543b883126"),
+    ("cubic4_dense", "fp64", 1, 1, 1): (1.6231e+07, "b81941651f0f1835"),
+    ("cubic4_dense", "fp64", 1, 1, 2): (1.6226e+07, "b81941651f0f1835"),
+    ("cubic4_dense", "fp64", 1, 1, 4): (1.6110e+07, "b81941651f0f1835"),
+    ("cubic4_dense", "fp64", 1, 1, 8): (1.6010e+07, "b81941651f0f1835"),
+    ("cubic4_dense", "fp64", 1, 2, 1): (1.6320e+07, "b81941651f0f1835"),
+    ("cubic4_dense", "fp64", 1, 2, 2): (1.6351e+07, "b81941651f0f1835"),
+    ("cubic4_dense", "fp64", 1, 2, 4): (1.6258e+07, "b81941651f0f1835"),
+    ("cubic4_dense", "fp64", 1, 4, 1): (9.2645e+06, "b81941651f0f1835"),
+    ("cubic4_dense", "fp64", 1, 4, 2): (1.6437e+07, "b81941651f0f1835"),
+    ("cubic4_dense", "fp64", 1, 4, 4): (1.6501e+07, "b81941651f0f1835"),
+    ("cubic4_dense", "fp64", 2, 1, 1): (7.8655e+06, "8b293585b2190e62"),
+    ("cubic4_dense", "fp64", 2, 1, 2): (7.8471e+06, "8b293585b2190e62"),
+    ("cubic4_dense", "fp64", 2, 1, 4): (7.8369e+06, "8b293585b2190e62"),
+    ("cubic4_dense", "fp64", 2, 1, 8): (7.8297e+06, "8b293585b2190e62"),
+    ("cubic4_dense", "fp64", 2, 2, 1): (7.8416e+06, "8b293585b2190e62"),
+    ("cubic4_dense", "fp64", 2, 2, 2): (7.8618e+06, "8b293585b2190e62"),
+    ("cubic4_dense", "fp64", 2, 2, 4): (7.8669e+06, "8b293585b2190e62"),
+    ("cubic4_dense", "fp64", 2, 2, 8): (7.8465e+06, "8b293585b2190e62"),
+    ("cubic4_dense", "fp64", 2, 4, 1): (6.7464e+06, "8b293585b2190e62"),
+    ("cubic4_dense", "fp64", 2, 4, 2): (6.9404e+06, "8b293585b2190e62"),
+    ("cubic4_dense", "fp64", 2, 4, 4): (7.0579e+06, "8b293585b2190e62"),
+    ("cubic16_mixed", "fp64", 0, 1, 1): (2.3546e+10, "1cc333543b883126"),
+    ("cubic16_mixed", "fp64", 0, 1, 2): (2.1083e+10, "1cc333543b883126"),
+    ("cubic16_mixed", "fp64", 0, 1, 4): (1.9357e+10, "1cc333543b883126"),
     ("cubic16_mixed", "fp64", 0, 1, 8): (1.7973e+10, "1cc333543b883126"),
-    ("cubic16_mixed", "fp64", 0, 2, 1): (1.9861e+10, "1cc333543b883126"),
-    ("cubic16_mixed", "fp64", 0, 2, 2): (1.7820e+10, "1cc333543b883126"),
-    ("cubic16_mixed", "fp64", 0, 2, 4): (1.8122e+10, "1cc333543b883126"),
-    ("cubic16_mixed", "fp64", 0, 2, 8): (1.7239e+10, "1cc333543b883126"),
-    ("cubic16_mixed", "fp64", 0, 4, 1): (1.4682e+10, "1cc333543b883126"),
-    ("cubic16_mixed", "fp64", 0, 4, 2): (1.4407e+10, "1cc333543b883126"),
-    ("cubic16_mixed", "fp64", 0, 4, 4): (1.6220e+10, "1cc333543b883126"),
-    ("cubic16_mixed", "fp64", 1, 1, 1): (5.5674e+10, "b81941651f0f1835"),
-    ("cubic16_mixed", "fp64", 1, 1, 2): (5.4450e+10, "b81941651f0f1835"),
-    ("cubic16_mixed", "fp64", 1, 1, 4): (5.4177e+10, "b81941651f0f1835"),
+    ("cubic16_mixed", "fp64", 0, 2, 1): (1.9890e+10, "1cc333543b883126"),
+    ("cubic16_mixed", "fp64", 0, 2, 2): (1.7823e+10, "1cc333543b883126"),
+    ("cubic16_mixed", "fp64", 0, 2, 4): (1.8128e+10, "1cc333543b883126"),
+    ("cubic16_mixed", "fp64", 0, 2, 8): (1.7240e+10, "1cc333543b883126"),
+    ("cubic16_mixed", "fp64", 0, 4, 1): (1.4684e+10, "1cc333543b883126"),
+    ("cubic16_mixed", "fp64", 0, 4, 2): (1.4403e+10, "1cc333543b883126"),
+    ("cubic16_mixed", "fp64", 0, 4, 4): (1.6216e+10, "1cc333543b883126"),
+    ("cubic16_mixed", "fp64", 1, 1, 1): (5.5693e+10, "b81941651f0f1835"),
+    ("cubic16_mixed", "fp64", 1, 1, 2): (5.4448e+10, "b81941651f0f1835"),
+    ("cubic16_mixed", "fp64", 1, 1, 4): (5.4182e+10, "b81941651f0f1835"),
     ("cubic16_mixed", "fp64", 1, 1, 8): (5.3462e+10, "b81941651f0f1835"),
-    ("cubic16_mixed", "fp64", 1, 2, 1): (5.5336e+10, "b81941651f0f1835"),
+    ("cubic16_mixed", "fp64", 1, 2, 1): (5.5340e+10, "b81941651f0f1835"),
     ("cubic16_mixed", "fp64", 1, 2, 2): (5.4144e+10, "b81941651f0f1835"),
     ("cubic16_mixed", "fp64", 1, 2, 4): (5.3778e+10, "b81941651f0f1835"),
-    ("cubic16_mixed", "fp64", 1, 4, 1): (5.7077e+10, "b81941651f0f1835"),
-    ("cubic16_mixed", "fp64", 1, 4, 2): (5.5693e+10, "b81941651f0f1835"),
-    ("cubic16_mixed", "fp64", 1, 4, 4): (5.4744e+10, "b81941651f0f1835"),
-    ("cubic16_mixed", "fp64", 2, 1, 1): (2.3709e+10, "5a14ee69c8294660"),
-    ("cubic16_mixed", "fp64", 2, 1, 2): (3.1277e+10, "5a14ee69c8294660"),
-    ("cubic16_mixed", "fp64", 2, 1, 4): (3.9439e+10, "5a14ee69c8294660"),
-    ("cubic16_mixed", "fp64", 2, 1, 8): (3.8033e+10, "5a14ee69c8294660"),
-    ("cubic16_mixed", "fp64", 2, 2, 1): (3.1357e+10, "5a14ee69c8294660"),
-    ("cubic16_mixed", "fp64", 2, 2, 2): (3.0449e+10, "5a14ee69c8294660"),
-    ("cubic16_mixed", "fp64", 2, 2, 4): (3.5065e+10, "5a14ee69c8294660"),
-    ("cubic16_mixed", "fp64", 2, 2, 8): (3.4673e+10, "5a14ee69c8294660"),
-    ("cubic16_mixed", "fp64", 2, 4, 1): (1.9672e+10, "5a14ee69c8294660"),
-    ("cubic16_mixed", "fp64", 2, 4, 2): (3.3038e+10, "5a14ee69c8294660"),
-    ("cubic16_mixed", "fp64", 2, 4, 4): (3.3510e+10, "5a14ee69c8294660"),
+    ("cubic16_mixed", "fp64", 1, 4, 1): (5.7076e+10, "b81941651f0f1835"),
+    ("cubic16_mixed", "fp64", 1, 4, 2): (5.5692e+10, "b81941651f0f1835"),
+    ("cubic16_mixed", "fp64", 1, 4, 4): (5.4745e+10, "b81941651f0f1835"),
+    ("cubic16_mixed", "fp64", 2, 1, 1): (2.3736e+10, "8b293585b2190e62"),
+    ("cubic16_mixed", "fp64", 2, 1, 2): (3.1220e+10, "8b293585b2190e62"),
+    ("cubic16_mixed", "fp64", 2, 1, 4): (3.9626e+10, "8b293585b2190e62"),
+    ("cubic16_mixed", "fp64", 2, 1, 8): (3.8126e+10, "8b293585b2190e62"),
+    ("cubic16_mixed", "fp64", 2, 2, 1): (3.0992e+10, "8b293585b2190e62"),
+    ("cubic16_mixed", "fp64", 2, 2, 2): (3.0503e+10, "8b293585b2190e62"),
+    ("cubic16_mixed", "fp64", 2, 2, 4): (3.5116e+10, "8b293585b2190e62"),
+    ("cubic16_mixed", "fp64", 2, 2, 8): (3.4733e+10, "8b293585b2190e62"),
+    ("cubic16_mixed", "fp64", 2, 4, 1): (1.9631e+10, "8b293585b2190e62"),
+    ("cubic16_mixed", "fp64", 2, 4, 2): (3.2932e+10, "8b293585b2190e62"),
+    ("cubic16_mixed", "fp64", 2, 4, 4): (3.2778e+10, "8b293585b2190e62"),
 }
 
 
