@@ -5,7 +5,8 @@
 //   S = L L^T (L = U^T lower triangular),  H~ = L^-1 H L^-T,  C~ = L^T C,
 //   and after minimization C = L^-T C~.
 //
-// All matrices are dense grids of 16x16 tiles (tile (I, J) at base + I*ld + J).
+// All matrices are dense grids of 16x16 tiles (tile (I, J) at base + I*ld + J,
+// elements in the storage order of tpos).
 // The factorization is right-looking by tile columns: factor the diagonal
 // tile (and invert it) in LDS, scale the panel below it by L_KK^-T on MFMA,
 // update the trailing lower triangle with one MFMA tile product per tile.
@@ -27,7 +28,7 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ A, int b
   __shared__ double li[16][17];
   const int tid = threadIdx.x, r = tid >> 4, c = tid & 15;
   double* tile = A + tix(base, RT, K, K);
-  a[r][c] = tile[r * 16 + c];
+  a[r][c] = tile[tpos(r, c)];
   __syncthreads();
   for (int k = 0; k < 16; ++k) {
     if (tid == 0) {
@@ -44,7 +45,7 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ A, int b
     if (r > k && c > k && c <= r) a[r][c] -= a[r][k] * a[c][k];
     __syncthreads();
   }
-  tile[r * 16 + c] = (c <= r) ? a[r][c] : 0.0;
+  tile[tpos(r, c)] = (c <= r) ? a[r][c] : 0.0;
   if (tid < 16) {   // column j of L^-1 by forward substitution
     const int j = tid;
     for (int i = 0; i < 16; ++i) {
@@ -58,7 +59,7 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ A, int b
     }
   }
   __syncthreads();
-  Linv[(size_t)K * TE + r * 16 + c] = li[r][c];
+  Linv[(size_t)K * TE + tpos(r, c)] = li[r][c];
 }
 
 // L(I,K) = A(I,K) L_KK^-T for I > K
@@ -118,10 +119,10 @@ __global__ __launch_bounds__(256) void k_trsm_fwd(const double* __restrict__ L, 
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int row = Lay<d4>::row(q, r);
-    const double bv = transB ? B[tix(bbase, ncols, J, I) + j * 16 + row] : B[tix(bbase, ncols, I, J) + row * 16 + j];
+    const double bv = transB ? B[tix(bbase, ncols, J, I) + tpos(j, row)] : B[tix(bbase, ncols, I, J) + tpos(row, j)];
     rhs[r] = bv - acc[r];
   }
-  __shared__ double lt[4][TE];
+  __shared__ __align__(16) double lt[4][TE];
   Frag<double> fa, fb = acc_as_b_lds(rhs, lt[threadIdx.x >> 6], lane);
   ld_row(fa, Linv + (size_t)I * TE, lane);
   d4 out = vzero<d4>();
@@ -167,7 +168,7 @@ __global__ __launch_bounds__(256) void k_trsm_bwd_t(const double* __restrict__ L
   d4 rhs;
 #pragma unroll
   for (int r = 0; r < 4; ++r) rhs[r] = Cin[tix(cbase, WT, I, g) + out_off<d4>(lane, r)] - acc[r];
-  __shared__ double lt[4][TE];
+  __shared__ __align__(16) double lt[4][TE];
   Frag<double> fa, fb = acc_as_b_lds(rhs, lt[threadIdx.x >> 6], lane);
   ld_col(fa, Linv + (size_t)I * TE, lane);         // A = Linv_I^T
   d4 out = vzero<d4>();

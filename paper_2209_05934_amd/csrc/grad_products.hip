@@ -86,9 +86,9 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_grad(
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = Lay<V>::row(q, r);
-      const int e = row * 16 + j;
+      const int e = tpos(row, j);
       const bool in = ((mk >> row) & 1u) && ((mk >> (16 + j)) & 1u);
-      const double gv = in ? 8.0 * hc[j * 16 + row] - 4.0 * (double)acc[u][r] : 0.0;
+      const double gv = in ? 8.0 * hc[tpos(j, row)] - 4.0 * (double)acc[u][r] : 0.0;
       G[(size_t)t * TE + e] = gv;
       gg += gv * gv;
       go += gv * Gold[(size_t)t * TE + e];

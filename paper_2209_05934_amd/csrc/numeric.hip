@@ -178,7 +178,7 @@ __device__ void ls_apply(SysState& S, const double* c, double ne, bool ok, doubl
 // sums: 0 Tr H0, 1 Tr Y, 2 Tr H2, 3 <S0,H0>, 4 <S0,Y>, 5 <X,H0>, 6 <S0,H2>, 7 <X,Y>,
 //       8 <X,Y^T>, 9 <S2,H0>, 10 <X,H2>, 11 <S2,Y>, 12 <S2,H2>, 13 Tr S0, 14 <S0,S0>
 // Every workgroup reduces a chunk of n x n tiles of one system, one tile per
-// wave at a time (each lane holds four consecutive elements of one tile row),
+// wave at a time (each lane holds four consecutive storage positions of a tile),
 // into one partial per sum; the partials of a system are added in chunk order
 // by sum_partials wherever the quartic is needed.  A tile is on the block
 // diagonal exactly when its transpose is itself.
@@ -196,13 +196,21 @@ __global__ __launch_bounds__(256) void k_traces(const int4* __restrict__ chunks,
 #pragma unroll
   for (int k = 0; k < NSUM; ++k) a[k] = 0.0;
   const int lane = threadIdx.x & 63, wv = wave_id();
-  const int r = lane >> 2, c0 = (lane & 3) * 4;   // row r, columns c0 .. c0 + 3
+  // storage positions 4 lane + i: element (row, column) and the position of
+  // its transpose
+  bool on_diag[4];
+  int pt[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int p = 4 * lane + i;
+    on_diag[i] = trow(p) == tcol(p);
+    pt[i] = tpos(tcol(p), trow(p));
+  }
 #pragma unroll 2
   for (int t = ch.x + wv; t < ch.y; t += 4) {
     const int tt = wtr[t];
-    const size_t o = (size_t)t * TE + r * 16 + c0;
-    const size_t ot = (size_t)tt * TE + c0 * 16 + r;
-    const bool diag = tt == t && r >= c0 && r < c0 + 4;
+    const size_t o = (size_t)t * TE + 4 * lane;
+    const size_t tb = (size_t)tt * TE;
     const bool mir = sym2 && tt < t;   // S2, H2 below the diagonal: transpose of the mirror tile
     double h0[4], s0[4], x[4], y[4], s2[4], h2[4], yt[4];
 #pragma unroll
@@ -211,13 +219,13 @@ __global__ __launch_bounds__(256) void k_traces(const int4* __restrict__ chunks,
       s0[i] = S0[o + i];
       x[i] = (double)X[o + i];
       y[i] = (double)Y[o + i];
-      s2[i] = (double)(mir ? S2[ot + 16 * i] : S2[o + i]);
-      h2[i] = (double)(mir ? H2[ot + 16 * i] : H2[o + i]);
-      yt[i] = (double)Y[ot + 16 * i];
+      s2[i] = (double)(mir ? S2[tb + pt[i]] : S2[o + i]);
+      h2[i] = (double)(mir ? H2[tb + pt[i]] : H2[o + i]);
+      yt[i] = (double)Y[tb + pt[i]];
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      if (diag && c0 + i == r) {
+      if (tt == t && on_diag[i]) {
         a[0] += h0[i]; a[1] += y[i]; a[2] += h2[i]; a[13] += s0[i];
       }
       a[3] += s0[i] * h0[i]; a[4] += s0[i] * y[i]; a[5] += x[i] * h0[i]; a[6] += s0[i] * h2[i];
@@ -283,7 +291,7 @@ __global__ __launch_bounds__(64) void k_ls_state(const SysInfo* __restrict__ inf
 
 // ------------------------------------------------------------------ line search + updates (one launch)
 // One wave per tile of the concatenated list [C tiles | HC/SC tiles | n x n
-// tiles]; each lane holds four consecutive elements of one tile row.  For a
+// tiles]; each lane holds four consecutive storage positions of a tile.  For a
 // system of at most FUSED_CHUNKS trace chunks every wave adds the chunk
 // partials and solves the line search itself (same inputs, same operations:
 // the same step in every wave, and its operand loads overlap the search); the
@@ -311,18 +319,20 @@ __global__ __launch_bounds__(256) void k_update(int nc, int nhc, int ntot, const
   const int ch0 = info[s].ch0, ch1 = info[s].ch1;
   const int kind = T < nc ? 0 : (T < nc + nhc ? 1 : 2);
   const int t = kind == 0 ? T : (kind == 1 ? T - nc : T - nc - nhc);
-  const int r = lane >> 2, c0 = (lane & 3) * 4;
-  const size_t o = (size_t)t * TE + r * 16 + c0;
+  const size_t o = (size_t)t * TE + 4 * lane;
+  int pt[4];   // position of the transpose of the element at storage position 4 lane + i
+#pragma unroll
+  for (int i = 0; i < 4; ++i) pt[i] = tpos(tcol(4 * lane + i), trow(4 * lane + i));
   // operands first: their loads overlap the line search
   double u[4], v[4], p[4], q[4], w[4], z[4];
   if (kind == 0) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) { u[i] = C[o + i]; p[i] = D[o + i]; }
-  } else if (kind == 1) {   // HC, SC tiles are stored transposed: element (r, c) at c * 16 + r
-    const size_t ot = (size_t)t * TE + c0 * 16 + r;
+  } else if (kind == 1) {   // HC, SC tiles are stored transposed: element (r, c) at tpos(c, r)
+    const size_t tb = (size_t)t * TE;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      u[i] = HC[ot + 16 * i]; v[i] = SC[ot + 16 * i]; p[i] = (double)HD[o + i]; q[i] = (double)SD[o + i];
+      u[i] = HC[tb + pt[i]]; v[i] = SC[tb + pt[i]]; p[i] = (double)HD[o + i]; q[i] = (double)SD[o + i];
     }
   } else {
     // H_W and S_W stay symmetric, and so do their increments: the wave of a tile
@@ -330,12 +340,12 @@ __global__ __launch_bounds__(256) void k_update(int nc, int nhc, int ntot, const
     // tile (the sum Y + Y^T commutes bitwise), and waves below the diagonal stop
     const int tt = wtr[t];
     if (tt < t) return;
-    const size_t ot = (size_t)tt * TE + c0 * 16 + r;
+    const size_t tb = (size_t)tt * TE;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       u[i] = H0[o + i]; v[i] = S0[o + i];
-      p[i] = (double)Y[o + i] + (double)Y[ot + 16 * i];
-      q[i] = (double)X[o + i] + (double)X[ot + 16 * i];
+      p[i] = (double)Y[o + i] + (double)Y[tb + pt[i]];
+      q[i] = (double)X[o + i] + (double)X[tb + pt[i]];
       w[i] = (double)H2[o + i];
       z[i] = (double)S2[o + i];
     }
@@ -360,20 +370,20 @@ __global__ __launch_bounds__(256) void k_update(int nc, int nhc, int ntot, const
       if (LOW) Cl[o + i] = cvt<TL, double>(nv);
     }
   } else if (kind == 1) {
-    const size_t ot = (size_t)t * TE + c0 * 16 + r;
+    const size_t tb = (size_t)t * TE;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const double h = u[i] + x * p[i], g = v[i] + x * q[i];
-      HC[ot + 16 * i] = h;
-      SC[ot + 16 * i] = g;
+      HC[tb + pt[i]] = h;
+      SC[tb + pt[i]] = g;
       if (LOW) {
-        HCl[ot + 16 * i] = cvt<TL, double>(h);
-        SCl[ot + 16 * i] = cvt<TL, double>(g);
+        HCl[tb + pt[i]] = cvt<TL, double>(h);
+        SCl[tb + pt[i]] = cvt<TL, double>(g);
       }
     }
   } else {
     const int tt = wtr[t];
-    const size_t ot = (size_t)tt * TE + c0 * 16 + r;
+    const size_t tb = (size_t)tt * TE;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const double h = u[i] + x * p[i] + x * x * w[i];
@@ -384,12 +394,12 @@ __global__ __launch_bounds__(256) void k_update(int nc, int nhc, int ntot, const
         H0l[o + i] = cvt<TL, double>(h);
         S0l[o + i] = cvt<TL, double>(g);
       }
-      if (tt != t) {   // element (r, c0 + i) of the mirror tile's transpose
-        H0[ot + 16 * i] = h;
-        S0[ot + 16 * i] = g;
+      if (tt != t) {   // the same element of the mirror tile's transpose
+        H0[tb + pt[i]] = h;
+        S0[tb + pt[i]] = g;
         if (LOW) {
-          H0l[ot + 16 * i] = cvt<TL, double>(h);
-          S0l[ot + 16 * i] = cvt<TL, double>(g);
+          H0l[tb + pt[i]] = cvt<TL, double>(h);
+          S0l[tb + pt[i]] = cvt<TL, double>(g);
         }
       }
     }
@@ -510,7 +520,7 @@ __global__ __launch_bounds__(256) void k_beta(const SysInfo* __restrict__ info, 
 }
 
 // D = -Z + beta D (Z = G, or P G under kinetic preconditioning) and G_old = G:
-// one wave per C tile, four consecutive elements of one tile row per lane.
+// one wave per C tile, four consecutive storage positions per lane.
 // For a system of at most FUSED_CTILES C tiles every wave adds the per-tile
 // sums in tile order and forms beta itself (the same value in every wave); the
 // wave of the system's first C tile also applies the stop rules and records
@@ -532,7 +542,7 @@ __global__ __launch_bounds__(256) void k_update_d(int nc, const int* __restrict_
   if (!on(st, s, mask)) return;
   if (LOW && st[s].prec == 0) return;
   const int ci0 = info[s].c0, ci1 = info[s].c1;
-  const size_t o = (size_t)t * TE + (lane >> 2) * 16 + (lane & 3) * 4;
+  const size_t o = (size_t)t * TE + 4 * lane;
   const double* Zs = zpart ? Z : G;
   double g[4], z[4], dv[4];
 #pragma unroll
@@ -577,20 +587,19 @@ __global__ __launch_bounds__(256) void k_mirror_w(int ntw, int woff, const int* 
   const int rt = tw_row[t], ct = tw_col[t];
   if (rt < ct) return;
   const int lane = threadIdx.x & 63;
-  const int r = lane >> 2, c0 = (lane & 3) * 4;
   const size_t src = (size_t)(rt == ct ? t : wtr[t]) * TE;
   const size_t dst = (size_t)t * TE;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int c = c0 + i;
+    const int p = 4 * lane + i, r = trow(p), c = tcol(p);
     if (rt == ct && r <= c) continue;
-    H0[dst + r * 16 + c] = H0[src + c * 16 + r];
-    S0[dst + r * 16 + c] = S0[src + c * 16 + r];
+    H0[dst + p] = H0[src + tpos(c, r)];
+    S0[dst + p] = S0[src + tpos(c, r)];
   }
 }
 
-// Start-up: H C and S C were formed into the H D and S D tiles (row-major, the
-// layout the n x n projections read down columns); the maintained HC and SC are
+// Start-up: H C and S C were formed into the H D and S D tiles (the
+// orientation the n x n projections read down columns); the maintained HC and SC are
 // stored with each tile transposed, the layout the gradient products read down
 // columns.  One wave per HC tile of a system in the masked phase.
 __global__ __launch_bounds__(256) void k_hc_from_hd(int nhc, int hoff, const int* __restrict__ upd_sys,
@@ -604,10 +613,10 @@ __global__ __launch_bounds__(256) void k_hc_from_hd(int nhc, int hoff, const int
   const int lane = threadIdx.x & 63;
   const size_t base = (size_t)t * TE;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {   // element e = 64 i + lane: row e / 16, column e % 16
-    const int e = 64 * i + lane, r = e >> 4, c = e & 15;
-    HC[base + c * 16 + r] = HD[base + e];
-    SC[base + c * 16 + r] = SD[base + e];
+  for (int i = 0; i < 4; ++i) {   // storage position e = 64 i + lane
+    const int e = 64 * i + lane, tp = tpos(tcol(e), trow(e));
+    HC[base + tp] = HD[base + e];
+    SC[base + tp] = SD[base + e];
   }
 }
 
@@ -721,8 +730,8 @@ __global__ __launch_bounds__(256) void k_transpose_tiles(int64_t n, const double
   const size_t base = (size_t)t * TE;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int e = 64 * i + lane, r = e >> 4, c = e & 15;
-    dst[base + c * 16 + r] = src[base + e];
+    const int e = 64 * i + lane;
+    dst[base + tpos(tcol(e), trow(e))] = src[base + e];
   }
 }
 
@@ -749,7 +758,7 @@ __global__ __launch_bounds__(256) void k_blkmap(BlkMap M, const double* __restri
     const int r = r0 + i, c = c0 + jj;
     const int tix = find_col(M.P, M.rtile[r], M.ctile[c]);
     if (tix < 0) continue;
-    const size_t to = (size_t)tix * TE + M.roff[r] * 16 + M.coff[c];
+    const size_t to = (size_t)tix * TE + tpos(M.roff[r], M.coff[c]);
     if (SCATTER) dst[to] = src[vo + e];
     else dst[vo + e] = src[to];
   }
@@ -763,7 +772,7 @@ __global__ __launch_bounds__(256) void k_gather_w(int t0, const int* __restrict_
   const int e = threadIdx.x, r = e >> 4, c = e & 15;
   const int gi = welem[tw_row[t] * 16 + r], gj = welem[tw_col[t] * 16 + c];
   if (gi < 0 || gj < 0) return;
-  dense[(int64_t)gi * n + gj] = tiles[(size_t)t * TE + e];
+  dense[(int64_t)gi * n + gj] = tiles[(size_t)t * TE + tpos(r, c)];
 }
 
 __global__ void k_axpy(int64_t n, double alpha, const double* __restrict__ X, double* __restrict__ Y) {
@@ -780,7 +789,7 @@ __global__ void k_pad_identity(double* S, int t_first, int RT, int64_t m) {
   const int64_t r = m + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= (int64_t)RT * 16) return;
   const int I = (int)(r / 16), o = (int)(r % 16);
-  S[((size_t)t_first + (size_t)I * RT + I) * TE + o * 16 + o] = 1.0;
+  S[((size_t)t_first + (size_t)I * RT + I) * TE + tpos(o, o)] = 1.0;
 }
 
 inline dim3 waves_grid(int n) { return dim3((unsigned)((n + 3) / 4)); }

@@ -1,10 +1,10 @@
 // Device helpers: 16x16 tile fragments and CDNA MFMA products for gfx950.
 //
-// One 64-lane wavefront multiplies two 16x16 row-major tiles.  Lane
-// l = i + 16*q (i = l & 15, q = l >> 4) supplies, at MFMA step s = 0..3,
-// A[i][k] and B[k][j=i] for one tile index k = K(q, s).  The pairing of k with
-// (q, s) is free as long as A and B agree (KMap).  Accumulator register r of
-// lane (j, q) holds output row
+// One 64-lane wavefront multiplies two 16x16 tiles.  Lane l = i + 16*q
+// (i = l & 15, q = l >> 4) supplies, at MFMA step s = 0..3, A[i][k] and
+// B[k][j=i] for one tile index k = K(q, s).  The pairing of k with (q, s) is
+// free as long as A and B agree (KMap).  Accumulator register r of lane (j, q)
+// holds output row
 //   v_mfma_f64_16x16x4f64 : 4r + q
 //   v_mfma_f32_16x16x4f32 and v_mfma_f32_16x16x16bf16_1k : 4q + r
 // (the f64 placement was measured on gfx950 with delta operands).
@@ -49,11 +49,26 @@ template <> struct Acc<bf16> { typedef f4 V; typedef float S; };
 
 template <typename T> struct Frag { T v[4]; };
 
+// Storage order inside a 16x16 tile.  Element (r, c) has the row-major index
+// e = 16 r + c, and e = 64 s + l splits it into a row group s (rows 4s .. 4s+3)
+// and a lane l.  Row groups 2h and 2h + 1 are interleaved element by element:
+// e sits at position 128 (s >> 1) + 2 l + (s & 1).  The four values a lane
+// reads for an operand of a tile product (row group s = MFMA step s, lane l)
+// are then two adjacent pairs, one 16-byte load each for FP64, and the
+// accumulator registers r = 0, 1 and 2, 3 of an FP64 product land in adjacent
+// pairs as well.
+__host__ __device__ constexpr int tpos(int r, int c) {
+  return ((r >> 3) << 7) | ((r & 3) << 5) | (c << 1) | ((r >> 2) & 1);
+}
+// row and column of the element at storage position p
+__host__ __device__ constexpr int trow(int p) { return ((p >> 7) << 3) | ((p & 1) << 2) | ((p >> 5) & 3); }
+__host__ __device__ constexpr int tcol(int p) { return (p >> 1) & 15; }
+
 // tile index k supplied by lane-quad q at step s: the four quads of step s take
-// the consecutive k = 4s .. 4s+3, so a column load reads four whole rows per
-// instruction (four cache lines of an FP64 tile) and MFMA step s contracts over
-// one aligned group of four k, which a work-list entry can mark as all zero
-// (chunk masks below)
+// the consecutive k = 4s .. 4s+3 (row group s of the tile, see tpos), so a
+// column load reads two whole row groups per instruction (1 KB of an FP64
+// tile) and MFMA step s contracts over one aligned group of four k, which a
+// work-list entry can mark as all zero (step masks below)
 template <typename T> struct KMap { static __device__ __forceinline__ int k(int q, int s) { return 4 * s + q; } };
 
 // output row of accumulator register r in lane-quad q
@@ -64,18 +79,29 @@ template <> struct Lay<f4> { static __device__ __forceinline__ int row(int q, in
 // "row" load: lane (i, q) takes tile[i][K(q, s)]   (A operand, or B^T)
 template <typename T, typename S>
 __device__ __forceinline__ void ld_row(Frag<T>& f, const S* __restrict__ t, int lane) {
-  const S* p = t + (lane & 15) * 16;
-  const int q = lane >> 4;
+  const int i = lane & 15, q = lane >> 4;
 #pragma unroll
-  for (int s = 0; s < 4; ++s) f.v[s] = cvt<T, S>(p[KMap<T>::k(q, s)]);
+  for (int s = 0; s < 4; ++s) f.v[s] = cvt<T, S>(t[tpos(i, KMap<T>::k(q, s))]);
 }
-// "col" load: lane (j, q) takes tile[K(q, s)][j]   (B operand, or A^T)
+// "col" load: lane (j, q) takes tile[K(q, s)][j] (B operand, or A^T): element
+// 64 s + lane, stored at 2 lane + (s & 1) + 128 (s >> 1)
+template <typename S> struct Pair;
+template <> struct Pair<double> { typedef double2 V; };
+template <> struct Pair<float> { typedef float2 V; };
+template <> struct Pair<bf16> { typedef uint32_t V; };
+template <typename S> __device__ __forceinline__ S pair_lo(const typename Pair<S>::V& v) { return v.x; }
+template <typename S> __device__ __forceinline__ S pair_hi(const typename Pair<S>::V& v) { return v.y; }
+template <> __device__ __forceinline__ bf16 pair_lo<bf16>(const uint32_t& v) { return (bf16)(v & 0xffffu); }
+template <> __device__ __forceinline__ bf16 pair_hi<bf16>(const uint32_t& v) { return (bf16)(v >> 16); }
 template <typename T, typename S>
 __device__ __forceinline__ void ld_col(Frag<T>& f, const S* __restrict__ t, int lane) {
-  const S* p = t + (lane & 15);
-  const int q = lane >> 4;
-#pragma unroll
-  for (int s = 0; s < 4; ++s) f.v[s] = cvt<T, S>(p[16 * KMap<T>::k(q, s)]);
+  typedef typename Pair<S>::V PV;
+  const PV* p = (const PV*)t;
+  const PV a = p[lane], b = p[64 + lane];
+  f.v[0] = cvt<T, S>(pair_lo<S>(a));
+  f.v[1] = cvt<T, S>(pair_hi<S>(a));
+  f.v[2] = cvt<T, S>(pair_lo<S>(b));
+  f.v[3] = cvt<T, S>(pair_hi<S>(b));
 }
 
 __device__ __forceinline__ void mma(d4& acc, const Frag<double>& a, const Frag<double>& b) {
@@ -119,10 +145,10 @@ template <> __device__ __forceinline__ f4 vzero<f4>() { return f4{0.f, 0.f, 0.f,
 
 // accumulator register r of this lane sits at tile offset out_off<V>(lane, r)
 template <typename V>
-__device__ __forceinline__ int out_off(int lane, int r) { return Lay<V>::row(lane >> 4, r) * 16 + (lane & 15); }
+__device__ __forceinline__ int out_off(int lane, int r) { return tpos(Lay<V>::row(lane >> 4, r), lane & 15); }
 // the same element in a tile stored transposed
 template <typename V>
-__device__ __forceinline__ int out_off_t(int lane, int r) { return (lane & 15) * 16 + Lay<V>::row(lane >> 4, r); }
+__device__ __forceinline__ int out_off_t(int lane, int r) { return tpos(lane & 15, Lay<V>::row(lane >> 4, r)); }
 
 // The transpose of an accumulator tile, in the same register layout: lane
 // (j, q) register r receives element (j, row) with row = Lay<V>::row(q, r),
@@ -146,8 +172,8 @@ __device__ __forceinline__ V transposed_tile(const V& a, int lane) {
 }
 
 // an FP64 accumulator tile as the B operand of the next product, through a
-// 16x16 LDS tile owned by the calling wave (LDS operations of one wave
-// complete in order, so the reads see the writes)
+// 16x16 LDS tile owned by the calling wave, 16-byte aligned (LDS operations of
+// one wave complete in order, so the reads see the writes)
 __device__ __forceinline__ Frag<double> acc_as_b_lds(const d4& a, double* t, int lane) {
 #pragma unroll
   for (int r = 0; r < 4; ++r) t[out_off<d4>(lane, r)] = a[r];
