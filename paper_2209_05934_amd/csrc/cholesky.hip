@@ -75,7 +75,7 @@ __global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ A, int 
   d4 acc = vzero<d4>();
   mma(acc, fa, fb);
 #pragma unroll
-  for (int r = 0; r < 4; ++r) t[out_off<d4>(lane, r)] = acc[r];
+  for (int r = 0; r < 4; ++r) t[out_off<d4, double>(lane, r)] = acc[r];
 }
 
 // A(I,J) -= L(I,K) L(J,K)^T for K < J <= I
@@ -96,7 +96,7 @@ __global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ A, int
   mma(acc, fa, fb);
   double* t = A + tix(base, RT, I, J);
 #pragma unroll
-  for (int r = 0; r < 4; ++r) t[out_off<d4>(lane, r)] -= acc[r];
+  for (int r = 0; r < 4; ++r) t[out_off<d4, double>(lane, r)] -= acc[r];
 }
 
 // forward substitution, tile row I of X = L^-1 op(B): X(I,J) = Linv_I (op(B)(I,J) - sum_{K<I} L(I,K) X(K,J))
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(256) void k_trsm_fwd(const double* __restrict__ L, 
   mma(out, fa, fb);
   double* t = X + tix(xbase, ncols, I, J);
 #pragma unroll
-  for (int r = 0; r < 4; ++r) t[out_off<d4>(lane, r)] = out[r];
+  for (int r = 0; r < 4; ++r) t[out_off<d4, double>(lane, r)] = out[r];
 }
 
 // Cout = L^T Cin on a dense RT x WT grid
@@ -148,7 +148,7 @@ __global__ __launch_bounds__(256) void k_apply_lt(const double* __restrict__ L, 
     mma(acc, fa, fb);
   }
 #pragma unroll
-  for (int r = 0; r < 4; ++r) Cout[tix(cbase, WT, I, g) + out_off<d4>(lane, r)] = acc[r];
+  for (int r = 0; r < 4; ++r) Cout[tix(cbase, WT, I, g) + out_off<d4, double>(lane, r)] = acc[r];
 }
 
 // backward substitution, tile row I of Cout = L^-T Cin
@@ -167,14 +167,14 @@ __global__ __launch_bounds__(256) void k_trsm_bwd_t(const double* __restrict__ L
   }
   d4 rhs;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) rhs[r] = Cin[tix(cbase, WT, I, g) + out_off<d4>(lane, r)] - acc[r];
+  for (int r = 0; r < 4; ++r) rhs[r] = Cin[tix(cbase, WT, I, g) + out_off<d4, double>(lane, r)] - acc[r];
   __shared__ __align__(16) double lt[4][TE];
   Frag<double> fa, fb = acc_as_b_lds(rhs, lt[threadIdx.x >> 6], lane);
   ld_col(fa, Linv + (size_t)I * TE, lane);         // A = Linv_I^T
   d4 out = vzero<d4>();
   mma(out, fa, fb);
 #pragma unroll
-  for (int r = 0; r < 4; ++r) Cout[tix(cbase, WT, I, g) + out_off<d4>(lane, r)] = out[r];
+  for (int r = 0; r < 4; ++r) Cout[tix(cbase, WT, I, g) + out_off<d4, double>(lane, r)] = out[r];
 }
 
 }  // namespace

@@ -102,7 +102,7 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s1(
       double zg = 0.0, zo = 0.0;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int e = out_off<V>(lane, r);
+        const int e = out_off<V, double>(lane, r);
         const double z = (double)acc[u][r];
         O1[base + e] = (TO)z;
         zg += z * (double)Bm[base + e];
@@ -125,7 +125,7 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s1(
         typedef typename Acc<TI>::S AS;
         const int ct = hc_to_c[t];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) a2[r] = ct >= 0 ? cvt<AS, TI>(Bm[(size_t)ct * TE + out_off<V>(lane, r)]) : (AS)0;
+        for (int r = 0; r < 4; ++r) a2[r] = ct >= 0 ? cvt<AS, TI>(Bm[(size_t)ct * TE + out_off<V, TI>(lane, r)]) : (AS)0;
       }
       if (e2 > 0.0) {
         const uint8_t* cs = wseg + 32 * (size_t)ocol[t];
@@ -146,7 +146,7 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s1(
       TO* o2 = O2 + (size_t)t * TE;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int e = out_off<V>(lane, r);
+        const int e = out_off<V, TO>(lane, r);
         o1[e] = (TO)a1[r];
         o2[e] = (TO)a2[r];
       }

@@ -196,20 +196,21 @@ __global__ __launch_bounds__(256) void k_traces(const int4* __restrict__ chunks,
 #pragma unroll
   for (int k = 0; k < NSUM; ++k) a[k] = 0.0;
   const int lane = threadIdx.x & 63, wv = wave_id();
-  // storage positions 4 lane + i: element (row, column) and the position of
-  // its transpose
+  // FP64 storage positions 4 lane + i: element (row, column), its position in
+  // a TN tile and the position of its transpose there
   bool on_diag[4];
-  int pt[4];
+  int pn[4], ptn[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int p = 4 * lane + i;
-    on_diag[i] = trow(p) == tcol(p);
-    pt[i] = tpos(tcol(p), trow(p));
+    const int p = 4 * lane + i, r = trow(p), c = tcol(p);
+    on_diag[i] = r == c;
+    pn[i] = tpos_of<TN>(r, c);
+    ptn[i] = tpos_of<TN>(c, r);
   }
 #pragma unroll 2
   for (int t = ch.x + wv; t < ch.y; t += 4) {
     const int tt = wtr[t];
-    const size_t o = (size_t)t * TE + 4 * lane;
+    const size_t ob = (size_t)t * TE, o = ob + 4 * lane;
     const size_t tb = (size_t)tt * TE;
     const bool mir = sym2 && tt < t;   // S2, H2 below the diagonal: transpose of the mirror tile
     double h0[4], s0[4], x[4], y[4], s2[4], h2[4], yt[4];
@@ -217,11 +218,11 @@ __global__ __launch_bounds__(256) void k_traces(const int4* __restrict__ chunks,
     for (int i = 0; i < 4; ++i) {
       h0[i] = H0[o + i];
       s0[i] = S0[o + i];
-      x[i] = (double)X[o + i];
-      y[i] = (double)Y[o + i];
-      s2[i] = (double)(mir ? S2[tb + pt[i]] : S2[o + i]);
-      h2[i] = (double)(mir ? H2[tb + pt[i]] : H2[o + i]);
-      yt[i] = (double)Y[tb + pt[i]];
+      x[i] = (double)X[ob + pn[i]];
+      y[i] = (double)Y[ob + pn[i]];
+      s2[i] = (double)(mir ? S2[tb + ptn[i]] : S2[ob + pn[i]]);
+      h2[i] = (double)(mir ? H2[tb + ptn[i]] : H2[ob + pn[i]]);
+      yt[i] = (double)Y[tb + ptn[i]];
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -319,10 +320,20 @@ __global__ __launch_bounds__(256) void k_update(int nc, int nhc, int ntot, const
   const int ch0 = info[s].ch0, ch1 = info[s].ch1;
   const int kind = T < nc ? 0 : (T < nc + nhc ? 1 : 2);
   const int t = kind == 0 ? T : (kind == 1 ? T - nc : T - nc - nhc);
-  const size_t o = (size_t)t * TE + 4 * lane;
-  int pt[4];   // position of the transpose of the element at storage position 4 lane + i
+  const size_t ob = (size_t)t * TE, o = ob + 4 * lane;
+  // the element (r, c) at FP64 storage position 4 lane + i: position of its
+  // transpose (pt), and of it and its transpose in TM tiles (pm, pmt) and TL
+  // tiles (pl, plt)
+  int pt[4], pm[4], pmt[4], pl[4], plt[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) pt[i] = tpos(tcol(4 * lane + i), trow(4 * lane + i));
+  for (int i = 0; i < 4; ++i) {
+    const int r = trow(4 * lane + i), c = tcol(4 * lane + i);
+    pt[i] = tpos(c, r);
+    pm[i] = tpos_of<TM>(r, c);
+    pmt[i] = tpos_of<TM>(c, r);
+    pl[i] = tpos_of<TL>(r, c);
+    plt[i] = tpos_of<TL>(c, r);
+  }
   // operands first: their loads overlap the line search
   double u[4], v[4], p[4], q[4], w[4], z[4];
   if (kind == 0) {
@@ -332,7 +343,7 @@ __global__ __launch_bounds__(256) void k_update(int nc, int nhc, int ntot, const
     const size_t tb = (size_t)t * TE;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      u[i] = HC[tb + pt[i]]; v[i] = SC[tb + pt[i]]; p[i] = (double)HD[o + i]; q[i] = (double)SD[o + i];
+      u[i] = HC[tb + pt[i]]; v[i] = SC[tb + pt[i]]; p[i] = (double)HD[ob + pm[i]]; q[i] = (double)SD[ob + pm[i]];
     }
   } else {
     // H_W and S_W stay symmetric, and so do their increments: the wave of a tile
@@ -344,10 +355,10 @@ __global__ __launch_bounds__(256) void k_update(int nc, int nhc, int ntot, const
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       u[i] = H0[o + i]; v[i] = S0[o + i];
-      p[i] = (double)Y[o + i] + (double)Y[tb + pt[i]];
-      q[i] = (double)X[o + i] + (double)X[tb + pt[i]];
-      w[i] = (double)H2[o + i];
-      z[i] = (double)S2[o + i];
+      p[i] = (double)Y[ob + pm[i]] + (double)Y[tb + pmt[i]];
+      q[i] = (double)X[ob + pm[i]] + (double)X[tb + pmt[i]];
+      w[i] = (double)H2[ob + pm[i]];
+      z[i] = (double)S2[ob + pm[i]];
     }
   }
   double x = 0.0;
@@ -367,7 +378,7 @@ __global__ __launch_bounds__(256) void k_update(int nc, int nhc, int ntot, const
     for (int i = 0; i < 4; ++i) {
       const double nv = u[i] + x * p[i];
       C[o + i] = nv;
-      if (LOW) Cl[o + i] = cvt<TL, double>(nv);
+      if (LOW) Cl[ob + pl[i]] = cvt<TL, double>(nv);
     }
   } else if (kind == 1) {
     const size_t tb = (size_t)t * TE;
@@ -377,8 +388,8 @@ __global__ __launch_bounds__(256) void k_update(int nc, int nhc, int ntot, const
       HC[tb + pt[i]] = h;
       SC[tb + pt[i]] = g;
       if (LOW) {
-        HCl[tb + pt[i]] = cvt<TL, double>(h);
-        SCl[tb + pt[i]] = cvt<TL, double>(g);
+        HCl[tb + plt[i]] = cvt<TL, double>(h);
+        SCl[tb + plt[i]] = cvt<TL, double>(g);
       }
     }
   } else {
@@ -391,15 +402,15 @@ __global__ __launch_bounds__(256) void k_update(int nc, int nhc, int ntot, const
       H0[o + i] = h;
       S0[o + i] = g;
       if (LOW) {
-        H0l[o + i] = cvt<TL, double>(h);
-        S0l[o + i] = cvt<TL, double>(g);
+        H0l[ob + pl[i]] = cvt<TL, double>(h);
+        S0l[ob + pl[i]] = cvt<TL, double>(g);
       }
       if (tt != t) {   // the same element of the mirror tile's transpose
         H0[tb + pt[i]] = h;
         S0[tb + pt[i]] = g;
         if (LOW) {
-          H0l[tb + pt[i]] = cvt<TL, double>(h);
-          S0l[tb + pt[i]] = cvt<TL, double>(g);
+          H0l[tb + plt[i]] = cvt<TL, double>(h);
+          S0l[tb + plt[i]] = cvt<TL, double>(g);
         }
       }
     }
@@ -566,7 +577,7 @@ __global__ __launch_bounds__(256) void k_update_d(int nc, const int* __restrict_
     const double d = -z[i] + beta * dv[i];
     D[o + i] = d;
     Gold[o + i] = g[i];
-    if (LOW) Dl[o + i] = cvt<TL, double>(d);
+    if (LOW) Dl[(size_t)t * TE + tpos_of<TL>(trow(4 * lane + i), tcol(4 * lane + i))] = cvt<TL, double>(d);
   }
 }
 
@@ -655,15 +666,15 @@ __global__ void k_init_finish(SysState* __restrict__ st, int nsys) {
 }
 
 template <typename TL>
-__global__ __launch_bounds__(256) void k_cast(int ntiles, const int* __restrict__ trow,
+__global__ __launch_bounds__(256) void k_cast(int ntiles, const int* __restrict__ tile_row,
                                             const int* __restrict__ row_sys, const SysState* __restrict__ st,
                                             int mask, const double* __restrict__ src, TL* __restrict__ dst) {
   const int t = blockIdx.x;
   if (t >= ntiles) return;
-  const int s = row_sys[trow[t]];
+  const int s = row_sys[tile_row[t]];
   if (mask && (!on(st, s, mask) || st[s].prec == 0)) return;
-  const size_t o = (size_t)t * TE + threadIdx.x;
-  dst[o] = cvt<TL, double>(src[o]);
+  const int p = threadIdx.x;   // FP64 storage position, moved to its place in a TL tile
+  dst[(size_t)t * TE + tpos_of<TL>(trow(p), tcol(p))] = cvt<TL, double>(src[(size_t)t * TE + p]);
 }
 
 // ------------------------------------------------------------------ density matrices (Eq. 5, Eq. 6)
@@ -698,7 +709,7 @@ __global__ __launch_bounds__(256) void k_cm(PlanView P, const int* __restrict__ 
     mma(acc, fa, fb);
   }
 #pragma unroll
-  for (int r = 0; r < 4; ++r) CMt[(size_t)t * TE + out_off_t<d4>(lane, r)] = acc[r];   // stored transposed
+  for (int r = 0; r < 4; ++r) CMt[(size_t)t * TE + out_off_t<d4, double>(lane, r)] = acc[r];   // stored transposed
 }
 
 __global__ __launch_bounds__(256) void k_rho(PlanView P, const int* __restrict__ orow,
@@ -718,7 +729,7 @@ __global__ __launch_bounds__(256) void k_rho(PlanView P, const int* __restrict__
     mma(acc, fa, fb);
   }
 #pragma unroll
-  for (int r = 0; r < 4; ++r) rho[(size_t)t * TE + out_off<d4>(lane, r)] = 2.0 * acc[r];
+  for (int r = 0; r < 4; ++r) rho[(size_t)t * TE + out_off<d4, double>(lane, r)] = 2.0 * acc[r];
 }
 
 // every tile of src transposed into dst (one wave per tile)
@@ -905,10 +916,10 @@ void launch_init_finish(hipStream_t s, const Bufs& b) {
 }
 
 template <typename TL>
-static void cast_go(hipStream_t s, int n, const int* trow, const int* rsys, const SysState* st, int mask,
+static void cast_go(hipStream_t s, int n, const int* tile_row, const int* rsys, const SysState* st, int mask,
                     const double* src, void* dst) {
   if (n <= 0) return;
-  LAUNCH(k_cast<TL>, dim3(n), dim3(256), s, n, trow, rsys, st, mask, src, (TL*)dst);
+  LAUNCH(k_cast<TL>, dim3(n), dim3(256), s, n, tile_row, rsys, st, mask, src, (TL*)dst);
 }
 
 void launch_cast_state(hipStream_t s, const Bufs& b, Prec prec, int mask) {

@@ -115,7 +115,7 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s2(
     const size_t o = (size_t)t * TE;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int e = out_off<V>(lane, r);
+      const int e = out_off<V, TO>(lane, r);
       X[o + e] = (TO)acc[u][r];
       Y[o + e] = (TO)acc[NT + u][r];
       if (NPROD == 4 && !low[u]) {

@@ -63,6 +63,14 @@ __host__ __device__ constexpr int tpos(int r, int c) {
 // row and column of the element at storage position p
 __host__ __device__ constexpr int trow(int p) { return ((p >> 7) << 3) | ((p & 1) << 2) | ((p >> 5) & 3); }
 __host__ __device__ constexpr int tcol(int p) { return (p >> 1) & 15; }
+// Tiles of 4- and 2-byte values (FP32, BF16 copies and products) keep a
+// lane's four operand values together: element 64 s + l at position 4 l + s,
+// one 16-byte load per lane for FP32 and 8 bytes for BF16.
+__host__ __device__ constexpr int tpos4(int r, int c) { return ((r & 3) << 6) | (c << 2) | (r >> 2); }
+// position of element (r, c) in a tile of storage type S
+template <typename S> __host__ __device__ constexpr int tpos_of(int r, int c) {
+  return sizeof(S) == 8 ? tpos(r, c) : tpos4(r, c);
+}
 
 // tile index k supplied by lane-quad q at step s: the four quads of step s take
 // the consecutive k = 4s .. 4s+3 (row group s of the tile, see tpos), so a
@@ -81,27 +89,34 @@ template <typename T, typename S>
 __device__ __forceinline__ void ld_row(Frag<T>& f, const S* __restrict__ t, int lane) {
   const int i = lane & 15, q = lane >> 4;
 #pragma unroll
-  for (int s = 0; s < 4; ++s) f.v[s] = cvt<T, S>(t[tpos(i, KMap<T>::k(q, s))]);
+  for (int s = 0; s < 4; ++s) f.v[s] = cvt<T, S>(t[tpos_of<S>(i, KMap<T>::k(q, s))]);
 }
 // "col" load: lane (j, q) takes tile[K(q, s)][j] (B operand, or A^T): element
-// 64 s + lane, stored at 2 lane + (s & 1) + 128 (s >> 1)
-template <typename S> struct Pair;
-template <> struct Pair<double> { typedef double2 V; };
-template <> struct Pair<float> { typedef float2 V; };
-template <> struct Pair<bf16> { typedef uint32_t V; };
-template <typename S> __device__ __forceinline__ S pair_lo(const typename Pair<S>::V& v) { return v.x; }
-template <typename S> __device__ __forceinline__ S pair_hi(const typename Pair<S>::V& v) { return v.y; }
-template <> __device__ __forceinline__ bf16 pair_lo<bf16>(const uint32_t& v) { return (bf16)(v & 0xffffu); }
-template <> __device__ __forceinline__ bf16 pair_hi<bf16>(const uint32_t& v) { return (bf16)(v >> 16); }
-template <typename T, typename S>
-__device__ __forceinline__ void ld_col(Frag<T>& f, const S* __restrict__ t, int lane) {
-  typedef typename Pair<S>::V PV;
-  const PV* p = (const PV*)t;
-  const PV a = p[lane], b = p[64 + lane];
-  f.v[0] = cvt<T, S>(pair_lo<S>(a));
-  f.v[1] = cvt<T, S>(pair_hi<S>(a));
-  f.v[2] = cvt<T, S>(pair_lo<S>(b));
-  f.v[3] = cvt<T, S>(pair_hi<S>(b));
+// 64 s + lane, at 2 lane + (s & 1) + 128 (s >> 1) in an FP64 tile (two 16-byte
+// loads) and at 4 lane + s in an FP32 or BF16 tile (one load)
+template <typename T>
+__device__ __forceinline__ void ld_col(Frag<T>& f, const double* __restrict__ t, int lane) {
+  const double2 a = ((const double2*)t)[lane], b = ((const double2*)t)[64 + lane];
+  f.v[0] = cvt<T, double>(a.x);
+  f.v[1] = cvt<T, double>(a.y);
+  f.v[2] = cvt<T, double>(b.x);
+  f.v[3] = cvt<T, double>(b.y);
+}
+template <typename T>
+__device__ __forceinline__ void ld_col(Frag<T>& f, const float* __restrict__ t, int lane) {
+  const float4 a = ((const float4*)t)[lane];
+  f.v[0] = cvt<T, float>(a.x);
+  f.v[1] = cvt<T, float>(a.y);
+  f.v[2] = cvt<T, float>(a.z);
+  f.v[3] = cvt<T, float>(a.w);
+}
+template <typename T>
+__device__ __forceinline__ void ld_col(Frag<T>& f, const bf16* __restrict__ t, int lane) {
+  const uint2 a = ((const uint2*)t)[lane];
+  f.v[0] = cvt<T, bf16>((bf16)(a.x & 0xffffu));
+  f.v[1] = cvt<T, bf16>((bf16)(a.x >> 16));
+  f.v[2] = cvt<T, bf16>((bf16)(a.y & 0xffffu));
+  f.v[3] = cvt<T, bf16>((bf16)(a.y >> 16));
 }
 
 __device__ __forceinline__ void mma(d4& acc, const Frag<double>& a, const Frag<double>& b) {
@@ -143,12 +158,13 @@ template <typename V> __device__ __forceinline__ V vzero();
 template <> __device__ __forceinline__ d4 vzero<d4>() { return d4{0.0, 0.0, 0.0, 0.0}; }
 template <> __device__ __forceinline__ f4 vzero<f4>() { return f4{0.f, 0.f, 0.f, 0.f}; }
 
-// accumulator register r of this lane sits at tile offset out_off<V>(lane, r)
-template <typename V>
-__device__ __forceinline__ int out_off(int lane, int r) { return tpos(Lay<V>::row(lane >> 4, r), lane & 15); }
+// accumulator register r of this lane sits at offset out_off<V, S>(lane, r) of
+// a tile of storage type S
+template <typename V, typename S>
+__device__ __forceinline__ int out_off(int lane, int r) { return tpos_of<S>(Lay<V>::row(lane >> 4, r), lane & 15); }
 // the same element in a tile stored transposed
-template <typename V>
-__device__ __forceinline__ int out_off_t(int lane, int r) { return tpos(lane & 15, Lay<V>::row(lane >> 4, r)); }
+template <typename V, typename S>
+__device__ __forceinline__ int out_off_t(int lane, int r) { return tpos_of<S>(lane & 15, Lay<V>::row(lane >> 4, r)); }
 
 // The transpose of an accumulator tile, in the same register layout: lane
 // (j, q) register r receives element (j, row) with row = Lay<V>::row(q, r),
@@ -176,7 +192,7 @@ __device__ __forceinline__ V transposed_tile(const V& a, int lane) {
 // one wave complete in order, so the reads see the writes)
 __device__ __forceinline__ Frag<double> acc_as_b_lds(const d4& a, double* t, int lane) {
 #pragma unroll
-  for (int r = 0; r < 4; ++r) t[out_off<d4>(lane, r)] = a[r];
+  for (int r = 0; r < 4; ++r) t[out_off<d4, double>(lane, r)] = a[r];
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
