@@ -48,6 +48,8 @@ template <> struct Acc<float> { typedef f4 V; typedef float S; };
 template <> struct Acc<bf16> { typedef f4 V; typedef float S; };
 
 template <typename T> struct Frag { T v[4]; };
+// BF16 values are kept packed as the operand of the BF16 MFMA
+template <> struct Frag<bf16> { s4 v; };
 
 // Storage order inside a 16x16 tile.  Element (r, c) has the row-major index
 // e = 16 r + c, and e = 64 s + l splits it into a row group s (rows 4s .. 4s+3)
@@ -63,13 +65,14 @@ __host__ __device__ constexpr int tpos(int r, int c) {
 // row and column of the element at storage position p
 __host__ __device__ constexpr int trow(int p) { return ((p >> 7) << 3) | ((p & 1) << 2) | ((p >> 5) & 3); }
 __host__ __device__ constexpr int tcol(int p) { return (p >> 1) & 15; }
-// Tiles of 4- and 2-byte values (FP32, BF16 copies and products) keep a
-// lane's four operand values together: element 64 s + l at position 4 l + s,
-// one 16-byte load per lane for FP32 and 8 bytes for BF16.
+// Tiles of 4-byte values (FP32 copies and products) keep a lane's four
+// operand values together: element 64 s + l at position 4 l + s, one 16-byte
+// load per lane.  BF16 tiles keep the FP64 order (two 4-byte loads per lane,
+// measured faster than one 8-byte load).
 __host__ __device__ constexpr int tpos4(int r, int c) { return ((r & 3) << 6) | (c << 2) | (r >> 2); }
 // position of element (r, c) in a tile of storage type S
 template <typename S> __host__ __device__ constexpr int tpos_of(int r, int c) {
-  return sizeof(S) == 8 ? tpos(r, c) : tpos4(r, c);
+  return sizeof(S) == 4 ? tpos4(r, c) : tpos(r, c);
 }
 
 // tile index k supplied by lane-quad q at step s: the four quads of step s take
@@ -92,8 +95,8 @@ __device__ __forceinline__ void ld_row(Frag<T>& f, const S* __restrict__ t, int 
   for (int s = 0; s < 4; ++s) f.v[s] = cvt<T, S>(t[tpos_of<S>(i, KMap<T>::k(q, s))]);
 }
 // "col" load: lane (j, q) takes tile[K(q, s)][j] (B operand, or A^T): element
-// 64 s + lane, at 2 lane + (s & 1) + 128 (s >> 1) in an FP64 tile (two 16-byte
-// loads) and at 4 lane + s in an FP32 or BF16 tile (one load)
+// 64 s + lane, at 2 lane + (s & 1) + 128 (s >> 1) in an FP64 or BF16 tile (two
+// loads) and at 4 lane + s in an FP32 tile (one load)
 template <typename T>
 __device__ __forceinline__ void ld_col(Frag<T>& f, const double* __restrict__ t, int lane) {
   const double2 a = ((const double2*)t)[lane], b = ((const double2*)t)[64 + lane];
@@ -110,13 +113,9 @@ __device__ __forceinline__ void ld_col(Frag<T>& f, const float* __restrict__ t, 
   f.v[2] = cvt<T, float>(a.z);
   f.v[3] = cvt<T, float>(a.w);
 }
-template <typename T>
-__device__ __forceinline__ void ld_col(Frag<T>& f, const bf16* __restrict__ t, int lane) {
-  const uint2 a = ((const uint2*)t)[lane];
-  f.v[0] = cvt<T, bf16>((bf16)(a.x & 0xffffu));
-  f.v[1] = cvt<T, bf16>((bf16)(a.x >> 16));
-  f.v[2] = cvt<T, bf16>((bf16)(a.y & 0xffffu));
-  f.v[3] = cvt<T, bf16>((bf16)(a.y >> 16));
+__device__ __forceinline__ void ld_col(Frag<bf16>& f, const bf16* __restrict__ t, int lane) {
+  const uint32_t* p = (const uint32_t*)t;
+  f.v = __builtin_bit_cast(s4, make_uint2(p[lane], p[64 + lane]));
 }
 
 __device__ __forceinline__ void mma(d4& acc, const Frag<double>& a, const Frag<double>& b) {
@@ -140,9 +139,7 @@ __device__ __forceinline__ void mma(f4& acc, const Frag<float>& a, const Frag<fl
     if ((act >> s) & 1) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[s], b.v[s], acc, 0, 0, 0);
 }
 __device__ __forceinline__ void mma(f4& acc, const Frag<bf16>& a, const Frag<bf16>& b) {
-  s4 av = {(short)a.v[0], (short)a.v[1], (short)a.v[2], (short)a.v[3]};
-  s4 bv = {(short)b.v[0], (short)b.v[1], (short)b.v[2], (short)b.v[3]};
-  acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.v, b.v, acc, 0, 0, 0);
 }
 // one instruction covers all 16 k: the step mask cannot skip part of it
 __device__ __forceinline__ void mma(f4& acc, const Frag<bf16>& a, const Frag<bf16>& b, int) { mma(acc, a, b); }
