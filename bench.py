@@ -70,70 +70,70 @@ PEAKS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}   # dense TFLOP/s of MI355
 # group width and split, and valid only for the kernel sources they were taken
 # with (sha256 prefix of the step's source file, tile_sched.hpp and tile_ops.hpp)
 MEASURED_TRAFFIC = {
-    ("cubic4_dense", "fp64", 0, 1, 1): (3.6251e+07, "1cc333543b883126"),
-    ("cubic4_dense", "fp64", 0, 1, 2): (3.6231e+07, "1cc333543b883126"),
-    ("cubic4_dense", "fp64", 0, 1, 4): (3.6524e+07, "1cc333543b883126"),
-    ("cubic4_dense", "fp64", 0, 1, 8): (3.8230e+07, "1cc333543b883126"),
-    ("cubic4_dense", "fp64", 0, 2, 1): (3.6204e+07, "1cc333543b883126"),
-    ("cubic4_dense", "fp64", 0, 2, 2): (3.6218e+07, "1cc333543b883126"),
-    ("cubic4_dense", "fp64", 0, 2, 4): (3.6185e+07, "1cc333543b883126"),
-    ("cubic4_dense", "fp64", 0, 2, 8): (3.6124e+07, "1cc333543b883126"),
-    ("cubic4_dense", "fp64", 0, 4, 1): (2.8147e+07, "1cc333543b883126"),
-    ("cubic4_dense", "fp64", 0, 4, 2): (2.9006e+07, "1cc333543b883126"),
-    ("cubic4_dense", "fp64", 0, 4, 4): (2.9465e+07, "1cc333543b883126"),
-    ("cubic4_dense", "fp64", 1, 1, 1): (1.6231e+07, "b81941651f0f1835"),
-    ("cubic4_dense", "fp64", 1, 1, 2): (1.6226e+07, "b81941651f0f1835"),
-    ("cubic4_dense", "fp64", 1, 1, 4): (1.6110e+07, "b81941651f0f1835"),
-    ("cubic4_dense", "fp64", 1, 1, 8): (1.6010e+07, "b81941651f0f1835"),
-    ("cubic4_dense", "fp64", 1, 2, 1): (1.6320e+07, "b81941651f0f1835"),
-    ("cubic4_dense", "fp64", 1, 2, 2): (1.6351e+07, "b81941651f0f1835"),
-    ("cubic4_dense", "fp64", 1, 2, 4): (1.6258e+07, "b81941651f0f1835"),
-    ("cubic4_dense", "fp64", 1, 4, 1): (9.2645e+06, "b81941651f0f1835"),
-    ("cubic4_dense", "fp64", 1, 4, 2): (1.6437e+07, "b81941651f0f1835"),
-    ("cubic4_dense", "fp64", 1, 4, 4): (1.6501e+07, "b81941651f0f1835"),
-    ("cubic4_dense", "fp64", 2, 1, 1): (7.8655e+06, "8b293585b2190e62"),
-    ("cubic4_dense", "fp64", 2, 1, 2): (7.8471e+06, "8b293585b2190e62"),
-    ("cubic4_dense", "fp64", 2, 1, 4): (7.8369e+06, "8b293585b2190e62"),
-    ("cubic4_dense", "fp64", 2, 1, 8): (7.8297e+06, "8b293585b2190e62"),
-    ("cubic4_dense", "fp64", 2, 2, 1): (7.8416e+06, "8b293585b2190e62"),
-    ("cubic4_dense", "fp64", 2, 2, 2): (7.8618e+06, "8b293585b2190e62"),
-    ("cubic4_dense", "fp64", 2, 2, 4): (7.8669e+06, "8b293585b2190e62"),
-    ("cubic4_dense", "fp64", 2, 2, 8): (7.8465e+06, "8b293585b2190e62"),
-    ("cubic4_dense", "fp64", 2, 4, 1): (6.7464e+06, "8b293585b2190e62"),
-    ("cubic4_dense", "fp64", 2, 4, 2): (6.9404e+06, "8b293585b2190e62"),
-    ("cubic4_dense", "fp64", 2, 4, 4): (7.0579e+06, "8b293585b2190e62"),
-    ("cubic16_mixed", "fp64", 0, 1, 1): (2.3546e+10, "1cc333543b883126"),
-    ("cubic16_mixed", "fp64", 0, 1, 2): (2.1083e+10, "1cc333543b883126"),
-    ("cubic16_mixed", "fp64", 0, 1, 4): (1.9357e+10, "1cc333543b883126"),
-    ("cubic16_mixed", "fp64", 0, 1, 8): (1.7973e+10, "1cc333543b883126"),
-    ("cubic16_mixed", "fp64", 0, 2, 1): (1.9890e+10, "1cc333543b883126"),
-    ("cubic16_mixed", "fp64", 0, 2, 2): (1.7823e+10, "1cc333543b883126"),
-    ("cubic16_mixed", "fp64", 0, 2, 4): (1.8128e+10, "1cc333543b883126"),
-    ("cubic16_mixed", "fp64", 0, 2, 8): (1.7240e+10, "1cc333543b883126"),
-    ("cubic16_mixed", "fp64", 0, 4, 1): (1.4684e+10, "1cc333543b883126"),
-    ("cubic16_mixed", "fp64", 0, 4, 2): (1.4403e+10, "1cc333543b883126"),
-    ("cubic16_mixed", "fp64", 0, 4, 4): (1.6216e+10, "1cc333543b883126"),
-    ("cubic16_mixed", "fp64", 1, 1, 1): (5.5693e+10, "b81941651f0f1835"),
-    ("cubic16_mixed", "fp64", 1, 1, 2): (5.4448e+10, "b81941651f0f1835"),
-    ("cubic16_mixed", "fp64", 1, 1, 4): (5.4182e+10, "b81941651f0f1835"),
-    ("cubic16_mixed", "fp64", 1, 1, 8): (5.3462e+10, "b81941651f0f1835"),
-    ("cubic16_mixed", "fp64", 1, 2, 1): (5.5340e+10, "b81941651f0f1835"),
-    ("cubic16_mixed", "fp64", 1, 2, 2): (5.4144e+10, "b81941651f0f1835"),
-    ("cubic16_mixed", "fp64", 1, 2, 4): (5.3778e+10, "b81941651f0f1835"),
-    ("cubic16_mixed", "fp64", 1, 4, 1): (5.7076e+10, "b81941651f0f1835"),
-    ("cubic16_mixed", "fp64", 1, 4, 2): (5.5692e+10, "b81941651f0f1835"),
-    ("cubic16_mixed", "fp64", 1, 4, 4): (5.4745e+10, "b81941651f0f1835"),
-    ("cubic16_mixed", "fp64", 2, 1, 1): (2.3736e+10, "8b293585b2190e62"),
-    ("cubic16_mixed", "fp64", 2, 1, 2): (3.1220e+10, "8b293585b2190e62"),
-    ("cubic16_mixed", "fp64", 2, 1, 4): (3.9626e+10, "8b293585b2190e62"),
-    ("cubic16_mixed", "fp64", 2, 1, 8): (3.8126e+10, "8b293585b2190e62"),
-    ("cubic16_mixed", "fp64", 2, 2, 1): (3.0992e+10, "8b293585b2190e62"),
-    ("cubic16_mixed", "fp64", 2, 2, 2): (3.0503e+10, "8b293585b2190e62"),
-    ("cubic16_mixed", "fp64", 2, 2, 4): (3.5116e+10, "8b293585b2190e62"),
-    ("cubic16_mixed", "fp64", 2, 2, 8): (3.4733e+10, "8b293585b2190e62"),
-    ("cubic16_mixed", "fp64", 2, 4, 1): (1.9631e+10, "8b293585b2190e62"),
-    ("cubic16_mixed", "fp64", 2, 4, 2): (3.2932e+10, "8b293585b2190e62"),
-    ("cubic16_mixed", "fp64", 2, 4, 4): (3.2778e+10, "8b293585b2190e62"),
+    ("cubic4_dense", "fp64", 0, 1, 1): (3.6203e+07, "0b7d1186da371671"),
+    ("cubic4_dense", "fp64", 0, 1, 2): (3.6203e+07, "0b7d1186da371671"),
+    ("cubic4_dense", "fp64", 0, 1, 4): (3.6238e+07, "0b7d1186da371671"),
+    ("cubic4_dense", "fp64", 0, 1, 8): (3.8095e+07, "0b7d1186da371671"),
+    ("cubic4_dense", "fp64", 0, 2, 1): (3.6148e+07, "0b7d1186da371671"),
+    ("cubic4_dense", "fp64", 0, 2, 2): (3.6177e+07, "0b7d1186da371671"),
+    ("cubic4_dense", "fp64", 0, 2, 4): (3.6161e+07, "0b7d1186da371671"),
+    ("cubic4_dense", "fp64", 0, 2, 8): (3.6101e+07, "0b7d1186da371671"),
+    ("cubic4_dense", "fp64", 0, 4, 1): (2.8090e+07, "0b7d1186da371671"),
+    ("cubic4_dense", "fp64", 0, 4, 2): (2.8982e+07, "0b7d1186da371671"),
+    ("cubic4_dense", "fp64", 0, 4, 4): (2.9455e+07, "0b7d1186da371671"),
+    ("cubic4_dense", "fp64", 1, 1, 1): (1.6136e+07, "eb3a3ed434999755"),
+    ("cubic4_dense", "fp64", 1, 1, 2): (1.6143e+07, "eb3a3ed434999755"),
+    ("cubic4_dense", "fp64", 1, 1, 4): (1.6064e+07, "eb3a3ed434999755"),
+    ("cubic4_dense", "fp64", 1, 1, 8): (1.6010e+07, "eb3a3ed434999755"),
+    ("cubic4_dense", "fp64", 1, 2, 1): (1.6243e+07, "eb3a3ed434999755"),
+    ("cubic4_dense", "fp64", 1, 2, 2): (1.6267e+07, "eb3a3ed434999755"),
+    ("cubic4_dense", "fp64", 1, 2, 4): (1.6213e+07, "eb3a3ed434999755"),
+    ("cubic4_dense", "fp64", 1, 4, 1): (9.2205e+06, "eb3a3ed434999755"),
+    ("cubic4_dense", "fp64", 1, 4, 2): (1.6352e+07, "eb3a3ed434999755"),
+    ("cubic4_dense", "fp64", 1, 4, 4): (1.6427e+07, "eb3a3ed434999755"),
+    ("cubic4_dense", "fp64", 2, 1, 1): (7.8492e+06, "6f34a80edf9f90af"),
+    ("cubic4_dense", "fp64", 2, 1, 2): (7.8369e+06, "6f34a80edf9f90af"),
+    ("cubic4_dense", "fp64", 2, 1, 4): (7.8154e+06, "6f34a80edf9f90af"),
+    ("cubic4_dense", "fp64", 2, 1, 8): (7.8246e+06, "6f34a80edf9f90af"),
+    ("cubic4_dense", "fp64", 2, 2, 1): (7.8140e+06, "6f34a80edf9f90af"),
+    ("cubic4_dense", "fp64", 2, 2, 2): (7.8618e+06, "6f34a80edf9f90af"),
+    ("cubic4_dense", "fp64", 2, 2, 4): (7.8547e+06, "6f34a80edf9f90af"),
+    ("cubic4_dense", "fp64", 2, 2, 8): (8.2643e+06, "6f34a80edf9f90af"),
+    ("cubic4_dense", "fp64", 2, 4, 1): (6.6901e+06, "6f34a80edf9f90af"),
+    ("cubic4_dense", "fp64", 2, 4, 2): (6.9261e+06, "6f34a80edf9f90af"),
+    ("cubic4_dense", "fp64", 2, 4, 4): (7.0518e+06, "6f34a80edf9f90af"),
+    ("cubic16_mixed", "fp64", 0, 1, 1): (1.7806e+10, "0b7d1186da371671"),
+    ("cubic16_mixed", "fp64", 0, 1, 2): (1.8327e+10, "0b7d1186da371671"),
+    ("cubic16_mixed", "fp64", 0, 1, 4): (1.8490e+10, "0b7d1186da371671"),
+    ("cubic16_mixed", "fp64", 0, 1, 8): (1.8005e+10, "0b7d1186da371671"),
+    ("cubic16_mixed", "fp64", 0, 2, 1): (1.9317e+10, "0b7d1186da371671"),
+    ("cubic16_mixed", "fp64", 0, 2, 2): (1.7480e+10, "0b7d1186da371671"),
+    ("cubic16_mixed", "fp64", 0, 2, 4): (1.7978e+10, "0b7d1186da371671"),
+    ("cubic16_mixed", "fp64", 0, 2, 8): (1.7245e+10, "0b7d1186da371671"),
+    ("cubic16_mixed", "fp64", 0, 4, 1): (1.4955e+10, "0b7d1186da371671"),
+    ("cubic16_mixed", "fp64", 0, 4, 2): (1.4579e+10, "0b7d1186da371671"),
+    ("cubic16_mixed", "fp64", 0, 4, 4): (1.6266e+10, "0b7d1186da371671"),
+    ("cubic16_mixed", "fp64", 1, 1, 1): (5.5534e+10, "eb3a3ed434999755"),
+    ("cubic16_mixed", "fp64", 1, 1, 2): (5.4284e+10, "eb3a3ed434999755"),
+    ("cubic16_mixed", "fp64", 1, 1, 4): (5.4044e+10, "eb3a3ed434999755"),
+    ("cubic16_mixed", "fp64", 1, 1, 8): (5.3460e+10, "eb3a3ed434999755"),
+    ("cubic16_mixed", "fp64", 1, 2, 1): (5.5330e+10, "eb3a3ed434999755"),
+    ("cubic16_mixed", "fp64", 1, 2, 2): (5.4082e+10, "eb3a3ed434999755"),
+    ("cubic16_mixed", "fp64", 1, 2, 4): (5.3800e+10, "eb3a3ed434999755"),
+    ("cubic16_mixed", "fp64", 1, 4, 1): (5.6954e+10, "eb3a3ed434999755"),
+    ("cubic16_mixed", "fp64", 1, 4, 2): (5.5636e+10, "eb3a3ed434999755"),
+    ("cubic16_mixed", "fp64", 1, 4, 4): (5.4737e+10, "eb3a3ed434999755"),
+    ("cubic16_mixed", "fp64", 2, 1, 1): (2.3496e+10, "6f34a80edf9f90af"),
+    ("cubic16_mixed", "fp64", 2, 1, 2): (3.1837e+10, "6f34a80edf9f90af"),
+    ("cubic16_mixed", "fp64", 2, 1, 4): (3.9476e+10, "6f34a80edf9f90af"),
+    ("cubic16_mixed", "fp64", 2, 1, 8): (3.8256e+10, "6f34a80edf9f90af"),
+    ("cubic16_mixed", "fp64", 2, 2, 1): (3.8308e+10, "6f34a80edf9f90af"),
+    ("cubic16_mixed", "fp64", 2, 2, 2): (3.9305e+10, "6f34a80edf9f90af"),
+    ("cubic16_mixed", "fp64", 2, 2, 4): (4.0901e+10, "6f34a80edf9f90af"),
+    ("cubic16_mixed", "fp64", 2, 2, 8): (3.5928e+10, "6f34a80edf9f90af"),
+    ("cubic16_mixed", "fp64", 2, 4, 1): (4.1786e+10, "6f34a80edf9f90af"),
+    ("cubic16_mixed", "fp64", 2, 4, 2): (3.9515e+10, "6f34a80edf9f90af"),
+    ("cubic16_mixed", "fp64", 2, 4, 4): (3.9014e+10, "6f34a80edf9f90af"),
 }
 
 
