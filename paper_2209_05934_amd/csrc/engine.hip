@@ -1159,6 +1159,11 @@ void prepare(omm_ctx* c) {
   b.S2 = dalloc<double>(c, ntw * TE, true);
   b.H2 = dalloc<double>(c, ntw * TE, true);
   for (double* p : {b.C, b.D, b.G, b.Gold}) OMM_HIP(hipMemsetAsync(p, 0, ntc * TE * sizeof(double), st));
+  {
+    double* z = dalloc<double>(c, TE, true);
+    OMM_HIP(hipMemsetAsync(z, 0, TE * sizeof(double), st));
+    b.zero = z;
+  }
   if (low) {
     const size_t es = c->prec == P32 ? 4 : 2;
     auto lal = [&](size_t ntiles) { return (void*)dalloc<uint8_t>(c, ntiles * TE * es, true); };

@@ -87,6 +87,8 @@ struct Bufs {   // every device buffer the iteration kernels touch
   int ks[3];                     // waves splitting one output tile: direction, n x n, gradient products
   int roll;                      // product kernels with the rolled work-list loop (multi-system contexts)
   int grad_steps;                // gradient entries carry skipped MFMA steps (a block-sparse system present)
+  const double* zero;            // one FP64 tile of zeros: operand halves whose MFMA steps are all skipped
+                                 // read it (it stays in each CU's L1)
 };
 
 // the n x n work-list copy of an iteration: pairs whose H D and S D tiles are both zero marked absent

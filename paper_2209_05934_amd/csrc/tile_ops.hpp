@@ -118,6 +118,32 @@ __device__ __forceinline__ void ld_col(Frag<bf16>& f, const bf16* __restrict__ t
   f.v = __builtin_bit_cast(s4, make_uint2(p[lane], p[64 + lane]));
 }
 
+// A column load of the MFMA steps whose bit (kept >> s) & 1 is set (kept wave-uniform):
+// the part of the tile a load instruction reads (steps 0-1 and 2-3 of an FP64 or BF16
+// tile, all four of an FP32 tile) comes from the zero tile z when none of its steps
+// is kept.  The instructions stay the same; the skipped MFMA steps never use the values.
+template <typename T>
+__device__ __forceinline__ void ld_col_kept(Frag<T>& f, const double* __restrict__ t, const double* __restrict__ z,
+                                            int kept, int lane) {
+  const double2 a = ((const double2*)((kept & 3) ? t : z))[lane];
+  const double2 b = ((const double2*)((kept & 12) ? t : z))[64 + lane];
+  f.v[0] = cvt<T, double>(a.x);
+  f.v[1] = cvt<T, double>(a.y);
+  f.v[2] = cvt<T, double>(b.x);
+  f.v[3] = cvt<T, double>(b.y);
+}
+template <typename T>
+__device__ __forceinline__ void ld_col_kept(Frag<T>& f, const float* __restrict__ t, const float* __restrict__ z,
+                                            int kept, int lane) {
+  ld_col(f, kept ? t : z, lane);
+}
+__device__ __forceinline__ void ld_col_kept(Frag<bf16>& f, const bf16* __restrict__ t, const bf16* __restrict__ z,
+                                            int kept, int lane) {
+  const uint32_t* p0 = (const uint32_t*)((kept & 3) ? t : z);
+  const uint32_t* p1 = (const uint32_t*)((kept & 12) ? t : z);
+  f.v = __builtin_bit_cast(s4, make_uint2(p0[lane], p1[64 + lane]));
+}
+
 __device__ __forceinline__ void mma(d4& acc, const Frag<double>& a, const Frag<double>& b) {
 #pragma unroll
   for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.v[s], b.v[s], acc, 0, 0, 0);
