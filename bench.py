@@ -70,70 +70,70 @@ PEAKS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}   # dense TFLOP/s of MI355
 # group width and split, and valid only for the kernel sources they were taken
 # with (sha256 prefix of the step's source file, tile_sched.hpp and tile_ops.hpp)
 MEASURED_TRAFFIC = {
-    ("cubic4_dense", "fp64", 0, 1, 1): (3.6203e+07, "0b7d1186da371671"),
-    ("cubic4_dense", "fp64", 0, 1, 2): (3.6203e+07, "0b7d1186da371671"),
-    ("cubic4_dense", "fp64", 0, 1, 4): (3.6238e+07, "0b7d1186da371671"),
-    ("cubic4_dense", "fp64", 0, 1, 8): (3.8095e+07, "0b7d1186da371671"),
-    ("cubic4_dense", "fp64", 0, 2, 1): (3.6148e+07, "0b7d1186da371671"),
-    ("cubic4_dense", "fp64", 0, 2, 2): (3.6177e+07, "0b7d1186da371671"),
-    ("cubic4_dense", "fp64", 0, 2, 4): (3.6161e+07, "0b7d1186da371671"),
-    ("cubic4_dense", "fp64", 0, 2, 8): (3.6101e+07, "0b7d1186da371671"),
-    ("cubic4_dense", "fp64", 0, 4, 1): (2.8090e+07, "0b7d1186da371671"),
-    ("cubic4_dense", "fp64", 0, 4, 2): (2.8982e+07, "0b7d1186da371671"),
-    ("cubic4_dense", "fp64", 0, 4, 4): (2.9455e+07, "0b7d1186da371671"),
-    ("cubic4_dense", "fp64", 1, 1, 1): (1.6136e+07, "eb3a3ed434999755"),
-    ("cubic4_dense", "fp64", 1, 1, 2): (1.6143e+07, "eb3a3ed434999755"),
-    ("cubic4_dense", "fp64", 1, 1, 4): (1.6064e+07, "eb3a3ed434999755"),
-    ("cubic4_dense", "fp64", 1, 1, 8): (1.6010e+07, "eb3a3ed434999755"),
-    ("cubic4_dense", "fp64", 1, 2, 1): (1.6243e+07, "eb3a3ed434999755"),
-    ("cubic4_dense", "fp64", 1, 2, 2): (1.6267e+07, "eb3a3ed434999755"),
-    ("cubic4_dense", "fp64", 1, 2, 4): (1.6213e+07, "eb3a3ed434999755"),
-    ("cubic4_dense", "fp64", 1, 4, 1): (9.2205e+06, "eb3a3ed434999755"),
-    ("cubic4_dense", "fp64", 1, 4, 2): (1.6352e+07, "eb3a3ed434999755"),
-    ("cubic4_dense", "fp64", 1, 4, 4): (1.6427e+07, "eb3a3ed434999755"),
-    ("cubic4_dense", "fp64", 2, 1, 1): (7.8492e+06, "6f34a80edf9f90af"),
-    ("cubic4_dense", "fp64", 2, 1, 2): (7.8369e+06, "6f34a80edf9f90af"),
-    ("cubic4_dense", "fp64", 2, 1, 4): (7.8154e+06, "6f34a80edf9f90af"),
-    ("cubic4_dense", "fp64", 2, 1, 8): (7.8246e+06, "6f34a80edf9f90af"),
-    ("cubic4_dense", "fp64", 2, 2, 1): (7.8140e+06, "6f34a80edf9f90af"),
-    ("cubic4_dense", "fp64", 2, 2, 2): (7.8618e+06, "6f34a80edf9f90af"),
-    ("cubic4_dense", "fp64", 2, 2, 4): (7.8547e+06, "6f34a80edf9f90af"),
-    ("cubic4_dense", "fp64", 2, 2, 8): (8.2643e+06, "6f34a80edf9f90af"),
-    ("cubic4_dense", "fp64", 2, 4, 1): (6.6901e+06, "6f34a80edf9f90af"),
-    ("cubic4_dense", "fp64", 2, 4, 2): (6.9261e+06, "6f34a80edf9f90af"),
-    ("cubic4_dense", "fp64", 2, 4, 4): (7.0518e+06, "6f34a80edf9f90af"),
-    ("cubic16_mixed", "fp64", 0, 1, 1): (1.7806e+10, "0b7d1186da371671"),
-    ("cubic16_mixed", "fp64", 0, 1, 2): (1.8327e+10, "0b7d1186da371671"),
-    ("cubic16_mixed", "fp64", 0, 1, 4): (1.8490e+10, "0b7d1186da371671"),
-    ("cubic16_mixed", "fp64", 0, 1, 8): (1.8005e+10, "0b7d1186da371671"),
-    ("cubic16_mixed", "fp64", 0, 2, 1): (1.9317e+10, "0b7d1186da371671"),
-    ("cubic16_mixed", "fp64", 0, 2, 2): (1.7480e+10, "0b7d1186da371671"),
-    ("cubic16_mixed", "fp64", 0, 2, 4): (1.7978e+10, "0b7d1186da371671"),
-    ("cubic16_mixed", "fp64", 0, 2, 8): (1.7245e+10, "0b7d1186da371671"),
-    ("cubic16_mixed", "fp64", 0, 4, 1): (1.4955e+10, "0b7d1186da371671"),
-    ("cubic16_mixed", "fp64", 0, 4, 2): (1.4579e+10, "0b7d1186da371671"),
-    ("cubic16_mixed", "fp64", 0, 4, 4): (1.6266e+10, "0b7d1186da371671"),
-    ("cubic16_mixed", "fp64", 1, 1, 1): (5.5534e+10, "eb3a3ed434999755"),
-    ("cubic16_mixed", "fp64", 1, 1, 2): (5.4284e+10, "eb3a3ed434999755"),
-    ("cubic16_mixed", "fp64", 1, 1, 4): (5.4044e+10, "eb3a3ed434999755"),
-    ("cubic16_mixed", "fp64", 1, 1, 8): (5.3460e+10, "eb3a3ed434999755"),
-    ("cubic16_mixed", "fp64", 1, 2, 1): (5.5330e+10, "eb3a3ed434999755"),
-    ("cubic16_mixed", "fp64", 1, 2, 2): (5.4082e+10, "eb3a3ed434999755"),
-    ("cubic16_mixed", "fp64", 1, 2, 4): (5.3800e+10, "eb3a3ed434999755"),
-    ("cubic16_mixed", "fp64", 1, 4, 1): (5.6954e+10, "eb3a3ed434999755"),
-    ("cubic16_mixed", "fp64", 1, 4, 2): (5.5636e+10, "eb3a3ed434999755"),
-    ("cubic16_mixed", "fp64", 1, 4, 4): (5.4737e+10, "eb3a3ed434999755"),
-    ("cubic16_mixed", "fp64", 2, 1, 1): (2.3496e+10, "6f34a80edf9f90af"),
-    ("cubic16_mixed", "fp64", 2, 1, 2): (3.1837e+10, "6f34a80edf9f90af"),
-    ("cubic16_mixed", "fp64", 2, 1, 4): (3.9476e+10, "6f34a80edf9f90af"),
-    ("cubic16_mixed", "fp64", 2, 1, 8): (3.8256e+10, "6f34a80edf9f90af"),
-    ("cubic16_mixed", "fp64", 2, 2, 1): (3.8308e+10, "6f34a80edf9f90af"),
-    ("cubic16_mixed", "fp64", 2, 2, 2): (3.9305e+10, "6f34a80edf9f90af"),
-    ("cubic16_mixed", "fp64", 2, 2, 4): (4.0901e+10, "6f34a80edf9f90af"),
-    ("cubic16_mixed", "fp64", 2, 2, 8): (3.5928e+10, "6f34a80edf9f90af"),
-    ("cubic16_mixed", "fp64", 2, 4, 1): (4.1786e+10, "6f34a80edf9f90af"),
-    ("cubic16_mixed", "fp64", 2, 4, 2): (3.9515e+10, "6f34a80edf9f90af"),
-    ("cubic16_mixed", "fp64", 2, 4, 4): (3.9014e+10, "6f34a80edf9f90af"),
+    ("cubic4_dense", "fp64", 0, 1, 1): (3.6203e+07, "ae501fa6cd10321d"),
+    ("cubic4_dense", "fp64", 0, 1, 2): (3.6203e+07, "ae501fa6cd10321d"),
+    ("cubic4_dense", "fp64", 0, 1, 4): (3.6233e+07, "ae501fa6cd10321d"),
+    ("cubic4_dense", "fp64", 0, 1, 8): (3.8098e+07, "ae501fa6cd10321d"),
+    ("cubic4_dense", "fp64", 0, 2, 1): (3.6148e+07, "ae501fa6cd10321d"),
+    ("cubic4_dense", "fp64", 0, 2, 2): (3.6177e+07, "ae501fa6cd10321d"),
+    ("cubic4_dense", "fp64", 0, 2, 4): (3.6161e+07, "ae501fa6cd10321d"),
+    ("cubic4_dense", "fp64", 0, 2, 8): (3.6101e+07, "ae501fa6cd10321d"),
+    ("cubic4_dense", "fp64", 0, 4, 1): (2.8090e+07, "ae501fa6cd10321d"),
+    ("cubic4_dense", "fp64", 0, 4, 2): (2.8982e+07, "ae501fa6cd10321d"),
+    ("cubic4_dense", "fp64", 0, 4, 4): (2.9455e+07, "ae501fa6cd10321d"),
+    ("cubic4_dense", "fp64", 1, 1, 1): (1.6136e+07, "ae075e4ff9dc8b7d"),
+    ("cubic4_dense", "fp64", 1, 1, 2): (1.6143e+07, "ae075e4ff9dc8b7d"),
+    ("cubic4_dense", "fp64", 1, 1, 4): (1.6064e+07, "ae075e4ff9dc8b7d"),
+    ("cubic4_dense", "fp64", 1, 1, 8): (1.6010e+07, "ae075e4ff9dc8b7d"),
+    ("cubic4_dense", "fp64", 1, 2, 1): (1.6243e+07, "ae075e4ff9dc8b7d"),
+    ("cubic4_dense", "fp64", 1, 2, 2): (1.6267e+07, "ae075e4ff9dc8b7d"),
+    ("cubic4_dense", "fp64", 1, 2, 4): (1.6213e+07, "ae075e4ff9dc8b7d"),
+    ("cubic4_dense", "fp64", 1, 4, 1): (9.2205e+06, "ae075e4ff9dc8b7d"),
+    ("cubic4_dense", "fp64", 1, 4, 2): (1.6352e+07, "ae075e4ff9dc8b7d"),
+    ("cubic4_dense", "fp64", 1, 4, 4): (1.6427e+07, "ae075e4ff9dc8b7d"),
+    ("cubic4_dense", "fp64", 2, 1, 1): (7.8492e+06, "4e18d9b47a44b32f"),
+    ("cubic4_dense", "fp64", 2, 1, 2): (7.8246e+06, "4e18d9b47a44b32f"),
+    ("cubic4_dense", "fp64", 2, 1, 4): (7.8277e+06, "4e18d9b47a44b32f"),
+    ("cubic4_dense", "fp64", 2, 1, 8): (7.8246e+06, "4e18d9b47a44b32f"),
+    ("cubic4_dense", "fp64", 2, 2, 1): (7.7996e+06, "4e18d9b47a44b32f"),
+    ("cubic4_dense", "fp64", 2, 2, 2): (7.8454e+06, "4e18d9b47a44b32f"),
+    ("cubic4_dense", "fp64", 2, 2, 4): (7.8393e+06, "4e18d9b47a44b32f"),
+    ("cubic4_dense", "fp64", 2, 2, 8): (8.2653e+06, "4e18d9b47a44b32f"),
+    ("cubic4_dense", "fp64", 2, 4, 1): (6.7065e+06, "4e18d9b47a44b32f"),
+    ("cubic4_dense", "fp64", 2, 4, 2): (6.9261e+06, "4e18d9b47a44b32f"),
+    ("cubic4_dense", "fp64", 2, 4, 4): (7.0497e+06, "4e18d9b47a44b32f"),
+    ("cubic16_mixed", "fp64", 0, 1, 1): (1.7803e+10, "ae501fa6cd10321d"),
+    ("cubic16_mixed", "fp64", 0, 1, 2): (1.8323e+10, "ae501fa6cd10321d"),
+    ("cubic16_mixed", "fp64", 0, 1, 4): (1.8487e+10, "ae501fa6cd10321d"),
+    ("cubic16_mixed", "fp64", 0, 1, 8): (1.8006e+10, "ae501fa6cd10321d"),
+    ("cubic16_mixed", "fp64", 0, 2, 1): (1.9319e+10, "ae501fa6cd10321d"),
+    ("cubic16_mixed", "fp64", 0, 2, 2): (1.7476e+10, "ae501fa6cd10321d"),
+    ("cubic16_mixed", "fp64", 0, 2, 4): (1.7976e+10, "ae501fa6cd10321d"),
+    ("cubic16_mixed", "fp64", 0, 2, 8): (1.7244e+10, "ae501fa6cd10321d"),
+    ("cubic16_mixed", "fp64", 0, 4, 1): (1.4959e+10, "ae501fa6cd10321d"),
+    ("cubic16_mixed", "fp64", 0, 4, 2): (1.4580e+10, "ae501fa6cd10321d"),
+    ("cubic16_mixed", "fp64", 0, 4, 4): (1.6263e+10, "ae501fa6cd10321d"),
+    ("cubic16_mixed", "fp64", 1, 1, 1): (5.5526e+10, "ae075e4ff9dc8b7d"),
+    ("cubic16_mixed", "fp64", 1, 1, 2): (5.4289e+10, "ae075e4ff9dc8b7d"),
+    ("cubic16_mixed", "fp64", 1, 1, 4): (5.4045e+10, "ae075e4ff9dc8b7d"),
+    ("cubic16_mixed", "fp64", 1, 1, 8): (5.3461e+10, "ae075e4ff9dc8b7d"),
+    ("cubic16_mixed", "fp64", 1, 2, 1): (5.5331e+10, "ae075e4ff9dc8b7d"),
+    ("cubic16_mixed", "fp64", 1, 2, 2): (5.4082e+10, "ae075e4ff9dc8b7d"),
+    ("cubic16_mixed", "fp64", 1, 2, 4): (5.3801e+10, "ae075e4ff9dc8b7d"),
+    ("cubic16_mixed", "fp64", 1, 4, 1): (5.6952e+10, "ae075e4ff9dc8b7d"),
+    ("cubic16_mixed", "fp64", 1, 4, 2): (5.5638e+10, "ae075e4ff9dc8b7d"),
+    ("cubic16_mixed", "fp64", 1, 4, 4): (5.4736e+10, "ae075e4ff9dc8b7d"),
+    ("cubic16_mixed", "fp64", 2, 1, 1): (1.6608e+10, "4e18d9b47a44b32f"),
+    ("cubic16_mixed", "fp64", 2, 1, 2): (2.3421e+10, "4e18d9b47a44b32f"),
+    ("cubic16_mixed", "fp64", 2, 1, 4): (3.2643e+10, "4e18d9b47a44b32f"),
+    ("cubic16_mixed", "fp64", 2, 1, 8): (3.2459e+10, "4e18d9b47a44b32f"),
+    ("cubic16_mixed", "fp64", 2, 2, 1): (2.7821e+10, "4e18d9b47a44b32f"),
+    ("cubic16_mixed", "fp64", 2, 2, 2): (2.7781e+10, "4e18d9b47a44b32f"),
+    ("cubic16_mixed", "fp64", 2, 2, 4): (3.2446e+10, "4e18d9b47a44b32f"),
+    ("cubic16_mixed", "fp64", 2, 2, 8): (3.0529e+10, "4e18d9b47a44b32f"),
+    ("cubic16_mixed", "fp64", 2, 4, 1): (3.3668e+10, "4e18d9b47a44b32f"),
+    ("cubic16_mixed", "fp64", 2, 4, 2): (3.2704e+10, "4e18d9b47a44b32f"),
+    ("cubic16_mixed", "fp64", 2, 4, 4): (3.2385e+10, "4e18d9b47a44b32f"),
 }
 
 
