@@ -339,11 +339,13 @@ __global__ __launch_bounds__(256) void k_update(int nc, int nhc, int ntot, const
   if (kind == 0) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) { u[i] = C[o + i]; p[i] = D[o + i]; }
-  } else if (kind == 1) {   // HC, SC tiles are stored transposed: element (r, c) at tpos(c, r)
-    const size_t tb = (size_t)t * TE;
+  } else if (kind == 1) {
+    // HC, SC tiles are stored transposed: their position 4 lane + i holds element
+    // (c, r), whose H D, S D value sits at pmt (the read and written HC, SC are
+    // contiguous per lane, the read-only H D, S D are gathered)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      u[i] = HC[tb + pt[i]]; v[i] = SC[tb + pt[i]]; p[i] = (double)HD[ob + pm[i]]; q[i] = (double)SD[ob + pm[i]];
+      u[i] = HC[o + i]; v[i] = SC[o + i]; p[i] = (double)HD[ob + pmt[i]]; q[i] = (double)SD[ob + pmt[i]];
     }
   } else {
     // H_W and S_W stay symmetric, and so do their increments: the wave of a tile
@@ -381,15 +383,14 @@ __global__ __launch_bounds__(256) void k_update(int nc, int nhc, int ntot, const
       if (LOW) Cl[ob + pl[i]] = cvt<TL, double>(nv);
     }
   } else if (kind == 1) {
-    const size_t tb = (size_t)t * TE;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const double h = u[i] + x * p[i], g = v[i] + x * q[i];
-      HC[tb + pt[i]] = h;
-      SC[tb + pt[i]] = g;
-      if (LOW) {
-        HCl[tb + plt[i]] = cvt<TL, double>(h);
-        SCl[tb + plt[i]] = cvt<TL, double>(g);
+      HC[o + i] = h;
+      SC[o + i] = g;
+      if (LOW) {   // element (c, r) of the transposed low-precision copy
+        HCl[ob + pl[i]] = cvt<TL, double>(h);
+        SCl[ob + pl[i]] = cvt<TL, double>(g);
       }
     }
   } else {
