@@ -198,6 +198,7 @@ struct omm_ctx {
   hipGraph_t graph[4] = {}, graph_small_h[4] = {};
   int graph_iters = 0, graph_small = 0;
   bool tuned = false;
+  bool grad_zero_fixed = false;   // OMM_GRAD_ZERO_TILE set: the gradient's load form is not tuned
   std::string tune_log;
   std::string tune_path, log_path;   // copies of the option strings (opt points at them)
   int64_t nsolves = 0;
@@ -1143,6 +1144,15 @@ void prepare(omm_ctx* c) {
   b.grad_steps = 0;
   for (int i = 0; i < c->nsys; ++i)
     if (c->sys[i].mode == OMM_BLOCK_SPARSE) b.grad_steps = 1;
+  // gradient loads of fully skipped step pairs: from the zero tile unless the
+  // autotuner finds the plain loads faster; OMM_GRAD_ZERO_TILE = 0 / 1 fixes it
+  b.grad_zero = 1;
+  c->grad_zero_fixed = false;
+  if (const char* e = std::getenv("OMM_GRAD_ZERO_TILE"))
+    if (*e) {
+      b.grad_zero = std::atoi(e) != 0 ? 1 : 0;
+      c->grad_zero_fixed = true;
+    }
   b.H = c->H; b.S = c->S;
   b.C = dalloc<double>(c, ntc * TE, true);
   b.D = dalloc<double>(c, ntc * TE, true);
@@ -1280,9 +1290,9 @@ bool any_filter(const omm_ctx* c);
 // lists (after the initial products, so every operand is valid) and keep the
 // fastest; results are cached per (step, precision, work-list size) in a text
 // file when a cache path is given.
-std::string tune_key(int cls, int prec, const GPlan& P) {
+std::string tune_key(int cls, int prec, const GPlan& P, bool zero_choice) {
   return std::to_string(cls) + ":" + std::to_string(prec) + ":" + std::to_string(P.ngroups) + ":" +
-         std::to_string(P.npairs);
+         std::to_string(P.npairs) + (zero_choice ? ":z" : "");
 }
 
 void set_plan(omm_ctx* c, int cls, int sel, int ks) {
@@ -1311,25 +1321,32 @@ void autotune(omm_ctx* c) {
   c->tune_log.clear();
   for (int cls = 0; cls < 3; ++cls) {
     if (c->opt.tile_group[cls] > 0 || c->opt.tile_split[cls] > 0) continue;   // shape given by the caller
-    const std::string key = tune_key(cls, (int)p, c->G[cls][0]);
+    // the gradient of a context with block-sparse systems also chooses where
+    // fully skipped step pairs are loaded from (zero tile or own tile)
+    const bool zero_choice = cls == 2 && c->b.grad_steps && !c->grad_zero_fixed;
+    const std::string key = tune_key(cls, (int)p, c->G[cls][0], zero_choice);
     int found = -1;
     for (auto& kv : cache)
       if (kv.first == key) found = kv.second;
-    if (found >= 0) {      // cached as 10 * plan + KS; an entry naming a shape the library cannot launch is tuned again
-      const int sel = found / 10, ks = found % 10;
-      if (sel < NPLAN && (ks == 1 || ks == 2 || ks == 4 || ks == 8) && plan_ok(cls, c->G[cls][sel].NT, ks)) {
+    if (found >= 0) {      // cached as 100 * zero tile + 10 * plan + KS; an entry naming a shape the library cannot launch is tuned again
+      const int zf = found / 100, sel = (found / 10) % 10, ks = found % 10;
+      if (sel < NPLAN && (ks == 1 || ks == 2 || ks == 4 || ks == 8) && plan_ok(cls, c->G[cls][sel].NT, ks) &&
+          (zf == 0 || zero_choice)) {
         set_plan(c, cls, sel, ks);
+        if (zero_choice) c->b.grad_zero = zf;
         continue;
       }
       cache.erase(std::remove_if(cache.begin(), cache.end(), [&](const auto& kv) { return kv.first == key; }),
                   cache.end());
     }
     float best = 1e30f;
-    int best_code = 10 * c->sel[cls] + c->b.ks[cls];
+    int best_code = (zero_choice ? 100 * c->b.grad_zero : 0) + 10 * c->sel[cls] + c->b.ks[cls];
+    for (int zf = zero_choice ? 1 : 0; zf >= 0; --zf)
     for (int sel = 0; sel < NPLAN; ++sel) {
       for (int ks : {1, 2, 4, 8}) {
         if (!plan_ok(cls, c->G[cls][sel].NT, ks)) continue;
         set_plan(c, cls, sel, ks);
+        if (zero_choice) c->b.grad_zero = zf;
         auto go = [&] {
           if (cls == 0) launch_s1(c->stream, c->b, p, mask, false);
           else if (cls == 1) launch_s2(c->stream, c->b, p, mask, false);
@@ -1349,15 +1366,17 @@ void autotune(omm_ctx* c) {
           OMM_HIP(hipEventElapsedTime(&ms, e0, e1));
           tmin = std::min(tmin, 0.25f * ms);
         }
-        c->tune_log += key + " nt=" + std::to_string(c->G[cls][sel].NT) + " ks=" + std::to_string(ks) + " " +
-                       std::to_string(tmin) + "ms; ";
+        c->tune_log += key + " nt=" + std::to_string(c->G[cls][sel].NT) + " ks=" + std::to_string(ks) +
+                       (zero_choice ? " zero=" + std::to_string(zf) : std::string()) + " " + std::to_string(tmin) +
+                       "ms; ";
         if (tmin < best) {
           best = tmin;
-          best_code = 10 * sel + ks;
+          best_code = 100 * zf + 10 * sel + ks;
         }
       }
     }
-    set_plan(c, cls, best_code / 10, best_code % 10);
+    set_plan(c, cls, (best_code / 10) % 10, best_code % 10);
+    if (zero_choice) c->b.grad_zero = best_code / 100;
     cache.emplace_back(key, best_code);
     added = true;
   }

@@ -20,7 +20,7 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_grad(
     const TI* __restrict__ SCm, const TI* __restrict__ S0m, const TI* __restrict__ H0m,
     const double* __restrict__ HC, const int* __restrict__ c_in_hc,
     const uint32_t* __restrict__ cmask, const double* __restrict__ Gold, double* __restrict__ G,
-    double* __restrict__ gpart, const TI* __restrict__ zt) {
+    double* __restrict__ gpart, const TI* __restrict__ zt, int keep_all) {
   typedef typename Acc<TI>::V V;
   typedef Split<KS> SP;
   constexpr int W = 1 + NT;
@@ -49,10 +49,11 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_grad(
         er, lane,
         [&](Stage& f, const int (&id)[W]) {
           if constexpr (STEPS) {   // parts of tiles whose MFMA steps are all skipped come from the zero tile
+            // (keep_all = 15: every part from its own tile)
             int kept[NT], ka = 0;
 #pragma unroll
             for (int u = 0; u < NT; ++u) {
-              kept[u] = id[1 + u] >= 0 ? ent_steps(id[1 + u]) : 0;
+              kept[u] = id[1 + u] >= 0 ? ent_steps(id[1 + u]) | keep_all : 0;
               ka |= kept[u];
             }
             ld_col_kept(f.h, HCm + (size_t)id[0] * TE, zt, ka, lane);   // HC, SC tiles are stored transposed
@@ -129,7 +130,7 @@ static void grad_go(hipStream_t s, const Bufs& b, int mask, const TI* HC, const 
     auto go = [&](auto rollc, auto stepsc) {
       constexpr bool R_ = decltype(rollc)::value, S_ = decltype(stepsc)::value;
       LAUNCH((k_grad<TI, K_, N_, R_, S_>), grid_for<K_>(b.grad.ngroups), block_for<K_>(), s, b.grad, b.st, mask, HC,
-             SC, S0, H0, b.HC, b.c_in_hc, b.cmask, b.Gold, b.G, b.gpart, (const TI*)b.zero);
+             SC, S0, H0, b.HC, b.c_in_hc, b.cmask, b.Gold, b.G, b.gpart, (const TI*)b.zero, b.grad_zero ? 0 : 15);
     };
     if (b.roll) {
       if (b.grad_steps) go(std::true_type{}, std::true_type{});

@@ -89,6 +89,8 @@ struct Bufs {   // every device buffer the iteration kernels touch
   int grad_steps;                // gradient entries carry skipped MFMA steps (a block-sparse system present)
   const double* zero;            // one FP64 tile of zeros: operand halves whose MFMA steps are all skipped
                                  // read it (it stays in each CU's L1)
+  int grad_zero;                 // 1: the gradient reads those halves from the zero tile, 0: from their
+                                 // own tiles (results are the same; the autotuner times both)
 };
 
 // the n x n work-list copy of an iteration: pairs whose H D and S D tiles are both zero marked absent
