@@ -73,7 +73,7 @@ MEASURED_TRAFFIC = {
     ("cubic4_dense", "fp64", 0, 1, 1): (3.6203e+07, "ae501fa6cd10321d"),
     ("cubic4_dense", "fp64", 0, 1, 2): (3.6203e+07, "ae501fa6cd10321d"),
     ("cubic4_dense", "fp64", 0, 1, 4): (3.6233e+07, "ae501fa6cd10321d"),
-    ("cubic4_dense", "fp64", 0, 1, 8): (3.8098e+07, "ae501fa6cd10321d"),
+    ("cubic4_dense", "fp64", 0, 1, 8): (3.8094e+07, "ae501fa6cd10321d"),
     ("cubic4_dense", "fp64", 0, 2, 1): (3.6148e+07, "ae501fa6cd10321d"),
     ("cubic4_dense", "fp64", 0, 2, 2): (3.6177e+07, "ae501fa6cd10321d"),
     ("cubic4_dense", "fp64", 0, 2, 4): (3.6161e+07, "ae501fa6cd10321d"),
@@ -91,49 +91,49 @@ MEASURED_TRAFFIC = {
     ("cubic4_dense", "fp64", 1, 4, 1): (9.2205e+06, "ae075e4ff9dc8b7d"),
     ("cubic4_dense", "fp64", 1, 4, 2): (1.6352e+07, "ae075e4ff9dc8b7d"),
     ("cubic4_dense", "fp64", 1, 4, 4): (1.6427e+07, "ae075e4ff9dc8b7d"),
-    ("cubic4_dense", "fp64", 2, 1, 1): (7.8492e+06, "4e18d9b47a44b32f"),
-    ("cubic4_dense", "fp64", 2, 1, 2): (7.8246e+06, "4e18d9b47a44b32f"),
-    ("cubic4_dense", "fp64", 2, 1, 4): (7.8277e+06, "4e18d9b47a44b32f"),
-    ("cubic4_dense", "fp64", 2, 1, 8): (7.8246e+06, "4e18d9b47a44b32f"),
-    ("cubic4_dense", "fp64", 2, 2, 1): (7.7996e+06, "4e18d9b47a44b32f"),
-    ("cubic4_dense", "fp64", 2, 2, 2): (7.8454e+06, "4e18d9b47a44b32f"),
-    ("cubic4_dense", "fp64", 2, 2, 4): (7.8393e+06, "4e18d9b47a44b32f"),
-    ("cubic4_dense", "fp64", 2, 2, 8): (8.2653e+06, "4e18d9b47a44b32f"),
-    ("cubic4_dense", "fp64", 2, 4, 1): (6.7065e+06, "4e18d9b47a44b32f"),
-    ("cubic4_dense", "fp64", 2, 4, 2): (6.9261e+06, "4e18d9b47a44b32f"),
-    ("cubic4_dense", "fp64", 2, 4, 4): (7.0497e+06, "4e18d9b47a44b32f"),
-    ("cubic16_mixed", "fp64", 0, 1, 1): (1.7803e+10, "ae501fa6cd10321d"),
-    ("cubic16_mixed", "fp64", 0, 1, 2): (1.8323e+10, "ae501fa6cd10321d"),
-    ("cubic16_mixed", "fp64", 0, 1, 4): (1.8487e+10, "ae501fa6cd10321d"),
-    ("cubic16_mixed", "fp64", 0, 1, 8): (1.8006e+10, "ae501fa6cd10321d"),
-    ("cubic16_mixed", "fp64", 0, 2, 1): (1.9319e+10, "ae501fa6cd10321d"),
-    ("cubic16_mixed", "fp64", 0, 2, 2): (1.7476e+10, "ae501fa6cd10321d"),
-    ("cubic16_mixed", "fp64", 0, 2, 4): (1.7976e+10, "ae501fa6cd10321d"),
-    ("cubic16_mixed", "fp64", 0, 2, 8): (1.7244e+10, "ae501fa6cd10321d"),
+    ("cubic4_dense", "fp64", 2, 1, 1): (7.8369e+06, "b41aa966817f4472"),
+    ("cubic4_dense", "fp64", 2, 1, 2): (7.8369e+06, "b41aa966817f4472"),
+    ("cubic4_dense", "fp64", 2, 1, 4): (7.8246e+06, "b41aa966817f4472"),
+    ("cubic4_dense", "fp64", 2, 1, 8): (7.8246e+06, "b41aa966817f4472"),
+    ("cubic4_dense", "fp64", 2, 2, 1): (7.8140e+06, "b41aa966817f4472"),
+    ("cubic4_dense", "fp64", 2, 2, 2): (7.8516e+06, "b41aa966817f4472"),
+    ("cubic4_dense", "fp64", 2, 2, 4): (7.8311e+06, "b41aa966817f4472"),
+    ("cubic4_dense", "fp64", 2, 2, 8): (8.2653e+06, "b41aa966817f4472"),
+    ("cubic4_dense", "fp64", 2, 4, 1): (6.6983e+06, "b41aa966817f4472"),
+    ("cubic4_dense", "fp64", 2, 4, 2): (6.9343e+06, "b41aa966817f4472"),
+    ("cubic4_dense", "fp64", 2, 4, 4): (7.0559e+06, "b41aa966817f4472"),
+    ("cubic16_mixed", "fp64", 0, 1, 1): (1.7802e+10, "ae501fa6cd10321d"),
+    ("cubic16_mixed", "fp64", 0, 1, 2): (1.8326e+10, "ae501fa6cd10321d"),
+    ("cubic16_mixed", "fp64", 0, 1, 4): (1.8489e+10, "ae501fa6cd10321d"),
+    ("cubic16_mixed", "fp64", 0, 1, 8): (1.8005e+10, "ae501fa6cd10321d"),
+    ("cubic16_mixed", "fp64", 0, 2, 1): (1.9326e+10, "ae501fa6cd10321d"),
+    ("cubic16_mixed", "fp64", 0, 2, 2): (1.7480e+10, "ae501fa6cd10321d"),
+    ("cubic16_mixed", "fp64", 0, 2, 4): (1.7972e+10, "ae501fa6cd10321d"),
+    ("cubic16_mixed", "fp64", 0, 2, 8): (1.7243e+10, "ae501fa6cd10321d"),
     ("cubic16_mixed", "fp64", 0, 4, 1): (1.4959e+10, "ae501fa6cd10321d"),
-    ("cubic16_mixed", "fp64", 0, 4, 2): (1.4580e+10, "ae501fa6cd10321d"),
-    ("cubic16_mixed", "fp64", 0, 4, 4): (1.6263e+10, "ae501fa6cd10321d"),
-    ("cubic16_mixed", "fp64", 1, 1, 1): (5.5526e+10, "ae075e4ff9dc8b7d"),
-    ("cubic16_mixed", "fp64", 1, 1, 2): (5.4289e+10, "ae075e4ff9dc8b7d"),
-    ("cubic16_mixed", "fp64", 1, 1, 4): (5.4045e+10, "ae075e4ff9dc8b7d"),
+    ("cubic16_mixed", "fp64", 0, 4, 2): (1.4578e+10, "ae501fa6cd10321d"),
+    ("cubic16_mixed", "fp64", 0, 4, 4): (1.6265e+10, "ae501fa6cd10321d"),
+    ("cubic16_mixed", "fp64", 1, 1, 1): (5.5531e+10, "ae075e4ff9dc8b7d"),
+    ("cubic16_mixed", "fp64", 1, 1, 2): (5.4284e+10, "ae075e4ff9dc8b7d"),
+    ("cubic16_mixed", "fp64", 1, 1, 4): (5.4038e+10, "ae075e4ff9dc8b7d"),
     ("cubic16_mixed", "fp64", 1, 1, 8): (5.3461e+10, "ae075e4ff9dc8b7d"),
     ("cubic16_mixed", "fp64", 1, 2, 1): (5.5331e+10, "ae075e4ff9dc8b7d"),
-    ("cubic16_mixed", "fp64", 1, 2, 2): (5.4082e+10, "ae075e4ff9dc8b7d"),
-    ("cubic16_mixed", "fp64", 1, 2, 4): (5.3801e+10, "ae075e4ff9dc8b7d"),
-    ("cubic16_mixed", "fp64", 1, 4, 1): (5.6952e+10, "ae075e4ff9dc8b7d"),
-    ("cubic16_mixed", "fp64", 1, 4, 2): (5.5638e+10, "ae075e4ff9dc8b7d"),
-    ("cubic16_mixed", "fp64", 1, 4, 4): (5.4736e+10, "ae075e4ff9dc8b7d"),
-    ("cubic16_mixed", "fp64", 2, 1, 1): (1.6608e+10, "4e18d9b47a44b32f"),
-    ("cubic16_mixed", "fp64", 2, 1, 2): (2.3421e+10, "4e18d9b47a44b32f"),
-    ("cubic16_mixed", "fp64", 2, 1, 4): (3.2643e+10, "4e18d9b47a44b32f"),
-    ("cubic16_mixed", "fp64", 2, 1, 8): (3.2459e+10, "4e18d9b47a44b32f"),
-    ("cubic16_mixed", "fp64", 2, 2, 1): (2.7821e+10, "4e18d9b47a44b32f"),
-    ("cubic16_mixed", "fp64", 2, 2, 2): (2.7781e+10, "4e18d9b47a44b32f"),
-    ("cubic16_mixed", "fp64", 2, 2, 4): (3.2446e+10, "4e18d9b47a44b32f"),
-    ("cubic16_mixed", "fp64", 2, 2, 8): (3.0529e+10, "4e18d9b47a44b32f"),
-    ("cubic16_mixed", "fp64", 2, 4, 1): (3.3668e+10, "4e18d9b47a44b32f"),
-    ("cubic16_mixed", "fp64", 2, 4, 2): (3.2704e+10, "4e18d9b47a44b32f"),
-    ("cubic16_mixed", "fp64", 2, 4, 4): (3.2385e+10, "4e18d9b47a44b32f"),
+    ("cubic16_mixed", "fp64", 1, 2, 2): (5.4084e+10, "ae075e4ff9dc8b7d"),
+    ("cubic16_mixed", "fp64", 1, 2, 4): (5.3800e+10, "ae075e4ff9dc8b7d"),
+    ("cubic16_mixed", "fp64", 1, 4, 1): (5.6956e+10, "ae075e4ff9dc8b7d"),
+    ("cubic16_mixed", "fp64", 1, 4, 2): (5.5632e+10, "ae075e4ff9dc8b7d"),
+    ("cubic16_mixed", "fp64", 1, 4, 4): (5.4732e+10, "ae075e4ff9dc8b7d"),
+    ("cubic16_mixed", "fp64", 2, 1, 1): (1.6508e+10, "b41aa966817f4472"),
+    ("cubic16_mixed", "fp64", 2, 1, 2): (2.3409e+10, "b41aa966817f4472"),
+    ("cubic16_mixed", "fp64", 2, 1, 4): (3.2630e+10, "b41aa966817f4472"),
+    ("cubic16_mixed", "fp64", 2, 1, 8): (3.2522e+10, "b41aa966817f4472"),
+    ("cubic16_mixed", "fp64", 2, 2, 1): (2.7375e+10, "b41aa966817f4472"),
+    ("cubic16_mixed", "fp64", 2, 2, 2): (2.6446e+10, "b41aa966817f4472"),
+    ("cubic16_mixed", "fp64", 2, 2, 4): (3.2196e+10, "b41aa966817f4472"),
+    ("cubic16_mixed", "fp64", 2, 2, 8): (3.0365e+10, "b41aa966817f4472"),
+    ("cubic16_mixed", "fp64", 2, 4, 1): (3.3662e+10, "b41aa966817f4472"),
+    ("cubic16_mixed", "fp64", 2, 4, 2): (3.2640e+10, "b41aa966817f4472"),
+    ("cubic16_mixed", "fp64", 2, 4, 4): (3.2456e+10, "b41aa966817f4472"),
 }
 
 
