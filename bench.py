@@ -70,27 +70,27 @@ PEAKS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}   # dense TFLOP/s of MI355
 # group width and split, and valid only for the kernel sources they were taken
 # with (sha256 prefix of the step's source file, tile_sched.hpp and tile_ops.hpp)
 MEASURED_TRAFFIC = {
-    ("cubic4_dense", "fp64", 0, 1, 1): (3.6203e+07, "ae501fa6cd10321d"),
-    ("cubic4_dense", "fp64", 0, 1, 2): (3.6203e+07, "ae501fa6cd10321d"),
-    ("cubic4_dense", "fp64", 0, 1, 4): (3.6233e+07, "ae501fa6cd10321d"),
-    ("cubic4_dense", "fp64", 0, 1, 8): (3.8094e+07, "ae501fa6cd10321d"),
-    ("cubic4_dense", "fp64", 0, 2, 1): (3.6148e+07, "ae501fa6cd10321d"),
-    ("cubic4_dense", "fp64", 0, 2, 2): (3.6177e+07, "ae501fa6cd10321d"),
-    ("cubic4_dense", "fp64", 0, 2, 4): (3.6161e+07, "ae501fa6cd10321d"),
-    ("cubic4_dense", "fp64", 0, 2, 8): (3.6101e+07, "ae501fa6cd10321d"),
-    ("cubic4_dense", "fp64", 0, 4, 1): (2.8090e+07, "ae501fa6cd10321d"),
-    ("cubic4_dense", "fp64", 0, 4, 2): (2.8982e+07, "ae501fa6cd10321d"),
-    ("cubic4_dense", "fp64", 0, 4, 4): (2.9455e+07, "ae501fa6cd10321d"),
-    ("cubic4_dense", "fp64", 1, 1, 1): (1.6136e+07, "ae075e4ff9dc8b7d"),
-    ("cubic4_dense", "fp64", 1, 1, 2): (1.6143e+07, "ae075e4ff9dc8b7d"),
-    ("cubic4_dense", "fp64", 1, 1, 4): (1.6064e+07, "ae075e4ff9dc8b7d"),
-    ("cubic4_dense", "fp64", 1, 1, 8): (1.6010e+07, "ae075e4ff9dc8b7d"),
-    ("cubic4_dense", "fp64", 1, 2, 1): (1.6243e+07, "ae075e4ff9dc8b7d"),
-    ("cubic4_dense", "fp64", 1, 2, 2): (1.6267e+07, "ae075e4ff9dc8b7d"),
-    ("cubic4_dense", "fp64", 1, 2, 4): (1.6213e+07, "ae075e4ff9dc8b7d"),
-    ("cubic4_dense", "fp64", 1, 4, 1): (9.2205e+06, "ae075e4ff9dc8b7d"),
-    ("cubic4_dense", "fp64", 1, 4, 2): (1.6352e+07, "ae075e4ff9dc8b7d"),
-    ("cubic4_dense", "fp64", 1, 4, 4): (1.6427e+07, "ae075e4ff9dc8b7d"),
+    ("cubic4_dense", "fp64", 0, 1, 1): (3.6203e+07, "f3396cb522e7c9aa"),
+    ("cubic4_dense", "fp64", 0, 1, 2): (3.6203e+07, "f3396cb522e7c9aa"),
+    ("cubic4_dense", "fp64", 0, 1, 4): (3.6233e+07, "f3396cb522e7c9aa"),
+    ("cubic4_dense", "fp64", 0, 1, 8): (3.8094e+07, "f3396cb522e7c9aa"),
+    ("cubic4_dense", "fp64", 0, 2, 1): (3.6148e+07, "f3396cb522e7c9aa"),
+    ("cubic4_dense", "fp64", 0, 2, 2): (3.6177e+07, "f3396cb522e7c9aa"),
+    ("cubic4_dense", "fp64", 0, 2, 4): (3.6161e+07, "f3396cb522e7c9aa"),
+    ("cubic4_dense", "fp64", 0, 2, 8): (3.6101e+07, "f3396cb522e7c9aa"),
+    ("cubic4_dense", "fp64", 0, 4, 1): (2.8090e+07, "f3396cb522e7c9aa"),
+    ("cubic4_dense", "fp64", 0, 4, 2): (2.8982e+07, "f3396cb522e7c9aa"),
+    ("cubic4_dense", "fp64", 0, 4, 4): (2.9455e+07, "f3396cb522e7c9aa"),
+    ("cubic4_dense", "fp64", 1, 1, 1): (1.6136e+07, "3b9a0568938b11a5"),
+    ("cubic4_dense", "fp64", 1, 1, 2): (1.6143e+07, "3b9a0568938b11a5"),
+    ("cubic4_dense", "fp64", 1, 1, 4): (1.6064e+07, "3b9a0568938b11a5"),
+    ("cubic4_dense", "fp64", 1, 1, 8): (1.6010e+07, "3b9a0568938b11a5"),
+    ("cubic4_dense", "fp64", 1, 2, 1): (1.6243e+07, "3b9a0568938b11a5"),
+    ("cubic4_dense", "fp64", 1, 2, 2): (1.6267e+07, "3b9a0568938b11a5"),
+    ("cubic4_dense", "fp64", 1, 2, 4): (1.6213e+07, "3b9a0568938b11a5"),
+    ("cubic4_dense", "fp64", 1, 4, 1): (9.2205e+06, "3b9a0568938b11a5"),
+    ("cubic4_dense", "fp64", 1, 4, 2): (1.6352e+07, "3b9a0568938b11a5"),
+    ("cubic4_dense", "fp64", 1, 4, 4): (1.6427e+07, "3b9a0568938b11a5"),
     ("cubic4_dense", "fp64", 2, 1, 1): (7.8369e+06, "b41aa966817f4472"),
     ("cubic4_dense", "fp64", 2, 1, 2): (7.8369e+06, "b41aa966817f4472"),
     ("cubic4_dense", "fp64", 2, 1, 4): (7.8246e+06, "b41aa966817f4472"),
@@ -102,27 +102,27 @@ MEASURED_TRAFFIC = {
     ("cubic4_dense", "fp64", 2, 4, 1): (6.6983e+06, "b41aa966817f4472"),
     ("cubic4_dense", "fp64", 2, 4, 2): (6.9343e+06, "b41aa966817f4472"),
     ("cubic4_dense", "fp64", 2, 4, 4): (7.0559e+06, "b41aa966817f4472"),
-    ("cubic16_mixed", "fp64", 0, 1, 1): (1.7802e+10, "ae501fa6cd10321d"),
-    ("cubic16_mixed", "fp64", 0, 1, 2): (1.8326e+10, "ae501fa6cd10321d"),
-    ("cubic16_mixed", "fp64", 0, 1, 4): (1.8489e+10, "ae501fa6cd10321d"),
-    ("cubic16_mixed", "fp64", 0, 1, 8): (1.8005e+10, "ae501fa6cd10321d"),
-    ("cubic16_mixed", "fp64", 0, 2, 1): (1.9326e+10, "ae501fa6cd10321d"),
-    ("cubic16_mixed", "fp64", 0, 2, 2): (1.7480e+10, "ae501fa6cd10321d"),
-    ("cubic16_mixed", "fp64", 0, 2, 4): (1.7972e+10, "ae501fa6cd10321d"),
-    ("cubic16_mixed", "fp64", 0, 2, 8): (1.7243e+10, "ae501fa6cd10321d"),
-    ("cubic16_mixed", "fp64", 0, 4, 1): (1.4959e+10, "ae501fa6cd10321d"),
-    ("cubic16_mixed", "fp64", 0, 4, 2): (1.4578e+10, "ae501fa6cd10321d"),
-    ("cubic16_mixed", "fp64", 0, 4, 4): (1.6265e+10, "ae501fa6cd10321d"),
-    ("cubic16_mixed", "fp64", 1, 1, 1): (5.5531e+10, "ae075e4ff9dc8b7d"),
-    ("cubic16_mixed", "fp64", 1, 1, 2): (5.4284e+10, "ae075e4ff9dc8b7d"),
-    ("cubic16_mixed", "fp64", 1, 1, 4): (5.4038e+10, "ae075e4ff9dc8b7d"),
-    ("cubic16_mixed", "fp64", 1, 1, 8): (5.3461e+10, "ae075e4ff9dc8b7d"),
-    ("cubic16_mixed", "fp64", 1, 2, 1): (5.5331e+10, "ae075e4ff9dc8b7d"),
-    ("cubic16_mixed", "fp64", 1, 2, 2): (5.4084e+10, "ae075e4ff9dc8b7d"),
-    ("cubic16_mixed", "fp64", 1, 2, 4): (5.3800e+10, "ae075e4ff9dc8b7d"),
-    ("cubic16_mixed", "fp64", 1, 4, 1): (5.6956e+10, "ae075e4ff9dc8b7d"),
-    ("cubic16_mixed", "fp64", 1, 4, 2): (5.5632e+10, "ae075e4ff9dc8b7d"),
-    ("cubic16_mixed", "fp64", 1, 4, 4): (5.4732e+10, "ae075e4ff9dc8b7d"),
+    ("cubic16_mixed", "fp64", 0, 1, 1): (1.7802e+10, "f3396cb522e7c9aa"),
+    ("cubic16_mixed", "fp64", 0, 1, 2): (1.8326e+10, "f3396cb522e7c9aa"),
+    ("cubic16_mixed", "fp64", 0, 1, 4): (1.8489e+10, "f3396cb522e7c9aa"),
+    ("cubic16_mixed", "fp64", 0, 1, 8): (1.8005e+10, "f3396cb522e7c9aa"),
+    ("cubic16_mixed", "fp64", 0, 2, 1): (1.9326e+10, "f3396cb522e7c9aa"),
+    ("cubic16_mixed", "fp64", 0, 2, 2): (1.7480e+10, "f3396cb522e7c9aa"),
+    ("cubic16_mixed", "fp64", 0, 2, 4): (1.7972e+10, "f3396cb522e7c9aa"),
+    ("cubic16_mixed", "fp64", 0, 2, 8): (1.7243e+10, "f3396cb522e7c9aa"),
+    ("cubic16_mixed", "fp64", 0, 4, 1): (1.4959e+10, "f3396cb522e7c9aa"),
+    ("cubic16_mixed", "fp64", 0, 4, 2): (1.4578e+10, "f3396cb522e7c9aa"),
+    ("cubic16_mixed", "fp64", 0, 4, 4): (1.6265e+10, "f3396cb522e7c9aa"),
+    ("cubic16_mixed", "fp64", 1, 1, 1): (5.5531e+10, "3b9a0568938b11a5"),
+    ("cubic16_mixed", "fp64", 1, 1, 2): (5.4284e+10, "3b9a0568938b11a5"),
+    ("cubic16_mixed", "fp64", 1, 1, 4): (5.4038e+10, "3b9a0568938b11a5"),
+    ("cubic16_mixed", "fp64", 1, 1, 8): (5.3461e+10, "3b9a0568938b11a5"),
+    ("cubic16_mixed", "fp64", 1, 2, 1): (5.5331e+10, "3b9a0568938b11a5"),
+    ("cubic16_mixed", "fp64", 1, 2, 2): (5.4084e+10, "3b9a0568938b11a5"),
+    ("cubic16_mixed", "fp64", 1, 2, 4): (5.3800e+10, "3b9a0568938b11a5"),
+    ("cubic16_mixed", "fp64", 1, 4, 1): (5.6956e+10, "3b9a0568938b11a5"),
+    ("cubic16_mixed", "fp64", 1, 4, 2): (5.5632e+10, "3b9a0568938b11a5"),
+    ("cubic16_mixed", "fp64", 1, 4, 4): (5.4732e+10, "3b9a0568938b11a5"),
     ("cubic16_mixed", "fp64", 2, 1, 1): (1.6508e+10, "b41aa966817f4472"),
     ("cubic16_mixed", "fp64", 2, 1, 2): (2.3409e+10, "b41aa966817f4472"),
     ("cubic16_mixed", "fp64", 2, 1, 4): (3.2630e+10, "b41aa966817f4472"),

@@ -174,7 +174,7 @@ static void s1_go(hipStream_t s, const Bufs& b, int mask, const TI* H, const TI*
 // one precision per object file (OMM_PREC 0: FP64, 1: FP32, 2: BF16)
 #if OMM_PREC == 0
 void launch_s1_p64(hipStream_t s, const Bufs& b, int mask, bool init) {
-  if (init) s1_go<double, double>(s, b, mask, b.H, b.S, b.C, b.HD, b.SD);   // H C, S C (row-major tiles)
+  if (init) s1_go<double, double>(s, b, mask, b.H, b.S, b.C, b.HD, b.SD);   // H C, S C (untransposed tiles)
   else s1_go<double, double>(s, b, mask, b.H, b.S, b.D, b.HD, b.SD, b.hcnz);
 }
 

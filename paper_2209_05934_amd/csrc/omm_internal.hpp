@@ -1,8 +1,9 @@
 // Internal declarations shared by the HIP sources of the OMM library.
 //
-// Storage model.  Every matrix lives on the GPU as a list of 16x16 row-major
-// FP64 tiles (plus FP32/BF16 copies for mixed precision) indexed by a tile
-// CSR pattern.  Basis rows: in block-sparse mode every atom block starts a new
+// Storage model.  Every matrix lives on the GPU as a list of 16x16 FP64 tiles
+// (plus FP32/BF16 copies for mixed precision) indexed by a tile CSR pattern;
+// inside a tile the elements follow the storage order of tpos / tpos4
+// (tile_ops.hpp), which matches the MFMA operand reads.  Basis rows: in block-sparse mode every atom block starts a new
 // tile row (13 orbitals -> 16 rows, 3 zero rows); in dense modes rows are cut
 // contiguously.  Wavefunction columns: block-sparse mode packs consecutive
 // wavefunction blocks into 16-wide tiles, dense modes cut contiguously.  A

@@ -147,7 +147,7 @@ static void s2_go(hipStream_t s, const Bufs& b, int mask, const TI* C, const TI*
 #if OMM_PREC == 0
 void launch_s2_p64(hipStream_t s, const Bufs& b, int mask, bool init) {
   if (init) {   // start-up products S0 = C^T S C, H0 = C^T H C (S C, H C in the S D, H D
-                // tiles, row-major) run on the unmarked list
+                // tiles, untransposed) run on the unmarked list
     Bufs bf = b;
     bf.s2 = b.s2_full;
     s2_go<double, double, double, 2>(s, bf, mask, b.C, b.C, b.HD, b.SD, b.S0, b.H0, b.S2, b.H2);
