@@ -118,15 +118,19 @@ typedef struct {
                                fastest (cached in tune_cache when set); default 0 */
   const char* tune_cache;   /* path of the autotuner cache file, or NULL: one line per
                                product step and work-list size, "key code" with
-                               code = 10 * group-width plan (0: 1, 1: 2, 2: 4 tiles)
+                               code = 10 * group-width plan (0: 1, 1: 2, 2: 4 tiles;
+                               for the n x n projections also 3: 2 rows)
                                + waves per group; a line whose shape this library
                                cannot launch is ignored and tuned again */
   void* hip_stream;         /* hipStream_t to run on; NULL: the library makes its own */
   int32_t tile_group[3];    /* launch shape of the tile products (direction products,
                                n x n projections, gradient): output tiles per wave
-                               (1, 2 or 4) and waves per output group (1, 2, 4 or 8,
+                               (1, 2 or 4 of one output row; for the n x n
+                               projections also -2: two consecutive output rows
+                               of one column, which share each loaded H D, S D
+                               tile) and waves per output group (1, 2, 4 or 8,
                                at most 4 with 4 tiles per wave or for the n x n
-                               projections at 2); 0 = chosen by the library (heuristic
+                               projections at 2 or -2); 0 = chosen by the library (heuristic
                                or autotuner).  A step given either value is not tuned.
                                Any shape gives the same result up to the order of
                                the sums; one shape gives bitwise repeatable results.
@@ -176,8 +180,9 @@ typedef struct {
   double flops_alg_step[3];
   double flops_exec_step[3];
   double bytes_alg_step[3];
-  /* launch shape in use per product step: output tiles per wave (group width)
-   * and waves splitting one group's work list (chosen by heuristic or autotuner) */
+  /* launch shape in use per product step: output tiles per wave (group width;
+   * -2 for two output rows of one column in the n x n projections) and waves
+   * splitting one group's work list (chosen by heuristic or autotuner) */
   int32_t tile_group[3];
   int32_t tile_split[3];
 } omm_sizes;

@@ -120,7 +120,9 @@ struct GPlan {   // grouped work list of one product step
   int4* meta = nullptr;
   std::vector<int> hgbase;          // first group of each output row (nrows + 1)
   std::vector<int64_t> hpairs;      // prefix of tile pairs over groups (ngroups + 1)
-  GroupView view() const { return GroupView{ngroups, NT, nent, xrun, go0, gn, gp, ent, meta}; }
+  int rows = 0;                     // 0, or P of a row-group list (NT == P)
+  int* gto = nullptr;               // row-group list: P output tiles per group (or -1)
+  GroupView view() const { return GroupView{ngroups, NT, nent, xrun, go0, gn, gp, ent, meta, rows, gto}; }
 };
 
 }  // namespace
@@ -168,6 +170,7 @@ struct omm_ctx {
   Pat TH, TC, TCt, THC, TW;
   Plan Pcm, Prho;
   GPlan G[3][NPLAN];  // product steps (direction, n x n, gradient) x group widths PLAN_NT
+  GPlan GR[NRG];      // row-group plans of the n x n projections (PLAN_ROWS output rows per wave)
   int sel[3] = {0, 0, 0};
   int *brow_sys = nullptr, *wrow_sys = nullptr, *c_in_hc = nullptr, *hc_to_c = nullptr, *w_tr = nullptr;
   int* upd_sys = nullptr;
@@ -218,6 +221,12 @@ struct omm_ctx {
   int64_t kt_n[3] = {0, 0, 0};
   std::vector<hipEvent_t> ev;
 };
+
+namespace {
+// plan sel of product step k: a group-width plan, or for the n x n projections
+// (sel >= NPLAN) a row-group plan
+GPlan& plan_at(omm_ctx* c, int k, int sel) { return (k == 1 && sel >= NPLAN) ? c->GR[sel - NPLAN] : c->G[k][sel]; }
+}  // namespace
 
 struct MultiGraph {
   std::vector<omm_ctx*> ctxs;
@@ -437,6 +446,42 @@ void make_gplan(omm_ctx* c, GPlan& G, const Pat& O, const PatView& A, const PatV
   G.nent = last[0];
   G.ent = dalloc<int>(c, (size_t)std::max<int64_t>(1, G.nent) * (1 + NT), true);
   group_lists(s, nrows, A, B, Ov, NT, G.gbase, gcnt, gpres, G.gp, G.ent, G.go0, G.gn);
+  std::vector<int64_t> pres = ddownload(c, gpres, G.ngroups);
+  G.hpairs.assign(G.ngroups + 1, 0);
+  for (int g = 0; g < G.ngroups; ++g) G.hpairs[g + 1] = G.hpairs[g] + pres[g];
+  G.npairs = G.hpairs[G.ngroups];
+}
+
+// Row-group work list of the n x n projections: groups of P consecutive output
+// rows (rfirst / rend per row, inside one system) by one output column, the
+// B tile of an entry shared by the P outputs.
+void make_rgplan(omm_ctx* c, GPlan& G, const Pat& O, const PatView& A, const PatView& B, int P, const int* rfirst,
+                 const int* rend) {
+  hipStream_t s = c->stream;
+  G.NT = P;
+  G.rows = P;
+  const int64_t nt = O.nnz;
+  PatView Ov = O.view();
+  Ov.ti = nullptr;
+  int* own = dalloc<int>(c, nt + 1, true);
+  OMM_HIP(hipMemsetAsync(own, 0, (nt + 1) * sizeof(int), s));
+  rg_owned(s, nt, O.row, Ov, rfirst, own);
+  int* gidx = dalloc<int>(c, nt + 1, true);
+  excl_scan(s, own, gidx, nt + 1);
+  G.ngroups = ddownload(c, gidx + nt, 1)[0];
+  int64_t* gcnt = dalloc<int64_t>(c, G.ngroups + 1, true);
+  int64_t* gpres = dalloc<int64_t>(c, G.ngroups + 1, true);
+  OMM_HIP(hipMemsetAsync(gcnt, 0, (G.ngroups + 1) * sizeof(int64_t), s));
+  OMM_HIP(hipMemsetAsync(gpres, 0, (G.ngroups + 1) * sizeof(int64_t), s));
+  G.gto = dalloc<int>(c, (size_t)std::max(1, G.ngroups) * P, true);
+  G.meta = dalloc<int4>(c, std::max(1, G.ngroups), true);
+  rg_lists(s, nt, P, O.row, Ov, A, B, rfirst, rend, c->wrow_sys, own, gidx, gcnt, gpres, nullptr, nullptr, G.gto,
+           G.meta);
+  G.gp = dalloc<int64_t>(c, G.ngroups + 1, true);
+  excl_scan64(s, gcnt, G.gp, G.ngroups + 1);
+  G.nent = ddownload(c, G.gp + G.ngroups, 1)[0];
+  G.ent = dalloc<int>(c, (size_t)std::max<int64_t>(1, G.nent) * (1 + P), true);
+  rg_lists(s, nt, P, O.row, Ov, A, B, rfirst, rend, c->wrow_sys, own, gidx, gcnt, gpres, G.gp, G.ent, G.gto, G.meta);
   std::vector<int64_t> pres = ddownload(c, gpres, G.ngroups);
   G.hpairs.assign(G.ngroups + 1, 0);
   for (int g = 0; g < G.ngroups; ++g) G.hpairs[g + 1] = G.hpairs[g] + pres[g];
@@ -1014,6 +1059,19 @@ void prepare(omm_ctx* c) {
         group_meta(st, G.ngroups, G.go0, G.gn, outs[k]->row, k == 1 ? c->wrow_sys : c->brow_sys, G.meta);
       }
     }
+    // row groups of the n x n projections: P consecutive WF tile rows of one system
+    std::vector<int> rf(c->NW, 0), re(c->NW, 0);
+    for (int q = 0; q < NRG; ++q) {
+      const int P = PLAN_ROWS[q];
+      for (int i = 0; i < c->nsys; ++i) {
+        const SysHost& sh = c->sys[i];
+        for (int r = sh.wb0; r < sh.wb0 + sh.WT; ++r) {
+          rf[r] = sh.wb0 + (r - sh.wb0) / P * P;
+          re[r] = std::min(rf[r] + P, sh.wb0 + sh.WT);
+        }
+      }
+      make_rgplan(c, c->GR[q], c->TW, c->TCt.view(), c->THC.view(), P, dupload(c, rf, true), dupload(c, re, true));
+    }
   }
   // density matrix rho = 2 C M C^T on H's pattern (Eq. 5): rho(b, b') sums
   // CM(b, g) C(b', g) over the WF tiles g of C's row b', and with H(b, b') != 0
@@ -1104,6 +1162,7 @@ void prepare(omm_ctx* c) {
     if (const char* e = std::getenv("OMM_XCD_RUN")) std::sscanf(e, "%d,%d,%d", &xr[0], &xr[1], &xr[2]);
     for (int k = 0; k < 3; ++k)
       for (int q = 0; q < NPLAN; ++q) c->G[k][q].xrun = std::max(1, xr[k]);
+    for (int q = 0; q < NRG; ++q) c->GR[q].xrun = std::max(1, xr[1]);
   }
   grad_step_masks(c);
   c->chunks = dupload(c, chunks, true);
@@ -1136,7 +1195,7 @@ void prepare(omm_ctx* c) {
     b.hcnz = dalloc<int>(c, std::max<size_t>(1, nhc), true);
     OMM_HIP(hipMemsetAsync(b.hcnz, 0xff, std::max<size_t>(1, nhc) * sizeof(int), st));
     int64_t words = 1;
-    for (int q = 0; q < NPLAN; ++q) words = std::max<int64_t>(words, c->G[1][q].nent * (1 + c->G[1][q].NT));
+    for (int q = 0; q < nplans(1); ++q) words = std::max<int64_t>(words, plan_at(c, 1, q).nent * (1 + plan_at(c, 1, q).NT));
     c->s2mark = dalloc<int>(c, (size_t)words, true);
   }
   pick_plans(c);
@@ -1226,10 +1285,10 @@ void prepare(omm_ctx* c) {
 // theirs (refreshed from the list whenever the plan changes)
 void bind_views(omm_ctx* c) {
   c->b.s1 = c->G[0][c->sel[0]].view();
-  c->b.s2 = c->b.s2_full = c->G[1][c->sel[1]].view();
+  c->b.s2 = c->b.s2_full = plan_at(c, 1, c->sel[1]).view();
   c->b.grad = c->G[2][c->sel[2]].view();
   if (c->b.hcnz && c->s2mark) {
-    const GPlan& G = c->G[1][c->sel[1]];
+    const GPlan& G = plan_at(c, 1, c->sel[1]);
     OMM_HIP(hipMemcpyAsync(c->s2mark, G.ent, (size_t)std::max<int64_t>(1, G.nent) * (1 + G.NT) * sizeof(int),
                            hipMemcpyDeviceToDevice, c->stream));
     c->b.s2.ent = c->s2mark;
@@ -1265,15 +1324,18 @@ void pick_plans(omm_ctx* c) {
   // launch shapes given in the options replace the heuristic choice
   for (int k = 0; k < 3; ++k) {
     const int gw = c->opt.tile_group[k], sp = c->opt.tile_split[k];
-    if (gw <= 0 && sp <= 0) continue;
+    if (gw == 0 && sp <= 0) continue;
     int sel = c->sel[k];
-    if (gw > 0) {
+    if (gw != 0) {
       sel = -1;
       for (int q = 0; q < NPLAN; ++q)
         if (PLAN_NT[q] == gw) sel = q;
-      if (sel < 0) throw ArgError("tile_group must be 1, 2 or 4");
+      if (k == 1)
+        for (int q = 0; q < NRG; ++q)
+          if (PLAN_ROWS[q] == -gw) sel = NPLAN + q;
+      if (sel < 0) throw ArgError("tile_group must be 1, 2 or 4 (or -2 for the n x n projections)");
     }
-    const GPlan& G = c->G[k][sel];
+    const GPlan& G = plan_at(c, k, sel);
     const int ks = sp > 0 ? sp : pick_ks(G.ngroups, G.nent, plan_ok(k, G.NT, 8) ? 8 : 4);
     if (!(ks == 1 || ks == 2 || ks == 4 || ks == 8) || !plan_ok(k, G.NT, ks))
       throw ArgError("tile_split must be 1, 2, 4 or 8 and fit the group width");
@@ -1320,7 +1382,7 @@ void autotune(omm_ctx* c) {
   bool added = false;
   c->tune_log.clear();
   for (int cls = 0; cls < 3; ++cls) {
-    if (c->opt.tile_group[cls] > 0 || c->opt.tile_split[cls] > 0) continue;   // shape given by the caller
+    if (c->opt.tile_group[cls] != 0 || c->opt.tile_split[cls] > 0) continue;   // shape given by the caller
     // the gradient of a context with block-sparse systems also chooses where
     // fully skipped step pairs are loaded from (zero tile or own tile)
     const bool zero_choice = cls == 2 && c->b.grad_steps && !c->grad_zero_fixed;
@@ -1330,7 +1392,7 @@ void autotune(omm_ctx* c) {
       if (kv.first == key) found = kv.second;
     if (found >= 0) {      // cached as 100 * zero tile + 10 * plan + KS; an entry naming a shape the library cannot launch is tuned again
       const int zf = found / 100, sel = (found / 10) % 10, ks = found % 10;
-      if (sel < NPLAN && (ks == 1 || ks == 2 || ks == 4 || ks == 8) && plan_ok(cls, c->G[cls][sel].NT, ks) &&
+      if (sel < nplans(cls) && (ks == 1 || ks == 2 || ks == 4 || ks == 8) && plan_ok(cls, plan_at(c, cls, sel).NT, ks) &&
           (zf == 0 || zero_choice)) {
         set_plan(c, cls, sel, ks);
         if (zero_choice) c->b.grad_zero = zf;
@@ -1342,9 +1404,9 @@ void autotune(omm_ctx* c) {
     float best = 1e30f;
     int best_code = (zero_choice ? 100 * c->b.grad_zero : 0) + 10 * c->sel[cls] + c->b.ks[cls];
     for (int zf = zero_choice ? 1 : 0; zf >= 0; --zf)
-    for (int sel = 0; sel < NPLAN; ++sel) {
+    for (int sel = 0; sel < nplans(cls); ++sel) {
       for (int ks : {1, 2, 4, 8}) {
-        if (!plan_ok(cls, c->G[cls][sel].NT, ks)) continue;
+        if (!plan_ok(cls, plan_at(c, cls, sel).NT, ks)) continue;
         set_plan(c, cls, sel, ks);
         if (zero_choice) c->b.grad_zero = zf;
         auto go = [&] {
@@ -1366,7 +1428,9 @@ void autotune(omm_ctx* c) {
           OMM_HIP(hipEventElapsedTime(&ms, e0, e1));
           tmin = std::min(tmin, 0.25f * ms);
         }
-        c->tune_log += key + " nt=" + std::to_string(c->G[cls][sel].NT) + " ks=" + std::to_string(ks) +
+        const GPlan& Gs = plan_at(c, cls, sel);
+        c->tune_log += key + " nt=" + std::to_string(Gs.rows ? -Gs.rows : Gs.NT) + " ks=" + std::to_string(ks) +
+                       " groups=" + std::to_string(Gs.ngroups) + " entries=" + std::to_string(Gs.nent) +
                        (zero_choice ? " zero=" + std::to_string(zf) : std::string()) + " " + std::to_string(tmin) +
                        "ms; ";
         if (tmin < best) {
@@ -2041,8 +2105,9 @@ int omm_init_batch(omm_ctx** out, int32_t count, const omm_matrix* H, const omm_
   }
   for (int k = 0; k < 3; ++k) {
     const int gw = o.tile_group[k], sp = o.tile_split[k];
-    if (!(gw == 0 || gw == 1 || gw == 2 || gw == 4) || !(sp == 0 || sp == 1 || sp == 2 || sp == 4 || sp == 8) ||
-        (gw > 0 && sp > 0 && !plan_ok(k, gw, sp))) {
+    const bool rows = k == 1 && gw == -2;   // row-group plan of the n x n projections
+    if (!(gw == 0 || gw == 1 || gw == 2 || gw == 4 || rows) || !(sp == 0 || sp == 1 || sp == 2 || sp == 4 || sp == 8) ||
+        (gw != 0 && sp > 0 && !plan_ok(k, gw < 0 ? -gw : gw, sp))) {
       g_last_init_error = "invalid tile_group / tile_split";
       return OMM_ERR_ARG;
     }
@@ -2616,7 +2681,10 @@ int omm_query(const omm_ctx* cc, int32_t sys, omm_sizes* z) {
   std::memset(z, 0, sizeof(*z));
   if (c->prepared)
     for (int k = 0; k < 3; ++k) {
-      z->tile_group[k] = c->G[k][c->sel[k]].NT;
+      {
+        const GPlan& G = plan_at(c, k, c->sel[k]);
+        z->tile_group[k] = G.rows ? -G.rows : G.NT;
+      }
       z->tile_split[k] = c->b.ks[k];
     }
   for (int i = 0; i < c->nsys; ++i) {

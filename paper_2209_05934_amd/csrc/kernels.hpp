@@ -31,6 +31,16 @@ void group_meta(hipStream_t st, int ngroups, const int* go0, const int* gn, cons
 // kept steps are added per system to act
 void entry_steps(hipStream_t st, int ngroups, int NT, const int64_t* gp, const int4* meta, int* ent,
                  const uint32_t* acm, const uint32_t* brm, unsigned long long* act);
+// row-group work lists (groups of P consecutive output rows by one column, P <= 4):
+// own[t] = 1 where output tile t is the first of its column inside its row
+// group (rfirst[i]: first row of row i's group); then, for the owning tiles
+// numbered by gidx, entry counts (gp == nullptr: also gto, P output tiles per
+// group or -1, and meta) or entries (B tile, then P A tiles; an absent one is
+// -2 - t, t the entry's first present A tile)
+void rg_owned(hipStream_t st, int64_t ntiles, const int* orow, PatView O, const int* rfirst, int* own);
+void rg_lists(hipStream_t st, int64_t ntiles, int P, const int* orow, PatView O, PatView A, PatView B,
+              const int* rfirst, const int* rend, const int* row_sys, const int* own, const int* gidx, int64_t* gcnt,
+              int64_t* gpres, const int64_t* gp, int* ent, int* gto, int4* meta);
 void excl_scan(hipStream_t st, const int* in, int* out, int64_t n);
 void excl_scan64(hipStream_t st, const int64_t* in, int64_t* out, int64_t n);
 
@@ -41,6 +51,12 @@ enum Prec { P64 = 0, P32 = 1, PBF = 2 };
 // grouped work lists built for every product step
 constexpr int NPLAN = 3;
 constexpr int PLAN_NT[NPLAN] = {1, 2, 4};
+// the n x n projections also have a row-group plan (P = 2 output rows of one
+// column per wave sharing the H D, S D tiles), plan NPLAN; its launch shape is
+// reported and given as tile_group = -2
+constexpr int NRG = 1;
+constexpr int PLAN_ROWS[NRG] = {2};
+constexpr int nplans(int step) { return step == 1 ? NPLAN + NRG : NPLAN; }
 // largest split KS of a product step (0 direction, 1 n x n, 2 gradient) at
 // group width NT: with KS = 8 a wave has at most 256 registers, too few for
 // four output tiles, or for two of the n x n projections (four products each)

@@ -638,17 +638,22 @@ __global__ __launch_bounds__(256) void k_hc_from_hd(int nhc, int hoff, const int
 // direction products of this iteration becomes -1, so the projections neither
 // load it nor multiply by it.  Skipping an all-zero tile leaves every sum as it
 // is.  One thread per entry.
-template <int W>
+// A row-group list holds the HC tile first and the C tiles after it (an absent
+// one written -2 - t, t a present C tile of the entry): an entry whose HC tile
+// was filtered to zero gets every C tile t written as -2 - t, so the
+// projections skip its products and still load only tiles of the entry.
+template <int W, bool ROWS = false>
 __global__ __launch_bounds__(256) void k_mark_pairs(int64_t nent, const int* __restrict__ ent,
                                                   const int* __restrict__ hcnz, int* __restrict__ out) {
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < nent; e += (int64_t)gridDim.x * 256) {
     const int* in = ent + e * W;
     int* o = out + e * W;
     o[0] = in[0];
+    const bool zero = ROWS && hcnz[in[0]] == 0;
 #pragma unroll
     for (int w = 1; w < W; ++w) {
       const int v = in[w];
-      o[w] = (v >= 0 && hcnz[v] == 0) ? -1 : v;
+      o[w] = ROWS ? ((zero && v >= 0) ? -2 - v : v) : ((v >= 0 && hcnz[v] == 0) ? -1 : v);
     }
   }
 }
@@ -904,7 +909,9 @@ void launch_hc_from_hd(hipStream_t s, const Bufs& b, int mask) {
 void launch_mark_pairs(hipStream_t s, const Bufs& b) {
   if (!b.hcnz || b.s2.nent <= 0 || b.s2.ent == b.s2_full.ent) return;
   const unsigned grid = (unsigned)std::min<int64_t>((b.s2.nent + 255) / 256, 8192);
-  if (b.s2.NT == 1)
+  if (b.s2.rows)   // row-group list (2 rows)
+    LAUNCH((k_mark_pairs<3, true>), dim3(grid), dim3(256), s, b.s2.nent, b.s2_full.ent, b.hcnz, (int*)b.s2.ent);
+  else if (b.s2.NT == 1)
     LAUNCH(k_mark_pairs<2>, dim3(grid), dim3(256), s, b.s2.nent, b.s2_full.ent, b.hcnz, (int*)b.s2.ent);
   else if (b.s2.NT == 2)
     LAUNCH(k_mark_pairs<3>, dim3(grid), dim3(256), s, b.s2.nent, b.s2_full.ent, b.hcnz, (int*)b.s2.ent);

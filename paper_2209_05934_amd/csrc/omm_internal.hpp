@@ -110,6 +110,8 @@ struct GroupView {
   const int64_t* gp;
   const int* ent;
   const int4* meta;   // per group: first output tile, output tiles, system, 0
+  int rows;           // 0, or P of a row-group list: the P output tiles of group g are
+  const int* gto;     // gto[g * P + u] (or -1), entries are (B tile, P A tiles; absent: -2 - t)
 };
 
 }  // namespace omm

@@ -272,6 +272,81 @@ __global__ __launch_bounds__(SYM_THREADS) void k_group_lists(PatView A, PatView 
   }
 }
 
+// ------------------------------------------------------- row-group work lists
+// A row group is P consecutive output rows i0 .. i0+P-1 (of one system); its
+// groups are the output columns j stored in any of those rows, one group per
+// column.  A group's entries are the k of the union of A.row(i0+u), in
+// increasing order, with B(k, j) stored and A(i0+u, k) stored for at least one
+// u; an entry holds the B tile index (shared by the P outputs) and P A tile
+// indices, -2 - t where A(i0+u, k) is absent (t: the entry's first present A
+// tile, so a wave that loads unconditionally reads a tile it loads anyway, not
+// one tile that every wave of the launch would read).  For the n x n projections (A = C^T,
+// B = the H C pattern) a wave then loads each H D, S D tile once for P output
+// rows: those tiles are the operands that other output rows reuse from far
+// away in time, so this form halves their loads at P = 2.
+// The column j is owned by the first row of the group that stores it; the
+// group of column j is numbered by a scan over the owning output tiles in tile
+// order, i.e. row by row and by column inside a row.
+__global__ void k_rg_owned(int64_t ntiles, const int* __restrict__ orow, PatView O, const int* __restrict__ rfirst,
+                           int* __restrict__ own) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntiles) return;
+  const int i = orow[t], j = O.ci[t];
+  int o = 1;
+  for (int r = rfirst[i]; r < i; ++r)
+    if (find_in_row(O, r, j) >= 0) { o = 0; break; }
+  own[t] = o;
+}
+
+template <bool FILL>
+__global__ void k_rg_lists(int64_t ntiles, int P, const int* __restrict__ orow, PatView O, PatView A, PatView B,
+                           const int* __restrict__ rfirst, const int* __restrict__ rend,
+                           const int* __restrict__ row_sys, const int* __restrict__ own,
+                           const int* __restrict__ gidx, int64_t* __restrict__ gcnt, int64_t* __restrict__ gpres,
+                           const int64_t* __restrict__ gp, int* __restrict__ ent, int* __restrict__ gto,
+                           int4* __restrict__ meta) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntiles || !own[t]) return;
+  const int g = gidx[t];
+  const int i = orow[t], j = O.ci[t];
+  const int i0 = rfirst[i], nr = rend[i] - i0;   // nr <= P
+  int cur[4], end[4];
+  for (int u = 0; u < 4; ++u) {
+    cur[u] = u < nr ? A.rp[i0 + u] : 0;
+    end[u] = u < nr ? A.rp[i0 + u + 1] : 0;
+  }
+  int64_t m = 0, pres = 0;
+  const int64_t base = FILL ? gp[g] : 0;
+  for (;;) {   // P-way merge of the A rows, k increasing
+    int k = 0x7fffffff;
+    for (int u = 0; u < nr; ++u)
+      if (cur[u] < end[u]) k = min(k, A.ci[cur[u]]);
+    if (k == 0x7fffffff) break;
+    const int bi = find_in_row(B, k, j);
+    int at[4] = {-1, -1, -1, -1}, first = -1;
+    for (int u = 0; u < nr; ++u)
+      if (cur[u] < end[u] && A.ci[cur[u]] == k) {
+        at[u] = a_tile(A, cur[u]);
+        ++cur[u];
+        if (first < 0) first = at[u];
+        if (bi >= 0) ++pres;
+      }
+    if (bi < 0) continue;
+    if (FILL) {   // an absent A tile is written -2 - t, t the entry's first present A tile
+      int* row = ent + (base + m) * (1 + P);
+      row[0] = B.ti ? B.ti[bi] : bi;
+      for (int u = 0; u < P; ++u) row[1 + u] = at[u] >= 0 ? at[u] : -2 - first;
+    }
+    ++m;
+  }
+  if (!FILL) {
+    gcnt[g] = m;
+    gpres[g] = pres;
+    for (int u = 0; u < P; ++u) gto[(size_t)g * P + u] = u < nr ? find_in_row(O, i0 + u, j) : -1;
+    meta[g] = make_int4((int)t, P, row_sys[i], 0);
+  }
+}
+
 __global__ void k_group_base(int nrows, const int* __restrict__ orp, int NT, int* __restrict__ ng) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nrows) return;
@@ -284,6 +359,27 @@ __global__ void k_group_base(int nrows, const int* __restrict__ orp, int NT, int
 void group_counts(hipStream_t st, int nrows, const int* orp, int NT, int* ng) {
   if (nrows <= 0) return;
   hipLaunchKernelGGL(k_group_base, dim3((nrows + 255) / 256), dim3(256), 0, st, nrows, orp, NT, ng);
+  OMM_HIP(hipGetLastError());
+}
+
+void rg_owned(hipStream_t st, int64_t ntiles, const int* orow, PatView O, const int* rfirst, int* own) {
+  if (ntiles <= 0) return;
+  hipLaunchKernelGGL(k_rg_owned, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, st, ntiles, orow, O, rfirst,
+                     own);
+  OMM_HIP(hipGetLastError());
+}
+
+void rg_lists(hipStream_t st, int64_t ntiles, int P, const int* orow, PatView O, PatView A, PatView B,
+              const int* rfirst, const int* rend, const int* row_sys, const int* own, const int* gidx, int64_t* gcnt,
+              int64_t* gpres, const int64_t* gp, int* ent, int* gto, int4* meta) {
+  if (ntiles <= 0) return;
+  const dim3 grid((unsigned)((ntiles + 255) / 256));
+  if (!gp)
+    hipLaunchKernelGGL(k_rg_lists<false>, grid, dim3(256), 0, st, ntiles, P, orow, O, A, B, rfirst, rend, row_sys,
+                       own, gidx, gcnt, gpres, gp, ent, gto, meta);
+  else
+    hipLaunchKernelGGL(k_rg_lists<true>, grid, dim3(256), 0, st, ntiles, P, orow, O, A, B, rfirst, rend, row_sys,
+                       own, gidx, gcnt, gpres, gp, ent, gto, meta);
   OMM_HIP(hipGetLastError());
 }
 

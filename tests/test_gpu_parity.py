@@ -113,13 +113,15 @@ def test_sparse_filtered_trajectory_parity():
     ctx.close()
 
 
-def test_filtered_trajectory_where_whole_tiles_drop():
+@pytest.mark.parametrize("group", [0, -2])
+def test_filtered_trajectory_where_whole_tiles_drop(group):
     # at 1e-2 every block of some H D and S D tiles falls below the threshold, so the
-    # n x n projections skip those tiles (their pairs are marked absent); skipping an
+    # n x n projections skip those tiles (their pairs are marked absent; in the
+    # row-group list, group -2, the entries of such a tile are); skipping an
     # all-zero tile is exact, so the trajectory is still the oracle's
     s = system("cubic5_sparse")
     eps, k = 1e-2, 40
-    ctx, r = gpu_run(s, "sparse", max_iter=k, filter_eps=eps)
+    ctx, r = gpu_run(s, "sparse", max_iter=k, filter_eps=eps, tile_group=[0, group, 0])
     ref = oracle_run(s, "sparse", max_iter=k, tol_grad=1e-9, filter_eps=eps)
     assert r.iters_total == k == ref.iterations
     check_trajectory(ctx.history(0), ref)
@@ -129,8 +131,11 @@ def test_filtered_trajectory_where_whole_tiles_drop():
 
 # every launch shape of every tile-product step (one step varied at a time, the
 # others at the library's choice) follows the oracle's trajectory
+# (the n x n projections also run a row-group list: tile_group -2 takes two
+# output rows of one column per wave, at most 4 waves per group)
 SHAPES = [(step, nt, ks) for step in range(3) for nt in (1, 2, 4) for ks in (1, 2, 4, 8)
           if ks <= (4 if (nt >= 4 or (step == 1 and nt >= 2)) else 8)]
+SHAPES += [(1, -2, ks) for ks in (1, 2, 4)]
 
 
 @pytest.mark.parametrize("name,mode,k", [("cubic4_dense", "dense", 12), ("cubic5_sparse", "sparse", 12)])
@@ -325,11 +330,12 @@ def test_corrupt_tune_cache_is_tuned_again(tmp_path):
             f.write(f"{k} {code}\n")
     ctx, r = gpu_run(s, "dense", autotune=1, tune_cache=str(cache).encode())
     z = ctx.sizes()
-    assert all(g in (1, 2, 4) for g in z.tile_group) and all(k in (1, 2, 4, 8) for k in z.tile_split)
+    assert all(g in ((1, 2, 4, -2) if k == 1 else (1, 2, 4)) for k, g in enumerate(z.tile_group))
+    assert all(k in (1, 2, 4, 8) for k in z.tile_split)
     assert r.status == L.OMM_OK and abs(r.energy - r0.energy) / s.natoms <= 1e-10
     codes = {k: int(v) for k, v in (line.split() for line in open(cache) if line.strip())}
     assert set(codes) == set(keys)
-    assert all(c // 10 < 3 and c % 10 in (1, 2, 4, 8) for c in codes.values())
+    assert all(c // 10 < (4 if k.startswith("1:") else 3) and c % 10 in (1, 2, 4, 8) for k, c in codes.items())
     ctx.close()
 
 
