@@ -70,70 +70,76 @@ PEAKS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}   # dense TFLOP/s of MI355
 # group width and split, and valid only for the kernel sources they were taken
 # with (sha256 prefix of the step's source file, tile_sched.hpp and tile_ops.hpp)
 MEASURED_TRAFFIC = {
-    ("cubic4_dense", "fp64", 0, 1, 1): (3.6203e+07, "f3396cb522e7c9aa"),
-    ("cubic4_dense", "fp64", 0, 1, 2): (3.6203e+07, "f3396cb522e7c9aa"),
-    ("cubic4_dense", "fp64", 0, 1, 4): (3.6233e+07, "f3396cb522e7c9aa"),
-    ("cubic4_dense", "fp64", 0, 1, 8): (3.8094e+07, "f3396cb522e7c9aa"),
-    ("cubic4_dense", "fp64", 0, 2, 1): (3.6148e+07, "f3396cb522e7c9aa"),
-    ("cubic4_dense", "fp64", 0, 2, 2): (3.6177e+07, "f3396cb522e7c9aa"),
-    ("cubic4_dense", "fp64", 0, 2, 4): (3.6161e+07, "f3396cb522e7c9aa"),
-    ("cubic4_dense", "fp64", 0, 2, 8): (3.6101e+07, "f3396cb522e7c9aa"),
-    ("cubic4_dense", "fp64", 0, 4, 1): (2.8090e+07, "f3396cb522e7c9aa"),
-    ("cubic4_dense", "fp64", 0, 4, 2): (2.8982e+07, "f3396cb522e7c9aa"),
-    ("cubic4_dense", "fp64", 0, 4, 4): (2.9455e+07, "f3396cb522e7c9aa"),
-    ("cubic4_dense", "fp64", 1, 1, 1): (1.6136e+07, "3b9a0568938b11a5"),
-    ("cubic4_dense", "fp64", 1, 1, 2): (1.6143e+07, "3b9a0568938b11a5"),
-    ("cubic4_dense", "fp64", 1, 1, 4): (1.6064e+07, "3b9a0568938b11a5"),
-    ("cubic4_dense", "fp64", 1, 1, 8): (1.6010e+07, "3b9a0568938b11a5"),
-    ("cubic4_dense", "fp64", 1, 2, 1): (1.6243e+07, "3b9a0568938b11a5"),
-    ("cubic4_dense", "fp64", 1, 2, 2): (1.6267e+07, "3b9a0568938b11a5"),
-    ("cubic4_dense", "fp64", 1, 2, 4): (1.6213e+07, "3b9a0568938b11a5"),
-    ("cubic4_dense", "fp64", 1, 4, 1): (9.2205e+06, "3b9a0568938b11a5"),
-    ("cubic4_dense", "fp64", 1, 4, 2): (1.6352e+07, "3b9a0568938b11a5"),
-    ("cubic4_dense", "fp64", 1, 4, 4): (1.6427e+07, "3b9a0568938b11a5"),
-    ("cubic4_dense", "fp64", 2, 1, 1): (7.8369e+06, "b41aa966817f4472"),
-    ("cubic4_dense", "fp64", 2, 1, 2): (7.8369e+06, "b41aa966817f4472"),
-    ("cubic4_dense", "fp64", 2, 1, 4): (7.8246e+06, "b41aa966817f4472"),
-    ("cubic4_dense", "fp64", 2, 1, 8): (7.8246e+06, "b41aa966817f4472"),
-    ("cubic4_dense", "fp64", 2, 2, 1): (7.8140e+06, "b41aa966817f4472"),
-    ("cubic4_dense", "fp64", 2, 2, 2): (7.8516e+06, "b41aa966817f4472"),
-    ("cubic4_dense", "fp64", 2, 2, 4): (7.8311e+06, "b41aa966817f4472"),
-    ("cubic4_dense", "fp64", 2, 2, 8): (8.2653e+06, "b41aa966817f4472"),
-    ("cubic4_dense", "fp64", 2, 4, 1): (6.6983e+06, "b41aa966817f4472"),
-    ("cubic4_dense", "fp64", 2, 4, 2): (6.9343e+06, "b41aa966817f4472"),
-    ("cubic4_dense", "fp64", 2, 4, 4): (7.0559e+06, "b41aa966817f4472"),
-    ("cubic16_mixed", "fp64", 0, 1, 1): (1.7802e+10, "f3396cb522e7c9aa"),
-    ("cubic16_mixed", "fp64", 0, 1, 2): (1.8326e+10, "f3396cb522e7c9aa"),
-    ("cubic16_mixed", "fp64", 0, 1, 4): (1.8489e+10, "f3396cb522e7c9aa"),
-    ("cubic16_mixed", "fp64", 0, 1, 8): (1.8005e+10, "f3396cb522e7c9aa"),
-    ("cubic16_mixed", "fp64", 0, 2, 1): (1.9326e+10, "f3396cb522e7c9aa"),
-    ("cubic16_mixed", "fp64", 0, 2, 2): (1.7480e+10, "f3396cb522e7c9aa"),
-    ("cubic16_mixed", "fp64", 0, 2, 4): (1.7972e+10, "f3396cb522e7c9aa"),
-    ("cubic16_mixed", "fp64", 0, 2, 8): (1.7243e+10, "f3396cb522e7c9aa"),
-    ("cubic16_mixed", "fp64", 0, 4, 1): (1.4959e+10, "f3396cb522e7c9aa"),
-    ("cubic16_mixed", "fp64", 0, 4, 2): (1.4578e+10, "f3396cb522e7c9aa"),
-    ("cubic16_mixed", "fp64", 0, 4, 4): (1.6265e+10, "f3396cb522e7c9aa"),
-    ("cubic16_mixed", "fp64", 1, 1, 1): (5.5531e+10, "3b9a0568938b11a5"),
-    ("cubic16_mixed", "fp64", 1, 1, 2): (5.4284e+10, "3b9a0568938b11a5"),
-    ("cubic16_mixed", "fp64", 1, 1, 4): (5.4038e+10, "3b9a0568938b11a5"),
-    ("cubic16_mixed", "fp64", 1, 1, 8): (5.3461e+10, "3b9a0568938b11a5"),
-    ("cubic16_mixed", "fp64", 1, 2, 1): (5.5331e+10, "3b9a0568938b11a5"),
-    ("cubic16_mixed", "fp64", 1, 2, 2): (5.4084e+10, "3b9a0568938b11a5"),
-    ("cubic16_mixed", "fp64", 1, 2, 4): (5.3800e+10, "3b9a0568938b11a5"),
-    ("cubic16_mixed", "fp64", 1, 4, 1): (5.6956e+10, "3b9a0568938b11a5"),
-    ("cubic16_mixed", "fp64", 1, 4, 2): (5.5632e+10, "3b9a0568938b11a5"),
-    ("cubic16_mixed", "fp64", 1, 4, 4): (5.4732e+10, "3b9a0568938b11a5"),
-    ("cubic16_mixed", "fp64", 2, 1, 1): (1.6508e+10, "b41aa966817f4472"),
-    ("cubic16_mixed", "fp64", 2, 1, 2): (2.3409e+10, "b41aa966817f4472"),
-    ("cubic16_mixed", "fp64", 2, 1, 4): (3.2630e+10, "b41aa966817f4472"),
-    ("cubic16_mixed", "fp64", 2, 1, 8): (3.2522e+10, "b41aa966817f4472"),
-    ("cubic16_mixed", "fp64", 2, 2, 1): (2.7375e+10, "b41aa966817f4472"),
-    ("cubic16_mixed", "fp64", 2, 2, 2): (2.6446e+10, "b41aa966817f4472"),
-    ("cubic16_mixed", "fp64", 2, 2, 4): (3.2196e+10, "b41aa966817f4472"),
-    ("cubic16_mixed", "fp64", 2, 2, 8): (3.0365e+10, "b41aa966817f4472"),
-    ("cubic16_mixed", "fp64", 2, 4, 1): (3.3662e+10, "b41aa966817f4472"),
-    ("cubic16_mixed", "fp64", 2, 4, 2): (3.2640e+10, "b41aa966817f4472"),
-    ("cubic16_mixed", "fp64", 2, 4, 4): (3.2456e+10, "b41aa966817f4472"),
+    ("cubic4_dense", "fp64", 0, 1, 1): (3.6204e+07, "f46fceb3fb92034a"),
+    ("cubic4_dense", "fp64", 0, 1, 2): (3.6204e+07, "f46fceb3fb92034a"),
+    ("cubic4_dense", "fp64", 0, 1, 4): (3.6224e+07, "f46fceb3fb92034a"),
+    ("cubic4_dense", "fp64", 0, 1, 8): (3.7885e+07, "f46fceb3fb92034a"),
+    ("cubic4_dense", "fp64", 0, 2, 1): (3.6167e+07, "f46fceb3fb92034a"),
+    ("cubic4_dense", "fp64", 0, 2, 2): (3.6194e+07, "f46fceb3fb92034a"),
+    ("cubic4_dense", "fp64", 0, 2, 4): (3.6162e+07, "f46fceb3fb92034a"),
+    ("cubic4_dense", "fp64", 0, 2, 8): (3.6092e+07, "f46fceb3fb92034a"),
+    ("cubic4_dense", "fp64", 0, 4, 1): (2.8130e+07, "f46fceb3fb92034a"),
+    ("cubic4_dense", "fp64", 0, 4, 2): (2.9017e+07, "f46fceb3fb92034a"),
+    ("cubic4_dense", "fp64", 0, 4, 4): (2.9467e+07, "f46fceb3fb92034a"),
+    ("cubic4_dense", "fp64", 1, -2, 1): (1.0602e+07, "888ede66e8544215"),
+    ("cubic4_dense", "fp64", 1, -2, 2): (1.0597e+07, "888ede66e8544215"),
+    ("cubic4_dense", "fp64", 1, -2, 4): (1.0572e+07, "888ede66e8544215"),
+    ("cubic4_dense", "fp64", 1, 1, 1): (1.6153e+07, "888ede66e8544215"),
+    ("cubic4_dense", "fp64", 1, 1, 2): (1.6149e+07, "888ede66e8544215"),
+    ("cubic4_dense", "fp64", 1, 1, 4): (1.6064e+07, "888ede66e8544215"),
+    ("cubic4_dense", "fp64", 1, 1, 8): (1.5989e+07, "888ede66e8544215"),
+    ("cubic4_dense", "fp64", 1, 2, 1): (1.6276e+07, "888ede66e8544215"),
+    ("cubic4_dense", "fp64", 1, 2, 2): (1.6297e+07, "888ede66e8544215"),
+    ("cubic4_dense", "fp64", 1, 2, 4): (1.6202e+07, "888ede66e8544215"),
+    ("cubic4_dense", "fp64", 1, 4, 1): (9.2438e+06, "888ede66e8544215"),
+    ("cubic4_dense", "fp64", 1, 4, 2): (1.6396e+07, "888ede66e8544215"),
+    ("cubic4_dense", "fp64", 1, 4, 4): (1.6467e+07, "888ede66e8544215"),
+    ("cubic4_dense", "fp64", 2, 1, 1): (7.8307e+06, "7027969265155556"),
+    ("cubic4_dense", "fp64", 2, 1, 2): (7.8379e+06, "7027969265155556"),
+    ("cubic4_dense", "fp64", 2, 1, 4): (7.8215e+06, "7027969265155556"),
+    ("cubic4_dense", "fp64", 2, 1, 8): (7.8256e+06, "7027969265155556"),
+    ("cubic4_dense", "fp64", 2, 2, 1): (7.8150e+06, "7027969265155556"),
+    ("cubic4_dense", "fp64", 2, 2, 2): (7.8485e+06, "7027969265155556"),
+    ("cubic4_dense", "fp64", 2, 2, 4): (7.8413e+06, "7027969265155556"),
+    ("cubic4_dense", "fp64", 2, 2, 8): (8.2663e+06, "7027969265155556"),
+    ("cubic4_dense", "fp64", 2, 4, 1): (6.6911e+06, "7027969265155556"),
+    ("cubic4_dense", "fp64", 2, 4, 2): (6.9353e+06, "7027969265155556"),
+    ("cubic4_dense", "fp64", 2, 4, 4): (7.0569e+06, "7027969265155556"),
+    ("cubic16_mixed", "fp64", 0, 1, 1): (1.7828e+10, "f46fceb3fb92034a"),
+    ("cubic16_mixed", "fp64", 0, 1, 2): (1.8319e+10, "f46fceb3fb92034a"),
+    ("cubic16_mixed", "fp64", 0, 1, 4): (1.8492e+10, "f46fceb3fb92034a"),
+    ("cubic16_mixed", "fp64", 0, 1, 8): (1.8004e+10, "f46fceb3fb92034a"),
+    ("cubic16_mixed", "fp64", 0, 2, 1): (1.9445e+10, "f46fceb3fb92034a"),
+    ("cubic16_mixed", "fp64", 0, 2, 2): (1.7529e+10, "f46fceb3fb92034a"),
+    ("cubic16_mixed", "fp64", 0, 2, 4): (1.8006e+10, "f46fceb3fb92034a"),
+    ("cubic16_mixed", "fp64", 0, 2, 8): (1.7238e+10, "f46fceb3fb92034a"),
+    ("cubic16_mixed", "fp64", 0, 4, 1): (1.4970e+10, "f46fceb3fb92034a"),
+    ("cubic16_mixed", "fp64", 0, 4, 2): (1.4582e+10, "f46fceb3fb92034a"),
+    ("cubic16_mixed", "fp64", 0, 4, 4): (1.6274e+10, "f46fceb3fb92034a"),
+    ("cubic16_mixed", "fp64", 1, -2, 1): (4.3947e+10, "888ede66e8544215"),
+    ("cubic16_mixed", "fp64", 1, -2, 2): (4.2108e+10, "888ede66e8544215"),
+    ("cubic16_mixed", "fp64", 1, -2, 4): (4.1199e+10, "888ede66e8544215"),
+    ("cubic16_mixed", "fp64", 1, 1, 1): (5.5561e+10, "888ede66e8544215"),
+    ("cubic16_mixed", "fp64", 1, 1, 2): (5.4299e+10, "888ede66e8544215"),
+    ("cubic16_mixed", "fp64", 1, 1, 4): (5.4076e+10, "888ede66e8544215"),
+    ("cubic16_mixed", "fp64", 1, 1, 8): (5.3458e+10, "888ede66e8544215"),
+    ("cubic16_mixed", "fp64", 1, 2, 1): (5.5383e+10, "888ede66e8544215"),
+    ("cubic16_mixed", "fp64", 1, 2, 2): (5.4148e+10, "888ede66e8544215"),
+    ("cubic16_mixed", "fp64", 1, 2, 4): (5.3826e+10, "888ede66e8544215"),
+    ("cubic16_mixed", "fp64", 1, 4, 1): (5.7016e+10, "888ede66e8544215"),
+    ("cubic16_mixed", "fp64", 1, 4, 2): (5.5681e+10, "888ede66e8544215"),
+    ("cubic16_mixed", "fp64", 1, 4, 4): (5.4778e+10, "888ede66e8544215"),
+    ("cubic16_mixed", "fp64", 2, 1, 1): (1.6805e+10, "7027969265155556"),
+    ("cubic16_mixed", "fp64", 2, 1, 2): (2.3557e+10, "7027969265155556"),
+    ("cubic16_mixed", "fp64", 2, 1, 4): (3.2606e+10, "7027969265155556"),
+    ("cubic16_mixed", "fp64", 2, 1, 8): (3.2545e+10, "7027969265155556"),
+    ("cubic16_mixed", "fp64", 2, 2, 1): (2.6841e+10, "7027969265155556"),
+    ("cubic16_mixed", "fp64", 2, 2, 2): (2.6294e+10, "7027969265155556"),
+    ("cubic16_mixed", "fp64", 2, 2, 4): (3.2067e+10, "7027969265155556"),
+    ("cubic16_mixed", "fp64", 2, 2, 8): (3.0448e+10, "7027969265155556"),
+    ("cubic16_mixed", "fp64", 2, 4, 1): (3.3419e+10, "7027969265155556"),
+    ("cubic16_mixed", "fp64", 2, 4, 2): (3.2342e+10, "7027969265155556"),
+    ("cubic16_mixed", "fp64", 2, 4, 4): (3.2076e+10, "7027969265155556"),
 }
 
 
