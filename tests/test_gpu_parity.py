@@ -186,15 +186,18 @@ def test_batch_equals_standalone():
     ctx.close()
 
 
-def test_batch_of_sixteen_uneven_systems_is_bitwise_standalone():
+@pytest.mark.parametrize("s2_group", [1, -2])
+def test_batch_of_sixteen_uneven_systems_is_bitwise_standalone(s2_group):
     # 16 systems of the 64-system batch workload (27 to 343 atoms, half dense, half
     # localized and filtered), at one launch shape: each system's sums run in the
-    # same order in the batch as alone, so every result is bitwise the same
+    # same order in the batch as alone, so every result is bitwise the same.  With
+    # the row-group n x n list (s2_group -2) the row pairs stay inside each system
+    # (a system with an odd number of wavefunction tile rows ends in a one-row group).
     from ommgen import batch_specs, make_system
     specs = batch_specs()
     pick = list(range(0, 64, 4))
     systems = [make_system(specs[k]) for k in pick]
-    shape = dict(tile_group=[2, 1, 1], tile_split=[2, 2, 2])
+    shape = dict(tile_group=[2, s2_group, 1], tile_split=[2, 2, 2])
     probs = [Problem(s.H, s.S, s.C0, s.n, L.OMM_DENSE if s.spec.dense else L.OMM_BLOCK_SPARSE,
                      eta=s.spec.eta) for s in systems]
     opts = dict(max_iter=60, filter_eps=1e-6, **shape)
