@@ -458,6 +458,7 @@ void make_gplan(omm_ctx* c, GPlan& G, const Pat& O, const PatView& A, const PatV
 void make_rgplan(omm_ctx* c, GPlan& G, const Pat& O, const PatView& A, const PatView& B, int P, const int* rfirst,
                  const int* rend) {
   hipStream_t s = c->stream;
+  if (P < 1 || P > 4) throw ArgError("internal: row groups of 1 to 4 rows");   // the list kernel holds 4 cursors
   G.NT = P;
   G.rows = P;
   const int64_t nt = O.nnz;
