@@ -70,76 +70,76 @@ PEAKS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}   # dense TFLOP/s of MI355
 # group width and split, and valid only for the kernel sources they were taken
 # with (sha256 prefix of the step's source file, tile_sched.hpp and tile_ops.hpp)
 MEASURED_TRAFFIC = {
-    ("cubic4_dense", "fp64", 0, 1, 1): (3.6204e+07, "f46fceb3fb92034a"),
-    ("cubic4_dense", "fp64", 0, 1, 2): (3.6204e+07, "f46fceb3fb92034a"),
-    ("cubic4_dense", "fp64", 0, 1, 4): (3.6224e+07, "f46fceb3fb92034a"),
-    ("cubic4_dense", "fp64", 0, 1, 8): (3.7885e+07, "f46fceb3fb92034a"),
-    ("cubic4_dense", "fp64", 0, 2, 1): (3.6167e+07, "f46fceb3fb92034a"),
-    ("cubic4_dense", "fp64", 0, 2, 2): (3.6194e+07, "f46fceb3fb92034a"),
-    ("cubic4_dense", "fp64", 0, 2, 4): (3.6162e+07, "f46fceb3fb92034a"),
-    ("cubic4_dense", "fp64", 0, 2, 8): (3.6092e+07, "f46fceb3fb92034a"),
-    ("cubic4_dense", "fp64", 0, 4, 1): (2.8130e+07, "f46fceb3fb92034a"),
-    ("cubic4_dense", "fp64", 0, 4, 2): (2.9017e+07, "f46fceb3fb92034a"),
-    ("cubic4_dense", "fp64", 0, 4, 4): (2.9467e+07, "f46fceb3fb92034a"),
-    ("cubic4_dense", "fp64", 1, -2, 1): (1.0602e+07, "888ede66e8544215"),
-    ("cubic4_dense", "fp64", 1, -2, 2): (1.0597e+07, "888ede66e8544215"),
-    ("cubic4_dense", "fp64", 1, -2, 4): (1.0572e+07, "888ede66e8544215"),
-    ("cubic4_dense", "fp64", 1, 1, 1): (1.6153e+07, "888ede66e8544215"),
-    ("cubic4_dense", "fp64", 1, 1, 2): (1.6149e+07, "888ede66e8544215"),
-    ("cubic4_dense", "fp64", 1, 1, 4): (1.6064e+07, "888ede66e8544215"),
-    ("cubic4_dense", "fp64", 1, 1, 8): (1.5989e+07, "888ede66e8544215"),
-    ("cubic4_dense", "fp64", 1, 2, 1): (1.6276e+07, "888ede66e8544215"),
-    ("cubic4_dense", "fp64", 1, 2, 2): (1.6297e+07, "888ede66e8544215"),
-    ("cubic4_dense", "fp64", 1, 2, 4): (1.6202e+07, "888ede66e8544215"),
-    ("cubic4_dense", "fp64", 1, 4, 1): (9.2438e+06, "888ede66e8544215"),
-    ("cubic4_dense", "fp64", 1, 4, 2): (1.6396e+07, "888ede66e8544215"),
-    ("cubic4_dense", "fp64", 1, 4, 4): (1.6467e+07, "888ede66e8544215"),
-    ("cubic4_dense", "fp64", 2, 1, 1): (7.8307e+06, "7027969265155556"),
-    ("cubic4_dense", "fp64", 2, 1, 2): (7.8379e+06, "7027969265155556"),
-    ("cubic4_dense", "fp64", 2, 1, 4): (7.8215e+06, "7027969265155556"),
-    ("cubic4_dense", "fp64", 2, 1, 8): (7.8256e+06, "7027969265155556"),
-    ("cubic4_dense", "fp64", 2, 2, 1): (7.8150e+06, "7027969265155556"),
-    ("cubic4_dense", "fp64", 2, 2, 2): (7.8485e+06, "7027969265155556"),
-    ("cubic4_dense", "fp64", 2, 2, 4): (7.8413e+06, "7027969265155556"),
-    ("cubic4_dense", "fp64", 2, 2, 8): (8.2663e+06, "7027969265155556"),
-    ("cubic4_dense", "fp64", 2, 4, 1): (6.6911e+06, "7027969265155556"),
-    ("cubic4_dense", "fp64", 2, 4, 2): (6.9353e+06, "7027969265155556"),
-    ("cubic4_dense", "fp64", 2, 4, 4): (7.0569e+06, "7027969265155556"),
-    ("cubic16_mixed", "fp64", 0, 1, 1): (1.7828e+10, "f46fceb3fb92034a"),
-    ("cubic16_mixed", "fp64", 0, 1, 2): (1.8319e+10, "f46fceb3fb92034a"),
-    ("cubic16_mixed", "fp64", 0, 1, 4): (1.8492e+10, "f46fceb3fb92034a"),
-    ("cubic16_mixed", "fp64", 0, 1, 8): (1.8004e+10, "f46fceb3fb92034a"),
-    ("cubic16_mixed", "fp64", 0, 2, 1): (1.9445e+10, "f46fceb3fb92034a"),
-    ("cubic16_mixed", "fp64", 0, 2, 2): (1.7529e+10, "f46fceb3fb92034a"),
-    ("cubic16_mixed", "fp64", 0, 2, 4): (1.8006e+10, "f46fceb3fb92034a"),
-    ("cubic16_mixed", "fp64", 0, 2, 8): (1.7238e+10, "f46fceb3fb92034a"),
-    ("cubic16_mixed", "fp64", 0, 4, 1): (1.4970e+10, "f46fceb3fb92034a"),
-    ("cubic16_mixed", "fp64", 0, 4, 2): (1.4582e+10, "f46fceb3fb92034a"),
-    ("cubic16_mixed", "fp64", 0, 4, 4): (1.6274e+10, "f46fceb3fb92034a"),
-    ("cubic16_mixed", "fp64", 1, -2, 1): (4.3947e+10, "888ede66e8544215"),
-    ("cubic16_mixed", "fp64", 1, -2, 2): (4.2108e+10, "888ede66e8544215"),
-    ("cubic16_mixed", "fp64", 1, -2, 4): (4.1199e+10, "888ede66e8544215"),
-    ("cubic16_mixed", "fp64", 1, 1, 1): (5.5561e+10, "888ede66e8544215"),
-    ("cubic16_mixed", "fp64", 1, 1, 2): (5.4299e+10, "888ede66e8544215"),
-    ("cubic16_mixed", "fp64", 1, 1, 4): (5.4076e+10, "888ede66e8544215"),
-    ("cubic16_mixed", "fp64", 1, 1, 8): (5.3458e+10, "888ede66e8544215"),
-    ("cubic16_mixed", "fp64", 1, 2, 1): (5.5383e+10, "888ede66e8544215"),
-    ("cubic16_mixed", "fp64", 1, 2, 2): (5.4148e+10, "888ede66e8544215"),
-    ("cubic16_mixed", "fp64", 1, 2, 4): (5.3826e+10, "888ede66e8544215"),
-    ("cubic16_mixed", "fp64", 1, 4, 1): (5.7016e+10, "888ede66e8544215"),
-    ("cubic16_mixed", "fp64", 1, 4, 2): (5.5681e+10, "888ede66e8544215"),
-    ("cubic16_mixed", "fp64", 1, 4, 4): (5.4778e+10, "888ede66e8544215"),
-    ("cubic16_mixed", "fp64", 2, 1, 1): (1.6805e+10, "7027969265155556"),
-    ("cubic16_mixed", "fp64", 2, 1, 2): (2.3557e+10, "7027969265155556"),
-    ("cubic16_mixed", "fp64", 2, 1, 4): (3.2606e+10, "7027969265155556"),
-    ("cubic16_mixed", "fp64", 2, 1, 8): (3.2545e+10, "7027969265155556"),
-    ("cubic16_mixed", "fp64", 2, 2, 1): (2.6841e+10, "7027969265155556"),
-    ("cubic16_mixed", "fp64", 2, 2, 2): (2.6294e+10, "7027969265155556"),
-    ("cubic16_mixed", "fp64", 2, 2, 4): (3.2067e+10, "7027969265155556"),
-    ("cubic16_mixed", "fp64", 2, 2, 8): (3.0448e+10, "7027969265155556"),
-    ("cubic16_mixed", "fp64", 2, 4, 1): (3.3419e+10, "7027969265155556"),
-    ("cubic16_mixed", "fp64", 2, 4, 2): (3.2342e+10, "7027969265155556"),
-    ("cubic16_mixed", "fp64", 2, 4, 4): (3.2076e+10, "7027969265155556"),
+    ("cubic4_dense", "fp64", 0, 1, 1): (3.6204e+07, "7f6ec2575e98f052"),
+    ("cubic4_dense", "fp64", 0, 1, 2): (3.6204e+07, "7f6ec2575e98f052"),
+    ("cubic4_dense", "fp64", 0, 1, 4): (3.6240e+07, "7f6ec2575e98f052"),
+    ("cubic4_dense", "fp64", 0, 1, 8): (3.7836e+07, "7f6ec2575e98f052"),
+    ("cubic4_dense", "fp64", 0, 2, 1): (3.6149e+07, "7f6ec2575e98f052"),
+    ("cubic4_dense", "fp64", 0, 2, 2): (3.6178e+07, "7f6ec2575e98f052"),
+    ("cubic4_dense", "fp64", 0, 2, 4): (3.6162e+07, "7f6ec2575e98f052"),
+    ("cubic4_dense", "fp64", 0, 2, 8): (3.6102e+07, "7f6ec2575e98f052"),
+    ("cubic4_dense", "fp64", 0, 4, 1): (2.8091e+07, "7f6ec2575e98f052"),
+    ("cubic4_dense", "fp64", 0, 4, 2): (2.8983e+07, "7f6ec2575e98f052"),
+    ("cubic4_dense", "fp64", 0, 4, 4): (2.9456e+07, "7f6ec2575e98f052"),
+    ("cubic4_dense", "fp64", 1, -2, 1): (1.0626e+07, "abdca07b294c4edf"),
+    ("cubic4_dense", "fp64", 1, -2, 2): (1.0635e+07, "abdca07b294c4edf"),
+    ("cubic4_dense", "fp64", 1, -2, 4): (1.0589e+07, "abdca07b294c4edf"),
+    ("cubic4_dense", "fp64", 1, 1, 1): (1.6137e+07, "abdca07b294c4edf"),
+    ("cubic4_dense", "fp64", 1, 1, 2): (1.6144e+07, "abdca07b294c4edf"),
+    ("cubic4_dense", "fp64", 1, 1, 4): (1.6065e+07, "abdca07b294c4edf"),
+    ("cubic4_dense", "fp64", 1, 1, 8): (1.6011e+07, "abdca07b294c4edf"),
+    ("cubic4_dense", "fp64", 1, 2, 1): (1.6244e+07, "abdca07b294c4edf"),
+    ("cubic4_dense", "fp64", 1, 2, 2): (1.6268e+07, "abdca07b294c4edf"),
+    ("cubic4_dense", "fp64", 1, 2, 4): (1.6214e+07, "abdca07b294c4edf"),
+    ("cubic4_dense", "fp64", 1, 4, 1): (9.2210e+06, "abdca07b294c4edf"),
+    ("cubic4_dense", "fp64", 1, 4, 2): (1.6353e+07, "abdca07b294c4edf"),
+    ("cubic4_dense", "fp64", 1, 4, 4): (1.6428e+07, "abdca07b294c4edf"),
+    ("cubic4_dense", "fp64", 2, 1, 1): (7.8307e+06, "816809e26cfbb54b"),
+    ("cubic4_dense", "fp64", 2, 1, 2): (7.8379e+06, "816809e26cfbb54b"),
+    ("cubic4_dense", "fp64", 2, 1, 4): (7.8215e+06, "816809e26cfbb54b"),
+    ("cubic4_dense", "fp64", 2, 1, 8): (7.8256e+06, "816809e26cfbb54b"),
+    ("cubic4_dense", "fp64", 2, 2, 1): (7.8150e+06, "816809e26cfbb54b"),
+    ("cubic4_dense", "fp64", 2, 2, 2): (7.8485e+06, "816809e26cfbb54b"),
+    ("cubic4_dense", "fp64", 2, 2, 4): (7.8413e+06, "816809e26cfbb54b"),
+    ("cubic4_dense", "fp64", 2, 2, 8): (8.2663e+06, "816809e26cfbb54b"),
+    ("cubic4_dense", "fp64", 2, 4, 1): (6.6911e+06, "816809e26cfbb54b"),
+    ("cubic4_dense", "fp64", 2, 4, 2): (6.9353e+06, "816809e26cfbb54b"),
+    ("cubic4_dense", "fp64", 2, 4, 4): (7.0569e+06, "816809e26cfbb54b"),
+    ("cubic16_mixed", "fp64", 0, 1, 1): (1.7805e+10, "7f6ec2575e98f052"),
+    ("cubic16_mixed", "fp64", 0, 1, 2): (1.8321e+10, "7f6ec2575e98f052"),
+    ("cubic16_mixed", "fp64", 0, 1, 4): (1.8490e+10, "7f6ec2575e98f052"),
+    ("cubic16_mixed", "fp64", 0, 1, 8): (1.8005e+10, "7f6ec2575e98f052"),
+    ("cubic16_mixed", "fp64", 0, 2, 1): (1.9325e+10, "7f6ec2575e98f052"),
+    ("cubic16_mixed", "fp64", 0, 2, 2): (1.7469e+10, "7f6ec2575e98f052"),
+    ("cubic16_mixed", "fp64", 0, 2, 4): (1.7972e+10, "7f6ec2575e98f052"),
+    ("cubic16_mixed", "fp64", 0, 2, 8): (1.7241e+10, "7f6ec2575e98f052"),
+    ("cubic16_mixed", "fp64", 0, 4, 1): (1.4959e+10, "7f6ec2575e98f052"),
+    ("cubic16_mixed", "fp64", 0, 4, 2): (1.4576e+10, "7f6ec2575e98f052"),
+    ("cubic16_mixed", "fp64", 0, 4, 4): (1.6270e+10, "7f6ec2575e98f052"),
+    ("cubic16_mixed", "fp64", 1, -2, 1): (4.4001e+10, "abdca07b294c4edf"),
+    ("cubic16_mixed", "fp64", 1, -2, 2): (4.2122e+10, "abdca07b294c4edf"),
+    ("cubic16_mixed", "fp64", 1, -2, 4): (4.1246e+10, "abdca07b294c4edf"),
+    ("cubic16_mixed", "fp64", 1, 1, 1): (5.5531e+10, "abdca07b294c4edf"),
+    ("cubic16_mixed", "fp64", 1, 1, 2): (5.4272e+10, "abdca07b294c4edf"),
+    ("cubic16_mixed", "fp64", 1, 1, 4): (5.4060e+10, "abdca07b294c4edf"),
+    ("cubic16_mixed", "fp64", 1, 1, 8): (5.3467e+10, "abdca07b294c4edf"),
+    ("cubic16_mixed", "fp64", 1, 2, 1): (5.5304e+10, "abdca07b294c4edf"),
+    ("cubic16_mixed", "fp64", 1, 2, 2): (5.4095e+10, "abdca07b294c4edf"),
+    ("cubic16_mixed", "fp64", 1, 2, 4): (5.3789e+10, "abdca07b294c4edf"),
+    ("cubic16_mixed", "fp64", 1, 4, 1): (5.6985e+10, "abdca07b294c4edf"),
+    ("cubic16_mixed", "fp64", 1, 4, 2): (5.5591e+10, "abdca07b294c4edf"),
+    ("cubic16_mixed", "fp64", 1, 4, 4): (5.4714e+10, "abdca07b294c4edf"),
+    ("cubic16_mixed", "fp64", 2, 1, 1): (1.6601e+10, "816809e26cfbb54b"),
+    ("cubic16_mixed", "fp64", 2, 1, 2): (2.3474e+10, "816809e26cfbb54b"),
+    ("cubic16_mixed", "fp64", 2, 1, 4): (3.2561e+10, "816809e26cfbb54b"),
+    ("cubic16_mixed", "fp64", 2, 1, 8): (3.2583e+10, "816809e26cfbb54b"),
+    ("cubic16_mixed", "fp64", 2, 2, 1): (2.6804e+10, "816809e26cfbb54b"),
+    ("cubic16_mixed", "fp64", 2, 2, 2): (2.6253e+10, "816809e26cfbb54b"),
+    ("cubic16_mixed", "fp64", 2, 2, 4): (3.2106e+10, "816809e26cfbb54b"),
+    ("cubic16_mixed", "fp64", 2, 2, 8): (3.0459e+10, "816809e26cfbb54b"),
+    ("cubic16_mixed", "fp64", 2, 4, 1): (3.3387e+10, "816809e26cfbb54b"),
+    ("cubic16_mixed", "fp64", 2, 4, 2): (3.2287e+10, "816809e26cfbb54b"),
+    ("cubic16_mixed", "fp64", 2, 4, 4): (3.2124e+10, "816809e26cfbb54b"),
 }
 
 

@@ -57,7 +57,7 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s1(
         [&](Stage& f, const int (&id)[W]) {
           ld_col(f.h, Hm + (size_t)id[0] * TE, lane);
 #pragma unroll
-          for (int u = 0; u < NT; ++u) ld_col(f.b[u], Bm + (size_t)slot_tile(id, u) * TE, lane);
+          for (int u = 0; u < NT; ++u) ld_col(f.b[u], Bm + (size_t)max(id[1 + u], 0) * TE, lane);
         },
         [&](const Stage& f, const int (&id)[W]) {
 #pragma unroll
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s1(
             ld_col(f.h, Hm + (size_t)id[0] * TE, lane);   // tile (k, i) of the symmetric H: A(i, k)
             if constexpr (!IDENT) ld_col(f.s, Sm + (size_t)id[0] * TE, lane);
 #pragma unroll
-            for (int u = 0; u < NT; ++u) ld_col(f.b[u], Bm + (size_t)slot_tile(id, u) * TE, lane);
+            for (int u = 0; u < NT; ++u) ld_col(f.b[u], Bm + (size_t)max(id[1 + u], 0) * TE, lane);
           },
           [&](const Stage& f, const int (&id)[W]) {
 #pragma unroll

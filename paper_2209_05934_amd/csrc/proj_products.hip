@@ -65,7 +65,7 @@ __global__ __launch_bounds__(Split<KS>::NW * 64) void k_s2(
           if constexpr (NPROD == 4 && !SKIP) ld_col(f.d, Dm + (size_t)id[0] * TE, lane);  // A = D^T
 #pragma unroll
           for (int u = 0; u < NT; ++u) {
-            const size_t bt = (size_t)slot_tile(id, u) * TE;
+            const size_t bt = (size_t)max(id[1 + u], 0) * TE;
             ld_col(f.hd[u], HDm + bt, lane);
             ld_col(f.sd[u], SDm + bt, lane);
           }

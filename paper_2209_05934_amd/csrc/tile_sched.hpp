@@ -27,13 +27,9 @@ __device__ __forceinline__ bool on(const SysState* __restrict__ st, int s, int m
 // (filtering of Sec. V).  Row/column segments give, for each tile row/column,
 // the [lo, hi) range of its block inside the tile; rseg == nullptr means the
 // whole tile height is one block.  Uniform shuffles, fixed summation order.
-// `filtered` takes and returns the tile by value and is always inlined: in a
-// kernel with many accumulators the compiler may keep `filter_tile` a call, and
-// its reference argument then puts the caller's whole accumulator array in
-// scratch memory.
 template <typename V>
-__device__ __forceinline__ V filtered(V acc, int lane, const uint8_t* __restrict__ rseg,
-                                      const uint8_t* __restrict__ cseg, double eps2) {
+__device__ void filter_tile(V& acc, int lane, const uint8_t* __restrict__ rseg,
+                            const uint8_t* __restrict__ cseg, double eps2) {
   const int j = lane & 15, q = lane >> 4;
   const int clo = cseg[j], chi = cseg[16 + j];
   // Common case, decided for the whole wave: every column block is an aligned
@@ -72,7 +68,7 @@ __device__ __forceinline__ V filtered(V acc, int lane, const uint8_t* __restrict
 #pragma unroll
     for (int r = 0; r < 4; ++r)
       if (tot[r] < eps2) acc[r] = 0;
-    return acc;
+    return;
   }
   double rowpart[4];
 #pragma unroll
@@ -102,13 +98,17 @@ __device__ __forceinline__ V filtered(V acc, int lane, const uint8_t* __restrict
 #pragma unroll
   for (int r = 0; r < 4; ++r)
     if (tot[r] < eps2) acc[r] = 0;
-  return acc;
 }
 
+// The same on a tile taken and returned by value, always inlined.  A kernel
+// with many accumulators where the compiler keeps `filter_tile` a call would
+// otherwise pass it the address of one element of its accumulator array, and
+// the whole array would live in scratch memory; here only the copy does.
 template <typename V>
-__device__ void filter_tile(V& acc, int lane, const uint8_t* __restrict__ rseg, const uint8_t* __restrict__ cseg,
-                            double eps2) {
-  acc = filtered(acc, lane, rseg, cseg, eps2);
+__device__ __forceinline__ V filtered(V acc, int lane, const uint8_t* __restrict__ rseg,
+                                      const uint8_t* __restrict__ cseg, double eps2) {
+  filter_tile(acc, lane, rseg, cseg, eps2);
+  return acc;
 }
 
 // Work distribution of the tile-product kernels.  A workgroup holds NW = max(4, KS)
@@ -273,18 +273,6 @@ __device__ __forceinline__ void run_entries(EntryRounds<W, D>& er, int lane, Loa
       er.nxt = er.batch(r0 + 2 * PB, lane);
     }
   }
-}
-
-// Tile that slot u of an entry (A tile, then W - 1 B tiles or -1) loads: its
-// own B tile, or for an absent slot the entry's largest present B tile, which
-// the same wave loads anyway.  A fixed placeholder tile read by every wave of
-// a launch would put all those reads on the few L2 channels that hold it.
-template <int W>
-__device__ __forceinline__ int slot_tile(const int (&id)[W], int u) {
-  int fb = 0;
-#pragma unroll
-  for (int w = 1; w < W; ++w) fb = max(fb, id[w]);
-  return id[1 + u] >= 0 ? id[1 + u] : fb;
 }
 
 // f(integral_constant<int, i>) for i = 0 .. N-1, unrolled in the source: loops
